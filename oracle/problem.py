@@ -1,0 +1,53 @@
+"""Whole-problem driver of the oracle (test infrastructure only).
+
+Builds, for a workload description, the fine system (immersed formulation
+section), the Galerkin hierarchy (coarsening subsection), the factored
+additive Schwarz smoothers on every level above the coarsest (smoothers
+subsection) and the V-cycle preconditioner (Algorithm alg:MGV).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import assemble as AS
+from . import geometry as G
+from . import hierarchy as H
+from . import multigrid as MG
+from . import schwarz as SW
+
+
+@dataclass
+class OracleProblem:
+    w: object
+    leaf: np.ndarray
+    system: AS.System
+    hier: H.Hierarchy
+    smoothers: list
+    vcycle: MG.VCycle
+
+    @property
+    def A(self):
+        return self.system.A
+
+    @property
+    def b(self):
+        return self.system.b
+
+    def solve(self, b=None, tol=1e-8, max_iter=1000):
+        b = self.b if b is None else b
+        return MG.pcg(self.A, b, self.vcycle.apply, tol=tol, max_iter=max_iter)
+
+
+def build(w, orders=None, smoothers=True) -> OracleProblem:
+    leaf = G.leaf_values(w, w.n, w.depth)
+    sysf = AS.assemble(w, leaf, w.n, w.depth, orders=orders)
+    hier = H.Hierarchy(w, sysf, leaf)
+    sm = [None] * w.levels
+    vc = None
+    if smoothers:
+        for l in range(1, w.levels):
+            sm[l] = SW.Smoother(hier.A[l], hier.levels[l])
+        vc = MG.VCycle(hier.A, hier.R, sm, nu_pre=w.nu, nu_post=w.nu)
+    return OracleProblem(w=w, leaf=leaf, system=sysf, hier=hier, smoothers=sm, vcycle=vc)
