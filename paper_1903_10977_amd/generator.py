@@ -1,0 +1,175 @@
+"""ctypes binding of the native problem generator (libimsmg_gen.so).
+
+`generate(workload)` returns a GeneratedProblem holding, per level (0 =
+coarsest), the active lattice indices, the CSR operator, the restriction to
+the next coarser level and the Schwarz blocks, plus the fine right-hand side
+(and optionally the fine mass matrix).  All arithmetic runs in the native
+library; this module only marshals arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import LIB_DIR
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = os.path.join(LIB_DIR, "libimsmg_gen.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() or python -m paper_1903_10977_amd.build")
+    lib = C.CDLL(path)
+    lib.imsmg_gen_build.argtypes = [C.POINTER(GenSpec), C.POINTER(C.c_void_p)]
+    lib.imsmg_gen_build.restype = C.c_int
+    lib.imsmg_gen_level_info_get.argtypes = [C.c_void_p, C.c_int, C.POINTER(LevelInfo)]
+    lib.imsmg_gen_get_operator.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.imsmg_gen_get_restriction.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.imsmg_gen_get_blocks.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.imsmg_gen_get_rhs.argtypes = [C.c_void_p, C.c_void_p]
+    lib.imsmg_gen_get_mass.argtypes = [C.c_void_p, C.c_void_p]
+    lib.imsmg_gen_get_volume_fractions.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
+    lib.imsmg_gen_setup_seconds.argtypes = [C.c_void_p]
+    lib.imsmg_gen_setup_seconds.restype = C.c_double
+    lib.imsmg_gen_last_error.restype = C.c_char_p
+    lib.imsmg_gen_free.argtypes = [C.c_void_p]
+    _lib = lib
+    return lib
+
+
+class GenSpec(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("degree", C.c_int32), ("n", C.c_int32), ("depth", C.c_int32),
+                ("levels", C.c_int32), ("basis", C.c_int32), ("bc", C.c_int32), ("rhs", C.c_int32),
+                ("geometry", C.c_int32), ("ndiscs", C.c_int32), ("discs", C.POINTER(C.c_double)),
+                ("phase", C.c_double * 3), ("gyroid_level", C.c_double), ("box_lo", C.c_double),
+                ("box_hi", C.c_double), ("penalty_factor", C.c_double), ("q_cell", C.c_int32),
+                ("q_simplex", C.c_int32), ("q_bnd", C.c_int32), ("nthreads", C.c_int32),
+                ("with_mass", C.c_int32)]
+
+
+class LevelInfo(C.Structure):
+    _fields_ = [("n_active", C.c_int32), ("nnz", C.c_int64), ("lattice", C.c_int32 * 3),
+                ("n_elements", C.c_int32), ("nblocks", C.c_int32), ("block_nnz", C.c_int64),
+                ("r_nnz", C.c_int64), ("n_cut", C.c_int32), ("eta_min", C.c_double)]
+
+
+_BASIS = {"bspline": 0, "lagrange": 1}
+_BC = {"box_dirichlet": 0, "penalty": 1, "neumann": 2}
+_RHS = {"one": 0, "manufactured": 1, "zero": 2}
+_GEOM = {"none": 0, "discs": 1, "gyroid": 2, "star": 3}
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+@dataclass
+class GenLevel:
+    n_elements: int
+    lattice: tuple
+    dof_to_lattice: np.ndarray
+    A: sp.csr_matrix
+    R: Optional[sp.csr_matrix]            # maps this level to the next coarser one
+    block_ptr: Optional[np.ndarray]
+    block_idx: Optional[np.ndarray]
+    block_assoc: Optional[np.ndarray]
+    n_cut: int
+    eta_min: float
+    eta: Optional[np.ndarray] = None      # per-element volume fractions (x fastest)
+
+    @property
+    def n(self):
+        return self.A.shape[0]
+
+    def blocks(self) -> List[np.ndarray]:
+        return [self.block_idx[self.block_ptr[j]:self.block_ptr[j + 1]] for j in range(len(self.block_ptr) - 1)]
+
+
+@dataclass
+class GeneratedProblem:
+    workload: object
+    levels: List[GenLevel]
+    b: np.ndarray
+    M: Optional[sp.csr_matrix]
+    seconds: float
+
+    @property
+    def fine(self) -> GenLevel:
+        return self.levels[-1]
+
+
+def generate(w, with_mass: bool = False, nthreads: int = 0, orders=None) -> GeneratedProblem:
+    lib = _load()
+    spec = GenSpec()
+    spec.dim, spec.degree, spec.n, spec.depth, spec.levels = w.dim, w.degree, w.n, w.depth, w.levels
+    spec.basis, spec.bc, spec.rhs, spec.geometry = _BASIS[w.basis], _BC[w.bc], _RHS[w.rhs], _GEOM[w.geometry]
+    discs = np.ascontiguousarray(np.array(w.discs if w.discs else [[0, 0, 0]], dtype=np.float64))
+    spec.ndiscs = len(w.discs) if w.discs else 0
+    spec.discs = discs.ctypes.data_as(C.POINTER(C.c_double))
+    ph = w.phase if w.phase else [0.0, 0.0, 0.0]
+    for a in range(3):
+        spec.phase[a] = ph[a]
+    spec.gyroid_level = w.gyroid_level
+    spec.box_lo, spec.box_hi = w.box_lo, w.box_hi
+    spec.penalty_factor = w.penalty_factor
+    q = orders if orders is not None else (0, 0, 0)
+    spec.q_cell, spec.q_simplex, spec.q_bnd = q
+    spec.nthreads = nthreads
+    spec.with_mass = 1 if with_mass else 0
+    h = C.c_void_p()
+    rc = lib.imsmg_gen_build(C.byref(spec), C.byref(h))
+    if rc != 0:
+        raise RuntimeError(f"imsmg_gen_build failed ({rc}): {lib.imsmg_gen_last_error().decode()}")
+    try:
+        levels = []
+        for l in range(w.levels):
+            info = LevelInfo()
+            assert lib.imsmg_gen_level_info_get(h, l, C.byref(info)) == 0
+            n, nnz = info.n_active, info.nnz
+            d2l = np.zeros(n, dtype=np.int32)
+            rp = np.zeros(n + 1, dtype=np.int32)
+            col = np.zeros(nnz, dtype=np.int32)
+            val = np.zeros(nnz, dtype=np.float64)
+            assert lib.imsmg_gen_get_operator(h, l, _ptr(d2l), _ptr(rp), _ptr(col), _ptr(val)) == 0
+            A = sp.csr_matrix((val, col, rp), shape=(n, n))
+            R = None
+            if l > 0:
+                nc = levels[l - 1].n
+                rrp = np.zeros(nc + 1, dtype=np.int32)
+                rcol = np.zeros(info.r_nnz, dtype=np.int32)
+                rval = np.zeros(info.r_nnz, dtype=np.float64)
+                assert lib.imsmg_gen_get_restriction(h, l, _ptr(rrp), _ptr(rcol), _ptr(rval)) == 0
+                R = sp.csr_matrix((rval, rcol, rrp), shape=(nc, n))
+            bp = bi = ba = None
+            if info.nblocks > 0:
+                bp = np.zeros(info.nblocks + 1, dtype=np.int32)
+                bi = np.zeros(info.block_nnz, dtype=np.int32)
+                ba = np.zeros(info.nblocks, dtype=np.int32)
+                assert lib.imsmg_gen_get_blocks(h, l, _ptr(bp), _ptr(bi), _ptr(ba)) == 0
+            eta = np.zeros(info.n_elements ** w.dim, dtype=np.float64)
+            assert lib.imsmg_gen_get_volume_fractions(h, l, _ptr(eta)) == 0
+            levels.append(GenLevel(n_elements=info.n_elements, lattice=tuple(info.lattice[:w.dim]),
+                                   dof_to_lattice=d2l, A=A, R=R, block_ptr=bp, block_idx=bi,
+                                   block_assoc=ba, n_cut=info.n_cut, eta_min=info.eta_min, eta=eta))
+        nf = levels[-1].n
+        b = np.zeros(nf, dtype=np.float64)
+        lib.imsmg_gen_get_rhs(h, _ptr(b))
+        M = None
+        if with_mass:
+            mv = np.zeros(levels[-1].A.nnz, dtype=np.float64)
+            assert lib.imsmg_gen_get_mass(h, _ptr(mv)) == 0
+            F = levels[-1].A
+            M = sp.csr_matrix((mv, F.indices.copy(), F.indptr.copy()), shape=F.shape)
+        secs = lib.imsmg_gen_setup_seconds(h)
+    finally:
+        lib.imsmg_gen_free(h)
+    return GeneratedProblem(workload=w, levels=levels, b=b, M=M, seconds=secs)
