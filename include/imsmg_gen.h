@@ -70,6 +70,8 @@ typedef struct {
   int64_t block_nnz;     /* total block entries */
   int64_t r_nnz;         /* entries of R_l (maps this level to level-1; 0 on level 0) */
   int32_t n_cut;         /* active elements that are cut */
+  int32_t n_active_elements;
+  int64_t elem_nnz;      /* entries of the element -> active function incidence */
   double eta_min;        /* smallest volume fraction of an active element */
 } imsmg_gen_level_info;
 
@@ -83,6 +85,10 @@ int imsmg_gen_get_restriction(const imsmg_gen_problem *p, int level, int32_t *ro
                               double *val);
 /* blocks: ptr[nblocks+1], idx[block_nnz] (sorted compact indices), assoc[nblocks] */
 int imsmg_gen_get_blocks(const imsmg_gen_problem *p, int level, int32_t *ptr, int32_t *idx, int32_t *assoc);
+/* active elements in ascending element index: eptr[n_active_elements+1],
+ * eidx[elem_nnz] = compact indices of the active functions non-zero on the
+ * element (x offset fastest), elem[n_active_elements] = element index */
+int imsmg_gen_get_elements(const imsmg_gen_problem *p, int level, int32_t *eptr, int32_t *eidx, int32_t *elem);
 /* fine right-hand side b[n_active(fine)] */
 int imsmg_gen_get_rhs(const imsmg_gen_problem *p, double *b);
 /* fine mass matrix values on the fine pattern (requires with_mass) */

@@ -1,0 +1,1003 @@
+// C-ABI of the solver library: context, setup (CSR -> lattice-ELL), block
+// factorization bookkeeping, V-cycle (Algorithm alg:MGV) and CG driver.
+//
+// Host code here only converts layouts, sizes buffers and sequences kernel
+// launches; every floating-point step of factorization, smoothing, transfer,
+// coarse solve and CG runs in the HIP kernels of this directory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/imsmg.h"
+#include "imsmg_internal.h"
+
+using namespace imsmg;
+
+namespace {
+
+struct InvalidArg {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void bad(const std::string &m, int code = IMSMG_ERR_INVALID_ARG) { throw InvalidArg{code, m}; }
+
+template <typename T>
+T *dalloc(std::vector<void *> &owned, size_t count) {
+  if (count == 0) count = 1;
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw std::bad_alloc();
+  }
+  owned.push_back(p);
+  return static_cast<T *>(p);
+}
+
+template <typename T>
+void h2d(hipStream_t s, T *dst, const T *src, size_t count) {
+  if (count) HIP_CHECK_RET(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, s));
+}
+template <typename T>
+void d2h(hipStream_t s, T *dst, const T *src, size_t count) {
+  if (count) HIP_CHECK_RET(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDeviceToHost, s));
+}
+
+struct Level {
+  int n = 0;
+  int K = 0, dim = 2, reach = 0, center = 0;
+  int shape[3] = {1, 1, 1};
+  Offsets off{};
+  int64_t lattice = 0, guard = 0;
+  std::vector<int32_t> h_row_lat;
+  int32_t *row_lat = nullptr;
+  double *val = nullptr;
+  float *val32 = nullptr;
+  // padded vectors (pointers already shifted past the guard band)
+  double *r = nullptr, *x = nullptr, *rh = nullptr;
+  // restriction R_l (rows: coarse level) and R_l^T (rows: this level)
+  int rw = 0, tw = 0;
+  int32_t *rcol = nullptr, *tcol = nullptr;
+  double *rval = nullptr, *tval = nullptr;
+  // input blocks
+  std::vector<int32_t> in_ptr, in_idx;
+  std::vector<double> omega;  // optional per-block weights
+  // factorized smoother
+  std::vector<int32_t> f_ptr, f_idx;  // post-removal blocks (incl. added singletons)
+  int nb_general = 0, ntask = 0;
+  int32_t *bstart = nullptr, *bsize = nullptr, *task_block = nullptr, *blat = nullptr;
+  int64_t *binv_off = nullptr;
+  double *binv = nullptr, *bw = nullptr, *ybuf = nullptr, *c = nullptr;
+  int32_t *gptr = nullptr, *gidx = nullptr;
+  double gamma = 0.0;
+  // elements (host)
+  std::vector<int32_t> e_ptr, e_idx;
+  // coarsest level
+  double *Ainv = nullptr;
+};
+
+}  // namespace
+
+struct imsmg_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  std::vector<void *> owned;      // setup-lifetime allocations
+  std::vector<void *> factor_owned;
+  std::vector<Level> lv;
+  imsmg_options opt{};
+  bool ready = false, factored = false;
+  int32_t *zero_flag = nullptr;   // always 0: "not done" for stand-alone calls
+  CGState *st = nullptr;
+  double *part = nullptr;
+  double *p = nullptr, *q = nullptr, *xs = nullptr, *bs = nullptr;  // CG vectors (padded)
+  double *c_in = nullptr, *c_out = nullptr;                          // compact staging
+  hipGraphExec_t graph = nullptr;
+  int graph_iters = 0;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  double t_kernel_ms = 0.0;
+  int64_t t_kernel_n = 0;
+};
+
+namespace {
+
+void free_list(std::vector<void *> &v) {
+  for (void *p : v) (void)hipFree(p);
+  v.clear();
+}
+
+int fail(imsmg_ctx *c, int code, const std::string &m) {
+  if (c) c->err = m;
+  return code;
+}
+
+template <typename F>
+int guarded(imsmg_ctx *c, F &&f) {
+  if (!c) return IMSMG_ERR_INVALID_ARG;
+  try {
+    HIP_CHECK_RET(hipSetDevice(c->device));
+    int rc = f();
+    if (rc == IMSMG_OK) c->err.clear();
+    return rc;
+  } catch (const InvalidArg &e) {
+    return fail(c, e.code, e.msg);
+  } catch (const HipFailure &e) {
+    return fail(c, IMSMG_ERR_HIP, e.msg);
+  } catch (const std::bad_alloc &) {
+    return fail(c, IMSMG_ERR_OOM, "out of device or host memory");
+  } catch (const std::exception &e) {
+    return fail(c, IMSMG_ERR_INVALID_ARG, e.what());
+  }
+}
+
+int64_t lat_linear(const int *m, const int *shape, int dim) {
+  int64_t L = 0;
+  for (int a = dim - 1; a >= 0; --a) L = L * shape[a] + m[a];
+  return L;
+}
+
+void lat_multi(int64_t L, const int *shape, int dim, int *m) {
+  for (int a = 0; a < dim; ++a) {
+    m[a] = int(L % shape[a]);
+    L /= shape[a];
+  }
+}
+
+// ------------------------------------------------------------------ setup
+void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice &lat) {
+  hipStream_t s = c->stream;
+  if (lat.dim < 2 || lat.dim > 3) bad("lattice dim must be 2 or 3");
+  if (lat.reach < 1 || lat.reach > 3) bad("lattice reach must be 1..3");
+  if (A.nrows <= 0 || A.nrows != A.ncols) bad("A must be square and non-empty");
+  if (!A.rowptr || !A.col || !A.val || !lat.dof_to_lattice) bad("null CSR or lattice array");
+  L.dim = lat.dim;
+  L.reach = lat.reach;
+  int64_t latsz = 1;
+  for (int a = 0; a < 3; ++a) {
+    L.shape[a] = a < lat.dim ? lat.shape[a] : 1;
+    if (L.shape[a] < 1) bad("lattice shape must be positive");
+    latsz *= L.shape[a];
+  }
+  if (latsz > (int64_t(1) << 30)) bad("lattice too large");
+  L.lattice = latsz;
+  L.n = A.nrows;
+  const int W = 2 * L.reach + 1;
+  L.K = L.dim == 2 ? W * W : W * W * W;
+  if (L.K > IMSMG_MAX_SLOTS) bad("stencil too large");
+  // slot offsets (x fastest)
+  int64_t maxoff = 0;
+  for (int sl = 0; sl < L.K; ++sl) {
+    int o[3] = {0, 0, 0}, r = sl;
+    for (int a = 0; a < L.dim; ++a) {
+      o[a] = r % W - L.reach;
+      r /= W;
+    }
+    int64_t lin = o[0] + int64_t(L.shape[0]) * (o[1] + int64_t(L.shape[1]) * o[2]);
+    L.off.off[sl] = int32_t(lin);
+    maxoff = std::max<int64_t>(maxoff, lin < 0 ? -lin : lin);
+    if (lin == 0) L.center = sl;
+  }
+  L.guard = maxoff + 64;
+  L.h_row_lat.assign(lat.dof_to_lattice, lat.dof_to_lattice + L.n);
+  for (int i = 0; i < L.n; ++i) {
+    if (L.h_row_lat[i] < 0 || L.h_row_lat[i] >= latsz) bad("dof_to_lattice out of range");
+    if (i && L.h_row_lat[i] <= L.h_row_lat[i - 1]) bad("dof_to_lattice must be strictly increasing");
+  }
+  // CSR -> slot-major lattice-ELL
+  if (A.rowptr[0] != 0 || A.rowptr[L.n] != A.nnz) bad("CSR rowptr inconsistent with nnz");
+  std::vector<double> ell(size_t(L.K) * L.n, 0.0);
+  for (int i = 0; i < L.n; ++i) {
+    int mi[3] = {0, 0, 0};
+    lat_multi(L.h_row_lat[i], L.shape, L.dim, mi);
+    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+      const int j = A.col[k];
+      if (j < 0 || j >= L.n) bad("CSR column out of range");
+      int mj[3] = {0, 0, 0};
+      lat_multi(L.h_row_lat[j], L.shape, L.dim, mj);
+      int sl = 0;
+      for (int a = L.dim - 1; a >= 0; --a) {
+        const int d = mj[a] - mi[a];
+        if (d < -L.reach || d > L.reach) bad("CSR entry outside the lattice stencil");
+        sl = sl * W + (d + L.reach);
+      }
+      ell[size_t(sl) * L.n + i] = A.val[k];
+    }
+  }
+  L.row_lat = dalloc<int32_t>(c->owned, L.n);
+  h2d(s, L.row_lat, L.h_row_lat.data(), L.n);
+  L.val = dalloc<double>(c->owned, ell.size());
+  h2d(s, L.val, ell.data(), ell.size());
+  if (c->opt.precision == IMSMG_MIXED) {
+    std::vector<float> e32(ell.begin(), ell.end());
+    L.val32 = dalloc<float>(c->owned, e32.size());
+    h2d(s, L.val32, e32.data(), e32.size());
+    HIP_CHECK_RET(hipStreamSynchronize(s));
+  }
+  const size_t vlen = size_t(L.lattice + 2 * L.guard);
+  double *vs[3];
+  for (int k = 0; k < 3; ++k) {
+    double *b = dalloc<double>(c->owned, vlen);
+    HIP_CHECK_RET(hipMemsetAsync(b, 0, vlen * sizeof(double), s));
+    vs[k] = b + L.guard;
+  }
+  L.r = vs[0];
+  L.x = vs[1];
+  L.rh = vs[2];
+  HIP_CHECK_RET(hipStreamSynchronize(s));
+}
+
+// R (coarse x fine, compact) -> ELL on coarse rows with fine lattice columns,
+// and R^T ELL on fine rows with coarse lattice columns.
+void setup_transfer(imsmg_ctx *c, Level &F, const Level &Cl, const imsmg_csr &R) {
+  hipStream_t s = c->stream;
+  if (R.nrows != Cl.n || R.ncols != F.n) bad("R shape must be n_{l-1} x n_l");
+  if (!R.rowptr || !R.col || !R.val) bad("null R array");
+  if (R.rowptr[0] != 0 || R.rowptr[R.nrows] != R.nnz) bad("R rowptr inconsistent with nnz");
+  int rw = 0;
+  for (int i = 0; i < R.nrows; ++i) rw = std::max<int>(rw, int(R.rowptr[i + 1] - R.rowptr[i]));
+  std::vector<int32_t> cnt(F.n, 0);
+  for (int64_t k = 0; k < R.nnz; ++k) {
+    if (R.col[k] < 0 || R.col[k] >= F.n) bad("R column out of range");
+    cnt[R.col[k]]++;
+  }
+  int tw = 0;
+  for (int i = 0; i < F.n; ++i) tw = std::max(tw, cnt[i]);
+  rw = std::max(rw, 1);
+  tw = std::max(tw, 1);
+  // padding entries: value 0 at the row's own first column (any in-range index)
+  std::vector<int32_t> rcol(size_t(rw) * Cl.n, int32_t(F.h_row_lat[0]));
+  std::vector<double> rval(size_t(rw) * Cl.n, 0.0);
+  std::vector<int32_t> tcol(size_t(tw) * F.n, int32_t(Cl.h_row_lat[0]));
+  std::vector<double> tval(size_t(tw) * F.n, 0.0);
+  std::vector<int32_t> fill(F.n, 0);
+  for (int i = 0; i < Cl.n; ++i) {
+    int slot = 0;
+    for (int64_t k = R.rowptr[i]; k < R.rowptr[i + 1]; ++k, ++slot) {
+      const int j = R.col[k];
+      rcol[size_t(slot) * Cl.n + i] = F.h_row_lat[j];
+      rval[size_t(slot) * Cl.n + i] = R.val[k];
+      const int ts = fill[j]++;
+      tcol[size_t(ts) * F.n + j] = Cl.h_row_lat[i];
+      tval[size_t(ts) * F.n + j] = R.val[k];
+    }
+  }
+  F.rw = rw;
+  F.tw = tw;
+  F.rcol = dalloc<int32_t>(c->owned, rcol.size());
+  F.rval = dalloc<double>(c->owned, rval.size());
+  F.tcol = dalloc<int32_t>(c->owned, tcol.size());
+  F.tval = dalloc<double>(c->owned, tval.size());
+  h2d(s, F.rcol, rcol.data(), rcol.size());
+  h2d(s, F.rval, rval.data(), rval.size());
+  h2d(s, F.tcol, tcol.data(), tcol.size());
+  h2d(s, F.tval, tval.data(), tval.size());
+  HIP_CHECK_RET(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------ V-cycle
+void residual(imsmg_ctx *c, Level &L, const double *x, const double *b, double *y, const int32_t *done,
+              bool timed) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed) {
+    if (c->ev_used + 2 > c->ev_pool.size()) {
+      for (int k = 0; k < 64; ++k) {
+        hipEvent_t e;
+        HIP_CHECK_RET(hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+      }
+    }
+    e0 = c->ev_pool[c->ev_used++];
+    e1 = c->ev_pool[c->ev_used++];
+    HIP_CHECK_RET(hipEventRecord(e0, c->stream));
+  }
+  if (c->opt.precision == IMSMG_MIXED && L.val32)
+    launch_ell_residual_f32(c->stream, L.n, L.K, L.off, L.row_lat, L.val32, x, b, y, done);
+  else
+    launch_ell_residual(c->stream, L.n, L.K, L.off, L.row_lat, L.val, x, b, y, done);
+  if (timed) HIP_CHECK_RET(hipEventRecord(e1, c->stream));
+}
+
+void smooth(imsmg_ctx *c, Level &L, const double *r, double *x, int accumulate, const int32_t *done) {
+  launch_schwarz_blocks(c->stream, L.ntask, L.task_block, L.bstart, L.bsize, L.binv_off, L.blat, L.binv, L.bw, r,
+                        L.ybuf, done);
+  launch_schwarz_gather(c->stream, L.n, L.row_lat, L.c, L.gptr, L.gidx, L.ybuf, r, x, accumulate, done);
+}
+
+// V-cycle on level l: input residual in lv[l].r, correction out in lv[l].x
+void vcycle_level(imsmg_ctx *c, int l, const int32_t *done, bool timing) {
+  Level &L = c->lv[l];
+  if (l == 0) {
+    launch_dense_gemv(c->stream, L.n, L.row_lat, L.Ainv, L.r, L.x, done);
+    return;
+  }
+  Level &Cl = c->lv[l - 1];
+  const bool fine = (l == int(c->lv.size()) - 1) && timing;
+  smooth(c, L, L.r, L.x, 0, done);
+  for (int k = 1; k < c->opt.nu_pre; ++k) {
+    residual(c, L, L.x, L.r, L.rh, done, fine);
+    smooth(c, L, L.rh, L.x, 1, done);
+  }
+  residual(c, L, L.x, L.r, L.rh, done, fine);
+  launch_ell_gather(c->stream, Cl.n, L.rw, Cl.row_lat, L.rcol, L.rval, L.rh, Cl.r, 0, done);
+  vcycle_level(c, l - 1, done, timing);
+  launch_ell_gather(c->stream, L.n, L.tw, L.row_lat, L.tcol, L.tval, Cl.x, L.x, 1, done);
+  for (int k = 0; k < c->opt.nu_post; ++k) {
+    residual(c, L, L.x, L.r, L.rh, done, fine);
+    smooth(c, L, L.rh, L.x, 1, done);
+  }
+}
+
+void collect_timing(imsmg_ctx *c) {
+  for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+    float ms = 0.f;
+    HIP_CHECK_RET(hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
+    c->t_kernel_ms += ms;
+    c->t_kernel_n += 1;
+  }
+  c->ev_used = 0;
+}
+
+// ------------------------------------------------------------- factorization
+void factor_level(imsmg_ctx *c, int l) {
+  hipStream_t s = c->stream;
+  Level &L = c->lv[l];
+  const int nb_in = int(L.in_ptr.size()) - 1;
+  const int n = L.n;
+  // which input blocks need the eigensolver (size >= 2)
+  std::vector<int32_t> fac_blocks;
+  int maxn = 1;
+  for (int j = 0; j < nb_in; ++j) {
+    const int sz = L.in_ptr[j + 1] - L.in_ptr[j];
+    if (sz >= 2) {
+      fac_blocks.push_back(j);
+      maxn = std::max(maxn, sz);
+    }
+  }
+  if (maxn > IMSMG_MAX_BLOCK)
+    bad("Schwarz block of size " + std::to_string(maxn) + " exceeds the supported " +
+        std::to_string(IMSMG_MAX_BLOCK));
+  const int nf = int(fac_blocks.size());
+  std::vector<int32_t> h_bstart(nf + 1, 0), h_bsize(nf), h_blat, h_brow;
+  std::vector<int64_t> h_invoff(nf + 1, 0);
+  for (int t = 0; t < nf; ++t) {
+    const int j = fac_blocks[t];
+    const int sz = L.in_ptr[j + 1] - L.in_ptr[j];
+    h_bsize[t] = sz;
+    h_bstart[t + 1] = h_bstart[t] + sz;
+    h_invoff[t + 1] = h_invoff[t] + int64_t(sz) * sz;
+    for (int k = L.in_ptr[j]; k < L.in_ptr[j + 1]; ++k) {
+      h_brow.push_back(L.in_idx[k]);
+      h_blat.push_back(L.h_row_lat[L.in_idx[k]]);
+    }
+  }
+  std::vector<void *> tmp;
+  struct TmpFree {
+    std::vector<void *> &v;
+    ~TmpFree() { free_list(v); }
+  } tf{tmp};
+  int32_t *d_bstart = dalloc<int32_t>(tmp, nf + 1), *d_bsize = dalloc<int32_t>(tmp, nf);
+  int32_t *d_blat = dalloc<int32_t>(tmp, h_blat.size()), *d_brow = dalloc<int32_t>(tmp, h_brow.size());
+  int64_t *d_invoff = dalloc<int64_t>(c->factor_owned, nf + 1);
+  double *d_inv = dalloc<double>(c->factor_owned, size_t(h_invoff[nf]));
+  uint8_t *d_keep = dalloc<uint8_t>(tmp, h_blat.size());
+  double *d_lam = dalloc<double>(tmp, 2 * size_t(nf));
+  int32_t *d_info = dalloc<int32_t>(tmp, nf);
+  h2d(s, d_bstart, h_bstart.data(), nf + 1);
+  h2d(s, d_bsize, h_bsize.data(), nf);
+  h2d(s, d_blat, h_blat.data(), h_blat.size());
+  h2d(s, d_brow, h_brow.data(), h_brow.size());
+  h2d(s, d_invoff, h_invoff.data(), nf + 1);
+  if (launch_block_factor_geom(s, nf, maxn, d_bstart, d_bsize, d_blat, d_brow, n, L.dim, L.shape[0], L.shape[1],
+                               L.reach, L.val, d_inv, d_invoff, d_keep, d_lam, d_info, 1e-16) != 0)
+    bad("block factorization launch rejected");
+  HIP_CHECK_RET(hipGetLastError());
+  std::vector<uint8_t> keep(h_blat.size());
+  std::vector<int32_t> info(nf);
+  d2h(s, keep.data(), d_keep, keep.size());
+  d2h(s, info.data(), d_info, info.size());
+  HIP_CHECK_RET(hipStreamSynchronize(s));
+  // diagonal of A for singleton checks
+  // final block lists: kept members of every input block, then singletons
+  // for DOFs left in no block
+  std::vector<int32_t> fptr(1, 0), fidx, forig;  // forig: input block index or -1 (added)
+  std::vector<int64_t> finvoff;                   // inverse offset for factorized blocks, -1 otherwise
+  std::vector<char> covered(n, 0);
+  int t = 0;
+  for (int j = 0; j < nb_in; ++j) {
+    const int sz = L.in_ptr[j + 1] - L.in_ptr[j];
+    if (sz >= 2) {
+      int kept = 0;
+      for (int a = 0; a < sz; ++a)
+        if (keep[h_bstart[t] + a]) {
+          fidx.push_back(L.in_idx[L.in_ptr[j] + a]);
+          covered[L.in_idx[L.in_ptr[j] + a]] = 1;
+          ++kept;
+        }
+      if (kept != info[t]) bad("internal: factorization bookkeeping mismatch", IMSMG_ERR_HIP);
+      finvoff.push_back(h_invoff[t]);
+      ++t;
+    } else if (sz == 1) {
+      fidx.push_back(L.in_idx[L.in_ptr[j]]);
+      covered[L.in_idx[L.in_ptr[j]]] = 1;
+      finvoff.push_back(-1);
+    } else {
+      finvoff.push_back(-1);
+    }
+    fptr.push_back(int32_t(fidx.size()));
+    forig.push_back(j);
+  }
+  for (int i = 0; i < n; ++i)
+    if (!covered[i]) {
+      fidx.push_back(i);
+      fptr.push_back(int32_t(fidx.size()));
+      forig.push_back(-1);
+      finvoff.push_back(-1);
+    }
+  L.f_ptr = fptr;
+  L.f_idx = fidx;
+  const int nbf = int(fptr.size()) - 1;
+  // number of final blocks holding each DOF
+  std::vector<int32_t> fcount(n, 0);
+  for (int32_t i : fidx) fcount[i]++;
+  // N_K -> gamma
+  double gamma = c->opt.gamma;
+  if (gamma <= 0.0) {
+    if (L.e_ptr.empty()) bad("gamma <= 0 needs the element incidence of every smoothed level");
+    std::vector<int32_t> fp(n + 1, 0), fb(fidx.size());
+    for (int32_t i : fidx) fp[i + 1]++;
+    for (int i = 0; i < n; ++i) fp[i + 1] += fp[i];
+    std::vector<int32_t> fill(fp.begin(), fp.end() - 1);
+    for (int j = 0; j < nbf; ++j)
+      for (int k = fptr[j]; k < fptr[j + 1]; ++k) fb[fill[fidx[k]]++] = j;
+    const int nel = int(L.e_ptr.size()) - 1;
+    int32_t *d_eptr = dalloc<int32_t>(tmp, nel + 1), *d_eidx = dalloc<int32_t>(tmp, L.e_idx.size());
+    int32_t *d_fp = dalloc<int32_t>(tmp, n + 1), *d_fb = dalloc<int32_t>(tmp, fb.size());
+    int32_t *d_nk = dalloc<int32_t>(tmp, nel), *d_ovf = dalloc<int32_t>(tmp, 1);
+    h2d(s, d_eptr, L.e_ptr.data(), nel + 1);
+    h2d(s, d_eidx, L.e_idx.data(), L.e_idx.size());
+    h2d(s, d_fp, fp.data(), n + 1);
+    h2d(s, d_fb, fb.data(), fb.size());
+    HIP_CHECK_RET(hipMemsetAsync(d_ovf, 0, sizeof(int32_t), s));
+    launch_count_nk(s, nel, d_eptr, d_eidx, d_fp, d_fb, d_nk, d_ovf);
+    HIP_CHECK_RET(hipGetLastError());
+    std::vector<int32_t> nk(nel);
+    int32_t ovf = 0;
+    d2h(s, nk.data(), d_nk, nel);
+    d2h(s, &ovf, d_ovf, 1);
+    HIP_CHECK_RET(hipStreamSynchronize(s));
+    if (ovf) bad("N_K count overflow (more than 128 blocks touch one element)");
+    int mx = 1;
+    for (int v : nk) mx = std::max(mx, v);
+    gamma = 1.0 / mx;
+  }
+  L.gamma = gamma;
+  // per final block weight
+  std::vector<double> w(nbf, gamma);
+  if (!L.omega.empty())
+    for (int j = 0; j < nbf; ++j)
+      if (forig[j] >= 0) w[j] = L.omega[forig[j]];
+  // trivial rows: the DOF's only block is its own singleton
+  std::vector<int32_t> trivial(n, -1);
+  std::vector<char> general(nbf, 0);
+  for (int j = 0; j < nbf; ++j) {
+    const int sz = fptr[j + 1] - fptr[j];
+    if (sz == 0) continue;
+    if (sz == 1 && fcount[fidx[fptr[j]]] == 1) trivial[fidx[fptr[j]]] = j;
+    else general[j] = 1;
+  }
+  // general blocks: singletons that share their DOF with another block need
+  // an inverse too; they get 1/A_ii through a factorized copy below
+  std::vector<int32_t> g_start(1, 0), g_size, g_lat, g_task_block;
+  std::vector<int64_t> g_invoff;
+  std::vector<double> g_w;
+  std::vector<int32_t> single_rows;  // general singletons needing 1/A_ii
+  std::vector<int64_t> single_off;
+  int64_t extra_off = h_invoff[nf];
+  for (int j = 0; j < nbf; ++j) {
+    if (!general[j]) continue;
+    const int sz = fptr[j + 1] - fptr[j];
+    const int gb = int(g_size.size());
+    g_size.push_back(sz);
+    g_w.push_back(w[j]);
+    for (int k = fptr[j]; k < fptr[j + 1]; ++k) {
+      g_lat.push_back(L.h_row_lat[fidx[k]]);
+      g_task_block.push_back(gb);
+    }
+    g_start.push_back(g_start.back() + sz);
+    if (finvoff[j] >= 0) {
+      g_invoff.push_back(finvoff[j]);
+    } else {
+      if (sz != 1) bad("internal: unfactorized general block", IMSMG_ERR_HIP);
+      g_invoff.push_back(extra_off);
+      single_rows.push_back(fidx[fptr[j]]);
+      single_off.push_back(extra_off);
+      extra_off += 1;
+    }
+  }
+  const int ng = int(g_size.size());
+  L.nb_general = ng;
+  L.ntask = g_start.back();
+  // inverse storage: factorized inverses followed by general singletons
+  double *inv = d_inv;
+  if (!single_rows.empty()) {
+    inv = dalloc<double>(c->factor_owned, size_t(extra_off));
+    HIP_CHECK_RET(hipMemcpyAsync(inv, d_inv, size_t(h_invoff[nf]) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // 1/A_ii through the diag-coefficient kernel with unit weight
+    const int ns = int(single_rows.size());
+    std::vector<int32_t> tb(n, -1);
+    std::vector<double> one(ns, 1.0);
+    for (int k = 0; k < ns; ++k) tb[single_rows[k]] = k;
+    int32_t *d_tb = dalloc<int32_t>(tmp, n);
+    double *d_one = dalloc<double>(tmp, ns), *d_c = dalloc<double>(tmp, n);
+    h2d(s, d_tb, tb.data(), n);
+    h2d(s, d_one, one.data(), ns);
+    launch_diag_coef(s, n, L.K, L.center, d_tb, L.val, d_one, d_c);
+    std::vector<double> cvals(n);
+    d2h(s, cvals.data(), d_c, n);
+    HIP_CHECK_RET(hipStreamSynchronize(s));
+    for (int k = 0; k < ns; ++k) {
+      const double v = cvals[single_rows[k]];
+      if (!(v > 0.0) || !std::isfinite(v)) bad("non-positive diagonal entry", IMSMG_ERR_NOT_SPD);
+      HIP_CHECK_RET(hipMemcpyAsync(inv + single_off[k], &cvals[single_rows[k]], sizeof(double),
+                                   hipMemcpyHostToDevice, s));
+    }
+    HIP_CHECK_RET(hipStreamSynchronize(s));
+  }
+  L.binv = inv;
+  L.bstart = dalloc<int32_t>(c->factor_owned, g_start.size());
+  L.bsize = dalloc<int32_t>(c->factor_owned, g_size.size());
+  L.blat = dalloc<int32_t>(c->factor_owned, g_lat.size());
+  L.task_block = dalloc<int32_t>(c->factor_owned, g_task_block.size());
+  L.binv_off = dalloc<int64_t>(c->factor_owned, g_invoff.size());
+  L.bw = dalloc<double>(c->factor_owned, g_w.size());
+  L.ybuf = dalloc<double>(c->factor_owned, L.ntask);
+  h2d(s, L.bstart, g_start.data(), g_start.size());
+  h2d(s, L.bsize, g_size.data(), g_size.size());
+  h2d(s, L.blat, g_lat.data(), g_lat.size());
+  h2d(s, L.task_block, g_task_block.data(), g_task_block.size());
+  h2d(s, L.binv_off, g_invoff.data(), g_invoff.size());
+  h2d(s, L.bw, g_w.data(), g_w.size());
+  // gather map: row -> task positions (ascending)
+  std::vector<int32_t> gp(n + 1, 0), gi(L.ntask);
+  for (int tk = 0; tk < L.ntask; ++tk) {
+    (void)tk;
+  }
+  {
+    std::vector<int32_t> task_row(L.ntask);
+    int tk = 0;
+    for (int j = 0; j < nbf; ++j) {
+      if (!general[j]) continue;
+      for (int k = fptr[j]; k < fptr[j + 1]; ++k) task_row[tk++] = fidx[k];
+    }
+    for (int k = 0; k < L.ntask; ++k) gp[task_row[k] + 1]++;
+    for (int i = 0; i < n; ++i) gp[i + 1] += gp[i];
+    std::vector<int32_t> fill(gp.begin(), gp.end() - 1);
+    for (int k = 0; k < L.ntask; ++k) gi[fill[task_row[k]]++] = k;
+  }
+  L.gptr = dalloc<int32_t>(c->factor_owned, n + 1);
+  L.gidx = dalloc<int32_t>(c->factor_owned, gi.size());
+  h2d(s, L.gptr, gp.data(), n + 1);
+  h2d(s, L.gidx, gi.data(), gi.size());
+  // trivial rows: c_i = w_j / A_ii
+  std::vector<int32_t> tb(n, -1);
+  std::vector<double> wt(nbf, 0.0);
+  for (int i = 0; i < n; ++i)
+    if (trivial[i] >= 0) tb[i] = trivial[i];
+  int32_t *d_tb = dalloc<int32_t>(tmp, n);
+  double *d_w = dalloc<double>(tmp, nbf);
+  h2d(s, d_tb, tb.data(), n);
+  h2d(s, d_w, w.data(), nbf);
+  L.c = dalloc<double>(c->factor_owned, n);
+  launch_diag_coef(s, n, L.K, L.center, d_tb, L.val, d_w, L.c);
+  HIP_CHECK_RET(hipGetLastError());
+  HIP_CHECK_RET(hipStreamSynchronize(s));
+}
+
+void factor_coarsest(imsmg_ctx *c) {
+  hipStream_t s = c->stream;
+  Level &L = c->lv[0];
+  const int n = L.n;
+  if (n > 8192) bad("coarsest level larger than 8192 unknowns; use more levels");
+  std::vector<int32_t> lat2c(size_t(L.lattice + 2 * L.guard), -1);
+  for (int i = 0; i < n; ++i) lat2c[size_t(L.h_row_lat[i] + L.guard)] = i;
+  std::vector<void *> tmp;
+  struct TmpFree {
+    std::vector<void *> &v;
+    ~TmpFree() { free_list(v); }
+  } tf{tmp};
+  int32_t *d_l2c = dalloc<int32_t>(tmp, lat2c.size());
+  h2d(s, d_l2c, lat2c.data(), lat2c.size());
+  L.Ainv = dalloc<double>(c->factor_owned, size_t(n) * n);
+  HIP_CHECK_RET(hipMemsetAsync(L.Ainv, 0, size_t(n) * n * sizeof(double), s));
+  launch_dense_from_ell(s, n, L.K, L.off, L.row_lat, d_l2c + L.guard, L.val, L.Ainv);
+  double *colk = dalloc<double>(tmp, n), *rowk = dalloc<double>(tmp, n);
+  for (int k = 0; k < n; ++k) launch_gauss_jordan_step(s, n, k, L.Ainv, colk, rowk);
+  HIP_CHECK_RET(hipGetLastError());
+  // the inverse of an SPD matrix has a positive, finite diagonal
+  std::vector<double> diag(n);
+  for (int i = 0; i < n; ++i)
+    HIP_CHECK_RET(hipMemcpyAsync(&diag[i], L.Ainv + size_t(i) * n + i, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_CHECK_RET(hipStreamSynchronize(s));
+  for (int i = 0; i < n; ++i)
+    if (!(diag[i] > 0.0) || !std::isfinite(diag[i])) bad("coarsest operator is not SPD", IMSMG_ERR_NOT_SPD);
+}
+
+void destroy_graph(imsmg_ctx *c) {
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  c->graph_iters = 0;
+}
+
+// One CG iteration after the initial residual: z = B r, beta, p, q = A p, alpha, x, r.
+void cg_iteration(imsmg_ctx *c, bool timing) {
+  Level &F = c->lv.back();
+  const int32_t *done = &c->st->done;
+  vcycle_level(c, int(c->lv.size()) - 1, done, timing);
+  launch_cg_dot_rz(c->stream, F.n, F.row_lat, F.r, F.x, c->part, c->st);
+  launch_cg_direction(c->stream, F.n, F.row_lat, F.x, c->p, c->st);
+  launch_cg_spmv_pq(c->stream, F.n, F.K, F.off, F.row_lat, F.val, c->p, c->q, c->part, c->st);
+  launch_cg_update(c->stream, F.n, F.row_lat, c->p, c->q, c->xs, F.r, c->part, c->st, c->opt.max_iter);
+}
+
+}  // namespace
+
+extern "C" {
+
+void imsmg_default_options(imsmg_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = IMSMG_FP64;
+  o->nu_pre = 1;
+  o->nu_post = 1;
+  o->max_iter = 500;
+  o->check_every = 4;
+  o->use_graph = 1;
+  o->timing = 0;
+  o->gamma = 0.0;
+}
+
+int imsmg_create(imsmg_ctx **out, int device, void *stream) {
+  if (!out) return IMSMG_ERR_INVALID_ARG;
+  *out = nullptr;
+  imsmg_ctx *c = nullptr;
+  try {
+    c = new imsmg_ctx();
+  } catch (...) {
+    return IMSMG_ERR_OOM;
+  }
+  c->device = device;
+  imsmg_default_options(&c->opt);
+  int rc = guarded(c, [&]() {
+    int ndev = 0;
+    HIP_CHECK_RET(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) bad("no such device");
+    if (stream) {
+      c->stream = static_cast<hipStream_t>(stream);
+    } else {
+      HIP_CHECK_RET(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+    return IMSMG_OK;
+  });
+  if (rc != IMSMG_OK) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return IMSMG_OK;
+}
+
+int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *R, const imsmg_patches *P,
+                const imsmg_lattice *Lt, const imsmg_elements *E, const imsmg_options *opt) {
+  return guarded(c, [&]() -> int {
+    if (nlevels < 1 || nlevels > 16 || !A || !Lt) bad("bad level count or null arrays");
+    if (nlevels > 1 && (!R || !P)) bad("R and P are required with more than one level");
+    destroy_graph(c);
+    free_list(c->factor_owned);
+    free_list(c->owned);
+    c->lv.clear();
+    c->ready = c->factored = false;
+    if (opt) c->opt = *opt;
+    if (c->opt.nu_pre < 1 || c->opt.nu_post < 1 || c->opt.max_iter < 1) bad("nu and max_iter must be >= 1");
+    if (c->opt.check_every < 1) c->opt.check_every = 1;
+    if (c->opt.precision != IMSMG_FP64 && c->opt.precision != IMSMG_MIXED) bad("unknown precision mode");
+    c->lv.resize(nlevels);
+    for (int l = 0; l < nlevels; ++l) {
+      if (Lt[l].dim != Lt[nlevels - 1].dim) bad("all levels must share the dimension");
+      setup_level(c, c->lv[l], A[l], Lt[l]);
+    }
+    for (int l = 1; l < nlevels; ++l) setup_transfer(c, c->lv[l], c->lv[l - 1], R[l]);
+    for (int l = 1; l < nlevels; ++l) {
+      Level &L = c->lv[l];
+      const imsmg_patches &p = P[l];
+      if (p.nblocks < 0 || (p.nblocks > 0 && (!p.ptr || !p.idx))) bad("bad patch arrays");
+      L.in_ptr.assign(p.ptr, p.ptr + p.nblocks + 1);
+      if (L.in_ptr[0] != 0) bad("patch ptr must start at 0");
+      for (int j = 0; j < p.nblocks; ++j)
+        if (L.in_ptr[j + 1] < L.in_ptr[j]) bad("patch ptr must be non-decreasing");
+      L.in_idx.assign(p.idx, p.idx + L.in_ptr[p.nblocks]);
+      for (int j = 0; j < p.nblocks; ++j)
+        for (int k = L.in_ptr[j]; k < L.in_ptr[j + 1]; ++k) {
+          if (L.in_idx[k] < 0 || L.in_idx[k] >= L.n) bad("patch index out of range");
+          if (k > L.in_ptr[j] && L.in_idx[k] <= L.in_idx[k - 1]) bad("patch indices must be sorted and unique");
+        }
+      if (E) {
+        const imsmg_elements &e = E[l];
+        if (e.nelements < 0 || (e.nelements > 0 && (!e.eptr || !e.eidx))) bad("bad element arrays");
+        L.e_ptr.assign(e.eptr, e.eptr + e.nelements + 1);
+        L.e_idx.assign(e.eidx, e.eidx + L.e_ptr.back());
+        for (int32_t f : L.e_idx)
+          if (f < 0 || f >= L.n) bad("element function index out of range");
+      }
+    }
+    Level &F = c->lv.back();
+    const size_t vlen = size_t(F.lattice + 2 * F.guard);
+    double *vv[4];
+    for (int k = 0; k < 4; ++k) {
+      vv[k] = dalloc<double>(c->owned, vlen);
+      HIP_CHECK_RET(hipMemsetAsync(vv[k], 0, vlen * sizeof(double), c->stream));
+    }
+    c->p = vv[0] + F.guard;
+    c->q = vv[1] + F.guard;
+    c->xs = vv[2] + F.guard;
+    c->bs = vv[3] + F.guard;
+    c->c_in = dalloc<double>(c->owned, F.n);
+    c->c_out = dalloc<double>(c->owned, F.n);
+    c->zero_flag = dalloc<int32_t>(c->owned, 1);
+    HIP_CHECK_RET(hipMemsetAsync(c->zero_flag, 0, sizeof(int32_t), c->stream));
+    c->st = dalloc<CGState>(c->owned, 1);
+    HIP_CHECK_RET(hipMemsetAsync(c->st, 0, sizeof(CGState), c->stream));
+    c->part = dalloc<double>(c->owned, 2 * 4096);
+    HIP_CHECK_RET(hipStreamSynchronize(c->stream));
+    c->ready = true;
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_set_patch_weights(imsmg_ctx *c, int level, const double *omega) {
+  return guarded(c, [&]() -> int {
+    if (!c->ready) bad("setup first", IMSMG_ERR_STATE);
+    if (level < 1 || level >= int(c->lv.size()) || !omega) bad("bad level or null weights");
+    Level &L = c->lv[level];
+    const int nb = int(L.in_ptr.size()) - 1;
+    for (int j = 0; j < nb; ++j)
+      if (!(omega[j] > 0.0) || !std::isfinite(omega[j])) bad("weights must be positive and finite");
+    L.omega.assign(omega, omega + nb);
+    c->factored = false;
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_factor_patches(imsmg_ctx *c) {
+  return guarded(c, [&]() -> int {
+    if (!c->ready) bad("setup first", IMSMG_ERR_STATE);
+    destroy_graph(c);
+    free_list(c->factor_owned);
+    c->factored = false;
+    for (int l = 1; l < int(c->lv.size()); ++l) factor_level(c, l);
+    factor_coarsest(c);
+    c->factored = true;
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_get_patches(imsmg_ctx *c, int level, int32_t *nblocks, int64_t *nnz, int32_t *ptr, int32_t *idx) {
+  return guarded(c, [&]() -> int {
+    if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    if (level < 1 || level >= int(c->lv.size())) bad("bad level");
+    const Level &L = c->lv[level];
+    if (nblocks) *nblocks = int32_t(L.f_ptr.size()) - 1;
+    if (nnz) *nnz = int64_t(L.f_idx.size());
+    if (ptr) std::copy(L.f_ptr.begin(), L.f_ptr.end(), ptr);
+    if (idx) std::copy(L.f_idx.begin(), L.f_idx.end(), idx);
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_get_gamma(imsmg_ctx *c, int level, double *gamma) {
+  return guarded(c, [&]() -> int {
+    if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    if (level < 1 || level >= int(c->lv.size()) || !gamma) bad("bad level");
+    *gamma = c->lv[level].gamma;
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_vcycle(imsmg_ctx *c, const double *r_dev, double *z_dev) {
+  return guarded(c, [&]() -> int {
+    if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    if (!r_dev || !z_dev) bad("null vector");
+    Level &F = c->lv.back();
+    launch_scatter(c->stream, F.n, F.row_lat, r_dev, F.r);
+    vcycle_level(c, int(c->lv.size()) - 1, c->zero_flag, c->opt.timing != 0);
+    launch_gather(c->stream, F.n, F.row_lat, F.x, z_dev);
+    HIP_CHECK_RET(hipGetLastError());
+    HIP_CHECK_RET(hipStreamSynchronize(c->stream));
+    if (c->opt.timing) collect_timing(c);
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_pcg_solve(imsmg_ctx *c, const double *b_dev, double *x_dev, double rtol, imsmg_info *info) {
+  return guarded(c, [&]() -> int {
+    if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    if (!b_dev || !x_dev) bad("null vector");
+    if (!(rtol > 0.0)) bad("rtol must be positive");
+    auto t0 = std::chrono::steady_clock::now();
+    Level &F = c->lv.back();
+    hipStream_t s = c->stream;
+    const bool timing = c->opt.timing != 0;
+    launch_scatter(s, F.n, F.row_lat, b_dev, c->bs);
+    launch_scatter(s, F.n, F.row_lat, x_dev, c->xs);
+    CGState h{};
+    int restarts = 0;
+    while (true) {
+      launch_cg_init(s, F.n, F.K, F.off, F.row_lat, F.val, c->xs, c->bs, F.r, c->part, c->st, rtol);
+      HIP_CHECK_RET(hipGetLastError());
+      const int m = c->opt.check_every;
+      const bool graph = c->opt.use_graph && !timing;
+      if (graph && !c->graph) {
+        hipGraph_t g = nullptr;
+        HIP_CHECK_RET(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < m; ++k) cg_iteration(c, false);
+        HIP_CHECK_RET(hipStreamEndCapture(s, &g));
+        hipError_t e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIP_CHECK_RET(e);
+        c->graph_iters = m;
+      }
+      while (true) {
+        if (graph) {
+          HIP_CHECK_RET(hipGraphLaunch(c->graph, s));
+        } else {
+          for (int k = 0; k < m; ++k) cg_iteration(c, timing);
+        }
+        HIP_CHECK_RET(hipGetLastError());
+        HIP_CHECK_RET(hipMemcpyAsync(&h, c->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+        HIP_CHECK_RET(hipStreamSynchronize(s));
+        if (timing) collect_timing(c);
+        if (h.done) break;
+      }
+      // true residual ||b - A x|| / ||b||
+      launch_cg_true_residual(s, F.n, F.K, F.off, F.row_lat, F.val, c->xs, c->bs, nullptr, c->part, c->st);
+      HIP_CHECK_RET(hipMemcpyAsync(&h, c->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+      HIP_CHECK_RET(hipStreamSynchronize(s));
+      const double true_rel = h.bb > 0.0 ? std::sqrt(h.aux / h.bb) : 0.0;
+      if (h.status == 0 && true_rel > rtol && restarts < 3 && h.iters < c->opt.max_iter) {
+        ++restarts;  // recursive residual drifted: restart from the current x
+        continue;
+      }
+      launch_gather(s, F.n, F.row_lat, c->xs, x_dev);
+      HIP_CHECK_RET(hipStreamSynchronize(s));
+      if (info) {
+        info->status = h.status;
+        info->iterations = h.iters;
+        info->rel_res = h.r0sq > 0.0 ? std::sqrt(h.rr / h.r0sq) : 0.0;
+        info->true_rel_res = true_rel;
+        info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      }
+      if (h.status != 0) {
+        c->err = h.status == IMSMG_ERR_NOT_CONVERGED ? "CG did not converge within max_iter"
+                 : h.status == IMSMG_ERR_NOT_SPD     ? "CG breakdown: p.Ap <= 0"
+                                                     : "NaN or Inf in the CG iteration";
+        return int(h.status);
+      }
+      return IMSMG_OK;
+    }
+  });
+}
+
+int imsmg_apply_operator(imsmg_ctx *c, int level, const double *x, double *y) {
+  return guarded(c, [&]() -> int {
+    if (!c->ready) bad("setup first", IMSMG_ERR_STATE);
+    if (level < 0 || level >= int(c->lv.size()) || !x || !y) bad("bad level or vector");
+    Level &L = c->lv[level];
+    launch_scatter(c->stream, L.n, L.row_lat, x, L.x);
+    residual(c, L, L.x, nullptr, L.rh, c->zero_flag, false);
+    launch_gather(c->stream, L.n, L.row_lat, L.rh, y);
+    HIP_CHECK_RET(hipGetLastError());
+    HIP_CHECK_RET(hipStreamSynchronize(c->stream));
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_apply_smoother(imsmg_ctx *c, int level, const double *r, double *y) {
+  return guarded(c, [&]() -> int {
+    if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    if (level < 1 || level >= int(c->lv.size()) || !r || !y) bad("bad level or vector");
+    Level &L = c->lv[level];
+    launch_scatter(c->stream, L.n, L.row_lat, r, L.rh);
+    smooth(c, L, L.rh, L.x, 0, c->zero_flag);
+    launch_gather(c->stream, L.n, L.row_lat, L.x, y);
+    HIP_CHECK_RET(hipGetLastError());
+    HIP_CHECK_RET(hipStreamSynchronize(c->stream));
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_apply_restriction(imsmg_ctx *c, int level, const double *rf, double *rc) {
+  return guarded(c, [&]() -> int {
+    if (!c->ready) bad("setup first", IMSMG_ERR_STATE);
+    if (level < 1 || level >= int(c->lv.size()) || !rf || !rc) bad("bad level or vector");
+    Level &L = c->lv[level], &Cl = c->lv[level - 1];
+    launch_scatter(c->stream, L.n, L.row_lat, rf, L.rh);
+    launch_ell_gather(c->stream, Cl.n, L.rw, Cl.row_lat, L.rcol, L.rval, L.rh, Cl.r, 0, c->zero_flag);
+    launch_gather(c->stream, Cl.n, Cl.row_lat, Cl.r, rc);
+    HIP_CHECK_RET(hipGetLastError());
+    HIP_CHECK_RET(hipStreamSynchronize(c->stream));
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_apply_prolongation(imsmg_ctx *c, int level, const double *xc, double *xf) {
+  return guarded(c, [&]() -> int {
+    if (!c->ready) bad("setup first", IMSMG_ERR_STATE);
+    if (level < 1 || level >= int(c->lv.size()) || !xc || !xf) bad("bad level or vector");
+    Level &L = c->lv[level], &Cl = c->lv[level - 1];
+    launch_scatter(c->stream, Cl.n, Cl.row_lat, xc, Cl.x);
+    launch_scatter(c->stream, L.n, L.row_lat, xf, L.x);
+    launch_ell_gather(c->stream, L.n, L.tw, L.row_lat, L.tcol, L.tval, Cl.x, L.x, 1, c->zero_flag);
+    launch_gather(c->stream, L.n, L.row_lat, L.x, xf);
+    HIP_CHECK_RET(hipGetLastError());
+    HIP_CHECK_RET(hipStreamSynchronize(c->stream));
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_coarse_solve(imsmg_ctx *c, const double *r, double *x) {
+  return guarded(c, [&]() -> int {
+    if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    if (!r || !x) bad("null vector");
+    Level &L = c->lv[0];
+    launch_scatter(c->stream, L.n, L.row_lat, r, L.r);
+    launch_dense_gemv(c->stream, L.n, L.row_lat, L.Ainv, L.r, L.x, c->zero_flag);
+    launch_gather(c->stream, L.n, L.row_lat, L.x, x);
+    HIP_CHECK_RET(hipGetLastError());
+    HIP_CHECK_RET(hipStreamSynchronize(c->stream));
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_kernel_time(imsmg_ctx *c, double *total_ms, int64_t *launches, int reset) {
+  return guarded(c, [&]() -> int {
+    if (total_ms) *total_ms = c->t_kernel_ms;
+    if (launches) *launches = c->t_kernel_n;
+    if (reset) {
+      c->t_kernel_ms = 0.0;
+      c->t_kernel_n = 0;
+    }
+    return IMSMG_OK;
+  });
+}
+
+const char *imsmg_last_error(imsmg_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int imsmg_destroy(imsmg_ctx *c) {
+  if (!c) return IMSMG_OK;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  destroy_graph(c);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  free_list(c->factor_owned);
+  free_list(c->owned);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return IMSMG_OK;
+}
+
+}  // extern "C"

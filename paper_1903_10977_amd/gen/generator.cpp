@@ -1281,6 +1281,28 @@ int imsmg_gen_level_info_get(const imsmg_gen_problem *p, int level, imsmg_gen_le
   info->block_nnz = int64_t(L.bidx.size());
   info->r_nnz = level > 0 ? int64_t(L.R.col.size()) : 0;
   info->n_cut = L.n_cut;
+  {
+    int32_t na = 0;
+    int64_t nz = 0;
+    const Basis1D B(p->P.spec.basis, L.n, p->P.spec.degree, p->P.spec.box_lo, p->P.spec.box_hi);
+    for (size_t t = 0; t < L.active_el.size(); ++t) {
+      if (!L.active_el[t]) continue;
+      ++na;
+      int e[3] = {0, 0, 0};
+      size_t r = t;
+      for (int a = 0; a < d; ++a) { e[a] = int(r % L.n); r /= L.n; }
+      const int m = p->P.spec.degree + 1;
+      int tot = 1;
+      for (int a = 0; a < d; ++a) tot *= m;
+      for (int A = 0; A < tot; ++A) {
+        int mf[3] = {0, 0, 0}, ra = A;
+        for (int a = 0; a < d; ++a) { mf[a] = B.first(e[a]) + ra % m; ra /= m; }
+        if (L.lat2c[size_t(multi_lat(mf, L.nf1, d))] >= 0) ++nz;
+      }
+    }
+    info->n_active_elements = na;
+    info->elem_nnz = nz;
+  }
   double em = 1.0;
   for (size_t t = 0; t < L.eta.size(); ++t)
     if (L.active_el[t]) em = std::min(em, L.eta[t]);
@@ -1314,6 +1336,38 @@ int imsmg_gen_get_blocks(const imsmg_gen_problem *p, int level, int32_t *ptr, in
   if (ptr) std::copy(L.bptr.begin(), L.bptr.end(), ptr);
   if (idx) std::copy(L.bidx.begin(), L.bidx.end(), idx);
   if (assoc) std::copy(L.bassoc.begin(), L.bassoc.end(), assoc);
+  return 0;
+}
+
+int imsmg_gen_get_elements(const imsmg_gen_problem *p, int level, int32_t *eptr, int32_t *eidx, int32_t *elem) {
+  if (!p || level < 0 || level >= int(p->P.lv.size())) { g_err = "bad level"; return -1; }
+  const LevelData &L = p->P.lv[level];
+  const int d = p->P.spec.dim;
+  const Basis1D B(p->P.spec.basis, L.n, p->P.spec.degree, p->P.spec.box_lo, p->P.spec.box_hi);
+  const int m = p->P.spec.degree + 1;
+  int tot = 1;
+  for (int a = 0; a < d; ++a) tot *= m;
+  int32_t na = 0;
+  int64_t nz = 0;
+  if (eptr) eptr[0] = 0;
+  for (size_t t = 0; t < L.active_el.size(); ++t) {
+    if (!L.active_el[t]) continue;
+    int e[3] = {0, 0, 0};
+    size_t r = t;
+    for (int a = 0; a < d; ++a) { e[a] = int(r % L.n); r /= L.n; }
+    for (int A = 0; A < tot; ++A) {
+      int mf[3] = {0, 0, 0}, ra = A;
+      for (int a = 0; a < d; ++a) { mf[a] = B.first(e[a]) + ra % m; ra /= m; }
+      const int32_t c = L.lat2c[size_t(multi_lat(mf, L.nf1, d))];
+      if (c >= 0) {
+        if (eidx) eidx[nz] = c;
+        ++nz;
+      }
+    }
+    if (elem) elem[na] = int32_t(t);
+    ++na;
+    if (eptr) eptr[na] = int32_t(nz);
+  }
   return 0;
 }
 

@@ -36,6 +36,7 @@ def _load():
     lib.imsmg_gen_get_restriction.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.imsmg_gen_get_blocks.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.imsmg_gen_get_rhs.argtypes = [C.c_void_p, C.c_void_p]
+    lib.imsmg_gen_get_elements.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.imsmg_gen_get_mass.argtypes = [C.c_void_p, C.c_void_p]
     lib.imsmg_gen_get_volume_fractions.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
     lib.imsmg_gen_setup_seconds.argtypes = [C.c_void_p]
@@ -59,7 +60,8 @@ class GenSpec(C.Structure):
 class LevelInfo(C.Structure):
     _fields_ = [("n_active", C.c_int32), ("nnz", C.c_int64), ("lattice", C.c_int32 * 3),
                 ("n_elements", C.c_int32), ("nblocks", C.c_int32), ("block_nnz", C.c_int64),
-                ("r_nnz", C.c_int64), ("n_cut", C.c_int32), ("eta_min", C.c_double)]
+                ("r_nnz", C.c_int64), ("n_cut", C.c_int32), ("n_active_elements", C.c_int32),
+                ("elem_nnz", C.c_int64), ("eta_min", C.c_double)]
 
 
 _BASIS = {"bspline": 0, "lagrange": 1}
@@ -85,6 +87,9 @@ class GenLevel:
     n_cut: int
     eta_min: float
     eta: Optional[np.ndarray] = None      # per-element volume fractions (x fastest)
+    elem_ptr: Optional[np.ndarray] = None  # active element -> active functions (CSR)
+    elem_idx: Optional[np.ndarray] = None
+    elem_id: Optional[np.ndarray] = None   # element index of each active element
 
     @property
     def n(self):
@@ -157,9 +162,14 @@ def generate(w, with_mass: bool = False, nthreads: int = 0, orders=None) -> Gene
                 assert lib.imsmg_gen_get_blocks(h, l, _ptr(bp), _ptr(bi), _ptr(ba)) == 0
             eta = np.zeros(info.n_elements ** w.dim, dtype=np.float64)
             assert lib.imsmg_gen_get_volume_fractions(h, l, _ptr(eta)) == 0
+            ep = np.zeros(info.n_active_elements + 1, dtype=np.int32)
+            ei = np.zeros(info.elem_nnz, dtype=np.int32)
+            eid = np.zeros(info.n_active_elements, dtype=np.int32)
+            assert lib.imsmg_gen_get_elements(h, l, _ptr(ep), _ptr(ei), _ptr(eid)) == 0
             levels.append(GenLevel(n_elements=info.n_elements, lattice=tuple(info.lattice[:w.dim]),
                                    dof_to_lattice=d2l, A=A, R=R, block_ptr=bp, block_idx=bi,
-                                   block_assoc=ba, n_cut=info.n_cut, eta_min=info.eta_min, eta=eta))
+                                   block_assoc=ba, n_cut=info.n_cut, eta_min=info.eta_min, eta=eta,
+                                   elem_ptr=ep, elem_idx=ei, elem_id=eid))
         nf = levels[-1].n
         b = np.zeros(nf, dtype=np.float64)
         lib.imsmg_gen_get_rhs(h, _ptr(b))

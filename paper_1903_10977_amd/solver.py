@@ -1,0 +1,286 @@
+"""ctypes binding of the HIP solver library libimsmg.so (same call names as the C ABI).
+
+Argument marshalling only: every step of factorization, V-cycle and CG runs in
+the library's HIP kernels.  Device vectors are torch tensors (float64, on the
+library context's device); torch provides memory, nothing else.  The library
+orders its work on its own stream and returns after completion; before each
+call the binding synchronizes torch's device so that tensors written by torch
+are complete.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import LIB_DIR
+
+OK = 0
+ERR = {-1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "NOT_SPD", -5: "NOT_CONVERGED", -6: "NAN", -7: "STATE"}
+FP64, MIXED = 0, 1
+
+_lib = None
+
+
+class Csr(C.Structure):
+    _fields_ = [("nrows", C.c_int32), ("ncols", C.c_int32), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+class Patches(C.Structure):
+    _fields_ = [("nblocks", C.c_int32), ("ptr", C.c_void_p), ("idx", C.c_void_p)]
+
+
+class Elements(C.Structure):
+    _fields_ = [("nelements", C.c_int32), ("eptr", C.c_void_p), ("eidx", C.c_void_p)]
+
+
+class Lattice(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("shape", C.c_int32 * 3), ("reach", C.c_int32), ("dof_to_lattice", C.c_void_p)]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("max_iter", C.c_int32),
+                ("check_every", C.c_int32), ("use_graph", C.c_int32), ("timing", C.c_int32), ("gamma", C.c_double)]
+
+
+class Info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("rel_res", C.c_double),
+                ("true_rel_res", C.c_double), ("solve_ms", C.c_double)]
+
+
+SYMBOLS = ["imsmg_default_options", "imsmg_create", "imsmg_setup", "imsmg_set_patch_weights",
+           "imsmg_factor_patches", "imsmg_get_patches", "imsmg_get_gamma", "imsmg_vcycle", "imsmg_pcg_solve",
+           "imsmg_apply_operator", "imsmg_apply_smoother", "imsmg_apply_restriction", "imsmg_apply_prolongation",
+           "imsmg_coarse_solve", "imsmg_kernel_time", "imsmg_last_error", "imsmg_destroy"]
+
+
+def library_path() -> str:
+    return os.path.join(LIB_DIR, "libimsmg.so")
+
+
+def load():
+    """Load libimsmg.so; raises if it is not built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
+    lib = C.CDLL(path)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    lib.imsmg_default_options.argtypes = [C.POINTER(Options)]
+    lib.imsmg_default_options.restype = None
+    lib.imsmg_create.argtypes = [C.POINTER(vp), i32, vp]
+    lib.imsmg_setup.argtypes = [vp, i32, C.POINTER(Csr), C.POINTER(Csr), C.POINTER(Patches), C.POINTER(Lattice),
+                                C.POINTER(Elements), C.POINTER(Options)]
+    lib.imsmg_set_patch_weights.argtypes = [vp, i32, vp]
+    lib.imsmg_factor_patches.argtypes = [vp]
+    lib.imsmg_get_patches.argtypes = [vp, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int64), vp, vp]
+    lib.imsmg_get_gamma.argtypes = [vp, i32, C.POINTER(C.c_double)]
+    lib.imsmg_vcycle.argtypes = [vp, vp, vp]
+    lib.imsmg_pcg_solve.argtypes = [vp, vp, vp, dbl, C.POINTER(Info)]
+    for f in ("imsmg_apply_operator", "imsmg_apply_smoother", "imsmg_apply_restriction", "imsmg_apply_prolongation"):
+        getattr(lib, f).argtypes = [vp, i32, vp, vp]
+    lib.imsmg_coarse_solve.argtypes = [vp, vp, vp]
+    lib.imsmg_kernel_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
+    lib.imsmg_last_error.argtypes = [vp]
+    lib.imsmg_last_error.restype = C.c_char_p
+    lib.imsmg_destroy.argtypes = [vp]
+    for s in SYMBOLS:
+        if s not in ("imsmg_default_options", "imsmg_last_error"):
+            getattr(lib, s).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+class SolverError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERR.get(code, code)}: {msg}")
+        self.code = code
+
+
+def default_options(**kw) -> Options:
+    lib = load()
+    o = Options()
+    lib.imsmg_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    iterations: int
+    rel_res: float
+    true_rel_res: float
+    solve_ms: float
+
+
+class Solver:
+    """One library context bound to a HIP device."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.device = device
+        h = C.c_void_p()
+        self._check(self.lib.imsmg_create(C.byref(h), device, None), h)
+        self.h = h
+        self.problem = None
+        self._keep = []
+
+    def _check(self, rc, h=None):
+        if rc != OK:
+            msg = self.lib.imsmg_last_error(h if h is not None else self.h)
+            raise SolverError(rc, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.imsmg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- setup
+    def setup(self, problem, options: Options = None, dim: int = None, reach: int = None):
+        """problem: a generator.GeneratedProblem (levels 0 = coarsest)."""
+        w = problem.workload
+        dim = dim or w.dim
+        reach = reach or w.degree
+        L = len(problem.levels)
+        keep = []
+        A = (Csr * L)()
+        R = (Csr * L)()
+        P = (Patches * L)()
+        Lt = (Lattice * L)()
+        E = (Elements * L)()
+        for l, lev in enumerate(problem.levels):
+            rp, ci, va = _i32(lev.A.indptr), _i32(lev.A.indices), np.ascontiguousarray(lev.A.data, np.float64)
+            keep += [rp, ci, va]
+            A[l] = Csr(lev.A.shape[0], lev.A.shape[1], lev.A.nnz, _p(rp).value, _p(ci).value, _p(va).value)
+            d2l = _i32(lev.dof_to_lattice)
+            keep.append(d2l)
+            shp = (C.c_int32 * 3)(*(list(lev.lattice) + [1] * (3 - len(lev.lattice))))
+            Lt[l] = Lattice(dim, shp, reach, _p(d2l).value)
+            if l > 0:
+                Rm = lev.R
+                rrp, rci, rva = _i32(Rm.indptr), _i32(Rm.indices), np.ascontiguousarray(Rm.data, np.float64)
+                keep += [rrp, rci, rva]
+                R[l] = Csr(Rm.shape[0], Rm.shape[1], Rm.nnz, _p(rrp).value, _p(rci).value, _p(rva).value)
+                bp, bi = _i32(lev.block_ptr), _i32(lev.block_idx)
+                keep += [bp, bi]
+                P[l] = Patches(len(bp) - 1, _p(bp).value, _p(bi).value)
+            if lev.elem_ptr is not None:
+                ep, ei = _i32(lev.elem_ptr), _i32(lev.elem_idx)
+                keep += [ep, ei]
+                E[l] = Elements(len(ep) - 1, _p(ep).value, _p(ei).value)
+        opt = options if options is not None else default_options(nu_pre=w.nu, nu_post=w.nu)
+        self._check(self.lib.imsmg_setup(self.h, L, A, R, P, Lt, E, C.byref(opt)))
+        self.problem = problem
+        self.options = opt
+        return self
+
+    def set_patch_weights(self, level: int, omega):
+        om = np.ascontiguousarray(omega, dtype=np.float64)
+        self._check(self.lib.imsmg_set_patch_weights(self.h, level, _p(om)))
+
+    def factor(self):
+        self._check(self.lib.imsmg_factor_patches(self.h))
+        return self
+
+    def get_patches(self, level: int):
+        nb = C.c_int32()
+        nnz = C.c_int64()
+        self._check(self.lib.imsmg_get_patches(self.h, level, C.byref(nb), C.byref(nnz), None, None))
+        ptr = np.zeros(nb.value + 1, np.int32)
+        idx = np.zeros(nnz.value, np.int32)
+        self._check(self.lib.imsmg_get_patches(self.h, level, C.byref(nb), C.byref(nnz), _p(ptr), _p(idx)))
+        return ptr, idx
+
+    def gamma(self, level: int) -> float:
+        g = C.c_double()
+        self._check(self.lib.imsmg_get_gamma(self.h, level, C.byref(g)))
+        return g.value
+
+    # ---------------------------------------------------------- device ops
+    def _dev(self, t):
+        torch = self.torch
+        assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+        return C.c_void_p(t.data_ptr())
+
+    def _sync(self):
+        self.torch.cuda.synchronize(self.device)
+
+    def _n(self, level):
+        return self.problem.levels[level].n
+
+    def empty(self, level: int):
+        return self.torch.zeros(self._n(level), dtype=self.torch.float64, device=f"cuda:{self.device}")
+
+    def vcycle(self, r, z=None):
+        z = self.empty(len(self.problem.levels) - 1) if z is None else z
+        self._sync()
+        self._check(self.lib.imsmg_vcycle(self.h, self._dev(r), self._dev(z)))
+        return z
+
+    def pcg(self, b, x, rtol: float = 1e-8, raise_on_error: bool = True) -> SolveInfo:
+        info = Info()
+        self._sync()
+        rc = self.lib.imsmg_pcg_solve(self.h, self._dev(b), self._dev(x), rtol, C.byref(info))
+        if rc != OK and raise_on_error:
+            self._check(rc)
+        return SolveInfo(info.status, info.iterations, info.rel_res, info.true_rel_res, info.solve_ms)
+
+    def apply_operator(self, level, x, y=None):
+        y = self.empty(level) if y is None else y
+        self._sync()
+        self._check(self.lib.imsmg_apply_operator(self.h, level, self._dev(x), self._dev(y)))
+        return y
+
+    def apply_smoother(self, level, r, y=None):
+        y = self.empty(level) if y is None else y
+        self._sync()
+        self._check(self.lib.imsmg_apply_smoother(self.h, level, self._dev(r), self._dev(y)))
+        return y
+
+    def apply_restriction(self, level, rf, rc=None):
+        rc = self.empty(level - 1) if rc is None else rc
+        self._sync()
+        self._check(self.lib.imsmg_apply_restriction(self.h, level, self._dev(rf), self._dev(rc)))
+        return rc
+
+    def apply_prolongation(self, level, xc, xf):
+        self._sync()
+        self._check(self.lib.imsmg_apply_prolongation(self.h, level, self._dev(xc), self._dev(xf)))
+        return xf
+
+    def coarse_solve(self, r, x=None):
+        x = self.empty(0) if x is None else x
+        self._sync()
+        self._check(self.lib.imsmg_coarse_solve(self.h, self._dev(r), self._dev(x)))
+        return x
+
+    def kernel_time(self, reset: bool = False):
+        ms = C.c_double()
+        n = C.c_int64()
+        self._check(self.lib.imsmg_kernel_time(self.h, C.byref(ms), C.byref(n), 1 if reset else 0))
+        return ms.value, n.value
