@@ -90,6 +90,13 @@ typedef struct {
   int32_t shape[3];             /* functions per axis (unused axes: 1) */
   int32_t reach;                /* stencil half width (B-splines and Lagrange: degree p) */
   const int32_t *dof_to_lattice;/* nrows, strictly increasing (host) */
+  /* Optional (may be NULL): the 1D two-scale matrix of R_l when R_l is the
+   * tensor product of one 1D matrix restricted to active rows and columns
+   * (eq:coarsening on a tensor grid).  Dense row-major, rows = functions per
+   * axis of level l-1, cols = shape[0] of this level.  When given, setup
+   * checks it against the CSR R_l entry by entry and then applies R_l and
+   * R_l^T without stored indices or values. */
+  const double *two_scale;
 } imsmg_lattice;
 
 typedef struct {

@@ -83,6 +83,9 @@ int imsmg_gen_get_operator(const imsmg_gen_problem *p, int level, int32_t *dof_t
 /* R_l: n_active(level-1) x n_active(level), rowptr[n_{l-1}+1], col/val[r_nnz] */
 int imsmg_gen_get_restriction(const imsmg_gen_problem *p, int level, int32_t *rowptr, int32_t *col,
                               double *val);
+/* 1D two-scale matrix of R_l (dense, row-major): rows = functions per axis of
+ * level l-1, cols = functions per axis of level l (level >= 1) */
+int imsmg_gen_get_two_scale(const imsmg_gen_problem *p, int level, double *R1);
 /* blocks: ptr[nblocks+1], idx[block_nnz] (sorted compact indices), assoc[nblocks] */
 int imsmg_gen_get_blocks(const imsmg_gen_problem *p, int level, int32_t *ptr, int32_t *idx, int32_t *assoc);
 /* active elements in ascending element index: eptr[n_active_elements+1],

@@ -70,6 +70,11 @@ struct Level {
   int rw = 0, tw = 0;
   int32_t *rcol = nullptr, *tcol = nullptr;
   double *rval = nullptr, *tval = nullptr;
+  // index-free tensor form of R_l (bands of the 1D two-scale matrix)
+  bool tensor = false;
+  int rbW = 0, pbW = 0;
+  int32_t *rb_start = nullptr, *rb_len = nullptr, *pb_start = nullptr, *pb_len = nullptr;
+  double *rb_coef = nullptr, *pb_coef = nullptr;
   // input blocks
   std::vector<int32_t> in_ptr, in_idx;
   std::vector<double> omega;  // optional per-block weights
@@ -241,7 +246,97 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
 
 // R (coarse x fine, compact) -> ELL on coarse rows with fine lattice columns,
 // and R^T ELL on fine rows with coarse lattice columns.
-void setup_transfer(imsmg_ctx *c, Level &F, const Level &Cl, const imsmg_csr &R) {
+// Bands of a dense 1D matrix M (rows x cols): per row the first and last
+// non-zero column and the coefficients in between (zeros included).
+void bands(const std::vector<double> &M, int rows, int cols, std::vector<int32_t> &start, std::vector<int32_t> &len,
+           std::vector<double> &coef, int &W) {
+  start.assign(rows, 0);
+  len.assign(rows, 0);
+  W = 1;
+  for (int i = 0; i < rows; ++i) {
+    int f = -1, l = -1;
+    for (int j = 0; j < cols; ++j)
+      if (M[size_t(i) * cols + j] != 0.0) {
+        if (f < 0) f = j;
+        l = j;
+      }
+    if (f >= 0) {
+      start[i] = f;
+      len[i] = l - f + 1;
+      W = std::max(W, l - f + 1);
+    }
+  }
+  coef.assign(size_t(rows) * W, 0.0);
+  for (int i = 0; i < rows; ++i)
+    for (int a = 0; a < len[i]; ++a) coef[size_t(i) * W + a] = M[size_t(i) * cols + start[i] + a];
+}
+
+void setup_tensor_transfer(imsmg_ctx *c, Level &F, const Level &Cl, const imsmg_csr &R, const double *R1) {
+  hipStream_t s = c->stream;
+  const int mc = Cl.shape[0], mf = F.shape[0];
+  for (int a = 1; a < F.dim; ++a)
+    if (Cl.shape[a] != mc || F.shape[a] != mf) bad("tensor transfer needs equal functions per axis");
+  std::vector<double> M(R1, R1 + size_t(mc) * mf), Mt(size_t(mf) * mc);
+  for (int i = 0; i < mc; ++i)
+    for (int j = 0; j < mf; ++j) Mt[size_t(j) * mc + i] = M[size_t(i) * mf + j];
+  // check the CSR R entry by entry against the masked tensor product
+  std::vector<int32_t> f2c(size_t(F.lattice), -1);
+  for (int k = 0; k < F.n; ++k) f2c[F.h_row_lat[k]] = k;
+  for (int i = 0; i < Cl.n; ++i) {
+    int mi[3] = {0, 0, 0};
+    lat_multi(Cl.h_row_lat[i], Cl.shape, Cl.dim, mi);
+    int64_t cnt = 0;
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+      if (a >= F.dim) continue;
+      lo[a] = mf;
+      hi[a] = -1;
+      for (int j = 0; j < mf; ++j)
+        if (M[size_t(mi[a]) * mf + j] != 0.0) {
+          lo[a] = std::min(lo[a], j);
+          hi[a] = std::max(hi[a], j);
+        }
+    }
+    for (int z = lo[2]; z <= hi[2]; ++z)
+      for (int y = lo[1]; y <= hi[1]; ++y)
+        for (int x = lo[0]; x <= hi[0]; ++x) {
+          int m[3] = {x, y, z};
+          double v = 1.0;
+          for (int a = 0; a < F.dim; ++a) v *= M[size_t(mi[a]) * mf + m[a]];
+          if (v == 0.0) continue;
+          if (f2c[size_t(lat_linear(m, F.shape, F.dim))] >= 0) ++cnt;
+        }
+    if (cnt != R.rowptr[i + 1] - R.rowptr[i]) bad("R is not the masked tensor product of the given two-scale matrix");
+    for (int64_t k = R.rowptr[i]; k < R.rowptr[i + 1]; ++k) {
+      int mk[3] = {0, 0, 0};
+      lat_multi(F.h_row_lat[R.col[k]], F.shape, F.dim, mk);
+      double v = 1.0;
+      for (int a = 0; a < F.dim; ++a) v *= M[size_t(mi[a]) * mf + mk[a]];
+      if (!(std::fabs(v - R.val[k]) <= 1e-13 * std::fabs(v)))
+        bad("R is not the masked tensor product of the given two-scale matrix");
+    }
+  }
+  std::vector<int32_t> rs, rl, ps, pl;
+  std::vector<double> rcf, pcf;
+  bands(M, mc, mf, rs, rl, rcf, F.rbW);
+  bands(Mt, mf, mc, ps, pl, pcf, F.pbW);
+  F.rb_start = dalloc<int32_t>(c->owned, mc);
+  F.rb_len = dalloc<int32_t>(c->owned, mc);
+  F.rb_coef = dalloc<double>(c->owned, rcf.size());
+  F.pb_start = dalloc<int32_t>(c->owned, mf);
+  F.pb_len = dalloc<int32_t>(c->owned, mf);
+  F.pb_coef = dalloc<double>(c->owned, pcf.size());
+  h2d(s, F.rb_start, rs.data(), mc);
+  h2d(s, F.rb_len, rl.data(), mc);
+  h2d(s, F.rb_coef, rcf.data(), rcf.size());
+  h2d(s, F.pb_start, ps.data(), mf);
+  h2d(s, F.pb_len, pl.data(), mf);
+  h2d(s, F.pb_coef, pcf.data(), pcf.size());
+  HIP_CHECK_RET(hipStreamSynchronize(s));
+  F.tensor = true;
+}
+
+void setup_transfer(imsmg_ctx *c, Level &F, const Level &Cl, const imsmg_csr &R, const double *two_scale) {
   hipStream_t s = c->stream;
   if (R.nrows != Cl.n || R.ncols != F.n) bad("R shape must be n_{l-1} x n_l");
   if (!R.rowptr || !R.col || !R.val) bad("null R array");
@@ -273,6 +368,10 @@ void setup_transfer(imsmg_ctx *c, Level &F, const Level &Cl, const imsmg_csr &R)
       tcol[size_t(ts) * F.n + j] = Cl.h_row_lat[i];
       tval[size_t(ts) * F.n + j] = R.val[k];
     }
+  }
+  if (two_scale) {
+    setup_tensor_transfer(c, F, Cl, R, two_scale);
+    return;
   }
   F.rw = rw;
   F.tw = tw;
@@ -310,6 +409,24 @@ void residual(imsmg_ctx *c, Level &L, const double *x, const double *b, double *
   if (timed) HIP_CHECK_RET(hipEventRecord(e1, c->stream));
 }
 
+// rc = R_l rf (fine level L, coarse level Cl; padded vectors)
+void restrict_to(imsmg_ctx *c, Level &L, Level &Cl, const double *rf, double *rc, const int32_t *done) {
+  if (L.tensor)
+    launch_tensor_transfer(c->stream, L.dim, Cl.n, Cl.row_lat, Cl.shape[0], Cl.shape[1], L.rb_start, L.rb_len,
+                           L.rb_coef, L.rbW, L.shape[0], L.shape[1], rf, rc, 0, done);
+  else
+    launch_ell_gather(c->stream, Cl.n, L.rw, Cl.row_lat, L.rcol, L.rval, rf, rc, 0, done);
+}
+
+// xf += R_l^T xc
+void prolong_add(imsmg_ctx *c, Level &L, Level &Cl, const double *xc, double *xf, const int32_t *done) {
+  if (L.tensor)
+    launch_tensor_transfer(c->stream, L.dim, L.n, L.row_lat, L.shape[0], L.shape[1], L.pb_start, L.pb_len, L.pb_coef,
+                           L.pbW, Cl.shape[0], Cl.shape[1], xc, xf, 1, done);
+  else
+    launch_ell_gather(c->stream, L.n, L.tw, L.row_lat, L.tcol, L.tval, xc, xf, 1, done);
+}
+
 void smooth(imsmg_ctx *c, Level &L, const double *r, double *x, int accumulate, const int32_t *done) {
   launch_schwarz_blocks(c->stream, L.ntask, L.task_block, L.bstart, L.bsize, L.binv_off, L.blat, L.binv, L.bw, r,
                         L.ybuf, done);
@@ -331,9 +448,9 @@ void vcycle_level(imsmg_ctx *c, int l, const int32_t *done, bool timing) {
     smooth(c, L, L.rh, L.x, 1, done);
   }
   residual(c, L, L.x, L.r, L.rh, done, fine);
-  launch_ell_gather(c->stream, Cl.n, L.rw, Cl.row_lat, L.rcol, L.rval, L.rh, Cl.r, 0, done);
+  restrict_to(c, L, Cl, L.rh, Cl.r, done);
   vcycle_level(c, l - 1, done, timing);
-  launch_ell_gather(c->stream, L.n, L.tw, L.row_lat, L.tcol, L.tval, Cl.x, L.x, 1, done);
+  prolong_add(c, L, Cl, Cl.x, L.x, done);
   for (int k = 0; k < c->opt.nu_post; ++k) {
     residual(c, L, L.x, L.r, L.rh, done, fine);
     smooth(c, L, L.rh, L.x, 1, done);
@@ -548,12 +665,14 @@ void factor_level(imsmg_ctx *c, int l) {
     std::vector<double> cvals(n);
     d2h(s, cvals.data(), d_c, n);
     HIP_CHECK_RET(hipStreamSynchronize(s));
+    // general singletons occupy one contiguous tail [h_invoff[nf], extra_off)
+    std::vector<double> tail(ns);
     for (int k = 0; k < ns; ++k) {
       const double v = cvals[single_rows[k]];
       if (!(v > 0.0) || !std::isfinite(v)) bad("non-positive diagonal entry", IMSMG_ERR_NOT_SPD);
-      HIP_CHECK_RET(hipMemcpyAsync(inv + single_off[k], &cvals[single_rows[k]], sizeof(double),
-                                   hipMemcpyHostToDevice, s));
+      tail[size_t(single_off[k] - h_invoff[nf])] = v;
     }
+    h2d(s, inv + h_invoff[nf], tail.data(), tail.size());
     HIP_CHECK_RET(hipStreamSynchronize(s));
   }
   L.binv = inv;
@@ -624,15 +743,14 @@ void factor_coarsest(imsmg_ctx *c) {
   HIP_CHECK_RET(hipMemsetAsync(L.Ainv, 0, size_t(n) * n * sizeof(double), s));
   launch_dense_from_ell(s, n, L.K, L.off, L.row_lat, d_l2c + L.guard, L.val, L.Ainv);
   double *colk = dalloc<double>(tmp, n), *rowk = dalloc<double>(tmp, n);
-  for (int k = 0; k < n; ++k) launch_gauss_jordan_step(s, n, k, L.Ainv, colk, rowk);
+  int32_t *d_bad = dalloc<int32_t>(tmp, 1);
+  HIP_CHECK_RET(hipMemsetAsync(d_bad, 0, sizeof(int32_t), s));
+  for (int k = 0; k < n; ++k) launch_gauss_jordan_step(s, n, k, L.Ainv, colk, rowk, d_bad);
   HIP_CHECK_RET(hipGetLastError());
-  // the inverse of an SPD matrix has a positive, finite diagonal
-  std::vector<double> diag(n);
-  for (int i = 0; i < n; ++i)
-    HIP_CHECK_RET(hipMemcpyAsync(&diag[i], L.Ainv + size_t(i) * n + i, sizeof(double), hipMemcpyDeviceToHost, s));
+  int32_t h_bad = 0;
   HIP_CHECK_RET(hipStreamSynchronize(s));
-  for (int i = 0; i < n; ++i)
-    if (!(diag[i] > 0.0) || !std::isfinite(diag[i])) bad("coarsest operator is not SPD", IMSMG_ERR_NOT_SPD);
+  HIP_CHECK_RET(hipMemcpy(&h_bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (h_bad) bad("coarsest operator is not SPD (non-positive Gauss-Jordan pivot)", IMSMG_ERR_NOT_SPD);
 }
 
 void destroy_graph(imsmg_ctx *c) {
@@ -721,7 +839,7 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
       if (Lt[l].dim != Lt[nlevels - 1].dim) bad("all levels must share the dimension");
       setup_level(c, c->lv[l], A[l], Lt[l]);
     }
-    for (int l = 1; l < nlevels; ++l) setup_transfer(c, c->lv[l], c->lv[l - 1], R[l]);
+    for (int l = 1; l < nlevels; ++l) setup_transfer(c, c->lv[l], c->lv[l - 1], R[l], Lt[l].two_scale);
     for (int l = 1; l < nlevels; ++l) {
       Level &L = c->lv[l];
       const imsmg_patches &p = P[l];
@@ -762,7 +880,7 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
     HIP_CHECK_RET(hipMemsetAsync(c->zero_flag, 0, sizeof(int32_t), c->stream));
     c->st = dalloc<CGState>(c->owned, 1);
     HIP_CHECK_RET(hipMemsetAsync(c->st, 0, sizeof(CGState), c->stream));
-    c->part = dalloc<double>(c->owned, 2 * 4096);
+    c->part = dalloc<double>(c->owned, 2 * size_t(reduction_blocks(F.n)) + 64);
     HIP_CHECK_RET(hipStreamSynchronize(c->stream));
     c->ready = true;
     return IMSMG_OK;
@@ -936,7 +1054,7 @@ int imsmg_apply_restriction(imsmg_ctx *c, int level, const double *rf, double *r
     if (level < 1 || level >= int(c->lv.size()) || !rf || !rc) bad("bad level or vector");
     Level &L = c->lv[level], &Cl = c->lv[level - 1];
     launch_scatter(c->stream, L.n, L.row_lat, rf, L.rh);
-    launch_ell_gather(c->stream, Cl.n, L.rw, Cl.row_lat, L.rcol, L.rval, L.rh, Cl.r, 0, c->zero_flag);
+    restrict_to(c, L, Cl, L.rh, Cl.r, c->zero_flag);
     launch_gather(c->stream, Cl.n, Cl.row_lat, Cl.r, rc);
     HIP_CHECK_RET(hipGetLastError());
     HIP_CHECK_RET(hipStreamSynchronize(c->stream));
@@ -951,7 +1069,7 @@ int imsmg_apply_prolongation(imsmg_ctx *c, int level, const double *xc, double *
     Level &L = c->lv[level], &Cl = c->lv[level - 1];
     launch_scatter(c->stream, Cl.n, Cl.row_lat, xc, Cl.x);
     launch_scatter(c->stream, L.n, L.row_lat, xf, L.x);
-    launch_ell_gather(c->stream, L.n, L.tw, L.row_lat, L.tcol, L.tval, Cl.x, L.x, 1, c->zero_flag);
+    prolong_add(c, L, Cl, Cl.x, L.x, c->zero_flag);
     launch_gather(c->stream, L.n, L.row_lat, L.x, xf);
     HIP_CHECK_RET(hipGetLastError());
     HIP_CHECK_RET(hipStreamSynchronize(c->stream));

@@ -235,11 +235,13 @@ __global__ void k_gj_copy(int n, int k, const double *__restrict__ A, double *__
 }
 
 __global__ void k_gj_update(int n, int k, double *__restrict__ A, const double *__restrict__ colk,
-                            const double *__restrict__ rowk) {
+                            const double *__restrict__ rowk, int32_t *__restrict__ bad_pivot) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (j >= n) return;
   const double piv = rowk[k];
+  // Gauss-Jordan pivots of an SPD matrix are the positive Schur-complement diagonals
+  if (i == k && j == k && !(piv > 0.0 && piv < INFINITY)) *bad_pivot = 1;
   double v;
   if (i == k && j == k) v = 1.0 / piv;
   else if (i == k) v = rowk[j] / piv;
@@ -248,10 +250,11 @@ __global__ void k_gj_update(int n, int k, double *__restrict__ A, const double *
   A[size_t(i) * n + j] = v;
 }
 
-void launch_gauss_jordan_step(hipStream_t s, int n, int k, double *A, double *colk, double *rowk) {
+void launch_gauss_jordan_step(hipStream_t s, int n, int k, double *A, double *colk, double *rowk,
+                              int32_t *bad_pivot) {
   k_gj_copy<<<(n + 255) / 256, 256, 0, s>>>(n, k, A, colk, rowk);
   dim3 g((n + 255) / 256, n);
-  k_gj_update<<<g, 256, 0, s>>>(n, k, A, colk, rowk);
+  k_gj_update<<<g, 256, 0, s>>>(n, k, A, colk, rowk, bad_pivot);
 }
 
 // -------- N_K: number of blocks holding a function non-zero on element K

@@ -46,10 +46,8 @@ struct CGState {
   int32_t iters;
   int32_t status;  // 0 ok, IMSMG_ERR_NOT_SPD on p.q <= 0, IMSMG_ERR_NAN on NaN
   int32_t first;   // 1 before the first direction is formed
-  uint32_t ticket[8];
 };
 
-enum Ticket { T_DOT_RZ = 0, T_SPMV_PQ = 1, T_UPDATE = 2, T_RESID = 3, T_DOT = 4 };
 
 // --------------------------------------------------------------- launchers
 // lattice-ELL residual / product: y = b - A x  (b may be null -> y = A x; sign=-1 gives -Ax)
@@ -60,6 +58,10 @@ void launch_ell_residual_f32(hipStream_t s, int n, int K, const Offsets &off, co
 // ELL gather: y[lat_row[i]] (+)= sum_s v[s*n+i] x[col[s*n+i]]
 void launch_ell_gather(hipStream_t s, int n, int w, const int32_t *row_lat, const int32_t *col, const double *v,
                        const double *x, double *y, int accumulate, const int32_t *done);
+// index-free tensor transfer: y[row_lat[i]] (+)= sum over the band product of xin
+void launch_tensor_transfer(hipStream_t s, int dim, int n, const int32_t *row_lat, int ox, int oy,
+                            const int32_t *start, const int32_t *len, const double *coef, int W, int ix, int iy,
+                            const double *xin, double *y, int accumulate, const int32_t *done);
 // Schwarz phase 1: y[t] = w_j * sum_b inv_j[a + n_j b] r[blat[start_j + b]]
 void launch_schwarz_blocks(hipStream_t s, int ntask, const int32_t *task_block, const int32_t *bstart,
                            const int32_t *bsize, const int64_t *binv_off, const int32_t *blat, const double *binv,
@@ -96,7 +98,8 @@ int launch_block_factor_geom(hipStream_t s, int nblocks, int maxn, const int32_t
                              const int32_t *blat, const int32_t *brow, int n, int dim, int nx, int ny, int reach,
                              const double *val, double *inv_out, const int64_t *inv_off, uint8_t *keep_out,
                              double *lam_out, int32_t *info_out, double ratio);
-void launch_gauss_jordan_step(hipStream_t s, int n, int k, double *A, double *colk, double *rowk);
+void launch_gauss_jordan_step(hipStream_t s, int n, int k, double *A, double *colk, double *rowk,
+                              int32_t *bad_pivot);
 void launch_dense_from_ell(hipStream_t s, int n, int K, const Offsets &off, const int32_t *row_lat,
                            const int32_t *lat2c, const double *val, double *dense);
 void launch_count_nk(hipStream_t s, int nel, const int32_t *eptr, const int32_t *eidx, const int32_t *fptr,

@@ -93,6 +93,7 @@ __global__ __launch_bounds__(kRowBlock) void k_ell_gather(int n, int w, const in
   const int i = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
   if (i >= n) return;
   double acc = 0.0;
+#pragma unroll 8
   for (int s = 0; s < w; ++s) acc += v[size_t(s) * n + i] * x[col[size_t(s) * n + i]];
   const int L = row_lat[i];
   y[L] = accumulate ? y[L] + acc : acc;
@@ -102,6 +103,73 @@ void launch_ell_gather(hipStream_t s, int n, int w, const int32_t *row_lat, cons
                        const double *x, double *y, int accumulate, const int32_t *done) {
   if (n <= 0) return;
   k_ell_gather<<<grid_for(n), kRowBlock, 0, s>>>(n, w, row_lat, col, v, x, y, accumulate, done);
+}
+
+// Index-free transfers R_l = tensor product of one 1D two-scale matrix
+// (eq:coarsening on the tensor grid), restricted to active functions.  The
+// vectors are zero at inactive lattice points, so the full tensor stencil can
+// be applied without a mask.  tab: per 1D index, start of the band in the
+// other level's 1D numbering, band length, and the band coefficients
+// (stride W).
+struct Band {
+  const int32_t *start;
+  const int32_t *len;
+  const double *coef;
+  int W;
+};
+
+template <int DIM>
+__global__ __launch_bounds__(kRowBlock) void k_tensor_transfer(int n, const int32_t *__restrict__ row_lat,
+                                                               int ox, int oy, Band band, int ix_, int iy_,
+                                                               const double *__restrict__ xin,
+                                                               double *__restrict__ y, int accumulate,
+                                                               const int32_t *__restrict__ done) {
+  // rows: this level (lattice ox x oy x .), inputs: other level (lattice ix_ x iy_ x .)
+  if (*done) return;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
+  if (i >= n) return;
+  const int L = row_lat[i];
+  const int mx = L % ox;
+  const int my = (L / ox) % oy;
+  const int mz = DIM == 3 ? L / (ox * oy) : 0;
+  const int sx = band.start[mx], nx = band.len[mx];
+  const int sy = band.start[my], ny = band.len[my];
+  const double *cx = band.coef + size_t(mx) * band.W;
+  const double *cy = band.coef + size_t(my) * band.W;
+  double acc = 0.0;
+  if (DIM == 2) {
+    for (int b = 0; b < ny; ++b) {
+      const double *row = xin + size_t(sy + b) * ix_ + sx;
+      double t = 0.0;
+      for (int a = 0; a < nx; ++a) t += cx[a] * row[a];
+      acc += cy[b] * t;
+    }
+  } else {
+    const int sz = band.start[mz], nz = band.len[mz];
+    const double *cz = band.coef + size_t(mz) * band.W;
+    for (int c = 0; c < nz; ++c) {
+      double tz = 0.0;
+      for (int b = 0; b < ny; ++b) {
+        const double *row = xin + (size_t(sz + c) * iy_ + (sy + b)) * ix_ + sx;
+        double t = 0.0;
+        for (int a = 0; a < nx; ++a) t += cx[a] * row[a];
+        tz += cy[b] * t;
+      }
+      acc += cz[c] * tz;
+    }
+  }
+  y[L] = accumulate ? y[L] + acc : acc;
+}
+
+void launch_tensor_transfer(hipStream_t s, int dim, int n, const int32_t *row_lat, int ox, int oy,
+                            const int32_t *start, const int32_t *len, const double *coef, int W, int ix, int iy,
+                            const double *xin, double *y, int accumulate, const int32_t *done) {
+  if (n <= 0) return;
+  Band b{start, len, coef, W};
+  if (dim == 2)
+    k_tensor_transfer<2><<<grid_for(n), kRowBlock, 0, s>>>(n, row_lat, ox, oy, b, ix, iy, xin, y, accumulate, done);
+  else
+    k_tensor_transfer<3><<<grid_for(n), kRowBlock, 0, s>>>(n, row_lat, ox, oy, b, ix, iy, xin, y, accumulate, done);
 }
 
 // Schwarz phase 1: one thread per block row.  The inverse is stored column
@@ -120,6 +188,7 @@ __global__ __launch_bounds__(kRowBlock) void k_schwarz_blocks(
   const int a = t - st;
   const double *inv = binv + binv_off[j];
   double acc = 0.0;
+#pragma unroll 4
   for (int b = 0; b < nj; ++b) acc += inv[a + size_t(nj) * b] * r[blat[st + b]];
   y[t] = bw[j] * acc;
 }

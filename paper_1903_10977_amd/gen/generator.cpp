@@ -1330,6 +1330,14 @@ int imsmg_gen_get_restriction(const imsmg_gen_problem *p, int level, int32_t *ro
   return 0;
 }
 
+int imsmg_gen_get_two_scale(const imsmg_gen_problem *p, int level, double *R1) {
+  if (!p || !R1 || level < 1 || level >= int(p->P.lv.size())) { g_err = "bad level"; return -1; }
+  const imsmg_gen_spec &s = p->P.spec;
+  std::vector<double> R = two_scale(s.basis, p->P.lv[level - 1].n, s.degree, s.box_lo, s.box_hi);
+  std::copy(R.begin(), R.end(), R1);
+  return 0;
+}
+
 int imsmg_gen_get_blocks(const imsmg_gen_problem *p, int level, int32_t *ptr, int32_t *idx, int32_t *assoc) {
   if (!p || level < 0 || level >= int(p->P.lv.size())) { g_err = "bad level"; return -1; }
   const LevelData &L = p->P.lv[level];

@@ -35,6 +35,7 @@ def _load():
     lib.imsmg_gen_get_operator.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.imsmg_gen_get_restriction.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.imsmg_gen_get_blocks.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.imsmg_gen_get_two_scale.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
     lib.imsmg_gen_get_rhs.argtypes = [C.c_void_p, C.c_void_p]
     lib.imsmg_gen_get_elements.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.imsmg_gen_get_mass.argtypes = [C.c_void_p, C.c_void_p]
@@ -90,6 +91,7 @@ class GenLevel:
     elem_ptr: Optional[np.ndarray] = None  # active element -> active functions (CSR)
     elem_idx: Optional[np.ndarray] = None
     elem_id: Optional[np.ndarray] = None   # element index of each active element
+    two_scale: Optional[np.ndarray] = None  # 1D factor of R (coarser 1D functions x these)
 
     @property
     def n(self):
@@ -147,6 +149,7 @@ def generate(w, with_mass: bool = False, nthreads: int = 0, orders=None) -> Gene
             assert lib.imsmg_gen_get_operator(h, l, _ptr(d2l), _ptr(rp), _ptr(col), _ptr(val)) == 0
             A = sp.csr_matrix((val, col, rp), shape=(n, n))
             R = None
+            R1 = None
             if l > 0:
                 nc = levels[l - 1].n
                 rrp = np.zeros(nc + 1, dtype=np.int32)
@@ -154,6 +157,8 @@ def generate(w, with_mass: bool = False, nthreads: int = 0, orders=None) -> Gene
                 rval = np.zeros(info.r_nnz, dtype=np.float64)
                 assert lib.imsmg_gen_get_restriction(h, l, _ptr(rrp), _ptr(rcol), _ptr(rval)) == 0
                 R = sp.csr_matrix((rval, rcol, rrp), shape=(nc, n))
+                R1 = np.zeros((levels[l - 1].lattice[0], info.lattice[0]), dtype=np.float64)
+                assert lib.imsmg_gen_get_two_scale(h, l, _ptr(R1)) == 0
             bp = bi = ba = None
             if info.nblocks > 0:
                 bp = np.zeros(info.nblocks + 1, dtype=np.int32)
@@ -169,7 +174,8 @@ def generate(w, with_mass: bool = False, nthreads: int = 0, orders=None) -> Gene
             levels.append(GenLevel(n_elements=info.n_elements, lattice=tuple(info.lattice[:w.dim]),
                                    dof_to_lattice=d2l, A=A, R=R, block_ptr=bp, block_idx=bi,
                                    block_assoc=ba, n_cut=info.n_cut, eta_min=info.eta_min, eta=eta,
-                                   elem_ptr=ep, elem_idx=ei, elem_id=eid))
+                                   elem_ptr=ep, elem_idx=ei, elem_id=eid,
+                                   two_scale=R1 if l > 0 else None))
         nf = levels[-1].n
         b = np.zeros(nf, dtype=np.float64)
         lib.imsmg_gen_get_rhs(h, _ptr(b))

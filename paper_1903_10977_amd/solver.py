@@ -38,7 +38,8 @@ class Elements(C.Structure):
 
 
 class Lattice(C.Structure):
-    _fields_ = [("dim", C.c_int32), ("shape", C.c_int32 * 3), ("reach", C.c_int32), ("dof_to_lattice", C.c_void_p)]
+    _fields_ = [("dim", C.c_int32), ("shape", C.c_int32 * 3), ("reach", C.c_int32), ("dof_to_lattice", C.c_void_p),
+                ("two_scale", C.c_void_p)]
 
 
 class Options(C.Structure):
@@ -161,7 +162,7 @@ class Solver:
             pass
 
     # ------------------------------------------------------------- setup
-    def setup(self, problem, options: Options = None, dim: int = None, reach: int = None):
+    def setup(self, problem, options: Options = None, dim: int = None, reach: int = None, implicit_transfer=True):
         """problem: a generator.GeneratedProblem (levels 0 = coarsest)."""
         w = problem.workload
         dim = dim or w.dim
@@ -180,7 +181,11 @@ class Solver:
             d2l = _i32(lev.dof_to_lattice)
             keep.append(d2l)
             shp = (C.c_int32 * 3)(*(list(lev.lattice) + [1] * (3 - len(lev.lattice))))
-            Lt[l] = Lattice(dim, shp, reach, _p(d2l).value)
+            ts = None
+            if implicit_transfer and l > 0 and getattr(lev, "two_scale", None) is not None:
+                ts = np.ascontiguousarray(lev.two_scale, dtype=np.float64)
+                keep.append(ts)
+            Lt[l] = Lattice(dim, shp, reach, _p(d2l).value, _p(ts).value if ts is not None else None)
             if l > 0:
                 Rm = lev.R
                 rrp, rci, rva = _i32(Rm.indptr), _i32(Rm.indices), np.ascontiguousarray(Rm.data, np.float64)

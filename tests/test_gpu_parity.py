@@ -52,10 +52,10 @@ def _problem(name):
     return _cache[name]
 
 
-def _solver(S, g, **opt):
+def _solver(S, g, implicit_transfer=True, **opt):
     w = g.workload
     o = S.default_options(nu_pre=w.nu, nu_post=w.nu, **opt)
-    return S.Solver(0).setup(g, o).factor()
+    return S.Solver(0).setup(g, o, implicit_transfer=implicit_transfer).factor()
 
 
 def _t(a):
@@ -66,11 +66,12 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+@pytest.mark.parametrize("implicit", [True, False], ids=["tensor", "ell"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_level_operators_and_transfers(name):
+def test_level_operators_and_transfers(name, implicit):
     S = _gpu()
     w, g, op = _problem(name)
-    sol = _solver(S, g)
+    sol = _solver(S, g, implicit_transfer=implicit)
     rng = np.random.default_rng(7)
     for l in range(w.levels):
         A = op.hier.A[l]
