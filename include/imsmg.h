@@ -108,6 +108,8 @@ typedef struct {
   int32_t use_graph;   /* replay each block of check_every iterations as one hipGraph */
   int32_t timing;      /* record HIP events around the finest-level residual kernel */
   double gamma;        /* > 0: uniform damping on all levels; <= 0: 1 / max_K N_K per level */
+  int32_t compress;    /* 1: rows equal to the level's interior stencil (1e-14 relative) read that
+                          stencil instead of their own values (default 1) */
 } imsmg_options;
 
 typedef struct {
@@ -118,7 +120,7 @@ typedef struct {
   double solve_ms;       /* wall time of the call */
 } imsmg_info;
 
-/* Fills opt with the defaults (FP64, V(1,1), max_iter 500, check_every 4, graph on). */
+/* Fills opt with the defaults (FP64, V(1,1), max_iter 500, check_every 4, graph on, compress on). */
 void imsmg_default_options(imsmg_options *opt);
 
 /* Creates a context on HIP device `device`.  stream: a hipStream_t to order

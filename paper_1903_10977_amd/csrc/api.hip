@@ -62,10 +62,16 @@ struct Level {
   int64_t lattice = 0, guard = 0;
   std::vector<int32_t> h_row_lat;
   int32_t *row_lat = nullptr;
-  double *val = nullptr;
-  float *val32 = nullptr;
-  // padded vectors (pointers already shifted past the guard band)
-  double *r = nullptr, *x = nullptr, *rh = nullptr;
+  double *val = nullptr;            // full lattice-ELL (setup, factorization, coarsest matrix)
+  // compressed operator used by the solve kernels
+  std::vector<uint32_t> h_meta;
+  uint32_t *meta = nullptr;
+  OpView<double> op64{};
+  OpView<float> op32{};
+  int n_uniform = 0;
+  // padded vectors (pointers already shifted past the guard band); x and x2
+  // alternate between smoothing steps, xs is where a V-cycle on this level starts
+  double *r = nullptr, *x = nullptr, *x2 = nullptr, *rh = nullptr, *xs = nullptr;
   // restriction R_l (rows: coarse level) and R_l^T (rows: this level)
   int rw = 0, tw = 0;
   int32_t *rcol = nullptr, *tcol = nullptr;
@@ -80,11 +86,11 @@ struct Level {
   std::vector<double> omega;  // optional per-block weights
   // factorized smoother
   std::vector<int32_t> f_ptr, f_idx;  // post-removal blocks (incl. added singletons)
-  int nb_general = 0, ntask = 0;
-  int32_t *bstart = nullptr, *bsize = nullptr, *task_block = nullptr, *blat = nullptr;
-  int64_t *binv_off = nullptr;
-  double *binv = nullptr, *bw = nullptr, *ybuf = nullptr, *c = nullptr;
-  int32_t *gptr = nullptr, *gidx = nullptr;
+  double *c = nullptr;               // trivial rows: omega_j / A_ii, else 0
+  int ng = 0;                         // rows in general blocks
+  int32_t *grow_lat = nullptr, *gptr = nullptr, *ent_mem = nullptr, *ent_n = nullptr, *blat = nullptr;
+  int64_t *ent_off = nullptr;
+  double *winv = nullptr;             // omega_j A_j^{-1} of the general blocks (symmetric)
   double gamma = 0.0;
   // elements (host)
   std::vector<int32_t> e_ptr, e_idx;
@@ -165,7 +171,7 @@ void lat_multi(int64_t L, const int *shape, int dim, int *m) {
 void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice &lat) {
   hipStream_t s = c->stream;
   if (lat.dim < 2 || lat.dim > 3) bad("lattice dim must be 2 or 3");
-  if (lat.reach < 1 || lat.reach > 3) bad("lattice reach must be 1..3");
+  if (lat.reach < 1 || (lat.dim == 3 && lat.reach > 2) || lat.reach > 5) bad("lattice reach must be 1..5 (2D) or 1..2 (3D)");
   if (A.nrows <= 0 || A.nrows != A.ncols) bad("A must be square and non-empty");
   if (!A.rowptr || !A.col || !A.val || !lat.dof_to_lattice) bad("null CSR or lattice array");
   L.dim = lat.dim;
@@ -225,22 +231,96 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
   h2d(s, L.row_lat, L.h_row_lat.data(), L.n);
   L.val = dalloc<double>(c->owned, ell.size());
   h2d(s, L.val, ell.data(), ell.size());
+  // uniform interior stencil: the most frequent row among rows with all K
+  // slots non-zero (rows hashed after rounding to 12 significant digits)
+  std::vector<double> ref(L.K, 0.0);
+  bool have_ref = false;
+  if (c->opt.compress && L.K <= IMSMG_MAX_REF) {
+    std::vector<std::pair<uint64_t, int>> keys;
+    keys.reserve(L.n);
+    for (int i = 0; i < L.n; ++i) {
+      bool full = true;
+      uint64_t h = 1469598103934665603ull;
+      for (int sl = 0; sl < L.K && full; ++sl) {
+        const double v = ell[size_t(sl) * L.n + i];
+        if (v == 0.0) full = false;
+        const double q = std::nearbyint(v * 1e12);
+        uint64_t u;
+        std::memcpy(&u, &q, 8);
+        h = (h ^ u) * 1099511628211ull;
+      }
+      if (full) keys.push_back({h, i});
+    }
+    std::sort(keys.begin(), keys.end());
+    int best = -1, bestc = 0;
+    for (size_t a = 0; a < keys.size();) {
+      size_t b = a;
+      while (b < keys.size() && keys[b].first == keys[a].first) ++b;
+      if (int(b - a) > bestc) {
+        bestc = int(b - a);
+        best = keys[a].second;
+      }
+      a = b;
+    }
+    if (best >= 0 && bestc >= 16) {
+      for (int sl = 0; sl < L.K; ++sl) ref[sl] = ell[size_t(sl) * L.n + best];
+      have_ref = true;
+    }
+  }
+  double refmax = 0.0;
+  for (double v : ref) refmax = std::max(refmax, std::fabs(v));
+  L.h_meta.assign(L.n, 0);
+  std::vector<int32_t> comp;
+  for (int i = 0; i < L.n; ++i) {
+    bool uni = have_ref;
+    for (int sl = 0; sl < L.K && uni; ++sl)
+      uni = std::fabs(ell[size_t(sl) * L.n + i] - ref[sl]) <= 1e-14 * refmax;
+    if (uni) {
+      L.h_meta[i] = kMetaIndex;
+      ++L.n_uniform;
+    } else {
+      L.h_meta[i] = uint32_t(comp.size());
+      comp.push_back(i);
+    }
+  }
+  const int nv = int(comp.size());
+  std::vector<double> cv(size_t(L.K) * std::max(nv, 1), 0.0);
+  for (int g = 0; g < nv; ++g)
+    for (int sl = 0; sl < L.K; ++sl) cv[size_t(sl) * nv + g] = ell[size_t(sl) * L.n + comp[g]];
+  L.meta = dalloc<uint32_t>(c->owned, L.n);
+  h2d(s, L.meta, L.h_meta.data(), L.n);
+  double *cv64 = dalloc<double>(c->owned, cv.size());
+  h2d(s, cv64, cv.data(), cv.size());
+  L.op64.off = L.off;
+  L.op64.val = cv64;
+  L.op64.nv = nv;
+  L.op32.off = L.off;
+  L.op32.nv = nv;
+  for (int sl = 0; sl < L.K && sl < IMSMG_MAX_REF; ++sl) {
+    L.op64.ref.v[sl] = ref[sl];
+    L.op32.ref.v[sl] = float(ref[sl]);
+  }
   if (c->opt.precision == IMSMG_MIXED) {
-    std::vector<float> e32(ell.begin(), ell.end());
-    L.val32 = dalloc<float>(c->owned, e32.size());
-    h2d(s, L.val32, e32.data(), e32.size());
+    std::vector<float> c32(cv.begin(), cv.end());
+    float *cv32 = dalloc<float>(c->owned, c32.size());
+    h2d(s, cv32, c32.data(), c32.size());
+    L.op32.val = cv32;
     HIP_CHECK_RET(hipStreamSynchronize(s));
   }
   const size_t vlen = size_t(L.lattice + 2 * L.guard);
-  double *vs[3];
-  for (int k = 0; k < 3; ++k) {
+  double *vs[4];
+  for (int k = 0; k < 4; ++k) {
     double *b = dalloc<double>(c->owned, vlen);
     HIP_CHECK_RET(hipMemsetAsync(b, 0, vlen * sizeof(double), s));
     vs[k] = b + L.guard;
   }
   L.r = vs[0];
   L.x = vs[1];
-  L.rh = vs[2];
+  L.x2 = vs[2];
+  L.rh = vs[3];
+  // a V-cycle on this level runs (nu_pre - 1) + nu_post ping-pong steps: start
+  // in the buffer that makes the result land in x
+  L.xs = ((c->opt.nu_pre - 1 + c->opt.nu_post) % 2) ? L.x2 : L.x;
   HIP_CHECK_RET(hipStreamSynchronize(s));
 }
 
@@ -387,53 +467,72 @@ void setup_transfer(imsmg_ctx *c, Level &F, const Level &Cl, const imsmg_csr &R,
 }
 
 // ------------------------------------------------------------ V-cycle
+hipEvent_t *timed_pair(imsmg_ctx *c) {
+  if (c->ev_used + 2 > c->ev_pool.size()) {
+    for (int k = 0; k < 64; ++k) {
+      hipEvent_t e;
+      HIP_CHECK_RET(hipEventCreate(&e));
+      c->ev_pool.push_back(e);
+    }
+  }
+  hipEvent_t *p = &c->ev_pool[c->ev_used];
+  c->ev_used += 2;
+  return p;
+}
+
+bool mixed(imsmg_ctx *c) { return c->opt.precision == IMSMG_MIXED; }
+
+// y = b - A_l x (b == nullptr: y = A_l x); the V-cycle operator precision
 void residual(imsmg_ctx *c, Level &L, const double *x, const double *b, double *y, const int32_t *done,
               bool timed) {
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (timed) {
-    if (c->ev_used + 2 > c->ev_pool.size()) {
-      for (int k = 0; k < 64; ++k) {
-        hipEvent_t e;
-        HIP_CHECK_RET(hipEventCreate(&e));
-        c->ev_pool.push_back(e);
-      }
-    }
-    e0 = c->ev_pool[c->ev_used++];
-    e1 = c->ev_pool[c->ev_used++];
-    HIP_CHECK_RET(hipEventRecord(e0, c->stream));
-  }
-  if (c->opt.precision == IMSMG_MIXED && L.val32)
-    launch_ell_residual_f32(c->stream, L.n, L.K, L.off, L.row_lat, L.val32, x, b, y, done);
+  hipEvent_t *ev = timed ? timed_pair(c) : nullptr;
+  if (ev) HIP_CHECK_RET(hipEventRecord(ev[0], c->stream));
+  if (mixed(c))
+    launch_residual(c->stream, L.n, L.K, L.op32, L.row_lat, L.meta, x, b, y, done);
   else
-    launch_ell_residual(c->stream, L.n, L.K, L.off, L.row_lat, L.val, x, b, y, done);
-  if (timed) HIP_CHECK_RET(hipEventRecord(e1, c->stream));
+    launch_residual(c->stream, L.n, L.K, L.op64, L.row_lat, L.meta, x, b, y, done);
+  if (ev) HIP_CHECK_RET(hipEventRecord(ev[1], c->stream));
+}
+
+// smoothing step from xa: rh = r - A xa, xb = xa + S rh  (trivial rows fused,
+// then the general rows)
+void smooth_step(imsmg_ctx *c, Level &L, const double *xa, double *xb, const int32_t *done, bool timed) {
+  hipEvent_t *ev = timed ? timed_pair(c) : nullptr;
+  if (ev) HIP_CHECK_RET(hipEventRecord(ev[0], c->stream));
+  if (mixed(c))
+    launch_residual_smooth(c->stream, L.n, L.K, L.op32, L.row_lat, L.meta, L.c, xa, L.r, L.rh, xb, done);
+  else
+    launch_residual_smooth(c->stream, L.n, L.K, L.op64, L.row_lat, L.meta, L.c, xa, L.r, L.rh, xb, done);
+  if (ev) HIP_CHECK_RET(hipEventRecord(ev[1], c->stream));
+  launch_smooth_general(c->stream, L.ng, L.grow_lat, L.gptr, L.ent_off, L.ent_mem, L.ent_n, L.blat, L.winv, L.rh, xb,
+                        done);
 }
 
 // rc = R_l rf (fine level L, coarse level Cl; padded vectors)
-void restrict_to(imsmg_ctx *c, Level &L, Level &Cl, const double *rf, double *rc, const int32_t *done) {
+// (xinit != nullptr: also xinit = c_coarse * rc, the trivial part of the
+// coarse level's first smoothing step)
+void restrict_to(imsmg_ctx *c, Level &L, Level &Cl, const double *rf, double *rc, double *xinit,
+                 const int32_t *done) {
+  const double *ci = xinit ? Cl.c : nullptr;
   if (L.tensor)
     launch_tensor_transfer(c->stream, L.dim, Cl.n, Cl.row_lat, Cl.shape[0], Cl.shape[1], L.rb_start, L.rb_len,
-                           L.rb_coef, L.rbW, L.shape[0], L.shape[1], rf, rc, 0, done);
+                           L.rb_coef, L.rbW, L.shape[0], L.shape[1], rf, rc, 0, ci, xinit, done);
   else
-    launch_ell_gather(c->stream, Cl.n, L.rw, Cl.row_lat, L.rcol, L.rval, rf, rc, 0, done);
+    launch_ell_gather(c->stream, Cl.n, L.rw, Cl.row_lat, L.rcol, L.rval, rf, rc, 0, ci, xinit, done);
 }
 
 // xf += R_l^T xc
 void prolong_add(imsmg_ctx *c, Level &L, Level &Cl, const double *xc, double *xf, const int32_t *done) {
   if (L.tensor)
     launch_tensor_transfer(c->stream, L.dim, L.n, L.row_lat, L.shape[0], L.shape[1], L.pb_start, L.pb_len, L.pb_coef,
-                           L.pbW, Cl.shape[0], Cl.shape[1], xc, xf, 1, done);
+                           L.pbW, Cl.shape[0], Cl.shape[1], xc, xf, 1, nullptr, nullptr, done);
   else
-    launch_ell_gather(c->stream, L.n, L.tw, L.row_lat, L.tcol, L.tval, xc, xf, 1, done);
+    launch_ell_gather(c->stream, L.n, L.tw, L.row_lat, L.tcol, L.tval, xc, xf, 1, nullptr, nullptr, done);
 }
 
-void smooth(imsmg_ctx *c, Level &L, const double *r, double *x, int accumulate, const int32_t *done) {
-  launch_schwarz_blocks(c->stream, L.ntask, L.task_block, L.bstart, L.bsize, L.binv_off, L.blat, L.binv, L.bw, r,
-                        L.ybuf, done);
-  launch_schwarz_gather(c->stream, L.n, L.row_lat, L.c, L.gptr, L.gidx, L.ybuf, r, x, accumulate, done);
-}
-
-// V-cycle on level l: input residual in lv[l].r, correction out in lv[l].x
+// V-cycle on level l (Algorithm alg:MGV): input residual in lv[l].r; on entry
+// lv[l].xs already holds c * r (trivial part of the first smoothing step,
+// written by the caller's fused kernel); the correction is left in lv[l].x.
 void vcycle_level(imsmg_ctx *c, int l, const int32_t *done, bool timing) {
   Level &L = c->lv[l];
   if (l == 0) {
@@ -442,18 +541,21 @@ void vcycle_level(imsmg_ctx *c, int l, const int32_t *done, bool timing) {
   }
   Level &Cl = c->lv[l - 1];
   const bool fine = (l == int(c->lv.size()) - 1) && timing;
-  smooth(c, L, L.r, L.x, 0, done);
+  // first smoothing step from x = 0: x = S r
+  launch_smooth_general(c->stream, L.ng, L.grow_lat, L.gptr, L.ent_off, L.ent_mem, L.ent_n, L.blat, L.winv, L.r, L.xs,
+                        done);
+  double *xa = L.xs, *xb = (L.xs == L.x) ? L.x2 : L.x;
   for (int k = 1; k < c->opt.nu_pre; ++k) {
-    residual(c, L, L.x, L.r, L.rh, done, fine);
-    smooth(c, L, L.rh, L.x, 1, done);
+    smooth_step(c, L, xa, xb, done, fine);
+    std::swap(xa, xb);
   }
-  residual(c, L, L.x, L.r, L.rh, done, fine);
-  restrict_to(c, L, Cl, L.rh, Cl.r, done);
+  residual(c, L, xa, L.r, L.rh, done, fine);
+  restrict_to(c, L, Cl, L.rh, Cl.r, l - 1 > 0 ? Cl.xs : nullptr, done);
   vcycle_level(c, l - 1, done, timing);
-  prolong_add(c, L, Cl, Cl.x, L.x, done);
+  prolong_add(c, L, Cl, Cl.x, xa, done);
   for (int k = 0; k < c->opt.nu_post; ++k) {
-    residual(c, L, L.x, L.r, L.rh, done, fine);
-    smooth(c, L, L.rh, L.x, 1, done);
+    smooth_step(c, L, xa, xb, done, fine);
+    std::swap(xa, xb);
   }
 }
 
@@ -471,6 +573,7 @@ void collect_timing(imsmg_ctx *c) {
 void factor_level(imsmg_ctx *c, int l) {
   hipStream_t s = c->stream;
   Level &L = c->lv[l];
+  for (auto &m : L.h_meta) m &= ~kMetaGeneral;
   const int nb_in = int(L.in_ptr.size()) - 1;
   const int n = L.n;
   // which input blocks need the eigensolver (size >= 2)
@@ -615,25 +718,20 @@ void factor_level(imsmg_ctx *c, int l) {
     if (sz == 1 && fcount[fidx[fptr[j]]] == 1) trivial[fidx[fptr[j]]] = j;
     else general[j] = 1;
   }
-  // general blocks: singletons that share their DOF with another block need
-  // an inverse too; they get 1/A_ii through a factorized copy below
-  std::vector<int32_t> g_start(1, 0), g_size, g_lat, g_task_block;
+  // general blocks (all blocks except the trivial singletons): inverse
+  // offsets; singletons that share their DOF with another block need 1/A_ii
+  std::vector<int32_t> g_blocks, g_size;
   std::vector<int64_t> g_invoff;
   std::vector<double> g_w;
-  std::vector<int32_t> single_rows;  // general singletons needing 1/A_ii
+  std::vector<int32_t> single_rows;
   std::vector<int64_t> single_off;
   int64_t extra_off = h_invoff[nf];
   for (int j = 0; j < nbf; ++j) {
     if (!general[j]) continue;
     const int sz = fptr[j + 1] - fptr[j];
-    const int gb = int(g_size.size());
+    g_blocks.push_back(j);
     g_size.push_back(sz);
     g_w.push_back(w[j]);
-    for (int k = fptr[j]; k < fptr[j + 1]; ++k) {
-      g_lat.push_back(L.h_row_lat[fidx[k]]);
-      g_task_block.push_back(gb);
-    }
-    g_start.push_back(g_start.back() + sz);
     if (finvoff[j] >= 0) {
       g_invoff.push_back(finvoff[j]);
     } else {
@@ -644,9 +742,7 @@ void factor_level(imsmg_ctx *c, int l) {
       extra_off += 1;
     }
   }
-  const int ng = int(g_size.size());
-  L.nb_general = ng;
-  L.ntask = g_start.back();
+  const int nbg = int(g_blocks.size());
   // inverse storage: factorized inverses followed by general singletons
   double *inv = d_inv;
   if (!single_rows.empty()) {
@@ -675,44 +771,74 @@ void factor_level(imsmg_ctx *c, int l) {
     h2d(s, inv + h_invoff[nf], tail.data(), tail.size());
     HIP_CHECK_RET(hipStreamSynchronize(s));
   }
-  L.binv = inv;
-  L.bstart = dalloc<int32_t>(c->factor_owned, g_start.size());
-  L.bsize = dalloc<int32_t>(c->factor_owned, g_size.size());
-  L.blat = dalloc<int32_t>(c->factor_owned, g_lat.size());
-  L.task_block = dalloc<int32_t>(c->factor_owned, g_task_block.size());
-  L.binv_off = dalloc<int64_t>(c->factor_owned, g_invoff.size());
-  L.bw = dalloc<double>(c->factor_owned, g_w.size());
-  L.ybuf = dalloc<double>(c->factor_owned, L.ntask);
-  h2d(s, L.bstart, g_start.data(), g_start.size());
-  h2d(s, L.bsize, g_size.data(), g_size.size());
-  h2d(s, L.blat, g_lat.data(), g_lat.size());
-  h2d(s, L.task_block, g_task_block.data(), g_task_block.size());
-  h2d(s, L.binv_off, g_invoff.data(), g_invoff.size());
-  h2d(s, L.bw, g_w.data(), g_w.size());
-  // gather map: row -> task positions (ascending)
-  std::vector<int32_t> gp(n + 1, 0), gi(L.ntask);
-  for (int tk = 0; tk < L.ntask; ++tk) {
-    (void)tk;
-  }
+  // fold the damping weight into each general block's inverse
   {
-    std::vector<int32_t> task_row(L.ntask);
-    int tk = 0;
-    for (int j = 0; j < nbf; ++j) {
-      if (!general[j]) continue;
-      for (int k = fptr[j]; k < fptr[j + 1]; ++k) task_row[tk++] = fidx[k];
-    }
-    for (int k = 0; k < L.ntask; ++k) gp[task_row[k] + 1]++;
-    for (int i = 0; i < n; ++i) gp[i + 1] += gp[i];
-    std::vector<int32_t> fill(gp.begin(), gp.end() - 1);
-    for (int k = 0; k < L.ntask; ++k) gi[fill[task_row[k]]++] = k;
+    int64_t *d_off = dalloc<int64_t>(tmp, std::max(nbg, 1));
+    int32_t *d_sz = dalloc<int32_t>(tmp, std::max(nbg, 1));
+    double *d_gw = dalloc<double>(tmp, std::max(nbg, 1));
+    h2d(s, d_off, g_invoff.data(), nbg);
+    h2d(s, d_sz, g_size.data(), nbg);
+    h2d(s, d_gw, g_w.data(), nbg);
+    launch_scale_blocks(s, nbg, d_off, d_sz, d_gw, inv);
+    HIP_CHECK_RET(hipGetLastError());
+    HIP_CHECK_RET(hipStreamSynchronize(s));
   }
-  L.gptr = dalloc<int32_t>(c->factor_owned, n + 1);
-  L.gidx = dalloc<int32_t>(c->factor_owned, gi.size());
-  h2d(s, L.gptr, gp.data(), n + 1);
-  h2d(s, L.gidx, gi.data(), gi.size());
+  L.winv = inv;
+  // member lattice lists of the general blocks, and per general row its
+  // entries (row a of block j): inverse row offset, member list, size
+  std::vector<int32_t> mem_start(nbg), blat;
+  for (int q = 0; q < nbg; ++q) {
+    const int j = g_blocks[q];
+    mem_start[q] = int32_t(blat.size());
+    for (int k = fptr[j]; k < fptr[j + 1]; ++k) blat.push_back(L.h_row_lat[fidx[k]]);
+  }
+  std::vector<int32_t> cnt(n, 0);
+  for (int q = 0; q < nbg; ++q) {
+    const int j = g_blocks[q];
+    for (int k = fptr[j]; k < fptr[j + 1]; ++k) cnt[fidx[k]]++;
+  }
+  std::vector<int32_t> grows, gp(1, 0), row_slot(n, -1);
+  for (int i = 0; i < n; ++i)
+    if (cnt[i] > 0) {
+      row_slot[i] = int32_t(grows.size());
+      grows.push_back(i);
+      gp.push_back(gp.back() + cnt[i]);
+    }
+  const int ngr = int(grows.size());
+  std::vector<int64_t> e_off(gp.back());
+  std::vector<int32_t> e_mem(gp.back()), e_n(gp.back()), fillp(gp.begin(), gp.end() - 1);
+  for (int q = 0; q < nbg; ++q) {  // ascending block order: deterministic summation
+    const int j = g_blocks[q];
+    const int sz = fptr[j + 1] - fptr[j];
+    for (int a = 0; a < sz; ++a) {
+      const int i = fidx[fptr[j] + a];
+      const int e = fillp[row_slot[i]]++;
+      e_off[e] = g_invoff[q] + int64_t(a) * sz;  // row a (= column a) of the symmetric inverse
+      e_mem[e] = mem_start[q];
+      e_n[e] = sz;
+    }
+  }
+  std::vector<int32_t> grow_lat(ngr);
+  for (int t = 0; t < ngr; ++t) {
+    grow_lat[t] = L.h_row_lat[grows[t]];
+    L.h_meta[grows[t]] |= kMetaGeneral;
+  }
+  L.ng = ngr;
+  L.grow_lat = dalloc<int32_t>(c->factor_owned, std::max(ngr, 1));
+  L.gptr = dalloc<int32_t>(c->factor_owned, gp.size());
+  L.ent_off = dalloc<int64_t>(c->factor_owned, std::max<size_t>(e_off.size(), 1));
+  L.ent_mem = dalloc<int32_t>(c->factor_owned, std::max<size_t>(e_mem.size(), 1));
+  L.ent_n = dalloc<int32_t>(c->factor_owned, std::max<size_t>(e_n.size(), 1));
+  L.blat = dalloc<int32_t>(c->factor_owned, std::max<size_t>(blat.size(), 1));
+  h2d(s, L.grow_lat, grow_lat.data(), grow_lat.size());
+  h2d(s, L.gptr, gp.data(), gp.size());
+  h2d(s, L.ent_off, e_off.data(), e_off.size());
+  h2d(s, L.ent_mem, e_mem.data(), e_mem.size());
+  h2d(s, L.ent_n, e_n.data(), e_n.size());
+  h2d(s, L.blat, blat.data(), blat.size());
+  h2d(s, L.meta, L.h_meta.data(), L.h_meta.size());
   // trivial rows: c_i = w_j / A_ii
   std::vector<int32_t> tb(n, -1);
-  std::vector<double> wt(nbf, 0.0);
   for (int i = 0; i < n; ++i)
     if (trivial[i] >= 0) tb[i] = trivial[i];
   int32_t *d_tb = dalloc<int32_t>(tmp, n);
@@ -751,6 +877,11 @@ void factor_coarsest(imsmg_ctx *c) {
   HIP_CHECK_RET(hipStreamSynchronize(s));
   HIP_CHECK_RET(hipMemcpy(&h_bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost));
   if (h_bad) bad("coarsest operator is not SPD (non-positive Gauss-Jordan pivot)", IMSMG_ERR_NOT_SPD);
+  if (c->lv.size() == 1) {  // single level: the "first smoothing step" scaling is zero
+    L.c = dalloc<double>(c->factor_owned, n);
+    HIP_CHECK_RET(hipMemsetAsync(L.c, 0, size_t(n) * sizeof(double), s));
+    HIP_CHECK_RET(hipStreamSynchronize(s));
+  }
 }
 
 void destroy_graph(imsmg_ctx *c) {
@@ -761,15 +892,16 @@ void destroy_graph(imsmg_ctx *c) {
   c->graph_iters = 0;
 }
 
-// One CG iteration after the initial residual: z = B r, beta, p, q = A p, alpha, x, r.
+// One CG iteration after the initial residual: z = B r, beta, p, q = A p,
+// alpha, x, r (the update kernel also prepares c * r for the next V-cycle).
 void cg_iteration(imsmg_ctx *c, bool timing) {
   Level &F = c->lv.back();
   const int32_t *done = &c->st->done;
   vcycle_level(c, int(c->lv.size()) - 1, done, timing);
   launch_cg_dot_rz(c->stream, F.n, F.row_lat, F.r, F.x, c->part, c->st);
   launch_cg_direction(c->stream, F.n, F.row_lat, F.x, c->p, c->st);
-  launch_cg_spmv_pq(c->stream, F.n, F.K, F.off, F.row_lat, F.val, c->p, c->q, c->part, c->st);
-  launch_cg_update(c->stream, F.n, F.row_lat, c->p, c->q, c->xs, F.r, c->part, c->st, c->opt.max_iter);
+  launch_cg_spmv_pq(c->stream, F.n, F.K, F.op64, F.row_lat, F.meta, c->p, c->q, c->part, c->st);
+  launch_cg_update(c->stream, F.n, F.row_lat, c->p, c->q, c->xs, F.r, F.c, F.xs, c->part, c->st, c->opt.max_iter);
 }
 
 }  // namespace
@@ -787,6 +919,7 @@ void imsmg_default_options(imsmg_options *o) {
   o->use_graph = 1;
   o->timing = 0;
   o->gamma = 0.0;
+  o->compress = 1;
 }
 
 int imsmg_create(imsmg_ctx **out, int device, void *stream) {
@@ -942,6 +1075,7 @@ int imsmg_vcycle(imsmg_ctx *c, const double *r_dev, double *z_dev) {
     if (!r_dev || !z_dev) bad("null vector");
     Level &F = c->lv.back();
     launch_scatter(c->stream, F.n, F.row_lat, r_dev, F.r);
+    launch_diag_scale(c->stream, F.n, F.row_lat, F.c, F.r, F.xs, c->zero_flag);
     vcycle_level(c, int(c->lv.size()) - 1, c->zero_flag, c->opt.timing != 0);
     launch_gather(c->stream, F.n, F.row_lat, F.x, z_dev);
     HIP_CHECK_RET(hipGetLastError());
@@ -965,7 +1099,8 @@ int imsmg_pcg_solve(imsmg_ctx *c, const double *b_dev, double *x_dev, double rto
     CGState h{};
     int restarts = 0;
     while (true) {
-      launch_cg_init(s, F.n, F.K, F.off, F.row_lat, F.val, c->xs, c->bs, F.r, c->part, c->st, rtol);
+      launch_cg_init(s, F.n, F.K, F.op64, F.row_lat, F.meta, c->xs, c->bs, F.r, c->part, c->st, rtol);
+      launch_diag_scale(s, F.n, F.row_lat, F.c, F.r, F.xs, &c->st->done);
       HIP_CHECK_RET(hipGetLastError());
       const int m = c->opt.check_every;
       const bool graph = c->opt.use_graph && !timing;
@@ -992,7 +1127,7 @@ int imsmg_pcg_solve(imsmg_ctx *c, const double *b_dev, double *x_dev, double rto
         if (h.done) break;
       }
       // true residual ||b - A x|| / ||b||
-      launch_cg_true_residual(s, F.n, F.K, F.off, F.row_lat, F.val, c->xs, c->bs, nullptr, c->part, c->st);
+      launch_cg_true_residual(s, F.n, F.K, F.op64, F.row_lat, F.meta, c->xs, c->bs, c->part, c->st);
       HIP_CHECK_RET(hipMemcpyAsync(&h, c->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
       HIP_CHECK_RET(hipStreamSynchronize(s));
       const double true_rel = h.bb > 0.0 ? std::sqrt(h.aux / h.bb) : 0.0;
@@ -1040,7 +1175,9 @@ int imsmg_apply_smoother(imsmg_ctx *c, int level, const double *r, double *y) {
     if (level < 1 || level >= int(c->lv.size()) || !r || !y) bad("bad level or vector");
     Level &L = c->lv[level];
     launch_scatter(c->stream, L.n, L.row_lat, r, L.rh);
-    smooth(c, L, L.rh, L.x, 0, c->zero_flag);
+    launch_diag_scale(c->stream, L.n, L.row_lat, L.c, L.rh, L.x, c->zero_flag);
+    launch_smooth_general(c->stream, L.ng, L.grow_lat, L.gptr, L.ent_off, L.ent_mem, L.ent_n, L.blat, L.winv, L.rh,
+                          L.x, c->zero_flag);
     launch_gather(c->stream, L.n, L.row_lat, L.x, y);
     HIP_CHECK_RET(hipGetLastError());
     HIP_CHECK_RET(hipStreamSynchronize(c->stream));
@@ -1054,7 +1191,7 @@ int imsmg_apply_restriction(imsmg_ctx *c, int level, const double *rf, double *r
     if (level < 1 || level >= int(c->lv.size()) || !rf || !rc) bad("bad level or vector");
     Level &L = c->lv[level], &Cl = c->lv[level - 1];
     launch_scatter(c->stream, L.n, L.row_lat, rf, L.rh);
-    restrict_to(c, L, Cl, L.rh, Cl.r, c->zero_flag);
+    restrict_to(c, L, Cl, L.rh, Cl.r, nullptr, c->zero_flag);
     launch_gather(c->stream, Cl.n, Cl.row_lat, Cl.r, rc);
     HIP_CHECK_RET(hipGetLastError());
     HIP_CHECK_RET(hipStreamSynchronize(c->stream));

@@ -10,6 +10,7 @@
 // part) is issued per workgroup.  Once the `done` flag is set, every kernel
 // returns at once.
 #include "imsmg_internal.h"
+#include "op_row.h"
 
 namespace imsmg {
 
@@ -47,24 +48,12 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ part, 
   return block_sum<kFinThreads>(v, lds);
 }
 
-template <int K>
-__device__ __forceinline__ double ell_row(int i, int n, const Offsets &off, int L, const double *__restrict__ val,
-                                          const double *__restrict__ x, int Kdyn) {
-  double acc = 0.0;
-  if (K > 0) {
-#pragma unroll
-    for (int s = 0; s < K; ++s) acc += val[size_t(s) * n + i] * x[L + off.off[s]];
-  } else {
-    for (int s = 0; s < Kdyn; ++s) acc += val[size_t(s) * n + i] * x[L + off.off[s]];
-  }
-  return acc;
-}
-
 // r = b - A x; partials of ||r||^2 (part[0..g)) and ||b||^2 (part[g..2g))
 template <int K>
-__global__ __launch_bounds__(kRedThreads) void k_cg_init(int n, int Kdyn, Offsets off,
+__global__ __launch_bounds__(kRedThreads) void k_cg_init(int n, int Kdyn, OpView<double> op,
                                                          const int32_t *__restrict__ row_lat,
-                                                         const double *__restrict__ val, const double *__restrict__ x,
+                                                         const uint32_t *__restrict__ meta,
+                                                         const double *__restrict__ x,
                                                          const double *__restrict__ b, double *__restrict__ r,
                                                          double *__restrict__ part) {
   __shared__ double lds[kRedThreads];
@@ -74,7 +63,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_init(int n, int Kdyn, Offset
   if (i < n) {
     const int L = row_lat[i];
     const double bi = b[L];
-    const double ri = bi - ell_row<K>(i, n, off, L, val, x, Kdyn);
+    const double ri = bi - op_row<K, double>(meta[i], op, x, L, Kdyn);
     r[L] = ri;
     rr = ri * ri;
     bb = bi * bi;
@@ -154,9 +143,9 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_direction(int n, const int32
 }
 
 template <int K>
-__global__ __launch_bounds__(kRedThreads) void k_cg_spmv_pq(int n, int Kdyn, Offsets off,
+__global__ __launch_bounds__(kRedThreads) void k_cg_spmv_pq(int n, int Kdyn, OpView<double> op,
                                                             const int32_t *__restrict__ row_lat,
-                                                            const double *__restrict__ val,
+                                                            const uint32_t *__restrict__ meta,
                                                             const double *__restrict__ p, double *__restrict__ q,
                                                             double *__restrict__ part, const CGState *st) {
   if (st->done) return;
@@ -166,7 +155,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_spmv_pq(int n, int Kdyn, Off
   double acc = 0.0;
   if (i < n) {
     const int L = row_lat[i];
-    const double qi = ell_row<K>(i, n, off, L, val, p, Kdyn);
+    const double qi = op_row<K, double>(meta[i], op, p, L, Kdyn);
     q[L] = qi;
     acc = p[L] * qi;
   }
@@ -194,7 +183,8 @@ __global__ __launch_bounds__(kFinThreads) void k_cg_pq_fin(int m, const double *
 __global__ __launch_bounds__(kRedThreads) void k_cg_update(int n, const int32_t *__restrict__ row_lat,
                                                            const double *__restrict__ p,
                                                            const double *__restrict__ q, double *__restrict__ x,
-                                                           double *__restrict__ r, double *__restrict__ part,
+                                                           double *__restrict__ r, const double *__restrict__ c,
+                                                           double *__restrict__ zs, double *__restrict__ part,
                                                            const CGState *st) {
   if (st->done) return;
   __shared__ double lds[kRedThreads];
@@ -207,6 +197,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_update(int n, const int32_t 
     x[L] += alpha * p[L];
     const double ri = r[L] - alpha * q[L];
     r[L] = ri;
+    zs[L] = c[i] * ri;
     acc = ri * ri;
   }
   acc = block_sum<kRedThreads>(acc, lds);
@@ -235,9 +226,9 @@ __global__ __launch_bounds__(kFinThreads) void k_cg_update_fin(int m, const doub
 
 // partials of ||b - A x||^2
 template <int K>
-__global__ __launch_bounds__(kRedThreads) void k_cg_true_residual(int n, int Kdyn, Offsets off,
+__global__ __launch_bounds__(kRedThreads) void k_cg_true_residual(int n, int Kdyn, OpView<double> op,
                                                                   const int32_t *__restrict__ row_lat,
-                                                                  const double *__restrict__ val,
+                                                                  const uint32_t *__restrict__ meta,
                                                                   const double *__restrict__ x,
                                                                   const double *__restrict__ b,
                                                                   double *__restrict__ part) {
@@ -247,7 +238,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_true_residual(int n, int Kdy
   double acc = 0.0;
   if (i < n) {
     const int L = row_lat[i];
-    const double ri = b[L] - ell_row<K>(i, n, off, L, val, x, Kdyn);
+    const double ri = b[L] - op_row<K, double>(meta[i], op, x, L, Kdyn);
     acc = ri * ri;
   }
   acc = block_sum<kRedThreads>(acc, lds);
@@ -270,10 +261,11 @@ __global__ __launch_bounds__(kFinThreads) void k_cg_aux_fin(int m, const double 
     default: KERNEL<0><<<g, kRedThreads, 0, s>>>(__VA_ARGS__); break;           \
   }
 
-void launch_cg_init(hipStream_t s, int n, int K, const Offsets &off, const int32_t *row_lat, const double *val,
-                    const double *x, const double *b, double *r, double *part, CGState *st, double rtol) {
+void launch_cg_init(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
+                    const uint32_t *meta, const double *x, const double *b, double *r, double *part, CGState *st,
+                    double rtol) {
   const int g = reduction_blocks(n);
-  IMSMG_DISPATCH_K(K, k_cg_init, n, K, off, row_lat, val, x, b, r, part);
+  IMSMG_DISPATCH_K(K, k_cg_init, n, K, op, row_lat, meta, x, b, r, part);
   k_cg_init_fin<<<1, kFinThreads, 0, s>>>(g, part, st, rtol);
 }
 
@@ -288,26 +280,24 @@ void launch_cg_direction(hipStream_t s, int n, const int32_t *row_lat, const dou
   k_cg_direction<<<reduction_blocks(n), kRedThreads, 0, s>>>(n, row_lat, z, p, st);
 }
 
-void launch_cg_spmv_pq(hipStream_t s, int n, int K, const Offsets &off, const int32_t *row_lat, const double *val,
-                       const double *p, double *q, double *part, CGState *st) {
+void launch_cg_spmv_pq(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
+                       const uint32_t *meta, const double *p, double *q, double *part, CGState *st) {
   const int g = reduction_blocks(n);
-  IMSMG_DISPATCH_K(K, k_cg_spmv_pq, n, K, off, row_lat, val, p, q, part, st);
+  IMSMG_DISPATCH_K(K, k_cg_spmv_pq, n, K, op, row_lat, meta, p, q, part, st);
   k_cg_pq_fin<<<1, kFinThreads, 0, s>>>(g, part, st);
 }
 
 void launch_cg_update(hipStream_t s, int n, const int32_t *row_lat, const double *p, const double *q, double *x,
-                      double *r, double *part, CGState *st, int max_iter) {
+                      double *r, const double *c, double *zs, double *part, CGState *st, int max_iter) {
   const int g = reduction_blocks(n);
-  k_cg_update<<<g, kRedThreads, 0, s>>>(n, row_lat, p, q, x, r, part, st);
+  k_cg_update<<<g, kRedThreads, 0, s>>>(n, row_lat, p, q, x, r, c, zs, part, st);
   k_cg_update_fin<<<1, kFinThreads, 0, s>>>(g, part, st, max_iter);
 }
 
-void launch_cg_true_residual(hipStream_t s, int n, int K, const Offsets &off, const int32_t *row_lat,
-                             const double *val, const double *x, const double *b, double *tmp, double *part,
-                             CGState *st) {
-  (void)tmp;
+void launch_cg_true_residual(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
+                             const uint32_t *meta, const double *x, const double *b, double *part, CGState *st) {
   const int g = reduction_blocks(n);
-  IMSMG_DISPATCH_K(K, k_cg_true_residual, n, K, off, row_lat, val, x, b, part);
+  IMSMG_DISPATCH_K(K, k_cg_true_residual, n, K, op, row_lat, meta, x, b, part);
   k_cg_aux_fin<<<1, kFinThreads, 0, s>>>(g, part, st);
 }
 

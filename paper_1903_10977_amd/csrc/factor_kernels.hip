@@ -286,6 +286,22 @@ void launch_count_nk(hipStream_t s, int nel, const int32_t *eptr, const int32_t 
   if (nel > 0) k_count_nk<<<(nel + 127) / 128, 128, 0, s>>>(nel, eptr, eidx, fptr, fblk, nk, overflow);
 }
 
+// inv_j *= w_j (the damping weight is folded into the stored inverse)
+__global__ void k_scale_blocks(int nblocks, const int64_t *__restrict__ off, const int32_t *__restrict__ size,
+                               const double *__restrict__ w, double *__restrict__ inv) {
+  const int j = blockIdx.x;
+  if (j >= nblocks) return;
+  const int m = size[j];
+  double *p = inv + off[j];
+  const double wj = w[j];
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) p[e] *= wj;
+}
+
+void launch_scale_blocks(hipStream_t s, int nblocks, const int64_t *off, const int32_t *size, const double *w,
+                         double *inv) {
+  if (nblocks > 0) k_scale_blocks<<<nblocks, 64, 0, s>>>(nblocks, off, size, w, inv);
+}
+
 // c_i = w_j / A_ii for rows whose only block is their own singleton
 __global__ void k_diag_coef(int n, int center, const int32_t *__restrict__ trivial_block,
                             const double *__restrict__ val, const double *__restrict__ bw, double *__restrict__ c) {

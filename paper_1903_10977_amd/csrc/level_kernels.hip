@@ -1,93 +1,190 @@
-// Per-level kernels of the V-cycle (Algorithm alg:MGV): lattice-ELL residual,
-// additive Schwarz smoother (two phases), restriction / prolongation, dense
-// coarsest solve, compact <-> lattice scatter and gather.
+// Per-level kernels of the V-cycle (Algorithm alg:MGV).
 //
-// All row kernels map one thread to one active row; consecutive threads
-// handle consecutive active rows, whose lattice positions are increasing, so
-// the slot-major value streams are fully coalesced and the stencil gathers of
-// the input vector hit the same cache lines across a wavefront.  Workgroups
-// are renumbered so that each of the 8 XCDs walks one contiguous chunk of rows
-// and keeps the neighbouring lattice lines of the input vector in its own L2.
+// Operator storage ("compressed lattice-ELL"): on a uniform tensor grid every
+// row whose support lies inside the physical domain carries the same stencil.
+// Such rows read their K values from a reference stencil passed as a kernel
+// argument; the other rows (cut region, box boundary) keep their own values,
+// slot-major over the compressed rows (val[s * nv + g]) so that consecutive
+// rows still read consecutive addresses.  Per row one 32-bit word `meta`
+// holds the compressed-value index (or kUniform) and the flag "row belongs to
+// a general Schwarz block".
+//
+// Additive Schwarz (smoothers subsection) is split by rows:
+//   * trivial rows (their only block is their own singleton):
+//       x_i += c_i (r - A x)_i,  c_i = omega_j / A_ii, fused into the residual
+//       kernel (ping-pong x buffers, because neighbours read the old x);
+//   * general rows: x_i += sum over the blocks j holding i of row a_ij of
+//       (omega_j A_j^{-1}) times the block's residual, one thread per row, no
+//       atomics and a fixed summation order (deterministic).
+//
+// All row kernels map one thread to one active row; workgroups are renumbered
+// so that each of the 8 XCDs walks one contiguous chunk of rows and keeps the
+// neighbouring lattice lines of the input vector in its own L2.
 #include "imsmg_internal.h"
+#include "op_row.h"
 
 namespace imsmg {
 
 constexpr int kRowBlock = 256;
 
 __device__ __forceinline__ int xcd_block(int b, int nb) {
-  // hardware dispatches workgroup b to XCD (b % 8); give XCD k the
-  // contiguous range [k * ceil(nb/8), ...) of logical blocks
+  // hardware dispatches workgroup b to XCD (b % 8); give XCD k a contiguous
+  // range of logical blocks (a bijection of [0, nb))
   const int per = (nb + 7) / 8;
   const int xcd = b % 8;
   const int k = b / 8;
-  const int full = nb % 8 == 0 ? 8 : nb % 8;  // XCDs that receive `per` blocks
-  // blocks b with xcd < full get index xcd*per + k; others are shifted
+  const int full = nb % 8 == 0 ? 8 : nb % 8;
   if (xcd < full) return xcd * per + k;
   return full * per + (xcd - full) * (per - 1) + k;
 }
 
 static inline int grid_for(int n) { return (n + kRowBlock - 1) / kRowBlock; }
 
+// y = b - A x   (b == nullptr: y = A x)
 template <int K, typename V>
-__global__ __launch_bounds__(kRowBlock) void k_ell_residual(int n, Offsets off, const int32_t *__restrict__ row_lat,
-                                                             const V *__restrict__ val, const double *__restrict__ x,
-                                                             const double *__restrict__ b, double *__restrict__ y,
-                                                             const int32_t *__restrict__ done) {
+__global__ __launch_bounds__(kRowBlock) void k_residual(int n, int Kdyn, OpView<V> op, const int32_t *__restrict__ row_lat,
+                                                        const uint32_t *__restrict__ meta,
+                                                        const double *__restrict__ x, const double *__restrict__ b,
+                                                        double *__restrict__ y, const int32_t *__restrict__ done) {
   if (*done) return;
   const int i = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
   if (i >= n) return;
   const int L = row_lat[i];
-  double acc = 0.0;
-#pragma unroll
-  for (int s = 0; s < K; ++s) acc += double(val[size_t(s) * n + i]) * x[L + off.off[s]];
-  y[L] = b ? b[L] - acc : acc;
+  const unsigned m = meta[i];
+  const double ax = op_row<K, V>(m, op, x, L, Kdyn);
+  y[L] = b ? b[L] - ax : ax;
 }
 
-template <typename V>
-__global__ __launch_bounds__(kRowBlock) void k_ell_residual_any(int n, int K, Offsets off,
-                                                                 const int32_t *__restrict__ row_lat,
-                                                                 const V *__restrict__ val,
-                                                                 const double *__restrict__ x,
-                                                                 const double *__restrict__ b, double *__restrict__ y,
-                                                                 const int32_t *__restrict__ done) {
+// smoothing step, trivial rows:  rh = r - A xa  (stored for general rows only),
+// xb = xa + c * rh   (c = 0 on general rows, which the general kernel completes)
+template <int K, typename V>
+__global__ __launch_bounds__(kRowBlock) void k_residual_smooth(int n, int Kdyn, OpView<V> op,
+                                                               const int32_t *__restrict__ row_lat,
+                                                               const uint32_t *__restrict__ meta,
+                                                               const double *__restrict__ c,
+                                                               const double *__restrict__ xa,
+                                                               const double *__restrict__ r, double *__restrict__ rh,
+                                                               double *__restrict__ xb,
+                                                               const int32_t *__restrict__ done) {
   if (*done) return;
   const int i = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
   if (i >= n) return;
   const int L = row_lat[i];
-  double acc = 0.0;
-  for (int s = 0; s < K; ++s) acc += double(val[size_t(s) * n + i]) * x[L + off.off[s]];
-  y[L] = b ? b[L] - acc : acc;
+  const unsigned m = meta[i];
+  const double ax = op_row<K, V>(m, op, xa, L, Kdyn);
+  const double res = r[L] - ax;
+  if (m & kMetaGeneral) rh[L] = res;
+  xb[L] = xa[L] + c[i] * res;
 }
 
 template <typename V>
-static void ell_residual(hipStream_t s, int n, int K, const Offsets &off, const int32_t *row_lat, const V *val,
-                         const double *x, const double *b, double *y, const int32_t *done) {
+static void dispatch_residual(hipStream_t s, int n, int K, const OpView<V> &op, const int32_t *row_lat,
+                              const uint32_t *meta, const double *x, const double *b, double *y, const int32_t *done) {
   if (n <= 0) return;
   dim3 g(grid_for(n)), t(kRowBlock);
   switch (K) {
-    case 9: k_ell_residual<9, V><<<g, t, 0, s>>>(n, off, row_lat, val, x, b, y, done); break;
-    case 25: k_ell_residual<25, V><<<g, t, 0, s>>>(n, off, row_lat, val, x, b, y, done); break;
-    case 49: k_ell_residual<49, V><<<g, t, 0, s>>>(n, off, row_lat, val, x, b, y, done); break;
-    case 27: k_ell_residual<27, V><<<g, t, 0, s>>>(n, off, row_lat, val, x, b, y, done); break;
-    case 125: k_ell_residual<125, V><<<g, t, 0, s>>>(n, off, row_lat, val, x, b, y, done); break;
-    default: k_ell_residual_any<V><<<g, t, 0, s>>>(n, K, off, row_lat, val, x, b, y, done); break;
+    case 9: k_residual<9, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done); break;
+    case 25: k_residual<25, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done); break;
+    case 49: k_residual<49, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done); break;
+    case 27: k_residual<27, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done); break;
+    case 125: k_residual<125, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done); break;
+    default: k_residual<0, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done); break;
   }
 }
 
-void launch_ell_residual(hipStream_t s, int n, int K, const Offsets &off, const int32_t *row_lat, const double *val,
-                         const double *x, const double *b, double *y, const int32_t *done) {
-  ell_residual<double>(s, n, K, off, row_lat, val, x, b, y, done);
-}
-void launch_ell_residual_f32(hipStream_t s, int n, int K, const Offsets &off, const int32_t *row_lat,
-                             const float *val, const double *x, const double *b, double *y, const int32_t *done) {
-  ell_residual<float>(s, n, K, off, row_lat, val, x, b, y, done);
+template <typename V>
+static void dispatch_residual_smooth(hipStream_t s, int n, int K, const OpView<V> &op, const int32_t *row_lat,
+                                     const uint32_t *meta, const double *c, const double *xa, const double *r,
+                                     double *rh, double *xb, const int32_t *done) {
+  if (n <= 0) return;
+  dim3 g(grid_for(n)), t(kRowBlock);
+  switch (K) {
+    case 9: k_residual_smooth<9, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done); break;
+    case 25: k_residual_smooth<25, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done); break;
+    case 49: k_residual_smooth<49, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done); break;
+    case 27: k_residual_smooth<27, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done); break;
+    case 125: k_residual_smooth<125, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done); break;
+    default: k_residual_smooth<0, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done); break;
+  }
 }
 
-// y[lat_row[i]] (+)= sum_s v[s n + i] x[col[s n + i]]   (restriction / prolongation)
+void launch_residual(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
+                     const uint32_t *meta, const double *x, const double *b, double *y, const int32_t *done) {
+  dispatch_residual<double>(s, n, K, op, row_lat, meta, x, b, y, done);
+}
+void launch_residual(hipStream_t s, int n, int K, const OpView<float> &op, const int32_t *row_lat,
+                     const uint32_t *meta, const double *x, const double *b, double *y, const int32_t *done) {
+  dispatch_residual<float>(s, n, K, op, row_lat, meta, x, b, y, done);
+}
+void launch_residual_smooth(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
+                            const uint32_t *meta, const double *c, const double *xa, const double *r, double *rh,
+                            double *xb, const int32_t *done) {
+  dispatch_residual_smooth<double>(s, n, K, op, row_lat, meta, c, xa, r, rh, xb, done);
+}
+void launch_residual_smooth(hipStream_t s, int n, int K, const OpView<float> &op, const int32_t *row_lat,
+                            const uint32_t *meta, const double *c, const double *xa, const double *r, double *rh,
+                            double *xb, const int32_t *done) {
+  dispatch_residual_smooth<float>(s, n, K, op, row_lat, meta, c, xa, r, rh, xb, done);
+}
+
+// General Schwarz rows: x[L_i] += sum_e sum_b W_e[b] r[blat[m_e + b]], where
+// W_e is row a of omega_j A_j^{-1} (symmetric, stored contiguously).
+__global__ __launch_bounds__(kRowBlock) void k_smooth_general(int ng, const int32_t *__restrict__ grow_lat,
+                                                              const int32_t *__restrict__ gptr,
+                                                              const int64_t *__restrict__ ent_off,
+                                                              const int32_t *__restrict__ ent_mem,
+                                                              const int32_t *__restrict__ ent_n,
+                                                              const int32_t *__restrict__ blat,
+                                                              const double *__restrict__ winv,
+                                                              const double *__restrict__ r, double *__restrict__ x,
+                                                              const int32_t *__restrict__ done) {
+  if (*done) return;
+  const int t = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
+  if (t >= ng) return;
+  double acc = 0.0;
+  for (int e = gptr[t]; e < gptr[t + 1]; ++e) {
+    const double *w = winv + ent_off[e];
+    const int32_t *mem = blat + ent_mem[e];
+    const int nj = ent_n[e];
+#pragma unroll 4
+    for (int b = 0; b < nj; ++b) acc += w[b] * r[mem[b]];
+  }
+  const int L = grow_lat[t];
+  x[L] += acc;
+}
+
+void launch_smooth_general(hipStream_t s, int ng, const int32_t *grow_lat, const int32_t *gptr,
+                           const int64_t *ent_off, const int32_t *ent_mem, const int32_t *ent_n, const int32_t *blat,
+                           const double *winv, const double *r, double *x, const int32_t *done) {
+  if (ng <= 0) return;
+  k_smooth_general<<<grid_for(ng), kRowBlock, 0, s>>>(ng, grow_lat, gptr, ent_off, ent_mem, ent_n, blat, winv, r, x,
+                                                      done);
+}
+
+// x[L_i] = c_i r[L_i]  (trivial part of the first smoothing step from x = 0)
+__global__ __launch_bounds__(kRowBlock) void k_diag_scale(int n, const int32_t *__restrict__ row_lat,
+                                                          const double *__restrict__ c, const double *__restrict__ r,
+                                                          double *__restrict__ x, const int32_t *__restrict__ done) {
+  if (*done) return;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
+  if (i >= n) return;
+  const int L = row_lat[i];
+  x[L] = c[i] * r[L];
+}
+
+void launch_diag_scale(hipStream_t s, int n, const int32_t *row_lat, const double *c, const double *r, double *x,
+                       const int32_t *done) {
+  if (n > 0) k_diag_scale<<<grid_for(n), kRowBlock, 0, s>>>(n, row_lat, c, r, x, done);
+}
+
+// ELL gather (transfer through stored CSR): y[lat_row[i]] (+)= sum_s v[s n + i] x[col[s n + i]];
+// optionally also xinit[lat] = cinit[i] * result (first smoothing step of the level)
 __global__ __launch_bounds__(kRowBlock) void k_ell_gather(int n, int w, const int32_t *__restrict__ row_lat,
                                                           const int32_t *__restrict__ col,
                                                           const double *__restrict__ v, const double *__restrict__ x,
                                                           double *__restrict__ y, int accumulate,
+                                                          const double *__restrict__ cinit,
+                                                          double *__restrict__ xinit,
                                                           const int32_t *__restrict__ done) {
   if (*done) return;
   const int i = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
@@ -96,19 +193,22 @@ __global__ __launch_bounds__(kRowBlock) void k_ell_gather(int n, int w, const in
 #pragma unroll 8
   for (int s = 0; s < w; ++s) acc += v[size_t(s) * n + i] * x[col[size_t(s) * n + i]];
   const int L = row_lat[i];
-  y[L] = accumulate ? y[L] + acc : acc;
+  const double out = accumulate ? y[L] + acc : acc;
+  y[L] = out;
+  if (xinit) xinit[L] = cinit[i] * out;
 }
 
 void launch_ell_gather(hipStream_t s, int n, int w, const int32_t *row_lat, const int32_t *col, const double *v,
-                       const double *x, double *y, int accumulate, const int32_t *done) {
+                       const double *x, double *y, int accumulate, const double *cinit, double *xinit,
+                       const int32_t *done) {
   if (n <= 0) return;
-  k_ell_gather<<<grid_for(n), kRowBlock, 0, s>>>(n, w, row_lat, col, v, x, y, accumulate, done);
+  k_ell_gather<<<grid_for(n), kRowBlock, 0, s>>>(n, w, row_lat, col, v, x, y, accumulate, cinit, xinit, done);
 }
 
 // Index-free transfers R_l = tensor product of one 1D two-scale matrix
 // (eq:coarsening on the tensor grid), restricted to active functions.  The
 // vectors are zero at inactive lattice points, so the full tensor stencil can
-// be applied without a mask.  tab: per 1D index, start of the band in the
+// be applied without a mask.  Band: per 1D index, start of the band in the
 // other level's 1D numbering, band length, and the band coefficients
 // (stride W).
 struct Band {
@@ -123,6 +223,8 @@ __global__ __launch_bounds__(kRowBlock) void k_tensor_transfer(int n, const int3
                                                                int ox, int oy, Band band, int ix_, int iy_,
                                                                const double *__restrict__ xin,
                                                                double *__restrict__ y, int accumulate,
+                                                               const double *__restrict__ cinit,
+                                                               double *__restrict__ xinit,
                                                                const int32_t *__restrict__ done) {
   // rows: this level (lattice ox x oy x .), inputs: other level (lattice ix_ x iy_ x .)
   if (*done) return;
@@ -158,77 +260,27 @@ __global__ __launch_bounds__(kRowBlock) void k_tensor_transfer(int n, const int3
       acc += cz[c] * tz;
     }
   }
-  y[L] = accumulate ? y[L] + acc : acc;
+  const double out = accumulate ? y[L] + acc : acc;
+  y[L] = out;
+  if (xinit) xinit[L] = cinit[i] * out;
 }
 
 void launch_tensor_transfer(hipStream_t s, int dim, int n, const int32_t *row_lat, int ox, int oy,
                             const int32_t *start, const int32_t *len, const double *coef, int W, int ix, int iy,
-                            const double *xin, double *y, int accumulate, const int32_t *done) {
+                            const double *xin, double *y, int accumulate, const double *cinit, double *xinit,
+                            const int32_t *done) {
   if (n <= 0) return;
   Band b{start, len, coef, W};
   if (dim == 2)
-    k_tensor_transfer<2><<<grid_for(n), kRowBlock, 0, s>>>(n, row_lat, ox, oy, b, ix, iy, xin, y, accumulate, done);
+    k_tensor_transfer<2><<<grid_for(n), kRowBlock, 0, s>>>(n, row_lat, ox, oy, b, ix, iy, xin, y, accumulate, cinit,
+                                                           xinit, done);
   else
-    k_tensor_transfer<3><<<grid_for(n), kRowBlock, 0, s>>>(n, row_lat, ox, oy, b, ix, iy, xin, y, accumulate, done);
-}
-
-// Schwarz phase 1: one thread per block row.  The inverse is stored column
-// major per block, so the threads of one block read consecutive addresses.
-__global__ __launch_bounds__(kRowBlock) void k_schwarz_blocks(
-    int ntask, const int32_t *__restrict__ task_block, const int32_t *__restrict__ bstart,
-    const int32_t *__restrict__ bsize, const int64_t *__restrict__ binv_off, const int32_t *__restrict__ blat,
-    const double *__restrict__ binv, const double *__restrict__ bw, const double *__restrict__ r,
-    double *__restrict__ y, const int32_t *__restrict__ done) {
-  if (*done) return;
-  const int t = blockIdx.x * kRowBlock + threadIdx.x;
-  if (t >= ntask) return;
-  const int j = task_block[t];
-  const int st = bstart[j];
-  const int nj = bsize[j];
-  const int a = t - st;
-  const double *inv = binv + binv_off[j];
-  double acc = 0.0;
-#pragma unroll 4
-  for (int b = 0; b < nj; ++b) acc += inv[a + size_t(nj) * b] * r[blat[st + b]];
-  y[t] = bw[j] * acc;
-}
-
-void launch_schwarz_blocks(hipStream_t s, int ntask, const int32_t *task_block, const int32_t *bstart,
-                           const int32_t *bsize, const int64_t *binv_off, const int32_t *blat, const double *binv,
-                           const double *bw, const double *r, double *y, const int32_t *done) {
-  if (ntask <= 0) return;
-  k_schwarz_blocks<<<grid_for(ntask), kRowBlock, 0, s>>>(ntask, task_block, bstart, bsize, binv_off, blat, binv,
-                                                         bw, r, y, done);
-}
-
-// Schwarz phase 2: deterministic gather of the block contributions per row.
-__global__ __launch_bounds__(kRowBlock) void k_schwarz_gather(int n, const int32_t *__restrict__ row_lat,
-                                                              const double *__restrict__ c,
-                                                              const int32_t *__restrict__ gptr,
-                                                              const int32_t *__restrict__ gidx,
-                                                              const double *__restrict__ y,
-                                                              const double *__restrict__ r, double *__restrict__ x,
-                                                              int accumulate, const int32_t *__restrict__ done) {
-  if (*done) return;
-  const int i = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
-  if (i >= n) return;
-  const int L = row_lat[i];
-  double v = c[i] * r[L];
-  const int g0 = gptr[i], g1 = gptr[i + 1];
-  for (int g = g0; g < g1; ++g) v += y[gidx[g]];
-  x[L] = accumulate ? x[L] + v : v;
-}
-
-void launch_schwarz_gather(hipStream_t s, int n, const int32_t *row_lat, const double *c, const int32_t *gptr,
-                           const int32_t *gidx, const double *y, const double *r, double *x, int accumulate,
-                           const int32_t *done) {
-  if (n <= 0) return;
-  k_schwarz_gather<<<grid_for(n), kRowBlock, 0, s>>>(n, row_lat, c, gptr, gidx, y, r, x, accumulate, done);
+    k_tensor_transfer<3><<<grid_for(n), kRowBlock, 0, s>>>(n, row_lat, ox, oy, b, ix, iy, xin, y, accumulate, cinit,
+                                                           xinit, done);
 }
 
 // Dense coarsest solve: r gathered into LDS, one wavefront per output row.
 constexpr int kGemvThreads = 256;
-constexpr int kGemvMaxN = 8192;
 __global__ __launch_bounds__(kGemvThreads) void k_dense_gemv(int n, const int32_t *__restrict__ row_lat,
                                                              const double *__restrict__ Ainv,
                                                              const double *__restrict__ r, double *__restrict__ x,
@@ -266,19 +318,12 @@ __global__ void k_gather(int n, const int32_t *__restrict__ row_lat, const doubl
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[row_lat[i]];
 }
-__global__ void k_fill(size_t n, double v, double *__restrict__ dst) {
-  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = v;
-}
 
 void launch_scatter(hipStream_t s, int n, const int32_t *row_lat, const double *src, double *dst) {
   if (n > 0) k_scatter<<<grid_for(n), kRowBlock, 0, s>>>(n, row_lat, src, dst);
 }
 void launch_gather(hipStream_t s, int n, const int32_t *row_lat, const double *src, double *dst) {
   if (n > 0) k_gather<<<grid_for(n), kRowBlock, 0, s>>>(n, row_lat, src, dst);
-}
-void launch_fill(hipStream_t s, size_t n, double v, double *dst) {
-  if (n > 0) k_fill<<<dim3(unsigned((n + kRowBlock - 1) / kRowBlock)), kRowBlock, 0, s>>>(n, v, dst);
 }
 
 }  // namespace imsmg
