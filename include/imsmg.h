@@ -161,8 +161,22 @@ int imsmg_apply_restriction(imsmg_ctx *ctx, int level, const double *rf, double 
 int imsmg_apply_prolongation(imsmg_ctx *ctx, int level, const double *xc, double *xf); /* xf += R_l^T xc */
 int imsmg_coarse_solve(imsmg_ctx *ctx, const double *r, double *x);               /* x = A_0^{-1} r */
 
+/* Storage statistics of level l (after imsmg_factor_patches). */
+typedef struct {
+  int32_t n;             /* active rows */
+  int32_t stencil;       /* K = (2 reach + 1)^dim slots per row */
+  int32_t stored_rows;   /* rows keeping their own values; the others read the uniform stencil */
+  int32_t general_rows;  /* rows in general (non-singleton or shared) Schwarz blocks */
+  int64_t sg_nnz;        /* entries of the assembled general smoother on those rows */
+  int64_t lattice;       /* padded lattice size of the level's vectors */
+  int32_t value_bytes;   /* 8 (FP64) or 4 (FP32 V-cycle operators) */
+  int32_t reserved;
+} imsmg_level_stats;
+int imsmg_get_level_stats(imsmg_ctx *ctx, int level, imsmg_level_stats *stats);
+
 /* Accumulated time of the finest-level residual kernel since the last reset
- * (requires opt.timing): total milliseconds and number of launches. */
+ * (requires opt.timing; the timed kernel is the finest level's fused residual +
+ * trivial-row smoothing step): total milliseconds and number of launches. */
 int imsmg_kernel_time(imsmg_ctx *ctx, double *total_ms, int64_t *launches, int reset);
 
 const char *imsmg_last_error(imsmg_ctx *ctx);

@@ -88,9 +88,9 @@ struct Level {
   std::vector<int32_t> f_ptr, f_idx;  // post-removal blocks (incl. added singletons)
   double *c = nullptr;               // trivial rows: omega_j / A_ii, else 0
   int ng = 0;                         // rows in general blocks
-  int32_t *grow_lat = nullptr, *gptr = nullptr, *ent_mem = nullptr, *ent_n = nullptr, *blat = nullptr;
-  int64_t *ent_off = nullptr;
-  double *winv = nullptr;             // omega_j A_j^{-1} of the general blocks (symmetric)
+  bool small = false;                 // latency-bound level (no convergence-flag load)
+  int32_t *grow_lat = nullptr, *sptr = nullptr, *scol = nullptr;
+  double *sval = nullptr;             // S_G = sum_j omega_j P_j A_j^{-1} P_j^T on the general rows (CSR)
   double gamma = 0.0;
   // elements (host)
   std::vector<int32_t> e_ptr, e_idx;
@@ -235,7 +235,7 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
   // slots non-zero (rows hashed after rounding to 12 significant digits)
   std::vector<double> ref(L.K, 0.0);
   bool have_ref = false;
-  if (c->opt.compress && L.K <= IMSMG_MAX_REF) {
+  if (c->opt.compress) {
     std::vector<std::pair<uint64_t, int>> keys;
     keys.reserve(L.n);
     for (int i = 0; i < L.n; ++i) {
@@ -296,9 +296,15 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
   L.op64.nv = nv;
   L.op32.off = L.off;
   L.op32.nv = nv;
-  for (int sl = 0; sl < L.K && sl < IMSMG_MAX_REF; ++sl) {
-    L.op64.ref.v[sl] = ref[sl];
-    L.op32.ref.v[sl] = float(ref[sl]);
+  {
+    std::vector<float> ref32(ref.begin(), ref.end());
+    double *r64 = dalloc<double>(c->owned, L.K);
+    float *r32 = dalloc<float>(c->owned, L.K);
+    h2d(s, r64, ref.data(), L.K);
+    h2d(s, r32, ref32.data(), L.K);
+    L.op64.ref = r64;
+    L.op32.ref = r32;
+    HIP_CHECK_RET(hipStreamSynchronize(s));
   }
   if (c->opt.precision == IMSMG_MIXED) {
     std::vector<float> c32(cv.begin(), cv.end());
@@ -482,6 +488,13 @@ hipEvent_t *timed_pair(imsmg_ctx *c) {
 
 bool mixed(imsmg_ctx *c) { return c->opt.precision == IMSMG_MIXED; }
 
+// Levels below this many rows are launch-latency bound: their kernels skip
+// the convergence-flag load, which would add one dependent memory round trip
+// to every launch (the wasted work after convergence is negligible there).
+constexpr int kSmallLevel = 65536;
+
+const int32_t *flag_for(const Level &L, const int32_t *done) { return L.n >= kSmallLevel ? done : nullptr; }
+
 // y = b - A_l x (b == nullptr: y = A_l x); the V-cycle operator precision
 void residual(imsmg_ctx *c, Level &L, const double *x, const double *b, double *y, const int32_t *done,
               bool timed) {
@@ -504,8 +517,7 @@ void smooth_step(imsmg_ctx *c, Level &L, const double *xa, double *xb, const int
   else
     launch_residual_smooth(c->stream, L.n, L.K, L.op64, L.row_lat, L.meta, L.c, xa, L.r, L.rh, xb, done);
   if (ev) HIP_CHECK_RET(hipEventRecord(ev[1], c->stream));
-  launch_smooth_general(c->stream, L.ng, L.grow_lat, L.gptr, L.ent_off, L.ent_mem, L.ent_n, L.blat, L.winv, L.rh, xb,
-                        done);
+  launch_smooth_general(c->stream, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, L.rh, xb, done);
 }
 
 // rc = R_l rf (fine level L, coarse level Cl; padded vectors)
@@ -533,25 +545,25 @@ void prolong_add(imsmg_ctx *c, Level &L, Level &Cl, const double *xc, double *xf
 // V-cycle on level l (Algorithm alg:MGV): input residual in lv[l].r; on entry
 // lv[l].xs already holds c * r (trivial part of the first smoothing step,
 // written by the caller's fused kernel); the correction is left in lv[l].x.
-void vcycle_level(imsmg_ctx *c, int l, const int32_t *done, bool timing) {
+void vcycle_level(imsmg_ctx *c, int l, const int32_t *done_top, bool timing) {
   Level &L = c->lv[l];
+  const int32_t *done = flag_for(L, done_top);
   if (l == 0) {
     launch_dense_gemv(c->stream, L.n, L.row_lat, L.Ainv, L.r, L.x, done);
     return;
   }
   Level &Cl = c->lv[l - 1];
   const bool fine = (l == int(c->lv.size()) - 1) && timing;
-  // first smoothing step from x = 0: x = S r
-  launch_smooth_general(c->stream, L.ng, L.grow_lat, L.gptr, L.ent_off, L.ent_mem, L.ent_n, L.blat, L.winv, L.r, L.xs,
-                        done);
+  // first smoothing step from x = 0: x = S r (general rows)
+  launch_smooth_general(c->stream, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, L.r, L.xs, done);
   double *xa = L.xs, *xb = (L.xs == L.x) ? L.x2 : L.x;
   for (int k = 1; k < c->opt.nu_pre; ++k) {
     smooth_step(c, L, xa, xb, done, fine);
     std::swap(xa, xb);
   }
-  residual(c, L, xa, L.r, L.rh, done, fine);
-  restrict_to(c, L, Cl, L.rh, Cl.r, l - 1 > 0 ? Cl.xs : nullptr, done);
-  vcycle_level(c, l - 1, done, timing);
+  residual(c, L, xa, L.r, L.rh, done, false);
+  restrict_to(c, L, Cl, L.rh, Cl.r, l - 1 > 0 ? Cl.xs : nullptr, flag_for(Cl, done_top));
+  vcycle_level(c, l - 1, done_top, timing);
   prolong_add(c, L, Cl, Cl.x, xa, done);
   for (int k = 0; k < c->opt.nu_post; ++k) {
     smooth_step(c, L, xa, xb, done, fine);
@@ -783,15 +795,8 @@ void factor_level(imsmg_ctx *c, int l) {
     HIP_CHECK_RET(hipGetLastError());
     HIP_CHECK_RET(hipStreamSynchronize(s));
   }
-  L.winv = inv;
-  // member lattice lists of the general blocks, and per general row its
-  // entries (row a of block j): inverse row offset, member list, size
-  std::vector<int32_t> mem_start(nbg), blat;
-  for (int q = 0; q < nbg; ++q) {
-    const int j = g_blocks[q];
-    mem_start[q] = int32_t(blat.size());
-    for (int k = fptr[j]; k < fptr[j + 1]; ++k) blat.push_back(L.h_row_lat[fidx[k]]);
-  }
+  // per general row its entries (row a of block j): inverse row offset and
+  // block size; the CSR pattern of S_G is the union of the row's block members
   std::vector<int32_t> cnt(n, 0);
   for (int q = 0; q < nbg; ++q) {
     const int j = g_blocks[q];
@@ -806,7 +811,7 @@ void factor_level(imsmg_ctx *c, int l) {
     }
   const int ngr = int(grows.size());
   std::vector<int64_t> e_off(gp.back());
-  std::vector<int32_t> e_mem(gp.back()), e_n(gp.back()), fillp(gp.begin(), gp.end() - 1);
+  std::vector<int32_t> e_n(gp.back()), e_blk(gp.back()), fillp(gp.begin(), gp.end() - 1);
   for (int q = 0; q < nbg; ++q) {  // ascending block order: deterministic summation
     const int j = g_blocks[q];
     const int sz = fptr[j + 1] - fptr[j];
@@ -814,8 +819,34 @@ void factor_level(imsmg_ctx *c, int l) {
       const int i = fidx[fptr[j] + a];
       const int e = fillp[row_slot[i]]++;
       e_off[e] = g_invoff[q] + int64_t(a) * sz;  // row a (= column a) of the symmetric inverse
-      e_mem[e] = mem_start[q];
       e_n[e] = sz;
+      e_blk[e] = j;
+    }
+  }
+  std::vector<int32_t> sp(1, 0), scol;
+  std::vector<int64_t> e_pos(gp.back());
+  std::vector<int32_t> epos;
+  {
+    std::vector<int32_t> members;
+    for (int t = 0; t < ngr; ++t) {
+      members.clear();
+      for (int e = gp[t]; e < gp[t + 1]; ++e) {
+        const int j = e_blk[e];
+        for (int k = fptr[j]; k < fptr[j + 1]; ++k) members.push_back(fidx[k]);
+      }
+      std::sort(members.begin(), members.end());
+      members.erase(std::unique(members.begin(), members.end()), members.end());
+      const int base = int(scol.size());
+      for (int m : members) scol.push_back(L.h_row_lat[m]);
+      sp.push_back(int32_t(scol.size()));
+      for (int e = gp[t]; e < gp[t + 1]; ++e) {
+        const int j = e_blk[e];
+        e_pos[e] = int64_t(epos.size());
+        for (int k = fptr[j]; k < fptr[j + 1]; ++k) {
+          const int pos = int(std::lower_bound(members.begin(), members.end(), fidx[k]) - members.begin());
+          epos.push_back(base + pos);
+        }
+      }
     }
   }
   std::vector<int32_t> grow_lat(ngr);
@@ -824,19 +855,30 @@ void factor_level(imsmg_ctx *c, int l) {
     L.h_meta[grows[t]] |= kMetaGeneral;
   }
   L.ng = ngr;
+  L.small = L.n < kSmallLevel;
   L.grow_lat = dalloc<int32_t>(c->factor_owned, std::max(ngr, 1));
-  L.gptr = dalloc<int32_t>(c->factor_owned, gp.size());
-  L.ent_off = dalloc<int64_t>(c->factor_owned, std::max<size_t>(e_off.size(), 1));
-  L.ent_mem = dalloc<int32_t>(c->factor_owned, std::max<size_t>(e_mem.size(), 1));
-  L.ent_n = dalloc<int32_t>(c->factor_owned, std::max<size_t>(e_n.size(), 1));
-  L.blat = dalloc<int32_t>(c->factor_owned, std::max<size_t>(blat.size(), 1));
+  L.sptr = dalloc<int32_t>(c->factor_owned, sp.size());
+  L.scol = dalloc<int32_t>(c->factor_owned, std::max<size_t>(scol.size(), 1));
+  L.sval = dalloc<double>(c->factor_owned, std::max<size_t>(scol.size(), 1));
   h2d(s, L.grow_lat, grow_lat.data(), grow_lat.size());
-  h2d(s, L.gptr, gp.data(), gp.size());
-  h2d(s, L.ent_off, e_off.data(), e_off.size());
-  h2d(s, L.ent_mem, e_mem.data(), e_mem.size());
-  h2d(s, L.ent_n, e_n.data(), e_n.size());
-  h2d(s, L.blat, blat.data(), blat.size());
+  h2d(s, L.sptr, sp.data(), sp.size());
+  h2d(s, L.scol, scol.data(), scol.size());
   h2d(s, L.meta, L.h_meta.data(), L.h_meta.size());
+  HIP_CHECK_RET(hipMemsetAsync(L.sval, 0, std::max<size_t>(scol.size(), 1) * sizeof(double), s));
+  {
+    int32_t *d_gp = dalloc<int32_t>(tmp, gp.size()), *d_en = dalloc<int32_t>(tmp, std::max<size_t>(e_n.size(), 1));
+    int32_t *d_epos = dalloc<int32_t>(tmp, std::max<size_t>(epos.size(), 1));
+    int64_t *d_eoff = dalloc<int64_t>(tmp, std::max<size_t>(e_off.size(), 1));
+    int64_t *d_epos0 = dalloc<int64_t>(tmp, std::max<size_t>(e_pos.size(), 1));
+    h2d(s, d_gp, gp.data(), gp.size());
+    h2d(s, d_en, e_n.data(), e_n.size());
+    h2d(s, d_epos, epos.data(), epos.size());
+    h2d(s, d_eoff, e_off.data(), e_off.size());
+    h2d(s, d_epos0, e_pos.data(), e_pos.size());
+    launch_assemble_sg(s, ngr, d_gp, d_eoff, d_en, d_epos0, d_epos, inv, L.sval);
+    HIP_CHECK_RET(hipGetLastError());
+    HIP_CHECK_RET(hipStreamSynchronize(s));
+  }
   // trivial rows: c_i = w_j / A_ii
   std::vector<int32_t> tb(n, -1);
   for (int i = 0; i < n; ++i)
@@ -1176,8 +1218,7 @@ int imsmg_apply_smoother(imsmg_ctx *c, int level, const double *r, double *y) {
     Level &L = c->lv[level];
     launch_scatter(c->stream, L.n, L.row_lat, r, L.rh);
     launch_diag_scale(c->stream, L.n, L.row_lat, L.c, L.rh, L.x, c->zero_flag);
-    launch_smooth_general(c->stream, L.ng, L.grow_lat, L.gptr, L.ent_off, L.ent_mem, L.ent_n, L.blat, L.winv, L.rh,
-                          L.x, c->zero_flag);
+    launch_smooth_general(c->stream, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, L.rh, L.x, c->zero_flag);
     launch_gather(c->stream, L.n, L.row_lat, L.x, y);
     HIP_CHECK_RET(hipGetLastError());
     HIP_CHECK_RET(hipStreamSynchronize(c->stream));
@@ -1224,6 +1265,28 @@ int imsmg_coarse_solve(imsmg_ctx *c, const double *r, double *x) {
     launch_gather(c->stream, L.n, L.row_lat, L.x, x);
     HIP_CHECK_RET(hipGetLastError());
     HIP_CHECK_RET(hipStreamSynchronize(c->stream));
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_get_level_stats(imsmg_ctx *c, int level, imsmg_level_stats *st) {
+  return guarded(c, [&]() -> int {
+    if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    if (level < 0 || level >= int(c->lv.size()) || !st) bad("bad level");
+    const Level &L = c->lv[level];
+    st->n = L.n;
+    st->stencil = L.K;
+    st->stored_rows = L.n - L.n_uniform;
+    st->general_rows = L.ng;
+    st->sg_nnz = 0;
+    if (L.ng > 0) {
+      int32_t last = 0;
+      HIP_CHECK_RET(hipMemcpy(&last, L.sptr + L.ng, sizeof(int32_t), hipMemcpyDeviceToHost));
+      st->sg_nnz = last;
+    }
+    st->lattice = L.lattice;
+    st->value_bytes = mixed(c) ? 4 : 8;
+    st->reserved = 0;
     return IMSMG_OK;
   });
 }

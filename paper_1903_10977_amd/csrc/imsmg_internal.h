@@ -23,7 +23,6 @@
 #include <vector>
 
 #define IMSMG_MAX_SLOTS 125  // (2*2+1)^3: 3D up to reach 2, 2D up to reach 5
-#define IMSMG_MAX_REF 125    // reference stencil capacity (2D p <= 5, 3D p <= 2)
 #define IMSMG_MAX_BLOCK 60   // largest Schwarz block factorized in LDS (2 x 60^2 FP64 < 64 KiB)
 
 namespace imsmg {
@@ -36,16 +35,11 @@ struct Offsets {
 };
 
 template <typename V>
-struct RefStencil {
-  V v[IMSMG_MAX_REF];
-};
-
-template <typename V>
 struct OpView {
   Offsets off;
-  RefStencil<V> ref;
-  const V *val;  // compressed rows, slot-major
-  int nv;        // number of compressed rows
+  const V *ref;  // uniform interior stencil (K values)
+  const V *val;  // stored rows, slot-major
+  int nv;        // number of stored rows
 };
 
 // Scalars of the CG iteration, kept on the device.
@@ -77,9 +71,13 @@ void launch_residual_smooth(hipStream_t s, int n, int K, const OpView<double> &o
 void launch_residual_smooth(hipStream_t s, int n, int K, const OpView<float> &op, const int32_t *row_lat,
                             const uint32_t *meta, const double *c, const double *xa, const double *r, double *rh,
                             double *xb, const int32_t *done);
-void launch_smooth_general(hipStream_t s, int ng, const int32_t *grow_lat, const int32_t *gptr,
-                           const int64_t *ent_off, const int32_t *ent_mem, const int32_t *ent_n, const int32_t *blat,
-                           const double *winv, const double *r, double *x, const int32_t *done);
+// general Schwarz rows: x[grow_lat[t]] += sum_k S[t,k] r[scol[k]]  (S_G in CSR, lattice columns)
+void launch_smooth_general(hipStream_t s, int ng, const int32_t *grow_lat, const int32_t *sptr,
+                           const int32_t *scol, const double *sval, const double *r, double *x, const int32_t *done);
+// S_G = sum_j omega_j P_j A_j^{-1} P_j^T on the general rows, accumulated entry by entry in
+// ascending block order into the CSR pattern (epos: CSR slot of every (entry, member) pair)
+void launch_assemble_sg(hipStream_t s, int ng, const int32_t *gptr, const int64_t *ent_off, const int32_t *ent_n,
+                        const int64_t *ent_pos, const int32_t *epos, const double *winv, double *sval);
 void launch_diag_scale(hipStream_t s, int n, const int32_t *row_lat, const double *c, const double *r, double *x,
                        const int32_t *done);
 void launch_ell_gather(hipStream_t s, int n, int w, const int32_t *row_lat, const int32_t *col, const double *v,

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kRowBlock) void k_residual(int n, int Kdyn, OpView<
                                                         const uint32_t *__restrict__ meta,
                                                         const double *__restrict__ x, const double *__restrict__ b,
                                                         double *__restrict__ y, const int32_t *__restrict__ done) {
-  if (*done) return;
+  if (done && *done) return;
   const int i = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
   if (i >= n) return;
   const int L = row_lat[i];
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kRowBlock) void k_residual_smooth(int n, int Kdyn, 
                                                                const double *__restrict__ r, double *__restrict__ rh,
                                                                double *__restrict__ xb,
                                                                const int32_t *__restrict__ done) {
-  if (*done) return;
+  if (done && *done) return;
   const int i = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
   if (i >= n) return;
   const int L = row_lat[i];
@@ -127,45 +127,58 @@ void launch_residual_smooth(hipStream_t s, int n, int K, const OpView<float> &op
   dispatch_residual_smooth<float>(s, n, K, op, row_lat, meta, c, xa, r, rh, xb, done);
 }
 
-// General Schwarz rows: x[L_i] += sum_e sum_b W_e[b] r[blat[m_e + b]], where
-// W_e is row a of omega_j A_j^{-1} (symmetric, stored contiguously).
+// General Schwarz rows: x[L_t] += sum_k S_G[t,k] r[col_k].  S_G is the sum of
+// omega_j P_j A_j^{-1} P_j^T over the general blocks, restricted to the rows
+// that belong to one, assembled once at factorization; applying it is a CSR
+// product with lattice column positions (deterministic, no atomics).
 __global__ __launch_bounds__(kRowBlock) void k_smooth_general(int ng, const int32_t *__restrict__ grow_lat,
-                                                              const int32_t *__restrict__ gptr,
-                                                              const int64_t *__restrict__ ent_off,
-                                                              const int32_t *__restrict__ ent_mem,
-                                                              const int32_t *__restrict__ ent_n,
-                                                              const int32_t *__restrict__ blat,
-                                                              const double *__restrict__ winv,
+                                                              const int32_t *__restrict__ sptr,
+                                                              const int32_t *__restrict__ scol,
+                                                              const double *__restrict__ sval,
                                                               const double *__restrict__ r, double *__restrict__ x,
                                                               const int32_t *__restrict__ done) {
-  if (*done) return;
+  if (done && *done) return;
   const int t = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
   if (t >= ng) return;
+  const int k0 = sptr[t], k1 = sptr[t + 1];
   double acc = 0.0;
-  for (int e = gptr[t]; e < gptr[t + 1]; ++e) {
-    const double *w = winv + ent_off[e];
-    const int32_t *mem = blat + ent_mem[e];
-    const int nj = ent_n[e];
-#pragma unroll 4
-    for (int b = 0; b < nj; ++b) acc += w[b] * r[mem[b]];
-  }
+#pragma unroll 8
+  for (int k = k0; k < k1; ++k) acc += sval[k] * r[scol[k]];
   const int L = grow_lat[t];
   x[L] += acc;
 }
 
-void launch_smooth_general(hipStream_t s, int ng, const int32_t *grow_lat, const int32_t *gptr,
-                           const int64_t *ent_off, const int32_t *ent_mem, const int32_t *ent_n, const int32_t *blat,
-                           const double *winv, const double *r, double *x, const int32_t *done) {
+void launch_smooth_general(hipStream_t s, int ng, const int32_t *grow_lat, const int32_t *sptr,
+                           const int32_t *scol, const double *sval, const double *r, double *x, const int32_t *done) {
   if (ng <= 0) return;
-  k_smooth_general<<<grid_for(ng), kRowBlock, 0, s>>>(ng, grow_lat, gptr, ent_off, ent_mem, ent_n, blat, winv, r, x,
-                                                      done);
+  k_smooth_general<<<grid_for(ng), kRowBlock, 0, s>>>(ng, grow_lat, sptr, scol, sval, r, x, done);
+}
+
+// one thread per general row: adds row a of every block holding the row into
+// the row's CSR slots, blocks in ascending order (fixed summation order)
+__global__ void k_assemble_sg(int ng, const int32_t *__restrict__ gptr, const int64_t *__restrict__ ent_off,
+                              const int32_t *__restrict__ ent_n, const int64_t *__restrict__ ent_pos,
+                              const int32_t *__restrict__ epos, const double *__restrict__ winv,
+                              double *__restrict__ sval) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ng) return;
+  for (int e = gptr[t]; e < gptr[t + 1]; ++e) {
+    const double *w = winv + ent_off[e];
+    const int32_t *pos = epos + ent_pos[e];
+    for (int b = 0; b < ent_n[e]; ++b) sval[pos[b]] += w[b];
+  }
+}
+
+void launch_assemble_sg(hipStream_t s, int ng, const int32_t *gptr, const int64_t *ent_off, const int32_t *ent_n,
+                        const int64_t *ent_pos, const int32_t *epos, const double *winv, double *sval) {
+  if (ng > 0) k_assemble_sg<<<(ng + 255) / 256, 256, 0, s>>>(ng, gptr, ent_off, ent_n, ent_pos, epos, winv, sval);
 }
 
 // x[L_i] = c_i r[L_i]  (trivial part of the first smoothing step from x = 0)
 __global__ __launch_bounds__(kRowBlock) void k_diag_scale(int n, const int32_t *__restrict__ row_lat,
                                                           const double *__restrict__ c, const double *__restrict__ r,
                                                           double *__restrict__ x, const int32_t *__restrict__ done) {
-  if (*done) return;
+  if (done && *done) return;
   const int i = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
   if (i >= n) return;
   const int L = row_lat[i];
@@ -186,7 +199,7 @@ __global__ __launch_bounds__(kRowBlock) void k_ell_gather(int n, int w, const in
                                                           const double *__restrict__ cinit,
                                                           double *__restrict__ xinit,
                                                           const int32_t *__restrict__ done) {
-  if (*done) return;
+  if (done && *done) return;
   const int i = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
   if (i >= n) return;
   double acc = 0.0;
@@ -227,7 +240,7 @@ __global__ __launch_bounds__(kRowBlock) void k_tensor_transfer(int n, const int3
                                                                double *__restrict__ xinit,
                                                                const int32_t *__restrict__ done) {
   // rows: this level (lattice ox x oy x .), inputs: other level (lattice ix_ x iy_ x .)
-  if (*done) return;
+  if (done && *done) return;
   const int i = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
   if (i >= n) return;
   const int L = row_lat[i];
@@ -285,7 +298,7 @@ __global__ __launch_bounds__(kGemvThreads) void k_dense_gemv(int n, const int32_
                                                              const double *__restrict__ Ainv,
                                                              const double *__restrict__ r, double *__restrict__ x,
                                                              const int32_t *__restrict__ done) {
-  if (*done) return;
+  if (done && *done) return;
   extern __shared__ double rs[];
   for (int j = threadIdx.x; j < n; j += kGemvThreads) rs[j] = r[row_lat[j]];
   __syncthreads();

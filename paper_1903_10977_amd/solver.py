@@ -53,10 +53,15 @@ class Info(C.Structure):
                 ("true_rel_res", C.c_double), ("solve_ms", C.c_double)]
 
 
+class LevelStats(C.Structure):
+    _fields_ = [("n", C.c_int32), ("stencil", C.c_int32), ("stored_rows", C.c_int32), ("general_rows", C.c_int32),
+                ("sg_nnz", C.c_int64), ("lattice", C.c_int64), ("value_bytes", C.c_int32), ("reserved", C.c_int32)]
+
+
 SYMBOLS = ["imsmg_default_options", "imsmg_create", "imsmg_setup", "imsmg_set_patch_weights",
            "imsmg_factor_patches", "imsmg_get_patches", "imsmg_get_gamma", "imsmg_vcycle", "imsmg_pcg_solve",
            "imsmg_apply_operator", "imsmg_apply_smoother", "imsmg_apply_restriction", "imsmg_apply_prolongation",
-           "imsmg_coarse_solve", "imsmg_kernel_time", "imsmg_last_error", "imsmg_destroy"]
+           "imsmg_coarse_solve", "imsmg_get_level_stats", "imsmg_kernel_time", "imsmg_last_error", "imsmg_destroy"]
 
 
 def library_path() -> str:
@@ -88,6 +93,7 @@ def load():
         getattr(lib, f).argtypes = [vp, i32, vp, vp]
     lib.imsmg_coarse_solve.argtypes = [vp, vp, vp]
     lib.imsmg_kernel_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
+    lib.imsmg_get_level_stats.argtypes = [vp, i32, C.POINTER(LevelStats)]
     lib.imsmg_last_error.argtypes = [vp]
     lib.imsmg_last_error.restype = C.c_char_p
     lib.imsmg_destroy.argtypes = [vp]
@@ -284,6 +290,11 @@ class Solver:
         self._sync()
         self._check(self.lib.imsmg_coarse_solve(self.h, self._dev(r), self._dev(x)))
         return x
+
+    def level_stats(self, level: int) -> dict:
+        st = LevelStats()
+        self._check(self.lib.imsmg_get_level_stats(self.h, level, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in LevelStats._fields_}
 
     def kernel_time(self, reset: bool = False):
         ms = C.c_double()

@@ -66,12 +66,12 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-@pytest.mark.parametrize("implicit", [True, False], ids=["tensor", "ell"])
+@pytest.mark.parametrize("implicit,compress", [(True, 1), (False, 0)], ids=["tensor-compressed", "ell-full"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_level_operators_and_transfers(name, implicit):
+def test_level_operators_and_transfers(name, implicit, compress):
     S = _gpu()
     w, g, op = _problem(name)
-    sol = _solver(S, g, implicit_transfer=implicit)
+    sol = _solver(S, g, implicit_transfer=implicit, compress=compress)
     rng = np.random.default_rng(7)
     for l in range(w.levels):
         A = op.hier.A[l]
@@ -157,8 +157,13 @@ def test_coarse_solve_and_vcycle(name):
     sol.close()
 
 
+FORMS = {"fp64": dict(precision=0, compress=1), "fp64-uncompressed": dict(precision=0, compress=0),
+         "mixed": dict(precision=1, compress=1)}
+
+
+@pytest.mark.parametrize("form", list(FORMS))
 @pytest.mark.parametrize("name", list(CASES))
-def test_pcg_solution_matches_oracle(name):
+def test_pcg_solution_matches_oracle(name, form):
     S = _gpu()
     w, g, op = _problem(name)
     if w.rhs == "zero":
@@ -166,7 +171,7 @@ def test_pcg_solution_matches_oracle(name):
     else:
         b = op.b
     xo, ito, _ = op.solve(b=b, tol=1e-8)
-    sol = _solver(S, g)
+    sol = _solver(S, g, **FORMS[form])
     bg = g.b if w.rhs != "zero" else b
     x = torch.zeros(len(bg), dtype=torch.float64, device="cuda:0")
     info = sol.pcg(_t(bg), x, rtol=1e-8)
@@ -177,7 +182,7 @@ def test_pcg_solution_matches_oracle(name):
     e = xg - xo
     rel_l2 = math.sqrt(e @ (M @ e)) / math.sqrt(xo @ (M @ xo))
     assert rel_l2 <= 1e-6, (name, rel_l2)
-    print(f"[{name}] iterations gpu {info.iterations} oracle {ito}, rel L2 {rel_l2:.2e}")
+    print(f"[{name}/{form}] iterations gpu {info.iterations} oracle {ito}, rel L2 {rel_l2:.2e}")
     assert abs(info.iterations - ito) <= max(2, ito // 10), (name, info.iterations, ito)
     # determinism: a second solve is bitwise identical
     x2 = torch.zeros_like(x)
