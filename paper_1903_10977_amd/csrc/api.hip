@@ -289,6 +289,23 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
     for (int sl = 0; sl < L.K; ++sl) cv[size_t(sl) * nv + g] = ell[size_t(sl) * L.n + comp[g]];
   L.meta = dalloc<uint32_t>(c->owned, L.n);
   h2d(s, L.meta, L.h_meta.data(), L.n);
+  // stored rows of every tile of kTileRows consecutive rows: [tile_g0[b], tile_g0[b + 1])
+  {
+    const int tiles = (L.n + kTileRows - 1) / kTileRows;
+    std::vector<int32_t> tg0(size_t(tiles) + 1, 0);
+    size_t g = 0;
+    for (int b = 0; b <= tiles; ++b) {
+      while (g < comp.size() && comp[g] < b * kTileRows) ++g;
+      tg0[b] = int32_t(g);
+    }
+    int32_t *d_srow = dalloc<int32_t>(c->owned, std::max<size_t>(comp.size(), 1));
+    if (!comp.empty()) h2d(s, d_srow, comp.data(), comp.size());
+    int32_t *d_tg0 = dalloc<int32_t>(c->owned, tg0.size());
+    h2d(s, d_tg0, tg0.data(), tg0.size());
+    L.op64.srow = L.op32.srow = d_srow;
+    L.op64.tile_g0 = L.op32.tile_g0 = d_tg0;
+    HIP_CHECK_RET(hipStreamSynchronize(s));
+  }
   double *cv64 = dalloc<double>(c->owned, cv.size());
   h2d(s, cv64, cv.data(), cv.size());
   L.op64.off = L.off;

@@ -15,6 +15,7 @@
 namespace imsmg {
 
 constexpr int kRedThreads = 256;
+static_assert(kRedThreads == kTileRows, "stencil kernels stage one tile per workgroup");
 constexpr int kFinThreads = 1024;
 
 int reduction_blocks(int n) { return n < 1 ? 1 : (n + kRedThreads - 1) / kRedThreads; }
@@ -57,17 +58,17 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_init(int n, int Kdyn, OpView
                                                          const double *__restrict__ b, double *__restrict__ r,
                                                          double *__restrict__ part) {
   __shared__ double lds[kRedThreads];
+  __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
-  const int i = blk * kRedThreads + threadIdx.x;
   double rr = 0.0, bb = 0.0;
-  if (i < n) {
-    const int L = row_lat[i];
-    const double bi = b[L];
-    const double ri = bi - op_row<K, double>(meta[i], op, x, L, Kdyn);
-    r[L] = ri;
-    rr = ri * ri;
-    bb = bi * bi;
-  }
+  tile_rows<K, double>(n, blk * kRedThreads, op, row_lat, meta, x, tile, Kdyn,
+                       [&](int, int L, unsigned, double ax, double) {
+                         const double bi = b[L];
+                         const double ri = bi - ax;
+                         r[L] = ri;
+                         rr += ri * ri;
+                         bb += bi * bi;
+                       });
   rr = block_sum<kRedThreads>(rr, lds);
   bb = block_sum<kRedThreads>(bb, lds);
   if (threadIdx.x == 0) {
@@ -150,15 +151,14 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_spmv_pq(int n, int Kdyn, OpV
                                                             double *__restrict__ part, const CGState *st) {
   if (st->done) return;
   __shared__ double lds[kRedThreads];
+  __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
-  const int i = blk * kRedThreads + threadIdx.x;
   double acc = 0.0;
-  if (i < n) {
-    const int L = row_lat[i];
-    const double qi = op_row<K, double>(meta[i], op, p, L, Kdyn);
-    q[L] = qi;
-    acc = p[L] * qi;
-  }
+  tile_rows<K, double>(n, blk * kRedThreads, op, row_lat, meta, p, tile, Kdyn,
+                       [&](int, int L, unsigned, double ax, double pc) {
+                         q[L] = ax;
+                         acc += pc * ax;
+                       });
   acc = block_sum<kRedThreads>(acc, lds);
   if (threadIdx.x == 0) part[blk] = acc;
 }
@@ -233,14 +233,14 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_true_residual(int n, int Kdy
                                                                   const double *__restrict__ b,
                                                                   double *__restrict__ part) {
   __shared__ double lds[kRedThreads];
+  __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
-  const int i = blk * kRedThreads + threadIdx.x;
   double acc = 0.0;
-  if (i < n) {
-    const int L = row_lat[i];
-    const double ri = b[L] - op_row<K, double>(meta[i], op, x, L, Kdyn);
-    acc = ri * ri;
-  }
+  tile_rows<K, double>(n, blk * kRedThreads, op, row_lat, meta, x, tile, Kdyn,
+                       [&](int, int L, unsigned, double ax, double) {
+                         const double ri = b[L] - ax;
+                         acc += ri * ri;
+                       });
   acc = block_sum<kRedThreads>(acc, lds);
   if (threadIdx.x == 0) part[blk] = acc;
 }

@@ -27,6 +27,8 @@
 
 namespace imsmg {
 
+constexpr int kTileRows = 256;  // rows (= threads) per workgroup of the stencil kernels
+
 constexpr uint32_t kMetaIndex = 0x3fffffffu;    // low 30 bits: compressed-value index, all ones = uniform
 constexpr uint32_t kMetaGeneral = 0x40000000u;  // row belongs to a general Schwarz block
 
@@ -37,9 +39,11 @@ struct Offsets {
 template <typename V>
 struct OpView {
   Offsets off;
-  const V *ref;  // uniform interior stencil (K values)
-  const V *val;  // stored rows, slot-major
-  int nv;        // number of stored rows
+  const V *ref;            // uniform interior stencil (K values)
+  const V *val;            // stored rows, slot-major
+  int nv;                  // number of stored rows
+  const int32_t *srow;     // row index of every stored row (ascending)
+  const int32_t *tile_g0;  // first stored row of every kTileRows-row tile (tiles + 1 entries)
 };
 
 // Scalars of the CG iteration, kept on the device.

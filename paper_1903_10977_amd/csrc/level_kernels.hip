@@ -19,13 +19,15 @@
 //
 // All row kernels map one thread to one active row; workgroups are renumbered
 // so that each of the 8 XCDs walks one contiguous chunk of rows and keeps the
-// neighbouring lattice lines of the input vector in its own L2.
+// neighbouring lattice lines of the input vector in its own L2.  The stencil
+// kernels stage the workgroup's window of the input vector in LDS (op_row.h).
 #include "imsmg_internal.h"
 #include "op_row.h"
 
 namespace imsmg {
 
 constexpr int kRowBlock = 256;
+static_assert(kRowBlock == kTileRows, "stencil kernels stage one tile per workgroup");
 
 __device__ __forceinline__ int xcd_block(int b, int nb) {
   // hardware dispatches workgroup b to XCD (b % 8); give XCD k a contiguous
@@ -47,12 +49,11 @@ __global__ __launch_bounds__(kRowBlock) void k_residual(int n, int Kdyn, OpView<
                                                         const double *__restrict__ x, const double *__restrict__ b,
                                                         double *__restrict__ y, const int32_t *__restrict__ done) {
   if (done && *done) return;
-  const int i = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
-  if (i >= n) return;
-  const int L = row_lat[i];
-  const unsigned m = meta[i];
-  const double ax = op_row<K, V>(m, op, x, L, Kdyn);
-  y[L] = b ? b[L] - ax : ax;
+  __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
+  const int first = xcd_block(blockIdx.x, gridDim.x) * kRowBlock;
+  tile_rows<K, V>(n, first, op, row_lat, meta, x, tile, Kdyn, [&](int, int L, unsigned, double ax, double) {
+    y[L] = b ? b[L] - ax : ax;
+  });
 }
 
 // smoothing step, trivial rows:  rh = r - A xa  (stored for general rows only),
@@ -67,14 +68,13 @@ __global__ __launch_bounds__(kRowBlock) void k_residual_smooth(int n, int Kdyn, 
                                                                double *__restrict__ xb,
                                                                const int32_t *__restrict__ done) {
   if (done && *done) return;
-  const int i = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
-  if (i >= n) return;
-  const int L = row_lat[i];
-  const unsigned m = meta[i];
-  const double ax = op_row<K, V>(m, op, xa, L, Kdyn);
-  const double res = r[L] - ax;
-  if (m & kMetaGeneral) rh[L] = res;
-  xb[L] = xa[L] + c[i] * res;
+  __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
+  const int first = xcd_block(blockIdx.x, gridDim.x) * kRowBlock;
+  tile_rows<K, V>(n, first, op, row_lat, meta, xa, tile, Kdyn, [&](int i, int L, unsigned m, double ax, double xc) {
+    const double res = r[L] - ax;
+    if (m & kMetaGeneral) rh[L] = res;
+    xb[L] = xc + c[i] * res;
+  });
 }
 
 template <typename V>

@@ -1,37 +1,43 @@
-// Rows of the compressed lattice-ELL operator: sum_s a_s x[L + off_s].
+// Rows of the compressed lattice-ELL operator: (A x)_L = sum_s a_s x[L + off_s].
 //
-// Two cooperating mechanisms keep the per-row memory instructions low (the
-// stencil kernels are bound by vector address processing, not by HBM: the
-// level's matrix and vectors stay resident in the Infinity Cache between the
-// V-cycle's sweeps):
-//   * LDS tile: a workgroup of consecutive active rows spans the lattice
-//     range [Lmin, Lmax]; for every stencil line (fixed dy, dz) the x window
-//     [Lmin - p + line_off, Lmax + p + line_off] is loaded once, coalesced,
-//     into LDS and the K gathers of a row become LDS reads;
-//   * wave-uniform stencil: when every row of a wavefront uses the level's
-//     reference stencil, its K coefficients are wave-uniform (scalar loads);
-//     otherwise each lane selects its own (pointer, stride): the reference
-//     stencil (stride 1) or its stored slot-major values (stride nv).
+// The stencil kernels are limited by vector address processing rather than by
+// HBM (the level's matrix and vectors stay resident in the Infinity Cache
+// between the V-cycle's sweeps), so these helpers minimise the vector memory
+// instructions per row:
+//   * LDS tile: the kTileRows consecutive active rows of a workgroup span the
+//     lattice range [lo, hi] (rows are numbered in lattice order); for every
+//     stencil line (fixed dy, dz) the x window [lo - p, hi + p], shifted by
+//     the line's offset, is loaded once and coalesced into LDS, and the K
+//     gathers of a row become LDS reads;
+//   * two phases per tile: (1) every row whose values equal the reference
+//     stencil takes its K coefficients from scalar loads (wave-uniform
+//     addresses); (2) the tile's stored rows, numbered consecutively, are
+//     packed onto the first lanes, so that their slot-major values are read
+//     with fully coalesced, fully active vector loads.
+// Workgroups whose span exceeds kTileSpan (large holes of the domain), the
+// 125-point 3D stencil and generic K gather per lane from global memory.
 // Shared by the level and CG kernels.
 #pragma once
 #include "imsmg_internal.h"
 
 namespace imsmg {
 
-constexpr int kTileRows = 256;  // rows per workgroup of the stencil kernels
-constexpr int kTileSpan = 640;  // largest lattice span staged in LDS (else global gathers)
+constexpr int kTileSpan = 512;  // largest lattice span of a workgroup staged in LDS
 
 template <int K>
 struct StencilShape {
   static constexpr int W = K == 9 ? 3 : K == 25 ? 5 : K == 49 ? 7 : K == 27 ? 3 : K == 125 ? 5 : 0;
-  static constexpr int P = (W - 1) / 2;
+  static constexpr int P = W > 0 ? (W - 1) / 2 : 0;
   static constexpr int LINES = W > 0 ? K / W : 0;
   static constexpr int STRIDE = kTileSpan + 2 * P;
-  // LDS tiling for the 2D stencils and the 27-point 3D stencil (the 125-point
-  // tile would need 25 lines and throttle occupancy)
-  static constexpr bool TILED = W > 0 && K != 125;
+  static constexpr bool TILED = W > 0 && K != 125;  // 125 points: 25 lines would throttle occupancy
   static constexpr int LDS_DOUBLES = TILED ? LINES * STRIDE : 1;
 };
+
+// Read-only device memory read with a wave-uniform address through the
+// constant address space, so that it is fetched by scalar loads.
+template <typename V>
+using ConstPtr = const __attribute__((address_space(4))) V *;
 
 // Per-lane (pointer, stride) row: global gathers.
 template <int K, typename V>
@@ -51,66 +57,85 @@ __device__ __forceinline__ double op_row(unsigned meta, const OpView<V> &op, con
   return acc;
 }
 
-// Stage the x window of the workgroup's rows [first, first + kTileRows) into
-// LDS.  Returns the workgroup's Lmin, or -1 when the span exceeds the tile
-// (then the rows use global gathers).  All threads of the workgroup call it.
+// Stages the x window of the workgroup's rows [first, min(first + kTileRows, n))
+// into LDS and returns lo = row_lat[first], or -1 when the operator is not
+// tiled or the span exceeds kTileSpan.  Every thread of the workgroup must
+// call it (it synchronizes); first < n.
 template <int K>
-__device__ __forceinline__ int stage_tile(const int32_t *__restrict__ row_lat, int first, int n,
-                                          const Offsets &off, const double *__restrict__ x, double *lds) {
+__device__ __forceinline__ int tile_stage(const int32_t *__restrict__ row_lat, int first, int n, const Offsets &off,
+                                          const double *__restrict__ x, double *lds) {
   using SS = StencilShape<K>;
-  __shared__ int s_lo, s_hi;
-  if (threadIdx.x == 0) {
-    const int last = min(first + kTileRows, n) - 1;
-    s_lo = row_lat[first];
-    s_hi = row_lat[last];
-  }
-  __syncthreads();
-  const int lo = s_lo, hi = s_hi;
-  const int span = hi - lo + 1 + 2 * SS::P;
-  if (hi - lo + 1 > kTileSpan) return -1;
-#pragma unroll
-  for (int j = 0; j < SS::LINES; ++j) {
-    const double *src = x + (lo - SS::P + off.off[j * SS::W + SS::P]);
-    for (int t = threadIdx.x; t < span; t += kTileRows) lds[j * SS::STRIDE + t] = src[t];
-  }
-  __syncthreads();
-  return lo;
-}
-
-// One row from the LDS tile (lo = the workgroup's Lmin).
-template <int K, typename V>
-__device__ __forceinline__ double op_row_tile(unsigned meta, const OpView<V> &op, const double *lds, int L, int lo,
-                                              bool wave_uniform) {
-  using SS = StencilShape<K>;
-  const int c0 = L - lo;  // column of dx = -p
-  double acc = 0.0;
-  if (wave_uniform) {
-    const V *__restrict__ ref = op.ref;
-#pragma unroll
-    for (int s = 0; s < K; ++s) acc += double(ref[s]) * lds[(s / SS::W) * SS::STRIDE + c0 + (s % SS::W)];
+  if constexpr (!SS::TILED) {
+    return -1;
   } else {
-    const unsigned g = meta & kMetaIndex;
-    const bool uni = g == kMetaIndex;
-    const V *__restrict__ v = uni ? op.ref : op.val + g;
-    const size_t st = uni ? 1 : size_t(op.nv);
+    const int lo = row_lat[first];
+    const int hi = row_lat[min(first + kTileRows, n) - 1];
+    if (hi - lo + 1 > kTileSpan) return -1;
+    const int span = hi - lo + 1 + 2 * SS::P;
 #pragma unroll
-    for (int s = 0; s < K; ++s) acc += double(v[s * st]) * lds[(s / SS::W) * SS::STRIDE + c0 + (s % SS::W)];
+    for (int j = 0; j < SS::LINES; ++j) {
+      const double *__restrict__ src = x + (lo - SS::P + off.off[j * SS::W + SS::P]);
+      for (int t = threadIdx.x; t < span; t += kTileRows) lds[j * SS::STRIDE + t] = src[t];
+    }
+    __syncthreads();
+    return lo;
   }
-  return acc;
 }
 
-// A x for row i of a workgroup staged with stage_tile (lo >= 0) or by
-// global gathers (lo < 0).  `active` = this thread owns a row.
-template <int K, typename V>
-__device__ __forceinline__ double op_apply(bool active, unsigned meta, const OpView<V> &op,
-                                           const double *__restrict__ x, int L, int lo, const double *lds, int Kdyn) {
+// tile entry of slot s for the row whose dx = -p column on line 0 is t
+template <int K>
+__device__ __forceinline__ double tile_at(const double *t, int s) {
+  using SS = StencilShape<K>;
+  return t[(s / SS::W) * SS::STRIDE + s % SS::W];
+}
+
+template <int K>
+__device__ __forceinline__ double tile_center(const double *t) {
+  using SS = StencilShape<K>;
+  return t[(SS::LINES / 2) * SS::STRIDE + SS::P];
+}
+
+// Applies the operator to every row of a workgroup tile and hands each row
+// exactly once to epi(i, L, meta, (A x)_L, x_L).  Every thread of the
+// workgroup must call it; first = the tile's first row (< n).
+template <int K, typename V, typename Epi>
+__device__ __forceinline__ void tile_rows(int n, int first, const OpView<V> &op, const int32_t *__restrict__ row_lat,
+                                          const uint32_t *__restrict__ meta, const double *__restrict__ x,
+                                          double *lds, int Kdyn, Epi &&epi) {
+  const int i = first + threadIdx.x;
+  const bool act = i < n;
+  const int L = act ? row_lat[i] : 0;
+  const unsigned m = act ? meta[i] : 0u;
+  const int lo = tile_stage<K>(row_lat, first, n, op.off, x, lds);
   if constexpr (StencilShape<K>::TILED) {
     if (lo >= 0) {
-      const bool wu = __all(!active || (meta & kMetaIndex) == kMetaIndex);
-      return active ? op_row_tile<K, V>(meta, op, lds, L, lo, wu) : 0.0;
+      // phase 1: rows on the reference stencil
+      if (act && (m & kMetaIndex) == kMetaIndex) {
+        const double *t = lds + (L - lo);
+        const ConstPtr<V> ref = (ConstPtr<V>)op.ref;
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < K; ++s) acc += double(ref[s]) * tile_at<K>(t, s);
+        epi(i, L, m, acc, tile_center<K>(t));
+      }
+      // phase 2: the tile's stored rows, packed onto the first lanes
+      const int tile = first / kTileRows;
+      const int g = op.tile_g0[tile] + threadIdx.x;
+      if (g < op.tile_g0[tile + 1]) {
+        const int ii = op.srow[g];
+        const int Ls = row_lat[ii];
+        const double *t = lds + (Ls - lo);
+        const V *__restrict__ v = op.val + g;
+        const size_t nv = size_t(op.nv);
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < K; ++s) acc += double(v[s * nv]) * tile_at<K>(t, s);
+        epi(ii, Ls, meta[ii], acc, tile_center<K>(t));
+      }
+      return;
     }
   }
-  return active ? op_row<K, V>(meta, op, x, L, Kdyn) : 0.0;
+  if (act) epi(i, L, m, op_row<K, V>(m, op, x, L, Kdyn), x[L]);
 }
 
 }  // namespace imsmg
