@@ -87,6 +87,7 @@ def main():
     import torch
     import workloads as W
     from paper_1903_10977_amd import generator as GN
+    from paper_1903_10977_amd import profiling as PR
     from paper_1903_10977_amd import solver as S
 
     assert torch.cuda.is_available(), "bench needs a GPU"
@@ -158,13 +159,23 @@ def main():
     solt.close()
 
     if args.copy_calibration_mib > 0:
+        # a plain device copy of known size for the counter scaling: one
+        # elementwise kernel reading M MiB and writing M MiB
         m = args.copy_calibration_mib * (1 << 20) // 8
-        src = torch.ones(m, dtype=torch.float64, device="cuda:0")
+        src = torch.rand(m, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
-        log(f"copy calibration: 3 copies of {args.copy_calibration_mib} MiB")
+        log(f"copy calibration: 3 elementwise copies of {args.copy_calibration_mib} MiB")
+        del src, dst
+
+    # measured HBM traffic of the same kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+    # copy-calibrated), valid only while the kernel sources are unchanged
+    traffic = None
+    if args.n == 1024:
+        form = "mixed" if head == S.MIXED else "fp64"
+        traffic = PR.read_traffic(os.path.join(ROOT, "profiles", f"traffic_k_residual_smooth_1024_discs_{form}.txt"))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -185,7 +196,7 @@ def main():
                    "pcg_time_s": round(ms_step / 1e3, 5), "forms": forms,
                    "speedup_mixed_vs_fp64": round(results[S.FP64]["ms"] / results[S.MIXED]["ms"], 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_residual_smooth (finest level)", "bytes_per_launch": int(bytes_launch),
                      "avg_launch_us": round(avg_ms * 1e3, 2)},
         "cpu_baseline": cpu,

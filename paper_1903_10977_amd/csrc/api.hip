@@ -299,10 +299,17 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
       tg0[b] = int32_t(g);
     }
     int32_t *d_srow = dalloc<int32_t>(c->owned, std::max<size_t>(comp.size(), 1));
-    if (!comp.empty()) h2d(s, d_srow, comp.data(), comp.size());
+    int32_t *d_slat = dalloc<int32_t>(c->owned, std::max<size_t>(comp.size(), 1));
+    std::vector<int32_t> slat(comp.size());
+    for (size_t k = 0; k < comp.size(); ++k) slat[k] = L.h_row_lat[comp[k]];
+    if (!comp.empty()) {
+      h2d(s, d_srow, comp.data(), comp.size());
+      h2d(s, d_slat, slat.data(), slat.size());
+    }
     int32_t *d_tg0 = dalloc<int32_t>(c->owned, tg0.size());
     h2d(s, d_tg0, tg0.data(), tg0.size());
     L.op64.srow = L.op32.srow = d_srow;
+    L.op64.slat = L.op32.slat = d_slat;
     L.op64.tile_g0 = L.op32.tile_g0 = d_tg0;
     HIP_CHECK_RET(hipStreamSynchronize(s));
   }

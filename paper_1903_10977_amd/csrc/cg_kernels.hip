@@ -49,9 +49,48 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ part, 
   return block_sum<kFinThreads>(v, lds);
 }
 
+// r = b - A x, accumulating (||r||^2, ||b||^2)
+struct InitEpi {
+  const double *__restrict__ b;
+  double *__restrict__ r;
+  struct Pre {
+    double b;
+  };
+  __device__ Pre pre(int, int L) const { return {b[L]}; }
+  __device__ double2 post(int, int L, unsigned, double ax, double, const Pre &p) const {
+    const double ri = p.b - ax;
+    r[L] = ri;
+    return make_double2(ri * ri, p.b * p.b);
+  }
+};
+
+// q = A p, accumulating p . q
+struct SpmvEpi {
+  double *__restrict__ q;
+  struct Pre {};
+  __device__ Pre pre(int, int) const { return {}; }
+  __device__ double2 post(int, int L, unsigned, double ax, double pc, const Pre &) const {
+    q[L] = ax;
+    return make_double2(pc * ax, 0.0);
+  }
+};
+
+// accumulates ||b - A x||^2
+struct TrueResEpi {
+  const double *__restrict__ b;
+  struct Pre {
+    double b;
+  };
+  __device__ Pre pre(int, int L) const { return {b[L]}; }
+  __device__ double2 post(int, int, unsigned, double ax, double, const Pre &p) const {
+    const double ri = p.b - ax;
+    return make_double2(ri * ri, 0.0);
+  }
+};
+
 // r = b - A x; partials of ||r||^2 (part[0..g)) and ||b||^2 (part[g..2g))
 template <int K>
-__global__ __launch_bounds__(kRedThreads) void k_cg_init(int n, int Kdyn, OpView<double> op,
+__global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_cg_init(int n, int Kdyn, OpView<double> op,
                                                          const int32_t *__restrict__ row_lat,
                                                          const uint32_t *__restrict__ meta,
                                                          const double *__restrict__ x,
@@ -60,15 +99,8 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_init(int n, int Kdyn, OpView
   __shared__ double lds[kRedThreads];
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
-  double rr = 0.0, bb = 0.0;
-  tile_rows<K, double>(n, blk * kRedThreads, op, row_lat, meta, x, tile, Kdyn,
-                       [&](int, int L, unsigned, double ax, double) {
-                         const double bi = b[L];
-                         const double ri = bi - ax;
-                         r[L] = ri;
-                         rr += ri * ri;
-                         bb += bi * bi;
-                       });
+  const double2 s = tile_rows<K, double>(n, blk * kRedThreads, op, row_lat, meta, x, tile, Kdyn, InitEpi{b, r});
+  double rr = s.x, bb = s.y;
   rr = block_sum<kRedThreads>(rr, lds);
   bb = block_sum<kRedThreads>(bb, lds);
   if (threadIdx.x == 0) {
@@ -144,7 +176,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_direction(int n, const int32
 }
 
 template <int K>
-__global__ __launch_bounds__(kRedThreads) void k_cg_spmv_pq(int n, int Kdyn, OpView<double> op,
+__global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_cg_spmv_pq(int n, int Kdyn, OpView<double> op,
                                                             const int32_t *__restrict__ row_lat,
                                                             const uint32_t *__restrict__ meta,
                                                             const double *__restrict__ p, double *__restrict__ q,
@@ -153,12 +185,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_spmv_pq(int n, int Kdyn, OpV
   __shared__ double lds[kRedThreads];
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
-  double acc = 0.0;
-  tile_rows<K, double>(n, blk * kRedThreads, op, row_lat, meta, p, tile, Kdyn,
-                       [&](int, int L, unsigned, double ax, double pc) {
-                         q[L] = ax;
-                         acc += pc * ax;
-                       });
+  double acc = tile_rows<K, double>(n, blk * kRedThreads, op, row_lat, meta, p, tile, Kdyn, SpmvEpi{q}).x;
   acc = block_sum<kRedThreads>(acc, lds);
   if (threadIdx.x == 0) part[blk] = acc;
 }
@@ -226,7 +253,7 @@ __global__ __launch_bounds__(kFinThreads) void k_cg_update_fin(int m, const doub
 
 // partials of ||b - A x||^2
 template <int K>
-__global__ __launch_bounds__(kRedThreads) void k_cg_true_residual(int n, int Kdyn, OpView<double> op,
+__global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_cg_true_residual(int n, int Kdyn, OpView<double> op,
                                                                   const int32_t *__restrict__ row_lat,
                                                                   const uint32_t *__restrict__ meta,
                                                                   const double *__restrict__ x,
@@ -235,12 +262,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_true_residual(int n, int Kdy
   __shared__ double lds[kRedThreads];
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
-  double acc = 0.0;
-  tile_rows<K, double>(n, blk * kRedThreads, op, row_lat, meta, x, tile, Kdyn,
-                       [&](int, int L, unsigned, double ax, double) {
-                         const double ri = b[L] - ax;
-                         acc += ri * ri;
-                       });
+  double acc = tile_rows<K, double>(n, blk * kRedThreads, op, row_lat, meta, x, tile, Kdyn, TrueResEpi{b}).x;
   acc = block_sum<kRedThreads>(acc, lds);
   if (threadIdx.x == 0) part[blk] = acc;
 }

@@ -43,6 +43,7 @@ struct OpView {
   const V *val;            // stored rows, slot-major
   int nv;                  // number of stored rows
   const int32_t *srow;     // row index of every stored row (ascending)
+  const int32_t *slat;     // lattice position of every stored row
   const int32_t *tile_g0;  // first stored row of every kTileRows-row tile (tiles + 1 entries)
 };
 

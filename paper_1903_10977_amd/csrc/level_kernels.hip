@@ -42,24 +42,55 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 
 static inline int grid_for(int n) { return (n + kRowBlock - 1) / kRowBlock; }
 
+// epilogue of the residual: y = b - A x (b == nullptr: y = A x)
+struct ResidualEpi {
+  const double *__restrict__ b;
+  double *__restrict__ y;
+  struct Pre {
+    double b;
+  };
+  __device__ Pre pre(int, int L) const { return {b ? b[L] : 0.0}; }
+  __device__ double2 post(int, int L, unsigned, double ax, double, const Pre &p) const {
+    y[L] = b ? p.b - ax : ax;
+    return make_double2(0.0, 0.0);
+  }
+};
+
+// epilogue of the smoothing step (trivial rows): rh = r - A xa on general
+// rows, xb = xa + c (r - A xa)
+struct SmoothEpi {
+  const double *__restrict__ r;
+  const double *__restrict__ c;
+  double *__restrict__ rh;
+  double *__restrict__ xb;
+  struct Pre {
+    double r, c;
+  };
+  __device__ Pre pre(int i, int L) const { return {r[L], c[i]}; }
+  __device__ double2 post(int, int L, unsigned m, double ax, double xc, const Pre &p) const {
+    const double res = p.r - ax;
+    if (m & kMetaGeneral) rh[L] = res;
+    xb[L] = xc + p.c * res;
+    return make_double2(0.0, 0.0);
+  }
+};
+
 // y = b - A x   (b == nullptr: y = A x)
 template <int K, typename V>
-__global__ __launch_bounds__(kRowBlock) void k_residual(int n, int Kdyn, OpView<V> op, const int32_t *__restrict__ row_lat,
+__global__ __launch_bounds__(kRowBlock, kTileBlocksPerCU) void k_residual(int n, int Kdyn, OpView<V> op, const int32_t *__restrict__ row_lat,
                                                         const uint32_t *__restrict__ meta,
                                                         const double *__restrict__ x, const double *__restrict__ b,
                                                         double *__restrict__ y, const int32_t *__restrict__ done) {
   if (done && *done) return;
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
   const int first = xcd_block(blockIdx.x, gridDim.x) * kRowBlock;
-  tile_rows<K, V>(n, first, op, row_lat, meta, x, tile, Kdyn, [&](int, int L, unsigned, double ax, double) {
-    y[L] = b ? b[L] - ax : ax;
-  });
+  tile_rows<K, V>(n, first, op, row_lat, meta, x, tile, Kdyn, ResidualEpi{b, y});
 }
 
 // smoothing step, trivial rows:  rh = r - A xa  (stored for general rows only),
 // xb = xa + c * rh   (c = 0 on general rows, which the general kernel completes)
 template <int K, typename V>
-__global__ __launch_bounds__(kRowBlock) void k_residual_smooth(int n, int Kdyn, OpView<V> op,
+__global__ __launch_bounds__(kRowBlock, kTileBlocksPerCU) void k_residual_smooth(int n, int Kdyn, OpView<V> op,
                                                                const int32_t *__restrict__ row_lat,
                                                                const uint32_t *__restrict__ meta,
                                                                const double *__restrict__ c,
@@ -70,11 +101,7 @@ __global__ __launch_bounds__(kRowBlock) void k_residual_smooth(int n, int Kdyn, 
   if (done && *done) return;
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
   const int first = xcd_block(blockIdx.x, gridDim.x) * kRowBlock;
-  tile_rows<K, V>(n, first, op, row_lat, meta, xa, tile, Kdyn, [&](int i, int L, unsigned m, double ax, double xc) {
-    const double res = r[L] - ax;
-    if (m & kMetaGeneral) rh[L] = res;
-    xb[L] = xc + c[i] * res;
-  });
+  tile_rows<K, V>(n, first, op, row_lat, meta, xa, tile, Kdyn, SmoothEpi{r, c, rh, xb});
 }
 
 template <typename V>

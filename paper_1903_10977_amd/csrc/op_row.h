@@ -23,6 +23,10 @@
 namespace imsmg {
 
 constexpr int kTileSpan = 512;  // largest lattice span of a workgroup staged in LDS
+// register cap of the tiled kernels: 4 resident workgroups per CU (16 waves);
+// the 49-point tile (7 x 518 doubles) would allow 5 in 160 KiB of LDS, but the
+// tighter register budget that needs spills in the FP64 kernels
+constexpr int kTileBlocksPerCU = 4;
 
 template <int K>
 struct StencilShape {
@@ -96,46 +100,75 @@ __device__ __forceinline__ double tile_center(const double *t) {
 }
 
 // Applies the operator to every row of a workgroup tile and hands each row
-// exactly once to epi(i, L, meta, (A x)_L, x_L).  Every thread of the
-// workgroup must call it; first = the tile's first row (< n).
+// exactly once to the epilogue: epi.post(i, L, meta, (A x)_L, x_L, pre) with
+// pre = epi.pre(i, L) fetched before the tile is staged (so that its loads
+// overlap the staging); post returns a pair of partial sums that tile_rows
+// adds up per thread.  Every thread of the workgroup must call it; first =
+// the tile's first row (< n).
 template <int K, typename V, typename Epi>
-__device__ __forceinline__ void tile_rows(int n, int first, const OpView<V> &op, const int32_t *__restrict__ row_lat,
-                                          const uint32_t *__restrict__ meta, const double *__restrict__ x,
-                                          double *lds, int Kdyn, Epi &&epi) {
+__device__ __forceinline__ double2 tile_rows(int n, int first, const OpView<V> &op,
+                                             const int32_t *__restrict__ row_lat, const uint32_t *__restrict__ meta,
+                                             const double *__restrict__ x, double *lds, int Kdyn, const Epi &epi) {
+  using Pre = typename Epi::Pre;
+  double2 acc = make_double2(0.0, 0.0);
   const int i = first + threadIdx.x;
   const bool act = i < n;
-  const int L = act ? row_lat[i] : 0;
-  const unsigned m = act ? meta[i] : 0u;
-  const int lo = tile_stage<K>(row_lat, first, n, op.off, x, lds);
+  int L = 0;
+  unsigned m = 0u;
+  Pre p1{};
+  if (act) {
+    L = row_lat[i];
+    m = meta[i];
+    p1 = epi.pre(i, L);
+  }
   if constexpr (StencilShape<K>::TILED) {
+    // the tile's stored rows (phase 2), fetched before staging as well
+    const int tile = first / kTileRows;
+    const int g = op.tile_g0[tile] + threadIdx.x;
+    const bool act2 = g < op.tile_g0[tile + 1];
+    int i2 = 0, L2 = 0;
+    unsigned m2 = 0u;
+    Pre p2{};
+    if (act2) {
+      i2 = op.srow[g];
+      L2 = op.slat[g];
+      m2 = meta[i2];
+      p2 = epi.pre(i2, L2);
+    }
+    const int lo = tile_stage<K>(row_lat, first, n, op.off, x, lds);
     if (lo >= 0) {
       // phase 1: rows on the reference stencil
       if (act && (m & kMetaIndex) == kMetaIndex) {
         const double *t = lds + (L - lo);
         const ConstPtr<V> ref = (ConstPtr<V>)op.ref;
-        double acc = 0.0;
+        double ax = 0.0;
 #pragma unroll
-        for (int s = 0; s < K; ++s) acc += double(ref[s]) * tile_at<K>(t, s);
-        epi(i, L, m, acc, tile_center<K>(t));
+        for (int s = 0; s < K; ++s) ax += double(ref[s]) * tile_at<K>(t, s);
+        const double2 c = epi.post(i, L, m, ax, tile_center<K>(t), p1);
+        acc.x += c.x;
+        acc.y += c.y;
       }
       // phase 2: the tile's stored rows, packed onto the first lanes
-      const int tile = first / kTileRows;
-      const int g = op.tile_g0[tile] + threadIdx.x;
-      if (g < op.tile_g0[tile + 1]) {
-        const int ii = op.srow[g];
-        const int Ls = row_lat[ii];
-        const double *t = lds + (Ls - lo);
+      if (act2) {
+        const double *t = lds + (L2 - lo);
         const V *__restrict__ v = op.val + g;
         const size_t nv = size_t(op.nv);
-        double acc = 0.0;
+        double ax = 0.0;
 #pragma unroll
-        for (int s = 0; s < K; ++s) acc += double(v[s * nv]) * tile_at<K>(t, s);
-        epi(ii, Ls, meta[ii], acc, tile_center<K>(t));
+        for (int s = 0; s < K; ++s) ax += double(v[s * nv]) * tile_at<K>(t, s);
+        const double2 c = epi.post(i2, L2, m2, ax, tile_center<K>(t), p2);
+        acc.x += c.x;
+        acc.y += c.y;
       }
-      return;
+      return acc;
     }
   }
-  if (act) epi(i, L, m, op_row<K, V>(m, op, x, L, Kdyn), x[L]);
+  if (act) {
+    const double2 c = epi.post(i, L, m, op_row<K, V>(m, op, x, L, Kdyn), x[L], p1);
+    acc.x += c.x;
+    acc.y += c.y;
+  }
+  return acc;
 }
 
 }  // namespace imsmg

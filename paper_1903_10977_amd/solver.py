@@ -65,7 +65,9 @@ SYMBOLS = ["imsmg_default_options", "imsmg_create", "imsmg_setup", "imsmg_set_pa
 
 
 def library_path() -> str:
-    return os.path.join(LIB_DIR, "libimsmg.so")
+    """The in-tree build, or the HIP library named by IMSMG_LIBRARY (another
+    build of the same sources, e.g. for side-by-side timing)."""
+    return os.environ.get("IMSMG_LIBRARY") or os.path.join(LIB_DIR, "libimsmg.so")
 
 
 def load():
