@@ -24,7 +24,10 @@ oracle favours the plain definition of each object over speed:
 * schwarz.py    - encapsulating-support blocks, the tiny-eigenvalue removal
                   remark, the additive Schwarz operator and its damping.
 * multigrid.py  - the V-cycle (Algorithm alg:MGV) and CG preconditioned by it.
-* mlp.py        - the per-patch damping network (forward/backward/Adam).
+* mlp.py        - the per-block damping network (forward/backward/Adam).
+* learned.py    - per-block damping: block features, the two-grid objective
+                  built on eq:eigenMulti with its adjoint gradient, and the
+                  lambda_max(S A) < 2(1 - 0.05) stability check.
 
 Parity unpinned (no independent pin exists): exact iteration counts against
 the paper (its convergence figures are not in the text), removal decisions
