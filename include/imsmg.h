@@ -77,11 +77,17 @@ typedef struct {
 
 /* Element incidence of one level (host arrays, optional): for every active
  * element e the compact indices of the active functions non-zero on it,
- * eidx[eptr[e] .. eptr[e+1]).  Used for N_K in gamma = 1 / max_K N_K. */
+ * eidx[eptr[e] .. eptr[e+1]).  Used for N_K in gamma = 1 / max_K N_K.
+ * The per-block damping features also need, per active element, its lattice
+ * index elem[e] (x fastest over shape = elements per axis) and its volume
+ * fraction eta[e] = |K cap Omega| / |K| in [0, 1] (NULL: all 1). */
 typedef struct {
   int32_t nelements;
   const int32_t *eptr;
   const int32_t *eidx;
+  int32_t shape[3];      /* elements per axis (unused axes: 1); read when elem != NULL */
+  const int32_t *elem;   /* nelements lattice indices, or NULL */
+  const double *eta;     /* nelements volume fractions, or NULL */
 } imsmg_elements;
 
 /* Function lattice of one level. */
@@ -110,6 +116,9 @@ typedef struct {
   double gamma;        /* > 0: uniform damping on all levels; <= 0: 1 / max_K N_K per level */
   int32_t compress;    /* 1: rows equal to the level's interior stencil (1e-14 relative) read that
                           stencil instead of their own values (default 1) */
+  int32_t use_learned; /* 1: imsmg_factor_patches damps every block of every level without given
+                          weights by the loaded damping network (imsmg_load_mlp), subject to the
+                          stability check; default 0 */
 } imsmg_options;
 
 typedef struct {
@@ -139,8 +148,81 @@ int imsmg_setup(imsmg_ctx *ctx, int nlevels, const imsmg_csr *A, const imsmg_csr
 int imsmg_set_patch_weights(imsmg_ctx *ctx, int level, const double *omega);
 
 /* Factorizes every block on the device (FP64 Jacobi eigensolver with the
- * removal rule), forms the smoother, the damping and the coarsest inverse. */
+ * removal rule), forms the smoother, the damping and the coarsest inverse.
+ * With opt.use_learned, every level l >= 1 without given weights then takes
+ * omega_j = gamma_l exp(clip(o_j, -3, 3)) from the damping network on the
+ * block features; the weights are kept only if a 60-step power iteration
+ * finds lambda_max(S_omega A_l) < 2 (1 - 0.05) (the stability condition
+ * eq:stabilityMulti keeps I - S A a contraction), else the level falls back
+ * to gamma_l (imsmg_get_patch_weights reports which). */
 int imsmg_factor_patches(imsmg_ctx *ctx);
+
+/* ---- per-block damping (an extension: the paper uses one factor per level,
+ * see the discussion after eq:applyCS).  "Final blocks" are the blocks after
+ * factorization: the input blocks in input order (members removed by the
+ * removal rule dropped, possibly empty) followed by singletons for DOFs left
+ * in no block; imsmg_get_patches lists them. */
+
+/* Copies the damping network's 5313 FP32 parameters (host) to the device:
+ * W1 (64 x 16, row-major), b1 (64), W2 (64 x 64, row-major), b2 (64),
+ * w3 (64), b3 (1); o = w3 . relu(W2 relu(W1 x + b1) + b2) + b3. */
+int imsmg_load_mlp(imsmg_ctx *ctx, const float *params, int64_t nparams);
+
+/* Features of the final blocks of level l >= 1 after imsmg_factor_patches
+ * (host, nblocks x 16 row-major; feat may be NULL to query nblocks).  Needs
+ * the element arrays with elem and eta.  For final block j with input block
+ * B (the block itself for added singletons), support S = union of the
+ * active elements of B's members, K = (2p+1)^d, E = (p+1)^d, p = reach:
+ *   0 |j| / K            1 |B| / K            2 |S| / E
+ *   3 sum_S eta / E      4 log10(max(min_S eta, 1e-16)) / 16
+ *   5 mean over cut elements of S (eta < 1 - 1e-12) of log10(max(eta, 1e-16)) / 16 (0 if none)
+ *   6 max_S N_K / E      7 mean_S N_K / E
+ *   8 log10(lambda_max / lambda_min) / 16 of the final block (0 below size 2)
+ *   9 log10(max(lambda_min / max diag, 1e-30)) / 16 of the input block
+ *  10 (|B| - |j|) / K (0 for added singletons)
+ *  11 fraction of j's functions with a cut element in their support
+ *  12-14 offset per axis of the eta-weighted mean element index of S from its
+ *        unweighted mean, / (p + 1) (0 on unused axes)
+ *  15 l / (nlevels - 1) */
+int imsmg_get_patch_features(imsmg_ctx *ctx, int level, int32_t *nblocks, float *feat);
+
+/* Current weight of every final block of level l (host, may be NULL),
+ * learned_status 1 = network weights accepted, -1 = rejected by the stability
+ * check (gamma used), 0 = gamma or given weights; lambda_max = the stability
+ * check's estimate (0 if it did not run).  Pointers other than nblocks may be NULL. */
+int imsmg_get_patch_weights(imsmg_ctx *ctx, int level, int32_t *nblocks, double *omega, int32_t *learned_status,
+                            double *lambda_max);
+
+/* Replaces the weights of the final blocks of level l (host, nblocks, > 0)
+ * of a factorized hierarchy without refactorizing (no stability check). */
+int imsmg_set_block_weights(imsmg_ctx *ctx, int level, const double *omega);
+
+/* Power-iteration estimate (iters steps, Rayleigh quotient in the A inner
+ * product, increasing towards the limit) of lambda_max(S A_l), level l >= 1. */
+int imsmg_lambda_max(imsmg_ctx *ctx, int level, int iters, double *lambda_max);
+
+/* Two-grid objective of a factorized TWO-level hierarchy (level 1 smoothed,
+ * level 0 solved exactly), with the current weights of level 1:
+ *   E = (I - S A)(I - R^T A_0^{-1} R A)(I - S A)   (eq:eigenMulti, one smoothing step each side),
+ *   J = ||E^k Z||_F^2 / ||Z||_F^2,
+ * Z: host, n_1 x m column-major (compact level-1 numbering).  grad (host,
+ * nblocks final blocks of level 1, may be NULL) receives dJ/domega_j by the
+ * adjoint recursion.  FP64 throughout. */
+int imsmg_two_grid_objective(imsmg_ctx *ctx, int m, const double *Z, int k, double *J, double *grad);
+
+/* Stand-alone network kernels (device pointers, ordered on `stream`, a
+ * hipStream_t or NULL; asynchronous).  X: n x 16 row-major FP32.
+ *   forward:   out[i] = o(X_i)
+ *   loss_grad: loss = mean_i (o(X_i) - t_i)^2 and its gradient (5313), with a
+ *              caller-owned device workspace of imsmg_mlp_workspace_bytes(n) bytes
+ *              (sums in a fixed order: deterministic)
+ *   adam:      one Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected; step >= 1)
+ * Return IMSMG_ERR_INVALID_ARG on bad arguments, IMSMG_ERR_HIP on a launch error. */
+int64_t imsmg_mlp_workspace_bytes(int n);
+int imsmg_mlp_forward(void *stream, const float *params, const float *X, int n, float *out);
+int imsmg_mlp_loss_grad(void *stream, const float *params, const float *X, const float *t, int n, void *work,
+                        float *loss, float *grad);
+int imsmg_mlp_adam(void *stream, float *params, const float *grad, float *m, float *v, int step, float lr);
 
 /* Post-removal blocks of level l: sizes first (ptr may be NULL to query). */
 int imsmg_get_patches(imsmg_ctx *ctx, int level, int32_t *nblocks, int64_t *nnz, int32_t *ptr, int32_t *idx);

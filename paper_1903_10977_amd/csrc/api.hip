@@ -92,8 +92,35 @@ struct Level {
   int32_t *grow_lat = nullptr, *sptr = nullptr, *scol = nullptr;
   double *sval = nullptr;             // S_G = sum_j omega_j P_j A_j^{-1} P_j^T on the general rows (CSR)
   double gamma = 0.0;
-  // elements (host)
-  std::vector<int32_t> e_ptr, e_idx;
+  // elements (host): incidence, lattice index (x fastest over el_shape) and
+  // volume fraction |K cap Omega| / |K| of every active element
+  std::vector<int32_t> e_ptr, e_idx, el_lat;
+  int el_shape[3] = {0, 0, 0};
+  std::vector<double> el_eta;
+  // factorization bookkeeping kept for the per-block damping
+  std::vector<int32_t> f_orig;   // input block of every final block (-1: added singleton)
+  std::vector<double> f_lam;     // per final block: input lambda_min, input max diag, final lambda_min, lambda_max
+  std::vector<int32_t> nk;       // N_K per active element (final blocks)
+  std::vector<double> f_w;       // damping weight of every final block
+  int learned_status = 0;        // 0: gamma / given weights, 1: learned weights accepted, -1: rejected
+  double lambda_max = 0.0;       // estimate of lambda_max(S A) from the stability check (0: not run)
+  // weight-dependent smoother data (device, factorization lifetime)
+  double *inv = nullptr;         // block inverses, general blocks scaled by their folded weight
+  int nbg = 0;
+  std::vector<int32_t> g_blocks; // final block of every general block
+  std::vector<double> g_wcur;    // weight folded into each general block's inverse
+  int64_t *g_off = nullptr;
+  int32_t *g_sz = nullptr;
+  int32_t *asm_gp = nullptr, *asm_en = nullptr, *asm_epos = nullptr;
+  int64_t *asm_eoff = nullptr, *asm_epos0 = nullptr;
+  size_t sg_nnz = 0;
+  int32_t *tb = nullptr;         // trivial block of every row (-1: none)
+  double *bw = nullptr;          // weight per final block (device)
+  // final blocks for bilinear forms: members' lattice positions, inverse offset
+  // (-1: singleton without a stored inverse, read 1 / A_ii), folded weight
+  int32_t *b_ptr = nullptr, *b_lat = nullptr;
+  int64_t *b_off = nullptr;
+  double *b_diag = nullptr, *b_wfold = nullptr;
   // coarsest level
   double *Ainv = nullptr;
 };
@@ -111,6 +138,7 @@ struct imsmg_ctx {
   imsmg_options opt{};
   bool ready = false, factored = false;
   int32_t *zero_flag = nullptr;   // always 0: "not done" for stand-alone calls
+  float *mlp = nullptr;           // damping network parameters (device, kMlpParams), or null
   CGState *st = nullptr;
   double *part = nullptr;
   double *p = nullptr, *q = nullptr, *xs = nullptr, *bs = nullptr;  // CG vectors (padded)
@@ -606,6 +634,8 @@ void collect_timing(imsmg_ctx *c) {
 }
 
 // ------------------------------------------------------------- factorization
+void apply_weights(imsmg_ctx *c, Level &L, const std::vector<double> &w);
+
 void factor_level(imsmg_ctx *c, int l) {
   hipStream_t s = c->stream;
   Level &L = c->lv[l];
@@ -649,7 +679,7 @@ void factor_level(imsmg_ctx *c, int l) {
   int64_t *d_invoff = dalloc<int64_t>(c->factor_owned, nf + 1);
   double *d_inv = dalloc<double>(c->factor_owned, size_t(h_invoff[nf]));
   uint8_t *d_keep = dalloc<uint8_t>(tmp, h_blat.size());
-  double *d_lam = dalloc<double>(tmp, 2 * size_t(nf));
+  double *d_lam = dalloc<double>(tmp, 4 * size_t(std::max(nf, 1)));
   int32_t *d_info = dalloc<int32_t>(tmp, nf);
   h2d(s, d_bstart, h_bstart.data(), nf + 1);
   h2d(s, d_bsize, h_bsize.data(), nf);
@@ -664,6 +694,10 @@ void factor_level(imsmg_ctx *c, int l) {
   std::vector<int32_t> info(nf);
   d2h(s, keep.data(), d_keep, keep.size());
   d2h(s, info.data(), d_info, info.size());
+  std::vector<double> lam(4 * size_t(nf));
+  d2h(s, lam.data(), d_lam, lam.size());
+  std::vector<double> diag(n);
+  d2h(s, diag.data(), L.val + size_t(L.center) * n, n);
   HIP_CHECK_RET(hipStreamSynchronize(s));
   // diagonal of A for singleton checks
   // final block lists: kept members of every input block, then singletons
@@ -705,13 +739,30 @@ void factor_level(imsmg_ctx *c, int l) {
   L.f_ptr = fptr;
   L.f_idx = fidx;
   const int nbf = int(fptr.size()) - 1;
+  L.f_orig = forig;
+  L.f_lam.assign(4 * size_t(nbf), 1.0);
+  {
+    int tt = 0;
+    for (int j = 0; j < nbf; ++j) {
+      const int jo = forig[j];
+      const int szin = jo >= 0 ? L.in_ptr[jo + 1] - L.in_ptr[jo] : 1;
+      if (jo >= 0 && szin >= 2) {
+        for (int q = 0; q < 4; ++q) L.f_lam[4 * size_t(j) + q] = lam[4 * size_t(tt) + q];
+        ++tt;
+      } else if (fptr[j + 1] > fptr[j]) {
+        const double d = diag[fidx[fptr[j]]];
+        for (int q = 0; q < 4; ++q) L.f_lam[4 * size_t(j) + q] = d;
+      }
+    }
+  }
   // number of final blocks holding each DOF
   std::vector<int32_t> fcount(n, 0);
   for (int32_t i : fidx) fcount[i]++;
   // N_K -> gamma
   double gamma = c->opt.gamma;
-  if (gamma <= 0.0) {
-    if (L.e_ptr.empty()) bad("gamma <= 0 needs the element incidence of every smoothed level");
+  if (gamma <= 0.0 && L.e_ptr.empty()) bad("gamma <= 0 needs the element incidence of every smoothed level");
+  L.nk.clear();
+  if (!L.e_ptr.empty()) {
     std::vector<int32_t> fp(n + 1, 0), fb(fidx.size());
     for (int32_t i : fidx) fp[i + 1]++;
     for (int i = 0; i < n; ++i) fp[i + 1] += fp[i];
@@ -737,7 +788,8 @@ void factor_level(imsmg_ctx *c, int l) {
     if (ovf) bad("N_K count overflow (more than 128 blocks touch one element)");
     int mx = 1;
     for (int v : nk) mx = std::max(mx, v);
-    gamma = 1.0 / mx;
+    if (gamma <= 0.0) gamma = 1.0 / mx;
+    L.nk = nk;
   }
   L.gamma = gamma;
   // per final block weight
@@ -807,18 +859,15 @@ void factor_level(imsmg_ctx *c, int l) {
     h2d(s, inv + h_invoff[nf], tail.data(), tail.size());
     HIP_CHECK_RET(hipStreamSynchronize(s));
   }
-  // fold the damping weight into each general block's inverse
-  {
-    int64_t *d_off = dalloc<int64_t>(tmp, std::max(nbg, 1));
-    int32_t *d_sz = dalloc<int32_t>(tmp, std::max(nbg, 1));
-    double *d_gw = dalloc<double>(tmp, std::max(nbg, 1));
-    h2d(s, d_off, g_invoff.data(), nbg);
-    h2d(s, d_sz, g_size.data(), nbg);
-    h2d(s, d_gw, g_w.data(), nbg);
-    launch_scale_blocks(s, nbg, d_off, d_sz, d_gw, inv);
-    HIP_CHECK_RET(hipGetLastError());
-    HIP_CHECK_RET(hipStreamSynchronize(s));
-  }
+  // weight-dependent part (folding into the inverses, S_G, c): apply_weights
+  L.inv = inv;
+  L.nbg = nbg;
+  L.g_blocks = g_blocks;
+  L.g_wcur.assign(nbg, 1.0);
+  L.g_off = dalloc<int64_t>(c->factor_owned, std::max(nbg, 1));
+  L.g_sz = dalloc<int32_t>(c->factor_owned, std::max(nbg, 1));
+  h2d(s, L.g_off, g_invoff.data(), nbg);
+  h2d(s, L.g_sz, g_size.data(), nbg);
   // per general row its entries (row a of block j): inverse row offset and
   // block size; the CSR pattern of S_G is the union of the row's block members
   std::vector<int32_t> cnt(n, 0);
@@ -888,33 +937,348 @@ void factor_level(imsmg_ctx *c, int l) {
   h2d(s, L.sptr, sp.data(), sp.size());
   h2d(s, L.scol, scol.data(), scol.size());
   h2d(s, L.meta, L.h_meta.data(), L.h_meta.size());
-  HIP_CHECK_RET(hipMemsetAsync(L.sval, 0, std::max<size_t>(scol.size(), 1) * sizeof(double), s));
-  {
-    int32_t *d_gp = dalloc<int32_t>(tmp, gp.size()), *d_en = dalloc<int32_t>(tmp, std::max<size_t>(e_n.size(), 1));
-    int32_t *d_epos = dalloc<int32_t>(tmp, std::max<size_t>(epos.size(), 1));
-    int64_t *d_eoff = dalloc<int64_t>(tmp, std::max<size_t>(e_off.size(), 1));
-    int64_t *d_epos0 = dalloc<int64_t>(tmp, std::max<size_t>(e_pos.size(), 1));
-    h2d(s, d_gp, gp.data(), gp.size());
-    h2d(s, d_en, e_n.data(), e_n.size());
-    h2d(s, d_epos, epos.data(), epos.size());
-    h2d(s, d_eoff, e_off.data(), e_off.size());
-    h2d(s, d_epos0, e_pos.data(), e_pos.size());
-    launch_assemble_sg(s, ngr, d_gp, d_eoff, d_en, d_epos0, d_epos, inv, L.sval);
-    HIP_CHECK_RET(hipGetLastError());
-    HIP_CHECK_RET(hipStreamSynchronize(s));
-  }
-  // trivial rows: c_i = w_j / A_ii
+  L.sg_nnz = std::max<size_t>(scol.size(), 1);
+  L.asm_gp = dalloc<int32_t>(c->factor_owned, gp.size());
+  L.asm_en = dalloc<int32_t>(c->factor_owned, std::max<size_t>(e_n.size(), 1));
+  L.asm_epos = dalloc<int32_t>(c->factor_owned, std::max<size_t>(epos.size(), 1));
+  L.asm_eoff = dalloc<int64_t>(c->factor_owned, std::max<size_t>(e_off.size(), 1));
+  L.asm_epos0 = dalloc<int64_t>(c->factor_owned, std::max<size_t>(e_pos.size(), 1));
+  h2d(s, L.asm_gp, gp.data(), gp.size());
+  h2d(s, L.asm_en, e_n.data(), e_n.size());
+  h2d(s, L.asm_epos, epos.data(), epos.size());
+  h2d(s, L.asm_eoff, e_off.data(), e_off.size());
+  h2d(s, L.asm_epos0, e_pos.data(), e_pos.size());
+  HIP_CHECK_RET(hipStreamSynchronize(s));
+  // trivial rows: c_i = w_j / A_ii (apply_weights)
   std::vector<int32_t> tb(n, -1);
   for (int i = 0; i < n; ++i)
     if (trivial[i] >= 0) tb[i] = trivial[i];
-  int32_t *d_tb = dalloc<int32_t>(tmp, n);
-  double *d_w = dalloc<double>(tmp, nbf);
-  h2d(s, d_tb, tb.data(), n);
-  h2d(s, d_w, w.data(), nbf);
+  L.tb = dalloc<int32_t>(c->factor_owned, n);
+  L.bw = dalloc<double>(c->factor_owned, std::max(nbf, 1));
+  h2d(s, L.tb, tb.data(), n);
   L.c = dalloc<double>(c->factor_owned, n);
-  launch_diag_coef(s, n, L.K, L.center, d_tb, L.val, d_w, L.c);
+  // final blocks for bilinear forms
+  {
+    std::vector<int32_t> blat(fidx.size());
+    for (size_t k = 0; k < fidx.size(); ++k) blat[k] = L.h_row_lat[fidx[k]];
+    std::vector<int64_t> boff(nbf, -1);
+    std::vector<double> bdiag(nbf, 0.0);
+    for (int q = 0; q < nbg; ++q) boff[g_blocks[q]] = g_invoff[q];
+    for (int j = 0; j < nbf; ++j)
+      if (fptr[j + 1] - fptr[j] == 1) bdiag[j] = 1.0 / diag[fidx[fptr[j]]];
+    L.b_ptr = dalloc<int32_t>(c->factor_owned, fptr.size());
+    L.b_lat = dalloc<int32_t>(c->factor_owned, std::max<size_t>(blat.size(), 1));
+    L.b_off = dalloc<int64_t>(c->factor_owned, std::max(nbf, 1));
+    L.b_diag = dalloc<double>(c->factor_owned, std::max(nbf, 1));
+    L.b_wfold = dalloc<double>(c->factor_owned, std::max(nbf, 1));
+    h2d(s, L.b_ptr, fptr.data(), fptr.size());
+    h2d(s, L.b_lat, blat.data(), blat.size());
+    h2d(s, L.b_off, boff.data(), nbf);
+    h2d(s, L.b_diag, bdiag.data(), nbf);
+    HIP_CHECK_RET(hipStreamSynchronize(s));
+  }
+  L.learned_status = 0;
+  L.lambda_max = 0.0;
+  apply_weights(c, L, w);
+}
+
+// Folds per-final-block weights w into the smoother: rescales the stored
+// general-block inverses from their folded weights to w, re-assembles S_G and
+// the trivial-row coefficients c_i = w_j / A_ii.
+void apply_weights(imsmg_ctx *c, Level &L, const std::vector<double> &w) {
+  hipStream_t s = c->stream;
+  const int nbf = int(L.f_ptr.size()) - 1;
+  if (int(w.size()) != nbf) bad("internal: weight count mismatch", IMSMG_ERR_HIP);
+  std::vector<void *> tmp;
+  struct TmpFree {
+    std::vector<void *> &v;
+    ~TmpFree() { free_list(v); }
+  } tf{tmp};
+  std::vector<double> ratio(std::max(L.nbg, 1), 1.0), wfold(std::max(nbf, 1), 1.0);
+  for (int q = 0; q < L.nbg; ++q) {
+    const int j = L.g_blocks[q];
+    ratio[q] = w[j] / L.g_wcur[q];
+    L.g_wcur[q] = w[j];
+    wfold[j] = w[j];
+  }
+  double *d_ratio = dalloc<double>(tmp, ratio.size());
+  h2d(s, d_ratio, ratio.data(), ratio.size());
+  launch_scale_blocks(s, L.nbg, L.g_off, L.g_sz, d_ratio, L.inv);
+  HIP_CHECK_RET(hipMemsetAsync(L.sval, 0, L.sg_nnz * sizeof(double), s));
+  launch_assemble_sg(s, L.ng, L.asm_gp, L.asm_eoff, L.asm_en, L.asm_epos0, L.asm_epos, L.inv, L.sval);
+  h2d(s, L.bw, w.data(), nbf);
+  launch_diag_coef(s, L.n, L.K, L.center, L.tb, L.val, L.bw, L.c);
+  h2d(s, L.b_wfold, wfold.data(), nbf);
   HIP_CHECK_RET(hipGetLastError());
   HIP_CHECK_RET(hipStreamSynchronize(s));
+  L.f_w = w;
+}
+
+// ------------------------------------------------------------ per-block damping
+// Sixteen scale-free features per final block (the network's inputs); see
+// the feature list in include/imsmg.h.
+std::vector<float> block_features(imsmg_ctx *c, int l) {
+  Level &L = c->lv[l];
+  if (L.e_ptr.empty() || L.el_lat.empty() || L.nk.empty())
+    bad("block features need the element incidence, element lattice indices and volume fractions");
+  const int n = L.n, d = L.dim, p = L.reach;
+  const int nbf = int(L.f_ptr.size()) - 1;
+  const double K = std::pow(2.0 * p + 1.0, d), E = std::pow(p + 1.0, d);
+  const int nel = int(L.e_ptr.size()) - 1;
+  constexpr double kCut = 1.0 - 1e-12;
+  // function -> active elements (ascending)
+  std::vector<int32_t> fp(n + 1, 0), fe(L.e_idx.size());
+  for (int32_t f : L.e_idx) fp[f + 1]++;
+  for (int i = 0; i < n; ++i) fp[i + 1] += fp[i];
+  {
+    std::vector<int32_t> fill(fp.begin(), fp.end() - 1);
+    for (int e = 0; e < nel; ++e)
+      for (int k = L.e_ptr[e]; k < L.e_ptr[e + 1]; ++k) fe[fill[L.e_idx[k]]++] = e;
+  }
+  std::vector<char> cut_fn(n, 0);
+  for (int i = 0; i < n; ++i)
+    for (int k = fp[i]; k < fp[i + 1]; ++k)
+      if (L.el_eta[fe[k]] < kCut) cut_fn[i] = 1;
+  const int finest = int(c->lv.size()) - 1;
+  std::vector<float> F(size_t(nbf) * kMlpInputs, 0.0f);
+  std::vector<int32_t> S;
+  for (int j = 0; j < nbf; ++j) {
+    const int jo = L.f_orig[j];
+    const int32_t *raw = jo >= 0 ? L.in_idx.data() + L.in_ptr[jo] : L.f_idx.data() + L.f_ptr[j];
+    const int nraw = jo >= 0 ? L.in_ptr[jo + 1] - L.in_ptr[jo] : L.f_ptr[j + 1] - L.f_ptr[j];
+    const int nfin = L.f_ptr[j + 1] - L.f_ptr[j];
+    S.clear();
+    for (int a = 0; a < nraw; ++a)
+      for (int k = fp[raw[a]]; k < fp[raw[a] + 1]; ++k) S.push_back(fe[k]);
+    std::sort(S.begin(), S.end());
+    S.erase(std::unique(S.begin(), S.end()), S.end());
+    double f[kMlpInputs] = {0.0};
+    double sum_eta = 0.0, min_eta = 2.0, sum_log_cut = 0.0, nk_max = 0.0, nk_sum = 0.0;
+    double cw[3] = {0, 0, 0}, cu[3] = {0, 0, 0};
+    int ncut = 0;
+    for (int e : S) {
+      const double et = L.el_eta[e];
+      sum_eta += et;
+      min_eta = std::min(min_eta, et);
+      if (et < kCut) {
+        sum_log_cut += std::log10(std::max(et, 1e-16));
+        ++ncut;
+      }
+      nk_max = std::max(nk_max, double(L.nk[e]));
+      nk_sum += L.nk[e];
+      int64_t r = L.el_lat[e];
+      for (int a = 0; a < d; ++a) {
+        const double m = double(r % L.el_shape[a]);
+        r /= L.el_shape[a];
+        cw[a] += et * m;
+        cu[a] += m;
+      }
+    }
+    const double ns = double(S.size());
+    f[0] = nfin / K;
+    f[1] = nraw / K;
+    f[2] = ns / E;
+    f[3] = sum_eta / E;
+    f[4] = S.empty() ? 0.0 : std::log10(std::max(min_eta, 1e-16)) / 16.0;
+    f[5] = ncut ? sum_log_cut / ncut / 16.0 : 0.0;
+    f[6] = nk_max / E;
+    f[7] = S.empty() ? 0.0 : nk_sum / ns / E;
+    const double *lam = L.f_lam.data() + 4 * size_t(j);
+    if (nfin >= 2) f[8] = std::log10(lam[3] / lam[2]) / 16.0;
+    f[9] = std::log10(std::max(lam[0] / lam[1], 1e-30)) / 16.0;
+    f[10] = jo >= 0 ? (nraw - nfin) / K : 0.0;
+    if (nfin > 0) {
+      int nc = 0;
+      for (int k = L.f_ptr[j]; k < L.f_ptr[j + 1]; ++k) nc += cut_fn[L.f_idx[k]];
+      f[11] = double(nc) / nfin;
+    }
+    if (sum_eta > 0.0)
+      for (int a = 0; a < d; ++a) f[12 + a] = (cw[a] / sum_eta - cu[a] / ns) / (p + 1);
+    f[15] = double(l) / finest;
+    for (int q = 0; q < kMlpInputs; ++q) F[size_t(j) * kMlpInputs + q] = float(f[q]);
+  }
+  return F;
+}
+
+double host_dot(imsmg_ctx *c, Level &L, const double *a, const double *b, double *part) {
+  launch_dot_partial(c->stream, L.n, L.row_lat, a, b, part);
+  std::vector<double> h(dot_blocks(L.n));
+  d2h(c->stream, h.data(), part, h.size());
+  HIP_CHECK_RET(hipStreamSynchronize(c->stream));
+  double acc = 0.0;
+  for (double v : h) acc += v;
+  return acc;
+}
+
+// y = S x on level L (current weights); y and x padded
+void apply_S(imsmg_ctx *c, Level &L, const double *x, double *y) {
+  launch_diag_scale(c->stream, L.n, L.row_lat, L.c, x, y, c->zero_flag);
+  launch_smooth_general(c->stream, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, x, y, c->zero_flag);
+}
+
+// y = A x on level L in FP64 (y, x padded)
+void apply_A64(imsmg_ctx *c, Level &L, const double *x, double *y) {
+  launch_residual(c->stream, L.n, L.K, L.op64, L.row_lat, L.meta, x, nullptr, y, c->zero_flag);
+}
+
+// Power iteration for lambda_max(S A) with the Rayleigh quotient in the A
+// inner product, (A v . S A v) / (A v . v), which increases towards it.
+double lambda_max_SA(imsmg_ctx *c, Level &L, int iters) {
+  std::vector<void *> tmp;
+  struct TmpFree {
+    std::vector<void *> &v;
+    ~TmpFree() { free_list(v); }
+  } tf{tmp};
+  double *part = dalloc<double>(tmp, dot_blocks(L.n));
+  std::vector<double> v0(L.n);
+  for (int i = 0; i < L.n; ++i) v0[i] = 1.0 + 0.5 * std::sin(0.7 * i + 0.3) + 0.25 * std::cos(1.9 * i);
+  double *dv = dalloc<double>(tmp, L.n);
+  h2d(c->stream, dv, v0.data(), L.n);
+  launch_scatter(c->stream, L.n, L.row_lat, dv, L.x);
+  double lam = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    apply_A64(c, L, L.x, L.rh);
+    apply_S(c, L, L.rh, L.x2);
+    const double ut = host_dot(c, L, L.rh, L.x2, part);
+    const double uv = host_dot(c, L, L.rh, L.x, part);
+    const double tt = host_dot(c, L, L.x2, L.x2, part);
+    if (!(uv > 0.0) || !(tt > 0.0)) bad("stability check: operator not positive", IMSMG_ERR_NOT_SPD);
+    lam = ut / uv;
+    launch_scale_copy(c->stream, L.n, L.row_lat, 1.0 / std::sqrt(tt), L.x2, L.x);
+  }
+  HIP_CHECK_RET(hipGetLastError());
+  return lam;
+}
+
+// Weights of level l from the damping network, omega_j = gamma exp(clip(o_j)),
+// kept only if lambda_max(S_omega A) < 2 (1 - 0.05); otherwise gamma again.
+void learned_weights(imsmg_ctx *c, int l) {
+  Level &L = c->lv[l];
+  if (!c->mlp) bad("use_learned needs the damping network (imsmg_load_mlp)", IMSMG_ERR_STATE);
+  std::vector<float> F = block_features(c, l);
+  const int nbf = int(L.f_ptr.size()) - 1;
+  std::vector<void *> tmp;
+  struct TmpFree {
+    std::vector<void *> &v;
+    ~TmpFree() { free_list(v); }
+  } tf{tmp};
+  float *dX = dalloc<float>(tmp, F.size()), *dout = dalloc<float>(tmp, std::max(nbf, 1));
+  h2d(c->stream, dX, F.data(), F.size());
+  launch_mlp_forward(c->stream, nbf, c->mlp, dX, dout);
+  std::vector<float> o(nbf);
+  d2h(c->stream, o.data(), dout, nbf);
+  HIP_CHECK_RET(hipStreamSynchronize(c->stream));
+  std::vector<double> w(nbf);
+  for (int j = 0; j < nbf; ++j) {
+    if (!std::isfinite(o[j])) bad("damping network produced a non-finite output", IMSMG_ERR_NAN);
+    w[j] = L.gamma * std::exp(std::min(std::max(double(o[j]), -kMlpOutClip), kMlpOutClip));
+  }
+  apply_weights(c, L, w);
+  L.lambda_max = lambda_max_SA(c, L, 60);
+  if (L.lambda_max < 2.0 * (1.0 - 0.05)) {
+    L.learned_status = 1;
+  } else {
+    L.learned_status = -1;
+    apply_weights(c, L, std::vector<double>(nbf, L.gamma));
+  }
+}
+
+bool L_has_no_user_weights(const Level &L) { return L.omega.empty(); }
+
+// Two-grid objective of level 1 of a two-level hierarchy (see imsmg.h).
+void two_grid(imsmg_ctx *c, int m, const double *Z, int k, double *J, double *grad) {
+  if (c->lv.size() != 2) bad("the two-grid objective needs a two-level hierarchy");
+  if (m < 1 || k < 1 || !Z || !J) bad("bad two-grid arguments");
+  Level &L = c->lv[1], &C0 = c->lv[0];
+  hipStream_t s = c->stream;
+  const int n = L.n, nbf = int(L.f_ptr.size()) - 1;
+  std::vector<void *> tmp;
+  struct TmpFree {
+    std::vector<void *> &v;
+    ~TmpFree() { free_list(v); }
+  } tf{tmp};
+  const size_t vlen = size_t(L.lattice + 2 * L.guard), clen = size_t(C0.lattice + 2 * C0.guard);
+  auto vec = [&](size_t len, int64_t guard) {
+    double *b = dalloc<double>(tmp, len);
+    HIP_CHECK_RET(hipMemsetAsync(b, 0, len * sizeof(double), s));
+    return b + guard;
+  };
+  // a_t = X_{t-1} and c_t = C M a_t for t = 1..k, plus work vectors
+  std::vector<double *> av(k + 1), cv(k + 1);
+  for (int t = 0; t <= k; ++t) {
+    av[t] = vec(vlen, L.guard);
+    cv[t] = vec(vlen, L.guard);
+  }
+  double *u = vec(vlen, L.guard), *w1 = vec(vlen, L.guard), *lam = vec(vlen, L.guard);
+  double *nu = vec(vlen, L.guard), *mu = vec(vlen, L.guard);
+  double *rc = vec(clen, C0.guard), *xc = vec(clen, C0.guard);
+  double *part = dalloc<double>(tmp, dot_blocks(n));
+  double *dz = dalloc<double>(tmp, n);
+  double *dg = dalloc<double>(tmp, std::max(nbf, 1));
+  HIP_CHECK_RET(hipMemsetAsync(dg, 0, std::max(nbf, 1) * sizeof(double), s));
+  double nz = 0.0;
+  for (size_t q = 0; q < size_t(n) * m; ++q) nz += Z[q] * Z[q];
+  if (!(nz > 0.0)) bad("Z must not vanish");
+  // y = (I - S A) x
+  auto smooth = [&](const double *x, double *y) {
+    apply_A64(c, L, x, u);
+    apply_S(c, L, u, y);
+    launch_sub_from(s, n, L.row_lat, x, y);
+  };
+  // y = x - R^T A_0^{-1} R A x   (C)
+  auto coarse = [&](const double *x, double *y) {
+    apply_A64(c, L, x, u);
+    restrict_to(c, L, C0, u, rc, nullptr, c->zero_flag);
+    launch_dense_gemv(s, C0.n, C0.row_lat, C0.Ainv, rc, xc, c->zero_flag);
+    launch_scale_copy(s, n, L.row_lat, 0.0, x, y);
+    prolong_add(c, L, C0, xc, y, c->zero_flag);
+    launch_sub_from(s, n, L.row_lat, x, y);
+  };
+  // y = x - A S x   ((I - S A)^T)
+  auto smooth_t = [&](const double *x, double *y) {
+    apply_S(c, L, x, u);
+    apply_A64(c, L, u, y);
+    launch_sub_from(s, n, L.row_lat, x, y);
+  };
+  // y = x - A R^T A_0^{-1} R x   (C^T)
+  auto coarse_t = [&](const double *x, double *y) {
+    restrict_to(c, L, C0, x, rc, nullptr, c->zero_flag);
+    launch_dense_gemv(s, C0.n, C0.row_lat, C0.Ainv, rc, xc, c->zero_flag);
+    launch_scale_copy(s, n, L.row_lat, 0.0, x, w1);
+    prolong_add(c, L, C0, xc, w1, c->zero_flag);
+    apply_A64(c, L, w1, y);
+    launch_sub_from(s, n, L.row_lat, x, y);
+  };
+  double num = 0.0;
+  for (int col = 0; col < m; ++col) {
+    h2d(s, dz, Z + size_t(col) * n, n);
+    launch_scatter(s, n, L.row_lat, dz, av[0]);
+    for (int t = 1; t <= k; ++t) {
+      smooth(av[t - 1], w1);
+      coarse(w1, cv[t]);
+      smooth(cv[t], av[t]);
+    }
+    num += host_dot(c, L, av[k], av[k], part);
+    if (!grad) continue;
+    launch_scale_copy(s, n, L.row_lat, 2.0 / nz, av[k], lam);
+    for (int t = k; t >= 1; --t) {
+      // g_j -= <Lambda, A_j^{-1} (A c_t)_j> + <mu, A_j^{-1} (A a_{t-1})_j>
+      smooth_t(lam, nu);
+      coarse_t(nu, mu);
+      double *Ac = w1;
+      apply_A64(c, L, cv[t], Ac);
+      launch_block_bilinear(s, nbf, L.b_ptr, L.b_lat, L.b_off, L.b_diag, L.b_wfold, L.inv, lam, Ac, -1.0, dg);
+      apply_A64(c, L, av[t - 1], Ac);
+      launch_block_bilinear(s, nbf, L.b_ptr, L.b_lat, L.b_off, L.b_diag, L.b_wfold, L.inv, mu, Ac, -1.0, dg);
+      smooth_t(mu, lam);
+    }
+  }
+  HIP_CHECK_RET(hipGetLastError());
+  *J = num / nz;
+  if (grad) {
+    d2h(s, grad, dg, nbf);
+    HIP_CHECK_RET(hipStreamSynchronize(s));
+  }
 }
 
 void factor_coarsest(imsmg_ctx *c) {
@@ -1060,6 +1424,24 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
         L.e_idx.assign(e.eidx, e.eidx + L.e_ptr.back());
         for (int32_t f : L.e_idx)
           if (f < 0 || f >= L.n) bad("element function index out of range");
+        L.el_lat.clear();
+        L.el_eta.assign(e.nelements, 1.0);
+        if (e.elem) {
+          int64_t tot = 1;
+          for (int a = 0; a < L.dim; ++a) {
+            if (e.shape[a] < 1) bad("element shape must be positive");
+            L.el_shape[a] = e.shape[a];
+            tot *= e.shape[a];
+          }
+          L.el_lat.assign(e.elem, e.elem + e.nelements);
+          for (int32_t v : L.el_lat)
+            if (v < 0 || v >= tot) bad("element lattice index out of range");
+        }
+        if (e.eta) {
+          L.el_eta.assign(e.eta, e.eta + e.nelements);
+          for (double v : L.el_eta)
+            if (!(v >= 0.0 && v <= 1.0 + 1e-9)) bad("volume fractions must lie in [0, 1]");
+        }
       }
     }
     Level &F = c->lv.back();
@@ -1108,6 +1490,9 @@ int imsmg_factor_patches(imsmg_ctx *c) {
     c->factored = false;
     for (int l = 1; l < int(c->lv.size()); ++l) factor_level(c, l);
     factor_coarsest(c);
+    if (c->opt.use_learned)
+      for (int l = 1; l < int(c->lv.size()); ++l)
+        if (L_has_no_user_weights(c->lv[l])) learned_weights(c, l);
     c->factored = true;
     return IMSMG_OK;
   });
@@ -1327,6 +1712,99 @@ int imsmg_kernel_time(imsmg_ctx *c, double *total_ms, int64_t *launches, int res
   });
 }
 
+int imsmg_set_block_weights(imsmg_ctx *c, int level, const double *omega) {
+  return guarded(c, [&]() -> int {
+    if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    if (level < 1 || level >= int(c->lv.size()) || !omega) bad("bad level or null weights");
+    Level &L = c->lv[level];
+    const int nbf = int(L.f_ptr.size()) - 1;
+    std::vector<double> w(omega, omega + nbf);
+    for (double v : w)
+      if (!(v > 0.0) || !std::isfinite(v)) bad("weights must be positive and finite");
+    apply_weights(c, L, w);
+    L.learned_status = 0;
+    L.lambda_max = 0.0;
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_load_mlp(imsmg_ctx *c, const float *params, int64_t nparams) {
+  return guarded(c, [&]() -> int {
+    if (!params || nparams != kMlpParams) bad("the damping network has " + std::to_string(kMlpParams) + " parameters");
+    for (int64_t k = 0; k < nparams; ++k)
+      if (!std::isfinite(params[k])) bad("non-finite network parameter");
+    if (!c->mlp) HIP_CHECK_RET(hipMalloc(reinterpret_cast<void **>(&c->mlp), kMlpParams * sizeof(float)));
+    HIP_CHECK_RET(hipMemcpy(c->mlp, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice));
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_get_patch_features(imsmg_ctx *c, int level, int32_t *nblocks, float *feat) {
+  return guarded(c, [&]() -> int {
+    if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    if (level < 1 || level >= int(c->lv.size()) || !nblocks) bad("bad level or null count");
+    Level &L = c->lv[level];
+    *nblocks = int32_t(L.f_ptr.size()) - 1;
+    if (feat) {
+      std::vector<float> F = block_features(c, level);
+      std::copy(F.begin(), F.end(), feat);
+    }
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_get_patch_weights(imsmg_ctx *c, int level, int32_t *nblocks, double *omega, int32_t *learned_status,
+                            double *lambda_max) {
+  return guarded(c, [&]() -> int {
+    if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    if (level < 1 || level >= int(c->lv.size()) || !nblocks) bad("bad level or null count");
+    Level &L = c->lv[level];
+    *nblocks = int32_t(L.f_w.size());
+    if (omega) std::copy(L.f_w.begin(), L.f_w.end(), omega);
+    if (learned_status) *learned_status = L.learned_status;
+    if (lambda_max) *lambda_max = L.lambda_max;
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_lambda_max(imsmg_ctx *c, int level, int iters, double *lambda_max) {
+  return guarded(c, [&]() -> int {
+    if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    if (level < 1 || level >= int(c->lv.size()) || iters < 1 || !lambda_max) bad("bad arguments");
+    *lambda_max = lambda_max_SA(c, c->lv[level], iters);
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_two_grid_objective(imsmg_ctx *c, int m, const double *Z, int k, double *J, double *grad) {
+  return guarded(c, [&]() -> int {
+    if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    two_grid(c, m, Z, k, J, grad);
+    return IMSMG_OK;
+  });
+}
+
+int64_t imsmg_mlp_workspace_bytes(int n) { return n < 1 ? 0 : int64_t(mlp_workspace_bytes(n)); }
+
+int imsmg_mlp_forward(void *stream, const float *params, const float *X, int n, float *out) {
+  if (n < 0 || (n > 0 && (!params || !X || !out))) return IMSMG_ERR_INVALID_ARG;
+  launch_mlp_forward(static_cast<hipStream_t>(stream), n, params, X, out);
+  return hipGetLastError() == hipSuccess ? IMSMG_OK : IMSMG_ERR_HIP;
+}
+
+int imsmg_mlp_loss_grad(void *stream, const float *params, const float *X, const float *t, int n, void *work,
+                        float *loss, float *grad) {
+  if (n < 1 || !params || !X || !t || !work || !loss || !grad) return IMSMG_ERR_INVALID_ARG;
+  launch_mlp_loss_grad(static_cast<hipStream_t>(stream), n, params, X, t, work, loss, grad);
+  return hipGetLastError() == hipSuccess ? IMSMG_OK : IMSMG_ERR_HIP;
+}
+
+int imsmg_mlp_adam(void *stream, float *params, const float *grad, float *m, float *v, int step, float lr) {
+  if (!params || !grad || !m || !v || step < 1 || !(lr > 0.0f)) return IMSMG_ERR_INVALID_ARG;
+  launch_mlp_adam(static_cast<hipStream_t>(stream), params, grad, m, v, step, lr);
+  return hipGetLastError() == hipSuccess ? IMSMG_OK : IMSMG_ERR_HIP;
+}
+
 const char *imsmg_last_error(imsmg_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 int imsmg_destroy(imsmg_ctx *c) {
@@ -1337,6 +1815,7 @@ int imsmg_destroy(imsmg_ctx *c) {
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   free_list(c->factor_owned);
   free_list(c->owned);
+  if (c->mlp) (void)hipFree(c->mlp);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return IMSMG_OK;

@@ -168,8 +168,13 @@ __global__ __launch_bounds__(kFacThreads) void k_block_factor(
         }
         removed_local = imax;
       }
-      lam_out[2 * j] = lmin;
-      lam_out[2 * j + 1] = lmax;
+      // [input block lambda_min, input block max diag, final lambda_min, final lambda_max]
+      if (round == 0) {
+        lam_out[4 * j] = lmin;
+        lam_out[4 * j + 1] = dmax_s;
+      }
+      lam_out[4 * j + 2] = lmin;
+      lam_out[4 * j + 3] = lmax;
     }
     __syncthreads();
     if (removed_local < 0) break;

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -113,6 +114,23 @@ void launch_cg_update(hipStream_t s, int n, const int32_t *row_lat, const double
 void launch_cg_true_residual(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                              const uint32_t *meta, const double *x, const double *b, double *part, CGState *st);
 int reduction_blocks(int n);
+
+// --------------------------------------------------------------- per-block damping
+constexpr int kMlpInputs = 16, kMlpHidden = 64;
+constexpr int kMlpParams = kMlpInputs * kMlpHidden + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden + kMlpHidden + 1;
+constexpr double kMlpOutClip = 3.0;  // omega_j = gamma exp(clip(o_j, -3, 3))
+size_t mlp_workspace_bytes(int n);
+void launch_mlp_forward(hipStream_t s, int n, const float *params, const float *X, float *out);
+void launch_mlp_loss_grad(hipStream_t s, int n, const float *params, const float *X, const float *t, void *work,
+                          float *loss, float *grad);
+void launch_mlp_adam(hipStream_t s, float *theta, const float *g, float *m, float *v, int step, float lr);
+void launch_block_bilinear(hipStream_t s, int nb, const int32_t *bptr, const int32_t *blat, const int64_t *boff,
+                           const double *bdiag, const double *wfold, const double *inv, const double *u,
+                           const double *v, double coef, double *out);
+int dot_blocks(int n);
+void launch_dot_partial(hipStream_t s, int n, const int32_t *row_lat, const double *a, const double *b, double *part);
+void launch_scale_copy(hipStream_t s, int n, const int32_t *row_lat, double alpha, const double *x, double *y);
+void launch_sub_from(hipStream_t s, int n, const int32_t *row_lat, const double *x, double *y);
 
 // --------------------------------------------------------------- factorization
 int launch_block_factor_geom(hipStream_t s, int nblocks, int maxn, const int32_t *bstart, const int32_t *bsize,

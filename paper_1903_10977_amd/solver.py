@@ -34,7 +34,8 @@ class Patches(C.Structure):
 
 
 class Elements(C.Structure):
-    _fields_ = [("nelements", C.c_int32), ("eptr", C.c_void_p), ("eidx", C.c_void_p)]
+    _fields_ = [("nelements", C.c_int32), ("eptr", C.c_void_p), ("eidx", C.c_void_p), ("shape", C.c_int32 * 3),
+                ("elem", C.c_void_p), ("eta", C.c_void_p)]
 
 
 class Lattice(C.Structure):
@@ -45,7 +46,7 @@ class Lattice(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("max_iter", C.c_int32),
                 ("check_every", C.c_int32), ("use_graph", C.c_int32), ("timing", C.c_int32), ("gamma", C.c_double),
-                ("compress", C.c_int32)]
+                ("compress", C.c_int32), ("use_learned", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -61,7 +62,12 @@ class LevelStats(C.Structure):
 SYMBOLS = ["imsmg_default_options", "imsmg_create", "imsmg_setup", "imsmg_set_patch_weights",
            "imsmg_factor_patches", "imsmg_get_patches", "imsmg_get_gamma", "imsmg_vcycle", "imsmg_pcg_solve",
            "imsmg_apply_operator", "imsmg_apply_smoother", "imsmg_apply_restriction", "imsmg_apply_prolongation",
-           "imsmg_coarse_solve", "imsmg_get_level_stats", "imsmg_kernel_time", "imsmg_last_error", "imsmg_destroy"]
+           "imsmg_coarse_solve", "imsmg_get_level_stats", "imsmg_kernel_time", "imsmg_last_error", "imsmg_destroy",
+           "imsmg_load_mlp", "imsmg_get_patch_features", "imsmg_get_patch_weights", "imsmg_set_block_weights",
+           "imsmg_lambda_max", "imsmg_two_grid_objective", "imsmg_mlp_workspace_bytes", "imsmg_mlp_forward",
+           "imsmg_mlp_loss_grad", "imsmg_mlp_adam"]
+MLP_PARAMS = 5313
+NFEAT = 16
 
 
 def library_path() -> str:
@@ -99,9 +105,21 @@ def load():
     lib.imsmg_last_error.argtypes = [vp]
     lib.imsmg_last_error.restype = C.c_char_p
     lib.imsmg_destroy.argtypes = [vp]
+    lib.imsmg_load_mlp.argtypes = [vp, vp, i64]
+    lib.imsmg_get_patch_features.argtypes = [vp, i32, C.POINTER(C.c_int32), vp]
+    lib.imsmg_get_patch_weights.argtypes = [vp, i32, C.POINTER(C.c_int32), vp, C.POINTER(C.c_int32),
+                                            C.POINTER(C.c_double)]
+    lib.imsmg_set_block_weights.argtypes = [vp, i32, vp]
+    lib.imsmg_lambda_max.argtypes = [vp, i32, i32, C.POINTER(C.c_double)]
+    lib.imsmg_two_grid_objective.argtypes = [vp, i32, vp, i32, C.POINTER(C.c_double), vp]
+    lib.imsmg_mlp_workspace_bytes.argtypes = [i32]
+    lib.imsmg_mlp_forward.argtypes = [vp, vp, vp, i32, vp]
+    lib.imsmg_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
+    lib.imsmg_mlp_adam.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float]
     for s in SYMBOLS:
         if s not in ("imsmg_default_options", "imsmg_last_error"):
             getattr(lib, s).restype = C.c_int
+    lib.imsmg_mlp_workspace_bytes.restype = C.c_int64
     _lib = lib
     return lib
 
@@ -206,7 +224,16 @@ class Solver:
             if lev.elem_ptr is not None:
                 ep, ei = _i32(lev.elem_ptr), _i32(lev.elem_idx)
                 keep += [ep, ei]
-                E[l] = Elements(len(ep) - 1, _p(ep).value, _p(ei).value)
+                eshape = (C.c_int32 * 3)(*([lev.n_elements] * dim + [1] * (3 - dim)))
+                el = et = None
+                if getattr(lev, "elem_id", None) is not None:
+                    el = _i32(lev.elem_id)
+                    keep.append(el)
+                    if getattr(lev, "eta", None) is not None:
+                        et = np.ascontiguousarray(np.asarray(lev.eta, np.float64)[lev.elem_id])
+                        keep.append(et)
+                E[l] = Elements(len(ep) - 1, _p(ep).value, _p(ei).value, eshape,
+                                _p(el).value if el is not None else None, _p(et).value if et is not None else None)
         opt = options if options is not None else default_options(nu_pre=w.nu, nu_post=w.nu)
         self._check(self.lib.imsmg_setup(self.h, L, A, R, P, Lt, E, C.byref(opt)))
         self.problem = problem
@@ -229,6 +256,46 @@ class Solver:
         idx = np.zeros(nnz.value, np.int32)
         self._check(self.lib.imsmg_get_patches(self.h, level, C.byref(nb), C.byref(nnz), _p(ptr), _p(idx)))
         return ptr, idx
+
+    # ------------------------------------------------- per-block damping
+    def load_mlp(self, params):
+        th = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self.lib.imsmg_load_mlp(self.h, _p(th), th.size))
+        return self
+
+    def features(self, level: int) -> np.ndarray:
+        nb = C.c_int32()
+        self._check(self.lib.imsmg_get_patch_features(self.h, level, C.byref(nb), None))
+        F = np.zeros((nb.value, NFEAT), np.float32)
+        self._check(self.lib.imsmg_get_patch_features(self.h, level, C.byref(nb), _p(F)))
+        return F
+
+    def weights(self, level: int):
+        """(omega per final block, learned_status, lambda_max estimate)"""
+        nb, st, lm = C.c_int32(), C.c_int32(), C.c_double()
+        self._check(self.lib.imsmg_get_patch_weights(self.h, level, C.byref(nb), None, None, None))
+        om = np.zeros(nb.value, np.float64)
+        self._check(self.lib.imsmg_get_patch_weights(self.h, level, C.byref(nb), _p(om), C.byref(st), C.byref(lm)))
+        return om, st.value, lm.value
+
+    def set_block_weights(self, level: int, omega):
+        om = np.ascontiguousarray(omega, dtype=np.float64)
+        self._check(self.lib.imsmg_set_block_weights(self.h, level, _p(om)))
+
+    def lambda_max(self, level: int, iters: int = 60) -> float:
+        lm = C.c_double()
+        self._check(self.lib.imsmg_lambda_max(self.h, level, iters, C.byref(lm)))
+        return lm.value
+
+    def two_grid_objective(self, Z, k: int = 1, grad: bool = True):
+        """J and dJ/domega (final blocks of level 1) of a two-level hierarchy;
+        Z: (n_1, m) host array."""
+        Zc = np.asfortranarray(np.asarray(Z, np.float64).reshape(self._n(1), -1))
+        J = C.c_double()
+        g = np.zeros(len(self.weights(1)[0]), np.float64) if grad else None
+        self._check(self.lib.imsmg_two_grid_objective(self.h, Zc.shape[1], Zc.ctypes.data_as(C.c_void_p), k,
+                                                      C.byref(J), _p(g) if grad else None))
+        return (J.value, g) if grad else J.value
 
     def gamma(self, level: int) -> float:
         g = C.c_double()
@@ -303,3 +370,61 @@ class Solver:
         n = C.c_int64()
         self._check(self.lib.imsmg_kernel_time(self.h, C.byref(ms), C.byref(n), 1 if reset else 0))
         return ms.value, n.value
+
+
+# ------------------------------------------------------ damping network kernels
+def _stream(torch):
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def mlp_forward(params, X):
+    """o for every row of X (torch float32 device tensors; params: 5313)."""
+    import torch
+    lib = load()
+    assert params.dtype == torch.float32 and X.dtype == torch.float32 and params.numel() == MLP_PARAMS
+    X = X.contiguous()
+    out = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    rc = lib.imsmg_mlp_forward(_stream(torch), C.c_void_p(params.data_ptr()), C.c_void_p(X.data_ptr()),
+                               X.shape[0], C.c_void_p(out.data_ptr()))
+    if rc != OK:
+        raise SolverError(rc, "imsmg_mlp_forward")
+    return out
+
+
+class MlpTrainer:
+    """Device-side training state of the damping network: parameters, Adam
+    moments and the loss-gradient workspace (all torch float32 tensors)."""
+
+    def __init__(self, params, n):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        dev = params.device
+        self.params = params.clone().contiguous()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.n = n
+        self.work = torch.empty(int(self.lib.imsmg_mlp_workspace_bytes(n)), dtype=torch.uint8, device=dev)
+        self.step_count = 0
+
+    def loss_grad(self, X, t):
+        assert X.shape == (self.n, NFEAT) and t.shape == (self.n,)
+        rc = self.lib.imsmg_mlp_loss_grad(_stream(self.torch), C.c_void_p(self.params.data_ptr()),
+                                          C.c_void_p(X.data_ptr()), C.c_void_p(t.data_ptr()), self.n,
+                                          C.c_void_p(self.work.data_ptr()), C.c_void_p(self.loss.data_ptr()),
+                                          C.c_void_p(self.grad.data_ptr()))
+        if rc != OK:
+            raise SolverError(rc, "imsmg_mlp_loss_grad")
+        return self.loss, self.grad
+
+    def step(self, X, t, lr):
+        self.loss_grad(X, t)
+        self.step_count += 1
+        rc = self.lib.imsmg_mlp_adam(_stream(self.torch), C.c_void_p(self.params.data_ptr()),
+                                     C.c_void_p(self.grad.data_ptr()), C.c_void_p(self.m.data_ptr()),
+                                     C.c_void_p(self.v.data_ptr()), self.step_count, C.c_float(lr))
+        if rc != OK:
+            raise SolverError(rc, "imsmg_mlp_adam")
+        return self.loss

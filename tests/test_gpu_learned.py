@@ -1,0 +1,184 @@
+"""GPU parity of the per-block damping path (through the C ABI) against the
+oracle: block features, the damping network's forward pass, loss gradient and
+Adam step, the two-grid objective with its adjoint gradient, the
+lambda_max(S A) estimate, and the learned-weights factorization and solve.
+
+Bars: features 2e-6 absolute (FP32 output of FP64 sums; the eigenvalue
+features only on blocks whose lambda_min / max diag > 1e-10, 1e-4, since
+near-singular eigenvalues are determined only to ~eps ||A_j||); network in
+FP32 against FP64: 1e-4 relative; two-grid J 1e-10 relative and gradient
+1e-8 of its largest entry (FP64 both sides, different summation order);
+lambda_max within [0.97, 1] of the dense value (the power iteration's
+Rayleigh quotient increases towards it).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_10977_amd import solver as S
+    S.load()
+    return S
+
+
+_cache = {}
+
+
+def _two_level():
+    if "p" not in _cache:
+        from paper_1903_10977_amd import generator as GN
+        from oracle import learned as LR
+        from oracle import problem as P
+        w = W.small_discs(seed=11, n=16, degree=2, levels=2, n_discs=3, rmin=0.08, rmax=0.15)
+        print(f"[case two-level discs] n={w.n} p={w.degree}", flush=True)
+        op = P.build(w)
+        eta = LR.volume_fractions(op.hier, op.system.vol_frac)
+        _cache["p"] = (w, GN.generate(w), op, eta)
+    return _cache["p"]
+
+
+def _solver(S, g, **opt):
+    w = g.workload
+    o = S.default_options(nu_pre=w.nu, nu_post=w.nu, **opt)
+    return S.Solver(0).setup(g, o)
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def test_block_features_match_oracle():
+    S = _gpu()
+    from oracle import learned as LR
+    w, g, op, eta = _two_level()
+    sol = _solver(S, g).factor()
+    F = sol.features(1).astype(np.float64)
+    sm = op.smoothers[1]
+    Fo = LR.block_features(op.hier.levels[1], op.hier.A[1], sm, eta[1], 1, 1)
+    assert F.shape == Fo.shape
+    plain = [q for q in range(16) if q not in (8, 9)]
+    assert np.abs(F[:, plain] - Fo[:, plain]).max() <= 2e-6
+    # eigenvalue features where the eigenvalues are well determined
+    A = op.hier.A[1].tocsr()
+    ok = []
+    for j, blk in enumerate(sm.blocks):
+        src = sm.raw_blocks[j] if j < len(sm.raw_blocks) else blk
+        Ar = A[src][:, src].toarray()
+        ok.append(np.linalg.eigvalsh(Ar)[0] / Ar.diagonal().max() > 1e-10)
+    ok = np.array(ok)
+    assert ok.sum() > len(ok) // 2
+    assert np.abs(F[ok][:, [8, 9]] - Fo[ok][:, [8, 9]]).max() <= 1e-4
+    sol.close()
+
+
+def test_network_forward_gradient_and_adam_match_oracle():
+    S = _gpu()
+    from oracle import mlp as NN
+    rng = _rng(21)
+    theta = NN.init(rng)
+    theta[-1] = 0.2
+    n = 700  # several gradient chunks and a ragged tail
+    X = rng.standard_normal((n, 16)) * 0.5
+    t = rng.standard_normal(n) * 0.3
+    th32 = torch.tensor(theta, dtype=torch.float32, device="cuda:0")
+    X32 = torch.tensor(X, dtype=torch.float32, device="cuda:0")
+    t32 = torch.tensor(t, dtype=torch.float32, device="cuda:0")
+    o = S.mlp_forward(th32, X32).cpu().numpy()
+    # the oracle on the FP32-rounded inputs
+    th_r = th32.cpu().double().numpy()
+    X_r = X32.cpu().double().numpy()
+    t_r = t32.cpu().double().numpy()
+    o_ref = NN.forward(th_r, X_r)
+    assert np.abs(o - o_ref).max() <= 1e-4 * max(1.0, np.abs(o_ref).max())
+    tr = S.MlpTrainer(th32, n)
+    loss, grad = tr.loss_grad(X32, t32)
+    L_ref, g_ref = NN.loss_and_grad(th_r, X_r, t_r)
+    assert abs(float(loss.item()) - L_ref) <= 1e-4 * L_ref
+    g = grad.cpu().double().numpy()
+    assert np.abs(g - g_ref).max() <= 1e-4 * np.abs(g_ref).max()
+    # deterministic: the same gradient again, bit for bit
+    g2 = tr.loss_grad(X32, t32)[1].cpu().numpy()
+    assert np.array_equal(g2, grad.cpu().numpy())
+    # one Adam step from zero moments
+    tr.step(X32, t32, 1e-3)
+    th1 = tr.params.cpu().double().numpy()
+    th1_ref, _, _ = NN.adam_step(th_r, g, np.zeros(NN.NPARAM), np.zeros(NN.NPARAM), 1, 1e-3)
+    assert np.abs(th1 - th1_ref).max() <= 2e-6
+
+
+def test_two_grid_objective_and_gradient_match_oracle():
+    S = _gpu()
+    from oracle import learned as LR
+    w, g, op, eta = _two_level()
+    sol = _solver(S, g).factor()
+    sm = op.smoothers[1]
+    rng = _rng(22)
+    nb = len(sm.blocks)
+    omega = sm.gamma * np.exp(0.3 * rng.standard_normal(nb))
+    sol.set_block_weights(1, omega)
+    n = op.hier.A[1].shape[0]
+    Z = rng.standard_normal((n, 3))
+    for k in (1, 2):
+        J, gr = sol.two_grid_objective(Z, k=k)
+        J_ref, g_ref = LR.two_grid_objective(op.hier.A[1], op.hier.R[0], op.hier.A[0], sm, omega, Z, k)
+        assert abs(J - J_ref) <= 1e-10 * J_ref, (k, J, J_ref)
+        assert np.abs(gr - g_ref).max() <= 1e-8 * np.abs(g_ref).max(), k
+    sol.close()
+
+
+def test_lambda_max_estimate_matches_dense():
+    S = _gpu()
+    from oracle import learned as LR
+    w, g, op, eta = _two_level()
+    sol = _solver(S, g).factor()
+    sm = op.smoothers[1]
+    om = np.full(len(sm.blocks), sm.gamma)
+    ref = LR.lambda_max_SA(op.hier.A[1], sm, om)
+    est = sol.lambda_max(1, 200)
+    assert 0.97 * ref <= est <= ref * (1 + 1e-9), (est, ref)
+    sol.close()
+
+
+@pytest.mark.parametrize("b3", [0.5, 1.2])
+def test_learned_weights_factorization_and_solve(b3):
+    """A constant network (only b3 non-zero) gives omega = gamma e^b3 on every
+    block; the stability check accepts it iff lambda_max(S A) < 1.9, and the
+    PCG solve then matches the oracle's PCG with the same weights."""
+    S = _gpu()
+    from oracle import learned as LR
+    from oracle import multigrid as MG
+    w, g, op, eta = _two_level()
+    theta = np.zeros(5313, np.float32)
+    theta[-1] = b3
+    sol = _solver(S, g, use_learned=1)
+    sol.load_mlp(theta).factor()
+    om, status, lam = sol.weights(1)
+    sm = op.smoothers[1]
+    ref_lam = LR.lambda_max_SA(op.hier.A[1], sm, np.full(len(sm.blocks), sm.gamma * np.exp(np.float32(b3))))
+    if ref_lam < 1.9 * 0.99:
+        assert status == 1 and np.allclose(om, sm.gamma * np.exp(np.float32(b3)), rtol=1e-6)
+    elif ref_lam > 1.9 * 1.01:
+        assert status == -1 and np.allclose(om, sm.gamma, rtol=1e-12)
+    # PCG with the weights in force vs the oracle with the same weights
+    sm.omega = om.copy()
+    try:
+        x_ref, it_ref, _ = MG.pcg(op.A, op.b, op.vcycle.apply, tol=1e-8)
+    finally:
+        sm.omega = None
+    b = torch.tensor(g.b, device="cuda:0")
+    x = torch.zeros_like(b)
+    info = sol.pcg(b, x, rtol=1e-8)
+    xs = x.cpu().numpy()
+    assert info.true_rel_res <= 1e-8
+    assert abs(info.iterations - it_ref) <= 1
+    e = xs - x_ref
+    assert np.sqrt(e @ (op.system.M @ e)) <= 1e-6 * np.sqrt(x_ref @ (op.system.M @ x_ref))
+    sol.close()
