@@ -76,6 +76,7 @@ def main():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the mixed+learned form")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for FETCH_SIZE/WRITE_SIZE scaling)")
     args = ap.parse_args()
@@ -99,11 +100,15 @@ def main():
     b = torch.tensor(g.b, device="cuda:0")
     n = g.fine.n
 
-    def make(prec, timing=0):
+    def make(prec, timing=0, learned=None):
         o = S.default_options(nu_pre=w.nu, nu_post=w.nu, precision=prec, timing=timing,
-                              use_graph=0 if (args.no_graph or timing) else 1, max_iter=1000)
+                              use_graph=0 if (args.no_graph or timing) else 1, max_iter=2000,
+                              use_learned=int(learned is not None))
         t = time.time()
-        sol = S.Solver(0).setup(g, o).factor()
+        sol = S.Solver(0).setup(g, o)
+        if learned is not None:
+            sol.load_mlp(learned)
+        sol.factor()
         log(f"setup+factor precision={prec} {time.time() - t:.2f} s")
         return sol
 
@@ -134,6 +139,19 @@ def main():
                              true_rel_res=res, x=x)
         log(f"precision={prec}: {args.steps} solves, {iters} iterations, {1e3 * dt / args.steps:.2f} ms/solve, "
             f"{n * iters / dt / 1e6:.1f} MDOF/s, true rel. residual {res:.2e}")
+        sol.close()
+    # mixed + learned per-block damping (the committed network), same solves
+    learned = None
+    if not args.no_learned:
+        from paper_1903_10977_amd import learn as LN
+        sol = make(S.MIXED, learned=LN.load_params())
+        status = [sol.weights(l)[1] for l in range(1, len(g.levels))]
+        x, iters, dt = timed(sol)
+        res = float(np.linalg.norm(g.b - g.fine.A @ x.cpu().numpy()) / np.linalg.norm(g.b))
+        learned = dict(iters=iters, ms=1e3 * dt / args.steps, mdofs=n * iters / dt / 1e6, true_rel_res=res,
+                       level_status=status)
+        log(f"mixed+learned: {args.steps} solves, {iters} iterations, {learned['ms']:.2f} ms/solve, "
+            f"level status {status} (1 = network weights kept), true rel. residual {res:.2e}")
         sol.close()
     hr = results[head]
     ms_step = hr["ms"]
@@ -185,6 +203,11 @@ def main():
     forms = {names[p]: {"ms_per_solve": round(r["ms"], 3), "mdofs": round(r["mdofs"], 1),
                         "iterations_per_solve": r["iters"] / args.steps, "true_rel_res": r["true_rel_res"]}
              for p, r in results.items()}
+    if learned is not None:
+        forms["mixed+learned"] = {"ms_per_solve": round(learned["ms"], 3), "mdofs": round(learned["mdofs"], 1),
+                                  "iterations_per_solve": learned["iters"] / args.steps,
+                                  "true_rel_res": learned["true_rel_res"],
+                                  "levels_with_network_weights": learned["level_status"]}
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "MDOF/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",

@@ -153,8 +153,10 @@ int imsmg_set_patch_weights(imsmg_ctx *ctx, int level, const double *omega);
  * omega_j = gamma_l exp(clip(o_j, -3, 3)) from the damping network on the
  * block features; the weights are kept only if a 60-step power iteration
  * finds lambda_max(S_omega A_l) < 2 (1 - 0.05) (the stability condition
- * eq:stabilityMulti keeps I - S A a contraction), else the level falls back
- * to gamma_l (imsmg_get_patch_weights reports which). */
+ * eq:stabilityMulti keeps I - S A a contraction).  On a first failure all
+ * weights of the level are scaled by 1.8 / lambda_max and checked again; on a
+ * second the level falls back to gamma_l (imsmg_get_patch_weights reports
+ * which). */
 int imsmg_factor_patches(imsmg_ctx *ctx);
 
 /* ---- per-block damping (an extension: the paper uses one factor per level,
@@ -183,7 +185,7 @@ int imsmg_load_mlp(imsmg_ctx *ctx, const float *params, int64_t nparams);
  *  11 fraction of j's functions with a cut element in their support
  *  12-14 offset per axis of the eta-weighted mean element index of S from its
  *        unweighted mean, / (p + 1) (0 on unused axes)
- *  15 l / (nlevels - 1) */
+ *  15 fraction of the level's active elements that are cut (eta < 1 - 1e-12) */
 int imsmg_get_patch_features(imsmg_ctx *ctx, int level, int32_t *nblocks, float *feat);
 
 /* Current weight of every final block of level l (host, may be NULL),
@@ -204,7 +206,7 @@ int imsmg_lambda_max(imsmg_ctx *ctx, int level, int iters, double *lambda_max);
 /* Two-grid objective of a factorized TWO-level hierarchy (level 1 smoothed,
  * level 0 solved exactly), with the current weights of level 1:
  *   E = (I - S A)(I - R^T A_0^{-1} R A)(I - S A)   (eq:eigenMulti, one smoothing step each side),
- *   J = ||E^k Z||_F^2 / ||Z||_F^2,
+ *   J = tr((E^k Z)^T A E^k Z) / tr(Z^T A Z)   (energy norm, in which E is self-adjoint),
  * Z: host, n_1 x m column-major (compact level-1 numbering).  grad (host,
  * nblocks final blocks of level 1, may be NULL) receives dJ/domega_j by the
  * adjoint recursion.  FP64 throughout. */

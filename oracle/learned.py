@@ -8,8 +8,9 @@ weights omega_j generalize it: S_omega = sum_j omega_j P_j A_j^{-1} P_j^T.
 * Objective.  The two-grid error propagation operator of the multigrid
   analysis (eq:eigenMulti) with one pre- and one post-smoothing step,
       E(omega) = (I - S_omega A)(I - R^T A_c^{-1} R A)(I - S_omega A),
-  is scored on a fixed block of vectors Z by
-      J(omega) = ||E^k Z||_F^2 / ||Z||_F^2,
+  is scored on a fixed block of vectors Z in the energy norm, in which E is
+  self-adjoint and (for stable weights) contractive:
+      J(omega) = sum_cols ||E^k z||_A^2 / sum_cols ||z||_A^2,
   whose gradient follows from the adjoint recursion written out in
   `two_grid_objective`.
 * Stability.  The smoother must keep lambda_max(S_omega A) below 2 so that
@@ -46,7 +47,7 @@ FEATURES = (
     "x offset of the eta-weighted element centroid of the support from its unweighted centroid / (p+1)",
     "y offset (same)",
     "z offset (same; 0 in 2D)",
-    "level index / finest level index",
+    "fraction of the level's active elements that are cut (eta_K < 1 - 1e-12)",
 )
 NFEAT = len(FEATURES)
 SAFETY = 2.0 * (1.0 - 0.05)
@@ -97,9 +98,9 @@ def _func_elements(lev):
     return fe
 
 
-def block_features(lev, A, sm, eta, level, finest):
-    """(nblocks x 16) features of the final blocks of smoother `sm` on level
-    `level` (A: the level's operator, eta: its volume fractions)."""
+def block_features(lev, A, sm, eta):
+    """(nblocks x 16) features of the final blocks of smoother `sm` on a level
+    (A: the level's operator, eta: its volume fractions)."""
     d, p = lev.dim, lev.p
     K = (2 * p + 1) ** d
     E = (p + 1) ** d
@@ -115,6 +116,7 @@ def block_features(lev, A, sm, eta, level, finest):
             nk[el] = nk.get(el, 0) + 1
     cut_fn = np.array([any(eta[el] < CUT_ETA for el in fe[i]) for i in range(len(fe))], dtype=bool)
     nraw = len(sm.raw_blocks)
+    cut_level = np.mean([v < CUT_ETA for v in eta.values()])
     F = np.zeros((len(sm.blocks), NFEAT))
     for j, blk in enumerate(sm.blocks):
         raw = np.asarray(sm.raw_blocks[j]) if j < nraw else np.asarray(blk)
@@ -143,7 +145,7 @@ def block_features(lev, A, sm, eta, level, finest):
         cen = np.array([_multi(el, lev.n, d) for el in S], dtype=np.float64)
         off = (et @ cen) / et.sum() - cen.mean(axis=0)
         F[j, 12:12 + d] = off / (p + 1)
-        F[j, 15] = level / finest
+        F[j, 15] = cut_level
     return F
 
 
@@ -157,10 +159,10 @@ def smoother_dense(sm, omega):
 
 
 def two_grid_objective(A, R, Ac, sm, omega, Z, k):
-    """J(omega) = ||E^k Z||_F^2 / ||Z||_F^2 and dJ/domega_j.
+    """J(omega) = tr(X_k^T A X_k) / tr(Z^T A Z) with X_k = E^k Z, and dJ/domega_j.
 
     Forward: X_0 = Z, X_t = E X_{t-1} with E = M C M, M = I - S A,
-    C = I - R^T A_c^{-1} R A.  Adjoint: Lambda_k = 2 X_k / ||Z||^2; for t = k..1
+    C = I - R^T A_c^{-1} R A.  Adjoint: Lambda_k = 2 A X_k / tr(Z^T A Z); for t = k..1
     with a = X_{t-1}, c = C M a:
         nu = (I - A S) Lambda_t,  mu = C^T nu,
         dJ/domega_j -= <P_j^T Lambda_t, A_j^{-1} P_j^T A c> + <P_j^T mu, A_j^{-1} P_j^T A a>,
@@ -180,9 +182,9 @@ def two_grid_objective(A, R, Ac, sm, omega, Z, k):
     X = [Z]
     for _ in range(k):
         X.append(E @ X[-1])
-    nz = float(np.sum(Z * Z))
-    J = float(np.sum(X[-1] * X[-1])) / nz
-    lam = 2.0 * X[-1] / nz
+    nz = float(np.sum(Z * (A @ Z)))
+    J = float(np.sum(X[-1] * (A @ X[-1]))) / nz
+    lam = 2.0 * (A @ X[-1]) / nz
     g = np.zeros(len(sm.blocks))
     for t in range(k, 0, -1):
         a = X[t - 1]

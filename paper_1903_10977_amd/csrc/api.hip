@@ -1039,7 +1039,9 @@ std::vector<float> block_features(imsmg_ctx *c, int l) {
   for (int i = 0; i < n; ++i)
     for (int k = fp[i]; k < fp[i + 1]; ++k)
       if (L.el_eta[fe[k]] < kCut) cut_fn[i] = 1;
-  const int finest = int(c->lv.size()) - 1;
+  int ncut_level = 0;
+  for (double v : L.el_eta) ncut_level += v < kCut;
+  const double cut_level = nel > 0 ? double(ncut_level) / nel : 0.0;
   std::vector<float> F(size_t(nbf) * kMlpInputs, 0.0f);
   std::vector<int32_t> S;
   for (int j = 0; j < nbf; ++j) {
@@ -1094,7 +1096,7 @@ std::vector<float> block_features(imsmg_ctx *c, int l) {
     }
     if (sum_eta > 0.0)
       for (int a = 0; a < d; ++a) f[12 + a] = (cw[a] / sum_eta - cu[a] / ns) / (p + 1);
-    f[15] = double(l) / finest;
+    f[15] = cut_level;
     for (int q = 0; q < kMlpInputs; ++q) F[size_t(j) * kMlpInputs + q] = float(f[q]);
   }
   return F;
@@ -1151,7 +1153,10 @@ double lambda_max_SA(imsmg_ctx *c, Level &L, int iters) {
 }
 
 // Weights of level l from the damping network, omega_j = gamma exp(clip(o_j)),
-// kept only if lambda_max(S_omega A) < 2 (1 - 0.05); otherwise gamma again.
+// kept only if lambda_max(S_omega A) < 2 (1 - 0.05); a first failure rescales
+// all of them so that lambda_max lands at 1.8 and checks again; a second
+// failure returns to gamma.
+constexpr double kSafety = 2.0 * (1.0 - 0.05), kRescaleTarget = 1.8;
 void learned_weights(imsmg_ctx *c, int l) {
   Level &L = c->lv[l];
   if (!c->mlp) bad("use_learned needs the damping network (imsmg_load_mlp)", IMSMG_ERR_STATE);
@@ -1175,7 +1180,14 @@ void learned_weights(imsmg_ctx *c, int l) {
   }
   apply_weights(c, L, w);
   L.lambda_max = lambda_max_SA(c, L, 60);
-  if (L.lambda_max < 2.0 * (1.0 - 0.05)) {
+  if (!(L.lambda_max < kSafety)) {
+    // one rescale towards the bound, then the check again
+    const double f = kRescaleTarget / L.lambda_max;
+    for (double &v : w) v *= f;
+    apply_weights(c, L, w);
+    L.lambda_max = lambda_max_SA(c, L, 60);
+  }
+  if (L.lambda_max < kSafety) {
     L.learned_status = 1;
   } else {
     L.learned_status = -1;
@@ -1216,9 +1228,15 @@ void two_grid(imsmg_ctx *c, int m, const double *Z, int k, double *J, double *gr
   double *dz = dalloc<double>(tmp, n);
   double *dg = dalloc<double>(tmp, std::max(nbf, 1));
   HIP_CHECK_RET(hipMemsetAsync(dg, 0, std::max(nbf, 1) * sizeof(double), s));
+  // energy norm of Z
   double nz = 0.0;
-  for (size_t q = 0; q < size_t(n) * m; ++q) nz += Z[q] * Z[q];
-  if (!(nz > 0.0)) bad("Z must not vanish");
+  for (int col = 0; col < m; ++col) {
+    h2d(s, dz, Z + size_t(col) * n, n);
+    launch_scatter(s, n, L.row_lat, dz, av[0]);
+    apply_A64(c, L, av[0], u);
+    nz += host_dot(c, L, av[0], u, part);
+  }
+  if (!(nz > 0.0)) bad("Z must have positive energy");
   // y = (I - S A) x
   auto smooth = [&](const double *x, double *y) {
     apply_A64(c, L, x, u);
@@ -1258,9 +1276,10 @@ void two_grid(imsmg_ctx *c, int m, const double *Z, int k, double *J, double *gr
       coarse(w1, cv[t]);
       smooth(cv[t], av[t]);
     }
-    num += host_dot(c, L, av[k], av[k], part);
+    apply_A64(c, L, av[k], w1);
+    num += host_dot(c, L, av[k], w1, part);
     if (!grad) continue;
-    launch_scale_copy(s, n, L.row_lat, 2.0 / nz, av[k], lam);
+    launch_scale_copy(s, n, L.row_lat, 2.0 / nz, w1, lam);
     for (int t = k; t >= 1; --t) {
       // g_j -= <Lambda, A_j^{-1} (A c_t)_j> + <mu, A_j^{-1} (A a_{t-1})_j>
       smooth_t(lam, nu);

@@ -62,7 +62,7 @@ def test_block_features_match_oracle():
     sol = _solver(S, g).factor()
     F = sol.features(1).astype(np.float64)
     sm = op.smoothers[1]
-    Fo = LR.block_features(op.hier.levels[1], op.hier.A[1], sm, eta[1], 1, 1)
+    Fo = LR.block_features(op.hier.levels[1], op.hier.A[1], sm, eta[1])
     assert F.shape == Fo.shape
     plain = [q for q in range(16) if q not in (8, 9)]
     assert np.abs(F[:, plain] - Fo[:, plain]).max() <= 2e-6
