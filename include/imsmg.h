@@ -159,6 +159,24 @@ int imsmg_set_patch_weights(imsmg_ctx *ctx, int level, const double *omega);
  * which). */
 int imsmg_factor_patches(imsmg_ctx *ctx);
 
+/* ---- several right-hand sides with the same matrix (nrhs = 1 .. 16) ----
+ * B, X, R, Z: device, compact numbering of the finest level, column-major
+ * n x nrhs (column k at offset k * n).  Internally the columns are
+ * interleaved on the lattice (4, 8 or 16 wide, unused columns zero) so that
+ * every stencil row, block row and transfer coefficient is read once for all
+ * columns. */
+
+/* Z = B R column by column (one V-cycle). */
+int imsmg_vcycle_multi(imsmg_ctx *ctx, int nrhs, const double *R_dev, double *Z_dev);
+
+/* nrhs independent PCG solves A x_k = b_k sharing every kernel launch; CG
+ * scalars, stopping test (||r_k|| <= rtol ||r_k,0||) and iteration counts are
+ * per column (a converged column stops moving while the others continue);
+ * the call returns when every column has converged or on the first error.
+ * infos: nrhs entries (may be NULL); solve_ms is the wall time of the call. */
+int imsmg_pcg_solve_multi(imsmg_ctx *ctx, int nrhs, const double *B_dev, double *X_dev, double rtol,
+                          imsmg_info *infos);
+
 /* ---- per-block damping (an extension: the paper uses one factor per level,
  * see the discussion after eq:applyCS).  "Final blocks" are the blocks after
  * factorization: the input blocks in input order (members removed by the

@@ -145,6 +145,15 @@ struct imsmg_ctx {
   double *c_in = nullptr, *c_out = nullptr;                          // compact staging
   hipGraphExec_t graph = nullptr;
   int graph_iters = 0;
+  // multi-right-hand-side buffers (R interleaved columns), allocated on first use
+  struct Multi {
+    int R = 0;
+    std::vector<double *> r, x, x2, rh, xs;  // per level, padded
+    double *p = nullptr, *q = nullptr, *xsol = nullptr, *bs = nullptr, *part = nullptr;
+    MState *st = nullptr;
+    hipGraphExec_t graph = nullptr;
+    std::vector<void *> owned;
+  } mb;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   double t_kernel_ms = 0.0;
@@ -1338,11 +1347,126 @@ void destroy_graph(imsmg_ctx *c) {
     (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;
   }
+  if (c->mb.graph) {
+    (void)hipGraphExecDestroy(c->mb.graph);
+    c->mb.graph = nullptr;
+  }
   c->graph_iters = 0;
 }
 
 // One CG iteration after the initial residual: z = B r, beta, p, q = A p,
 // alpha, x, r (the update kernel also prepares c * r for the next V-cycle).
+// ------------------------------------------------------------ multi-RHS path
+void free_multi(imsmg_ctx *c) {
+  if (c->mb.graph) {
+    (void)hipGraphExecDestroy(c->mb.graph);
+    c->mb.graph = nullptr;
+  }
+  free_list(c->mb.owned);
+  c->mb = imsmg_ctx::Multi{};
+}
+
+void ensure_multi(imsmg_ctx *c, int R) {
+  if (c->mb.R == R) return;
+  free_multi(c);
+  hipStream_t s = c->stream;
+  auto &m = c->mb;
+  const int nl = int(c->lv.size());
+  auto vec = [&](const Level &L) {
+    const size_t len = size_t(L.lattice + 2 * L.guard) * R;
+    double *b = dalloc<double>(m.owned, len);
+    HIP_CHECK_RET(hipMemsetAsync(b, 0, len * sizeof(double), s));
+    return b + size_t(L.guard) * R;
+  };
+  for (int l = 0; l < nl; ++l) {
+    const Level &L = c->lv[l];
+    m.r.push_back(vec(L));
+    m.x.push_back(vec(L));
+    m.x2.push_back(vec(L));
+    m.rh.push_back(vec(L));
+    m.xs.push_back(((c->opt.nu_pre - 1 + c->opt.nu_post) % 2) ? m.x2.back() : m.x.back());
+  }
+  const Level &F = c->lv.back();
+  m.p = vec(F);
+  m.q = vec(F);
+  m.xsol = vec(F);
+  m.bs = vec(F);
+  m.part = dalloc<double>(m.owned, size_t(2) * multi_blocks(R, F.n) * R + 16);
+  m.st = dalloc<MState>(m.owned, 1);
+  HIP_CHECK_RET(hipMemsetAsync(m.st, 0, sizeof(MState), s));
+  HIP_CHECK_RET(hipStreamSynchronize(s));
+  m.R = R;
+}
+
+void m_smooth_step(imsmg_ctx *c, int l, const double *xa, double *xb, const int32_t *done) {
+  Level &L = c->lv[l];
+  auto &m = c->mb;
+  if (mixed(c))
+    launch_m_residual_smooth(c->stream, m.R, L.n, L.K, L.op32, L.row_lat, L.meta, L.c, xa, m.r[l], m.rh[l], xb, done);
+  else
+    launch_m_residual_smooth(c->stream, m.R, L.n, L.K, L.op64, L.row_lat, L.meta, L.c, xa, m.r[l], m.rh[l], xb, done);
+  launch_m_smooth_general(c->stream, m.R, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, m.rh[l], xb, done);
+}
+
+void m_vcycle_level(imsmg_ctx *c, int l, const int32_t *done_top) {
+  Level &L = c->lv[l];
+  auto &m = c->mb;
+  const int R = m.R;
+  hipStream_t s = c->stream;
+  const int32_t *done = flag_for(L, done_top);
+  if (l == 0) {
+    launch_m_dense_gemm(s, R, L.n, L.row_lat, L.Ainv, m.r[0], m.x[0], done);
+    return;
+  }
+  Level &Cl = c->lv[l - 1];
+  launch_m_smooth_general(s, R, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, m.r[l], m.xs[l], done);
+  double *xa = m.xs[l], *xb = (m.xs[l] == m.x[l]) ? m.x2[l] : m.x[l];
+  for (int k = 1; k < c->opt.nu_pre; ++k) {
+    m_smooth_step(c, l, xa, xb, done);
+    std::swap(xa, xb);
+  }
+  if (mixed(c))
+    launch_m_residual(s, R, L.n, L.K, L.op32, L.row_lat, L.meta, xa, m.r[l], m.rh[l], done);
+  else
+    launch_m_residual(s, R, L.n, L.K, L.op64, L.row_lat, L.meta, xa, m.r[l], m.rh[l], done);
+  const double *ci = l - 1 > 0 ? Cl.c : nullptr;
+  double *xinit = l - 1 > 0 ? m.xs[l - 1] : nullptr;
+  const int32_t *cdone = flag_for(Cl, done_top);
+  if (L.tensor)
+    launch_m_tensor_transfer(s, R, L.dim, Cl.n, Cl.row_lat, Cl.shape[0], Cl.shape[1], L.rb_start, L.rb_len,
+                             L.rb_coef, L.rbW, L.shape[0], L.shape[1], m.rh[l], m.r[l - 1], 0, ci, xinit, cdone);
+  else
+    launch_m_ell_gather(s, R, Cl.n, L.rw, Cl.row_lat, L.rcol, L.rval, m.rh[l], m.r[l - 1], 0, ci, xinit, cdone);
+  m_vcycle_level(c, l - 1, done_top);
+  if (L.tensor)
+    launch_m_tensor_transfer(s, R, L.dim, L.n, L.row_lat, L.shape[0], L.shape[1], L.pb_start, L.pb_len, L.pb_coef,
+                             L.pbW, Cl.shape[0], Cl.shape[1], m.x[l - 1], xa, 1, nullptr, nullptr, done);
+  else
+    launch_m_ell_gather(s, R, L.n, L.tw, L.row_lat, L.tcol, L.tval, m.x[l - 1], xa, 1, nullptr, nullptr, done);
+  for (int k = 0; k < c->opt.nu_post; ++k) {
+    m_smooth_step(c, l, xa, xb, done);
+    std::swap(xa, xb);
+  }
+}
+
+void m_cg_iteration(imsmg_ctx *c) {
+  Level &F = c->lv.back();
+  auto &m = c->mb;
+  const int f = int(c->lv.size()) - 1;
+  const int32_t *done = &m.st->done;
+  hipStream_t s = c->stream;
+  m_vcycle_level(c, f, done);
+  launch_mcg_dot_rz(s, m.R, F.n, F.row_lat, m.r[f], m.x[f], m.part, m.st);
+  launch_mcg_direction(s, m.R, F.n, F.row_lat, m.x[f], m.p, m.st);
+  launch_mcg_spmv_pq(s, m.R, F.n, F.K, F.op64, F.row_lat, F.meta, m.p, m.q, m.part, m.st);
+  launch_mcg_update(s, m.R, F.n, F.row_lat, m.p, m.q, m.xsol, m.r[f], F.c, m.xs[f], m.part, m.st, c->opt.max_iter);
+}
+
+int rhs_width(int nrhs) {
+  if (nrhs < 1 || nrhs > kMaxRhs) bad("nrhs must be 1 .. 16");
+  return nrhs <= 4 ? 4 : nrhs <= 8 ? 8 : 16;
+}
+
 void cg_iteration(imsmg_ctx *c, bool timing) {
   Level &F = c->lv.back();
   const int32_t *done = &c->st->done;
@@ -1408,6 +1532,7 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
     if (nlevels < 1 || nlevels > 16 || !A || !Lt) bad("bad level count or null arrays");
     if (nlevels > 1 && (!R || !P)) bad("R and P are required with more than one level");
     destroy_graph(c);
+    free_multi(c);
     free_list(c->factor_owned);
     free_list(c->owned);
     c->lv.clear();
@@ -1569,7 +1694,7 @@ int imsmg_pcg_solve(imsmg_ctx *c, const double *b_dev, double *x_dev, double rto
     CGState h{};
     int restarts = 0;
     while (true) {
-      launch_cg_init(s, F.n, F.K, F.op64, F.row_lat, F.meta, c->xs, c->bs, F.r, c->part, c->st, rtol);
+      launch_cg_init(s, F.n, F.K, F.op64, F.row_lat, F.meta, c->xs, c->bs, F.r, c->part, c->st, rtol, restarts > 0);
       launch_diag_scale(s, F.n, F.row_lat, F.c, F.r, F.xs, &c->st->done);
       HIP_CHECK_RET(hipGetLastError());
       const int m = c->opt.check_every;
@@ -1824,6 +1949,106 @@ int imsmg_mlp_adam(void *stream, float *params, const float *grad, float *m, flo
   return hipGetLastError() == hipSuccess ? IMSMG_OK : IMSMG_ERR_HIP;
 }
 
+int imsmg_vcycle_multi(imsmg_ctx *c, int nrhs, const double *R_dev, double *Z_dev) {
+  return guarded(c, [&]() -> int {
+    if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    if (!R_dev || !Z_dev) bad("null vector");
+    const int R = rhs_width(nrhs);
+    ensure_multi(c, R);
+    Level &F = c->lv.back();
+    const int f = int(c->lv.size()) - 1;
+    auto &m = c->mb;
+    launch_m_scatter(c->stream, R, F.n, nrhs, F.row_lat, R_dev, m.r[f]);
+    launch_m_diag_scale(c->stream, R, F.n, F.row_lat, F.c, m.r[f], m.xs[f], c->zero_flag);
+    m_vcycle_level(c, f, c->zero_flag);
+    launch_m_gather(c->stream, R, F.n, nrhs, F.row_lat, m.x[f], Z_dev);
+    HIP_CHECK_RET(hipGetLastError());
+    HIP_CHECK_RET(hipStreamSynchronize(c->stream));
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_pcg_solve_multi(imsmg_ctx *c, int nrhs, const double *B_dev, double *X_dev, double rtol,
+                          imsmg_info *infos) {
+  return guarded(c, [&]() -> int {
+    if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    if (!B_dev || !X_dev) bad("null vector");
+    if (!(rtol > 0.0)) bad("rtol must be positive");
+    const int R = rhs_width(nrhs);
+    auto t0 = std::chrono::steady_clock::now();
+    ensure_multi(c, R);
+    auto &m = c->mb;
+    Level &F = c->lv.back();
+    const int f = int(c->lv.size()) - 1;
+    hipStream_t s = c->stream;
+    launch_m_scatter(s, R, F.n, nrhs, F.row_lat, B_dev, m.bs);
+    launch_m_scatter(s, R, F.n, nrhs, F.row_lat, X_dev, m.xsol);
+    MState h{};
+    int restarts = 0, keep = 0;
+    std::vector<double> true_rel(R, 0.0);
+    while (true) {
+      launch_mcg_init(s, R, nrhs, F.n, F.K, F.op64, F.row_lat, F.meta, m.xsol, m.bs, m.r[f], m.part, m.st, rtol,
+                      restarts > 0, keep);
+      launch_m_diag_scale(s, R, F.n, F.row_lat, F.c, m.r[f], m.xs[f], &m.st->done);
+      HIP_CHECK_RET(hipGetLastError());
+      const int mit = c->opt.check_every;
+      if (c->opt.use_graph && !m.graph) {
+        hipGraph_t g = nullptr;
+        HIP_CHECK_RET(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < mit; ++k) m_cg_iteration(c);
+        HIP_CHECK_RET(hipStreamEndCapture(s, &g));
+        hipError_t e = hipGraphInstantiate(&m.graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIP_CHECK_RET(e);
+      }
+      while (true) {
+        if (c->opt.use_graph) {
+          HIP_CHECK_RET(hipGraphLaunch(m.graph, s));
+        } else {
+          for (int k = 0; k < mit; ++k) m_cg_iteration(c);
+        }
+        HIP_CHECK_RET(hipGetLastError());
+        HIP_CHECK_RET(hipMemcpyAsync(&h, m.st, sizeof(MState), hipMemcpyDeviceToHost, s));
+        HIP_CHECK_RET(hipStreamSynchronize(s));
+        if (h.done) break;
+      }
+      launch_mcg_true_residual(s, R, F.n, F.K, F.op64, F.row_lat, F.meta, m.xsol, m.bs, m.part, m.st);
+      HIP_CHECK_RET(hipMemcpyAsync(&h, m.st, sizeof(MState), hipMemcpyDeviceToHost, s));
+      HIP_CHECK_RET(hipStreamSynchronize(s));
+      bool again = false;
+      keep = 0;
+      for (int k = 0; k < nrhs; ++k) {
+        true_rel[k] = h.bb[k] > 0.0 ? std::sqrt(h.aux[k] / h.bb[k]) : 0.0;
+        if (true_rel[k] > rtol && h.iters[k] < c->opt.max_iter) again = true;
+        else keep |= 1 << k;  // this column stays converged on a restart
+      }
+      if (h.status == 0 && again && restarts < 3) {
+        ++restarts;
+        continue;
+      }
+      break;
+    }
+    launch_m_gather(s, R, F.n, nrhs, F.row_lat, m.xsol, X_dev);
+    HIP_CHECK_RET(hipStreamSynchronize(s));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (infos)
+      for (int k = 0; k < nrhs; ++k) {
+        infos[k].status = h.status;
+        infos[k].iterations = h.iters[k];
+        infos[k].rel_res = h.r0sq[k] > 0.0 ? std::sqrt(h.rr[k] / h.r0sq[k]) : 0.0;
+        infos[k].true_rel_res = true_rel[k];
+        infos[k].solve_ms = ms;
+      }
+    if (h.status != 0) {
+      c->err = h.status == IMSMG_ERR_NOT_CONVERGED ? "CG did not converge within max_iter"
+               : h.status == IMSMG_ERR_NOT_SPD     ? "CG breakdown: p.Ap <= 0"
+                                                   : "NaN or Inf in the CG iteration";
+      return int(h.status);
+    }
+    return IMSMG_OK;
+  });
+}
+
 const char *imsmg_last_error(imsmg_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 int imsmg_destroy(imsmg_ctx *c) {
@@ -1832,6 +2057,7 @@ int imsmg_destroy(imsmg_ctx *c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   destroy_graph(c);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  free_multi(c);
   free_list(c->factor_owned);
   free_list(c->owned);
   if (c->mlp) (void)hipFree(c->mlp);

@@ -109,17 +109,21 @@ __global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_cg_init(int n
   }
 }
 
+// restart != 0: CG restarted from the current iterate; the stopping threshold
+// and the iteration count of the first start are kept
 __global__ __launch_bounds__(kFinThreads) void k_cg_init_fin(int m, const double *__restrict__ part, CGState *st,
-                                                             double rtol) {
+                                                             double rtol, int restart) {
   __shared__ double lds[kFinThreads];
   const double rr = sum_partials(part, m, lds);
   const double bb = sum_partials(part + m, m, lds);
   if (threadIdx.x == 0) {
-    st->r0sq = rr;
+    if (!restart) {
+      st->r0sq = rr;
+      st->tol2 = rtol * rtol * rr;
+      st->iters = 0;
+    }
     st->rr = rr;
     st->bb = bb;
-    st->tol2 = rtol * rtol * rr;
-    st->iters = 0;
     st->first = 1;
     st->status = 0;
     st->beta = 0.0;
@@ -285,10 +289,10 @@ __global__ __launch_bounds__(kFinThreads) void k_cg_aux_fin(int m, const double 
 
 void launch_cg_init(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                     const uint32_t *meta, const double *x, const double *b, double *r, double *part, CGState *st,
-                    double rtol) {
+                    double rtol, int restart) {
   const int g = reduction_blocks(n);
   IMSMG_DISPATCH_K(K, k_cg_init, n, K, op, row_lat, meta, x, b, r, part);
-  k_cg_init_fin<<<1, kFinThreads, 0, s>>>(g, part, st, rtol);
+  k_cg_init_fin<<<1, kFinThreads, 0, s>>>(g, part, st, rtol, restart);
 }
 
 void launch_cg_dot_rz(hipStream_t s, int n, const int32_t *row_lat, const double *r, const double *z, double *part,

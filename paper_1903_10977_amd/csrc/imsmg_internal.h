@@ -66,6 +66,19 @@ struct CGState {
   int32_t first;   // 1 before the first direction is formed
 };
 
+// Scalars of the multi-right-hand-side CG (up to kMaxRhs columns).
+constexpr int kMaxRhs = 16;
+struct MState {
+  double rz[kMaxRhs], rz_old[kMaxRhs], beta[kMaxRhs], alpha[kMaxRhs], rr[kMaxRhs], r0sq[kMaxRhs];
+  double tol2[kMaxRhs], bb[kMaxRhs], aux[kMaxRhs];
+  int32_t cdone[kMaxRhs];  // column converged
+  int32_t iters[kMaxRhs];
+  int32_t done;            // every column converged, or stopped
+  int32_t status;
+  int32_t first;
+  int32_t pad;
+};
+
 // --------------------------------------------------------------- level kernels
 void launch_residual(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                      const uint32_t *meta, const double *x, const double *b, double *y, const int32_t *done);
@@ -102,7 +115,7 @@ void launch_gather(hipStream_t s, int n, const int32_t *row_lat, const double *s
 // (finest level, padded vectors, active rows only, operator in FP64)
 void launch_cg_init(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                     const uint32_t *meta, const double *x, const double *b, double *r, double *part, CGState *st,
-                    double rtol);
+                    double rtol, int restart);
 void launch_cg_dot_rz(hipStream_t s, int n, const int32_t *row_lat, const double *r, const double *z, double *part,
                       CGState *st);
 void launch_cg_direction(hipStream_t s, int n, const int32_t *row_lat, const double *z, double *p, CGState *st);
@@ -114,6 +127,48 @@ void launch_cg_update(hipStream_t s, int n, const int32_t *row_lat, const double
 void launch_cg_true_residual(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                              const uint32_t *meta, const double *x, const double *b, double *part, CGState *st);
 int reduction_blocks(int n);
+
+// --------------------------------------------------------------- multi-RHS (R = 4, 8, 16 interleaved columns)
+bool multi_supported(int R);
+int multi_blocks(int R, int n);
+void launch_m_residual(hipStream_t s, int R, int n, int K, const OpView<double> &op, const int32_t *row_lat,
+                       const uint32_t *meta, const double *x, const double *b, double *y, const int32_t *done);
+void launch_m_residual(hipStream_t s, int R, int n, int K, const OpView<float> &op, const int32_t *row_lat,
+                       const uint32_t *meta, const double *x, const double *b, double *y, const int32_t *done);
+void launch_m_residual_smooth(hipStream_t s, int R, int n, int K, const OpView<double> &op, const int32_t *row_lat,
+                              const uint32_t *meta, const double *c, const double *xa, const double *r, double *rh,
+                              double *xb, const int32_t *done);
+void launch_m_residual_smooth(hipStream_t s, int R, int n, int K, const OpView<float> &op, const int32_t *row_lat,
+                              const uint32_t *meta, const double *c, const double *xa, const double *r, double *rh,
+                              double *xb, const int32_t *done);
+void launch_m_smooth_general(hipStream_t s, int R, int ng, const int32_t *grow_lat, const int32_t *sptr,
+                             const int32_t *scol, const double *sval, const double *r, double *x, const int32_t *done);
+void launch_m_diag_scale(hipStream_t s, int R, int n, const int32_t *row_lat, const double *c, const double *r,
+                         double *x, const int32_t *done);
+void launch_m_tensor_transfer(hipStream_t s, int R, int dim, int n, const int32_t *row_lat, int ox, int oy,
+                              const int32_t *start, const int32_t *len, const double *coef, int W, int ix, int iy,
+                              const double *xin, double *y, int accumulate, const double *cinit, double *xinit,
+                              const int32_t *done);
+void launch_m_ell_gather(hipStream_t s, int R, int n, int w, const int32_t *row_lat, const int32_t *col,
+                         const double *v, const double *x, double *y, int accumulate, const double *cinit,
+                         double *xinit, const int32_t *done);
+void launch_m_dense_gemm(hipStream_t s, int R, int n, const int32_t *row_lat, const double *Ainv, const double *r,
+                         double *x, const int32_t *done);
+void launch_m_scatter(hipStream_t s, int R, int n, int ncols, const int32_t *row_lat, const double *src, double *dst);
+void launch_m_gather(hipStream_t s, int R, int n, int ncols, const int32_t *row_lat, const double *src, double *dst);
+void launch_mcg_init(hipStream_t s, int R, int ncols, int n, int K, const OpView<double> &op, const int32_t *row_lat,
+                     const uint32_t *meta, const double *x, const double *b, double *r, double *part, MState *st,
+                     double rtol, int restart, int keep_mask);
+void launch_mcg_dot_rz(hipStream_t s, int R, int n, const int32_t *row_lat, const double *r, const double *z,
+                       double *part, MState *st);
+void launch_mcg_direction(hipStream_t s, int R, int n, const int32_t *row_lat, const double *z, double *p,
+                          MState *st);
+void launch_mcg_spmv_pq(hipStream_t s, int R, int n, int K, const OpView<double> &op, const int32_t *row_lat,
+                        const uint32_t *meta, const double *p, double *q, double *part, MState *st);
+void launch_mcg_update(hipStream_t s, int R, int n, const int32_t *row_lat, const double *p, const double *q,
+                       double *x, double *r, const double *c, double *zs, double *part, MState *st, int max_iter);
+void launch_mcg_true_residual(hipStream_t s, int R, int n, int K, const OpView<double> &op, const int32_t *row_lat,
+                              const uint32_t *meta, const double *x, const double *b, double *part, MState *st);
 
 // --------------------------------------------------------------- per-block damping
 constexpr int kMlpInputs = 16, kMlpHidden = 64;

@@ -1,0 +1,664 @@
+// Multi-right-hand-side form of the V-cycle and of CG: R systems with the
+// same matrix solved together (R = 4, 8 or 16 columns).
+//
+// Layout: every level vector holds the R columns interleaved on the padded
+// function lattice, v[L * R + col], so that the R values of one lattice point
+// are one contiguous 8R-byte segment.  One thread per (row, column): the R
+// lanes of a row share the row's lattice position, meta word and stencil
+// coefficients (broadcast loads) and read the neighbours' R values with
+// contiguous, coalesced loads.  The matrix bytes per row are thereby read
+// once for R solves.
+//
+// CG keeps separate scalars per column (MState); a column that has converged
+// stops moving (its alpha and beta are zero) while the others continue.
+// Reductions are deterministic: per workgroup and column one partial sum
+// (fixed LDS tree over the workgroup's rows), then one workgroup adds the
+// partials of each column in index order.
+#include "imsmg_internal.h"
+#include "op_row.h"
+
+namespace imsmg {
+
+namespace {
+constexpr int kMT = 256;   // threads per workgroup
+constexpr int kMFin = 1024;
+
+__device__ __forceinline__ int xcd_map(int b, int nb) {
+  const int per = (nb + 7) / 8;
+  const int xcd = b % 8;
+  const int k = b / 8;
+  const int full = nb % 8 == 0 ? 8 : nb % 8;
+  if (xcd < full) return xcd * per + k;
+  return full * per + (xcd - full) * (per - 1) + k;
+}
+
+template <int R>
+__host__ __device__ constexpr int rows_per_block() {
+  return kMT / R;
+}
+
+template <int R>
+inline int mgrid(int n) {
+  return std::max(1, (n + rows_per_block<R>() - 1) / rows_per_block<R>());
+}
+
+// (A x)_{L, col} with per-lane coefficient select (reference or stored row)
+template <int K, int R, typename V>
+__device__ __forceinline__ double mrow(unsigned meta, const OpView<V> &op, const double *__restrict__ x, int L,
+                                       int col, int Kdyn) {
+  const unsigned g = meta & kMetaIndex;
+  const bool uni = g == kMetaIndex;
+  const V *__restrict__ v = uni ? op.ref : op.val + g;
+  const size_t st = uni ? 1 : size_t(op.nv);
+  double acc = 0.0;
+  if (K > 0) {
+#pragma unroll
+    for (int s = 0; s < K; ++s) acc += double(v[s * st]) * x[size_t(L + op.off.off[s]) * R + col];
+  } else {
+    for (int s = 0; s < Kdyn; ++s) acc += double(v[s * st]) * x[size_t(L + op.off.off[s]) * R + col];
+  }
+  return acc;
+}
+
+// per-column sum over the workgroup's rows (lds: kMT doubles); result valid in
+// threads 0 .. R-1 (column = thread index)
+template <int R>
+__device__ __forceinline__ double col_sum(double v, double *lds) {
+  lds[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kMT / 2; s >= R; s >>= 1) {
+    if (threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+    __syncthreads();
+  }
+  return lds[threadIdx.x];
+}
+
+__device__ __forceinline__ double sum_part(const double *__restrict__ part, int m, int R, int col, double *lds) {
+  double v = 0.0;
+  for (int b = threadIdx.x; b < m; b += kMFin) v += part[size_t(b) * R + col];
+  lds[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kMFin / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = lds[0];
+  __syncthreads();
+  return r;
+}
+}  // namespace
+
+// ------------------------------------------------------------------ level kernels
+template <int K, int R, typename V>
+__global__ __launch_bounds__(kMT) void k_m_residual(int n, int Kdyn, OpView<V> op, const int32_t *__restrict__ row_lat,
+                                                    const uint32_t *__restrict__ meta, const double *__restrict__ x,
+                                                    const double *__restrict__ b, double *__restrict__ y,
+                                                    const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  const int t = xcd_map(blockIdx.x, gridDim.x) * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
+  if (i >= n) return;
+  const int L = row_lat[i];
+  const double ax = mrow<K, R, V>(meta[i], op, x, L, col, Kdyn);
+  const size_t o = size_t(L) * R + col;
+  y[o] = b ? b[o] - ax : ax;
+}
+
+template <int K, int R, typename V>
+__global__ __launch_bounds__(kMT) void k_m_residual_smooth(int n, int Kdyn, OpView<V> op,
+                                                           const int32_t *__restrict__ row_lat,
+                                                           const uint32_t *__restrict__ meta,
+                                                           const double *__restrict__ c,
+                                                           const double *__restrict__ xa,
+                                                           const double *__restrict__ r, double *__restrict__ rh,
+                                                           double *__restrict__ xb, const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  const int t = xcd_map(blockIdx.x, gridDim.x) * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
+  if (i >= n) return;
+  const int L = row_lat[i];
+  const unsigned m = meta[i];
+  const double ax = mrow<K, R, V>(m, op, xa, L, col, Kdyn);
+  const size_t o = size_t(L) * R + col;
+  const double res = r[o] - ax;
+  if (m & kMetaGeneral) rh[o] = res;
+  xb[o] = xa[o] + c[i] * res;
+}
+
+template <int R>
+__global__ __launch_bounds__(kMT) void k_m_smooth_general(int ng, const int32_t *__restrict__ grow_lat,
+                                                          const int32_t *__restrict__ sptr,
+                                                          const int32_t *__restrict__ scol,
+                                                          const double *__restrict__ sval,
+                                                          const double *__restrict__ r, double *__restrict__ x,
+                                                          const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  const int t = xcd_map(blockIdx.x, gridDim.x) * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
+  if (i >= ng) return;
+  double acc = 0.0;
+  for (int k = sptr[i]; k < sptr[i + 1]; ++k) acc += sval[k] * r[size_t(scol[k]) * R + col];
+  x[size_t(grow_lat[i]) * R + col] += acc;
+}
+
+template <int R>
+__global__ __launch_bounds__(kMT) void k_m_diag_scale(int n, const int32_t *__restrict__ row_lat,
+                                                      const double *__restrict__ c, const double *__restrict__ r,
+                                                      double *__restrict__ x, const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  const int t = xcd_map(blockIdx.x, gridDim.x) * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
+  if (i >= n) return;
+  const size_t o = size_t(row_lat[i]) * R + col;
+  x[o] = c[i] * r[o];
+}
+
+struct MBand {
+  const int32_t *start;
+  const int32_t *len;
+  const double *coef;
+  int W;
+};
+
+template <int DIM, int R>
+__global__ __launch_bounds__(kMT) void k_m_tensor_transfer(int n, const int32_t *__restrict__ row_lat, int ox, int oy,
+                                                           MBand band, int ix_, int iy_,
+                                                           const double *__restrict__ xin, double *__restrict__ y,
+                                                           int accumulate, const double *__restrict__ cinit,
+                                                           double *__restrict__ xinit,
+                                                           const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  const int t = xcd_map(blockIdx.x, gridDim.x) * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
+  if (i >= n) return;
+  const int L = row_lat[i];
+  const int mx = L % ox;
+  const int my = (L / ox) % oy;
+  const int mz = DIM == 3 ? L / (ox * oy) : 0;
+  const int sx = band.start[mx], nx = band.len[mx];
+  const int sy = band.start[my], ny = band.len[my];
+  const double *cx = band.coef + size_t(mx) * band.W;
+  const double *cy = band.coef + size_t(my) * band.W;
+  double acc = 0.0;
+  if (DIM == 2) {
+    for (int b = 0; b < ny; ++b) {
+      const size_t row = size_t(sy + b) * ix_ + sx;
+      double s = 0.0;
+      for (int a = 0; a < nx; ++a) s += cx[a] * xin[(row + a) * R + col];
+      acc += cy[b] * s;
+    }
+  } else {
+    const int sz = band.start[mz], nz = band.len[mz];
+    const double *cz = band.coef + size_t(mz) * band.W;
+    for (int c3 = 0; c3 < nz; ++c3) {
+      double tz = 0.0;
+      for (int b = 0; b < ny; ++b) {
+        const size_t row = (size_t(sz + c3) * iy_ + (sy + b)) * ix_ + sx;
+        double s = 0.0;
+        for (int a = 0; a < nx; ++a) s += cx[a] * xin[(row + a) * R + col];
+        tz += cy[b] * s;
+      }
+      acc += cz[c3] * tz;
+    }
+  }
+  const size_t o = size_t(L) * R + col;
+  const double out = accumulate ? y[o] + acc : acc;
+  y[o] = out;
+  if (xinit) xinit[o] = cinit[i] * out;
+}
+
+template <int R>
+__global__ __launch_bounds__(kMT) void k_m_ell_gather(int n, int w, const int32_t *__restrict__ row_lat,
+                                                      const int32_t *__restrict__ colidx,
+                                                      const double *__restrict__ v, const double *__restrict__ x,
+                                                      double *__restrict__ y, int accumulate,
+                                                      const double *__restrict__ cinit, double *__restrict__ xinit,
+                                                      const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  const int t = xcd_map(blockIdx.x, gridDim.x) * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int s = 0; s < w; ++s) acc += v[size_t(s) * n + i] * x[size_t(colidx[size_t(s) * n + i]) * R + col];
+  const size_t o = size_t(row_lat[i]) * R + col;
+  const double out = accumulate ? y[o] + acc : acc;
+  y[o] = out;
+  if (xinit) xinit[o] = cinit[i] * out;
+}
+
+// coarsest level: X = A^{-1} Rhs for R columns.  Workgroup = 256/R rows x R
+// columns; the right-hand sides are staged through LDS in chunks of kGChunk
+// rows (kGChunk x R doubles).
+constexpr int kGChunk = 128;
+template <int R>
+__global__ __launch_bounds__(kMT) void k_m_dense_gemm(int n, const int32_t *__restrict__ row_lat,
+                                                      const double *__restrict__ Ainv, const double *__restrict__ r,
+                                                      double *__restrict__ x, const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  __shared__ double rs[kGChunk * R];
+  const int t = blockIdx.x * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
+  double acc = 0.0;
+  for (int j0 = 0; j0 < n; j0 += kGChunk) {
+    const int m = min(kGChunk, n - j0);
+    for (int e = threadIdx.x; e < m * R; e += kMT) rs[e] = r[size_t(row_lat[j0 + e / R]) * R + (e % R)];
+    __syncthreads();
+    if (i < n) {
+      const double *row = Ainv + size_t(i) * n + j0;
+      for (int j = 0; j < m; ++j) acc += row[j] * rs[j * R + col];
+    }
+    __syncthreads();
+  }
+  if (i < n) x[size_t(row_lat[i]) * R + col] = acc;
+}
+
+// user layout (column-major n x ncols, ld = n) <-> interleaved padded lattice
+template <int R>
+__global__ void k_m_scatter(int n, int ncols, const int32_t *__restrict__ row_lat, const double *__restrict__ src,
+                            double *__restrict__ dst) {
+  const int t = blockIdx.x * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
+  if (i >= n) return;
+  dst[size_t(row_lat[i]) * R + col] = col < ncols ? src[size_t(col) * n + i] : 0.0;
+}
+template <int R>
+__global__ void k_m_gather(int n, int ncols, const int32_t *__restrict__ row_lat, const double *__restrict__ src,
+                           double *__restrict__ dst) {
+  const int t = blockIdx.x * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
+  if (i >= n || col >= ncols) return;
+  dst[size_t(col) * n + i] = src[size_t(row_lat[i]) * R + col];
+}
+
+// ------------------------------------------------------------------ CG kernels
+// (finest level, FP64 operator)
+template <int K, int R>
+__global__ __launch_bounds__(kMT) void k_mcg_init(int n, int Kdyn, OpView<double> op,
+                                                  const int32_t *__restrict__ row_lat,
+                                                  const uint32_t *__restrict__ meta, const double *__restrict__ x,
+                                                  const double *__restrict__ b, double *__restrict__ r,
+                                                  double *__restrict__ part) {
+  __shared__ double lds[kMT];
+  const int blk = xcd_map(blockIdx.x, gridDim.x);
+  const int t = blk * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
+  double rr = 0.0, bb = 0.0;
+  if (i < n) {
+    const int L = row_lat[i];
+    const size_t o = size_t(L) * R + col;
+    const double bi = b[o];
+    const double ri = bi - mrow<K, R, double>(meta[i], op, x, L, col, Kdyn);
+    r[o] = ri;
+    rr = ri * ri;
+    bb = bi * bi;
+  }
+  rr = col_sum<R>(rr, lds);
+  if (threadIdx.x < R) part[size_t(blk) * R + threadIdx.x] = rr;
+  __syncthreads();
+  bb = col_sum<R>(bb, lds);
+  if (threadIdx.x < R) part[(size_t(gridDim.x) + blk) * R + threadIdx.x] = bb;
+}
+
+template <int R>
+__global__ __launch_bounds__(kMT) void k_mcg_dot(int n, const int32_t *__restrict__ row_lat,
+                                                 const double *__restrict__ a, const double *__restrict__ b,
+                                                 double *__restrict__ part, const MState *st) {
+  if (st->done) return;
+  __shared__ double lds[kMT];
+  const int blk = xcd_map(blockIdx.x, gridDim.x);
+  const int t = blk * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
+  double acc = 0.0;
+  if (i < n) {
+    const size_t o = size_t(row_lat[i]) * R + col;
+    acc = a[o] * b[o];
+  }
+  acc = col_sum<R>(acc, lds);
+  if (threadIdx.x < R) part[size_t(blk) * R + threadIdx.x] = acc;
+}
+
+template <int R>
+__global__ __launch_bounds__(kMT) void k_mcg_direction(int n, const int32_t *__restrict__ row_lat,
+                                                       const double *__restrict__ z, double *__restrict__ p,
+                                                       const MState *st) {
+  if (st->done) return;
+  const int t = xcd_map(blockIdx.x, gridDim.x) * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
+  if (i >= n) return;
+  const size_t o = size_t(row_lat[i]) * R + col;
+  const double beta = st->beta[col];
+  p[o] = st->first ? z[o] : z[o] + beta * p[o];
+}
+
+template <int K, int R>
+__global__ __launch_bounds__(kMT) void k_mcg_spmv_pq(int n, int Kdyn, OpView<double> op,
+                                                     const int32_t *__restrict__ row_lat,
+                                                     const uint32_t *__restrict__ meta, const double *__restrict__ p,
+                                                     double *__restrict__ q, double *__restrict__ part,
+                                                     const MState *st) {
+  if (st->done) return;
+  __shared__ double lds[kMT];
+  const int blk = xcd_map(blockIdx.x, gridDim.x);
+  const int t = blk * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
+  double acc = 0.0;
+  if (i < n) {
+    const int L = row_lat[i];
+    const size_t o = size_t(L) * R + col;
+    const double qi = mrow<K, R, double>(meta[i], op, p, L, col, Kdyn);
+    q[o] = qi;
+    acc = p[o] * qi;
+  }
+  acc = col_sum<R>(acc, lds);
+  if (threadIdx.x < R) part[size_t(blk) * R + threadIdx.x] = acc;
+}
+
+template <int R>
+__global__ __launch_bounds__(kMT) void k_mcg_update(int n, const int32_t *__restrict__ row_lat,
+                                                    const double *__restrict__ p, const double *__restrict__ q,
+                                                    double *__restrict__ x, double *__restrict__ r,
+                                                    const double *__restrict__ c, double *__restrict__ zs,
+                                                    double *__restrict__ part, const MState *st) {
+  if (st->done) return;
+  __shared__ double lds[kMT];
+  const int blk = xcd_map(blockIdx.x, gridDim.x);
+  const int t = blk * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
+  double acc = 0.0;
+  if (i < n) {
+    const size_t o = size_t(row_lat[i]) * R + col;
+    const double alpha = st->alpha[col];
+    x[o] += alpha * p[o];
+    const double ri = r[o] - alpha * q[o];
+    r[o] = ri;
+    zs[o] = c[i] * ri;
+    acc = ri * ri;
+  }
+  acc = col_sum<R>(acc, lds);
+  if (threadIdx.x < R) part[size_t(blk) * R + threadIdx.x] = acc;
+}
+
+template <int K, int R>
+__global__ __launch_bounds__(kMT) void k_mcg_true_residual(int n, int Kdyn, OpView<double> op,
+                                                           const int32_t *__restrict__ row_lat,
+                                                           const uint32_t *__restrict__ meta,
+                                                           const double *__restrict__ x,
+                                                           const double *__restrict__ b, double *__restrict__ part) {
+  __shared__ double lds[kMT];
+  const int blk = xcd_map(blockIdx.x, gridDim.x);
+  const int t = blk * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
+  double acc = 0.0;
+  if (i < n) {
+    const int L = row_lat[i];
+    const double ri = b[size_t(L) * R + col] - mrow<K, R, double>(meta[i], op, x, L, col, Kdyn);
+    acc = ri * ri;
+  }
+  acc = col_sum<R>(acc, lds);
+  if (threadIdx.x < R) part[size_t(blk) * R + threadIdx.x] = acc;
+}
+
+// ---- finalize kernels (one workgroup; columns one after the other)
+// restart != 0: CG restarted from the current iterate; the stopping threshold
+// and the iteration counts of the first start are kept, and the columns in
+// keep_mask (bit col) stay converged
+__global__ __launch_bounds__(kMFin) void k_mcg_init_fin(int m, int R, int ncols, const double *__restrict__ part,
+                                                        MState *st, double rtol, int restart, int keep_mask) {
+  __shared__ double lds[kMFin];
+  int all = 1;
+  for (int col = 0; col < R; ++col) {
+    const double rr = sum_part(part, m, R, col, lds);
+    const double bb = sum_part(part + size_t(m) * R, m, R, col, lds);
+    if (threadIdx.x == 0) {
+      if (!restart) {
+        st->r0sq[col] = rr;
+        st->tol2[col] = rtol * rtol * rr;
+        st->iters[col] = 0;
+      }
+      st->rr[col] = rr;
+      st->bb[col] = bb;
+      st->beta[col] = 0.0;
+      st->alpha[col] = 0.0;
+      st->rz[col] = 0.0;
+      const int d = (col >= ncols || rr == 0.0 || (restart && ((keep_mask >> col) & 1))) ? 1 : 0;
+      st->cdone[col] = d;
+      all &= d;
+      if (!(rr == rr) || !(bb == bb)) st->status = -6;
+    }
+  }
+  if (threadIdx.x == 0) {
+    st->first = 1;
+    if (st->status != -6) st->status = 0;
+    st->done = (all || st->status != 0) ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(kMFin) void k_mcg_rz_fin(int m, int R, const double *__restrict__ part, MState *st) {
+  if (st->done) return;
+  __shared__ double lds[kMFin];
+  for (int col = 0; col < R; ++col) {
+    const double tot = sum_part(part, m, R, col, lds);
+    if (threadIdx.x == 0) {
+      if (st->cdone[col]) {
+        st->beta[col] = 0.0;
+      } else {
+        st->rz_old[col] = st->rz[col];
+        st->rz[col] = tot;
+        st->beta[col] = st->first ? 0.0 : tot / st->rz_old[col];
+        if (!(tot == tot)) {
+          st->status = -6;
+          st->done = 1;
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kMFin) void k_mcg_pq_fin(int m, int R, const double *__restrict__ part, MState *st) {
+  if (st->done) return;
+  __shared__ double lds[kMFin];
+  for (int col = 0; col < R; ++col) {
+    const double tot = sum_part(part, m, R, col, lds);
+    if (threadIdx.x == 0) {
+      if (st->cdone[col]) {
+        st->alpha[col] = 0.0;
+      } else if (!(tot > 0.0)) {
+        st->status = (tot == tot) ? -4 : -6;
+        st->done = 1;
+        st->alpha[col] = 0.0;
+      } else {
+        st->alpha[col] = st->rz[col] / tot;
+      }
+    }
+  }
+  if (threadIdx.x == 0) st->first = 0;
+}
+
+__global__ __launch_bounds__(kMFin) void k_mcg_update_fin(int m, int R, const double *__restrict__ part, MState *st,
+                                                          int max_iter) {
+  if (st->done) return;
+  __shared__ double lds[kMFin];
+  int all = 1;
+  for (int col = 0; col < R; ++col) {
+    const double tot = sum_part(part, m, R, col, lds);
+    if (threadIdx.x == 0) {
+      if (!st->cdone[col]) {
+        st->rr[col] = tot;
+        st->iters[col] += 1;
+        if (!(tot == tot)) {
+          st->status = -6;
+        } else if (tot <= st->tol2[col]) {
+          st->cdone[col] = 1;
+        } else if (st->iters[col] >= max_iter) {
+          st->status = -5;
+        }
+      }
+      all &= st->cdone[col];
+    }
+  }
+  if (threadIdx.x == 0 && (all || st->status != 0)) st->done = 1;
+}
+
+__global__ __launch_bounds__(kMFin) void k_mcg_aux_fin(int m, int R, const double *__restrict__ part, MState *st) {
+  __shared__ double lds[kMFin];
+  for (int col = 0; col < R; ++col) {
+    const double tot = sum_part(part, m, R, col, lds);
+    if (threadIdx.x == 0) st->aux[col] = tot;
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+#define MR_DISPATCH(R, BODY)                 \
+  switch (R) {                               \
+    case 4: { constexpr int RR = 4; BODY; } break;  \
+    case 8: { constexpr int RR = 8; BODY; } break;  \
+    case 16: { constexpr int RR = 16; BODY; } break; \
+    default: break;                          \
+  }
+#define MK_DISPATCH(K, BODY)                         \
+  switch (K) {                                       \
+    case 9: { constexpr int KK = 9; BODY; } break;   \
+    case 25: { constexpr int KK = 25; BODY; } break; \
+    case 49: { constexpr int KK = 49; BODY; } break; \
+    case 27: { constexpr int KK = 27; BODY; } break; \
+    case 125: { constexpr int KK = 125; BODY; } break; \
+    default: { constexpr int KK = 0; BODY; } break;  \
+  }
+
+bool multi_supported(int R) { return R == 4 || R == 8 || R == 16; }
+
+int multi_blocks(int R, int n) { return std::max(1, (n * R + kMT - 1) / kMT); }
+
+template <typename V>
+static void m_residual_impl(hipStream_t s, int R, int n, int K, const OpView<V> &op, const int32_t *row_lat,
+                            const uint32_t *meta, const double *x, const double *b, double *y, const int32_t *done) {
+  if (n <= 0) return;
+  const int g = multi_blocks(R, n);
+  MR_DISPATCH(R, MK_DISPATCH(K, (k_m_residual<KK, RR, V><<<g, kMT, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done))))
+}
+void launch_m_residual(hipStream_t s, int R, int n, int K, const OpView<double> &op, const int32_t *row_lat,
+                       const uint32_t *meta, const double *x, const double *b, double *y, const int32_t *done) {
+  m_residual_impl<double>(s, R, n, K, op, row_lat, meta, x, b, y, done);
+}
+void launch_m_residual(hipStream_t s, int R, int n, int K, const OpView<float> &op, const int32_t *row_lat,
+                       const uint32_t *meta, const double *x, const double *b, double *y, const int32_t *done) {
+  m_residual_impl<float>(s, R, n, K, op, row_lat, meta, x, b, y, done);
+}
+
+template <typename V>
+static void m_residual_smooth_impl(hipStream_t s, int R, int n, int K, const OpView<V> &op, const int32_t *row_lat,
+                                   const uint32_t *meta, const double *c, const double *xa, const double *r,
+                                   double *rh, double *xb, const int32_t *done) {
+  if (n <= 0) return;
+  const int g = multi_blocks(R, n);
+  MR_DISPATCH(R, MK_DISPATCH(K, (k_m_residual_smooth<KK, RR, V><<<g, kMT, 0, s>>>(n, K, op, row_lat, meta, c, xa, r,
+                                                                                   rh, xb, done))))
+}
+void launch_m_residual_smooth(hipStream_t s, int R, int n, int K, const OpView<double> &op, const int32_t *row_lat,
+                              const uint32_t *meta, const double *c, const double *xa, const double *r, double *rh,
+                              double *xb, const int32_t *done) {
+  m_residual_smooth_impl<double>(s, R, n, K, op, row_lat, meta, c, xa, r, rh, xb, done);
+}
+void launch_m_residual_smooth(hipStream_t s, int R, int n, int K, const OpView<float> &op, const int32_t *row_lat,
+                              const uint32_t *meta, const double *c, const double *xa, const double *r, double *rh,
+                              double *xb, const int32_t *done) {
+  m_residual_smooth_impl<float>(s, R, n, K, op, row_lat, meta, c, xa, r, rh, xb, done);
+}
+
+void launch_m_smooth_general(hipStream_t s, int R, int ng, const int32_t *grow_lat, const int32_t *sptr,
+                             const int32_t *scol, const double *sval, const double *r, double *x,
+                             const int32_t *done) {
+  if (ng <= 0) return;
+  const int g = multi_blocks(R, ng);
+  MR_DISPATCH(R, (k_m_smooth_general<RR><<<g, kMT, 0, s>>>(ng, grow_lat, sptr, scol, sval, r, x, done)))
+}
+
+void launch_m_diag_scale(hipStream_t s, int R, int n, const int32_t *row_lat, const double *c, const double *r,
+                         double *x, const int32_t *done) {
+  if (n <= 0) return;
+  const int g = multi_blocks(R, n);
+  MR_DISPATCH(R, (k_m_diag_scale<RR><<<g, kMT, 0, s>>>(n, row_lat, c, r, x, done)))
+}
+
+void launch_m_tensor_transfer(hipStream_t s, int R, int dim, int n, const int32_t *row_lat, int ox, int oy,
+                              const int32_t *start, const int32_t *len, const double *coef, int W, int ix, int iy,
+                              const double *xin, double *y, int accumulate, const double *cinit, double *xinit,
+                              const int32_t *done) {
+  if (n <= 0) return;
+  const int g = multi_blocks(R, n);
+  MBand b{start, len, coef, W};
+  if (dim == 2) {
+    MR_DISPATCH(R, (k_m_tensor_transfer<2, RR><<<g, kMT, 0, s>>>(n, row_lat, ox, oy, b, ix, iy, xin, y, accumulate,
+                                                                  cinit, xinit, done)))
+  } else {
+    MR_DISPATCH(R, (k_m_tensor_transfer<3, RR><<<g, kMT, 0, s>>>(n, row_lat, ox, oy, b, ix, iy, xin, y, accumulate,
+                                                                  cinit, xinit, done)))
+  }
+}
+
+void launch_m_ell_gather(hipStream_t s, int R, int n, int w, const int32_t *row_lat, const int32_t *col,
+                         const double *v, const double *x, double *y, int accumulate, const double *cinit,
+                         double *xinit, const int32_t *done) {
+  if (n <= 0) return;
+  const int g = multi_blocks(R, n);
+  MR_DISPATCH(R, (k_m_ell_gather<RR><<<g, kMT, 0, s>>>(n, w, row_lat, col, v, x, y, accumulate, cinit, xinit, done)))
+}
+
+void launch_m_dense_gemm(hipStream_t s, int R, int n, const int32_t *row_lat, const double *Ainv, const double *r,
+                         double *x, const int32_t *done) {
+  if (n <= 0) return;
+  const int g = multi_blocks(R, n);
+  MR_DISPATCH(R, (k_m_dense_gemm<RR><<<g, kMT, 0, s>>>(n, row_lat, Ainv, r, x, done)))
+}
+
+void launch_m_scatter(hipStream_t s, int R, int n, int ncols, const int32_t *row_lat, const double *src,
+                      double *dst) {
+  if (n <= 0) return;
+  const int g = multi_blocks(R, n);
+  MR_DISPATCH(R, (k_m_scatter<RR><<<g, kMT, 0, s>>>(n, ncols, row_lat, src, dst)))
+}
+void launch_m_gather(hipStream_t s, int R, int n, int ncols, const int32_t *row_lat, const double *src,
+                     double *dst) {
+  if (n <= 0) return;
+  const int g = multi_blocks(R, n);
+  MR_DISPATCH(R, (k_m_gather<RR><<<g, kMT, 0, s>>>(n, ncols, row_lat, src, dst)))
+}
+
+void launch_mcg_init(hipStream_t s, int R, int ncols, int n, int K, const OpView<double> &op, const int32_t *row_lat,
+                     const uint32_t *meta, const double *x, const double *b, double *r, double *part, MState *st,
+                     double rtol, int restart, int keep_mask) {
+  const int g = multi_blocks(R, n);
+  MR_DISPATCH(R, MK_DISPATCH(K, (k_mcg_init<KK, RR><<<g, kMT, 0, s>>>(n, K, op, row_lat, meta, x, b, r, part))))
+  k_mcg_init_fin<<<1, kMFin, 0, s>>>(g, R, ncols, part, st, rtol, restart, keep_mask);
+}
+void launch_mcg_dot_rz(hipStream_t s, int R, int n, const int32_t *row_lat, const double *r, const double *z,
+                       double *part, MState *st) {
+  const int g = multi_blocks(R, n);
+  MR_DISPATCH(R, (k_mcg_dot<RR><<<g, kMT, 0, s>>>(n, row_lat, r, z, part, st)))
+  k_mcg_rz_fin<<<1, kMFin, 0, s>>>(g, R, part, st);
+}
+void launch_mcg_direction(hipStream_t s, int R, int n, const int32_t *row_lat, const double *z, double *p,
+                          MState *st) {
+  const int g = multi_blocks(R, n);
+  MR_DISPATCH(R, (k_mcg_direction<RR><<<g, kMT, 0, s>>>(n, row_lat, z, p, st)))
+}
+void launch_mcg_spmv_pq(hipStream_t s, int R, int n, int K, const OpView<double> &op, const int32_t *row_lat,
+                        const uint32_t *meta, const double *p, double *q, double *part, MState *st) {
+  const int g = multi_blocks(R, n);
+  MR_DISPATCH(R, MK_DISPATCH(K, (k_mcg_spmv_pq<KK, RR><<<g, kMT, 0, s>>>(n, K, op, row_lat, meta, p, q, part, st))))
+  k_mcg_pq_fin<<<1, kMFin, 0, s>>>(g, R, part, st);
+}
+void launch_mcg_update(hipStream_t s, int R, int n, const int32_t *row_lat, const double *p, const double *q,
+                       double *x, double *r, const double *c, double *zs, double *part, MState *st, int max_iter) {
+  const int g = multi_blocks(R, n);
+  MR_DISPATCH(R, (k_mcg_update<RR><<<g, kMT, 0, s>>>(n, row_lat, p, q, x, r, c, zs, part, st)))
+  k_mcg_update_fin<<<1, kMFin, 0, s>>>(g, R, part, st, max_iter);
+}
+void launch_mcg_true_residual(hipStream_t s, int R, int n, int K, const OpView<double> &op, const int32_t *row_lat,
+                              const uint32_t *meta, const double *x, const double *b, double *part, MState *st) {
+  const int g = multi_blocks(R, n);
+  MR_DISPATCH(R, MK_DISPATCH(K, (k_mcg_true_residual<KK, RR><<<g, kMT, 0, s>>>(n, K, op, row_lat, meta, x, b, part))))
+  k_mcg_aux_fin<<<1, kMFin, 0, s>>>(g, R, part, st);
+}
+
+}  // namespace imsmg

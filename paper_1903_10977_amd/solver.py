@@ -65,7 +65,7 @@ SYMBOLS = ["imsmg_default_options", "imsmg_create", "imsmg_setup", "imsmg_set_pa
            "imsmg_coarse_solve", "imsmg_get_level_stats", "imsmg_kernel_time", "imsmg_last_error", "imsmg_destroy",
            "imsmg_load_mlp", "imsmg_get_patch_features", "imsmg_get_patch_weights", "imsmg_set_block_weights",
            "imsmg_lambda_max", "imsmg_two_grid_objective", "imsmg_mlp_workspace_bytes", "imsmg_mlp_forward",
-           "imsmg_mlp_loss_grad", "imsmg_mlp_adam"]
+           "imsmg_mlp_loss_grad", "imsmg_mlp_adam", "imsmg_vcycle_multi", "imsmg_pcg_solve_multi"]
 MLP_PARAMS = 5313
 NFEAT = 16
 
@@ -116,6 +116,8 @@ def load():
     lib.imsmg_mlp_forward.argtypes = [vp, vp, vp, i32, vp]
     lib.imsmg_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
     lib.imsmg_mlp_adam.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float]
+    lib.imsmg_vcycle_multi.argtypes = [vp, i32, vp, vp]
+    lib.imsmg_pcg_solve_multi.argtypes = [vp, i32, vp, vp, dbl, C.POINTER(Info)]
     for s in SYMBOLS:
         if s not in ("imsmg_default_options", "imsmg_last_error"):
             getattr(lib, s).restype = C.c_int
@@ -330,6 +332,28 @@ class Solver:
         if rc != OK and raise_on_error:
             self._check(rc)
         return SolveInfo(info.status, info.iterations, info.rel_res, info.true_rel_res, info.solve_ms)
+
+    def _devm(self, t):
+        torch = self.torch
+        assert t.dtype == torch.float64 and t.is_cuda and t.dim() == 2 and t.is_contiguous()
+        return C.c_void_p(t.data_ptr())
+
+    def vcycle_multi(self, Rm, Zm=None):
+        """Rm: (nrhs, n) device tensor (row k = right-hand side k)."""
+        Zm = self.torch.zeros_like(Rm) if Zm is None else Zm
+        self._sync()
+        self._check(self.lib.imsmg_vcycle_multi(self.h, Rm.shape[0], self._devm(Rm), self._devm(Zm)))
+        return Zm
+
+    def pcg_multi(self, Bm, Xm, rtol: float = 1e-8, raise_on_error: bool = True):
+        """Bm, Xm: (nrhs, n) device tensors; returns one SolveInfo per column."""
+        k = Bm.shape[0]
+        infos = (Info * k)()
+        self._sync()
+        rc = self.lib.imsmg_pcg_solve_multi(self.h, k, self._devm(Bm), self._devm(Xm), rtol, infos)
+        if rc != OK and raise_on_error:
+            self._check(rc)
+        return [SolveInfo(i.status, i.iterations, i.rel_res, i.true_rel_res, i.solve_ms) for i in infos]
 
     def apply_operator(self, level, x, y=None):
         y = self.empty(level) if y is None else y
