@@ -77,6 +77,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the mixed+learned form")
+    ap.add_argument("--nrhs", type=int, default=16, help="columns of the multi-right-hand-side form (1: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for FETCH_SIZE/WRITE_SIZE scaling)")
     args = ap.parse_args()
@@ -95,7 +96,7 @@ def main():
     levels = int(round(math.log2(args.n // 32))) + 1
     w = W.c2(n=args.n, levels=levels)
     t0 = time.time()
-    g = GN.generate(w)
+    g = GN.generate(w, with_mass=args.nrhs > 1)
     log(f"generated {w.name}: fine DOFs {g.fine.n}, nnz {g.fine.A.nnz}, {time.time() - t0:.1f} s")
     b = torch.tensor(g.b, device="cuda:0")
     n = g.fine.n
@@ -152,6 +153,34 @@ def main():
                        level_status=status)
         log(f"mixed+learned: {args.steps} solves, {iters} iterations, {learned['ms']:.2f} ms/solve, "
             f"level status {status} (1 = network weights kept), true rel. residual {res:.2e}")
+        sol.close()
+    # several right-hand sides with the same matrix: the 16-column form
+    multi = None
+    if args.nrhs > 1:
+        rng = np.random.Generator(np.random.PCG64(1000))
+        M = g.M
+        U = rng.standard_normal((args.nrhs, n))
+        Bm = torch.tensor(np.stack([M @ u for u in U]), device="cuda:0")  # load vectors of random L2 data
+        Bm[0] = b
+        sol = make(head)
+        Xm = torch.zeros_like(Bm)
+        sol.pcg_multi(Bm, Xm, rtol=1e-8)  # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tot_it = 0
+        for _ in range(args.steps):
+            Xm.zero_()
+            infos = sol.pcg_multi(Bm, Xm, rtol=1e-8)
+            tot_it += sum(i.iterations for i in infos)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        worst = max(i.true_rel_res for i in infos)
+        multi = {"nrhs": args.nrhs, "ms_per_solve": round(1e3 * dt / args.steps, 3),
+                 "mdofs": round(n * tot_it / dt / 1e6, 1),
+                 "iterations_per_column": [i.iterations for i in infos], "worst_true_rel_res": worst,
+                 "rhs": "column 0: the workload's load vector; others: load vectors M u of random normal u"}
+        log(f"{args.nrhs} right-hand sides: {multi['ms_per_solve']:.2f} ms per solve, {multi['mdofs']} MDOF/s "
+            f"(DOF x iterations summed over columns), worst true rel. residual {worst:.2e}")
         sol.close()
     hr = results[head]
     ms_step = hr["ms"]
@@ -217,7 +246,8 @@ def main():
                                f"(r ~ U[0.01,0.04]), manufactured sin(2 pi x) sin(2 pi y), {levels}-level V(2,2), "
                                f"PCG to 1e-8 from x0 = 0", "fine_dofs": n, "headline_form": names[head],
                    "pcg_time_s": round(ms_step / 1e3, 5), "forms": forms,
-                   "speedup_mixed_vs_fp64": round(results[S.FP64]["ms"] / results[S.MIXED]["ms"], 3)},
+                   "speedup_mixed_vs_fp64": round(results[S.FP64]["ms"] / results[S.MIXED]["ms"], 3),
+                   "multi_rhs": multi},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_residual_smooth (finest level)", "bytes_per_launch": int(bytes_launch),
