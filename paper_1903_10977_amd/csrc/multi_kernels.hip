@@ -60,6 +60,77 @@ __device__ __forceinline__ double mrow(unsigned meta, const OpView<V> &op, const
   return acc;
 }
 
+// LDS tile of the multi-column stencil kernels: the kMT / R consecutive rows
+// of a workgroup span the lattice range [lo, hi]; for every stencil line the
+// R-column window [lo - p, hi + p] is staged once (contiguous, coalesced) and
+// the K neighbour reads of every (row, column) become LDS reads.  Tiles whose
+// span exceeds twice their row count (holes) read from global memory.
+template <int K, int R>
+struct MTile {
+  static constexpr int TR = kMT / R;
+  static constexpr int W = StencilShape<K>::W, P = StencilShape<K>::P, LINES = StencilShape<K>::LINES;
+  static constexpr int SPAN = 2 * TR;
+  static constexpr int POS = SPAN + 2 * P;
+  static constexpr bool TILED = StencilShape<K>::TILED;
+  static constexpr int LDS = TILED ? LINES * POS * R : 1;
+  static constexpr int CLDS = TILED ? K * TR : 1;  // coefficients of the tile's rows, slot-major
+};
+
+// Stages the tile's x window and the K coefficients of each of its rows (the
+// reference stencil or the row's stored values: one load per (slot, row)
+// instead of one per (slot, row, column)).  Every thread calls it; first < n.
+template <int K, int R, typename V>
+__device__ __forceinline__ int mtile_stage(const int32_t *__restrict__ row_lat, const uint32_t *__restrict__ meta,
+                                           int first, int n, const OpView<V> &op, const double *__restrict__ x,
+                                           double *lds, V *clds) {
+  using T = MTile<K, R>;
+  if constexpr (!T::TILED) {
+    return -1;
+  } else {
+    const int lo = row_lat[first];
+    const int rows = min(first + T::TR, n) - first;
+    const int hi = row_lat[first + rows - 1];
+    if (hi - lo + 1 > T::SPAN) return -1;
+    const int span = hi - lo + 1 + 2 * T::P;
+    const int per_line = span * R;
+    for (int e = threadIdx.x; e < T::LINES * per_line; e += kMT) {
+      const int j = e / per_line, rem = e - j * per_line;
+      const int pos = rem / R, col = rem - pos * R;
+      lds[(j * T::POS + pos) * R + col] = x[size_t(lo - T::P + op.off.off[j * T::W + T::P] + pos) * R + col];
+    }
+    for (int e = threadIdx.x; e < K * T::TR; e += kMT) {
+      const int sl = e / T::TR, r = e - sl * T::TR;
+      if (r < rows) {
+        const unsigned g = meta[first + r] & kMetaIndex;
+        clds[e] = g == kMetaIndex ? op.ref[sl] : op.val[size_t(sl) * op.nv + g];
+      }
+    }
+    __syncthreads();
+    return lo;
+  }
+}
+
+// (A x)_{L, col} for local row lr from the tile (lo >= 0) or by global reads; also x_{L, col}
+template <int K, int R, typename V>
+__device__ __forceinline__ double mtile_row(unsigned meta, const OpView<V> &op, const double *__restrict__ x,
+                                            const double *lds, const V *clds, int lr, int L, int lo, int col, int Kdyn,
+                                            double *xc) {
+  using T = MTile<K, R>;
+  if constexpr (T::TILED) {
+    if (lo >= 0) {
+      const double *t = lds + (L - lo) * R + col;
+      const V *cf = clds + lr;
+      double acc = 0.0;
+#pragma unroll
+      for (int s = 0; s < K; ++s) acc += double(cf[s * T::TR]) * t[((s / T::W) * T::POS + s % T::W) * R];
+      *xc = t[((T::LINES / 2) * T::POS + T::P) * R];
+      return acc;
+    }
+  }
+  *xc = x[size_t(L) * R + col];
+  return mrow<K, R, V>(meta, op, x, L, col, Kdyn);
+}
+
 // per-column sum over the workgroup's rows (lds: kMT doubles); result valid in
 // threads 0 .. R-1 (column = thread index)
 template <int R>
@@ -90,22 +161,26 @@ __device__ __forceinline__ double sum_part(const double *__restrict__ part, int 
 
 // ------------------------------------------------------------------ level kernels
 template <int K, int R, typename V>
-__global__ __launch_bounds__(kMT) void k_m_residual(int n, int Kdyn, OpView<V> op, const int32_t *__restrict__ row_lat,
+__global__ __launch_bounds__(kMT, 4) void k_m_residual(int n, int Kdyn, OpView<V> op, const int32_t *__restrict__ row_lat,
                                                     const uint32_t *__restrict__ meta, const double *__restrict__ x,
                                                     const double *__restrict__ b, double *__restrict__ y,
                                                     const int32_t *__restrict__ done) {
   if (done && *done) return;
-  const int t = xcd_map(blockIdx.x, gridDim.x) * kMT + threadIdx.x;
-  const int i = t / R, col = t % R;
+  __shared__ double tile[MTile<K, R>::LDS];
+  __shared__ V clds[MTile<K, R>::CLDS];
+  const int first = xcd_map(blockIdx.x, gridDim.x) * MTile<K, R>::TR;
+  const int lr = threadIdx.x / R, i = first + lr, col = threadIdx.x % R;
+  const int lo = mtile_stage<K, R, V>(row_lat, meta, first, n, op, x, tile, clds);
   if (i >= n) return;
   const int L = row_lat[i];
-  const double ax = mrow<K, R, V>(meta[i], op, x, L, col, Kdyn);
+  double xc;
+  const double ax = mtile_row<K, R, V>(meta[i], op, x, tile, clds, lr, L, lo, col, Kdyn, &xc);
   const size_t o = size_t(L) * R + col;
   y[o] = b ? b[o] - ax : ax;
 }
 
 template <int K, int R, typename V>
-__global__ __launch_bounds__(kMT) void k_m_residual_smooth(int n, int Kdyn, OpView<V> op,
+__global__ __launch_bounds__(kMT, 4) void k_m_residual_smooth(int n, int Kdyn, OpView<V> op,
                                                            const int32_t *__restrict__ row_lat,
                                                            const uint32_t *__restrict__ meta,
                                                            const double *__restrict__ c,
@@ -113,16 +188,20 @@ __global__ __launch_bounds__(kMT) void k_m_residual_smooth(int n, int Kdyn, OpVi
                                                            const double *__restrict__ r, double *__restrict__ rh,
                                                            double *__restrict__ xb, const int32_t *__restrict__ done) {
   if (done && *done) return;
-  const int t = xcd_map(blockIdx.x, gridDim.x) * kMT + threadIdx.x;
-  const int i = t / R, col = t % R;
+  __shared__ double tile[MTile<K, R>::LDS];
+  __shared__ V clds[MTile<K, R>::CLDS];
+  const int first = xcd_map(blockIdx.x, gridDim.x) * MTile<K, R>::TR;
+  const int lr = threadIdx.x / R, i = first + lr, col = threadIdx.x % R;
+  const int lo = mtile_stage<K, R, V>(row_lat, meta, first, n, op, xa, tile, clds);
   if (i >= n) return;
   const int L = row_lat[i];
   const unsigned m = meta[i];
-  const double ax = mrow<K, R, V>(m, op, xa, L, col, Kdyn);
+  double xc;
+  const double ax = mtile_row<K, R, V>(m, op, xa, tile, clds, lr, L, lo, col, Kdyn, &xc);
   const size_t o = size_t(L) * R + col;
   const double res = r[o] - ax;
   if (m & kMetaGeneral) rh[o] = res;
-  xb[o] = xa[o] + c[i] * res;
+  xb[o] = xc + c[i] * res;
 }
 
 template <int R>
@@ -273,21 +352,25 @@ __global__ void k_m_gather(int n, int ncols, const int32_t *__restrict__ row_lat
 // ------------------------------------------------------------------ CG kernels
 // (finest level, FP64 operator)
 template <int K, int R>
-__global__ __launch_bounds__(kMT) void k_mcg_init(int n, int Kdyn, OpView<double> op,
+__global__ __launch_bounds__(kMT, 4) void k_mcg_init(int n, int Kdyn, OpView<double> op,
                                                   const int32_t *__restrict__ row_lat,
                                                   const uint32_t *__restrict__ meta, const double *__restrict__ x,
                                                   const double *__restrict__ b, double *__restrict__ r,
                                                   double *__restrict__ part) {
   __shared__ double lds[kMT];
+  __shared__ double tile[MTile<K, R>::LDS];
+  __shared__ double clds[MTile<K, R>::CLDS];
   const int blk = xcd_map(blockIdx.x, gridDim.x);
-  const int t = blk * kMT + threadIdx.x;
-  const int i = t / R, col = t % R;
+  const int first = blk * MTile<K, R>::TR;
+  const int lr = threadIdx.x / R, i = first + lr, col = threadIdx.x % R;
+  const int lo = mtile_stage<K, R, double>(row_lat, meta, first, n, op, x, tile, clds);
   double rr = 0.0, bb = 0.0;
   if (i < n) {
     const int L = row_lat[i];
     const size_t o = size_t(L) * R + col;
     const double bi = b[o];
-    const double ri = bi - mrow<K, R, double>(meta[i], op, x, L, col, Kdyn);
+    double xc;
+    const double ri = bi - mtile_row<K, R, double>(meta[i], op, x, tile, clds, lr, L, lo, col, Kdyn, &xc);
     r[o] = ri;
     rr = ri * ri;
     bb = bi * bi;
@@ -331,23 +414,27 @@ __global__ __launch_bounds__(kMT) void k_mcg_direction(int n, const int32_t *__r
 }
 
 template <int K, int R>
-__global__ __launch_bounds__(kMT) void k_mcg_spmv_pq(int n, int Kdyn, OpView<double> op,
+__global__ __launch_bounds__(kMT, 4) void k_mcg_spmv_pq(int n, int Kdyn, OpView<double> op,
                                                      const int32_t *__restrict__ row_lat,
                                                      const uint32_t *__restrict__ meta, const double *__restrict__ p,
                                                      double *__restrict__ q, double *__restrict__ part,
                                                      const MState *st) {
   if (st->done) return;
   __shared__ double lds[kMT];
+  __shared__ double tile[MTile<K, R>::LDS];
+  __shared__ double clds[MTile<K, R>::CLDS];
   const int blk = xcd_map(blockIdx.x, gridDim.x);
-  const int t = blk * kMT + threadIdx.x;
-  const int i = t / R, col = t % R;
+  const int first = blk * MTile<K, R>::TR;
+  const int lr = threadIdx.x / R, i = first + lr, col = threadIdx.x % R;
+  const int lo = mtile_stage<K, R, double>(row_lat, meta, first, n, op, p, tile, clds);
   double acc = 0.0;
   if (i < n) {
     const int L = row_lat[i];
     const size_t o = size_t(L) * R + col;
-    const double qi = mrow<K, R, double>(meta[i], op, p, L, col, Kdyn);
+    double pc;
+    const double qi = mtile_row<K, R, double>(meta[i], op, p, tile, clds, lr, L, lo, col, Kdyn, &pc);
     q[o] = qi;
-    acc = p[o] * qi;
+    acc = pc * qi;
   }
   acc = col_sum<R>(acc, lds);
   if (threadIdx.x < R) part[size_t(blk) * R + threadIdx.x] = acc;
@@ -379,23 +466,48 @@ __global__ __launch_bounds__(kMT) void k_mcg_update(int n, const int32_t *__rest
 }
 
 template <int K, int R>
-__global__ __launch_bounds__(kMT) void k_mcg_true_residual(int n, int Kdyn, OpView<double> op,
+__global__ __launch_bounds__(kMT, 4) void k_mcg_true_residual(int n, int Kdyn, OpView<double> op,
                                                            const int32_t *__restrict__ row_lat,
                                                            const uint32_t *__restrict__ meta,
                                                            const double *__restrict__ x,
                                                            const double *__restrict__ b, double *__restrict__ part) {
   __shared__ double lds[kMT];
+  __shared__ double tile[MTile<K, R>::LDS];
+  __shared__ double clds[MTile<K, R>::CLDS];
   const int blk = xcd_map(blockIdx.x, gridDim.x);
-  const int t = blk * kMT + threadIdx.x;
-  const int i = t / R, col = t % R;
+  const int first = blk * MTile<K, R>::TR;
+  const int lr = threadIdx.x / R, i = first + lr, col = threadIdx.x % R;
+  const int lo = mtile_stage<K, R, double>(row_lat, meta, first, n, op, x, tile, clds);
   double acc = 0.0;
   if (i < n) {
     const int L = row_lat[i];
-    const double ri = b[size_t(L) * R + col] - mrow<K, R, double>(meta[i], op, x, L, col, Kdyn);
+    double xc;
+    const double ri = b[size_t(L) * R + col] - mtile_row<K, R, double>(meta[i], op, x, tile, clds, lr, L, lo, col, Kdyn, &xc);
     acc = ri * ri;
   }
   acc = col_sum<R>(acc, lds);
   if (threadIdx.x < R) part[size_t(blk) * R + threadIdx.x] = acc;
+}
+
+// ---- first stage of the partial sums: workgroup b adds the partials of a
+// contiguous range of source workgroups for all R columns (coalesced reads,
+// fixed order) -> out[b * R + col]
+constexpr int kStage = 256;  // second-stage partials per column
+__global__ __launch_bounds__(kMT) void k_mcg_stage(int m, int R, const double *__restrict__ part,
+                                                   double *__restrict__ out) {
+  __shared__ double lds[kMT];
+  const int per = (m + kStage - 1) / kStage;
+  const int b0 = blockIdx.x * per, b1 = min(m, b0 + per);
+  const int col = threadIdx.x % R, lane = threadIdx.x / R, lanes = kMT / R;
+  double v = 0.0;
+  for (int b = b0 + lane; b < b1; b += lanes) v += part[size_t(b) * R + col];
+  lds[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kMT / 2; s >= R; s >>= 1) {
+    if (threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < R) out[size_t(blockIdx.x) * R + threadIdx.x] = lds[threadIdx.x];
 }
 
 // ---- finalize kernels (one workgroup; columns one after the other)
@@ -528,6 +640,8 @@ __global__ __launch_bounds__(kMFin) void k_mcg_aux_fin(int m, int R, const doubl
 bool multi_supported(int R) { return R == 4 || R == 8 || R == 16; }
 
 int multi_blocks(int R, int n) { return std::max(1, (n * R + kMT - 1) / kMT); }
+// partial-sum workspace (doubles): two first-level arrays and the second stage
+size_t multi_part_size(int R, int n) { return size_t(2) * multi_blocks(R, n) * R + size_t(2) * kStage * R; }
 
 template <typename V>
 static void m_residual_impl(hipStream_t s, int R, int n, int K, const OpView<V> &op, const int32_t *row_lat,
@@ -629,13 +743,18 @@ void launch_mcg_init(hipStream_t s, int R, int ncols, int n, int K, const OpView
                      double rtol, int restart, int keep_mask) {
   const int g = multi_blocks(R, n);
   MR_DISPATCH(R, MK_DISPATCH(K, (k_mcg_init<KK, RR><<<g, kMT, 0, s>>>(n, K, op, row_lat, meta, x, b, r, part))))
-  k_mcg_init_fin<<<1, kMFin, 0, s>>>(g, R, ncols, part, st, rtol, restart, keep_mask);
+  double *p2 = part + size_t(2) * g * R;
+  k_mcg_stage<<<kStage, kMT, 0, s>>>(g, R, part, p2);
+  k_mcg_stage<<<kStage, kMT, 0, s>>>(g, R, part + size_t(g) * R, p2 + size_t(kStage) * R);
+  k_mcg_init_fin<<<1, kMFin, 0, s>>>(kStage, R, ncols, p2, st, rtol, restart, keep_mask);
 }
 void launch_mcg_dot_rz(hipStream_t s, int R, int n, const int32_t *row_lat, const double *r, const double *z,
                        double *part, MState *st) {
   const int g = multi_blocks(R, n);
   MR_DISPATCH(R, (k_mcg_dot<RR><<<g, kMT, 0, s>>>(n, row_lat, r, z, part, st)))
-  k_mcg_rz_fin<<<1, kMFin, 0, s>>>(g, R, part, st);
+  double *p2 = part + size_t(2) * g * R;
+  k_mcg_stage<<<kStage, kMT, 0, s>>>(g, R, part, p2);
+  k_mcg_rz_fin<<<1, kMFin, 0, s>>>(kStage, R, p2, st);
 }
 void launch_mcg_direction(hipStream_t s, int R, int n, const int32_t *row_lat, const double *z, double *p,
                           MState *st) {
@@ -646,19 +765,25 @@ void launch_mcg_spmv_pq(hipStream_t s, int R, int n, int K, const OpView<double>
                         const uint32_t *meta, const double *p, double *q, double *part, MState *st) {
   const int g = multi_blocks(R, n);
   MR_DISPATCH(R, MK_DISPATCH(K, (k_mcg_spmv_pq<KK, RR><<<g, kMT, 0, s>>>(n, K, op, row_lat, meta, p, q, part, st))))
-  k_mcg_pq_fin<<<1, kMFin, 0, s>>>(g, R, part, st);
+  double *p2 = part + size_t(2) * g * R;
+  k_mcg_stage<<<kStage, kMT, 0, s>>>(g, R, part, p2);
+  k_mcg_pq_fin<<<1, kMFin, 0, s>>>(kStage, R, p2, st);
 }
 void launch_mcg_update(hipStream_t s, int R, int n, const int32_t *row_lat, const double *p, const double *q,
                        double *x, double *r, const double *c, double *zs, double *part, MState *st, int max_iter) {
   const int g = multi_blocks(R, n);
   MR_DISPATCH(R, (k_mcg_update<RR><<<g, kMT, 0, s>>>(n, row_lat, p, q, x, r, c, zs, part, st)))
-  k_mcg_update_fin<<<1, kMFin, 0, s>>>(g, R, part, st, max_iter);
+  double *p2 = part + size_t(2) * g * R;
+  k_mcg_stage<<<kStage, kMT, 0, s>>>(g, R, part, p2);
+  k_mcg_update_fin<<<1, kMFin, 0, s>>>(kStage, R, p2, st, max_iter);
 }
 void launch_mcg_true_residual(hipStream_t s, int R, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                               const uint32_t *meta, const double *x, const double *b, double *part, MState *st) {
   const int g = multi_blocks(R, n);
   MR_DISPATCH(R, MK_DISPATCH(K, (k_mcg_true_residual<KK, RR><<<g, kMT, 0, s>>>(n, K, op, row_lat, meta, x, b, part))))
-  k_mcg_aux_fin<<<1, kMFin, 0, s>>>(g, R, part, st);
+  double *p2 = part + size_t(2) * g * R;
+  k_mcg_stage<<<kStage, kMT, 0, s>>>(g, R, part, p2);
+  k_mcg_aux_fin<<<1, kMFin, 0, s>>>(kStage, R, p2, st);
 }
 
 }  // namespace imsmg

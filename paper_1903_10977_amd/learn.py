@@ -15,6 +15,8 @@ Training, all on the GPU through the library:
      squared error by the library's backpropagation and Adam kernels.
 
     python3 -m paper_1903_10977_amd.learn --problems 48 --out paper_1903_10977_amd/models/omega_mlp
+    python3 -m paper_1903_10977_amd.learn --family gyroid3d --problems 64 \
+        --out paper_1903_10977_amd/models/omega_mlp_gyroid3d
 """
 from __future__ import annotations
 
@@ -38,10 +40,17 @@ def _log(msg):
     print(f"[learn] {msg}", file=sys.stderr, flush=True)
 
 
-def training_workloads(count: int, seed0: int = 10000):
-    """Two-level 2D cubic B-spline problems, unit square minus 4..12 random
-    discs (radii U[0.03, 0.12]), 32^2 or 64^2 elements, one bisection level."""
+FAMILIES = ("discs2d", "gyroid3d")
+
+
+def training_workloads(count: int, seed0: int = 10000, family: str = "discs2d"):
+    """Two-level training problems.  discs2d: 2D cubic B-splines, unit square
+    minus 4..12 random discs (radii U[0.03, 0.12]), 32^2 or 64^2 elements, one
+    bisection level.  gyroid3d: 16^3 windows of the gyroid at the element
+    size of a 96^3 grid (quadratic B-splines, random offset and phase)."""
     import workloads as W
+    if family == "gyroid3d":
+        return [W.gyroid_window(seed0 + i) for i in range(count)]
     out = []
     for i in range(count):
         rng = np.random.Generator(np.random.PCG64(seed0 + i))
@@ -94,10 +103,10 @@ def labels(sol, rng, m=8, k=8, steps=60, lr=0.05, lam_target=1.7):
     return th, J0, J1
 
 
-def train(problems=48, label_steps=60, train_steps=3000, lr=1e-3, seed=0):
+def train(problems=48, label_steps=60, train_steps=3000, lr=1e-3, seed=0, family="discs2d"):
     import torch
     X, T, rep = [], [], []
-    for i, w in enumerate(training_workloads(problems)):
+    for i, w in enumerate(training_workloads(problems, family=family)):
         t0 = time.time()
         g = GN.generate(w)
         sol = S.Solver(0).setup(g, S.default_options(nu_pre=1, nu_post=1)).factor()
@@ -125,7 +134,7 @@ def train(problems=48, label_steps=60, train_steps=3000, lr=1e-3, seed=0):
     o = S.mlp_forward(tr.params, Xd).cpu().numpy()
     report = {"problems": rep, "samples": int(X.shape[0]), "label_var": float(T.var()),
               "final_mse": float(np.mean((o - T) ** 2)), "losses": losses,
-              "label_steps": label_steps, "train_steps": train_steps, "lr": lr, "seed": seed}
+              "label_steps": label_steps, "train_steps": train_steps, "lr": lr, "seed": seed, "family": family}
     return params, report
 
 
@@ -144,32 +153,40 @@ def load_params(path=MODEL_DEFAULT):
     return th.astype(np.float32)
 
 
-def evaluate(workloads, params, precision=S.FP64):
-    """PCG iterations and time with gamma and with the network's weights."""
+def evaluate(workloads, params, precision=S.FP64, scales=(0.8, 1.25, 1.6)):
+    """PCG iterations and time with gamma, with uniformly scaled gamma (the
+    tuned-scalar comparison) and with the network's weights."""
     import torch
     out = []
     for w in workloads:
+        t0 = time.time()
         g = GN.generate(w)
+        _log(f"{w.name}: generated {g.fine.n} DOFs in {time.time() - t0:.1f} s")
         b = torch.tensor(g.b, device="cuda:0")
         row = {"problem": w.name, "fine_dofs": int(g.fine.n), "levels": len(g.levels)}
-        for form in ("gamma", "learned"):
+        forms = ["gamma"] + [f"gamma x {sc}" for sc in scales] + ["learned"]
+        for form in forms:
             o = S.default_options(nu_pre=w.nu, nu_post=w.nu, precision=precision, max_iter=2000,
                                   use_learned=int(form == "learned"))
             sol = S.Solver(0).setup(g, o)
             if form == "learned":
                 sol.load_mlp(params)
             sol.factor()
+            if form.startswith("gamma x"):
+                sc = float(form.split("x")[1])
+                for l in range(1, len(g.levels)):
+                    sol.set_block_weights(l, sc * sol.weights(l)[0])
             x = torch.zeros_like(b)
-            sol.pcg(b, x, rtol=1e-8)  # warm-up (graph capture)
+            sol.pcg(b, x, rtol=1e-8, raise_on_error=False)  # warm-up (graph capture)
             x.zero_()
-            info = sol.pcg(b, x, rtol=1e-8)
+            info = sol.pcg(b, x, rtol=1e-8, raise_on_error=False)
             st = [sol.weights(l)[1] for l in range(1, len(g.levels))]
             row[form] = {"iterations": info.iterations, "ms": info.solve_ms, "true_rel_res": info.true_rel_res,
-                         "level_status": st}
+                         "status": info.status, "level_status": st}
             sol.close()
         out.append(row)
-        _log(f"{w.name}: gamma {row['gamma']['iterations']} it, learned {row['learned']['iterations']} it "
-             f"(levels accepted {row['learned']['level_status']})")
+        _log(f"{w.name}: " + ", ".join(f"{f} {row[f]['iterations']} it" for f in forms) +
+             f" (levels with network weights {row['learned']['level_status']})")
     return out
 
 
@@ -182,12 +199,19 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=MODEL_DEFAULT)
     ap.add_argument("--evaluate", action="store_true", help="after training, compare PCG with gamma and learned")
+    ap.add_argument("--family", choices=FAMILIES, default="discs2d")
+    ap.add_argument("--eval-n", type=int, nargs="*", default=None, help="evaluation grid sizes")
     a = ap.parse_args(argv)
-    params, report = train(a.problems, a.label_steps, a.train_steps, a.lr, a.seed)
+    params, report = train(a.problems, a.label_steps, a.train_steps, a.lr, a.seed, a.family)
     if a.evaluate:
         import workloads as W
-        report["evaluation"] = evaluate([W.c2(n=128, levels=3), W.c2(n=256, levels=4), W.c2(n=512, levels=5)],
-                                        params)
+        if a.family == "gyroid3d":
+            ns = a.eval_n or [48, 96]
+            ws = [W.c5(n=n, levels=3 if n <= 48 else 4) for n in ns]
+        else:
+            ns = a.eval_n or [128, 256, 512]
+            ws = [W.c2(n=n, levels=int(round(np.log2(n // 32))) + 1) for n in ns]
+        report["evaluation"] = evaluate(ws, params)
     save(params, report, a.out)
     _log(f"saved {a.out}.npy (final mse {report['final_mse']:.4f}, label variance {report['label_var']:.4f})")
 

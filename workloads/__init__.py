@@ -157,6 +157,24 @@ def small_gyroid(seed: int, n: int, degree: int = 2, levels: int = 2) -> Workloa
                     geometry="gyroid", phase=gyroid_phase(seed).tolist(), rhs="one", nu=1)
 
 
+def c5(seed: int = 5, n: int = 96, levels: int = 4) -> Workload:
+    """3D Poisson, quadratic B-splines, n^3 gyroid {g < 0.3} (two periods,
+    seeded phase), f = 1, u = 0 on the box, V(1,1): the learned-damping test."""
+    return Workload(name="C5" if n == 96 else f"C5-{n}", dim=3, degree=2, n=n, depth=0, levels=levels,
+                    geometry="gyroid", phase=gyroid_phase(seed).tolist(), rhs="one", nu=1)
+
+
+def gyroid_window(seed: int, n: int = 16, resolution: int = 96, levels: int = 2) -> Workload:
+    """An n^3 sub-window of the gyroid at the element size of a resolution^3
+    grid of the unit cube: random offset along the diagonal, random phase."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    width = n / resolution
+    lo = float(rng.uniform(0.0, 1.0 - width))
+    return Workload(name=f"gyroid-window-s{seed}", dim=3, degree=2, n=n, depth=0, levels=levels,
+                    geometry="gyroid", phase=gyroid_phase(seed + 7919).tolist(), rhs="one", nu=1,
+                    box_lo=lo, box_hi=lo + width)
+
+
 def batched_c4(index: int) -> Workload:
     """Problem `index` (0..63) of the batched workload: n ~ U{64,128,256,512},
     p ~ U{1,2,3}, 10..100 discs with radii U[0.01,0.04], depth log2(1024/n)."""
