@@ -78,6 +78,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the mixed+learned form")
     ap.add_argument("--nrhs", type=int, default=16, help="columns of the multi-right-hand-side form (1: skip)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-problem form")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for FETCH_SIZE/WRITE_SIZE scaling)")
     args = ap.parse_args()
@@ -182,6 +183,12 @@ def main():
         log(f"{args.nrhs} right-hand sides: {multi['ms_per_solve']:.2f} ms per solve, {multi['mdofs']} MDOF/s "
             f"(DOF x iterations summed over columns), worst true rel. residual {worst:.2e}")
         sol.close()
+    # batched: 64 independent problems (n in {64..512}^2, p in {1,2,3}), 16
+    # right-hand sides each, one context and stream per problem, 4 host threads
+    batched = None
+    if not args.no_batched:
+        from paper_1903_10977_amd import batch as BT
+        batched = BT.run_batch(64, 16, workers=4, steps=2, precision=head)
     hr = results[head]
     ms_step = hr["ms"]
     value = hr["mdofs"]
@@ -247,7 +254,7 @@ def main():
                                f"PCG to 1e-8 from x0 = 0", "fine_dofs": n, "headline_form": names[head],
                    "pcg_time_s": round(ms_step / 1e3, 5), "forms": forms,
                    "speedup_mixed_vs_fp64": round(results[S.FP64]["ms"] / results[S.MIXED]["ms"], 3),
-                   "multi_rhs": multi},
+                   "multi_rhs": multi, "batched": batched},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_residual_smooth (finest level)", "bytes_per_launch": int(bytes_launch),

@@ -345,11 +345,15 @@ class Solver:
         self._check(self.lib.imsmg_vcycle_multi(self.h, Rm.shape[0], self._devm(Rm), self._devm(Zm)))
         return Zm
 
-    def pcg_multi(self, Bm, Xm, rtol: float = 1e-8, raise_on_error: bool = True):
-        """Bm, Xm: (nrhs, n) device tensors; returns one SolveInfo per column."""
+    def pcg_multi(self, Bm, Xm, rtol: float = 1e-8, raise_on_error: bool = True, sync: bool = True):
+        """Bm, Xm: (nrhs, n) device tensors; returns one SolveInfo per column.
+        sync=False skips the device-wide synchronization before the call (the
+        caller guarantees that Bm and Xm are complete, e.g. several contexts
+        driven from host threads)."""
         k = Bm.shape[0]
         infos = (Info * k)()
-        self._sync()
+        if sync:
+            self._sync()
         rc = self.lib.imsmg_pcg_solve_multi(self.h, k, self._devm(Bm), self._devm(Xm), rtol, infos)
         if rc != OK and raise_on_error:
             self._check(rc)
