@@ -18,7 +18,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/imsmg.h"
+#include "imsmg.h"
 #include "imsmg_internal.h"
 
 using namespace imsmg;

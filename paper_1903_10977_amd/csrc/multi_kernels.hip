@@ -15,7 +15,6 @@
 // (fixed LDS tree over the workgroup's rows), then one workgroup adds the
 // partials of each column in index order.
 #include "imsmg_internal.h"
-#include "op_row.h"
 
 namespace imsmg {
 
@@ -30,16 +29,6 @@ __device__ __forceinline__ int xcd_map(int b, int nb) {
   const int full = nb % 8 == 0 ? 8 : nb % 8;
   if (xcd < full) return xcd * per + k;
   return full * per + (xcd - full) * (per - 1) + k;
-}
-
-template <int R>
-__host__ __device__ constexpr int rows_per_block() {
-  return kMT / R;
-}
-
-template <int R>
-inline int mgrid(int n) {
-  return std::max(1, (n + rows_per_block<R>() - 1) / rows_per_block<R>());
 }
 
 // (A x)_{L, col} with per-lane coefficient select (reference or stored row)
@@ -58,77 +47,6 @@ __device__ __forceinline__ double mrow(unsigned meta, const OpView<V> &op, const
     for (int s = 0; s < Kdyn; ++s) acc += double(v[s * st]) * x[size_t(L + op.off.off[s]) * R + col];
   }
   return acc;
-}
-
-// LDS tile of the multi-column stencil kernels: the kMT / R consecutive rows
-// of a workgroup span the lattice range [lo, hi]; for every stencil line the
-// R-column window [lo - p, hi + p] is staged once (contiguous, coalesced) and
-// the K neighbour reads of every (row, column) become LDS reads.  Tiles whose
-// span exceeds twice their row count (holes) read from global memory.
-template <int K, int R>
-struct MTile {
-  static constexpr int TR = kMT / R;
-  static constexpr int W = StencilShape<K>::W, P = StencilShape<K>::P, LINES = StencilShape<K>::LINES;
-  static constexpr int SPAN = 2 * TR;
-  static constexpr int POS = SPAN + 2 * P;
-  static constexpr bool TILED = StencilShape<K>::TILED;
-  static constexpr int LDS = TILED ? LINES * POS * R : 1;
-  static constexpr int CLDS = TILED ? K * TR : 1;  // coefficients of the tile's rows, slot-major
-};
-
-// Stages the tile's x window and the K coefficients of each of its rows (the
-// reference stencil or the row's stored values: one load per (slot, row)
-// instead of one per (slot, row, column)).  Every thread calls it; first < n.
-template <int K, int R, typename V>
-__device__ __forceinline__ int mtile_stage(const int32_t *__restrict__ row_lat, const uint32_t *__restrict__ meta,
-                                           int first, int n, const OpView<V> &op, const double *__restrict__ x,
-                                           double *lds, V *clds) {
-  using T = MTile<K, R>;
-  if constexpr (!T::TILED) {
-    return -1;
-  } else {
-    const int lo = row_lat[first];
-    const int rows = min(first + T::TR, n) - first;
-    const int hi = row_lat[first + rows - 1];
-    if (hi - lo + 1 > T::SPAN) return -1;
-    const int span = hi - lo + 1 + 2 * T::P;
-    const int per_line = span * R;
-    for (int e = threadIdx.x; e < T::LINES * per_line; e += kMT) {
-      const int j = e / per_line, rem = e - j * per_line;
-      const int pos = rem / R, col = rem - pos * R;
-      lds[(j * T::POS + pos) * R + col] = x[size_t(lo - T::P + op.off.off[j * T::W + T::P] + pos) * R + col];
-    }
-    for (int e = threadIdx.x; e < K * T::TR; e += kMT) {
-      const int sl = e / T::TR, r = e - sl * T::TR;
-      if (r < rows) {
-        const unsigned g = meta[first + r] & kMetaIndex;
-        clds[e] = g == kMetaIndex ? op.ref[sl] : op.val[size_t(sl) * op.nv + g];
-      }
-    }
-    __syncthreads();
-    return lo;
-  }
-}
-
-// (A x)_{L, col} for local row lr from the tile (lo >= 0) or by global reads; also x_{L, col}
-template <int K, int R, typename V>
-__device__ __forceinline__ double mtile_row(unsigned meta, const OpView<V> &op, const double *__restrict__ x,
-                                            const double *lds, const V *clds, int lr, int L, int lo, int col, int Kdyn,
-                                            double *xc) {
-  using T = MTile<K, R>;
-  if constexpr (T::TILED) {
-    if (lo >= 0) {
-      const double *t = lds + (L - lo) * R + col;
-      const V *cf = clds + lr;
-      double acc = 0.0;
-#pragma unroll
-      for (int s = 0; s < K; ++s) acc += double(cf[s * T::TR]) * t[((s / T::W) * T::POS + s % T::W) * R];
-      *xc = t[((T::LINES / 2) * T::POS + T::P) * R];
-      return acc;
-    }
-  }
-  *xc = x[size_t(L) * R + col];
-  return mrow<K, R, V>(meta, op, x, L, col, Kdyn);
 }
 
 // per-column sum over the workgroup's rows (lds: kMT doubles); result valid in
@@ -161,26 +79,22 @@ __device__ __forceinline__ double sum_part(const double *__restrict__ part, int 
 
 // ------------------------------------------------------------------ level kernels
 template <int K, int R, typename V>
-__global__ __launch_bounds__(kMT, 4) void k_m_residual(int n, int Kdyn, OpView<V> op, const int32_t *__restrict__ row_lat,
+__global__ __launch_bounds__(kMT) void k_m_residual(int n, int Kdyn, OpView<V> op, const int32_t *__restrict__ row_lat,
                                                     const uint32_t *__restrict__ meta, const double *__restrict__ x,
                                                     const double *__restrict__ b, double *__restrict__ y,
                                                     const int32_t *__restrict__ done) {
   if (done && *done) return;
-  __shared__ double tile[MTile<K, R>::LDS];
-  __shared__ V clds[MTile<K, R>::CLDS];
-  const int first = xcd_map(blockIdx.x, gridDim.x) * MTile<K, R>::TR;
-  const int lr = threadIdx.x / R, i = first + lr, col = threadIdx.x % R;
-  const int lo = mtile_stage<K, R, V>(row_lat, meta, first, n, op, x, tile, clds);
+  const int t = xcd_map(blockIdx.x, gridDim.x) * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
   if (i >= n) return;
   const int L = row_lat[i];
-  double xc;
-  const double ax = mtile_row<K, R, V>(meta[i], op, x, tile, clds, lr, L, lo, col, Kdyn, &xc);
+  const double ax = mrow<K, R, V>(meta[i], op, x, L, col, Kdyn);
   const size_t o = size_t(L) * R + col;
   y[o] = b ? b[o] - ax : ax;
 }
 
 template <int K, int R, typename V>
-__global__ __launch_bounds__(kMT, 4) void k_m_residual_smooth(int n, int Kdyn, OpView<V> op,
+__global__ __launch_bounds__(kMT) void k_m_residual_smooth(int n, int Kdyn, OpView<V> op,
                                                            const int32_t *__restrict__ row_lat,
                                                            const uint32_t *__restrict__ meta,
                                                            const double *__restrict__ c,
@@ -188,20 +102,16 @@ __global__ __launch_bounds__(kMT, 4) void k_m_residual_smooth(int n, int Kdyn, O
                                                            const double *__restrict__ r, double *__restrict__ rh,
                                                            double *__restrict__ xb, const int32_t *__restrict__ done) {
   if (done && *done) return;
-  __shared__ double tile[MTile<K, R>::LDS];
-  __shared__ V clds[MTile<K, R>::CLDS];
-  const int first = xcd_map(blockIdx.x, gridDim.x) * MTile<K, R>::TR;
-  const int lr = threadIdx.x / R, i = first + lr, col = threadIdx.x % R;
-  const int lo = mtile_stage<K, R, V>(row_lat, meta, first, n, op, xa, tile, clds);
+  const int t = xcd_map(blockIdx.x, gridDim.x) * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
   if (i >= n) return;
   const int L = row_lat[i];
   const unsigned m = meta[i];
-  double xc;
-  const double ax = mtile_row<K, R, V>(m, op, xa, tile, clds, lr, L, lo, col, Kdyn, &xc);
+  const double ax = mrow<K, R, V>(m, op, xa, L, col, Kdyn);
   const size_t o = size_t(L) * R + col;
   const double res = r[o] - ax;
   if (m & kMetaGeneral) rh[o] = res;
-  xb[o] = xc + c[i] * res;
+  xb[o] = xa[o] + c[i] * res;
 }
 
 template <int R>
@@ -352,25 +262,21 @@ __global__ void k_m_gather(int n, int ncols, const int32_t *__restrict__ row_lat
 // ------------------------------------------------------------------ CG kernels
 // (finest level, FP64 operator)
 template <int K, int R>
-__global__ __launch_bounds__(kMT, 4) void k_mcg_init(int n, int Kdyn, OpView<double> op,
+__global__ __launch_bounds__(kMT) void k_mcg_init(int n, int Kdyn, OpView<double> op,
                                                   const int32_t *__restrict__ row_lat,
                                                   const uint32_t *__restrict__ meta, const double *__restrict__ x,
                                                   const double *__restrict__ b, double *__restrict__ r,
                                                   double *__restrict__ part) {
   __shared__ double lds[kMT];
-  __shared__ double tile[MTile<K, R>::LDS];
-  __shared__ double clds[MTile<K, R>::CLDS];
   const int blk = xcd_map(blockIdx.x, gridDim.x);
-  const int first = blk * MTile<K, R>::TR;
-  const int lr = threadIdx.x / R, i = first + lr, col = threadIdx.x % R;
-  const int lo = mtile_stage<K, R, double>(row_lat, meta, first, n, op, x, tile, clds);
+  const int t = blk * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
   double rr = 0.0, bb = 0.0;
   if (i < n) {
     const int L = row_lat[i];
     const size_t o = size_t(L) * R + col;
     const double bi = b[o];
-    double xc;
-    const double ri = bi - mtile_row<K, R, double>(meta[i], op, x, tile, clds, lr, L, lo, col, Kdyn, &xc);
+    const double ri = bi - mrow<K, R, double>(meta[i], op, x, L, col, Kdyn);
     r[o] = ri;
     rr = ri * ri;
     bb = bi * bi;
@@ -414,27 +320,23 @@ __global__ __launch_bounds__(kMT) void k_mcg_direction(int n, const int32_t *__r
 }
 
 template <int K, int R>
-__global__ __launch_bounds__(kMT, 4) void k_mcg_spmv_pq(int n, int Kdyn, OpView<double> op,
+__global__ __launch_bounds__(kMT) void k_mcg_spmv_pq(int n, int Kdyn, OpView<double> op,
                                                      const int32_t *__restrict__ row_lat,
                                                      const uint32_t *__restrict__ meta, const double *__restrict__ p,
                                                      double *__restrict__ q, double *__restrict__ part,
                                                      const MState *st) {
   if (st->done) return;
   __shared__ double lds[kMT];
-  __shared__ double tile[MTile<K, R>::LDS];
-  __shared__ double clds[MTile<K, R>::CLDS];
   const int blk = xcd_map(blockIdx.x, gridDim.x);
-  const int first = blk * MTile<K, R>::TR;
-  const int lr = threadIdx.x / R, i = first + lr, col = threadIdx.x % R;
-  const int lo = mtile_stage<K, R, double>(row_lat, meta, first, n, op, p, tile, clds);
+  const int t = blk * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
   double acc = 0.0;
   if (i < n) {
     const int L = row_lat[i];
     const size_t o = size_t(L) * R + col;
-    double pc;
-    const double qi = mtile_row<K, R, double>(meta[i], op, p, tile, clds, lr, L, lo, col, Kdyn, &pc);
+    const double qi = mrow<K, R, double>(meta[i], op, p, L, col, Kdyn);
     q[o] = qi;
-    acc = pc * qi;
+    acc = p[o] * qi;
   }
   acc = col_sum<R>(acc, lds);
   if (threadIdx.x < R) part[size_t(blk) * R + threadIdx.x] = acc;
@@ -466,23 +368,19 @@ __global__ __launch_bounds__(kMT) void k_mcg_update(int n, const int32_t *__rest
 }
 
 template <int K, int R>
-__global__ __launch_bounds__(kMT, 4) void k_mcg_true_residual(int n, int Kdyn, OpView<double> op,
+__global__ __launch_bounds__(kMT) void k_mcg_true_residual(int n, int Kdyn, OpView<double> op,
                                                            const int32_t *__restrict__ row_lat,
                                                            const uint32_t *__restrict__ meta,
                                                            const double *__restrict__ x,
                                                            const double *__restrict__ b, double *__restrict__ part) {
   __shared__ double lds[kMT];
-  __shared__ double tile[MTile<K, R>::LDS];
-  __shared__ double clds[MTile<K, R>::CLDS];
   const int blk = xcd_map(blockIdx.x, gridDim.x);
-  const int first = blk * MTile<K, R>::TR;
-  const int lr = threadIdx.x / R, i = first + lr, col = threadIdx.x % R;
-  const int lo = mtile_stage<K, R, double>(row_lat, meta, first, n, op, x, tile, clds);
+  const int t = blk * kMT + threadIdx.x;
+  const int i = t / R, col = t % R;
   double acc = 0.0;
   if (i < n) {
     const int L = row_lat[i];
-    double xc;
-    const double ri = b[size_t(L) * R + col] - mtile_row<K, R, double>(meta[i], op, x, tile, clds, lr, L, lo, col, Kdyn, &xc);
+    const double ri = b[size_t(L) * R + col] - mrow<K, R, double>(meta[i], op, x, L, col, Kdyn);
     acc = ri * ri;
   }
   acc = col_sum<R>(acc, lds);
