@@ -221,6 +221,58 @@ def assemble(w, leaf, n, depth, orders=None, with_rhs=True) -> System:
     return System(level=lev, A=A, b=b, M=M, vol_frac=vol_frac, bnd_measure=bnd_meas, omega_measure=omega)
 
 
+def assemble_rows(w, leaf, n, depth, rows_lattice, orders=None):
+    """Rows of A (and entries of b) for the active functions with the given
+    lattice indices, from exactly the element contributions `assemble` adds
+    for them, in the same element order: the same numbers as the full
+    assembly, for problems too large to assemble whole.
+
+    Returns (level, {row L: {column L': A value}}, {row L: b value})."""
+    strong = w.bc == "box_dirichlet"
+    lev = make_level(w, leaf, n, depth, strong)
+    d, p = w.dim, w.degree
+    qc, qs, qb = orders if orders is not None else Q.default_orders(d, p)
+    beta = w.penalty_factor / lev.h if w.bc == "penalty" else 0.0
+    active = set(int(L) for L in lev.active)
+    want = set(int(L) for L in rows_lattice)
+    if not want <= active:
+        raise ValueError("requested rows must be active functions")
+    # elements whose local functions include a requested row, ascending
+    els = sorted(el for el, fl in lev.elem_funcs.items() if want.intersection(int(L) for L in fl))
+    A = {L: {} for L in want}
+    b = {L: 0.0 for L in want}
+    for el in els:
+        e = tuple(int(v) for v in np.unravel_index(el, (n,) * d, order="F"))
+        fl = lev.elem_funcs[el]
+        vp, vw, bp, bw, bn = Q.element_quadrature(leaf, e, depth, lev.lo, lev.h, qc, qs, qb)
+        V, Gr = tensor_eval(lev, e, vp)
+        K = np.einsum("q,aqc,bqc->ab", vw, Gr, Gr)
+        fb = np.zeros(len(fl))
+        if w.rhs == "one":
+            fb += V @ vw
+        elif w.rhs == "manufactured":
+            _, f, _ = manufactured(vp)
+            fb += V @ (vw * f)
+        if len(bw):
+            Vb, _ = tensor_eval(lev, e, bp)
+            if beta > 0.0:
+                K = K + beta * np.einsum("q,aq,bq->ab", bw, Vb, Vb)
+            if w.rhs == "manufactured" and w.bc == "box_dirichlet":
+                _, _, gu = manufactured(bp)
+                fb += Vb @ (bw * np.sum(gu * bn, axis=1))
+        K = np.triu(K) + np.triu(K, 1).T
+        for a, La in enumerate(fl):
+            La = int(La)
+            if La not in want:
+                continue
+            b[La] += fb[a]
+            for c, Lc in enumerate(fl):
+                Lc = int(Lc)
+                if Lc in active:
+                    A[La][Lc] = A[La].get(Lc, 0.0) + K[a, c]
+    return lev, A, b
+
+
 def _mirror(A: sp.csr_matrix) -> sp.csr_matrix:
     """Exactly symmetric copy: upper triangle (with diagonal) mirrored.  The
     structural pattern is kept (explicit zeros included)."""

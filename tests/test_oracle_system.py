@@ -304,3 +304,27 @@ def test_vectorised_activation_matches_element_loop():
     # mask is indexed [x, y]; lattice index is x fastest
     lat = np.array(sorted(int(i + lev.nf1 * j) for i, j in zip(*np.nonzero(mask))))
     assert np.array_equal(lat, lev.active)
+
+
+def test_assemble_rows_equals_full_assembly():
+    """The row-restricted assembly (used for full-size spot checks) adds the
+    same element contributions as the full assembly."""
+    import workloads as W
+    from oracle import assemble as AS
+    from oracle import geometry as G
+    w = W.small_discs(seed=11, n=32, degree=3, levels=3, n_discs=6, depth=1, rhs="manufactured", nu=2)
+    leaf = G.leaf_values(w, w.n, w.depth)
+    sysf = AS.assemble(w, leaf, w.n, w.depth)
+    lev = sysf.level
+    pick = np.random.default_rng(0).choice(len(lev.active), 25, replace=False)
+    rows = [int(lev.active[i]) for i in pick]
+    _, A, b = AS.assemble_rows(w, leaf, w.n, w.depth, rows)
+    pos = {int(L): i for i, L in enumerate(lev.active)}
+    for L in rows:
+        i = pos[L]
+        full = sysf.A.getrow(i).toarray().ravel()
+        mine = np.zeros_like(full)
+        for Lc, v in A[L].items():
+            mine[pos[Lc]] = v
+        assert np.abs(full - mine).max() <= 1e-13 * np.abs(full).max()
+        assert abs(sysf.b[i] - b[L]) <= 1e-13 * max(abs(sysf.b[i]), np.abs(sysf.b).max())
