@@ -185,11 +185,11 @@ __global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_cg_spmv_pq(in
                                                             const uint32_t *__restrict__ meta,
                                                             const double *__restrict__ p, double *__restrict__ q,
                                                             double *__restrict__ part, const CGState *st) {
-  if (st->done) return;
   __shared__ double lds[kRedThreads];
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
-  double acc = tile_rows<K, double>(n, blk * kRedThreads, op, row_lat, meta, p, tile, Kdyn, SpmvEpi{q}).x;
+  double acc = tile_rows<K, double>(n, blk * kRedThreads, op, row_lat, meta, p, tile, Kdyn, SpmvEpi{q}, &st->done).x;
+  if (st->done) return;  // uniform: the flag does not change during the kernel
   acc = block_sum<kRedThreads>(acc, lds);
   if (threadIdx.x == 0) part[blk] = acc;
 }

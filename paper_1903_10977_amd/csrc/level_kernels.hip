@@ -81,10 +81,9 @@ __global__ __launch_bounds__(kRowBlock, kTileBlocksPerCU) void k_residual(int n,
                                                         const uint32_t *__restrict__ meta,
                                                         const double *__restrict__ x, const double *__restrict__ b,
                                                         double *__restrict__ y, const int32_t *__restrict__ done) {
-  if (done && *done) return;
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
   const int first = xcd_block(blockIdx.x, gridDim.x) * kRowBlock;
-  tile_rows<K, V>(n, first, op, row_lat, meta, x, tile, Kdyn, ResidualEpi{b, y});
+  tile_rows<K, V>(n, first, op, row_lat, meta, x, tile, Kdyn, ResidualEpi{b, y}, done);
 }
 
 // smoothing step, trivial rows:  rh = r - A xa  (stored for general rows only),
@@ -98,10 +97,9 @@ __global__ __launch_bounds__(kRowBlock, kTileBlocksPerCU) void k_residual_smooth
                                                                const double *__restrict__ r, double *__restrict__ rh,
                                                                double *__restrict__ xb,
                                                                const int32_t *__restrict__ done) {
-  if (done && *done) return;
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
   const int first = xcd_block(blockIdx.x, gridDim.x) * kRowBlock;
-  tile_rows<K, V>(n, first, op, row_lat, meta, xa, tile, Kdyn, SmoothEpi{r, c, rh, xb});
+  tile_rows<K, V>(n, first, op, row_lat, meta, xa, tile, Kdyn, SmoothEpi{r, c, rh, xb}, done);
 }
 
 template <typename V>

@@ -61,19 +61,23 @@ __device__ __forceinline__ double op_row(unsigned meta, const OpView<V> &op, con
   return acc;
 }
 
+constexpr int kTileDone = -2;  // tile_stage: the convergence flag is set, nothing to do
+
 // Stages the x window of the workgroup's rows [first, min(first + kTileRows, n))
-// into LDS and returns lo = row_lat[first], or -1 when the operator is not
-// tiled or the span exceeds kTileSpan.  Every thread of the workgroup must
-// call it (it synchronizes); first < n.
+// into LDS and returns lo = row_lat[first], -1 when the operator is not tiled
+// or the span exceeds kTileSpan, or kTileDone when *done is set (read
+// together with the tile bounds, so that the flag adds no latency of its
+// own).  Every thread of the workgroup must call it (it synchronizes); first < n.
 template <int K>
 __device__ __forceinline__ int tile_stage(const int32_t *__restrict__ row_lat, int first, int n, const Offsets &off,
-                                          const double *__restrict__ x, double *lds) {
+                                          const double *__restrict__ x, double *lds, const int32_t *done) {
   using SS = StencilShape<K>;
   if constexpr (!SS::TILED) {
-    return -1;
+    return (done && *done) ? kTileDone : -1;
   } else {
     const int lo = row_lat[first];
     const int hi = row_lat[min(first + kTileRows, n) - 1];
+    if (done && *done) return kTileDone;
     if (hi - lo + 1 > kTileSpan) return -1;
     const int span = hi - lo + 1 + 2 * SS::P;
 #pragma unroll
@@ -103,12 +107,14 @@ __device__ __forceinline__ double tile_center(const double *t) {
 // exactly once to the epilogue: epi.post(i, L, meta, (A x)_L, x_L, pre) with
 // pre = epi.pre(i, L) fetched before the tile is staged (so that its loads
 // overlap the staging); post returns a pair of partial sums that tile_rows
-// adds up per thread.  Every thread of the workgroup must call it; first =
+// adds up per thread.  With done != nullptr nothing is computed or stored
+// once *done is set.  Every thread of the workgroup must call it; first =
 // the tile's first row (< n).
 template <int K, typename V, typename Epi>
 __device__ __forceinline__ double2 tile_rows(int n, int first, const OpView<V> &op,
                                              const int32_t *__restrict__ row_lat, const uint32_t *__restrict__ meta,
-                                             const double *__restrict__ x, double *lds, int Kdyn, const Epi &epi) {
+                                             const double *__restrict__ x, double *lds, int Kdyn, const Epi &epi,
+                                             const int32_t *done = nullptr) {
   using Pre = typename Epi::Pre;
   double2 acc = make_double2(0.0, 0.0);
   const int i = first + threadIdx.x;
@@ -135,7 +141,8 @@ __device__ __forceinline__ double2 tile_rows(int n, int first, const OpView<V> &
       m2 = meta[i2];
       p2 = epi.pre(i2, L2);
     }
-    const int lo = tile_stage<K>(row_lat, first, n, op.off, x, lds);
+    const int lo = tile_stage<K>(row_lat, first, n, op.off, x, lds, done);
+    if (lo == kTileDone) return acc;
     if (lo >= 0) {
       // phase 1: rows on the reference stencil
       if (act && (m & kMetaIndex) == kMetaIndex) {
@@ -162,6 +169,9 @@ __device__ __forceinline__ double2 tile_rows(int n, int first, const OpView<V> &
       }
       return acc;
     }
+  }
+  if constexpr (!StencilShape<K>::TILED) {
+    if (done && *done) return acc;
   }
   if (act) {
     const double2 c = epi.post(i, L, m, op_row<K, V>(m, op, x, L, Kdyn), x[L], p1);
