@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed",
                     help="headline form (the other form is timed too)")
     ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
+                    help="c2: 1024^2 cubic discs (headline); c3: 128^3 quadratic gyroid")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the mixed+learned form")
@@ -94,8 +96,14 @@ def main():
     from paper_1903_10977_amd import solver as S
 
     assert torch.cuda.is_available(), "bench needs a GPU"
-    levels = int(round(math.log2(args.n // 32))) + 1
-    w = W.c2(n=args.n, levels=levels)
+    if args.workload == "c3":
+        # 3D gyroid, quadratic B-splines, 128^3, 4 levels, V(1,1); no multi-column or batched forms
+        w = W.c3(n=args.n if args.n != 1024 else 128)
+        levels = w.levels
+        args.nrhs, args.no_batched = 1, True
+    else:
+        levels = int(round(math.log2(args.n // 32))) + 1
+        w = W.c2(n=args.n, levels=levels)
     t0 = time.time()
     g = GN.generate(w, with_mass=args.nrhs > 1)
     log(f"generated {w.name}: fine DOFs {g.fine.n}, nnz {g.fine.A.nnz}, {time.time() - t0:.1f} s")
@@ -146,7 +154,8 @@ def main():
     learned = None
     if not args.no_learned:
         from paper_1903_10977_amd import learn as LN
-        sol = make(S.MIXED, learned=LN.load_params())
+        model = LN.MODEL_DEFAULT + ("_gyroid3d" if args.workload == "c3" else "")
+        sol = make(S.MIXED, learned=LN.load_params(model))
         status = [sol.weights(l)[1] for l in range(1, len(g.levels))]
         x, iters, dt = timed(sol)
         res = float(np.linalg.norm(g.b - g.fine.A @ x.cpu().numpy()) / np.linalg.norm(g.b))
@@ -227,12 +236,12 @@ def main():
     # measured HBM traffic of the same kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE,
     # copy-calibrated), valid only while the kernel sources are unchanged
     traffic = None
-    if args.n == 1024:
+    if args.n == 1024 and args.workload == "c2":
         form = "mixed" if head == S.MIXED else "fp64"
         traffic = PR.read_traffic(os.path.join(ROOT, "profiles", f"traffic_k_residual_smooth_1024_discs_{form}.txt"))
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "c2":
         log("timing the oracle on the host (bounded sample)")
         cpu = cpu_baseline()
     names = {S.FP64: "fp64", S.MIXED: "mixed"}
@@ -249,9 +258,12 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if head == S.FP64 else "f32-vcycle-operators/f64",
         "data": "synthetic",
-        "config": {"workload": f"2D Poisson, cubic B-splines, {args.n}^2, unit square minus 200 seeded discs "
-                               f"(r ~ U[0.01,0.04]), manufactured sin(2 pi x) sin(2 pi y), {levels}-level V(2,2), "
-                               f"PCG to 1e-8 from x0 = 0", "fine_dofs": n, "headline_form": names[head],
+        "config": {"workload": (f"2D Poisson, cubic B-splines, {args.n}^2, unit square minus 200 seeded discs "
+                                f"(r ~ U[0.01,0.04]), manufactured sin(2 pi x) sin(2 pi y), {levels}-level V(2,2), "
+                                f"PCG to 1e-8 from x0 = 0") if args.workload == "c2" else
+                               (f"3D Poisson, quadratic B-splines, {w.n}^3 gyroid {{g < 0.3}} (two periods, seeded "
+                                f"phase), f = 1, u = 0 on the box, {levels}-level V(1,1), PCG to 1e-8 from x0 = 0"),
+                   "fine_dofs": n, "headline_form": names[head],
                    "pcg_time_s": round(ms_step / 1e3, 5), "forms": forms,
                    "speedup_mixed_vs_fp64": round(results[S.FP64]["ms"] / results[S.MIXED]["ms"], 3),
                    "multi_rhs": multi, "batched": batched},
