@@ -45,7 +45,14 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
 // ordered sum of part[0 .. m) by one workgroup
 __device__ __forceinline__ double sum_partials(const double *__restrict__ part, int m, double *lds) {
   double v = 0.0;
-  for (int b = threadIdx.x; b < m; b += kFinThreads) v += part[b];
+  // chunks of 4 per thread, loads issued together, added in index order
+  for (int b0 = threadIdx.x; b0 < m; b0 += 4 * kFinThreads) {
+    double w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[q] = b0 + q * kFinThreads < m ? part[b0 + q * kFinThreads] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v += w[q];
+  }
   return block_sum<kFinThreads>(v, lds);
 }
 

@@ -166,10 +166,24 @@ __global__ __launch_bounds__(kRowBlock) void k_smooth_general(int ng, const int3
   const int t = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
   if (t >= ng) return;
   const int k0 = sptr[t], k1 = sptr[t + 1];
-  double acc = 0.0;
-#pragma unroll 8
-  for (int k = k0; k < k1; ++k) acc += sval[k] * r[scol[k]];
   const int L = grow_lat[t];
+  double acc = 0.0;
+  // chunks of 8 with guarded, fixed trip counts: the index, value and r loads
+  // of a chunk issue together (entries past the row end add 0 x r[first])
+  for (int kb = k0; kb < k1; kb += 8) {
+    int c[8];
+    double v[8], rv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const bool in = kb + q < k1;
+      c[q] = scol[in ? kb + q : kb];
+      v[q] = in ? sval[kb + q] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) rv[q] = r[c[q]];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc += v[q] * rv[q];
+  }
   x[L] += acc;
 }
 
@@ -255,6 +269,7 @@ struct Band {
   const double *coef;
   int W;
 };
+constexpr int kBandMax = 5;  // bands up to this length take the unrolled 2D path (p <= 3 B-splines)
 
 template <int DIM>
 __global__ __launch_bounds__(kRowBlock) void k_tensor_transfer(int n, const int32_t *__restrict__ row_lat,
@@ -277,7 +292,29 @@ __global__ __launch_bounds__(kRowBlock) void k_tensor_transfer(int n, const int3
   const double *cx = band.coef + size_t(mx) * band.W;
   const double *cy = band.coef + size_t(my) * band.W;
   double acc = 0.0;
-  if (DIM == 2) {
+  if (DIM == 2 && band.W <= kBandMax) {
+    // fixed trip counts with guards: every coefficient and input load of the
+    // row issues before the first wait
+    double cxv[kBandMax], cyv[kBandMax];
+#pragma unroll
+    for (int a = 0; a < kBandMax; ++a) {
+      cxv[a] = a < nx ? cx[a] : 0.0;
+      cyv[a] = a < ny ? cy[a] : 0.0;
+    }
+    double in[kBandMax][kBandMax];
+#pragma unroll
+    for (int b = 0; b < kBandMax; ++b)
+#pragma unroll
+      for (int a = 0; a < kBandMax; ++a)
+        in[b][a] = (a < nx && b < ny) ? xin[size_t(sy + b) * ix_ + sx + a] : 0.0;
+#pragma unroll
+    for (int b = 0; b < kBandMax; ++b) {
+      double t = 0.0;
+#pragma unroll
+      for (int a = 0; a < kBandMax; ++a) t += cxv[a] * in[b][a];
+      acc += cyv[b] * t;
+    }
+  } else if (DIM == 2) {
     for (int b = 0; b < ny; ++b) {
       const double *row = xin + size_t(sy + b) * ix_ + sx;
       double t = 0.0;
@@ -325,7 +362,22 @@ __global__ __launch_bounds__(kGemvThreads) void k_dense_gemv(int n, const int32_
                                                              const int32_t *__restrict__ done) {
   if (done && *done) return;
   extern __shared__ double rs[];
-  for (int j = threadIdx.x; j < n; j += kGemvThreads) rs[j] = r[row_lat[j]];
+  // gather r in batches of 8 per thread: indices first, then values, so that
+  // the loads of a batch are in flight together
+  for (int j0 = threadIdx.x; j0 < n; j0 += 8 * kGemvThreads) {
+    int idx[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int j = j0 + q * kGemvThreads;
+      idx[q] = j < n ? row_lat[j] : 0;
+    }
+    double val[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) val[q] = j0 + q * kGemvThreads < n ? r[idx[q]] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (j0 + q * kGemvThreads < n) rs[j0 + q * kGemvThreads] = val[q];
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -334,6 +386,7 @@ __global__ __launch_bounds__(kGemvThreads) void k_dense_gemv(int n, const int32_
   if (i >= n) return;
   const double *row = Ainv + size_t(i) * n;
   double acc = 0.0;
+#pragma unroll 8
   for (int j = lane; j < n; j += 64) acc += row[j] * rs[j];
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
   if (lane == 0) x[row_lat[i]] = acc;

@@ -125,8 +125,23 @@ __global__ __launch_bounds__(kMT) void k_m_smooth_general(int ng, const int32_t 
   const int t = xcd_map(blockIdx.x, gridDim.x) * kMT + threadIdx.x;
   const int i = t / R, col = t % R;
   if (i >= ng) return;
+  const int k0 = sptr[i], k1 = sptr[i + 1];
   double acc = 0.0;
-  for (int k = sptr[i]; k < sptr[i + 1]; ++k) acc += sval[k] * r[size_t(scol[k]) * R + col];
+  // chunks of 8 with guarded, fixed trip counts (see the single-column kernel)
+  for (int kb = k0; kb < k1; kb += 8) {
+    int c[8];
+    double v[8], rv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const bool in = kb + q < k1;
+      c[q] = scol[in ? kb + q : kb];
+      v[q] = in ? sval[kb + q] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) rv[q] = r[size_t(c[q]) * R + col];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc += v[q] * rv[q];
+  }
   x[size_t(grow_lat[i]) * R + col] += acc;
 }
 
@@ -148,6 +163,7 @@ struct MBand {
   const double *coef;
   int W;
 };
+constexpr int kMBandMax = 5;
 
 template <int DIM, int R>
 __global__ __launch_bounds__(kMT) void k_m_tensor_transfer(int n, const int32_t *__restrict__ row_lat, int ox, int oy,
@@ -169,7 +185,27 @@ __global__ __launch_bounds__(kMT) void k_m_tensor_transfer(int n, const int32_t 
   const double *cx = band.coef + size_t(mx) * band.W;
   const double *cy = band.coef + size_t(my) * band.W;
   double acc = 0.0;
-  if (DIM == 2) {
+  if (DIM == 2 && band.W <= kMBandMax) {
+    // fixed trip counts with guards: all loads of the row issue before the first wait
+    double cxv[kMBandMax], cyv[kMBandMax], in[kMBandMax][kMBandMax];
+#pragma unroll
+    for (int a = 0; a < kMBandMax; ++a) {
+      cxv[a] = a < nx ? cx[a] : 0.0;
+      cyv[a] = a < ny ? cy[a] : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < kMBandMax; ++b)
+#pragma unroll
+      for (int a = 0; a < kMBandMax; ++a)
+        in[b][a] = (a < nx && b < ny) ? xin[(size_t(sy + b) * ix_ + sx + a) * R + col] : 0.0;
+#pragma unroll
+    for (int b = 0; b < kMBandMax; ++b) {
+      double s = 0.0;
+#pragma unroll
+      for (int a = 0; a < kMBandMax; ++a) s += cxv[a] * in[b][a];
+      acc += cyv[b] * s;
+    }
+  } else if (DIM == 2) {
     for (int b = 0; b < ny; ++b) {
       const size_t row = size_t(sy + b) * ix_ + sx;
       double s = 0.0;

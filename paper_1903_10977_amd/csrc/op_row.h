@@ -80,11 +80,26 @@ __device__ __forceinline__ int tile_stage(const int32_t *__restrict__ row_lat, i
     if (done && *done) return kTileDone;
     if (hi - lo + 1 > kTileSpan) return -1;
     const int span = hi - lo + 1 + 2 * SS::P;
+    // all loads of the window first, then all LDS writes: the thread waits for
+    // its loads once instead of once per element
+    constexpr int PER = (SS::STRIDE + kTileRows - 1) / kTileRows;
+    double v[SS::LINES][PER];
 #pragma unroll
     for (int j = 0; j < SS::LINES; ++j) {
       const double *__restrict__ src = x + (lo - SS::P + off.off[j * SS::W + SS::P]);
-      for (int t = threadIdx.x; t < span; t += kTileRows) lds[j * SS::STRIDE + t] = src[t];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int t = threadIdx.x + q * kTileRows;
+        v[j][q] = t < span ? src[t] : 0.0;
+      }
     }
+#pragma unroll
+    for (int j = 0; j < SS::LINES; ++j)
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int t = threadIdx.x + q * kTileRows;
+        if (t < span) lds[j * SS::STRIDE + t] = v[j][q];
+      }
     __syncthreads();
     return lo;
   }
