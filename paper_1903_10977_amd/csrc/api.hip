@@ -321,35 +321,78 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
     }
   }
   const int nv = int(comp.size());
-  std::vector<double> cv(size_t(L.K) * std::max(nv, 1), 0.0);
-  for (int g = 0; g < nv; ++g)
-    for (int sl = 0; sl < L.K; ++sl) cv[size_t(sl) * nv + g] = ell[size_t(sl) * L.n + comp[g]];
-  L.meta = dalloc<uint32_t>(c->owned, L.n);
-  h2d(s, L.meta, L.h_meta.data(), L.n);
-  // stored rows of every tile of kTileRows consecutive rows: [tile_g0[b], tile_g0[b + 1])
+  // lattice tiles of the stencil kernels (32 x 8 points in 2D, 16 x 4 x 4 in
+  // 3D): stored rows renumbered tile by tile (lattice order inside a tile), so
+  // that the stored rows of a tile are one consecutive range of value columns
+  const bool tiled = (L.dim == 2 && L.reach <= 3) || (L.dim == 3 && L.reach <= 2);
+  std::vector<int32_t> ord(comp);  // value column g -> row
   {
-    const int tiles = (L.n + kTileRows - 1) / kTileRows;
-    std::vector<int32_t> tg0(size_t(tiles) + 1, 0);
-    size_t g = 0;
-    for (int b = 0; b <= tiles; ++b) {
-      while (g < comp.size() && comp[g] < b * kTileRows) ++g;
-      tg0[b] = int32_t(g);
+    const int TX = L.dim == 2 ? kTile2X : kTile3X, TY = L.dim == 2 ? kTile2Y : kTile3Y;
+    const int TZ = L.dim == 2 ? 1 : kTile3Z;
+    const int WX = TX + 2 * L.reach, WY = TY + 2 * L.reach;
+    const int sx = L.shape[0], sy = L.shape[1], sz = L.shape[2];
+    const int ntx = (sx + TX - 1) / TX, nty = (sy + TY - 1) / TY, ntz = (sz + TZ - 1) / TZ;
+    const int64_t ntiles = tiled ? int64_t(ntx) * nty * ntz : 0;
+    if (ntiles > (int64_t(1) << 30)) bad("too many lattice tiles");
+    auto tile_of = [&](int64_t Lp) {
+      const int x = int(Lp % sx), y = int((Lp / sx) % sy), z = int(Lp / (int64_t(sx) * sy));
+      return (x / TX) + int64_t(ntx) * ((y / TY) + int64_t(nty) * (z / TZ));
+    };
+    auto local_of = [&](int64_t Lp) {
+      const int x = int(Lp % sx), y = int((Lp / sx) % sy), z = int(Lp / (int64_t(sx) * sy));
+      return int32_t(((z % TZ) * WY + (y % TY)) * WX + (x % TX));
+    };
+    std::vector<int32_t> tg0(size_t(ntiles) + 1, 0), tany(std::max<int64_t>(ntiles, 1), 0), sloc;
+    if (tiled) {
+      for (int i = 0; i < L.n; ++i) tany[size_t(tile_of(L.h_row_lat[i]))] = 1;
+      std::vector<int32_t> cnt(size_t(ntiles) + 1, 0);
+      for (int32_t i : comp) ++cnt[size_t(tile_of(L.h_row_lat[i])) + 1];
+      for (int64_t b = 0; b < ntiles; ++b) cnt[size_t(b) + 1] += cnt[size_t(b)];
+      tg0.assign(cnt.begin(), cnt.end());
+      // rows in lattice order: a stable placement keeps lattice order per tile
+      for (int32_t i : comp) ord[size_t(cnt[size_t(tile_of(L.h_row_lat[i]))]++)] = i;
+      sloc.resize(ord.size());
+      for (size_t g = 0; g < ord.size(); ++g) sloc[g] = local_of(L.h_row_lat[ord[g]]);
     }
-    int32_t *d_srow = dalloc<int32_t>(c->owned, std::max<size_t>(comp.size(), 1));
-    int32_t *d_slat = dalloc<int32_t>(c->owned, std::max<size_t>(comp.size(), 1));
-    std::vector<int32_t> slat(comp.size());
-    for (size_t k = 0; k < comp.size(); ++k) slat[k] = L.h_row_lat[comp[k]];
-    if (!comp.empty()) {
-      h2d(s, d_srow, comp.data(), comp.size());
+    for (int g = 0; g < nv; ++g) L.h_meta[ord[g]] = uint32_t(g);
+    std::vector<int32_t> slat(ord.size());
+    for (size_t k = 0; k < ord.size(); ++k) slat[k] = L.h_row_lat[ord[k]];
+    int32_t *d_srow = dalloc<int32_t>(c->owned, std::max<size_t>(ord.size(), 1));
+    int32_t *d_slat = dalloc<int32_t>(c->owned, std::max<size_t>(ord.size(), 1));
+    int32_t *d_sloc = dalloc<int32_t>(c->owned, std::max<size_t>(ord.size(), 1));
+    if (!ord.empty()) {
+      h2d(s, d_srow, ord.data(), ord.size());
       h2d(s, d_slat, slat.data(), slat.size());
+      if (tiled) h2d(s, d_sloc, sloc.data(), sloc.size());
     }
     int32_t *d_tg0 = dalloc<int32_t>(c->owned, tg0.size());
     h2d(s, d_tg0, tg0.data(), tg0.size());
-    L.op64.srow = L.op32.srow = d_srow;
-    L.op64.slat = L.op32.slat = d_slat;
-    L.op64.tile_g0 = L.op32.tile_g0 = d_tg0;
+    int32_t *d_tany = dalloc<int32_t>(c->owned, tany.size());
+    h2d(s, d_tany, tany.data(), tany.size());
+    std::vector<int32_t> l2r(tiled ? size_t(L.lattice) : 1, -1);
+    if (tiled)
+      for (int i = 0; i < L.n; ++i) l2r[size_t(L.h_row_lat[i])] = i;
+    int32_t *d_l2r = dalloc<int32_t>(c->owned, l2r.size());
+    h2d(s, d_l2r, l2r.data(), l2r.size());
+    for (auto *o : {&L.op64.srow, &L.op32.srow}) *o = d_srow;
+    for (auto *o : {&L.op64.slat, &L.op32.slat}) *o = d_slat;
+    for (auto *o : {&L.op64.sloc, &L.op32.sloc}) *o = d_sloc;
+    for (auto *o : {&L.op64.tile_g0, &L.op32.tile_g0}) *o = d_tg0;
+    for (auto *o : {&L.op64.tile_any, &L.op32.tile_any}) *o = d_tany;
+    for (auto *o : {&L.op64.lat2row, &L.op32.lat2row}) *o = d_l2r;
+    L.op64.sx = L.op32.sx = sx;
+    L.op64.sy = L.op32.sy = sy;
+    L.op64.sz = L.op32.sz = sz;
+    L.op64.ntx = L.op32.ntx = ntx;
+    L.op64.nty = L.op32.nty = nty;
+    L.op64.ntiles = L.op32.ntiles = int(ntiles);
     HIP_CHECK_RET(hipStreamSynchronize(s));
   }
+  std::vector<double> cv(size_t(L.K) * std::max(nv, 1), 0.0);
+  for (int g = 0; g < nv; ++g)
+    for (int sl = 0; sl < L.K; ++sl) cv[size_t(sl) * nv + g] = ell[size_t(sl) * L.n + ord[g]];
+  L.meta = dalloc<uint32_t>(c->owned, L.n);
+  h2d(s, L.meta, L.h_meta.data(), L.n);
   double *cv64 = dalloc<double>(c->owned, cv.size());
   h2d(s, cv64, cv.data(), cv.size());
   L.op64.off = L.off;
@@ -1605,7 +1648,7 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
     HIP_CHECK_RET(hipMemsetAsync(c->zero_flag, 0, sizeof(int32_t), c->stream));
     c->st = dalloc<CGState>(c->owned, 1);
     HIP_CHECK_RET(hipMemsetAsync(c->st, 0, sizeof(CGState), c->stream));
-    c->part = dalloc<double>(c->owned, 2 * size_t(reduction_blocks(F.n)) + 64);
+    c->part = dalloc<double>(c->owned, 2 * size_t(std::max(reduction_blocks(F.n), F.op64.ntiles)) + 64);
     HIP_CHECK_RET(hipStreamSynchronize(c->stream));
     c->ready = true;
     return IMSMG_OK;

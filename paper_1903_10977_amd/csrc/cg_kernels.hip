@@ -15,7 +15,7 @@
 namespace imsmg {
 
 constexpr int kRedThreads = 256;
-static_assert(kRedThreads == kTileRows, "stencil kernels stage one tile per workgroup");
+static_assert(kRedThreads == kTileRows, "stencil kernels: one lattice point or row per thread");
 constexpr int kFinThreads = 1024;
 
 int reduction_blocks(int n) { return n < 1 ? 1 : (n + kRedThreads - 1) / kRedThreads; }
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_cg_init(int n
   __shared__ double lds[kRedThreads];
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
-  const double2 s = tile_rows<K, double>(n, blk * kRedThreads, op, row_lat, meta, x, tile, Kdyn, InitEpi{b, r});
+  const double2 s = tile_rows<K, double>(n, blk, op, row_lat, meta, x, tile, Kdyn, InitEpi{b, r});
   double rr = s.x, bb = s.y;
   rr = block_sum<kRedThreads>(rr, lds);
   bb = block_sum<kRedThreads>(bb, lds);
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_cg_spmv_pq(in
   __shared__ double lds[kRedThreads];
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
-  double acc = tile_rows<K, double>(n, blk * kRedThreads, op, row_lat, meta, p, tile, Kdyn, SpmvEpi{q}, &st->done).x;
+  double acc = tile_rows<K, double>(n, blk, op, row_lat, meta, p, tile, Kdyn, SpmvEpi{q}, &st->done).x;
   if (st->done) return;  // uniform: the flag does not change during the kernel
   acc = block_sum<kRedThreads>(acc, lds);
   if (threadIdx.x == 0) part[blk] = acc;
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_cg_true_resid
   __shared__ double lds[kRedThreads];
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
-  double acc = tile_rows<K, double>(n, blk * kRedThreads, op, row_lat, meta, x, tile, Kdyn, TrueResEpi{b}).x;
+  double acc = tile_rows<K, double>(n, blk, op, row_lat, meta, x, tile, Kdyn, TrueResEpi{b}).x;
   acc = block_sum<kRedThreads>(acc, lds);
   if (threadIdx.x == 0) part[blk] = acc;
 }
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(kFinThreads) void k_cg_aux_fin(int m, const double 
 void launch_cg_init(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                     const uint32_t *meta, const double *x, const double *b, double *r, double *part, CGState *st,
                     double rtol, int restart) {
-  const int g = reduction_blocks(n);
+  const int g = stencil_grid(K, n, op);
   IMSMG_DISPATCH_K(K, k_cg_init, n, K, op, row_lat, meta, x, b, r, part);
   k_cg_init_fin<<<1, kFinThreads, 0, s>>>(g, part, st, rtol, restart);
 }
@@ -315,7 +315,7 @@ void launch_cg_direction(hipStream_t s, int n, const int32_t *row_lat, const dou
 
 void launch_cg_spmv_pq(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                        const uint32_t *meta, const double *p, double *q, double *part, CGState *st) {
-  const int g = reduction_blocks(n);
+  const int g = stencil_grid(K, n, op);
   IMSMG_DISPATCH_K(K, k_cg_spmv_pq, n, K, op, row_lat, meta, p, q, part, st);
   k_cg_pq_fin<<<1, kFinThreads, 0, s>>>(g, part, st);
 }
@@ -329,7 +329,7 @@ void launch_cg_update(hipStream_t s, int n, const int32_t *row_lat, const double
 
 void launch_cg_true_residual(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                              const uint32_t *meta, const double *x, const double *b, double *part, CGState *st) {
-  const int g = reduction_blocks(n);
+  const int g = stencil_grid(K, n, op);
   IMSMG_DISPATCH_K(K, k_cg_true_residual, n, K, op, row_lat, meta, x, b, part);
   k_cg_aux_fin<<<1, kFinThreads, 0, s>>>(g, part, st);
 }

@@ -29,6 +29,9 @@
 namespace imsmg {
 
 constexpr int kTileRows = 256;  // rows (= threads) per workgroup of the stencil kernels
+// lattice box of a stencil workgroup: 32 x 8 points in 2D, 16 x 4 x 4 in 3D
+constexpr int kTile2X = 32, kTile2Y = 8;
+constexpr int kTile3X = 16, kTile3Y = 4, kTile3Z = 4;
 
 constexpr uint32_t kMetaIndex = 0x3fffffffu;    // low 30 bits: compressed-value index, all ones = uniform
 constexpr uint32_t kMetaGeneral = 0x40000000u;  // row belongs to a general Schwarz block
@@ -42,10 +45,15 @@ struct OpView {
   Offsets off;
   const V *ref;            // uniform interior stencil (K values)
   const V *val;            // stored rows, slot-major
-  int nv;                  // number of stored rows
-  const int32_t *srow;     // row index of every stored row (ascending)
+  int nv;                  // number of stored rows (numbered tile by tile)
+  const int32_t *srow;     // row index of every stored row
   const int32_t *slat;     // lattice position of every stored row
-  const int32_t *tile_g0;  // first stored row of every kTileRows-row tile (tiles + 1 entries)
+  const int32_t *sloc;     // window offset of every stored row within its tile's LDS window
+  const int32_t *tile_g0;  // first stored row of every lattice tile (ntiles + 1 entries)
+  const int32_t *tile_any; // 1 if the tile holds an active row
+  const int32_t *lat2row;  // lattice point -> row (-1: inactive)
+  int sx, sy, sz;          // lattice shape (sz = 1 in 2D)
+  int ntx, nty, ntiles;    // lattice tiles along x, along y, in total
 };
 
 // Scalars of the CG iteration, kept on the device.

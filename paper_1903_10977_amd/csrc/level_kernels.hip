@@ -27,7 +27,7 @@
 namespace imsmg {
 
 constexpr int kRowBlock = 256;
-static_assert(kRowBlock == kTileRows, "stencil kernels stage one tile per workgroup");
+static_assert(kRowBlock == kTileRows, "stencil kernels: one lattice point or row per thread");
 
 __device__ __forceinline__ int xcd_block(int b, int nb) {
   // hardware dispatches workgroup b to XCD (b % 8); give XCD k a contiguous
@@ -82,8 +82,7 @@ __global__ __launch_bounds__(kRowBlock, kTileBlocksPerCU) void k_residual(int n,
                                                         const double *__restrict__ x, const double *__restrict__ b,
                                                         double *__restrict__ y, const int32_t *__restrict__ done) {
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
-  const int first = xcd_block(blockIdx.x, gridDim.x) * kRowBlock;
-  tile_rows<K, V>(n, first, op, row_lat, meta, x, tile, Kdyn, ResidualEpi{b, y}, done);
+  tile_rows<K, V>(n, xcd_block(blockIdx.x, gridDim.x), op, row_lat, meta, x, tile, Kdyn, ResidualEpi{b, y}, done);
 }
 
 // smoothing step, trivial rows:  rh = r - A xa  (stored for general rows only),
@@ -98,15 +97,14 @@ __global__ __launch_bounds__(kRowBlock, kTileBlocksPerCU) void k_residual_smooth
                                                                double *__restrict__ xb,
                                                                const int32_t *__restrict__ done) {
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
-  const int first = xcd_block(blockIdx.x, gridDim.x) * kRowBlock;
-  tile_rows<K, V>(n, first, op, row_lat, meta, xa, tile, Kdyn, SmoothEpi{r, c, rh, xb}, done);
+  tile_rows<K, V>(n, xcd_block(blockIdx.x, gridDim.x), op, row_lat, meta, xa, tile, Kdyn, SmoothEpi{r, c, rh, xb}, done);
 }
 
 template <typename V>
 static void dispatch_residual(hipStream_t s, int n, int K, const OpView<V> &op, const int32_t *row_lat,
                               const uint32_t *meta, const double *x, const double *b, double *y, const int32_t *done) {
   if (n <= 0) return;
-  dim3 g(grid_for(n)), t(kRowBlock);
+  dim3 g(stencil_grid(K, n, op)), t(kRowBlock);
   switch (K) {
     case 9: k_residual<9, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done); break;
     case 25: k_residual<25, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done); break;
@@ -122,7 +120,7 @@ static void dispatch_residual_smooth(hipStream_t s, int n, int K, const OpView<V
                                      const uint32_t *meta, const double *c, const double *xa, const double *r,
                                      double *rh, double *xb, const int32_t *done) {
   if (n <= 0) return;
-  dim3 g(grid_for(n)), t(kRowBlock);
+  dim3 g(stencil_grid(K, n, op)), t(kRowBlock);
   switch (K) {
     case 9: k_residual_smooth<9, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done); break;
     case 25: k_residual_smooth<25, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done); break;
