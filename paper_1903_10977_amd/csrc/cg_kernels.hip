@@ -29,15 +29,16 @@ __device__ __forceinline__ int xcd_block_cg(int b, int nb) {
   return full * per + (xcd - full) * (per - 1) + k;
 }
 
+// workgroup sum in a fixed order: a lane-shuffle tree per wavefront, then the
+// NT / 64 wavefront sums in index order (one barrier instead of log2 NT)
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double *lds) {
-  lds[threadIdx.x] = v;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
-    __syncthreads();
-  }
-  double r = lds[0];
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) r += lds[w];
   __syncthreads();
   return r;
 }

@@ -153,7 +153,11 @@ void launch_residual_smooth(hipStream_t s, int n, int K, const OpView<float> &op
 // General Schwarz rows: x[L_t] += sum_k S_G[t,k] r[col_k].  S_G is the sum of
 // omega_j P_j A_j^{-1} P_j^T over the general blocks, restricted to the rows
 // that belong to one, assembled once at factorization; applying it is a CSR
-// product with lattice column positions (deterministic, no atomics).
+// product with lattice column positions (deterministic, no atomics).  Four
+// lanes share a row (entries k0 + lane, k0 + lane + 4, ...: coalesced index
+// and value loads, four times the rows' parallelism), then add their sums in
+// a fixed shuffle order.
+constexpr int kGenLanes = 4;
 __global__ __launch_bounds__(kRowBlock) void k_smooth_general(int ng, const int32_t *__restrict__ grow_lat,
                                                               const int32_t *__restrict__ sptr,
                                                               const int32_t *__restrict__ scol,
@@ -161,34 +165,38 @@ __global__ __launch_bounds__(kRowBlock) void k_smooth_general(int ng, const int3
                                                               const double *__restrict__ r, double *__restrict__ x,
                                                               const int32_t *__restrict__ done) {
   if (done && *done) return;
-  const int t = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
-  if (t >= ng) return;
+  const int gt = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
+  const int t = gt / kGenLanes, sub = gt % kGenLanes;
+  if (t >= ng) return;  // all lanes of a row leave together
   const int k0 = sptr[t], k1 = sptr[t + 1];
   const int L = grow_lat[t];
   double acc = 0.0;
-  // chunks of 8 with guarded, fixed trip counts: the index, value and r loads
-  // of a chunk issue together (entries past the row end add 0 x r[first])
-  for (int kb = k0; kb < k1; kb += 8) {
-    int c[8];
-    double v[8], rv[8];
+  // chunks of 4 entries per lane with guarded, fixed trip counts: the index,
+  // value and r loads of a chunk issue together
+  for (int kb = k0 + sub; kb < k1; kb += 4 * kGenLanes) {
+    int c[4];
+    double v[4], rv[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const bool in = kb + q < k1;
-      c[q] = scol[in ? kb + q : kb];
-      v[q] = in ? sval[kb + q] : 0.0;
+    for (int q = 0; q < 4; ++q) {
+      const int k = kb + q * kGenLanes;
+      const bool in = k < k1;
+      c[q] = scol[in ? k : kb];
+      v[q] = in ? sval[k] : 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) rv[q] = r[c[q]];
+    for (int q = 0; q < 4; ++q) rv[q] = r[c[q]];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc += v[q] * rv[q];
+    for (int q = 0; q < 4; ++q) acc += v[q] * rv[q];
   }
-  x[L] += acc;
+  acc += __shfl_xor(acc, 1, kGenLanes);
+  acc += __shfl_xor(acc, 2, kGenLanes);
+  if (sub == 0) x[L] += acc;
 }
 
 void launch_smooth_general(hipStream_t s, int ng, const int32_t *grow_lat, const int32_t *sptr,
                            const int32_t *scol, const double *sval, const double *r, double *x, const int32_t *done) {
   if (ng <= 0) return;
-  k_smooth_general<<<grid_for(ng), kRowBlock, 0, s>>>(ng, grow_lat, sptr, scol, sval, r, x, done);
+  k_smooth_general<<<grid_for(ng * kGenLanes), kRowBlock, 0, s>>>(ng, grow_lat, sptr, scol, sval, r, x, done);
 }
 
 // one thread per general row: adds row a of every block holding the row into
