@@ -329,7 +329,6 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
   {
     const int TX = L.dim == 2 ? kTile2X : kTile3X, TY = L.dim == 2 ? kTile2Y : kTile3Y;
     const int TZ = L.dim == 2 ? 1 : kTile3Z;
-    const int WX = TX + 2 * L.reach, WY = TY + 2 * L.reach;
     const int sx = L.shape[0], sy = L.shape[1], sz = L.shape[2];
     const int ntx = (sx + TX - 1) / TX, nty = (sy + TY - 1) / TY, ntz = (sz + TZ - 1) / TZ;
     const int64_t ntiles = tiled ? int64_t(ntx) * nty * ntz : 0;
@@ -338,13 +337,12 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
       const int x = int(Lp % sx), y = int((Lp / sx) % sy), z = int(Lp / (int64_t(sx) * sy));
       return (x / TX) + int64_t(ntx) * ((y / TY) + int64_t(nty) * (z / TZ));
     };
-    auto local_of = [&](int64_t Lp) {
+    auto local_of = [&](int64_t Lp) {  // the box-local point = the thread owning it
       const int x = int(Lp % sx), y = int((Lp / sx) % sy), z = int(Lp / (int64_t(sx) * sy));
-      return int32_t(((z % TZ) * WY + (y % TY)) * WX + (x % TX));
+      return int32_t(((z % TZ) * TY + (y % TY)) * TX + (x % TX));
     };
-    std::vector<int32_t> tg0(size_t(ntiles) + 1, 0), tany(std::max<int64_t>(ntiles, 1), 0), sloc;
+    std::vector<int32_t> tg0(size_t(ntiles) + 1, 0), sloc;
     if (tiled) {
-      for (int i = 0; i < L.n; ++i) tany[size_t(tile_of(L.h_row_lat[i]))] = 1;
       std::vector<int32_t> cnt(size_t(ntiles) + 1, 0);
       for (int32_t i : comp) ++cnt[size_t(tile_of(L.h_row_lat[i])) + 1];
       for (int64_t b = 0; b < ntiles; ++b) cnt[size_t(b) + 1] += cnt[size_t(b)];
@@ -355,30 +353,17 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
       for (size_t g = 0; g < ord.size(); ++g) sloc[g] = local_of(L.h_row_lat[ord[g]]);
     }
     for (int g = 0; g < nv; ++g) L.h_meta[ord[g]] = uint32_t(g);
-    std::vector<int32_t> slat(ord.size());
-    for (size_t k = 0; k < ord.size(); ++k) slat[k] = L.h_row_lat[ord[k]];
-    int32_t *d_srow = dalloc<int32_t>(c->owned, std::max<size_t>(ord.size(), 1));
-    int32_t *d_slat = dalloc<int32_t>(c->owned, std::max<size_t>(ord.size(), 1));
-    int32_t *d_sloc = dalloc<int32_t>(c->owned, std::max<size_t>(ord.size(), 1));
-    if (!ord.empty()) {
-      h2d(s, d_srow, ord.data(), ord.size());
-      h2d(s, d_slat, slat.data(), slat.size());
-      if (tiled) h2d(s, d_sloc, sloc.data(), sloc.size());
-    }
+    int32_t *d_sloc = dalloc<int32_t>(c->owned, std::max<size_t>(sloc.size(), 1));
+    if (!sloc.empty()) h2d(s, d_sloc, sloc.data(), sloc.size());
     int32_t *d_tg0 = dalloc<int32_t>(c->owned, tg0.size());
     h2d(s, d_tg0, tg0.data(), tg0.size());
-    int32_t *d_tany = dalloc<int32_t>(c->owned, tany.size());
-    h2d(s, d_tany, tany.data(), tany.size());
     std::vector<int32_t> l2r(tiled ? size_t(L.lattice) : 1, -1);
     if (tiled)
       for (int i = 0; i < L.n; ++i) l2r[size_t(L.h_row_lat[i])] = i;
     int32_t *d_l2r = dalloc<int32_t>(c->owned, l2r.size());
     h2d(s, d_l2r, l2r.data(), l2r.size());
-    for (auto *o : {&L.op64.srow, &L.op32.srow}) *o = d_srow;
-    for (auto *o : {&L.op64.slat, &L.op32.slat}) *o = d_slat;
     for (auto *o : {&L.op64.sloc, &L.op32.sloc}) *o = d_sloc;
     for (auto *o : {&L.op64.tile_g0, &L.op32.tile_g0}) *o = d_tg0;
-    for (auto *o : {&L.op64.tile_any, &L.op32.tile_any}) *o = d_tany;
     for (auto *o : {&L.op64.lat2row, &L.op32.lat2row}) *o = d_l2r;
     L.op64.sx = L.op32.sx = sx;
     L.op64.sy = L.op32.sy = sy;

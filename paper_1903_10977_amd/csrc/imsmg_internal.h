@@ -46,11 +46,8 @@ struct OpView {
   const V *ref;            // uniform interior stencil (K values)
   const V *val;            // stored rows, slot-major
   int nv;                  // number of stored rows (numbered tile by tile)
-  const int32_t *srow;     // row index of every stored row
-  const int32_t *slat;     // lattice position of every stored row
-  const int32_t *sloc;     // window offset of every stored row within its tile's LDS window
+  const int32_t *sloc;     // lattice point of every stored row within its tile box (tx + TX (ty + TY tz))
   const int32_t *tile_g0;  // first stored row of every lattice tile (ntiles + 1 entries)
-  const int32_t *tile_any; // 1 if the tile holds an active row
   const int32_t *lat2row;  // lattice point -> row (-1: inactive)
   int sx, sy, sz;          // lattice shape (sz = 1 in 2D)
   int ntx, nty, ntiles;    // lattice tiles along x, along y, in total

@@ -14,7 +14,8 @@
 //     stencil takes its K coefficients from scalar loads (wave-uniform
 //     addresses); (2) the tile's stored rows, numbered consecutively tile by
 //     tile, are packed onto the first lanes, so that their slot-major values
-//     are read with fully coalesced, fully active vector loads.
+//     are read with fully coalesced, fully active vector loads; their
+//     results go back to the rows' own lanes through LDS.
 // Generic K gathers per lane from global memory (one row per thread).
 // Shared by the level and CG kernels.
 #pragma once
@@ -39,7 +40,9 @@ struct StencilShape {
   static constexpr int WX = TX + 2 * P;
   static constexpr int WY = TY + 2 * P;
   static constexpr int WZ = DIM == 2 ? 1 : TZ + 2 * P;
-  static constexpr int LDS_DOUBLES = TILED ? WX * WY * WZ : 1;
+  static constexpr int WINDOW = WX * WY * WZ;
+  // x window, then one exchange slot per lattice point of the box
+  static constexpr int LDS_DOUBLES = TILED ? WINDOW + kTileRows : 1;
   static_assert(!TILED || TX * TY * TZ == kTileRows, "one lattice point per thread");
 };
 
@@ -79,20 +82,23 @@ __device__ __forceinline__ TileBox tile_box(int b, int ntx, int nty) {
   return {bx * SS::TX, (r % nty) * SS::TY, (r / nty) * SS::TZ};
 }
 
-// Stages the x window of the tile box into LDS: window point (wx, wy, wz) is
-// lattice point (x0 - p + wx, y0 - p + wy, z0 - p + wz), 0 outside the
-// lattice (such points only meet zero coefficients).  All loads of a thread
-// are issued before its LDS writes, so that it waits for them once.  Every
-// thread of the workgroup must call it (it synchronizes).
-template <int K, typename V>
-__device__ __forceinline__ void tile_stage(const TileBox &tb, const OpView<V> &op, const double *__restrict__ x,
-                                           double *lds) {
-  using SS = StencilShape<K>;
-  constexpr int N = SS::WX * SS::WY * SS::WZ;
-  constexpr int PER = (N + kTileRows - 1) / kTileRows;
+// The x window of the tile box: window point (wx, wy, wz) is lattice point
+// (x0 - p + wx, y0 - p + wy, z0 - p + wz), 0 outside the lattice (such points
+// only meet zero coefficients).  tile_load issues every load of a thread
+// (they depend on the box only), tile_store writes them to LDS once they have
+// arrived (the caller synchronizes).
+template <int K>
+struct TileRegs {
+  static constexpr int PER = StencilShape<K>::TILED ? (StencilShape<K>::WINDOW + kTileRows - 1) / kTileRows : 1;
   double v[PER];
+};
+
+template <int K, typename V>
+__device__ __forceinline__ void tile_load(const TileBox &tb, const OpView<V> &op, const double *__restrict__ x,
+                                          TileRegs<K> &w) {
+  using SS = StencilShape<K>;
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
+  for (int q = 0; q < TileRegs<K>::PER; ++q) {
     const int e = threadIdx.x + q * kTileRows;
     const int wx = e % SS::WX;
     const int wy = (e / SS::WX) % SS::WY;
@@ -100,15 +106,22 @@ __device__ __forceinline__ void tile_stage(const TileBox &tb, const OpView<V> &o
     const int gx = tb.x0 - SS::P + wx;
     const int gy = tb.y0 - SS::P + wy;
     const int gz = tb.z0 - (SS::DIM == 3 ? SS::P : 0) + wz;
-    const bool in = e < N && gx >= 0 && gx < op.sx && gy >= 0 && gy < op.sy && gz >= 0 && gz < op.sz;
-    v[q] = in ? x[gx + op.sx * (gy + op.sy * gz)] : 0.0;
+    const bool in = e < SS::WINDOW && gx >= 0 && gx < op.sx && gy >= 0 && gy < op.sy && gz >= 0 && gz < op.sz;
+    // unconditional load (lattice point 0 outside the box), so that the
+    // loads stay countable and a later wait for an older load need not
+    // include them
+    const double t = x[in ? gx + op.sx * (gy + op.sy * gz) : 0];
+    w.v[q] = in ? t : 0.0;
   }
+}
+
+template <int K>
+__device__ __forceinline__ void tile_store(const TileRegs<K> &w, double *lds) {
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
+  for (int q = 0; q < TileRegs<K>::PER; ++q) {
     const int e = threadIdx.x + q * kTileRows;
-    if (e < N) lds[e] = v[q];
+    if (e < StencilShape<K>::WINDOW) lds[e] = w.v[q];
   }
-  __syncthreads();
 }
 
 // window entry of slot s for the row whose window corner (dx = dy = dz = -p)
@@ -126,10 +139,12 @@ __device__ __forceinline__ double tile_center(const double *t) {
   return t[((SS::DIM == 3 ? SS::P : 0) * SS::WY + SS::P) * SS::WX + SS::P];
 }
 
-// window corner offset of the lattice point at box-local (tx, ty, tz)
+// window corner offset of the box's lattice point t (= tx + TX (ty + TY tz),
+// the thread that owns it)
 template <int K>
-__device__ __forceinline__ int tile_local(int tx, int ty, int tz) {
+__device__ __forceinline__ int tile_local(int t) {
   using SS = StencilShape<K>;
+  const int tx = t % SS::TX, ty = (t / SS::TX) % SS::TY, tz = t / (SS::TX * SS::TY);
   return (tz * SS::WY + ty) * SS::WX + tx;
 }
 
@@ -148,6 +163,12 @@ inline int stencil_grid(int K, int n, const OpView<V> &op) {
 // adds up per thread.  Tiled K: blk is a lattice tile; otherwise rows
 // [blk * kTileRows, ...).  With done != nullptr nothing is computed or stored
 // once *done is set.  Every thread of the workgroup must call it.
+//
+// Tiled, the dependent memory rounds are: (1) the x window (it depends on
+// the box only), the lane's row index and the tile's stored-row range;
+// (2) the lane's meta and epilogue loads, the stored rows' owners.  A stored
+// row's A x is computed on a packed lane and handed to the lane owning the row
+// through LDS, so that every epilogue runs on its own lane's data.
 template <int K, typename V, typename Epi>
 __device__ __forceinline__ double2 tile_rows(int n, int blk, const OpView<V> &op,
                                              const int32_t *__restrict__ row_lat, const uint32_t *__restrict__ meta,
@@ -164,53 +185,47 @@ __device__ __forceinline__ double2 tile_rows(int n, int blk, const OpView<V> &op
     const int gx = tb.x0 + tx, gy = tb.y0 + ty, gz = tb.z0 + tz;
     const bool inbox = gx < op.sx && gy < op.sy && gz < op.sz;
     const int L = inbox ? gx + op.sx * (gy + op.sy * gz) : 0;
-    int i = -1;
-    unsigned m = 0u;
-    Pre p1{};
-    if (inbox) {
-      i = op.lat2row[L];
-      if (i >= 0) {
-        m = meta[i];
-        p1 = epi.pre(i, L);
-      }
-    }
-    const bool act = i >= 0;
-    // the tile's stored rows (phase 2), fetched before staging as well
+    // the row index first: the wait for it (loads complete in issue order)
+    // then does not include the window
+    const int i0 = op.lat2row[L];  // L = 0 outside the box: a valid address
+    const int i = inbox ? i0 : -1;
+    TileRegs<K> w;
+    tile_load<K>(tb, op, x, w);
     const int g = op.tile_g0[blk] + threadIdx.x;
     const bool act2 = g < op.tile_g0[blk + 1];
-    int i2 = 0, L2 = 0, o2 = 0;
-    unsigned m2 = 0u;
-    Pre p2{};
-    if (act2) {
-      i2 = op.srow[g];
-      L2 = op.slat[g];
-      o2 = op.sloc[g];
-      m2 = meta[i2];
-      p2 = epi.pre(i2, L2);
+    unsigned m = 0u;
+    Pre p1{};
+    if (i >= 0) {
+      m = meta[i];
+      p1 = epi.pre(i, L);
     }
+    const int own2 = act2 ? op.sloc[g] : 0;
     if (done && *done) return acc;
-    if (!op.tile_any[blk]) return acc;  // no active row in the box (uniform)
-    tile_stage<K>(tb, op, x, lds);
+    double *xch = lds + SS::WINDOW;
+    tile_store<K>(w, lds);
+    __syncthreads();
+    const double *t = lds + tile_local<K>(threadIdx.x);
+    double ax = 0.0;
     // phase 1: rows on the reference stencil
-    if (act && (m & kMetaIndex) == kMetaIndex) {
-      const double *t = lds + tile_local<K>(tx, ty, tz);
+    if (i >= 0 && (m & kMetaIndex) == kMetaIndex) {
       const ConstPtr<V> ref = (ConstPtr<V>)op.ref;
-      double ax = 0.0;
 #pragma unroll
       for (int s = 0; s < K; ++s) ax += double(ref[s]) * tile_at<K>(t, s);
-      const double2 c = epi.post(i, L, m, ax, tile_center<K>(t), p1);
-      acc.x += c.x;
-      acc.y += c.y;
     }
     // phase 2: the tile's stored rows, packed onto the first lanes
     if (act2) {
-      const double *t = lds + o2;
+      const double *t2 = lds + tile_local<K>(own2);
       const V *__restrict__ v = op.val + g;
       const size_t nv = size_t(op.nv);
-      double ax = 0.0;
+      double a2 = 0.0;
 #pragma unroll
-      for (int s = 0; s < K; ++s) ax += double(v[s * nv]) * tile_at<K>(t, s);
-      const double2 c = epi.post(i2, L2, m2, ax, tile_center<K>(t), p2);
+      for (int s = 0; s < K; ++s) a2 += double(v[s * nv]) * tile_at<K>(t2, s);
+      xch[own2] = a2;
+    }
+    __syncthreads();
+    if (i >= 0) {
+      if ((m & kMetaIndex) != kMetaIndex) ax = xch[threadIdx.x];
+      const double2 c = epi.post(i, L, m, ax, tile_center<K>(t), p1);
       acc.x += c.x;
       acc.y += c.y;
     }
