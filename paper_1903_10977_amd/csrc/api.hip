@@ -81,6 +81,10 @@ struct Level {
   int rbW = 0, pbW = 0;
   int32_t *rb_start = nullptr, *rb_len = nullptr, *pb_start = nullptr, *pb_len = nullptr;
   double *rb_coef = nullptr, *pb_coef = nullptr;
+  // prolongation fused into the first post-smoothing step (tiled stencil,
+  // tensor transfer, every tile's coarse window within the fixed bound)
+  bool pro_ok = false;
+  int32_t *pro_org = nullptr;  // coarse window origin per tile along x, y, z
   // input blocks
   std::vector<int32_t> in_ptr, in_idx;
   std::vector<double> omega;  // optional per-block weights
@@ -509,6 +513,40 @@ void setup_tensor_transfer(imsmg_ctx *c, Level &F, const Level &Cl, const imsmg_
   h2d(s, F.pb_coef, pcf.data(), pcf.size());
   HIP_CHECK_RET(hipStreamSynchronize(s));
   F.tensor = true;
+  // coarse window of every lattice tile for the fused prolongation: along
+  // each axis, the coarse indices the bands of the tile's x window reach
+  // (window = tile extent + the stencil reach on both sides)
+  F.pro_ok = false;
+  const bool tiled = F.op64.ntiles > 0;
+  if (tiled && F.dim == 2 && F.pbW <= kBandMax) {
+    const int T[3] = {F.dim == 2 ? kTile2X : kTile3X, F.dim == 2 ? kTile2Y : kTile3Y, F.dim == 2 ? 1 : kTile3Z};
+    const int nt[3] = {F.op64.ntx, F.op64.nty, F.dim == 3 ? (F.shape[2] + T[2] - 1) / T[2] : 1};
+    // per-axis bound of the coarse window (the kernels' compile-time extent)
+    std::vector<int32_t> org;
+    bool ok = true;
+    for (int a = 0; a < F.dim && ok; ++a) {
+      const int P = F.reach, Wa = T[a] + 2 * P;
+      const int cwa = Wa / 2 + kBandMax + 1;
+      for (int b = 0; b < nt[a]; ++b) {
+        int lo = INT32_MAX, hi = -1;
+        for (int j = 0; j < Wa; ++j) {
+          const int f = b * T[a] - P + j;
+          if (f < 0 || f >= mf || pl[f] <= 0) continue;
+          lo = std::min(lo, ps[f]);
+          hi = std::max(hi, ps[f] + pl[f]);
+        }
+        if (hi < 0) lo = hi = 0;
+        if (hi - lo > cwa) ok = false;
+        org.push_back(lo);
+      }
+    }
+    if (ok) {
+      F.pro_org = dalloc<int32_t>(c->owned, org.size());
+      h2d(s, F.pro_org, org.data(), org.size());
+      HIP_CHECK_RET(hipStreamSynchronize(s));
+      F.pro_ok = true;
+    }
+  }
 }
 
 void setup_transfer(imsmg_ctx *c, Level &F, const Level &Cl, const imsmg_csr &R, const double *two_scale) {
@@ -597,14 +635,15 @@ void residual(imsmg_ctx *c, Level &L, const double *x, const double *b, double *
 }
 
 // smoothing step from xa: rh = r - A xa, xb = xa + S rh  (trivial rows fused,
-// then the general rows)
-void smooth_step(imsmg_ctx *c, Level &L, const double *xa, double *xb, const int32_t *done, bool timed) {
+// then the general rows); pv: from xa + R^T xc (prolongation fused)
+void smooth_step(imsmg_ctx *c, Level &L, const double *xa, double *xb, const int32_t *done, bool timed,
+                 const ProlongView *pv = nullptr) {
   hipEvent_t *ev = timed ? timed_pair(c) : nullptr;
   if (ev) HIP_CHECK_RET(hipEventRecord(ev[0], c->stream));
   if (mixed(c))
-    launch_residual_smooth(c->stream, L.n, L.K, L.op32, L.row_lat, L.meta, L.c, xa, L.r, L.rh, xb, done);
+    launch_residual_smooth(c->stream, L.n, L.K, L.op32, L.row_lat, L.meta, L.c, xa, L.r, L.rh, xb, done, pv);
   else
-    launch_residual_smooth(c->stream, L.n, L.K, L.op64, L.row_lat, L.meta, L.c, xa, L.r, L.rh, xb, done);
+    launch_residual_smooth(c->stream, L.n, L.K, L.op64, L.row_lat, L.meta, L.c, xa, L.r, L.rh, xb, done, pv);
   if (ev) HIP_CHECK_RET(hipEventRecord(ev[1], c->stream));
   launch_smooth_general(c->stream, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, L.rh, xb, done);
 }
@@ -653,8 +692,18 @@ void vcycle_level(imsmg_ctx *c, int l, const int32_t *done_top, bool timing) {
   residual(c, L, xa, L.r, L.rh, done, false);
   restrict_to(c, L, Cl, L.rh, Cl.r, l - 1 > 0 ? Cl.xs : nullptr, flag_for(Cl, done_top));
   vcycle_level(c, l - 1, done_top, timing);
-  prolong_add(c, L, Cl, Cl.x, xa, done);
-  for (int k = 0; k < c->opt.nu_post; ++k) {
+  int k = 0;
+  if (L.pro_ok && c->opt.nu_post > 0) {
+    // x += R^T x_c inside the first post-smoothing step's staging (not one of
+    // the timed plain smoothing steps)
+    const ProlongView pv{Cl.x, L.pb_start, L.pb_len, L.pb_coef, L.pbW, Cl.shape[0], L.pro_org};
+    smooth_step(c, L, xa, xb, done, false, &pv);
+    std::swap(xa, xb);
+    k = 1;
+  } else {
+    prolong_add(c, L, Cl, Cl.x, xa, done);
+  }
+  for (; k < c->opt.nu_post; ++k) {
     smooth_step(c, L, xa, xb, done, fine);
     std::swap(xa, xb);
   }

@@ -53,6 +53,25 @@ struct OpView {
   int ntx, nty, ntiles;    // lattice tiles along x, along y, in total
 };
 
+// bands of 1D two-scale matrices up to this length take the unrolled
+// transfer paths (B-splines of degree <= 3)
+constexpr int kBandMax = 5;
+
+// Prolongation x_f += R^T x_c applied inside a smoothing step's staging:
+// R^T is the tensor product of one 1D matrix given by bands (per fine 1D
+// index: first coarse index, length, coefficients with stride W <= kBandMax);
+// org holds, per lattice tile along x, then y, then z, the first coarse index
+// of the coarse window the tile's x window needs.
+struct ProlongView {
+  const double *xc;
+  const int32_t *start;
+  const int32_t *len;
+  const double *coef;
+  int W;
+  int cs;  // coarse functions per axis
+  const int32_t *org;
+};
+
 // Scalars of the CG iteration, kept on the device.
 struct CGState {
   double rz;       // r . z of the current iterate
@@ -89,12 +108,14 @@ void launch_residual(hipStream_t s, int n, int K, const OpView<double> &op, cons
                      const uint32_t *meta, const double *x, const double *b, double *y, const int32_t *done);
 void launch_residual(hipStream_t s, int n, int K, const OpView<float> &op, const int32_t *row_lat,
                      const uint32_t *meta, const double *x, const double *b, double *y, const int32_t *done);
+// pv != nullptr: the step starts from xa + R^T xc (prolongation of the coarse
+// correction applied while the x window is staged; tiled K, tensor transfers)
 void launch_residual_smooth(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                             const uint32_t *meta, const double *c, const double *xa, const double *r, double *rh,
-                            double *xb, const int32_t *done);
+                            double *xb, const int32_t *done, const ProlongView *pv = nullptr);
 void launch_residual_smooth(hipStream_t s, int n, int K, const OpView<float> &op, const int32_t *row_lat,
                             const uint32_t *meta, const double *c, const double *xa, const double *r, double *rh,
-                            double *xb, const int32_t *done);
+                            double *xb, const int32_t *done, const ProlongView *pv = nullptr);
 // general Schwarz rows: x[grow_lat[t]] += sum_k S[t,k] r[scol[k]]  (S_G in CSR, lattice columns)
 void launch_smooth_general(hipStream_t s, int ng, const int32_t *grow_lat, const int32_t *sptr,
                            const int32_t *scol, const double *sval, const double *r, double *x, const int32_t *done);

@@ -21,6 +21,8 @@
 // so that each of the 8 XCDs walks one contiguous chunk of rows and keeps the
 // neighbouring lattice lines of the input vector in its own L2.  The stencil
 // kernels stage the workgroup's window of the input vector in LDS (op_row.h).
+#include <stdexcept>
+
 #include "imsmg_internal.h"
 #include "op_row.h"
 
@@ -86,8 +88,9 @@ __global__ __launch_bounds__(kRowBlock, kTileBlocksPerCU) void k_residual(int n,
 }
 
 // smoothing step, trivial rows:  rh = r - A xa  (stored for general rows only),
-// xb = xa + c * rh   (c = 0 on general rows, which the general kernel completes)
-template <int K, typename V>
+// xb = xa + c * rh   (c = 0 on general rows, which the general kernel completes);
+// PRO: xa + R^T xc in place of xa (the prolongation of the coarse correction)
+template <int K, typename V, bool PRO>
 __global__ __launch_bounds__(kRowBlock, kTileBlocksPerCU) void k_residual_smooth(int n, int Kdyn, OpView<V> op,
                                                                const int32_t *__restrict__ row_lat,
                                                                const uint32_t *__restrict__ meta,
@@ -95,9 +98,10 @@ __global__ __launch_bounds__(kRowBlock, kTileBlocksPerCU) void k_residual_smooth
                                                                const double *__restrict__ xa,
                                                                const double *__restrict__ r, double *__restrict__ rh,
                                                                double *__restrict__ xb,
-                                                               const int32_t *__restrict__ done) {
-  __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
-  tile_rows<K, V>(n, xcd_block(blockIdx.x, gridDim.x), op, row_lat, meta, xa, tile, Kdyn, SmoothEpi{r, c, rh, xb}, done);
+                                                               const int32_t *__restrict__ done, ProlongView pv) {
+  __shared__ double tile[StencilShape<K>::LDS_DOUBLES + (PRO ? ProShape<K>::LDS_EXTRA : 0)];
+  tile_rows<K, V, SmoothEpi, PRO>(n, xcd_block(blockIdx.x, gridDim.x), op, row_lat, meta, xa, tile, Kdyn,
+                                  SmoothEpi{r, c, rh, xb}, done, &pv);
 }
 
 template <typename V>
@@ -118,17 +122,31 @@ static void dispatch_residual(hipStream_t s, int n, int K, const OpView<V> &op, 
 template <typename V>
 static void dispatch_residual_smooth(hipStream_t s, int n, int K, const OpView<V> &op, const int32_t *row_lat,
                                      const uint32_t *meta, const double *c, const double *xa, const double *r,
-                                     double *rh, double *xb, const int32_t *done) {
+                                     double *rh, double *xb, const int32_t *done, const ProlongView *pv) {
   if (n <= 0) return;
   dim3 g(stencil_grid(K, n, op)), t(kRowBlock);
+  const ProlongView p = pv ? *pv : ProlongView{};
+#define IMSMG_RS(KK)                                                                                   \
+  if (pv)                                                                                              \
+    k_residual_smooth<KK, V, true><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done, p); \
+  else                                                                                                 \
+    k_residual_smooth<KK, V, false><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done, p);
+#define IMSMG_RS3(KK)                                                                                   \
+  if (pv) throw std::invalid_argument("fused prolongation: 2D lattices only");                          \
+  k_residual_smooth<KK, V, false><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done, p);
   switch (K) {
-    case 9: k_residual_smooth<9, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done); break;
-    case 25: k_residual_smooth<25, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done); break;
-    case 49: k_residual_smooth<49, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done); break;
-    case 27: k_residual_smooth<27, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done); break;
-    case 125: k_residual_smooth<125, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done); break;
-    default: k_residual_smooth<0, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done); break;
+    case 9: IMSMG_RS(9) break;
+    case 25: IMSMG_RS(25) break;
+    case 49: IMSMG_RS(49) break;
+    case 27: IMSMG_RS3(27) break;
+    case 125: IMSMG_RS3(125) break;
+    default:
+      if (pv) throw std::invalid_argument("fused prolongation needs a tiled stencil");
+      k_residual_smooth<0, V, false><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done, p);
+      break;
   }
+#undef IMSMG_RS
+#undef IMSMG_RS3
 }
 
 void launch_residual(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
@@ -141,13 +159,13 @@ void launch_residual(hipStream_t s, int n, int K, const OpView<float> &op, const
 }
 void launch_residual_smooth(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                             const uint32_t *meta, const double *c, const double *xa, const double *r, double *rh,
-                            double *xb, const int32_t *done) {
-  dispatch_residual_smooth<double>(s, n, K, op, row_lat, meta, c, xa, r, rh, xb, done);
+                            double *xb, const int32_t *done, const ProlongView *pv) {
+  dispatch_residual_smooth<double>(s, n, K, op, row_lat, meta, c, xa, r, rh, xb, done, pv);
 }
 void launch_residual_smooth(hipStream_t s, int n, int K, const OpView<float> &op, const int32_t *row_lat,
                             const uint32_t *meta, const double *c, const double *xa, const double *r, double *rh,
-                            double *xb, const int32_t *done) {
-  dispatch_residual_smooth<float>(s, n, K, op, row_lat, meta, c, xa, r, rh, xb, done);
+                            double *xb, const int32_t *done, const ProlongView *pv) {
+  dispatch_residual_smooth<float>(s, n, K, op, row_lat, meta, c, xa, r, rh, xb, done, pv);
 }
 
 // General Schwarz rows: x[L_t] += sum_k S_G[t,k] r[col_k].  S_G is the sum of
@@ -275,7 +293,6 @@ struct Band {
   const double *coef;
   int W;
 };
-constexpr int kBandMax = 5;  // bands up to this length take the unrolled 2D path (p <= 3 B-splines)
 
 template <int DIM>
 __global__ __launch_bounds__(kRowBlock) void k_tensor_transfer(int n, const int32_t *__restrict__ row_lat,

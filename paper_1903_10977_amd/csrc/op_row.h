@@ -148,6 +148,27 @@ __device__ __forceinline__ int tile_local(int t) {
   return (tz * SS::WY + ty) * SS::WX + tx;
 }
 
+// Coarse window of a tile for the fused prolongation (2D): the coarse points
+// the two-scale bands of the x window reach (at most W / 2 + kBandMax + 1
+// per axis, checked on the host), per window index along x and y the band
+// (local first index, length, kBandMax coefficients), and the x-pass sums
+// (one per coarse row of the window and window column).
+template <int K>
+struct ProShape {
+  using SS = StencilShape<K>;
+  static constexpr int CWX = SS::WX / 2 + kBandMax + 1;
+  static constexpr int CWY = SS::WY / 2 + kBandMax + 1;
+  static constexpr int CWN = CWX * CWY;
+  static constexpr int NB = SS::WX + SS::WY;  // band rows
+  static constexpr int NT = CWY * SS::WX;     // x-pass sums
+  static constexpr int PERC = (CWN + kTileRows - 1) / kTileRows;
+  static constexpr int PERT = (NT + kTileRows - 1) / kTileRows;
+  // LDS (doubles) after the x window and the exchange slots: coarse window,
+  // band coefficients, band first index and length (two ints per double),
+  // x-pass sums
+  static constexpr int LDS_EXTRA = CWN + NB * kBandMax + NB + NT;
+};
+
 // Grid of a stencil kernel over a level: one workgroup per lattice tile when
 // K is tiled, else one per kTileRows rows.
 template <typename V>
@@ -169,11 +190,16 @@ inline int stencil_grid(int K, int n, const OpView<V> &op) {
 // (2) the lane's meta and epilogue loads, the stored rows' owners.  A stored
 // row's A x is computed on a packed lane and handed to the lane owning the row
 // through LDS, so that every epilogue runs on its own lane's data.
-template <int K, typename V, typename Epi>
+//
+// PRO: the rows see x + R^T xc (pv): the band rows of the window and the
+// coarse window origins join round 1, the coarse window round 2; the
+// corrections are added to the window registers before they go to LDS, in
+// the order of the transfer kernel (bitwise the same x + R^T xc).
+template <int K, typename V, typename Epi, bool PRO = false>
 __device__ __forceinline__ double2 tile_rows(int n, int blk, const OpView<V> &op,
                                              const int32_t *__restrict__ row_lat, const uint32_t *__restrict__ meta,
                                              const double *__restrict__ x, double *lds, int Kdyn, const Epi &epi,
-                                             const int32_t *done = nullptr) {
+                                             const int32_t *done = nullptr, const ProlongView *pv = nullptr) {
   using Pre = typename Epi::Pre;
   using SS = StencilShape<K>;
   double2 acc = make_double2(0.0, 0.0);
@@ -191,6 +217,30 @@ __device__ __forceinline__ double2 tile_rows(int n, int blk, const OpView<V> &op
     const int i = inbox ? i0 : -1;
     TileRegs<K> w;
     tile_load<K>(tb, op, x, w);
+    using PS = ProShape<K>;
+    // PRO, round 1: this lane's band row (lanes < NB) and the coarse origins
+    int bsx = 0, bln = 0;
+    double bcf[kBandMax];
+    int co[2] = {0, 0};
+    if constexpr (PRO) {
+      static_assert(SS::DIM == 2, "fused prolongation: 2D lattices");
+      co[0] = pv->org[blk % op.ntx];
+      co[1] = pv->org[op.ntx + (blk / op.ntx) % op.nty];
+      const int e = threadIdx.x;
+      const int ax = e < SS::WX ? 0 : 1;
+      const int f = (ax == 0 ? tb.x0 + e : tb.y0 + e - SS::WX) - SS::P;
+      const int sa = ax == 0 ? op.sx : op.sy;
+      const bool ok = e < PS::NB && f >= 0 && f < sa;
+      const int fc = ok ? f : 0;  // unconditional loads
+      const int st = pv->start[fc], ln = pv->len[fc];
+#pragma unroll
+      for (int a = 0; a < kBandMax; ++a) {
+        const double cv = pv->coef[size_t(fc) * pv->W + (a < pv->W ? a : 0)];
+        bcf[a] = (ok && a < pv->W) ? cv : 0.0;
+      }
+      bsx = (ok && ln > 0) ? st : 0;
+      bln = ok ? ln : 0;
+    }
     const int g = op.tile_g0[blk] + threadIdx.x;
     const bool act2 = g < op.tile_g0[blk + 1];
     unsigned m = 0u;
@@ -202,6 +252,69 @@ __device__ __forceinline__ double2 tile_rows(int n, int blk, const OpView<V> &op
     const int own2 = act2 ? op.sloc[g] : 0;
     if (done && *done) return acc;
     double *xch = lds + SS::WINDOW;
+    if constexpr (PRO) {
+      // round 2: the coarse window
+      double cwv[PS::PERC];
+#pragma unroll
+      for (int q = 0; q < PS::PERC; ++q) {
+        const int e = threadIdx.x + q * kTileRows;
+        const int cx = co[0] + e % PS::CWX;
+        const int cy = co[1] + e / PS::CWX;
+        const bool in = e < PS::CWN && cx < pv->cs && cy < pv->cs;
+        const double t = pv->xc[in ? cx + size_t(pv->cs) * cy : 0];
+        cwv[q] = in ? t : 0.0;
+      }
+      double *cw = xch + kTileRows;
+      double *bc = cw + PS::CWN;
+      int *bi = reinterpret_cast<int *>(bc + PS::NB * kBandMax);
+      double *tx1 = bc + PS::NB * kBandMax + PS::NB;
+      if (threadIdx.x < PS::NB) {
+        const int ax = threadIdx.x < SS::WX ? 0 : 1;
+#pragma unroll
+        for (int a = 0; a < kBandMax; ++a) bc[threadIdx.x * kBandMax + a] = bcf[a];
+        bi[2 * threadIdx.x] = max(bsx - co[ax], 0);  // length-0 bands: 0 (zero coefficients)
+        bi[2 * threadIdx.x + 1] = bln;
+      }
+#pragma unroll
+      for (int q = 0; q < PS::PERC; ++q) {
+        const int e = threadIdx.x + q * kTileRows;
+        if (e < PS::CWN) cw[e] = cwv[q];
+      }
+      __syncthreads();
+      // R^T xc separably, in the transfer kernel's order: per coarse row and
+      // window column t = sum_a cx[a] xc[row][sx + a], then per window point
+      // sum_b cy[b] t[sy + b].  Entries past a band's length have zero
+      // coefficients; their (clamped, finite) inputs add exact zeros.
+      const int W = pv->W;
+#pragma unroll
+      for (int q = 0; q < PS::PERT; ++q) {
+        const int e = threadIdx.x + q * kTileRows;
+        if (e < PS::NT) {
+          const int wx = e % SS::WX, cyl = e / SS::WX;
+          const double *cxv = bc + wx * kBandMax;
+          const double *row = cw + cyl * PS::CWX;
+          const int sxl = bi[2 * wx];
+          double t = 0.0;
+          for (int a = 0; a < W; ++a) t += cxv[a] * row[min(sxl + a, PS::CWX - 1)];
+          tx1[e] = t;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < TileRegs<K>::PER; ++q) {
+        const int e = threadIdx.x + q * kTileRows;
+        const int wx = e % SS::WX, wy = e / SS::WX;
+        const int gx2 = tb.x0 - SS::P + wx, gy2 = tb.y0 - SS::P + wy;
+        const bool in = e < SS::WINDOW && gx2 >= 0 && gx2 < op.sx && gy2 >= 0 && gy2 < op.sy;
+        if (!in) continue;
+        const int ry = SS::WX + wy;
+        const double *cyv = bc + ry * kBandMax;
+        const int syl = bi[2 * ry];
+        double corr = 0.0;
+        for (int b = 0; b < W; ++b) corr += cyv[b] * tx1[min(syl + b, PS::CWY - 1) * SS::WX + wx];
+        w.v[q] = w.v[q] + corr;
+      }
+    }
     tile_store<K>(w, lds);
     __syncthreads();
     const double *t = lds + tile_local<K>(threadIdx.x);
