@@ -84,7 +84,8 @@ struct Level {
   // prolongation fused into the first post-smoothing step (tiled stencil,
   // tensor transfer, every tile's coarse window within the fixed bound)
   bool pro_ok = false;
-  int32_t *pro_org = nullptr;  // coarse window origin per tile along x, y, z
+  int32_t *pro_org = nullptr;  // coarse window origin per tile along x, y
+  double *pro_coef = nullptr;  // R^T band coefficients, stride kBandMax
   // input blocks
   std::vector<int32_t> in_ptr, in_idx;
   std::vector<double> omega;  // optional per-block weights
@@ -543,6 +544,11 @@ void setup_tensor_transfer(imsmg_ctx *c, Level &F, const Level &Cl, const imsmg_
     if (ok) {
       F.pro_org = dalloc<int32_t>(c->owned, org.size());
       h2d(s, F.pro_org, org.data(), org.size());
+      std::vector<double> c5(size_t(mf) * kBandMax, 0.0);
+      for (int f = 0; f < mf; ++f)
+        for (int a = 0; a < pl[f]; ++a) c5[size_t(f) * kBandMax + a] = pcf[size_t(f) * F.pbW + a];
+      F.pro_coef = dalloc<double>(c->owned, c5.size());
+      h2d(s, F.pro_coef, c5.data(), c5.size());
       HIP_CHECK_RET(hipStreamSynchronize(s));
       F.pro_ok = true;
     }
@@ -696,7 +702,7 @@ void vcycle_level(imsmg_ctx *c, int l, const int32_t *done_top, bool timing) {
   if (L.pro_ok && c->opt.nu_post > 0) {
     // x += R^T x_c inside the first post-smoothing step's staging (not one of
     // the timed plain smoothing steps)
-    const ProlongView pv{Cl.x, L.pb_start, L.pb_len, L.pb_coef, L.pbW, Cl.shape[0], L.pro_org};
+    const ProlongView pv{Cl.x, L.pb_start, L.pb_len, L.pro_coef, L.pbW, Cl.shape[0], L.pro_org};
     smooth_step(c, L, xa, xb, done, false, &pv);
     std::swap(xa, xb);
     k = 1;

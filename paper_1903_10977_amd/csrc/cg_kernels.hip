@@ -151,11 +151,10 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_dot_rz(int n, const int32_t 
   __shared__ double lds[kRedThreads];
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
   const int i = blk * kRedThreads + threadIdx.x;
-  double acc = 0.0;
-  if (i < n) {
-    const int L = row_lat[i];
-    acc = r[L] * z[L];
-  }
+  // unconditional loads at a clamped row (n >= 1), then a select
+  const int L = row_lat[min(i, n - 1)];
+  const double rz = r[L] * z[L];
+  double acc = i < n ? rz : 0.0;
   acc = block_sum<kRedThreads>(acc, lds);
   if (threadIdx.x == 0) part[blk] = acc;
 }

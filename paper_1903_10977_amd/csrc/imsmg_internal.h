@@ -59,7 +59,8 @@ constexpr int kBandMax = 5;
 
 // Prolongation x_f += R^T x_c applied inside a smoothing step's staging:
 // R^T is the tensor product of one 1D matrix given by bands (per fine 1D
-// index: first coarse index, length, coefficients with stride W <= kBandMax);
+// index: first coarse index, length, and coefficients with stride kBandMax,
+// zero past the length; W <= kBandMax is the longest band);
 // org holds, per lattice tile along x, then y, then z, the first coarse index
 // of the coarse window the tile's x window needs.
 struct ProlongView {

@@ -388,15 +388,13 @@ __global__ __launch_bounds__(kGemvThreads) void k_dense_gemv(int n, const int32_
   // gather r in batches of 8 per thread: indices first, then values, so that
   // the loads of a batch are in flight together
   for (int j0 = threadIdx.x; j0 < n; j0 += 8 * kGemvThreads) {
+    // unconditional loads at clamped positions: no wait between them
     int idx[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int j = j0 + q * kGemvThreads;
-      idx[q] = j < n ? row_lat[j] : 0;
-    }
+    for (int q = 0; q < 8; ++q) idx[q] = row_lat[min(j0 + q * kGemvThreads, n - 1)];
     double val[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) val[q] = j0 + q * kGemvThreads < n ? r[idx[q]] : 0.0;
+    for (int q = 0; q < 8; ++q) val[q] = r[idx[q]];
 #pragma unroll
     for (int q = 0; q < 8; ++q)
       if (j0 + q * kGemvThreads < n) rs[j0 + q * kGemvThreads] = val[q];

@@ -235,8 +235,8 @@ __device__ __forceinline__ double2 tile_rows(int n, int blk, const OpView<V> &op
       const int st = pv->start[fc], ln = pv->len[fc];
 #pragma unroll
       for (int a = 0; a < kBandMax; ++a) {
-        const double cv = pv->coef[size_t(fc) * pv->W + (a < pv->W ? a : 0)];
-        bcf[a] = (ok && a < pv->W) ? cv : 0.0;
+        const double cv = pv->coef[fc * kBandMax + a];  // stride kBandMax, zero-padded
+        bcf[a] = ok ? cv : 0.0;
       }
       bsx = (ok && ln > 0) ? st : 0;
       bln = ok ? ln : 0;
