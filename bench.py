@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed",
                     help="headline form (the other form is timed too)")
     ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="general-row smoother with 4 lanes per row on every level instead of the measured choice")
     ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
                     help="c2: 1024^2 cubic discs (headline); c3: 128^3 quadratic gyroid")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -113,13 +115,14 @@ def main():
     def make(prec, timing=0, learned=None):
         o = S.default_options(nu_pre=w.nu, nu_post=w.nu, precision=prec, timing=timing,
                               use_graph=0 if (args.no_graph or timing) else 1, max_iter=2000,
-                              use_learned=int(learned is not None))
+                              use_learned=int(learned is not None), autotune=int(not args.no_autotune))
         t = time.time()
         sol = S.Solver(0).setup(g, o)
         if learned is not None:
             sol.load_mlp(learned)
         sol.factor()
-        log(f"setup+factor precision={prec} {time.time() - t:.2f} s")
+        lanes = [sol.level_stats(l)["general_lanes"] for l in range(1, len(g.levels))]
+        log(f"setup+factor precision={prec} {time.time() - t:.2f} s (general-row lanes per level {lanes})")
         return sol
 
     def timed(sol):

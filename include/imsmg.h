@@ -119,6 +119,11 @@ typedef struct {
   int32_t use_learned; /* 1: imsmg_factor_patches damps every block of every level without given
                           weights by the loaded damping network (imsmg_load_mlp), subject to the
                           stability check; default 0 */
+  int32_t autotune;    /* 1: imsmg_factor_patches times the general-row smoother with 2, 4 and 8
+                          lanes per row on each level (HIP events, a few launches each) and keeps
+                          the fastest; 0: 4 lanes.  The lane count fixes the summation order of
+                          that product, so contexts tuned differently round differently (each
+                          context stays bitwise reproducible); default 0 */
 } imsmg_options;
 
 typedef struct {
@@ -272,7 +277,7 @@ typedef struct {
   int64_t sg_nnz;        /* entries of the assembled general smoother on those rows */
   int64_t lattice;       /* padded lattice size of the level's vectors */
   int32_t value_bytes;   /* 8 (FP64) or 4 (FP32 V-cycle operators) */
-  int32_t reserved;
+  int32_t general_lanes; /* lanes per row of the general-row smoother (2, 4 or 8) */
 } imsmg_level_stats;
 int imsmg_get_level_stats(imsmg_ctx *ctx, int level, imsmg_level_stats *stats);
 

@@ -93,6 +93,7 @@ struct Level {
   std::vector<int32_t> f_ptr, f_idx;  // post-removal blocks (incl. added singletons)
   double *c = nullptr;               // trivial rows: omega_j / A_ii, else 0
   int ng = 0;                         // rows in general blocks
+  int gen_lanes = 4;                  // lanes per row of the general-row product (tuned: 2, 4, 8)
   bool small = false;                 // latency-bound level (no convergence-flag load)
   int32_t *grow_lat = nullptr, *sptr = nullptr, *scol = nullptr;
   double *sval = nullptr;             // S_G = sum_j omega_j P_j A_j^{-1} P_j^T on the general rows (CSR)
@@ -651,7 +652,7 @@ void smooth_step(imsmg_ctx *c, Level &L, const double *xa, double *xb, const int
   else
     launch_residual_smooth(c->stream, L.n, L.K, L.op64, L.row_lat, L.meta, L.c, xa, L.r, L.rh, xb, done, pv);
   if (ev) HIP_CHECK_RET(hipEventRecord(ev[1], c->stream));
-  launch_smooth_general(c->stream, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, L.rh, xb, done);
+  launch_smooth_general(c->stream, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, L.rh, xb, done, L.gen_lanes);
 }
 
 // rc = R_l rf (fine level L, coarse level Cl; padded vectors)
@@ -689,7 +690,7 @@ void vcycle_level(imsmg_ctx *c, int l, const int32_t *done_top, bool timing) {
   Level &Cl = c->lv[l - 1];
   const bool fine = (l == int(c->lv.size()) - 1) && timing;
   // first smoothing step from x = 0: x = S r (general rows)
-  launch_smooth_general(c->stream, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, L.r, L.xs, done);
+  launch_smooth_general(c->stream, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, L.r, L.xs, done, L.gen_lanes);
   double *xa = L.xs, *xb = (L.xs == L.x) ? L.x2 : L.x;
   for (int k = 1; k < c->opt.nu_pre; ++k) {
     smooth_step(c, L, xa, xb, done, fine);
@@ -1106,6 +1107,37 @@ void apply_weights(imsmg_ctx *c, Level &L, const std::vector<double> &w) {
   L.f_w = w;
 }
 
+// Lanes per row of the general-row product, by measurement on the level's
+// own S_G (autotune option): HIP events around a few launches of each
+// variant on the library stream (r = the level's residual buffer, x = the
+// scratch rh buffer, which every smoothing step rewrites before reading).
+void tune_general(imsmg_ctx *c, Level &L) {
+  L.gen_lanes = 4;
+  if (!c->opt.autotune || L.ng <= 0) return;
+  hipStream_t s = c->stream;
+  hipEvent_t e0, e1;
+  HIP_CHECK_RET(hipEventCreate(&e0));
+  HIP_CHECK_RET(hipEventCreate(&e1));
+  float best = 0.f;
+  for (int lanes : {4, 2, 8}) {
+    launch_smooth_general(s, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, L.r, L.rh, c->zero_flag, lanes);
+    HIP_CHECK_RET(hipEventRecord(e0, s));
+    for (int k = 0; k < 8; ++k)
+      launch_smooth_general(s, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, L.r, L.rh, c->zero_flag, lanes);
+    HIP_CHECK_RET(hipEventRecord(e1, s));
+    HIP_CHECK_RET(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_CHECK_RET(hipEventElapsedTime(&ms, e0, e1));
+    if (lanes == 4 || ms < best) {
+      best = ms;
+      L.gen_lanes = lanes;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_CHECK_RET(hipGetLastError());
+}
+
 // ------------------------------------------------------------ per-block damping
 // Sixteen scale-free features per final block (the network's inputs); see
 // the feature list in include/imsmg.h.
@@ -1207,7 +1239,7 @@ double host_dot(imsmg_ctx *c, Level &L, const double *a, const double *b, double
 // y = S x on level L (current weights); y and x padded
 void apply_S(imsmg_ctx *c, Level &L, const double *x, double *y) {
   launch_diag_scale(c->stream, L.n, L.row_lat, L.c, x, y, c->zero_flag);
-  launch_smooth_general(c->stream, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, x, y, c->zero_flag);
+  launch_smooth_general(c->stream, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, x, y, c->zero_flag, L.gen_lanes);
 }
 
 // y = A x on level L in FP64 (y, x padded)
@@ -1720,6 +1752,7 @@ int imsmg_factor_patches(imsmg_ctx *c) {
     if (c->opt.use_learned)
       for (int l = 1; l < int(c->lv.size()); ++l)
         if (L_has_no_user_weights(c->lv[l])) learned_weights(c, l);
+    for (int l = 1; l < int(c->lv.size()); ++l) tune_general(c, c->lv[l]);
     c->factored = true;
     return IMSMG_OK;
   });
@@ -1854,7 +1887,7 @@ int imsmg_apply_smoother(imsmg_ctx *c, int level, const double *r, double *y) {
     Level &L = c->lv[level];
     launch_scatter(c->stream, L.n, L.row_lat, r, L.rh);
     launch_diag_scale(c->stream, L.n, L.row_lat, L.c, L.rh, L.x, c->zero_flag);
-    launch_smooth_general(c->stream, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, L.rh, L.x, c->zero_flag);
+    launch_smooth_general(c->stream, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, L.rh, L.x, c->zero_flag, L.gen_lanes);
     launch_gather(c->stream, L.n, L.row_lat, L.x, y);
     HIP_CHECK_RET(hipGetLastError());
     HIP_CHECK_RET(hipStreamSynchronize(c->stream));
@@ -1922,7 +1955,7 @@ int imsmg_get_level_stats(imsmg_ctx *c, int level, imsmg_level_stats *st) {
     }
     st->lattice = L.lattice;
     st->value_bytes = mixed(c) ? 4 : 8;
-    st->reserved = 0;
+    st->general_lanes = L.gen_lanes;
     return IMSMG_OK;
   });
 }

@@ -119,7 +119,8 @@ void launch_residual_smooth(hipStream_t s, int n, int K, const OpView<float> &op
                             double *xb, const int32_t *done, const ProlongView *pv = nullptr);
 // general Schwarz rows: x[grow_lat[t]] += sum_k S[t,k] r[scol[k]]  (S_G in CSR, lattice columns)
 void launch_smooth_general(hipStream_t s, int ng, const int32_t *grow_lat, const int32_t *sptr,
-                           const int32_t *scol, const double *sval, const double *r, double *x, const int32_t *done);
+                           const int32_t *scol, const double *sval, const double *r, double *x, const int32_t *done,
+                           int lanes = 4);  // lanes per row: 2, 4 or 8
 // S_G = sum_j omega_j P_j A_j^{-1} P_j^T on the general rows, accumulated entry by entry in
 // ascending block order into the CSR pattern (epos: CSR slot of every (entry, member) pair)
 void launch_assemble_sg(hipStream_t s, int ng, const int32_t *gptr, const int64_t *ent_off, const int32_t *ent_n,

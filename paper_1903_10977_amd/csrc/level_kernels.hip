@@ -171,11 +171,11 @@ void launch_residual_smooth(hipStream_t s, int n, int K, const OpView<float> &op
 // General Schwarz rows: x[L_t] += sum_k S_G[t,k] r[col_k].  S_G is the sum of
 // omega_j P_j A_j^{-1} P_j^T over the general blocks, restricted to the rows
 // that belong to one, assembled once at factorization; applying it is a CSR
-// product with lattice column positions (deterministic, no atomics).  Four
-// lanes share a row (entries k0 + lane, k0 + lane + 4, ...: coalesced index
-// and value loads, four times the rows' parallelism), then add their sums in
-// a fixed shuffle order.
-constexpr int kGenLanes = 4;
+// product with lattice column positions (deterministic, no atomics).  LANES
+// lanes share a row (entries k0 + lane, k0 + lane + LANES, ...: coalesced
+// index and value loads, LANES times the rows' parallelism), then add their
+// sums in a fixed shuffle order; LANES (2, 4, 8) is chosen per level.
+template <int LANES>
 __global__ __launch_bounds__(kRowBlock) void k_smooth_general(int ng, const int32_t *__restrict__ grow_lat,
                                                               const int32_t *__restrict__ sptr,
                                                               const int32_t *__restrict__ scol,
@@ -184,19 +184,19 @@ __global__ __launch_bounds__(kRowBlock) void k_smooth_general(int ng, const int3
                                                               const int32_t *__restrict__ done) {
   if (done && *done) return;
   const int gt = xcd_block(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
-  const int t = gt / kGenLanes, sub = gt % kGenLanes;
+  const int t = gt / LANES, sub = gt % LANES;
   if (t >= ng) return;  // all lanes of a row leave together
   const int k0 = sptr[t], k1 = sptr[t + 1];
   const int L = grow_lat[t];
   double acc = 0.0;
   // chunks of 4 entries per lane with guarded, fixed trip counts: the index,
   // value and r loads of a chunk issue together
-  for (int kb = k0 + sub; kb < k1; kb += 4 * kGenLanes) {
+  for (int kb = k0 + sub; kb < k1; kb += 4 * LANES) {
     int c[4];
     double v[4], rv[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int k = kb + q * kGenLanes;
+      const int k = kb + q * LANES;
       const bool in = k < k1;
       c[q] = scol[in ? k : kb];
       v[q] = in ? sval[k] : 0.0;
@@ -206,15 +206,26 @@ __global__ __launch_bounds__(kRowBlock) void k_smooth_general(int ng, const int3
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc += v[q] * rv[q];
   }
-  acc += __shfl_xor(acc, 1, kGenLanes);
-  acc += __shfl_xor(acc, 2, kGenLanes);
+#pragma unroll
+  for (int o = 1; o < LANES; o <<= 1) acc += __shfl_xor(acc, o, LANES);
   if (sub == 0) x[L] += acc;
 }
 
 void launch_smooth_general(hipStream_t s, int ng, const int32_t *grow_lat, const int32_t *sptr,
-                           const int32_t *scol, const double *sval, const double *r, double *x, const int32_t *done) {
+                           const int32_t *scol, const double *sval, const double *r, double *x, const int32_t *done,
+                           int lanes) {
   if (ng <= 0) return;
-  k_smooth_general<<<grid_for(ng * kGenLanes), kRowBlock, 0, s>>>(ng, grow_lat, sptr, scol, sval, r, x, done);
+  switch (lanes) {
+    case 2:
+      k_smooth_general<2><<<grid_for(ng * 2), kRowBlock, 0, s>>>(ng, grow_lat, sptr, scol, sval, r, x, done);
+      break;
+    case 8:
+      k_smooth_general<8><<<grid_for(ng * 8), kRowBlock, 0, s>>>(ng, grow_lat, sptr, scol, sval, r, x, done);
+      break;
+    default:
+      k_smooth_general<4><<<grid_for(ng * 4), kRowBlock, 0, s>>>(ng, grow_lat, sptr, scol, sval, r, x, done);
+      break;
+  }
 }
 
 // one thread per general row: adds row a of every block holding the row into
