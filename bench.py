@@ -112,10 +112,11 @@ def main():
     b = torch.tensor(g.b, device="cuda:0")
     n = g.fine.n
 
-    def make(prec, timing=0, learned=None):
+    def make(prec, timing=0, learned=None, block_gemm=0):
         o = S.default_options(nu_pre=w.nu, nu_post=w.nu, precision=prec, timing=timing,
                               use_graph=0 if (args.no_graph or timing) else 1, max_iter=2000,
-                              use_learned=int(learned is not None), autotune=int(not args.no_autotune))
+                              use_learned=int(learned is not None), autotune=int(not args.no_autotune),
+                              block_gemm=block_gemm)
         t = time.time()
         sol = S.Solver(0).setup(g, o)
         if learned is not None:
@@ -175,32 +176,42 @@ def main():
         U = rng.standard_normal((args.nrhs, n))
         Bm = torch.tensor(np.stack([M @ u for u in U]), device="cuda:0")  # load vectors of random L2 data
         Bm[0] = b
-        sol = make(head)
-        Xm = torch.zeros_like(Bm)
-        sol.pcg_multi(Bm, Xm, rtol=1e-8)  # warm-up (graph capture)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        tot_it = 0
-        for _ in range(args.steps):
-            Xm.zero_()
-            infos = sol.pcg_multi(Bm, Xm, rtol=1e-8)
-            tot_it += sum(i.iterations for i in infos)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        worst = max(i.true_rel_res for i in infos)
-        multi = {"nrhs": args.nrhs, "ms_per_solve": round(1e3 * dt / args.steps, 3),
-                 "mdofs": round(n * tot_it / dt / 1e6, 1),
-                 "iterations_per_column": [i.iterations for i in infos], "worst_true_rel_res": worst,
+        # general Schwarz blocks: 0 assembled FP64 CSR product, 1 FP64 patch
+        # GEMMs on the matrix cores, 2 BF16 patch GEMMs with FP32 accumulation
+        forms = {}
+        for mode, label in ((0, "csr_fp64"), (1, "mfma_fp64"), (2, "mfma_bf16")):
+            sol = make(head, block_gemm=mode)
+            Xm = torch.zeros_like(Bm)
+            sol.pcg_multi(Bm, Xm, rtol=1e-8)  # warm-up (graph capture)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tot_it = 0
+            for _ in range(args.steps):
+                Xm.zero_()
+                infos = sol.pcg_multi(Bm, Xm, rtol=1e-8)
+                tot_it += sum(i.iterations for i in infos)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            worst = max(i.true_rel_res for i in infos)
+            forms[label] = {"ms_per_solve": round(1e3 * dt / args.steps, 3), "mdofs": round(n * tot_it / dt / 1e6, 1),
+                            "iterations_per_column": [i.iterations for i in infos], "worst_true_rel_res": worst,
+                            "patch_gemm_levels": [sol.level_stats(l)["patch_gemm"] for l in range(1, len(g.levels))]}
+            log(f"{args.nrhs} right-hand sides ({label}): {forms[label]['ms_per_solve']:.2f} ms per solve, "
+                f"{forms[label]['mdofs']} MDOF/s (DOF x iterations summed over columns), worst true rel. residual "
+                f"{worst:.2e}")
+            sol.close()
+        multi = {"nrhs": args.nrhs, **{k: v for k, v in forms["csr_fp64"].items() if k != "patch_gemm_levels"},
+                 "general_blocks": forms,
                  "rhs": "column 0: the workload's load vector; others: load vectors M u of random normal u"}
-        log(f"{args.nrhs} right-hand sides: {multi['ms_per_solve']:.2f} ms per solve, {multi['mdofs']} MDOF/s "
-            f"(DOF x iterations summed over columns), worst true rel. residual {worst:.2e}")
-        sol.close()
     # batched: 64 independent problems (n in {64..512}^2, p in {1,2,3}), 16
     # right-hand sides each, one context and stream per problem, 4 host threads
     batched = None
     if not args.no_batched:
         from paper_1903_10977_amd import batch as BT
-        batched = BT.run_batch(64, 16, workers=4, steps=2, precision=head)
+        # the configuration's form: general blocks as BF16 patch GEMMs (FP32
+        # accumulation) on the matrix cores; the assembled CSR product beside it
+        batched = BT.run_batch(64, 16, workers=4, steps=2, precision=head, block_gemm=2)
+        batched["csr_fp64"] = BT.run_batch(64, 16, workers=4, steps=2, precision=head, block_gemm=0)
     hr = results[head]
     ms_step = hr["ms"]
     value = hr["mdofs"]

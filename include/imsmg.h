@@ -124,6 +124,13 @@ typedef struct {
                           the fastest; 0: 4 lanes.  The lane count fixes the summation order of
                           that product, so contexts tuned differently round differently (each
                           context stays bitwise reproducible); default 0 */
+  int32_t block_gemm;  /* general Schwarz blocks in the multi-right-hand-side solve
+                          (imsmg_vcycle_multi, imsmg_pcg_solve_multi): 0 the assembled FP64
+                          CSR product (default); 1 one patch GEMM W_j R_j per block on the
+                          matrix cores with FP64 operands; 2 the same with BF16 operands and
+                          FP32 accumulation.  1 and 2 apply on levels whose general blocks all
+                          have <= 16 functions (others keep 0); the single-column solve always
+                          uses 0 */
 } imsmg_options;
 
 typedef struct {
@@ -278,6 +285,10 @@ typedef struct {
   int64_t lattice;       /* padded lattice size of the level's vectors */
   int32_t value_bytes;   /* 8 (FP64) or 4 (FP32 V-cycle operators) */
   int32_t general_lanes; /* lanes per row of the general-row smoother (2, 4 or 8) */
+  int32_t patch_gemm;    /* 1: the multi-right-hand-side smoother applies this level's general
+                            blocks as patch GEMMs (options.block_gemm > 0, blocks <= 16) */
+  int32_t bf16_blocks;   /* of those, the blocks with cond(A_j) <= 16, which take BF16 operands
+                            when options.block_gemm == 2 (the others stay FP64) */
 } imsmg_level_stats;
 int imsmg_get_level_stats(imsmg_ctx *ctx, int level, imsmg_level_stats *stats);
 

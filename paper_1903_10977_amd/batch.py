@@ -29,7 +29,7 @@ def _log(msg):
 
 
 class BatchSolver:
-    def __init__(self, problems, nrhs=16, precision=S.MIXED, max_iter=2000, workers=4):
+    def __init__(self, problems, nrhs=16, precision=S.MIXED, max_iter=2000, workers=4, block_gemm=0):
         import torch
         self.torch = torch
         self.problems = problems
@@ -38,7 +38,8 @@ class BatchSolver:
         self.solvers = []
         for g in problems:
             w = g.workload
-            o = S.default_options(nu_pre=w.nu, nu_post=w.nu, precision=precision, max_iter=max_iter)
+            o = S.default_options(nu_pre=w.nu, nu_post=w.nu, precision=precision, max_iter=max_iter,
+                                  block_gemm=block_gemm)
             self.solvers.append(S.Solver(0).setup(g, o).factor())
 
     def rhs(self, seed0=1000):
@@ -80,12 +81,12 @@ class BatchSolver:
         self.solvers = []
 
 
-def run_batch(count=64, nrhs=16, workers=4, steps=2, precision=S.MIXED):
+def run_batch(count=64, nrhs=16, workers=4, steps=2, precision=S.MIXED, block_gemm=0):
     import workloads as W
     t0 = time.time()
     probs = [GN.generate(W.batched_c4(i), with_mass=True) for i in range(count)]
     _log(f"generated {count} problems ({sum(g.fine.n for g in probs)} DOFs) in {time.time() - t0:.1f} s")
-    bs = BatchSolver(probs, nrhs=nrhs, precision=precision, workers=workers)
+    bs = BatchSolver(probs, nrhs=nrhs, precision=precision, workers=workers, block_gemm=block_gemm)
     B = bs.rhs()
     bs.solve(B)  # warm-up: graph capture per context
     dof_it, wall, worst, status = 0, 0.0, 0.0, 0
@@ -97,7 +98,8 @@ def run_batch(count=64, nrhs=16, workers=4, steps=2, precision=S.MIXED):
             worst = max(worst, max(i.true_rel_res for i in inf))
             status = status or next((i.status for i in inf if i.status != 0), 0)
     bs.close()
-    res = {"problems": count, "nrhs": nrhs, "workers": workers, "fine_dofs": int(sum(g.fine.n for g in probs)),
+    res = {"problems": count, "nrhs": nrhs, "workers": workers, "block_gemm": block_gemm,
+           "fine_dofs": int(sum(g.fine.n for g in probs)),
            "ms_per_batch": round(1e3 * wall / steps, 2), "mdofs": round(dof_it / wall / 1e6, 1),
            "worst_true_rel_res": worst, "status": status}
     _log(json.dumps(res))
@@ -110,8 +112,10 @@ def main(argv=None):
     ap.add_argument("--nrhs", type=int, default=16)
     ap.add_argument("--workers", type=int, default=4)
     ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--block-gemm", type=int, default=0, choices=[0, 1, 2],
+                    help="general blocks: 0 CSR FP64, 1 FP64 patch GEMMs, 2 BF16 patch GEMMs (matrix cores)")
     a = ap.parse_args(argv)
-    print(json.dumps(run_batch(a.problems, a.nrhs, a.workers, a.steps)))
+    print(json.dumps(run_batch(a.problems, a.nrhs, a.workers, a.steps, block_gemm=a.block_gemm)))
 
 
 if __name__ == "__main__":

@@ -94,6 +94,16 @@ struct Level {
   double *c = nullptr;               // trivial rows: omega_j / A_ii, else 0
   int ng = 0;                         // rows in general blocks
   int gen_lanes = 4;                  // lanes per row of the general-row product (tuned: 2, 4, 8)
+  // multi-column smoother as patch GEMMs (option block_gemm; every general
+  // block of this level has <= 16 functions): per block the members' lattice
+  // positions (16, -1 padded), W = omega A^-1 padded to 16 x 16 (FP64 and
+  // BF16), the products Y, and per general row its (block, member) rows of Y
+  bool mb_on = false;
+  int32_t *mb_lat = nullptr, *mb_yp = nullptr, *mb_ypos = nullptr;
+  int32_t *mb_lp = nullptr;  // 1: well conditioned (cond(A_j) <= kBf16Kappa), BF16 allowed
+  int mb_nlp = 0;
+  double *mb_W = nullptr, *mb_Y = nullptr;
+  uint16_t *mb_Wb = nullptr;
   bool small = false;                 // latency-bound level (no convergence-flag load)
   int32_t *grow_lat = nullptr, *sptr = nullptr, *scol = nullptr;
   double *sval = nullptr;             // S_G = sum_j omega_j P_j A_j^{-1} P_j^T on the general rows (CSR)
@@ -1042,6 +1052,42 @@ void factor_level(imsmg_ctx *c, int l) {
   h2d(s, L.asm_eoff, e_off.data(), e_off.size());
   h2d(s, L.asm_epos0, e_pos.data(), e_pos.size());
   HIP_CHECK_RET(hipStreamSynchronize(s));
+  // patch GEMMs for the multi-column smoother
+  L.mb_on = false;
+  if (c->opt.block_gemm > 0 && nbg > 0 &&
+      std::all_of(g_size.begin(), g_size.end(), [](int32_t z) { return z <= 16; })) {
+    std::vector<int32_t> blat(size_t(nbg) * 16, -1), j2q(size_t(nbf), -1), ypos(e_off.size());
+    for (int q = 0; q < nbg; ++q) {
+      const int j = g_blocks[q];
+      j2q[j] = q;
+      for (int a = 0; a < fptr[j + 1] - fptr[j]; ++a) blat[size_t(q) * 16 + a] = L.h_row_lat[fidx[fptr[j] + a]];
+    }
+    for (size_t e = 0; e < e_off.size(); ++e) {
+      const int q = j2q[e_blk[e]];
+      const int a = int((e_off[e] - g_invoff[q]) / e_n[e]);  // the row's member position in the block
+      ypos[e] = q * 256 + a * 16;
+    }
+    std::vector<int32_t> lp(nbg, 0);
+    L.mb_nlp = 0;
+    for (int q = 0; q < nbg; ++q) {
+      const double *lam = L.f_lam.data() + 4 * size_t(g_blocks[q]);
+      lp[q] = (lam[2] > 0.0 && lam[3] <= kBf16Kappa * lam[2]) ? 1 : 0;
+      L.mb_nlp += lp[q];
+    }
+    L.mb_lp = dalloc<int32_t>(c->factor_owned, lp.size());
+    h2d(s, L.mb_lp, lp.data(), lp.size());
+    L.mb_lat = dalloc<int32_t>(c->factor_owned, blat.size());
+    L.mb_yp = dalloc<int32_t>(c->factor_owned, gp.size());
+    L.mb_ypos = dalloc<int32_t>(c->factor_owned, std::max<size_t>(ypos.size(), 1));
+    L.mb_W = dalloc<double>(c->factor_owned, size_t(nbg) * 256);
+    L.mb_Wb = dalloc<uint16_t>(c->factor_owned, size_t(nbg) * 256);
+    L.mb_Y = dalloc<double>(c->factor_owned, size_t(nbg) * 256);
+    h2d(s, L.mb_lat, blat.data(), blat.size());
+    h2d(s, L.mb_yp, gp.data(), gp.size());
+    if (!ypos.empty()) h2d(s, L.mb_ypos, ypos.data(), ypos.size());
+    HIP_CHECK_RET(hipStreamSynchronize(s));
+    L.mb_on = true;
+  }
   // trivial rows: c_i = w_j / A_ii (apply_weights)
   std::vector<int32_t> tb(n, -1);
   for (int i = 0; i < n; ++i)
@@ -1099,6 +1145,7 @@ void apply_weights(imsmg_ctx *c, Level &L, const std::vector<double> &w) {
   launch_scale_blocks(s, L.nbg, L.g_off, L.g_sz, d_ratio, L.inv);
   HIP_CHECK_RET(hipMemsetAsync(L.sval, 0, L.sg_nnz * sizeof(double), s));
   launch_assemble_sg(s, L.ng, L.asm_gp, L.asm_eoff, L.asm_en, L.asm_epos0, L.asm_epos, L.inv, L.sval);
+  if (L.mb_on) launch_pack_blocks(s, L.nbg, L.g_off, L.g_sz, L.inv, L.mb_W, L.mb_Wb);
   h2d(s, L.bw, w.data(), nbf);
   launch_diag_coef(s, L.n, L.K, L.center, L.tb, L.val, L.bw, L.c);
   h2d(s, L.b_wfold, wfold.data(), nbf);
@@ -1513,6 +1560,19 @@ void ensure_multi(imsmg_ctx *c, int R) {
   m.R = R;
 }
 
+// x += S_G r on the general rows of the multi-column vectors: the assembled
+// CSR product, or the blocks' patch GEMMs on the matrix cores (block_gemm)
+void m_general(imsmg_ctx *c, Level &L, const double *r, double *x, const int32_t *done) {
+  auto &m = c->mb;
+  if (L.mb_on) {
+    launch_m_block_gemm(c->stream, c->opt.block_gemm == 2, L.nbg, m.R, L.mb_lat, L.mb_W, L.mb_Wb, L.mb_lp, r, L.mb_Y,
+                        done);
+    launch_m_block_gather(c->stream, m.R, L.ng, L.grow_lat, L.mb_yp, L.mb_ypos, L.mb_Y, x, done);
+  } else {
+    launch_m_smooth_general(c->stream, m.R, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, r, x, done);
+  }
+}
+
 void m_smooth_step(imsmg_ctx *c, int l, const double *xa, double *xb, const int32_t *done) {
   Level &L = c->lv[l];
   auto &m = c->mb;
@@ -1520,7 +1580,7 @@ void m_smooth_step(imsmg_ctx *c, int l, const double *xa, double *xb, const int3
     launch_m_residual_smooth(c->stream, m.R, L.n, L.K, L.op32, L.row_lat, L.meta, L.c, xa, m.r[l], m.rh[l], xb, done);
   else
     launch_m_residual_smooth(c->stream, m.R, L.n, L.K, L.op64, L.row_lat, L.meta, L.c, xa, m.r[l], m.rh[l], xb, done);
-  launch_m_smooth_general(c->stream, m.R, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, m.rh[l], xb, done);
+  m_general(c, L, m.rh[l], xb, done);
 }
 
 void m_vcycle_level(imsmg_ctx *c, int l, const int32_t *done_top) {
@@ -1534,7 +1594,7 @@ void m_vcycle_level(imsmg_ctx *c, int l, const int32_t *done_top) {
     return;
   }
   Level &Cl = c->lv[l - 1];
-  launch_m_smooth_general(s, R, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, m.r[l], m.xs[l], done);
+  m_general(c, L, m.r[l], m.xs[l], done);
   double *xa = m.xs[l], *xb = (m.xs[l] == m.x[l]) ? m.x2[l] : m.x[l];
   for (int k = 1; k < c->opt.nu_pre; ++k) {
     m_smooth_step(c, l, xa, xb, done);
@@ -1656,6 +1716,7 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
     if (c->opt.nu_pre < 1 || c->opt.nu_post < 1 || c->opt.max_iter < 1) bad("nu and max_iter must be >= 1");
     if (c->opt.check_every < 1) c->opt.check_every = 1;
     if (c->opt.precision != IMSMG_FP64 && c->opt.precision != IMSMG_MIXED) bad("unknown precision mode");
+    if (c->opt.block_gemm < 0 || c->opt.block_gemm > 2) bad("block_gemm must be 0, 1 or 2");
     c->lv.resize(nlevels);
     for (int l = 0; l < nlevels; ++l) {
       if (Lt[l].dim != Lt[nlevels - 1].dim) bad("all levels must share the dimension");
@@ -1956,6 +2017,8 @@ int imsmg_get_level_stats(imsmg_ctx *c, int level, imsmg_level_stats *st) {
     st->lattice = L.lattice;
     st->value_bytes = mixed(c) ? 4 : 8;
     st->general_lanes = L.gen_lanes;
+    st->patch_gemm = L.mb_on ? 1 : 0;
+    st->bf16_blocks = L.mb_on ? L.mb_nlp : 0;
     return IMSMG_OK;
   });
 }

@@ -174,6 +174,17 @@ void launch_m_smooth_general(hipStream_t s, int R, int ng, const int32_t *grow_l
                              const int32_t *scol, const double *sval, const double *r, double *x, const int32_t *done);
 void launch_m_diag_scale(hipStream_t s, int R, int n, const int32_t *row_lat, const double *c, const double *r,
                          double *x, const int32_t *done);
+// general blocks of <= 16 functions as patch GEMMs on the matrix cores: Y_q =
+// W_q R_q (bf16 != 0: BF16 operands with FP32 accumulation on the blocks
+// flagged in lp, FP64 on the others), then per general row x += sum of its
+// blocks' Y rows (ascending block order)
+constexpr double kBf16Kappa = 16.0;  // blocks with cond(A_j) up to this take BF16
+void launch_m_block_gemm(hipStream_t s, int bf16, int nb, int R, const int32_t *blat, const double *W,
+                         const uint16_t *Wb, const int32_t *lp, const double *r, double *Y, const int32_t *done);
+void launch_m_block_gather(hipStream_t s, int R, int ng, const int32_t *grow_lat, const int32_t *yp,
+                           const int32_t *ypos, const double *Y, double *x, const int32_t *done);
+void launch_pack_blocks(hipStream_t s, int nb, const int64_t *g_off, const int32_t *g_sz, const double *inv,
+                        double *W, uint16_t *Wb);
 void launch_m_tensor_transfer(hipStream_t s, int R, int dim, int n, const int32_t *row_lat, int ox, int oy,
                               const int32_t *start, const int32_t *len, const double *coef, int W, int ix, int iy,
                               const double *xin, double *y, int accumulate, const double *cinit, double *xinit,

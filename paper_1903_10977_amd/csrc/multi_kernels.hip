@@ -621,6 +621,126 @@ void launch_m_smooth_general(hipStream_t s, int R, int ng, const int32_t *grow_l
   MR_DISPATCH(R, (k_m_smooth_general<RR><<<g, kMT, 0, s>>>(ng, grow_lat, sptr, scol, sval, r, x, done)))
 }
 
+// ---------------------------------------------------------- patch GEMMs
+// General Schwarz blocks of up to 16 functions applied as dense products on
+// the matrix cores, one wavefront per block: Y_q = W_q R_q with W_q =
+// omega_q A_q^{-1} (16 x 16, zero-padded, row-major) and R_q = the block
+// members' residual rows (member k x right-hand-side column n, 16 columns,
+// columns >= R and members past the block size zero).  FP64 operands: four
+// v_mfma_f64_16x16x4 steps (exact FP64 products); BF16 operands with FP32
+// accumulation: one v_mfma_f32_16x16x16_bf16.  Lane layouts (checked on the
+// device): FP64 A[lane % 16][k], B[k][lane % 16] with k = 4 step + lane / 16,
+// D[lane / 16 + 4 q][lane % 16]; BF16 A[lane % 16][4 (lane / 16) + q],
+// B[4 (lane / 16) + q][lane % 16], D[4 (lane / 16) + q][lane % 16].
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float f) {  // round to nearest even (finite inputs)
+  unsigned u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return short(u >> 16);
+}
+
+constexpr int kGemmWaves = 4;  // blocks (wavefronts) per workgroup
+
+// BF16 = true: blocks flagged in lp (well conditioned) take BF16 operands,
+// the others FP64 (a wavefront-uniform choice per block)
+template <bool BF16>
+__global__ __launch_bounds__(64 * kGemmWaves) void k_m_block_gemm(int nb, int R, const int32_t *__restrict__ blat,
+                                                                   const double *__restrict__ W,
+                                                                   const uint16_t *__restrict__ Wb,
+                                                                   const int32_t *__restrict__ lp,
+                                                                   const double *__restrict__ r,
+                                                                   double *__restrict__ Y,
+                                                                   const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  const int q = blockIdx.x * kGemmWaves + threadIdx.x / 64;
+  if (q >= nb) return;  // whole wavefronts
+  const int lane = threadIdx.x % 64;
+  const int n = lane % 16;
+  if (BF16 && lp[q]) {
+    bf16x4 a, b;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = 4 * (lane / 16) + t;
+      a[t] = short(Wb[size_t(q) * 256 + n * 16 + k]);  // A[m = lane % 16][k]
+      const int L = blat[q * 16 + k];
+      const double v = (L >= 0 && n < R) ? r[size_t(L) * R + n] : 0.0;
+      b[t] = bf16_bits(float(v));
+    }
+    f32x4 c = {0.f, 0.f, 0.f, 0.f};
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) Y[size_t(q) * 256 + (4 * (lane / 16) + t) * 16 + n] = double(c[t]);
+  } else {
+    f64x4 c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int k = 4 * st + lane / 16;
+      const double a = W[size_t(q) * 256 + n * 16 + k];  // A[m = lane % 16][k]
+      const int L = blat[q * 16 + k];
+      const double b = (L >= 0 && n < R) ? r[size_t(L) * R + n] : 0.0;
+      c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) Y[size_t(q) * 256 + (lane / 16 + 4 * t) * 16 + n] = c[t];
+  }
+}
+
+// x[row] += sum over the row's blocks (ascending block order) of Y[block][row's
+// member position][column]; one thread per (general row, column)
+template <int R>
+__global__ __launch_bounds__(kMT) void k_m_block_gather(int ng, const int32_t *__restrict__ grow_lat,
+                                                        const int32_t *__restrict__ yp,
+                                                        const int32_t *__restrict__ ypos,
+                                                        const double *__restrict__ Y, double *__restrict__ x,
+                                                        const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  const int gt = blockIdx.x * kMT + threadIdx.x;
+  const int t = gt / R, col = gt % R;
+  if (t >= ng) return;
+  double acc = 0.0;
+  for (int k = yp[t]; k < yp[t + 1]; ++k) acc += Y[size_t(ypos[k]) + col];
+  x[size_t(grow_lat[t]) * R + col] += acc;
+}
+
+// W (FP64, 16 x 16 zero-padded per block) and its BF16 copy from the packed
+// block inverses (size g_sz[q] at g_off[q], row-major)
+__global__ void k_pack_blocks(int nb, const int64_t *__restrict__ g_off, const int32_t *__restrict__ g_sz,
+                              const double *__restrict__ inv, double *__restrict__ W, uint16_t *__restrict__ Wb) {
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = gt / 256, e = gt % 256;
+  if (q >= nb) return;
+  const int m = e / 16, k = e % 16, sz = g_sz[q];
+  const double v = (m < sz && k < sz) ? inv[g_off[q] + int64_t(m) * sz + k] : 0.0;
+  W[gt] = v;
+  Wb[gt] = uint16_t(bf16_bits(float(v)));
+}
+
+void launch_m_block_gemm(hipStream_t s, int bf16, int nb, int R, const int32_t *blat, const double *W,
+                         const uint16_t *Wb, const int32_t *lp, const double *r, double *Y, const int32_t *done) {
+  if (nb <= 0) return;
+  const int g = (nb + kGemmWaves - 1) / kGemmWaves;
+  if (bf16)
+    k_m_block_gemm<true><<<g, 64 * kGemmWaves, 0, s>>>(nb, R, blat, W, Wb, lp, r, Y, done);
+  else
+    k_m_block_gemm<false><<<g, 64 * kGemmWaves, 0, s>>>(nb, R, blat, W, Wb, lp, r, Y, done);
+}
+
+void launch_m_block_gather(hipStream_t s, int R, int ng, const int32_t *grow_lat, const int32_t *yp,
+                           const int32_t *ypos, const double *Y, double *x, const int32_t *done) {
+  if (ng <= 0) return;
+  const int g = multi_blocks(R, ng);
+  MR_DISPATCH(R, (k_m_block_gather<RR><<<g, kMT, 0, s>>>(ng, grow_lat, yp, ypos, Y, x, done)))
+}
+
+void launch_pack_blocks(hipStream_t s, int nb, const int64_t *g_off, const int32_t *g_sz, const double *inv,
+                        double *W, uint16_t *Wb) {
+  if (nb <= 0) return;
+  k_pack_blocks<<<(nb * 256 + 255) / 256, 256, 0, s>>>(nb, g_off, g_sz, inv, W, Wb);
+}
+
 void launch_m_diag_scale(hipStream_t s, int R, int n, const int32_t *row_lat, const double *c, const double *r,
                          double *x, const int32_t *done) {
   if (n <= 0) return;

@@ -46,7 +46,8 @@ class Lattice(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("max_iter", C.c_int32),
                 ("check_every", C.c_int32), ("use_graph", C.c_int32), ("timing", C.c_int32), ("gamma", C.c_double),
-                ("compress", C.c_int32), ("use_learned", C.c_int32), ("autotune", C.c_int32)]
+                ("compress", C.c_int32), ("use_learned", C.c_int32), ("autotune", C.c_int32),
+                ("block_gemm", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -56,7 +57,8 @@ class Info(C.Structure):
 
 class LevelStats(C.Structure):
     _fields_ = [("n", C.c_int32), ("stencil", C.c_int32), ("stored_rows", C.c_int32), ("general_rows", C.c_int32),
-                ("sg_nnz", C.c_int64), ("lattice", C.c_int64), ("value_bytes", C.c_int32), ("general_lanes", C.c_int32)]
+                ("sg_nnz", C.c_int64), ("lattice", C.c_int64), ("value_bytes", C.c_int32), ("general_lanes", C.c_int32),
+                ("patch_gemm", C.c_int32), ("bf16_blocks", C.c_int32)]
 
 
 SYMBOLS = ["imsmg_default_options", "imsmg_create", "imsmg_setup", "imsmg_set_patch_weights",

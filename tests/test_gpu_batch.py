@@ -2,7 +2,8 @@
 right-hand sides each, driven concurrently (one context and stream per
 problem, a pool of host threads).  Bars: every column reaches a true relative
 residual <= 1e-8, and the concurrent run gives bit-for-bit the results of a
-sequential run (no state is shared between contexts)."""
+sequential run (no state is shared between contexts); with the general
+blocks as BF16 patch GEMMs every column still reaches 1e-8."""
 import numpy as np
 import pytest
 
@@ -45,3 +46,13 @@ def test_concurrent_batch_matches_sequential_and_converges():
     assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(B[0][3].cpu().numpy()) * 1.0001
     sol.close()
     bs.close()
+    # the same batch with the general blocks as BF16 patch GEMMs on the matrix
+    # cores (FP32 accumulation): every column still reaches 1e-8
+    bs2 = BT.BatchSolver(probs, nrhs=16, precision=S.MIXED, workers=4, block_gemm=2)
+    X2, infos2, _ = bs2.solve(B)
+    for i, inf in enumerate(infos2):
+        assert all(x.status == 0 and x.true_rel_res <= 1e-8 for x in inf), \
+            (INDICES[i], [(x.status, x.iterations, x.true_rel_res) for x in inf])
+    print(f"[case batch] BF16 patch GEMM iterations {[max(x.iterations for x in inf) for inf in infos2]} "
+          f"(CSR {[max(x.iterations for x in inf) for inf in infos_c]})", flush=True)
+    bs2.close()

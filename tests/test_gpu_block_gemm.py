@@ -1,0 +1,132 @@
+"""Patch GEMMs of the multi-right-hand-side smoother on the matrix cores.
+
+block_gemm = 1 applies every general Schwarz block as one FP64 product
+W_j R_j (16 x 16 x 16 on v_mfma_f64_16x16x4) and sums the blocks' rows per
+general row: the same arithmetic as the assembled CSR product up to the
+summation order, so one multi-column V-cycle agrees with block_gemm = 0 to
+1e-12 relative.  block_gemm = 2 rounds W_j and R_j to BF16 and accumulates
+in FP32 on the well-conditioned blocks (cond(A_j) <= 16; near-singular cut
+blocks have inverse entries whose cancellation BF16 cannot carry, so they
+stay FP64): the V-cycle agrees to 2e-2 relative (BF16 keeps 8 bits; the
+smoother's general part is a fraction of the correction) and, where such
+blocks exist, moves further from the CSR result than the FP64 reordering
+does (the path ran); the FP64 outer CG still reaches a true
+relative residual <= 1e-8 on every column, in at most 1.5x + 2 the FP64
+iterations.  Levels with a general block of more than 16 functions (the
+quadratic 3D case) keep the CSR product: bitwise the block_gemm = 0 result.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CASES = {
+    "cubic-discs": lambda: W.small_discs(seed=11, n=32, degree=3, levels=3, n_discs=6, depth=1,
+                                         rhs="manufactured", nu=2),
+    "linear-discs": lambda: W.small_discs(seed=12, n=32, degree=1, levels=3, n_discs=8, depth=2),
+    "discs-256": lambda: W.c2(n=256, levels=4),
+}
+_cache = {}
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_10977_amd import solver as S
+    S.load()
+    return S
+
+
+def _problem(name, case=CASES):
+    if name not in _cache:
+        from paper_1903_10977_amd import generator as GN
+        w = case[name]()
+        print(f"[case {name}] n={w.n} p={w.degree} levels={w.levels}", flush=True)
+        _cache[name] = (w, GN.generate(w, with_mass=True))
+    return _cache[name]
+
+
+def _solver(S, g, **opt):
+    w = g.workload
+    o = S.default_options(nu_pre=w.nu, nu_post=w.nu, **opt)
+    return S.Solver(0).setup(g, o).factor()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_patch_gemm_vcycle(name):
+    S = _gpu()
+    w, g = _problem(name)
+    n = g.fine.n
+    rng = np.random.Generator(np.random.PCG64(71))
+    Rm = torch.tensor(rng.standard_normal((16, n)), device="cuda:0")
+    Z, nlp = {}, 0
+    for mode in (0, 1, 2):
+        sol = _solver(S, g, block_gemm=mode)
+        st = [sol.level_stats(l) for l in range(1, len(g.levels))]
+        on = [x["patch_gemm"] for x in st]
+        print(f"[case {name}] block_gemm={mode} patch GEMM levels {on}, well-conditioned blocks "
+              f"{[x['bf16_blocks'] for x in st]}", flush=True)
+        assert any(on) == (mode > 0)
+        nlp = sum(x["bf16_blocks"] for x in st)
+        Z[mode] = sol.vcycle_multi(Rm).cpu().numpy()
+        sol.close()
+    scale = np.abs(Z[0]).max()
+    d1 = np.abs(Z[1] - Z[0]).max()
+    d2 = np.abs(Z[2] - Z[0]).max()
+    print(f"[case {name}] FP64 patch GEMM {d1 / scale:.2e}, BF16 {d2 / scale:.2e}", flush=True)
+    assert d1 <= 1e-12 * scale
+    assert d2 <= 2e-2 * scale
+    if nlp > 0:
+        assert d2 > d1  # the BF16 blocks ran
+
+
+@pytest.mark.parametrize("name", ["cubic-discs", "discs-256"])
+def test_patch_gemm_bf16_pcg_converges(name):
+    S = _gpu()
+    w, g = _problem(name)
+    n = g.fine.n
+    rng = np.random.Generator(np.random.PCG64(73))
+    U = rng.standard_normal((8, n))
+    B = np.stack([g.b] + [g.M @ u for u in U[1:]])
+    Bm = torch.tensor(B, device="cuda:0")
+    its = {}
+    for mode in (0, 2):
+        sol = _solver(S, g, precision=S.MIXED, block_gemm=mode, max_iter=2000)
+        Xm = torch.zeros_like(Bm)
+        infos = sol.pcg_multi(Bm, Xm, rtol=1e-8)
+        assert all(i.status == 0 and i.true_rel_res <= 1e-8 for i in infos), \
+            (mode, [(i.status, i.iterations, i.true_rel_res) for i in infos])
+        its[mode] = [i.iterations for i in infos]
+        sol.close()
+    print(f"[case {name}] iterations FP64 {its[0]} BF16 {its[2]}", flush=True)
+    assert all(b <= 1.5 * a + 2 for a, b in zip(its[0], its[2]))
+
+
+def test_large_blocks_keep_the_csr_product():
+    """Levels with a block of more than 16 functions keep the CSR product;
+    where no level qualifies the result is bitwise the block_gemm = 0 one."""
+    S = _gpu()
+    w, g = _problem("gyroid-3d", {"gyroid-3d": lambda: W.small_gyroid(seed=5, n=16, degree=2, levels=2)})
+    rng = np.random.Generator(np.random.PCG64(75))
+    Rm = torch.tensor(rng.standard_normal((4, g.fine.n)), device="cuda:0")
+    Z, on = {}, None
+    for mode in (0, 2):
+        sol = _solver(S, g, block_gemm=mode)
+        if mode == 2:
+            on = [sol.level_stats(l)["patch_gemm"] for l in range(1, len(g.levels))]
+            for l in range(1, len(g.levels)):
+                ptr, _ = sol.get_patches(l)
+                largest = int(np.diff(ptr).max())
+                print(f"[case gyroid-3d] level {l}: largest block {largest}, patch GEMM {on[l - 1]}", flush=True)
+                if largest > 16:
+                    assert on[l - 1] == 0
+        Z[mode] = sol.vcycle_multi(Rm).cpu().numpy()
+        sol.close()
+    if not any(on):
+        assert np.array_equal(Z[0], Z[2])
+    else:
+        assert np.abs(Z[2] - Z[0]).max() <= 2e-2 * np.abs(Z[0]).max()
