@@ -189,6 +189,28 @@ int imsmg_vcycle_multi(imsmg_ctx *ctx, int nrhs, const double *R_dev, double *Z_
 int imsmg_pcg_solve_multi(imsmg_ctx *ctx, int nrhs, const double *B_dev, double *X_dev, double rtol,
                           imsmg_info *infos);
 
+/* ---- batched problems.  A fresh context becomes a batch context holding
+ * nprob independent problems; each gets its own device context and stream
+ * (created on the batch context's device), the per-problem arguments are
+ * those of imsmg_setup (E may be NULL, or E[p] NULL per problem).  The
+ * library owns the children: imsmg_destroy(ctx) destroys them.  Errors name
+ * the problem.  imsmg_factor_patches(ctx) factorizes every problem. */
+int imsmg_setup_batched(imsmg_ctx *ctx, int nprob, const int *nlevels, const imsmg_csr *const *A,
+                        const imsmg_csr *const *R, const imsmg_patches *const *P, const imsmg_lattice *const *L,
+                        const imsmg_elements *const *E, const imsmg_options *opt);
+/* The context of problem p of a batch (owned by the batch; for per-problem
+ * queries such as imsmg_get_level_stats). */
+int imsmg_batch_problem(imsmg_ctx *ctx, int p, imsmg_ctx **child);
+/* nrhs systems per problem: B_dev[p], X_dev[p] are device arrays n_p x nrhs
+ * (column k at offset k n_p) as in imsmg_pcg_solve_multi; infos (may be NULL)
+ * holds nprob * nrhs entries, problem-major.  nthreads host threads (<= 0: 4)
+ * each take the next unsolved problem and drive its multi-column solve on the
+ * problem's stream, so the problems' latency-bound V-cycles overlap on the
+ * device.  Results do not depend on nthreads (no state is shared).  Returns
+ * IMSMG_OK or the first error. */
+int imsmg_pcg_solve_batched(imsmg_ctx *ctx, int nrhs, const double *const *B_dev, double *const *X_dev, double rtol,
+                            imsmg_info *infos, int nthreads);
+
 /* ---- per-block damping (an extension: the paper uses one factor per level,
  * see the discussion after eq:applyCS).  "Final blocks" are the blocks after
  * factorization: the input blocks in input order (members removed by the

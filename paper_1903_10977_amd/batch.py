@@ -1,12 +1,13 @@
 """Many independent problems, each with several right-hand sides, solved
 concurrently on one GPU.
 
-Every problem gets its own library context and therefore its own HIP stream
-and its own captured CG graph; a pool of host threads drives the contexts
-(the C calls release the interpreter lock), so the small, latency-bound
-V-cycles of different problems overlap on the device instead of running one
-after the other.  Each problem uses the multi-column solve (all of its
-right-hand sides share every kernel launch).
+One library batch context (imsmg_setup_batched) holds the problems; each
+problem gets its own child context and therefore its own HIP stream and its
+own captured CG graph, and imsmg_pcg_solve_batched drives them from a pool
+of native host threads, so the small, latency-bound V-cycles of different
+problems overlap on the device instead of running one after the other.
+Each problem uses the multi-column solve (all of its right-hand sides share
+every kernel launch).
 
     python3 -m paper_1903_10977_amd.batch --problems 64 --nrhs 16
 """
@@ -16,7 +17,6 @@ import argparse
 import json
 import sys
 import time
-from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -35,12 +35,12 @@ class BatchSolver:
         self.problems = problems
         self.nrhs = nrhs
         self.workers = workers
-        self.solvers = []
-        for g in problems:
-            w = g.workload
-            o = S.default_options(nu_pre=w.nu, nu_post=w.nu, precision=precision, max_iter=max_iter,
-                                  block_gemm=block_gemm)
-            self.solvers.append(S.Solver(0).setup(g, o).factor())
+        nus = {g.workload.nu for g in problems}
+        if len(nus) != 1:
+            raise ValueError("one batch shares its smoothing steps")
+        nu = nus.pop()
+        o = S.default_options(nu_pre=nu, nu_post=nu, precision=precision, max_iter=max_iter, block_gemm=block_gemm)
+        self.ctx = S.BatchContext(0).setup(problems, o).factor()
 
     def rhs(self, seed0=1000):
         """nrhs right-hand sides per problem: load vectors b = M u of random
@@ -59,26 +59,17 @@ class BatchSolver:
         return out
 
     def solve(self, B, rtol=1e-8):
-        """X (list of (nrhs, n) tensors), infos per problem, wall seconds."""
+        """X (list of (nrhs, n) tensors), infos per problem, wall seconds; the
+        library's batched solve drives the problems from `workers` host threads."""
         X = [self.torch.zeros_like(b) for b in B]
         self.torch.cuda.synchronize()
-
-        def run(i):
-            return self.solvers[i].pcg_multi(B[i], X[i], rtol=rtol, raise_on_error=False, sync=False)
-
         t0 = time.perf_counter()
-        if self.workers > 1:
-            with ThreadPoolExecutor(self.workers) as ex:
-                infos = list(ex.map(run, range(len(B))))
-        else:
-            infos = [run(i) for i in range(len(B))]
+        infos = self.ctx.pcg(B, X, rtol=rtol, nthreads=self.workers, raise_on_error=False)
         self.torch.cuda.synchronize()
         return X, infos, time.perf_counter() - t0
 
     def close(self):
-        for s in self.solvers:
-            s.close()
-        self.solvers = []
+        self.ctx.close()
 
 
 def run_batch(count=64, nrhs=16, workers=4, steps=2, precision=S.MIXED, block_gemm=0):

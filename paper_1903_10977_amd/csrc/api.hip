@@ -7,14 +7,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <stdexcept>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -148,6 +151,9 @@ struct imsmg_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
+  // batch context (imsmg_setup_batched): one child context, with its own
+  // stream, per problem
+  std::vector<imsmg_ctx *> batch;
   std::vector<void *> owned;      // setup-lifetime allocations
   std::vector<void *> factor_owned;
   std::vector<Level> lv;
@@ -1803,6 +1809,14 @@ int imsmg_set_patch_weights(imsmg_ctx *c, int level, const double *omega) {
 }
 
 int imsmg_factor_patches(imsmg_ctx *c) {
+  if (c && !c->batch.empty()) {  // batch context: every problem in turn
+    for (size_t p = 0; p < c->batch.size(); ++p) {
+      const int rc = imsmg_factor_patches(c->batch[p]);
+      if (rc != IMSMG_OK) return fail(c, rc, "problem " + std::to_string(p) + ": " + c->batch[p]->err);
+    }
+    c->err.clear();
+    return IMSMG_OK;
+  }
   return guarded(c, [&]() -> int {
     if (!c->ready) bad("setup first", IMSMG_ERR_STATE);
     destroy_graph(c);
@@ -2230,8 +2244,77 @@ int imsmg_pcg_solve_multi(imsmg_ctx *c, int nrhs, const double *B_dev, double *X
 
 const char *imsmg_last_error(imsmg_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
+int imsmg_setup_batched(imsmg_ctx *c, int nprob, const int *nlevels, const imsmg_csr *const *A,
+                        const imsmg_csr *const *R, const imsmg_patches *const *P, const imsmg_lattice *const *L,
+                        const imsmg_elements *const *E, const imsmg_options *opt) {
+  if (!c) return IMSMG_ERR_INVALID_ARG;
+  if (nprob < 1 || !nlevels || !A || !R || !P || !L) return fail(c, IMSMG_ERR_INVALID_ARG, "bad batched arguments");
+  if (c->ready) return fail(c, IMSMG_ERR_STATE, "a set-up single-problem context cannot become a batch");
+  for (imsmg_ctx *b : c->batch) imsmg_destroy(b);
+  c->batch.clear();
+  for (int p = 0; p < nprob; ++p) {
+    imsmg_ctx *ch = nullptr;
+    int rc = imsmg_create(&ch, c->device, nullptr);
+    if (rc == IMSMG_OK) rc = imsmg_setup(ch, nlevels[p], A[p], R[p], P[p], L[p], E ? E[p] : nullptr, opt);
+    if (rc != IMSMG_OK) {
+      const std::string m = "problem " + std::to_string(p) + ": " + (ch ? ch->err : std::string("create failed"));
+      imsmg_destroy(ch);
+      for (imsmg_ctx *b : c->batch) imsmg_destroy(b);
+      c->batch.clear();
+      return fail(c, rc, m);
+    }
+    c->batch.push_back(ch);
+  }
+  c->err.clear();
+  return IMSMG_OK;
+}
+
+int imsmg_batch_problem(imsmg_ctx *c, int p, imsmg_ctx **child) {
+  if (!c || !child) return IMSMG_ERR_INVALID_ARG;
+  if (p < 0 || p >= int(c->batch.size())) return fail(c, IMSMG_ERR_INVALID_ARG, "no such problem in the batch");
+  *child = c->batch[p];
+  return IMSMG_OK;
+}
+
+int imsmg_pcg_solve_batched(imsmg_ctx *c, int nrhs, const double *const *B_dev, double *const *X_dev, double rtol,
+                            imsmg_info *infos, int nthreads) {
+  if (!c) return IMSMG_ERR_INVALID_ARG;
+  const int np = int(c->batch.size());
+  if (np == 0) return fail(c, IMSMG_ERR_STATE, "imsmg_setup_batched first");
+  if (!B_dev || !X_dev) return fail(c, IMSMG_ERR_INVALID_ARG, "null vector arrays");
+  const int nt = std::max(1, std::min(nthreads > 0 ? nthreads : 4, np));
+  std::atomic<int> next{0};
+  std::mutex mu;
+  int first_rc = IMSMG_OK;
+  std::string first_msg;
+  // each thread takes the next problem and runs its multi-column solve on the
+  // problem's own stream, so that the problems' latency-bound V-cycles overlap
+  auto work = [&]() {
+    for (int p = next++; p < np; p = next++) {
+      const int rc = imsmg_pcg_solve_multi(c->batch[p], nrhs, B_dev[p], X_dev[p], rtol,
+                                           infos ? infos + size_t(p) * nrhs : nullptr);
+      if (rc != IMSMG_OK) {
+        std::lock_guard<std::mutex> g(mu);
+        if (first_rc == IMSMG_OK) {
+          first_rc = rc;
+          first_msg = "problem " + std::to_string(p) + ": " + c->batch[p]->err;
+        }
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+  work();
+  for (auto &th : pool) th.join();
+  if (first_rc != IMSMG_OK) return fail(c, first_rc, first_msg);
+  c->err.clear();
+  return IMSMG_OK;
+}
+
 int imsmg_destroy(imsmg_ctx *c) {
   if (!c) return IMSMG_OK;
+  for (imsmg_ctx *b : c->batch) imsmg_destroy(b);
+  c->batch.clear();
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   destroy_graph(c);

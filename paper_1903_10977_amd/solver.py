@@ -67,7 +67,8 @@ SYMBOLS = ["imsmg_default_options", "imsmg_create", "imsmg_setup", "imsmg_set_pa
            "imsmg_coarse_solve", "imsmg_get_level_stats", "imsmg_kernel_time", "imsmg_last_error", "imsmg_destroy",
            "imsmg_load_mlp", "imsmg_get_patch_features", "imsmg_get_patch_weights", "imsmg_set_block_weights",
            "imsmg_lambda_max", "imsmg_two_grid_objective", "imsmg_mlp_workspace_bytes", "imsmg_mlp_forward",
-           "imsmg_mlp_loss_grad", "imsmg_mlp_adam", "imsmg_vcycle_multi", "imsmg_pcg_solve_multi"]
+           "imsmg_mlp_loss_grad", "imsmg_mlp_adam", "imsmg_vcycle_multi", "imsmg_pcg_solve_multi",
+           "imsmg_setup_batched", "imsmg_batch_problem", "imsmg_pcg_solve_batched"]
 MLP_PARAMS = 5313
 NFEAT = 16
 
@@ -120,6 +121,12 @@ def load():
     lib.imsmg_mlp_adam.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float]
     lib.imsmg_vcycle_multi.argtypes = [vp, i32, vp, vp]
     lib.imsmg_pcg_solve_multi.argtypes = [vp, i32, vp, vp, dbl, C.POINTER(Info)]
+    lib.imsmg_setup_batched.argtypes = [vp, i32, C.POINTER(C.c_int), C.POINTER(C.POINTER(Csr)),
+                                        C.POINTER(C.POINTER(Csr)), C.POINTER(C.POINTER(Patches)),
+                                        C.POINTER(C.POINTER(Lattice)), C.POINTER(C.POINTER(Elements)),
+                                        C.POINTER(Options)]
+    lib.imsmg_batch_problem.argtypes = [vp, i32, C.POINTER(vp)]
+    lib.imsmg_pcg_solve_batched.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(vp), dbl, C.POINTER(Info), i32]
     for s in SYMBOLS:
         if s not in ("imsmg_default_options", "imsmg_last_error"):
             getattr(lib, s).restype = C.c_int
@@ -162,6 +169,56 @@ class SolveInfo:
     solve_ms: float
 
 
+def problem_structs(problem, dim: int = None, reach: int = None, implicit_transfer=True):
+    """The C-ABI arrays of one generated problem (levels 0 = coarsest):
+    (nlevels, A, R, P, L, E, keep); keep holds the numpy arrays the structs
+    point into and must outlive the setup call."""
+    w = problem.workload
+    dim = dim or w.dim
+    reach = reach or w.degree
+    L = len(problem.levels)
+    keep = []
+    A = (Csr * L)()
+    R = (Csr * L)()
+    P = (Patches * L)()
+    Lt = (Lattice * L)()
+    E = (Elements * L)()
+    for l, lev in enumerate(problem.levels):
+        rp, ci, va = _i32(lev.A.indptr), _i32(lev.A.indices), np.ascontiguousarray(lev.A.data, np.float64)
+        keep += [rp, ci, va]
+        A[l] = Csr(lev.A.shape[0], lev.A.shape[1], lev.A.nnz, _p(rp).value, _p(ci).value, _p(va).value)
+        d2l = _i32(lev.dof_to_lattice)
+        keep.append(d2l)
+        shp = (C.c_int32 * 3)(*(list(lev.lattice) + [1] * (3 - len(lev.lattice))))
+        ts = None
+        if implicit_transfer and l > 0 and getattr(lev, "two_scale", None) is not None:
+            ts = np.ascontiguousarray(lev.two_scale, dtype=np.float64)
+            keep.append(ts)
+        Lt[l] = Lattice(dim, shp, reach, _p(d2l).value, _p(ts).value if ts is not None else None)
+        if l > 0:
+            Rm = lev.R
+            rrp, rci, rva = _i32(Rm.indptr), _i32(Rm.indices), np.ascontiguousarray(Rm.data, np.float64)
+            keep += [rrp, rci, rva]
+            R[l] = Csr(Rm.shape[0], Rm.shape[1], Rm.nnz, _p(rrp).value, _p(rci).value, _p(rva).value)
+            bp, bi = _i32(lev.block_ptr), _i32(lev.block_idx)
+            keep += [bp, bi]
+            P[l] = Patches(len(bp) - 1, _p(bp).value, _p(bi).value)
+        if lev.elem_ptr is not None:
+            ep, ei = _i32(lev.elem_ptr), _i32(lev.elem_idx)
+            keep += [ep, ei]
+            eshape = (C.c_int32 * 3)(*([lev.n_elements] * dim + [1] * (3 - dim)))
+            el = et = None
+            if getattr(lev, "elem_id", None) is not None:
+                el = _i32(lev.elem_id)
+                keep.append(el)
+                if getattr(lev, "eta", None) is not None:
+                    et = np.ascontiguousarray(np.asarray(lev.eta, np.float64)[lev.elem_id])
+                    keep.append(et)
+            E[l] = Elements(len(ep) - 1, _p(ep).value, _p(ei).value, eshape,
+                            _p(el).value if el is not None else None, _p(et).value if et is not None else None)
+    return L, A, R, P, Lt, E, keep
+
+
 class Solver:
     """One library context bound to a HIP device."""
 
@@ -196,48 +253,7 @@ class Solver:
     def setup(self, problem, options: Options = None, dim: int = None, reach: int = None, implicit_transfer=True):
         """problem: a generator.GeneratedProblem (levels 0 = coarsest)."""
         w = problem.workload
-        dim = dim or w.dim
-        reach = reach or w.degree
-        L = len(problem.levels)
-        keep = []
-        A = (Csr * L)()
-        R = (Csr * L)()
-        P = (Patches * L)()
-        Lt = (Lattice * L)()
-        E = (Elements * L)()
-        for l, lev in enumerate(problem.levels):
-            rp, ci, va = _i32(lev.A.indptr), _i32(lev.A.indices), np.ascontiguousarray(lev.A.data, np.float64)
-            keep += [rp, ci, va]
-            A[l] = Csr(lev.A.shape[0], lev.A.shape[1], lev.A.nnz, _p(rp).value, _p(ci).value, _p(va).value)
-            d2l = _i32(lev.dof_to_lattice)
-            keep.append(d2l)
-            shp = (C.c_int32 * 3)(*(list(lev.lattice) + [1] * (3 - len(lev.lattice))))
-            ts = None
-            if implicit_transfer and l > 0 and getattr(lev, "two_scale", None) is not None:
-                ts = np.ascontiguousarray(lev.two_scale, dtype=np.float64)
-                keep.append(ts)
-            Lt[l] = Lattice(dim, shp, reach, _p(d2l).value, _p(ts).value if ts is not None else None)
-            if l > 0:
-                Rm = lev.R
-                rrp, rci, rva = _i32(Rm.indptr), _i32(Rm.indices), np.ascontiguousarray(Rm.data, np.float64)
-                keep += [rrp, rci, rva]
-                R[l] = Csr(Rm.shape[0], Rm.shape[1], Rm.nnz, _p(rrp).value, _p(rci).value, _p(rva).value)
-                bp, bi = _i32(lev.block_ptr), _i32(lev.block_idx)
-                keep += [bp, bi]
-                P[l] = Patches(len(bp) - 1, _p(bp).value, _p(bi).value)
-            if lev.elem_ptr is not None:
-                ep, ei = _i32(lev.elem_ptr), _i32(lev.elem_idx)
-                keep += [ep, ei]
-                eshape = (C.c_int32 * 3)(*([lev.n_elements] * dim + [1] * (3 - dim)))
-                el = et = None
-                if getattr(lev, "elem_id", None) is not None:
-                    el = _i32(lev.elem_id)
-                    keep.append(el)
-                    if getattr(lev, "eta", None) is not None:
-                        et = np.ascontiguousarray(np.asarray(lev.eta, np.float64)[lev.elem_id])
-                        keep.append(et)
-                E[l] = Elements(len(ep) - 1, _p(ep).value, _p(ei).value, eshape,
-                                _p(el).value if el is not None else None, _p(et).value if et is not None else None)
+        L, A, R, P, Lt, E, keep = problem_structs(problem, dim, reach, implicit_transfer)
         opt = options if options is not None else default_options(nu_pre=w.nu, nu_post=w.nu)
         self._check(self.lib.imsmg_setup(self.h, L, A, R, P, Lt, E, C.byref(opt)))
         self.problem = problem
@@ -403,6 +419,87 @@ class Solver:
 
 
 # ------------------------------------------------------ damping network kernels
+class BatchContext:
+    """Many independent problems in one library batch context
+    (imsmg_setup_batched): one child context and HIP stream per problem, the
+    solves driven by the library's own pool of host threads."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.device = device
+        h = C.c_void_p()
+        rc = self.lib.imsmg_create(C.byref(h), device, None)
+        if rc != OK:
+            raise SolverError(rc, "imsmg_create failed")
+        self.h = h
+        self.problems = []
+
+    def _check(self, rc):
+        if rc != OK:
+            msg = self.lib.imsmg_last_error(self.h)
+            raise SolverError(rc, msg.decode() if msg else "")
+
+    def setup(self, problems, options: Options, implicit_transfer=True):
+        """problems: generator.GeneratedProblem list; one options struct for all."""
+        k = len(problems)
+        structs = [problem_structs(g, implicit_transfer=implicit_transfer) for g in problems]
+        nl = (C.c_int * k)(*[st[0] for st in structs])
+        arr = lambda T, i: (C.POINTER(T) * k)(*[C.cast(st[i], C.POINTER(T)) for st in structs])
+        self._check(self.lib.imsmg_setup_batched(self.h, k, nl, arr(Csr, 1), arr(Csr, 2), arr(Patches, 3),
+                                                 arr(Lattice, 4), arr(Elements, 5), C.byref(options)))
+        self.problems = list(problems)
+        return self
+
+    def factor(self):
+        self._check(self.lib.imsmg_factor_patches(self.h))
+        return self
+
+    def problem_handle(self, p: int):
+        ch = C.c_void_p()
+        self._check(self.lib.imsmg_batch_problem(self.h, p, C.byref(ch)))
+        return ch
+
+    def level_stats(self, p: int, level: int) -> dict:
+        st = LevelStats()
+        ch = self.problem_handle(p)
+        rc = self.lib.imsmg_get_level_stats(ch, level, C.byref(st))
+        if rc != OK:
+            raise SolverError(rc, (self.lib.imsmg_last_error(ch) or b"").decode())
+        return {f: getattr(st, f) for f, _ in LevelStats._fields_}
+
+    def pcg(self, B, X, rtol: float = 1e-8, nthreads: int = 4, raise_on_error: bool = True):
+        """B, X: per problem a (nrhs, n_p) FP64 device tensor (row k = right-hand
+        side k); returns per problem one SolveInfo per column."""
+        torch = self.torch
+        k = len(B)
+        nrhs = B[0].shape[0]
+        for b, x, g in zip(B, X, self.problems):
+            assert b.shape == x.shape == (nrhs, g.fine.n) and b.dtype == x.dtype == torch.float64
+            assert b.is_cuda and x.is_cuda and b.is_contiguous() and x.is_contiguous()
+        torch.cuda.synchronize(self.device)
+        bp = (C.c_void_p * k)(*[b.data_ptr() for b in B])
+        xp = (C.c_void_p * k)(*[x.data_ptr() for x in X])
+        infos = (Info * (k * nrhs))()
+        rc = self.lib.imsmg_pcg_solve_batched(self.h, nrhs, bp, xp, rtol, infos, nthreads)
+        if rc != OK and raise_on_error:
+            self._check(rc)
+        return [[SolveInfo(i.status, i.iterations, i.rel_res, i.true_rel_res, i.solve_ms)
+                 for i in infos[p * nrhs:(p + 1) * nrhs]] for p in range(k)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.imsmg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def _stream(torch):
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 

@@ -1,6 +1,8 @@
-"""Batched form: independent problems of mixed size and degree, 16
-right-hand sides each, driven concurrently (one context and stream per
-problem, a pool of host threads).  Bars: every column reaches a true relative
+"""Batched form through the C ABI (imsmg_setup_batched /
+imsmg_pcg_solve_batched): independent problems of mixed size and degree, 16
+right-hand sides each, driven concurrently (one child context and stream per
+problem, the library's pool of host threads); a batch problem equals the same
+problem in a stand-alone context bit for bit.  Bars: every column reaches a true relative
 residual <= 1e-8, and the concurrent run gives bit-for-bit the results of a
 sequential run (no state is shared between contexts); with the general
 blocks as BF16 patch GEMMs every column still reaches 1e-8."""
@@ -36,6 +38,15 @@ def test_concurrent_batch_matches_sequential_and_converges():
         assert all(x.status == 0 and x.true_rel_res <= 1e-8 for x in infos_c[i]), \
             (INDICES[i], [(x.status, x.iterations, x.true_rel_res) for x in infos_c[i]])
         assert [x.iterations for x in infos_c[i]] == [x.iterations for x in infos_s[i]]
+    # the batch context's problem 1 against a stand-alone context of the same
+    # problem (same kernels, its own stream): bitwise the same columns
+    g1 = probs[1]
+    o1 = S.default_options(nu_pre=g1.workload.nu, nu_post=g1.workload.nu, precision=S.MIXED, max_iter=2000)
+    alone = S.Solver(0).setup(g1, o1).factor()
+    X1 = torch.zeros_like(B[1])
+    alone.pcg_multi(B[1], X1, rtol=1e-8)
+    assert torch.equal(X1, Xc[1])
+    alone.close()
     # one problem against the stand-alone single-column solve of column 3
     g = probs[0]
     sol = S.Solver(0).setup(g, S.default_options(nu_pre=1, nu_post=1, precision=S.MIXED, max_iter=2000)).factor()
