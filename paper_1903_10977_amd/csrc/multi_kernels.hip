@@ -15,6 +15,7 @@
 // (fixed LDS tree over the workgroup's rows), then one workgroup adds the
 // partials of each column in index order.
 #include "imsmg_internal.h"
+#include "op_row.h"
 
 namespace imsmg {
 
@@ -112,6 +113,134 @@ __global__ __launch_bounds__(kMT) void k_m_residual_smooth(int n, int Kdyn, OpVi
   const double res = r[o] - ax;
   if (m & kMetaGeneral) rh[o] = res;
   xb[o] = xa[o] + c[i] * res;
+}
+
+// Lattice-tiled forms of the two kernels above for tiled stencils (the
+// single-column tiles: one lattice point per thread, x window in LDS), four
+// interleaved columns per workgroup: workgroup = (tile, column group), the
+// window holds the group's four columns of every window point (32 bytes,
+// contiguous in the interleaved layout), and each lane applies its row to
+// the four columns.  Same slot order and arithmetic as mrow: bitwise the
+// results of the untiled kernels.  SMOOTH: rh = r - A xa (general rows), xb
+// = xa + c (r - A xa); else y = b - A x (b == nullptr: y = A x).
+constexpr int kMCols = 4;
+template <int K, typename V, bool SMOOTH>
+__global__ __launch_bounds__(kTileRows) void k_m_tile(int R, OpView<V> op, const uint32_t *__restrict__ meta,
+                                                      const double *__restrict__ c, const double *__restrict__ x,
+                                                      const double *__restrict__ b, double *__restrict__ y,
+                                                      double *__restrict__ xb, const int32_t *__restrict__ done) {
+  using SS = StencilShape<K>;
+  constexpr int NC = kMCols;
+  __shared__ double win[SS::WINDOW * NC];
+  __shared__ double xch[kTileRows * NC];
+  const int ngrp = R / NC;
+  const int bid = xcd_map(blockIdx.x, gridDim.x);
+  const int blk = bid / ngrp, col0 = (bid % ngrp) * NC;
+  const TileBox tb = tile_box<K>(blk, op.ntx, op.nty);
+  const int tx = threadIdx.x % SS::TX;
+  const int ty = (threadIdx.x / SS::TX) % SS::TY;
+  const int tz = threadIdx.x / (SS::TX * SS::TY);
+  const int gx = tb.x0 + tx, gy = tb.y0 + ty, gz = tb.z0 + tz;
+  const bool inbox = gx < op.sx && gy < op.sy && gz < op.sz;
+  const int L = inbox ? gx + op.sx * (gy + op.sy * gz) : 0;
+  const int i0 = op.lat2row[L];
+  const int i = inbox ? i0 : -1;
+  // round 1: the window's four columns (unconditional loads at lattice point
+  // 0 outside the lattice, so that the wait for the row index excludes them)
+  constexpr int PER = (SS::WINDOW + kTileRows - 1) / kTileRows;
+  double w[PER][NC];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * kTileRows;
+    const int wx = e % SS::WX, wy = (e / SS::WX) % SS::WY, wz = e / (SS::WX * SS::WY);
+    const int ex = tb.x0 - SS::P + wx, ey = tb.y0 - SS::P + wy, ez = tb.z0 - (SS::DIM == 3 ? SS::P : 0) + wz;
+    const bool in = e < SS::WINDOW && ex >= 0 && ex < op.sx && ey >= 0 && ey < op.sy && ez >= 0 && ez < op.sz;
+    const double *src = x + size_t(in ? ex + op.sx * (ey + op.sy * ez) : 0) * R + col0;
+    const double2 u0 = *reinterpret_cast<const double2 *>(src);
+    const double2 u1 = *reinterpret_cast<const double2 *>(src + 2);
+    w[q][0] = in ? u0.x : 0.0;
+    w[q][1] = in ? u0.y : 0.0;
+    w[q][2] = in ? u1.x : 0.0;
+    w[q][3] = in ? u1.y : 0.0;
+  }
+  const int g = op.tile_g0[blk] + threadIdx.x;
+  const bool act2 = g < op.tile_g0[blk + 1];
+  // round 2: the row's meta and epilogue inputs, the stored rows' owners
+  unsigned m = 0u;
+  double bv[NC] = {0.0, 0.0, 0.0, 0.0}, ci = 0.0;
+  if (i >= 0) {
+    m = meta[i];
+    if (b) {
+      const double *bs = b + size_t(L) * R + col0;
+      const double2 v0 = *reinterpret_cast<const double2 *>(bs);
+      const double2 v1 = *reinterpret_cast<const double2 *>(bs + 2);
+      bv[0] = v0.x;
+      bv[1] = v0.y;
+      bv[2] = v1.x;
+      bv[3] = v1.y;
+    }
+    if (SMOOTH) ci = c[i];
+  }
+  const int own2 = act2 ? op.sloc[g] : 0;
+  if (done && *done) return;  // uniform
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * kTileRows;
+    if (e < SS::WINDOW) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) win[e * NC + k] = w[q][k];
+    }
+  }
+  __syncthreads();
+  const int tl = tile_local<K>(threadIdx.x);
+  double ax[NC] = {0.0, 0.0, 0.0, 0.0};
+  // phase 1: rows on the reference stencil
+  if (i >= 0 && (m & kMetaIndex) == kMetaIndex) {
+    const ConstPtr<V> ref = (ConstPtr<V>)op.ref;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      const int dx = s % SS::W, dy = (s / SS::W) % SS::W, dz = s / (SS::W * SS::W);
+      const double *t = win + (tl + (dz * SS::WY + dy) * SS::WX + dx) * NC;
+      const double a = double(ref[s]);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) ax[k] += a * t[k];
+    }
+  }
+  // phase 2: the tile's stored rows on the first lanes, results to the owners
+  if (act2) {
+    const int t2 = tile_local<K>(own2);
+    const V *__restrict__ v = op.val + g;
+    const size_t nv = size_t(op.nv);
+    double a2[NC] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      const int dx = s % SS::W, dy = (s / SS::W) % SS::W, dz = s / (SS::W * SS::W);
+      const double *t = win + (t2 + (dz * SS::WY + dy) * SS::WX + dx) * NC;
+      const double a = double(v[s * nv]);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) a2[k] += a * t[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) xch[own2 * NC + k] = a2[k];
+  }
+  __syncthreads();
+  if (i < 0) return;
+  if ((m & kMetaIndex) != kMetaIndex)
+#pragma unroll
+    for (int k = 0; k < NC; ++k) ax[k] = xch[threadIdx.x * NC + k];
+  const size_t o = size_t(L) * R + col0;
+  if constexpr (SMOOTH) {
+    const double *xc = win + (tl + ((SS::DIM == 3 ? SS::P : 0) * SS::WY + SS::P) * SS::WX + SS::P) * NC;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const double res = bv[k] - ax[k];
+      if (m & kMetaGeneral) y[o + k] = res;
+      xb[o + k] = xc[k] + ci * res;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NC; ++k) y[o + k] = b ? bv[k] - ax[k] : ax[k];
+  }
 }
 
 template <int R>
@@ -577,10 +706,28 @@ int multi_blocks(int R, int n) { return std::max(1, (n * R + kMT - 1) / kMT); }
 // partial-sum workspace (doubles): two first-level arrays and the second stage
 size_t multi_part_size(int R, int n) { return size_t(2) * multi_blocks(R, n) * R + size_t(2) * kStage * R; }
 
+#define MT_DISPATCH(K, BODY)                           \
+  switch (K) {                                         \
+    case 9: { constexpr int KK = 9; BODY; } break;     \
+    case 25: { constexpr int KK = 25; BODY; } break;   \
+    case 49: { constexpr int KK = 49; BODY; } break;   \
+    case 27: { constexpr int KK = 27; BODY; } break;   \
+    case 125: { constexpr int KK = 125; BODY; } break; \
+    default: break;                                    \
+  }
+static bool m_tiled(int K, int R) {
+  return (K == 9 || K == 25 || K == 49 || K == 27 || K == 125) && R % kMCols == 0;
+}
+
 template <typename V>
 static void m_residual_impl(hipStream_t s, int R, int n, int K, const OpView<V> &op, const int32_t *row_lat,
                             const uint32_t *meta, const double *x, const double *b, double *y, const int32_t *done) {
   if (n <= 0) return;
+  if (m_tiled(K, R) && op.ntiles > 0) {
+    const int gt = op.ntiles * (R / kMCols);
+    MT_DISPATCH(K, (k_m_tile<KK, V, false><<<gt, kTileRows, 0, s>>>(R, op, meta, nullptr, x, b, y, nullptr, done)))
+    return;
+  }
   const int g = multi_blocks(R, n);
   MR_DISPATCH(R, MK_DISPATCH(K, (k_m_residual<KK, RR, V><<<g, kMT, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done))))
 }
@@ -598,6 +745,11 @@ static void m_residual_smooth_impl(hipStream_t s, int R, int n, int K, const OpV
                                    const uint32_t *meta, const double *c, const double *xa, const double *r,
                                    double *rh, double *xb, const int32_t *done) {
   if (n <= 0) return;
+  if (m_tiled(K, R) && op.ntiles > 0) {
+    const int gt = op.ntiles * (R / kMCols);
+    MT_DISPATCH(K, (k_m_tile<KK, V, true><<<gt, kTileRows, 0, s>>>(R, op, meta, c, xa, r, rh, xb, done)))
+    return;
+  }
   const int g = multi_blocks(R, n);
   MR_DISPATCH(R, MK_DISPATCH(K, (k_m_residual_smooth<KK, RR, V><<<g, kMT, 0, s>>>(n, K, op, row_lat, meta, c, xa, r,
                                                                                    rh, xb, done))))
