@@ -1559,7 +1559,7 @@ void ensure_multi(imsmg_ctx *c, int R) {
   m.q = vec(F);
   m.xsol = vec(F);
   m.bs = vec(F);
-  m.part = dalloc<double>(m.owned, multi_part_size(R, F.n));
+  m.part = dalloc<double>(m.owned, multi_part_size(R, F.n, F.op64.ntiles));
   m.st = dalloc<MState>(m.owned, 1);
   HIP_CHECK_RET(hipMemsetAsync(m.st, 0, sizeof(MState), s));
   HIP_CHECK_RET(hipStreamSynchronize(s));

@@ -159,7 +159,7 @@ int reduction_blocks(int n);
 // --------------------------------------------------------------- multi-RHS (R = 4, 8, 16 interleaved columns)
 bool multi_supported(int R);
 int multi_blocks(int R, int n);
-size_t multi_part_size(int R, int n);
+size_t multi_part_size(int R, int n, int ntiles);  // partial-sum workspace (doubles)
 void launch_m_residual(hipStream_t s, int R, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                        const uint32_t *meta, const double *x, const double *b, double *y, const int32_t *done);
 void launch_m_residual(hipStream_t s, int R, int n, int K, const OpView<float> &op, const int32_t *row_lat,

@@ -122,13 +122,17 @@ __global__ __launch_bounds__(kMT) void k_m_residual_smooth(int n, int Kdyn, OpVi
 // contiguous in the interleaved layout), and each lane applies its row to
 // the four columns.  Same slot order and arithmetic as mrow: bitwise the
 // results of the untiled kernels.  SMOOTH: rh = r - A xa (general rows), xb
-// = xa + c (r - A xa); else y = b - A x (b == nullptr: y = A x).
+// = xa + c (r - A xa); RESIDUAL: y = b - A x (b == nullptr: y = A x); SPMV
+// (the multi-column CG): y = q = A p and, per column, the tile's partial sum
+// of p . q into part[tile * R + column].
 constexpr int kMCols = 4;
-template <int K, typename V, bool SMOOTH>
+enum MTileMode { RESIDUAL = 0, SMOOTH = 1, SPMV = 2 };
+template <int K, typename V, int MODE>
 __global__ __launch_bounds__(kTileRows) void k_m_tile(int R, OpView<V> op, const uint32_t *__restrict__ meta,
                                                       const double *__restrict__ c, const double *__restrict__ x,
                                                       const double *__restrict__ b, double *__restrict__ y,
-                                                      double *__restrict__ xb, const int32_t *__restrict__ done) {
+                                                      double *__restrict__ xb, const int32_t *__restrict__ done,
+                                                      double *__restrict__ part) {
   using SS = StencilShape<K>;
   constexpr int NC = kMCols;
   __shared__ double win[SS::WINDOW * NC];
@@ -179,7 +183,7 @@ __global__ __launch_bounds__(kTileRows) void k_m_tile(int R, OpView<V> op, const
       bv[2] = v1.x;
       bv[3] = v1.y;
     }
-    if (SMOOTH) ci = c[i];
+    if (MODE == SMOOTH) ci = c[i];
   }
   const int own2 = act2 ? op.sloc[g] : 0;
   if (done && *done) return;  // uniform
@@ -224,13 +228,44 @@ __global__ __launch_bounds__(kTileRows) void k_m_tile(int R, OpView<V> op, const
     for (int k = 0; k < NC; ++k) xch[own2 * NC + k] = a2[k];
   }
   __syncthreads();
+  const double *xc = win + (tl + ((SS::DIM == 3 ? SS::P : 0) * SS::WY + SS::P) * SS::WX + SS::P) * NC;
+  if constexpr (MODE == SPMV) {
+    // q = A p; per column the workgroup's p . q in a fixed order (shuffle
+    // tree per wavefront, then the four wavefronts in index order)
+    double pq[NC] = {0.0, 0.0, 0.0, 0.0};
+    if (i >= 0) {
+      if ((m & kMetaIndex) != kMetaIndex)
+#pragma unroll
+        for (int k = 0; k < NC; ++k) ax[k] = xch[threadIdx.x * NC + k];
+      const size_t o = size_t(L) * R + col0;
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        y[o + k] = ax[k];
+        pq[k] = xc[k] * ax[k];
+      }
+    }
+    __syncthreads();  // xch is reused for the wavefront sums
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      double v = pq[k];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      if ((threadIdx.x & 63) == 0) xch[(threadIdx.x >> 6) * NC + k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NC) {
+      double t = 0.0;
+#pragma unroll
+      for (int wv = 0; wv < kTileRows / 64; ++wv) t += xch[wv * NC + threadIdx.x];
+      part[size_t(blk) * R + col0 + threadIdx.x] = t;
+    }
+    return;
+  }
   if (i < 0) return;
   if ((m & kMetaIndex) != kMetaIndex)
 #pragma unroll
     for (int k = 0; k < NC; ++k) ax[k] = xch[threadIdx.x * NC + k];
   const size_t o = size_t(L) * R + col0;
-  if constexpr (SMOOTH) {
-    const double *xc = win + (tl + ((SS::DIM == 3 ? SS::P : 0) * SS::WY + SS::P) * SS::WX + SS::P) * NC;
+  if constexpr (MODE == SMOOTH) {
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       const double res = bv[k] - ax[k];
@@ -704,7 +739,9 @@ bool multi_supported(int R) { return R == 4 || R == 8 || R == 16; }
 
 int multi_blocks(int R, int n) { return std::max(1, (n * R + kMT - 1) / kMT); }
 // partial-sum workspace (doubles): two first-level arrays and the second stage
-size_t multi_part_size(int R, int n) { return size_t(2) * multi_blocks(R, n) * R + size_t(2) * kStage * R; }
+size_t multi_part_size(int R, int n, int ntiles) {
+  return size_t(2) * std::max(multi_blocks(R, n), ntiles) * R + size_t(2) * kStage * R;
+}
 
 #define MT_DISPATCH(K, BODY)                           \
   switch (K) {                                         \
@@ -725,7 +762,8 @@ static void m_residual_impl(hipStream_t s, int R, int n, int K, const OpView<V> 
   if (n <= 0) return;
   if (m_tiled(K, R) && op.ntiles > 0) {
     const int gt = op.ntiles * (R / kMCols);
-    MT_DISPATCH(K, (k_m_tile<KK, V, false><<<gt, kTileRows, 0, s>>>(R, op, meta, nullptr, x, b, y, nullptr, done)))
+    MT_DISPATCH(K, (k_m_tile<KK, V, RESIDUAL><<<gt, kTileRows, 0, s>>>(R, op, meta, nullptr, x, b, y, nullptr, done,
+                                                                      nullptr)))
     return;
   }
   const int g = multi_blocks(R, n);
@@ -747,7 +785,7 @@ static void m_residual_smooth_impl(hipStream_t s, int R, int n, int K, const OpV
   if (n <= 0) return;
   if (m_tiled(K, R) && op.ntiles > 0) {
     const int gt = op.ntiles * (R / kMCols);
-    MT_DISPATCH(K, (k_m_tile<KK, V, true><<<gt, kTileRows, 0, s>>>(R, op, meta, c, xa, r, rh, xb, done)))
+    MT_DISPATCH(K, (k_m_tile<KK, V, SMOOTH><<<gt, kTileRows, 0, s>>>(R, op, meta, c, xa, r, rh, xb, done, nullptr)))
     return;
   }
   const int g = multi_blocks(R, n);
@@ -969,8 +1007,15 @@ void launch_mcg_direction(hipStream_t s, int R, int n, const int32_t *row_lat, c
 }
 void launch_mcg_spmv_pq(hipStream_t s, int R, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                         const uint32_t *meta, const double *p, double *q, double *part, MState *st) {
-  const int g = multi_blocks(R, n);
-  MR_DISPATCH(R, MK_DISPATCH(K, (k_mcg_spmv_pq<KK, RR><<<g, kMT, 0, s>>>(n, K, op, row_lat, meta, p, q, part, st))))
+  int g = multi_blocks(R, n);
+  if (m_tiled(K, R) && op.ntiles > 0) {
+    g = op.ntiles;  // one partial row per tile
+    const int gt = op.ntiles * (R / kMCols);
+    MT_DISPATCH(K, (k_m_tile<KK, double, SPMV><<<gt, kTileRows, 0, s>>>(R, op, meta, nullptr, p, nullptr, q, nullptr,
+                                                                       &st->done, part)))
+  } else {
+    MR_DISPATCH(R, MK_DISPATCH(K, (k_mcg_spmv_pq<KK, RR><<<g, kMT, 0, s>>>(n, K, op, row_lat, meta, p, q, part, st))))
+  }
   double *p2 = part + size_t(2) * g * R;
   k_mcg_stage<<<kStage, kMT, 0, s>>>(g, R, part, p2);
   k_mcg_pq_fin<<<1, kMFin, 0, s>>>(kStage, R, p2, st);
