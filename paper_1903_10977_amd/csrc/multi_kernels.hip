@@ -396,6 +396,71 @@ __global__ __launch_bounds__(kMT) void k_m_tensor_transfer(int n, const int32_t 
   if (xinit) xinit[o] = cinit[i] * out;
 }
 
+// 2D tensor transfer with bands up to kMBandMax, four interleaved columns
+// per thread: the row's band starts, lengths and coefficients are loaded
+// once for the four columns, the inputs as 32-byte vectors; per column the
+// same arithmetic as k_m_tensor_transfer (bitwise the same results).
+template <int R>
+__global__ __launch_bounds__(kMT) void k_m_tensor_transfer4(int n, const int32_t *__restrict__ row_lat, int ox,
+                                                            MBand band, int ix_, const double *__restrict__ xin,
+                                                            double *__restrict__ y, int accumulate,
+                                                            const double *__restrict__ cinit,
+                                                            double *__restrict__ xinit,
+                                                            const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  constexpr int NG = R / 4;
+  const int t = xcd_map(blockIdx.x, gridDim.x) * kMT + threadIdx.x;
+  const int i = t / NG, col0 = (t % NG) * 4;
+  if (i >= n) return;
+  const int L = row_lat[i];
+  const int mx = L % ox;
+  const int my = L / ox;
+  const int sx = band.start[mx], nx = band.len[mx];
+  const int sy = band.start[my], ny = band.len[my];
+  const double *cx = band.coef + size_t(mx) * band.W;
+  const double *cy = band.coef + size_t(my) * band.W;
+  double cxv[kMBandMax], cyv[kMBandMax];
+#pragma unroll
+  for (int a = 0; a < kMBandMax; ++a) {
+    cxv[a] = a < nx ? cx[a] : 0.0;
+    cyv[a] = a < ny ? cy[a] : 0.0;
+  }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int b = 0; b < kMBandMax; ++b) {
+    double in[kMBandMax][4];
+#pragma unroll
+    for (int a = 0; a < kMBandMax; ++a) {
+      if (a < nx && b < ny) {
+        const double *src = xin + (size_t(sy + b) * ix_ + sx + a) * R + col0;
+        const double2 u0 = *reinterpret_cast<const double2 *>(src);
+        const double2 u1 = *reinterpret_cast<const double2 *>(src + 2);
+        in[a][0] = u0.x;
+        in[a][1] = u0.y;
+        in[a][2] = u1.x;
+        in[a][3] = u1.y;
+      } else {
+        in[a][0] = in[a][1] = in[a][2] = in[a][3] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double sum = 0.0;
+#pragma unroll
+      for (int a = 0; a < kMBandMax; ++a) sum += cxv[a] * in[a][k];
+      acc[k] += cyv[b] * sum;
+    }
+  }
+  const size_t o = size_t(L) * R + col0;
+  const double ci = xinit ? cinit[i] : 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double out = accumulate ? y[o + k] + acc[k] : acc[k];
+    y[o + k] = out;
+    if (xinit) xinit[o + k] = ci * out;
+  }
+}
+
 template <int R>
 __global__ __launch_bounds__(kMT) void k_m_ell_gather(int n, int w, const int32_t *__restrict__ row_lat,
                                                       const int32_t *__restrict__ colidx,
@@ -945,7 +1010,11 @@ void launch_m_tensor_transfer(hipStream_t s, int R, int dim, int n, const int32_
   if (n <= 0) return;
   const int g = multi_blocks(R, n);
   MBand b{start, len, coef, W};
-  if (dim == 2) {
+  if (dim == 2 && W <= kMBandMax && R % 4 == 0) {
+    const int g4 = std::max(1, (n * (R / 4) + kMT - 1) / kMT);
+    MR_DISPATCH(R, (k_m_tensor_transfer4<RR><<<g4, kMT, 0, s>>>(n, row_lat, ox, b, ix, xin, y, accumulate, cinit,
+                                                                 xinit, done)))
+  } else if (dim == 2) {
     MR_DISPATCH(R, (k_m_tensor_transfer<2, RR><<<g, kMT, 0, s>>>(n, row_lat, ox, oy, b, ix, iy, xin, y, accumulate,
                                                                   cinit, xinit, done)))
   } else {
