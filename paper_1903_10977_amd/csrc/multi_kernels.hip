@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kTileRows) void k_m_tile(int R, OpView<V> op, const
   const int L = inbox ? gx + op.sx * (gy + op.sy * gz) : 0;
   const int i0 = op.lat2row[L];
   const int i = inbox ? i0 : -1;
-  // round 1: the window's four columns (unconditional loads at lattice point
+  // load (1): the window's four columns (unconditional loads at lattice point
   // 0 outside the lattice, so that the wait for the row index excludes them)
   constexpr int PER = (SS::WINDOW + kTileRows - 1) / kTileRows;
   double w[PER][NC];
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kTileRows) void k_m_tile(int R, OpView<V> op, const
   }
   const int g = op.tile_g0[blk] + threadIdx.x;
   const bool act2 = g < op.tile_g0[blk + 1];
-  // round 2: the row's meta and epilogue inputs, the stored rows' owners
+  // load (2): the row's meta and epilogue inputs, the stored rows' owners
   unsigned m = 0u;
   double bv[NC] = {0.0, 0.0, 0.0, 0.0}, ci = 0.0;
   if (i >= 0) {

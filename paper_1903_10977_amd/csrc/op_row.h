@@ -185,14 +185,14 @@ inline int stencil_grid(int K, int n, const OpView<V> &op) {
 // [blk * kTileRows, ...).  With done != nullptr nothing is computed or stored
 // once *done is set.  Every thread of the workgroup must call it.
 //
-// Tiled, the dependent memory rounds are: (1) the x window (it depends on
+// Tiled, the dependent memory steps are: (1) the x window (it depends on
 // the box only), the lane's row index and the tile's stored-row range;
 // (2) the lane's meta and epilogue loads, the stored rows' owners.  A stored
 // row's A x is computed on a packed lane and handed to the lane owning the row
 // through LDS, so that every epilogue runs on its own lane's data.
 //
 // PRO: the rows see x + R^T xc (pv): the band rows of the window and the
-// coarse window origins join round 1, the coarse window round 2; the
+// coarse window origins join load (1), the coarse window load (2); the
 // corrections are added to the window registers before they go to LDS, in
 // the order of the transfer kernel (bitwise the same x + R^T xc).
 template <int K, typename V, typename Epi, bool PRO = false>
@@ -218,7 +218,7 @@ __device__ __forceinline__ double2 tile_rows(int n, int blk, const OpView<V> &op
     TileRegs<K> w;
     tile_load<K>(tb, op, x, w);
     using PS = ProShape<K>;
-    // PRO, round 1: this lane's band row (lanes < NB) and the coarse origins
+    // PRO, load (1): this lane's band row (lanes < NB) and the coarse origins
     int bsx = 0, bln = 0;
     double bcf[kBandMax];
     int co[2] = {0, 0};
@@ -253,7 +253,7 @@ __device__ __forceinline__ double2 tile_rows(int n, int blk, const OpView<V> &op
     if (done && *done) return acc;
     double *xch = lds + SS::WINDOW;
     if constexpr (PRO) {
-      // round 2: the coarse window
+      // load (2): the coarse window
       double cwv[PS::PERC];
 #pragma unroll
       for (int q = 0; q < PS::PERC; ++q) {
