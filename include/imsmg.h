@@ -112,7 +112,11 @@ typedef struct {
   int32_t max_iter;    /* CG iteration cap */
   int32_t check_every; /* host reads the convergence flag every this many iterations */
   int32_t use_graph;   /* replay each block of check_every iterations as one hipGraph */
-  int32_t timing;      /* record HIP events around the finest-level residual kernel */
+  int32_t timing;      /* 0: off; n >= 1: record HIP events around each plain smoothing step of the
+                          finest level, whose kernel (fused residual + trivial rows) is launched
+                          n times back to back inside the event pair (the step reads x_a and r
+                          and writes x_b and rh only, so the repeats leave the same result;
+                          n > 1 spreads the events' own overhead over n launches); at most 64 */
   double gamma;        /* > 0: uniform damping on all levels; <= 0: 1 / max_K N_K per level */
   int32_t compress;    /* 1: rows equal to the level's interior stencil (1e-14 relative) read that
                           stencil instead of their own values (default 1) */
@@ -316,7 +320,8 @@ int imsmg_get_level_stats(imsmg_ctx *ctx, int level, imsmg_level_stats *stats);
 
 /* Accumulated time of the finest-level residual kernel since the last reset
  * (requires opt.timing; the timed kernel is the finest level's fused residual +
- * trivial-row smoothing step): total milliseconds and number of launches. */
+ * trivial-row smoothing step): total milliseconds and number of launches
+ * (opt.timing launches per timed step). */
 int imsmg_kernel_time(imsmg_ctx *ctx, double *total_ms, int64_t *launches, int reset);
 
 const char *imsmg_last_error(imsmg_ctx *ctx);

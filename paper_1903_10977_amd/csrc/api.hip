@@ -409,12 +409,17 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
   L.op32.nv = nv;
   {
     std::vector<float> ref32(ref.begin(), ref.end());
+    std::vector<double> ref32d(ref32.begin(), ref32.end());
     double *r64 = dalloc<double>(c->owned, L.K);
     float *r32 = dalloc<float>(c->owned, L.K);
+    double *r32d = dalloc<double>(c->owned, L.K);
     h2d(s, r64, ref.data(), L.K);
     h2d(s, r32, ref32.data(), L.K);
+    h2d(s, r32d, ref32d.data(), L.K);
     L.op64.ref = r64;
+    L.op64.refd = r64;
     L.op32.ref = r32;
+    L.op32.refd = r32d;
     HIP_CHECK_RET(hipStreamSynchronize(s));
   }
   if (c->opt.precision == IMSMG_MIXED) {
@@ -663,10 +668,14 @@ void smooth_step(imsmg_ctx *c, Level &L, const double *xa, double *xb, const int
                  const ProlongView *pv = nullptr) {
   hipEvent_t *ev = timed ? timed_pair(c) : nullptr;
   if (ev) HIP_CHECK_RET(hipEventRecord(ev[0], c->stream));
-  if (mixed(c))
-    launch_residual_smooth(c->stream, L.n, L.K, L.op32, L.row_lat, L.meta, L.c, xa, L.r, L.rh, xb, done, pv);
-  else
-    launch_residual_smooth(c->stream, L.n, L.K, L.op64, L.row_lat, L.meta, L.c, xa, L.r, L.rh, xb, done, pv);
+  // timed: opt.timing identical launches (xa and r are only read)
+  const int reps = ev ? c->opt.timing : 1;
+  for (int k = 0; k < reps; ++k) {
+    if (mixed(c))
+      launch_residual_smooth(c->stream, L.n, L.K, L.op32, L.row_lat, L.meta, L.c, xa, L.r, L.rh, xb, done, pv);
+    else
+      launch_residual_smooth(c->stream, L.n, L.K, L.op64, L.row_lat, L.meta, L.c, xa, L.r, L.rh, xb, done, pv);
+  }
   if (ev) HIP_CHECK_RET(hipEventRecord(ev[1], c->stream));
   launch_smooth_general(c->stream, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, L.rh, xb, done, L.gen_lanes);
 }
@@ -737,7 +746,7 @@ void collect_timing(imsmg_ctx *c) {
     float ms = 0.f;
     HIP_CHECK_RET(hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
     c->t_kernel_ms += ms;
-    c->t_kernel_n += 1;
+    c->t_kernel_n += c->opt.timing;
   }
   c->ev_used = 0;
 }
@@ -1723,6 +1732,7 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
     if (c->opt.check_every < 1) c->opt.check_every = 1;
     if (c->opt.precision != IMSMG_FP64 && c->opt.precision != IMSMG_MIXED) bad("unknown precision mode");
     if (c->opt.block_gemm < 0 || c->opt.block_gemm > 2) bad("block_gemm must be 0, 1 or 2");
+    if (c->opt.timing < 0 || c->opt.timing > 64) bad("timing must be 0 .. 64");
     c->lv.resize(nlevels);
     for (int l = 0; l < nlevels; ++l) {
       if (Lt[l].dim != Lt[nlevels - 1].dim) bad("all levels must share the dimension");

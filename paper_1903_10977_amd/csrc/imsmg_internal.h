@@ -44,6 +44,7 @@ template <typename V>
 struct OpView {
   Offsets off;
   const V *ref;            // uniform interior stencil (K values)
+  const double *refd;      // the same K values widened to FP64 (tiled kernels: no per-tap conversion)
   const V *val;            // stored rows, slot-major
   int nv;                  // number of stored rows (numbered tile by tile)
   const int32_t *sloc;     // lattice point of every stored row within its tile box (tx + TX (ty + TY tz))

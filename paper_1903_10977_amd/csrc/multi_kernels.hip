@@ -200,12 +200,12 @@ __global__ __launch_bounds__(kTileRows) void k_m_tile(int R, OpView<V> op, const
   double ax[NC] = {0.0, 0.0, 0.0, 0.0};
   // phase 1: rows on the reference stencil
   if (i >= 0 && (m & kMetaIndex) == kMetaIndex) {
-    const ConstPtr<V> ref = (ConstPtr<V>)op.ref;
+    const ConstPtr<double> ref = (ConstPtr<double>)op.refd;
 #pragma unroll
     for (int s = 0; s < K; ++s) {
       const int dx = s % SS::W, dy = (s / SS::W) % SS::W, dz = s / (SS::W * SS::W);
       const double *t = win + (tl + (dz * SS::WY + dy) * SS::WX + dx) * NC;
-      const double a = double(ref[s]);
+      const double a = ref[s];
 #pragma unroll
       for (int k = 0; k < NC; ++k) ax[k] += a * t[k];
     }

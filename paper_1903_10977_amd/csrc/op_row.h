@@ -321,9 +321,9 @@ __device__ __forceinline__ double2 tile_rows(int n, int blk, const OpView<V> &op
     double ax = 0.0;
     // phase 1: rows on the reference stencil
     if (i >= 0 && (m & kMetaIndex) == kMetaIndex) {
-      const ConstPtr<V> ref = (ConstPtr<V>)op.ref;
+      const ConstPtr<double> ref = (ConstPtr<double>)op.refd;
 #pragma unroll
-      for (int s = 0; s < K; ++s) ax += double(ref[s]) * tile_at<K>(t, s);
+      for (int s = 0; s < K; ++s) ax += ref[s] * tile_at<K>(t, s);
     }
     // phase 2: the tile's stored rows, packed onto the first lanes
     if (act2) {
