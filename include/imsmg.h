@@ -135,6 +135,12 @@ typedef struct {
                           FP32 accumulation.  1 and 2 apply on levels whose general blocks all
                           have <= 16 functions (others keep 0); the single-column solve always
                           uses 0 */
+  int32_t flexible_cg; /* 1: imsmg_pcg_solve takes beta_k = (r_{k+1}.z_{k+1} - r_{k+1}.z_k) / (r_k.z_k)
+                          (Polak-Ribiere form, robust to a preconditioner that changes between
+                          iterations; one more dot product, reduced inside the update kernel);
+                          0: beta_k = r_{k+1}.z_{k+1} / (r_k.z_k) (default).  The two agree in
+                          exact arithmetic for the fixed SPD V-cycle.  The multi-column and
+                          batched solves use 0 and reject 1 */
 } imsmg_options;
 
 typedef struct {

@@ -18,7 +18,13 @@ Readings:
 * the V-cycle is used as the preconditioner of CG (the paragraph after the
   algorithm), with x_0 = 0 and the stopping test ||r_k|| <= tol ||r_0|| in the
   2-norm; on stopping, the true residual ||b - A x|| / ||b|| is recomputed and
-  the iteration continues while it is above tol.
+  the iteration continues while it is above tol;
+* the paper names CG without a variant; besides the Hestenes-Stiefel beta the
+  Polak-Ribiere ("flexible") form beta = r_{k+1}.(z_{k+1} - z_k) / r_k.z_k is
+  offered, which equals it in exact arithmetic for a fixed SPD preconditioner
+  (r_{k+1}.z_k = 0 there).  It is pinned only through that equality; how it
+  behaves under a preconditioner that changes between iterations is parity
+  unpinned (nothing here varies the V-cycle).
 """
 from __future__ import annotations
 
@@ -67,9 +73,9 @@ class VCycle:
         return Bm
 
 
-def pcg(A, b, precond, tol=1e-8, max_iter=1000, x0=None):
-    """Preconditioned CG (Hestenes-Stiefel).  Returns (x, iterations, history)
-    where history holds ||r_k|| / ||r_0||."""
+def pcg(A, b, precond, tol=1e-8, max_iter=1000, x0=None, flexible=False):
+    """Preconditioned CG (Hestenes-Stiefel; flexible=True: Polak-Ribiere beta).
+    Returns (x, iterations, history) where history holds ||r_k|| / ||r_0||."""
     x = np.zeros_like(b) if x0 is None else x0.copy()
     r = b - A @ x
     r0 = np.linalg.norm(r)
@@ -92,8 +98,10 @@ def pcg(A, b, precond, tol=1e-8, max_iter=1000, x0=None):
             true_rel = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
             if true_rel <= tol:
                 break
+        z_old = z
         z = precond(r)
         rz_new = r @ z
-        p = z + (rz_new / rz) * p
+        num = rz_new - r @ z_old if flexible else rz_new
+        p = z + (num / rz) * p
         rz = rz_new
     return x, it, hist

@@ -35,9 +35,9 @@ class OracleProblem:
     def b(self):
         return self.system.b
 
-    def solve(self, b=None, tol=1e-8, max_iter=1000):
+    def solve(self, b=None, tol=1e-8, max_iter=1000, flexible=False):
         b = self.b if b is None else b
-        return MG.pcg(self.A, b, self.vcycle.apply, tol=tol, max_iter=max_iter)
+        return MG.pcg(self.A, b, self.vcycle.apply, tol=tol, max_iter=max_iter, flexible=flexible)
 
 
 def build(w, orders=None, smoothers=True) -> OracleProblem:

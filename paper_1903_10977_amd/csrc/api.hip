@@ -1661,10 +1661,12 @@ void cg_iteration(imsmg_ctx *c, bool timing) {
   Level &F = c->lv.back();
   const int32_t *done = &c->st->done;
   vcycle_level(c, int(c->lv.size()) - 1, done, timing);
-  launch_cg_dot_rz(c->stream, F.n, F.row_lat, F.r, F.x, c->part, c->st);
+  launch_cg_dot_rz(c->stream, F.n, F.row_lat, F.r, F.x, c->part, c->st, c->opt.flexible_cg);
   launch_cg_direction(c->stream, F.n, F.row_lat, F.x, c->p, c->st);
   launch_cg_spmv_pq(c->stream, F.n, F.K, F.op64, F.row_lat, F.meta, c->p, c->q, c->part, c->st);
-  launch_cg_update(c->stream, F.n, F.row_lat, c->p, c->q, c->xs, F.r, F.c, F.xs, c->part, c->st, c->opt.max_iter);
+  // z_k = F.x until the next V-cycle (F.xs may be the same buffer)
+  launch_cg_update(c->stream, F.n, F.row_lat, c->p, c->q, c->xs, F.r, F.c, F.xs, c->opt.flexible_cg ? F.x : nullptr,
+                   c->part, c->st, c->opt.max_iter);
 }
 
 }  // namespace
@@ -1733,6 +1735,7 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
     if (c->opt.precision != IMSMG_FP64 && c->opt.precision != IMSMG_MIXED) bad("unknown precision mode");
     if (c->opt.block_gemm < 0 || c->opt.block_gemm > 2) bad("block_gemm must be 0, 1 or 2");
     if (c->opt.timing < 0 || c->opt.timing > 64) bad("timing must be 0 .. 64");
+    if (c->opt.flexible_cg != 0 && c->opt.flexible_cg != 1) bad("flexible_cg must be 0 or 1");
     c->lv.resize(nlevels);
     for (int l = 0; l < nlevels; ++l) {
       if (Lt[l].dim != Lt[nlevels - 1].dim) bad("all levels must share the dimension");
@@ -2177,6 +2180,7 @@ int imsmg_pcg_solve_multi(imsmg_ctx *c, int nrhs, const double *B_dev, double *X
     if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
     if (!B_dev || !X_dev) bad("null vector");
     if (!(rtol > 0.0)) bad("rtol must be positive");
+    if (c->opt.flexible_cg) bad("flexible_cg applies to imsmg_pcg_solve only");
     const int R = rhs_width(nrhs);
     auto t0 = std::chrono::steady_clock::now();
     ensure_multi(c, R);

@@ -159,14 +159,19 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_dot_rz(int n, const int32_t 
   if (threadIdx.x == 0) part[blk] = acc;
 }
 
-__global__ __launch_bounds__(kFinThreads) void k_cg_rz_fin(int m, const double *__restrict__ part, CGState *st) {
+// beta: Hestenes-Stiefel r_{k+1}.z_{k+1} / r_k.z_k, or (flexible) the
+// Polak-Ribiere form (r_{k+1}.z_{k+1} - r_{k+1}.z_k) / r_k.z_k, whose second
+// term the update kernel reduced while z_k was still in place; both agree
+// in exact arithmetic when the preconditioner is one fixed SPD operator
+__global__ __launch_bounds__(kFinThreads) void k_cg_rz_fin(int m, const double *__restrict__ part, CGState *st,
+                                                           int flexible) {
   if (st->done) return;
   __shared__ double lds[kFinThreads];
   const double tot = sum_partials(part, m, lds);
   if (threadIdx.x == 0) {
     st->rz_old = st->rz;
     st->rz = tot;
-    st->beta = st->first ? 0.0 : tot / st->rz_old;
+    st->beta = st->first ? 0.0 : (flexible ? tot - st->rz_mix : tot) / st->rz_old;
     if (!(tot == tot)) {
       st->status = -6;
       st->done = 1;
@@ -218,36 +223,47 @@ __global__ __launch_bounds__(kFinThreads) void k_cg_pq_fin(int m, const double *
   }
 }
 
+// FLEX: also the partials of r_{k+1} . z_k into part[gridDim.x + blk]; zs
+// may be the buffer holding z_k (then each lane reads its z_k before it
+// writes zs at the same index), so neither pointer is restrict-qualified
+template <bool FLEX>
 __global__ __launch_bounds__(kRedThreads) void k_cg_update(int n, const int32_t *__restrict__ row_lat,
                                                            const double *__restrict__ p,
                                                            const double *__restrict__ q, double *__restrict__ x,
                                                            double *__restrict__ r, const double *__restrict__ c,
-                                                           double *__restrict__ zs, double *__restrict__ part,
+                                                           double *zs, const double *zk, double *__restrict__ part,
                                                            const CGState *st) {
   if (st->done) return;
   __shared__ double lds[kRedThreads];
   const double alpha = st->alpha;
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
   const int i = blk * kRedThreads + threadIdx.x;
-  double acc = 0.0;
+  double acc = 0.0, mix = 0.0;
   if (i < n) {
     const int L = row_lat[i];
     x[L] += alpha * p[L];
     const double ri = r[L] - alpha * q[L];
     r[L] = ri;
+    if (FLEX) mix = ri * zk[L];
     zs[L] = c[i] * ri;
     acc = ri * ri;
   }
   acc = block_sum<kRedThreads>(acc, lds);
   if (threadIdx.x == 0) part[blk] = acc;
+  if (FLEX) {
+    mix = block_sum<kRedThreads>(mix, lds);
+    if (threadIdx.x == 0) part[gridDim.x + blk] = mix;
+  }
 }
 
 __global__ __launch_bounds__(kFinThreads) void k_cg_update_fin(int m, const double *__restrict__ part, CGState *st,
-                                                               int max_iter) {
+                                                               int max_iter, int flexible) {
   if (st->done) return;
   __shared__ double lds[kFinThreads];
   const double tot = sum_partials(part, m, lds);
+  const double mix = flexible ? sum_partials(part + m, m, lds) : 0.0;
   if (threadIdx.x == 0) {
+    st->rz_mix = mix;
     st->rr = tot;
     st->iters += 1;
     if (!(tot == tot)) {
@@ -303,10 +319,10 @@ void launch_cg_init(hipStream_t s, int n, int K, const OpView<double> &op, const
 }
 
 void launch_cg_dot_rz(hipStream_t s, int n, const int32_t *row_lat, const double *r, const double *z, double *part,
-                      CGState *st) {
+                      CGState *st, int flexible) {
   const int g = reduction_blocks(n);
   k_cg_dot_rz<<<g, kRedThreads, 0, s>>>(n, row_lat, r, z, part, st);
-  k_cg_rz_fin<<<1, kFinThreads, 0, s>>>(g, part, st);
+  k_cg_rz_fin<<<1, kFinThreads, 0, s>>>(g, part, st, flexible);
 }
 
 void launch_cg_direction(hipStream_t s, int n, const int32_t *row_lat, const double *z, double *p, CGState *st) {
@@ -321,10 +337,14 @@ void launch_cg_spmv_pq(hipStream_t s, int n, int K, const OpView<double> &op, co
 }
 
 void launch_cg_update(hipStream_t s, int n, const int32_t *row_lat, const double *p, const double *q, double *x,
-                      double *r, const double *c, double *zs, double *part, CGState *st, int max_iter) {
+                      double *r, const double *c, double *zs, const double *zk, double *part, CGState *st,
+                      int max_iter) {
   const int g = reduction_blocks(n);
-  k_cg_update<<<g, kRedThreads, 0, s>>>(n, row_lat, p, q, x, r, c, zs, part, st);
-  k_cg_update_fin<<<1, kFinThreads, 0, s>>>(g, part, st, max_iter);
+  if (zk)
+    k_cg_update<true><<<g, kRedThreads, 0, s>>>(n, row_lat, p, q, x, r, c, zs, zk, part, st);
+  else
+    k_cg_update<false><<<g, kRedThreads, 0, s>>>(n, row_lat, p, q, x, r, c, zs, nullptr, part, st);
+  k_cg_update_fin<<<1, kFinThreads, 0, s>>>(g, part, st, max_iter, zk != nullptr);
 }
 
 void launch_cg_true_residual(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,

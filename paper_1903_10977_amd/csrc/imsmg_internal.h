@@ -86,6 +86,7 @@ struct CGState {
   double tol2;     // (rtol * ||r_0||)^2
   double bb;       // ||b||^2
   double aux;      // scratch scalar (true residual)
+  double rz_mix;   // r_{k+1} . z_k (flexible CG)
   int32_t done;    // 1: converged or stopped
   int32_t iters;
   int32_t status;  // 0 ok, IMSMG_ERR_NOT_SPD on p.q <= 0, IMSMG_ERR_NAN on NaN
@@ -145,14 +146,17 @@ void launch_gather(hipStream_t s, int n, const int32_t *row_lat, const double *s
 void launch_cg_init(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                     const uint32_t *meta, const double *x, const double *b, double *r, double *part, CGState *st,
                     double rtol, int restart);
+// r . z and beta (flexible: Polak-Ribiere form with the r_{k+1} . z_k of the last update)
 void launch_cg_dot_rz(hipStream_t s, int n, const int32_t *row_lat, const double *r, const double *z, double *part,
-                      CGState *st);
+                      CGState *st, int flexible);
 void launch_cg_direction(hipStream_t s, int n, const int32_t *row_lat, const double *z, double *p, CGState *st);
 void launch_cg_spmv_pq(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                        const uint32_t *meta, const double *p, double *q, double *part, CGState *st);
-// x += alpha p, r -= alpha q, ||r||^2; also zs = c * r (first smoothing step of the next V-cycle)
+// x += alpha p, r -= alpha q, ||r||^2; also zs = c * r (first smoothing step of the next V-cycle);
+// zk != nullptr (flexible CG): also r_{k+1} . z_k (part must hold two partial arrays)
 void launch_cg_update(hipStream_t s, int n, const int32_t *row_lat, const double *p, const double *q, double *x,
-                      double *r, const double *c, double *zs, double *part, CGState *st, int max_iter);
+                      double *r, const double *c, double *zs, const double *zk, double *part, CGState *st,
+                      int max_iter);
 void launch_cg_true_residual(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                              const uint32_t *meta, const double *x, const double *b, double *part, CGState *st);
 int reduction_blocks(int n);

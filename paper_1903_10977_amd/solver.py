@@ -47,7 +47,7 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("max_iter", C.c_int32),
                 ("check_every", C.c_int32), ("use_graph", C.c_int32), ("timing", C.c_int32), ("gamma", C.c_double),
                 ("compress", C.c_int32), ("use_learned", C.c_int32), ("autotune", C.c_int32),
-                ("block_gemm", C.c_int32)]
+                ("block_gemm", C.c_int32), ("flexible_cg", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -158,7 +158,7 @@ def test_coarse_solve_and_vcycle(name):
 
 
 FORMS = {"fp64": dict(precision=0, compress=1), "fp64-uncompressed": dict(precision=0, compress=0),
-         "mixed": dict(precision=1, compress=1)}
+         "mixed": dict(precision=1, compress=1), "mixed-flexible": dict(precision=1, compress=1, flexible_cg=1)}
 
 
 @pytest.mark.parametrize("form", list(FORMS))
@@ -170,7 +170,7 @@ def test_pcg_solution_matches_oracle(name, form):
         b = np.random.default_rng(10).standard_normal(op.A.shape[0])
     else:
         b = op.b
-    xo, ito, _ = op.solve(b=b, tol=1e-8)
+    xo, ito, _ = op.solve(b=b, tol=1e-8, flexible=FORMS[form].get("flexible_cg", 0) == 1)
     sol = _solver(S, g, **FORMS[form])
     bg = g.b if w.rhs != "zero" else b
     x = torch.zeros(len(bg), dtype=torch.float64, device="cuda:0")
@@ -202,4 +202,14 @@ def test_solver_errors_are_reported():
     sol.setup(g, S.default_options(max_iter=1)).factor()
     info = sol.pcg(_t(g.b), x, rtol=1e-8, raise_on_error=False)
     assert info.status == -5 and info.iterations == 1
+    sol.close()
+    # option checks: flexible_cg is 0 or 1, and only the single-column solve takes it
+    with pytest.raises(S.SolverError) as ei:
+        S.Solver(0).setup(g, S.default_options(flexible_cg=2))
+    assert ei.value.code == -1
+    sol = S.Solver(0).setup(g, S.default_options(flexible_cg=1)).factor()
+    Bm = torch.zeros((4, g.fine.n), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(S.SolverError) as ei:
+        sol.pcg_multi(Bm, torch.zeros_like(Bm), rtol=1e-8)
+    assert ei.value.code == -1
     sol.close()

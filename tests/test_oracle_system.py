@@ -269,6 +269,35 @@ def test_pcg_matches_direct_solve_c1():
     assert it < 60
 
 
+def test_flexible_pcg_equals_standard_for_the_fixed_vcycle():
+    """The V-cycle is one fixed SPD operator (the paragraph after Algorithm
+    alg:MGV), so r_{k+1}.z_k = 0 in exact arithmetic and the Polak-Ribiere
+    beta equals the Hestenes-Stiefel one: same iterates up to rounding, same
+    iteration count, and the cross term is rounding-small against r_k.z_k."""
+    op = P.build(W.c1())
+    xs, its, hs = op.solve(tol=1e-8)
+    xf, itf, hf = op.solve(tol=1e-8, flexible=True)
+    assert itf == its
+    k = min(10, len(hs))
+    assert np.allclose(hf[:k], hs[:k], rtol=1e-8, atol=0.0)
+    M = op.system.M
+    e = xf - xs
+    assert math.sqrt(e @ (M @ e)) / math.sqrt(xs @ (M @ xs)) < 1e-9
+    # the cross term along the standard iteration
+    A, B = op.A, op.vcycle.apply
+    r = op.b.copy()
+    z = B(r)
+    p = z.copy()
+    for _ in range(5):
+        q = A @ p
+        a = (r @ z) / (p @ q)
+        r_new = r - a * q
+        z_new = B(r_new)
+        assert abs(r_new @ z) <= 1e-8 * abs(r @ z)
+        p = z_new + ((r_new @ z_new) / (r @ z)) * p
+        r, z = r_new, z_new
+
+
 @pytest.mark.slow
 def test_iterations_mesh_independent():
     """Numerical examples: iteration counts virtually independent of the grid."""
