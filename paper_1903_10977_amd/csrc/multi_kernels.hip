@@ -159,29 +159,29 @@ __global__ __launch_bounds__(kTileRows) void k_m_tile(int R, OpView<V> op, const
     const int wx = e % SS::WX, wy = (e / SS::WX) % SS::WY, wz = e / (SS::WX * SS::WY);
     const int ex = tb.x0 - SS::P + wx, ey = tb.y0 - SS::P + wy, ez = tb.z0 - (SS::DIM == 3 ? SS::P : 0) + wz;
     const bool in = e < SS::WINDOW && ex >= 0 && ex < op.sx && ey >= 0 && ey < op.sy && ez >= 0 && ez < op.sz;
-    const double *src = x + size_t(in ? ex + op.sx * (ey + op.sy * ez) : 0) * R + col0;
-    const double2 u0 = *reinterpret_cast<const double2 *>(src);
-    const double2 u1 = *reinterpret_cast<const double2 *>(src + 2);
-    w[q][0] = in ? u0.x : 0.0;
-    w[q][1] = in ? u0.y : 0.0;
-    w[q][2] = in ? u1.x : 0.0;
-    w[q][3] = in ? u1.y : 0.0;
+    const double2 *src = reinterpret_cast<const double2 *>(x + size_t(in ? ex + op.sx * (ey + op.sy * ez) : 0) * R + col0);
+#pragma unroll
+    for (int k = 0; k < NC / 2; ++k) {
+      const double2 u = src[k];
+      w[q][2 * k] = in ? u.x : 0.0;
+      w[q][2 * k + 1] = in ? u.y : 0.0;
+    }
   }
   const int g = op.tile_g0[blk] + threadIdx.x;
   const bool act2 = g < op.tile_g0[blk + 1];
   // load (2): the row's meta and epilogue inputs, the stored rows' owners
   unsigned m = 0u;
-  double bv[NC] = {0.0, 0.0, 0.0, 0.0}, ci = 0.0;
+  double bv[NC] = {}, ci = 0.0;
   if (i >= 0) {
     m = meta[i];
     if (b) {
-      const double *bs = b + size_t(L) * R + col0;
-      const double2 v0 = *reinterpret_cast<const double2 *>(bs);
-      const double2 v1 = *reinterpret_cast<const double2 *>(bs + 2);
-      bv[0] = v0.x;
-      bv[1] = v0.y;
-      bv[2] = v1.x;
-      bv[3] = v1.y;
+      const double2 *bs = reinterpret_cast<const double2 *>(b + size_t(L) * R + col0);
+#pragma unroll
+      for (int k = 0; k < NC / 2; ++k) {
+        const double2 u = bs[k];
+        bv[2 * k] = u.x;
+        bv[2 * k + 1] = u.y;
+      }
     }
     if (MODE == SMOOTH) ci = c[i];
   }
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(kTileRows) void k_m_tile(int R, OpView<V> op, const
   }
   __syncthreads();
   const int tl = tile_local<K>(threadIdx.x);
-  double ax[NC] = {0.0, 0.0, 0.0, 0.0};
+  double ax[NC] = {};
   // phase 1: rows on the reference stencil
   if (i >= 0 && (m & kMetaIndex) == kMetaIndex) {
     const ConstPtr<double> ref = (ConstPtr<double>)op.refd;
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kTileRows) void k_m_tile(int R, OpView<V> op, const
     const int t2 = tile_local<K>(own2);
     const V *__restrict__ v = op.val + g;
     const size_t nv = size_t(op.nv);
-    double a2[NC] = {0.0, 0.0, 0.0, 0.0};
+    double a2[NC] = {};
 #pragma unroll
     for (int s = 0; s < K; ++s) {
       const int dx = s % SS::W, dy = (s / SS::W) % SS::W, dz = s / (SS::W * SS::W);
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kTileRows) void k_m_tile(int R, OpView<V> op, const
   if constexpr (MODE == SPMV) {
     // q = A p; per column the workgroup's p . q in a fixed order (shuffle
     // tree per wavefront, then the four wavefronts in index order)
-    double pq[NC] = {0.0, 0.0, 0.0, 0.0};
+    double pq[NC] = {};
     if (i >= 0) {
       if ((m & kMetaIndex) != kMetaIndex)
 #pragma unroll
