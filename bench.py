@@ -92,7 +92,7 @@ def main():
                     help="also run a plain device copy of this size (for FETCH_SIZE/WRITE_SIZE scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU: --gpus must be 1 (sharding across GPUs is designed, not implemented)"}))
         sys.exit(2)
 
     import numpy as np
