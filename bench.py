@@ -209,14 +209,14 @@ def main():
                  "general_blocks": forms,
                  "rhs": "column 0: the workload's load vector; others: load vectors M u of random normal u"}
     # batched: 64 independent problems (n in {64..512}^2, p in {1,2,3}), 16
-    # right-hand sides each, one context and stream per problem, 4 host threads
+    # right-hand sides each, one context and stream per problem, 16 host threads
     batched = None
     if not args.no_batched:
         from paper_1903_10977_amd import batch as BT
         # the configuration's form: general blocks as BF16 patch GEMMs (FP32
         # accumulation) on the matrix cores; the assembled CSR product beside it
-        batched = BT.run_batch(64, 16, workers=4, steps=2, precision=head, block_gemm=2)
-        batched["csr_fp64"] = BT.run_batch(64, 16, workers=4, steps=2, precision=head, block_gemm=0)
+        batched = BT.run_batch(64, 16, workers=16, steps=2, precision=head, block_gemm=2)
+        batched["csr_fp64"] = BT.run_batch(64, 16, workers=16, steps=2, precision=head, block_gemm=0)
     hr = results[head]
     ms_step = hr["ms"]
     value = hr["mdofs"]

@@ -29,7 +29,7 @@ def _log(msg):
 
 
 class BatchSolver:
-    def __init__(self, problems, nrhs=16, precision=S.MIXED, max_iter=2000, workers=4, block_gemm=0):
+    def __init__(self, problems, nrhs=16, precision=S.MIXED, max_iter=2000, workers=16, block_gemm=0):
         import torch
         self.torch = torch
         self.problems = problems
@@ -72,7 +72,7 @@ class BatchSolver:
         self.ctx.close()
 
 
-def run_batch(count=64, nrhs=16, workers=4, steps=2, precision=S.MIXED, block_gemm=0):
+def run_batch(count=64, nrhs=16, workers=16, steps=2, precision=S.MIXED, block_gemm=0):
     import workloads as W
     t0 = time.time()
     probs = [GN.generate(W.batched_c4(i), with_mass=True) for i in range(count)]
@@ -101,7 +101,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--problems", type=int, default=64)
     ap.add_argument("--nrhs", type=int, default=16)
-    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--block-gemm", type=int, default=0, choices=[0, 1, 2],
                     help="general blocks: 0 CSR FP64, 1 FP64 patch GEMMs, 2 BF16 patch GEMMs (matrix cores)")
