@@ -293,11 +293,27 @@ int imsmg_get_patches(imsmg_ctx *ctx, int level, int32_t *nblocks, int64_t *nnz,
 /* Damping factor of level l (1 / max_K N_K or the uniform override). */
 int imsmg_get_gamma(imsmg_ctx *ctx, int level, double *gamma);
 
-/* z = B r for the finest level (one V-cycle).  r, z: device, compact, FP64. */
+/* z = B r: one V-cycle of Algorithm alg:MGV on the finest level (x = 0, nu_pre
+ * smoothing steps, residual, restriction, recursion, prolongation, nu_post
+ * smoothing steps; direct solve on level 0).  r_dev, z_dev: caller-owned
+ * device arrays of n_{L} FP64 (compact numbering of the finest level); r is
+ * only read.  Errors: IMSMG_ERR_STATE before imsmg_factor_patches,
+ * IMSMG_ERR_INVALID_ARG for a null pointer, IMSMG_ERR_HIP. */
 int imsmg_vcycle(imsmg_ctx *ctx, const double *r_dev, double *z_dev);
 
-/* Preconditioned CG from x (device; in: x0, out: solution) until
- * ||r_k|| <= rtol ||r_0|| and ||b - A x|| <= rtol ||b||. */
+/* CG preconditioned by the V-cycle (the paragraph after Algorithm alg:MGV).
+ * b_dev: right-hand side, x_dev: x0 on entry and the solution on return, both
+ * caller-owned device arrays of n_{L} FP64 (compact numbering of the finest
+ * level).  Iterates until ||r_k|| <= rtol ||r_0|| (2-norm, recursive
+ * residual), then recomputes ||b - A x|| / ||b|| in FP64 and restarts from x
+ * while that is above rtol (the first start's threshold and iteration count
+ * are kept).  beta: opt.flexible_cg.  The iterations run as captured graphs
+ * of opt.check_every iterations (opt.use_graph) with every CG scalar on the
+ * device.  info (may be NULL): status, iterations, both residuals, wall time.
+ * Errors: IMSMG_ERR_STATE before imsmg_factor_patches; IMSMG_ERR_INVALID_ARG
+ * for null vectors or rtol <= 0; IMSMG_ERR_NOT_SPD when p.Ap <= 0;
+ * IMSMG_ERR_NOT_CONVERGED after opt.max_iter iterations (x holds the last
+ * iterate); IMSMG_ERR_NAN; IMSMG_ERR_HIP. */
 int imsmg_pcg_solve(imsmg_ctx *ctx, const double *b_dev, double *x_dev, double rtol, imsmg_info *info);
 
 /* Kernel-level entry points (device, compact vectors of the level). */
