@@ -63,18 +63,21 @@ __device__ __forceinline__ double col_sum(double v, double *lds) {
   return lds[threadIdx.x];
 }
 
-__device__ __forceinline__ double sum_part(const double *__restrict__ part, int m, int R, int col, double *lds) {
+// per-column sums of part[b * R + col] over b < m for all R columns at once
+// (R a power of two <= 16): thread t adds column t % R over b = t / R,
+// t / R + kMFin / R, ... in that order, then a fixed tree over the kMFin / R
+// threads of each column (strides are multiples of R).  The sums are left in
+// lds[0 .. R); every thread of the workgroup must call it.
+__device__ __forceinline__ void sum_cols(const double *__restrict__ part, int m, int R, double *lds) {
+  const int col = threadIdx.x % R, lane = threadIdx.x / R, lanes = kMFin / R;
   double v = 0.0;
-  for (int b = threadIdx.x; b < m; b += kMFin) v += part[size_t(b) * R + col];
+  for (int b = lane; b < m; b += lanes) v += part[size_t(b) * R + col];
   lds[threadIdx.x] = v;
   __syncthreads();
-  for (int s = kMFin / 2; s > 0; s >>= 1) {
+  for (int s = kMFin / 2; s >= R; s >>= 1) {
     if (threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
     __syncthreads();
   }
-  const double r = lds[0];
-  __syncthreads();
-  return r;
 }
 }  // namespace
 
@@ -673,18 +676,23 @@ __global__ __launch_bounds__(kMT) void k_mcg_stage(int m, int R, const double *_
   if (threadIdx.x < R) out[size_t(blockIdx.x) * R + threadIdx.x] = lds[threadIdx.x];
 }
 
-// ---- finalize kernels (one workgroup; columns one after the other)
+// ---- finalize kernels (one workgroup; all columns reduced together, then
+// thread 0 updates the per-column state in column order)
 // restart != 0: CG restarted from the current iterate; the stopping threshold
 // and the iteration counts of the first start are kept, and the columns in
 // keep_mask (bit col) stay converged
 __global__ __launch_bounds__(kMFin) void k_mcg_init_fin(int m, int R, int ncols, const double *__restrict__ part,
                                                         MState *st, double rtol, int restart, int keep_mask) {
   __shared__ double lds[kMFin];
+  __shared__ double rrs[16];
+  sum_cols(part, m, R, lds);
+  if (threadIdx.x < R) rrs[threadIdx.x] = lds[threadIdx.x];
+  __syncthreads();
+  sum_cols(part + size_t(m) * R, m, R, lds);
   int all = 1;
   for (int col = 0; col < R; ++col) {
-    const double rr = sum_part(part, m, R, col, lds);
-    const double bb = sum_part(part + size_t(m) * R, m, R, col, lds);
     if (threadIdx.x == 0) {
+      const double rr = rrs[col], bb = lds[col];
       if (!restart) {
         st->r0sq[col] = rr;
         st->tol2[col] = rtol * rtol * rr;
@@ -711,9 +719,10 @@ __global__ __launch_bounds__(kMFin) void k_mcg_init_fin(int m, int R, int ncols,
 __global__ __launch_bounds__(kMFin) void k_mcg_rz_fin(int m, int R, const double *__restrict__ part, MState *st) {
   if (st->done) return;
   __shared__ double lds[kMFin];
+  sum_cols(part, m, R, lds);
   for (int col = 0; col < R; ++col) {
-    const double tot = sum_part(part, m, R, col, lds);
     if (threadIdx.x == 0) {
+      const double tot = lds[col];
       if (st->cdone[col]) {
         st->beta[col] = 0.0;
       } else {
@@ -732,9 +741,10 @@ __global__ __launch_bounds__(kMFin) void k_mcg_rz_fin(int m, int R, const double
 __global__ __launch_bounds__(kMFin) void k_mcg_pq_fin(int m, int R, const double *__restrict__ part, MState *st) {
   if (st->done) return;
   __shared__ double lds[kMFin];
+  sum_cols(part, m, R, lds);
   for (int col = 0; col < R; ++col) {
-    const double tot = sum_part(part, m, R, col, lds);
     if (threadIdx.x == 0) {
+      const double tot = lds[col];
       if (st->cdone[col]) {
         st->alpha[col] = 0.0;
       } else if (!(tot > 0.0)) {
@@ -753,10 +763,11 @@ __global__ __launch_bounds__(kMFin) void k_mcg_update_fin(int m, int R, const do
                                                           int max_iter) {
   if (st->done) return;
   __shared__ double lds[kMFin];
+  sum_cols(part, m, R, lds);
   int all = 1;
   for (int col = 0; col < R; ++col) {
-    const double tot = sum_part(part, m, R, col, lds);
     if (threadIdx.x == 0) {
+      const double tot = lds[col];
       if (!st->cdone[col]) {
         st->rr[col] = tot;
         st->iters[col] += 1;
@@ -776,10 +787,9 @@ __global__ __launch_bounds__(kMFin) void k_mcg_update_fin(int m, int R, const do
 
 __global__ __launch_bounds__(kMFin) void k_mcg_aux_fin(int m, int R, const double *__restrict__ part, MState *st) {
   __shared__ double lds[kMFin];
-  for (int col = 0; col < R; ++col) {
-    const double tot = sum_part(part, m, R, col, lds);
-    if (threadIdx.x == 0) st->aux[col] = tot;
-  }
+  sum_cols(part, m, R, lds);
+  if (threadIdx.x == 0)
+    for (int col = 0; col < R; ++col) st->aux[col] = lds[col];
 }
 
 // ------------------------------------------------------------------ launchers
