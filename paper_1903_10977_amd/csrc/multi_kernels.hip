@@ -483,30 +483,48 @@ __global__ __launch_bounds__(kMT) void k_m_ell_gather(int n, int w, const int32_
   if (xinit) xinit[o] = cinit[i] * out;
 }
 
-// coarsest level: X = A^{-1} Rhs for R columns.  Workgroup = 256/R rows x R
-// columns; the right-hand sides are staged through LDS in chunks of kGChunk
-// rows (kGChunk x R doubles).
+// coarsest level: X = A^{-1} Rhs for R columns, one wavefront per row; the
+// right-hand sides are staged through LDS in chunks of kGChunk rows
+// (kGChunk x R doubles).
 constexpr int kGChunk = 128;
+static_assert(kGChunk % 64 == 0, "chunks keep each lane's ascending j sequence");
 template <int R>
 __global__ __launch_bounds__(kMT) void k_m_dense_gemm(int n, const int32_t *__restrict__ row_lat,
                                                       const double *__restrict__ Ainv, const double *__restrict__ r,
                                                       double *__restrict__ x, const int32_t *__restrict__ done) {
+  // one wavefront per row of A^{-1}: lane l adds the entries j = l, l + 64,
+  // ... in ascending order for all R columns, then a shuffle tree per column
+  // (per column the order of the single-column product); the right-hand
+  // sides are staged per chunk in LDS, column-major, so that the lanes of a
+  // wavefront read consecutive doubles
   if (done && *done) return;
-  __shared__ double rs[kGChunk * R];
-  const int t = blockIdx.x * kMT + threadIdx.x;
-  const int i = t / R, col = t % R;
-  double acc = 0.0;
+  __shared__ double rs[R * kGChunk];
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (kMT / 64) + (threadIdx.x >> 6);
+  const double *row = Ainv + size_t(i < n ? i : 0) * n;
+  double acc[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) acc[c] = 0.0;
   for (int j0 = 0; j0 < n; j0 += kGChunk) {
     const int m = min(kGChunk, n - j0);
-    for (int e = threadIdx.x; e < m * R; e += kMT) rs[e] = r[size_t(row_lat[j0 + e / R]) * R + (e % R)];
+    for (int e = threadIdx.x; e < m * R; e += kMT) rs[(e % R) * kGChunk + e / R] = r[size_t(row_lat[j0 + e / R]) * R + (e % R)];
     __syncthreads();
     if (i < n) {
-      const double *row = Ainv + size_t(i) * n + j0;
-      for (int j = 0; j < m; ++j) acc += row[j] * rs[j * R + col];
+      for (int j = lane; j < m; j += 64) {
+        const double a = row[j0 + j];
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc[c] += a * rs[c * kGChunk + j];
+      }
     }
     __syncthreads();
   }
-  if (i < n) x[size_t(row_lat[i]) * R + col] = acc;
+#pragma unroll
+  for (int c = 0; c < R; ++c)
+    for (int o = 32; o > 0; o >>= 1) acc[c] += __shfl_down(acc[c], o, 64);
+  if (i < n && lane == 0) {
+#pragma unroll
+    for (int c = 0; c < R; ++c) x[size_t(row_lat[i]) * R + c] = acc[c];
+  }
 }
 
 // user layout (column-major n x ncols, ld = n) <-> interleaved padded lattice
@@ -1044,7 +1062,7 @@ void launch_m_ell_gather(hipStream_t s, int R, int n, int w, const int32_t *row_
 void launch_m_dense_gemm(hipStream_t s, int R, int n, const int32_t *row_lat, const double *Ainv, const double *r,
                          double *x, const int32_t *done) {
   if (n <= 0) return;
-  const int g = multi_blocks(R, n);
+  const int g = (n + kMT / 64 - 1) / (kMT / 64);  // one wavefront per row
   MR_DISPATCH(R, (k_m_dense_gemm<RR><<<g, kMT, 0, s>>>(n, row_lat, Ainv, r, x, done)))
 }
 
