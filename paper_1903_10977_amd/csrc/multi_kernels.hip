@@ -488,8 +488,9 @@ __global__ __launch_bounds__(kMT) void k_m_ell_gather(int n, int w, const int32_
 // (kGChunk x R doubles).
 constexpr int kGChunk = 128;
 static_assert(kGChunk % 64 == 0, "chunks keep each lane's ascending j sequence");
+constexpr int kGemmThreads = 1024;  // 16 rows per workgroup: each staged chunk serves 16 rows
 template <int R>
-__global__ __launch_bounds__(kMT) void k_m_dense_gemm(int n, const int32_t *__restrict__ row_lat,
+__global__ __launch_bounds__(kGemmThreads) void k_m_dense_gemm(int n, const int32_t *__restrict__ row_lat,
                                                       const double *__restrict__ Ainv, const double *__restrict__ r,
                                                       double *__restrict__ x, const int32_t *__restrict__ done) {
   // one wavefront per row of A^{-1}: lane l adds the entries j = l, l + 64,
@@ -500,14 +501,14 @@ __global__ __launch_bounds__(kMT) void k_m_dense_gemm(int n, const int32_t *__re
   if (done && *done) return;
   __shared__ double rs[R * kGChunk];
   const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (kMT / 64) + (threadIdx.x >> 6);
+  const int i = blockIdx.x * (kGemmThreads / 64) + (threadIdx.x >> 6);
   const double *row = Ainv + size_t(i < n ? i : 0) * n;
   double acc[R];
 #pragma unroll
   for (int c = 0; c < R; ++c) acc[c] = 0.0;
   for (int j0 = 0; j0 < n; j0 += kGChunk) {
     const int m = min(kGChunk, n - j0);
-    for (int e = threadIdx.x; e < m * R; e += kMT) rs[(e % R) * kGChunk + e / R] = r[size_t(row_lat[j0 + e / R]) * R + (e % R)];
+    for (int e = threadIdx.x; e < m * R; e += kGemmThreads) rs[(e % R) * kGChunk + e / R] = r[size_t(row_lat[j0 + e / R]) * R + (e % R)];
     __syncthreads();
     if (i < n) {
       for (int j = lane; j < m; j += 64) {
@@ -1062,8 +1063,8 @@ void launch_m_ell_gather(hipStream_t s, int R, int n, int w, const int32_t *row_
 void launch_m_dense_gemm(hipStream_t s, int R, int n, const int32_t *row_lat, const double *Ainv, const double *r,
                          double *x, const int32_t *done) {
   if (n <= 0) return;
-  const int g = (n + kMT / 64 - 1) / (kMT / 64);  // one wavefront per row
-  MR_DISPATCH(R, (k_m_dense_gemm<RR><<<g, kMT, 0, s>>>(n, row_lat, Ainv, r, x, done)))
+  const int g = (n + kGemmThreads / 64 - 1) / (kGemmThreads / 64);  // one wavefront per row
+  MR_DISPATCH(R, (k_m_dense_gemm<RR><<<g, kGemmThreads, 0, s>>>(n, row_lat, Ainv, r, x, done)))
 }
 
 void launch_m_scatter(hipStream_t s, int R, int n, int ncols, const int32_t *row_lat, const double *src,
