@@ -16,9 +16,12 @@ Readings:
   cubic benchmark asks for two): each step is x += S (r_in - A x);
 * the coarsest "direct solve" is a dense Cholesky solve;
 * the V-cycle is used as the preconditioner of CG (the paragraph after the
-  algorithm), with x_0 = 0 and the stopping test ||r_k|| <= tol ||r_0|| in the
-  2-norm; on stopping, the true residual ||b - A x|| / ||b|| is recomputed and
-  the iteration continues while it is above tol;
+  algorithm), with x_0 = 0 and the stopping test ||r_k|| <= tol min(||r_0||,
+  ||b||) in the 2-norm (the two agree for x_0 = 0); on stopping, the true
+  residual ||b - A x|| / ||b|| is recomputed and, while it is above tol, CG is
+  restarted from the current x (r = b - A x, fresh direction; the threshold
+  and the iteration count carry over), at most three times; a solve that
+  ends above tol reports that it did not converge;
 * the paper names CG without a variant; besides the Hestenes-Stiefel beta the
   Polak-Ribiere ("flexible") form beta = r_{k+1}.(z_{k+1} - z_k) / r_k.z_k is
   offered, which equals it in exact arithmetic for a fixed SPD preconditioner
@@ -73,35 +76,51 @@ class VCycle:
         return Bm
 
 
-def pcg(A, b, precond, tol=1e-8, max_iter=1000, x0=None, flexible=False):
+MAX_RESTARTS = 3
+
+
+def pcg(A, b, precond, tol=1e-8, max_iter=1000, x0=None, flexible=False, info=None):
     """Preconditioned CG (Hestenes-Stiefel; flexible=True: Polak-Ribiere beta).
-    Returns (x, iterations, history) where history holds ||r_k|| / ||r_0||."""
+    Returns (x, iterations, history) where history holds ||r_k|| / ||r_0|| of
+    the first start.  If a dict is passed as `info` it receives the restart
+    count, the final true relative residual and `converged`."""
     x = np.zeros_like(b) if x0 is None else x0.copy()
+    bnorm = np.linalg.norm(b)
     r = b - A @ x
     r0 = np.linalg.norm(r)
+    thr = tol * min(r0, bnorm)
     hist = [1.0]
-    if r0 == 0.0:
-        return x, 0, hist
-    z = precond(r)
-    p = z.copy()
-    rz = r @ z
     it = 0
-    while it < max_iter:
-        q = A @ p
-        alpha = rz / (p @ q)
-        x = x + alpha * p
-        r = r - alpha * q
-        it += 1
-        rel = np.linalg.norm(r) / r0
-        hist.append(rel)
-        if rel <= tol:
-            true_rel = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
-            if true_rel <= tol:
-                break
-        z_old = z
+    restarts = 0
+    true_rel = r0 / bnorm if bnorm > 0 else 0.0
+    while r0 > 0.0:
         z = precond(r)
-        rz_new = r @ z
-        num = rz_new - r @ z_old if flexible else rz_new
-        p = z + (num / rz) * p
-        rz = rz_new
+        p = z.copy()
+        rz = r @ z
+        stopped = False
+        while it < max_iter:
+            q = A @ p
+            alpha = rz / (p @ q)
+            x = x + alpha * p
+            r = r - alpha * q
+            it += 1
+            rn = np.linalg.norm(r)
+            if restarts == 0:
+                hist.append(rn / r0)
+            if rn <= thr:
+                stopped = True
+                break
+            z_old = z
+            z = precond(r)
+            rz_new = r @ z
+            num = rz_new - r @ z_old if flexible else rz_new
+            p = z + (num / rz) * p
+            rz = rz_new
+        r = b - A @ x
+        true_rel = np.linalg.norm(r) / bnorm if bnorm > 0 else np.linalg.norm(r)
+        if true_rel <= tol or not stopped or restarts == MAX_RESTARTS:
+            break
+        restarts += 1
+    if info is not None:
+        info.update(restarts=restarts, true_rel=true_rel, converged=bool(true_rel <= tol))
     return x, it, hist

@@ -19,6 +19,7 @@ from oracle import geometry as G
 from oracle import hierarchy as H
 from oracle import multigrid as MG
 from oracle import problem as P
+from oracle import quadrature as Q
 from oracle import schwarz as SW
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
@@ -230,6 +231,78 @@ def test_two_level_error_propagation_identity():
     assert lam[0] > 0 and lam[-1] <= 1 + 1e-8
 
 
+@pytest.mark.parametrize("nu", [1, 2])
+def test_multilevel_error_propagation_recursion(nu):
+    """eq:eigenMulti applied level by level (Algorithm alg:MGV is recursive):
+    with nu smoothing steps on either side, the error propagation of the
+    l-level cycle is E_l = (I - S_l A_l)^nu (I - R_l^T B_{l-1} R_l A_l)
+    (I - S_l A_l)^nu with B_{l-1} = (I - E_{l-1}) A_{l-1}^{-1} and
+    B_0 = A_0^{-1}.  Built here from the level matrices, compared with the
+    oracle's V-cycle probed by unit vectors on a three-level hierarchy.  A
+    dropped or extra smoothing step, a wrong level index or a missing
+    residual update breaks the equality."""
+    w = _w(degree=2, n=16, depth=1, levels=3, nu=nu, discs=[[0.45, 0.55, 0.23]])
+    op = P.build(w)
+    A = [a.toarray() for a in op.hier.A]
+    R = [r.toarray() for r in op.hier.R]
+    B = np.linalg.inv(A[0])
+    for l in (1, 2):
+        I = np.eye(len(A[l]))
+        Sm = np.linalg.matrix_power(I - op.smoothers[l].dense() @ A[l], nu)
+        E = Sm @ (I - R[l - 1].T @ B @ R[l - 1] @ A[l]) @ Sm
+        B = (I - E) @ np.linalg.inv(A[l])
+        Bv = op.vcycle.dense(l)
+        scale = np.abs(B).max()
+        assert np.abs(Bv - B).max() < 1e-8 * scale, (l, np.abs(Bv - B).max() / scale)
+    # the symmetric cycle is SPD-preconditioning: spectrum of B A in (0, 1]
+    lam = np.sort(np.linalg.eigvals(Bv @ A[2]).real)
+    assert lam[0] > 0 and lam[-1] <= 1 + 1e-8
+
+
+def _manufactured_errors(p, n, leaf_n, discs):
+    """L2 and H1-seminorm errors of the Galerkin solution (direct solve) of the
+    manufactured problem on the level with n elements, on the Omega_h of a
+    fixed leaf lattice with leaf_n cells per axis."""
+    depth = int(round(math.log2(leaf_n // n)))
+    w = W.Workload(name="ph", dim=2, degree=p, n=n, depth=depth, levels=1, geometry="discs",
+                   discs=discs, rhs="manufactured")
+    leaf = G.leaf_values(w, n, depth)
+    s = AS.assemble(w, leaf, n, depth)
+    x = spla.spsolve(s.A.tocsc(), s.b)
+    lev = s.level
+    pos = {int(L): i for i, L in enumerate(lev.active)}
+    l2 = h1 = 0.0
+    for e in zip(*np.nonzero(lev.active_el)):
+        fl = lev.elem_funcs[AS.element_lin(e, n)]
+        # rules well above the integrands' polynomial degree
+        vp, vw, _, _, _ = Q.element_quadrature(leaf, e, depth, lev.lo, lev.h, p + 4, 2 * p + 4, 2)
+        if not len(vw):
+            continue
+        V, Gr = AS.tensor_eval(lev, e, vp)
+        cf = np.array([x[pos[L]] if L in pos else 0.0 for L in fl])
+        u, _, g = AS.manufactured(vp)
+        l2 += np.sum(vw * (cf @ V - u) ** 2)
+        h1 += np.sum(vw * np.sum((np.einsum("a,aqc->qc", cf, Gr) - g) ** 2, axis=1))
+    return math.sqrt(l2), math.sqrt(h1)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_manufactured_solution_rates(p):
+    """u* = sin(2 pi x) sin(2 pi y) solves -lap u = f with f = 8 pi^2 u*, u = 0
+    on the box and the Neumann data grad u* . n_h on the immersed boundary of
+    Omega_h, so on a fixed Omega_h (leaf lattice held at 1/256 while the grid
+    is refined) the Galerkin error must fall at the optimal rates of degree-p
+    B-splines: L2 ~ h^(p+1), H1 ~ h^p.  A sign or factor error in f, in g or
+    in the boundary normal leaves the error at a plateau (slope ~0)."""
+    discs = [[0.46, 0.53, 0.21], [0.17, 0.2, 0.08]]
+    e = [_manufactured_errors(p, n, 256, discs) for n in (8, 16, 32)]
+    for k in (1, 2):
+        s_l2 = math.log2(e[k - 1][0] / e[k][0])
+        s_h1 = math.log2(e[k - 1][1] / e[k][1])
+        assert p + 1 - 0.2 < s_l2 < p + 1 + 0.4, (k, s_l2)
+        assert p - 0.2 < s_h1 < p + 0.4, (k, s_h1)
+
+
 @pytest.mark.parametrize("n", [16, 32])
 def test_star_domain_spectra_match_paper(n):
     """Smoothers subsection (Additive Schwarz): star domain, quadratic
@@ -267,6 +340,31 @@ def test_pcg_matches_direct_solve_c1():
     e = x - xd
     assert math.sqrt(e @ (M @ e)) / math.sqrt(xd @ (M @ xd)) < 1e-6
     assert it < 60
+
+
+def test_pcg_from_a_far_start_meets_the_true_residual():
+    """CG from an x0 whose residual is 1e3 times ||b||: the solve must end with
+    the true relative residual ||b - A x|| / ||b|| <= tol (the criterion the
+    solve reports) and equal the direct solve (P-j); with too few iterations
+    it must say that it did not converge."""
+    op = P.build(W.c1())
+    b = op.b
+    rng = np.random.Generator(np.random.PCG64(7))
+    x0 = rng.standard_normal(len(b))
+    x0 *= 1e3 * np.linalg.norm(b) / np.linalg.norm(b - op.A @ x0)
+    info = {}
+    x, it, _ = MG.pcg(op.A, b, op.vcycle.apply, tol=1e-8, x0=x0, info=info)
+    assert info["converged"] and info["true_rel"] <= 1e-8
+    assert np.linalg.norm(b - op.A @ x) / np.linalg.norm(b) == pytest.approx(info["true_rel"], rel=1e-12)
+    xd = spla.spsolve(op.A.tocsc(), b)
+    M = op.system.M
+    e = x - xd
+    assert math.sqrt(e @ (M @ e)) / math.sqrt(xd @ (M @ xd)) < 1e-6
+    # the far start needs more iterations than x0 = 0 (the residual falls by 1e11)
+    assert it > op.solve(tol=1e-8)[1]
+    info2 = {}
+    MG.pcg(op.A, b, op.vcycle.apply, tol=1e-8, x0=x0, max_iter=5, info=info2)
+    assert not info2["converged"] and info2["true_rel"] > 1e-8
 
 
 def test_flexible_pcg_equals_standard_for_the_fixed_vcycle():
@@ -323,6 +421,21 @@ def test_apple_active_counts_match_paper():
     nl = 3 * AS.active_function_mask(act, "lagrange", 2).sum()
     assert abs(nb / gold["bspline"] - 1) < 0.002
     assert abs(nl / gold["lagrange"] - 1) < 0.002
+
+
+def test_helix_active_counts_match_paper():
+    """Numerical examples, triple helix: 128^3 quadratic, depth 0 -> 1.11M
+    B-spline and 6.96M Lagrange DOFs (3 components each), printed to three
+    significant figures: the counts must round to the printed values."""
+    gold = GOLD["helix_dofs_128"]
+    w = W.Workload(name="helix", dim=3, degree=2, n=128, depth=0, levels=1, geometry="helix",
+                   box_lo=-2.0, box_hi=2.0)
+    leaf = G.leaf_values(w, 128, 0)
+    act = G.active_elements(leaf, 128, 0)
+    nb = 3 * AS.active_function_mask(act, "bspline", 2).sum()
+    nl = 3 * AS.active_function_mask(act, "lagrange", 2).sum()
+    assert abs(nb - gold["bspline"]) <= 0.005e6
+    assert abs(nl - gold["lagrange"]) <= 0.005e6
 
 
 def test_vectorised_activation_matches_element_loop():
