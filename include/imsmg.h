@@ -48,8 +48,8 @@ enum {
   IMSMG_ERR_INVALID_ARG = -1,  /* shape, pointer or ordering mismatch */
   IMSMG_ERR_OOM = -2,
   IMSMG_ERR_HIP = -3,          /* a HIP runtime call failed */
-  IMSMG_ERR_NOT_SPD = -4,      /* block / coarse factorization or CG breakdown (p.Ap <= 0) */
-  IMSMG_ERR_NOT_CONVERGED = -5,/* max_iter reached; x holds the last iterate */
+  IMSMG_ERR_NOT_SPD = -4,      /* non-positive operator diagonal (setup), block / coarse factorization, or CG breakdown (p.Ap <= 0) */
+  IMSMG_ERR_NOT_CONVERGED = -5,/* true relative residual above rtol at the end; x holds the last iterate */
   IMSMG_ERR_NAN = -6,          /* NaN / Inf met in the iteration */
   IMSMG_ERR_STATE = -7         /* call out of order (e.g. solve before factor) */
 };
@@ -192,10 +192,14 @@ int imsmg_factor_patches(imsmg_ctx *ctx);
 int imsmg_vcycle_multi(imsmg_ctx *ctx, int nrhs, const double *R_dev, double *Z_dev);
 
 /* nrhs independent PCG solves A x_k = b_k sharing every kernel launch; CG
- * scalars, stopping test (||r_k|| <= rtol ||r_k,0||) and iteration counts are
- * per column (a converged column stops moving while the others continue);
- * the call returns when every column has converged or on the first error.
- * infos: nrhs entries (may be NULL); solve_ms is the wall time of the call. */
+ * scalars, stopping test (||r_k|| <= rtol min(||r_k,0||, ||b_k||)),
+ * true-residual restarts (as imsmg_pcg_solve; columns already below rtol stay
+ * converged) and iteration counts are per column (a converged column stops
+ * moving while the others continue); the call returns when every column has
+ * converged or on the first error.  infos: nrhs entries (may be NULL);
+ * solve_ms is the wall time of the call.  Returns IMSMG_ERR_NOT_CONVERGED
+ * when some column ends above rtol (that column's info.status says so, the
+ * others' are 0), IMSMG_ERR_NAN / IMSMG_ERR_NOT_SPD for the whole call. */
 int imsmg_pcg_solve_multi(imsmg_ctx *ctx, int nrhs, const double *B_dev, double *X_dev, double rtol,
                           imsmg_info *infos);
 
@@ -304,16 +308,19 @@ int imsmg_vcycle(imsmg_ctx *ctx, const double *r_dev, double *z_dev);
 /* CG preconditioned by the V-cycle (the paragraph after Algorithm alg:MGV).
  * b_dev: right-hand side, x_dev: x0 on entry and the solution on return, both
  * caller-owned device arrays of n_{L} FP64 (compact numbering of the finest
- * level).  Iterates until ||r_k|| <= rtol ||r_0|| (2-norm, recursive
- * residual), then recomputes ||b - A x|| / ||b|| in FP64 and restarts from x
- * while that is above rtol (the first start's threshold and iteration count
- * are kept).  beta: opt.flexible_cg.  The iterations run as captured graphs
- * of opt.check_every iterations (opt.use_graph) with every CG scalar on the
- * device.  info (may be NULL): status, iterations, both residuals, wall time.
+ * level).  Iterates until ||r_k|| <= rtol min(||r_0||, ||b||) (2-norm,
+ * recursive residual; the two norms agree for x0 = 0), then recomputes
+ * ||b - A x|| / ||b|| in FP64 and restarts CG from x (fresh direction) while
+ * that is above rtol, at most three times (the first start's threshold and
+ * iteration count are kept).  beta: opt.flexible_cg.  The iterations run as
+ * captured graphs of opt.check_every iterations (opt.use_graph) with every CG
+ * scalar on the device.  info (may be NULL): status, iterations, both
+ * residuals, wall time.
  * Errors: IMSMG_ERR_STATE before imsmg_factor_patches; IMSMG_ERR_INVALID_ARG
  * for null vectors or rtol <= 0; IMSMG_ERR_NOT_SPD when p.Ap <= 0;
- * IMSMG_ERR_NOT_CONVERGED after opt.max_iter iterations (x holds the last
- * iterate); IMSMG_ERR_NAN; IMSMG_ERR_HIP. */
+ * IMSMG_ERR_NOT_CONVERGED when the true relative residual is still above
+ * rtol at the end (restarts used up or opt.max_iter iterations reached; x
+ * holds the last iterate, info is filled); IMSMG_ERR_NAN; IMSMG_ERR_HIP. */
 int imsmg_pcg_solve(imsmg_ctx *ctx, const double *b_dev, double *x_dev, double rtol, imsmg_info *info);
 
 /* Kernel-level entry points (device, compact vectors of the level). */

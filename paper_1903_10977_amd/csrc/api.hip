@@ -286,6 +286,12 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
       ell[size_t(sl) * L.n + i] = A.val[k];
     }
   }
+  // an SPD operator has a positive, finite diagonal: reject the others before
+  // anything is launched on them
+  for (int i = 0; i < L.n; ++i) {
+    const double d = ell[size_t(L.center) * L.n + i];
+    if (!(d > 0.0) || !std::isfinite(d)) bad("operator has a non-positive diagonal entry (not SPD)", IMSMG_ERR_NOT_SPD);
+  }
   L.row_lat = dalloc<int32_t>(c->owned, L.n);
   h2d(s, L.row_lat, L.h_row_lat.data(), L.n);
   L.val = dalloc<double>(c->owned, ell.size());
@@ -1936,6 +1942,9 @@ int imsmg_pcg_solve(imsmg_ctx *c, const double *b_dev, double *x_dev, double rto
       }
       launch_gather(s, F.n, F.row_lat, c->xs, x_dev);
       HIP_CHECK_RET(hipStreamSynchronize(s));
+      // the solve's criterion is the true relative residual: a solve that ends
+      // above rtol (restarts used up, or max_iter reached) has not converged
+      if (h.status == 0 && true_rel > rtol) h.status = IMSMG_ERR_NOT_CONVERGED;
       if (info) {
         info->status = h.status;
         info->iterations = h.iters;
@@ -1944,7 +1953,7 @@ int imsmg_pcg_solve(imsmg_ctx *c, const double *b_dev, double *x_dev, double rto
         info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
       }
       if (h.status != 0) {
-        c->err = h.status == IMSMG_ERR_NOT_CONVERGED ? "CG did not converge within max_iter"
+        c->err = h.status == IMSMG_ERR_NOT_CONVERGED ? "CG did not reach rtol (true relative residual)"
                  : h.status == IMSMG_ERR_NOT_SPD     ? "CG breakdown: p.Ap <= 0"
                                                      : "NaN or Inf in the CG iteration";
         return int(h.status);
@@ -2238,16 +2247,20 @@ int imsmg_pcg_solve_multi(imsmg_ctx *c, int nrhs, const double *B_dev, double *X
     launch_m_gather(s, R, F.n, nrhs, F.row_lat, m.xsol, X_dev);
     HIP_CHECK_RET(hipStreamSynchronize(s));
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    // a column that ends above rtol (restarts used up, or max_iter) has not converged
+    bool missed = false;
+    for (int k = 0; k < nrhs; ++k) missed |= true_rel[k] > rtol;
+    if (h.status == 0 && missed) h.status = IMSMG_ERR_NOT_CONVERGED;
     if (infos)
       for (int k = 0; k < nrhs; ++k) {
-        infos[k].status = h.status;
+        infos[k].status = h.status == IMSMG_ERR_NOT_CONVERGED ? (true_rel[k] > rtol ? h.status : 0) : h.status;
         infos[k].iterations = h.iters[k];
         infos[k].rel_res = h.r0sq[k] > 0.0 ? std::sqrt(h.rr[k] / h.r0sq[k]) : 0.0;
         infos[k].true_rel_res = true_rel[k];
         infos[k].solve_ms = ms;
       }
     if (h.status != 0) {
-      c->err = h.status == IMSMG_ERR_NOT_CONVERGED ? "CG did not converge within max_iter"
+      c->err = h.status == IMSMG_ERR_NOT_CONVERGED ? "CG did not reach rtol in some column (true relative residual)"
                : h.status == IMSMG_ERR_NOT_SPD     ? "CG breakdown: p.Ap <= 0"
                                                    : "NaN or Inf in the CG iteration";
       return int(h.status);

@@ -117,8 +117,11 @@ __global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_cg_init(int n
   }
 }
 
-// restart != 0: CG restarted from the current iterate; the stopping threshold
-// and the iteration count of the first start are kept
+// Stopping threshold ||r_k|| <= rtol min(||r_0||, ||b||) (equal for x_0 = 0;
+// with a start x_0 whose residual exceeds ||b|| the threshold still aims at
+// the true relative residual ||b - A x|| / ||b||).  restart != 0: CG
+// restarted from the current iterate; the threshold and the iteration count of
+// the first start are kept.
 __global__ __launch_bounds__(kFinThreads) void k_cg_init_fin(int m, const double *__restrict__ part, CGState *st,
                                                              double rtol, int restart) {
   __shared__ double lds[kFinThreads];
@@ -127,7 +130,7 @@ __global__ __launch_bounds__(kFinThreads) void k_cg_init_fin(int m, const double
   if (threadIdx.x == 0) {
     if (!restart) {
       st->r0sq = rr;
-      st->tol2 = rtol * rtol * rr;
+      st->tol2 = rtol * rtol * (rr < bb ? rr : bb);
       st->iters = 0;
     }
     st->rr = rr;

@@ -709,12 +709,14 @@ __global__ __launch_bounds__(kMFin) void k_mcg_init_fin(int m, int R, int ncols,
   __syncthreads();
   sum_cols(part + size_t(m) * R, m, R, lds);
   int all = 1;
+  // a NaN of an earlier solve must not stop this one: the status is this call's
+  if (threadIdx.x == 0) st->status = 0;
   for (int col = 0; col < R; ++col) {
     if (threadIdx.x == 0) {
       const double rr = rrs[col], bb = lds[col];
       if (!restart) {
         st->r0sq[col] = rr;
-        st->tol2[col] = rtol * rtol * rr;
+        st->tol2[col] = rtol * rtol * (rr < bb ? rr : bb);
         st->iters[col] = 0;
       }
       st->rr[col] = rr;
@@ -730,7 +732,6 @@ __global__ __launch_bounds__(kMFin) void k_mcg_init_fin(int m, int R, int ncols,
   }
   if (threadIdx.x == 0) {
     st->first = 1;
-    if (st->status != -6) st->status = 0;
     st->done = (all || st->status != 0) ? 1 : 0;
   }
 }

@@ -3,8 +3,9 @@
 The oracle builds each problem from the same seeded workload with its own
 assembly, hierarchy and smoother; the GPU path gets its inputs from the
 native generator.  Bars: FP64 operator / transfer applications 1e-13
-relative, Schwarz and V-cycle applications within the block inverses'
-conditioning (tolerance stated per test), PCG solutions to a true relative
+relative, Schwarz and V-cycle applications on load vectors M u within 1e-6 /
+1e-7 in L2(Omega) (random vectors: per-row block-conditioning bounds, and
+1e-10 in the energy norm where every block has kappa <= 1e9), PCG solutions to a true relative
 residual <= 1e-8 and relative L2(Omega) difference <= 1e-6 against the
 oracle's solution, block lists identical (removal decisions whose
 eigenvalue ratio lies within a factor 10 of the threshold may differ).
@@ -90,41 +91,102 @@ def test_level_operators_and_transfers(name, implicit, compress):
     sol.close()
 
 
+EPS = 2.0 ** -52
+
+
+def _removal_band_hit(A, raw):
+    """Replays the tiny-eigenvalue removal on one raw block and says whether
+    some step's ratio lambda_min / max diag lies within a factor 10 of the
+    1e-16 threshold, where any FP64 eigensolver may decide either way."""
+    keep = list(raw)
+    while keep:
+        Aj = A[keep][:, keep].toarray()
+        lam, V = np.linalg.eigh(Aj)
+        ratio = lam[0] / Aj.diagonal().max()
+        if 1e-17 < abs(ratio) < 1e-15:
+            return True
+        if ratio >= 1e-16:
+            return False
+        del keep[int(np.argmax(np.abs(V[:, 0])))]
+    return False
+
+
+def _level_mass(op, l):
+    """Mass matrix of level l: the fine mass matrix restricted by the two-scale
+    relation (the coarse functions are combinations of the fine ones)."""
+    M = op.system.M
+    for ll in range(len(op.hier.A) - 1, l, -1):
+        R = op.hier.R[ll - 1]
+        M = R @ M @ R.T
+    return M
+
+
+def _row_bars(sm, r):
+    """Per-row bound of the rounding of y = sum_j w_j A_j^-1 r_j: a backward
+    stable block inversion has relative error ~ kappa_j eps in A_j^-1, i.e.
+    |dy| <~ w_j (kappa_j + 1) eps / lambda_min,j ||r_j|| on the rows of block
+    j (factor 100 for the eigensolver and the summation)."""
+    bar = np.zeros(len(r))
+    for wj, k, lam in zip(sm.weights(), sm.blocks, sm.lam):
+        if len(k):
+            lmin, lmax = float(np.min(lam)), float(np.max(lam))
+            bar[k] += wj * 100 * EPS * (lmax / lmin + 1.0) / lmin * np.linalg.norm(r[k])
+    return bar
+
+
+def _mnorm_rel(e, ref, M):
+    return math.sqrt(max(e @ (M @ e), 0.0)) / math.sqrt(ref @ (M @ ref))
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_blocks_gamma_and_smoother(name):
+    """Block lists equal the oracle's (a differing list only where the removal
+    replay passes through the ambiguous band around 1e-16), gamma equal, and
+    the smoother application S r equal to the oracle's: row by row within the
+    block-conditioning bound on random r, and in L2(Omega) within 1e-6 on
+    load vectors r = M u of random data (these do not excite the near-null
+    cut modes whose block-inverse components no FP64 route fixes)."""
     S = _gpu()
     w, g, op = _problem(name)
     sol = _solver(S, g)
     rng = np.random.default_rng(8)
     for l in range(1, w.levels):
         sm = op.smoothers[l]
+        A = op.hier.A[l]
         ptr, idx = sol.get_patches(l)
         gblocks = [idx[ptr[j]:ptr[j + 1]] for j in range(len(ptr) - 1)]
         oblocks = [np.asarray(b) for b in sm.blocks]
         assert len(gblocks) == len(oblocks)
         differ = [j for j, (a, b) in enumerate(zip(gblocks, oblocks)) if not np.array_equal(a, b)]
-        # a differing removal must sit in the ambiguous band around the threshold
         for j in differ:
-            lam = sm.lam[j]
-            A = op.hier.A[l]
-            raw = np.asarray(sm.raw_blocks[j])
-            Aj = A[raw][:, raw].toarray()
-            lmin = np.linalg.eigvalsh(Aj)[0] / Aj.diagonal().max()
-            assert 1e-17 < abs(lmin) < 1e-15 or lmin < 1e-15, (name, l, j, lmin)
+            assert j < len(sm.raw_blocks) and _removal_band_hit(A, np.asarray(sm.raw_blocks[j])), (name, l, j)
         assert len(differ) <= max(1, len(oblocks) // 1000)
         assert sol.gamma(l) == pytest.approx(sm.gamma, rel=0, abs=0)
         if differ:
             continue
-        r = rng.standard_normal(op.hier.A[l].shape[0])
+        r = rng.standard_normal(A.shape[0])
         y = sol.apply_smoother(l, _t(r)).cpu().numpy()
         ref = sm.apply(r)
-        kmax = max(float(np.max(lm) / np.min(lm)) if len(lm) else 1.0 for lm in sm.lam)
-        assert _rel(y, ref) < max(1e-12, 1e-16 * kmax * 100), (name, l, kmax)
+        bar = _row_bars(sm, r) + 1e-13 * np.abs(ref) + 1e-300
+        worst = float(np.max(np.abs(y - ref) / bar))
+        assert worst <= 1.0, (name, l, worst)
+        M = _level_mass(op, l)
+        rm = M @ rng.standard_normal(A.shape[0])
+        ym = sol.apply_smoother(l, _t(rm)).cpu().numpy()
+        refm = sm.apply(rm)
+        d = _mnorm_rel(ym - refm, refm, M)
+        print(f"[{name}] level {l}: smoother row err/bar {worst:.2e}, L2 rel on M u {d:.2e}")
+        assert d <= 1e-6, (name, l, d)
     sol.close()
 
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_coarse_solve_and_vcycle(name):
+    """Coarsest solve against the oracle's Cholesky solve (bar from the
+    coarsest matrix's condition number); one V-cycle z = B r against the
+    oracle's: in L2(Omega) within 1e-7 on load vectors r = M u, and, where
+    every block is well conditioned (kappa_j <= 1e9), also on random r in the
+    energy norm within 1e-10."""
     S = _gpu()
     w, g, op = _problem(name)
     sol = _solver(S, g)
@@ -136,24 +198,23 @@ def test_coarse_solve_and_vcycle(name):
     ref0 = sla.cho_solve(sla.cho_factor(A0), r0)
     kappa0 = np.linalg.cond(A0)
     assert _rel(x0, ref0) < max(1e-12, 1e-15 * kappa0)
-    r = rng.standard_normal(op.A.shape[0])
+    A = op.A
+    M = op.system.M
+    r = M @ rng.standard_normal(A.shape[0])
     z = sol.vcycle(_t(r)).cpu().numpy()
     zr = op.vcycle.apply(r)
-    # Block inverses whose smallest eigenvalue sits just above the removal
-    # threshold are only determined to ~kappa_j * eps by any FP64
-    # eigensolver (LAPACK in the oracle, Jacobi on the GPU); the bar scales
-    # with the worst block condition number of the hierarchy.
-    kmax = 1.0
-    for sm in op.smoothers[1:]:
-        for lm in sm.lam:
-            if len(lm):
-                kmax = max(kmax, float(np.max(lm) / np.min(lm)))
-    tol = max(1e-10, 100 * kmax * 1.1e-16)
-    A = op.A
-    e = z - zr
-    rel = math.sqrt(e @ (A @ e)) / math.sqrt(zr @ (A @ zr))
-    print(f"[{name}] vcycle A-norm rel diff {rel:.3e} (max block kappa {kmax:.2e}, bar {tol:.2e})")
-    assert rel <= tol, name
+    d = _mnorm_rel(z - zr, zr, M)
+    kmax = max(float(np.max(lm) / np.min(lm)) for sm in op.smoothers[1:] for lm in sm.lam if len(lm))
+    print(f"[{name}] vcycle L2 rel diff on M u {d:.3e} (max block kappa {kmax:.2e})")
+    assert d <= 1e-7, name
+    if kmax <= 1e9:
+        r = rng.standard_normal(A.shape[0])
+        z = sol.vcycle(_t(r)).cpu().numpy()
+        zr = op.vcycle.apply(r)
+        e = z - zr
+        da = math.sqrt(e @ (A @ e)) / math.sqrt(zr @ (A @ zr))
+        print(f"[{name}] vcycle energy-norm rel diff on random r {da:.3e}")
+        assert da <= 1e-10, name
     sol.close()
 
 
@@ -183,7 +244,10 @@ def test_pcg_solution_matches_oracle(name, form):
     rel_l2 = math.sqrt(e @ (M @ e)) / math.sqrt(xo @ (M @ xo))
     assert rel_l2 <= 1e-6, (name, rel_l2)
     print(f"[{name}/{form}] iterations gpu {info.iterations} oracle {ito}, rel L2 {rel_l2:.2e}")
-    assert abs(info.iterations - ito) <= max(2, ito // 10), (name, info.iterations, ito)
+    # FP64 forms follow the oracle's iteration to rounding: the same count up
+    # to one; FP32 operator values inside the V-cycle may shift it by two
+    assert abs(info.iterations - ito) <= (1 if FORMS[form]["precision"] == 0 else 2), \
+        (name, info.iterations, ito)
     # determinism: a second solve is bitwise identical
     x2 = torch.zeros_like(x)
     sol.pcg(_t(bg), x2, rtol=1e-8)
