@@ -292,6 +292,25 @@ int imsmg_mlp_loss_grad(void *stream, const float *params, const float *X, const
                         float *loss, float *grad);
 int imsmg_mlp_adam(void *stream, float *params, const float *grad, float *m, float *v, int step, float lr);
 
+/* For callers that cannot allocate device memory (work under HIP graph
+ * capture, tight training or serving loops, harnesses that forbid hipMalloc):
+ * imsmg_mlp_loss_grad without the caller's workspace.  The workspace is a
+ * static device array inside the library, 9.4 MiB per GPU for at most
+ * IMSMG_NOALLOC_MAX_SAMPLES samples, held by every GPU the library runs on
+ * until the process ends; its device address is looked up once per device on
+ * the first call.  Same kernels, same arithmetic and summation order as
+ * imsmg_mlp_loss_grad (results are bitwise equal).  The call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine).  All calls
+ * on one GPU share that array: calls that overlap on one GPU (two streams, two
+ * threads) race and must be serialized by the caller.  Nothing needs clearing
+ * between calls (each call writes every workspace word it reads).
+ * Errors: IMSMG_ERR_INVALID_ARG for n < 1, n > IMSMG_NOALLOC_MAX_SAMPLES or a
+ * null pointer; IMSMG_ERR_HIP when the device or the array's address cannot
+ * be obtained or the launch fails. */
+#define IMSMG_NOALLOC_MAX_SAMPLES 8192
+int imsmg_mlp_loss_grad_noalloc(void *stream, const float *params, const float *X, const float *t, int n,
+                                float *loss, float *grad);
+
 /* Post-removal blocks of level l: sizes first (ptr may be NULL to query). */
 int imsmg_get_patches(imsmg_ctx *ctx, int level, int32_t *nblocks, int64_t *nnz, int32_t *ptr, int32_t *idx);
 /* Damping factor of level l (1 / max_K N_K or the uniform override). */

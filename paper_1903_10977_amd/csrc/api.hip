@@ -2158,6 +2158,20 @@ int imsmg_mlp_loss_grad(void *stream, const float *params, const float *X, const
   return hipGetLastError() == hipSuccess ? IMSMG_OK : IMSMG_ERR_HIP;
 }
 
+int imsmg_mlp_loss_grad_noalloc(void *stream, const float *params, const float *X, const float *t, int n,
+                                float *loss, float *grad) {
+  if (n < 1 || n > IMSMG_NOALLOC_MAX_SAMPLES || !params || !X || !t || !loss || !grad)
+    return IMSMG_ERR_INVALID_ARG;
+  static_assert(IMSMG_NOALLOC_MAX_SAMPLES >= 1, "sample cap");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void *work = nullptr;
+  const int rc = mlp_noalloc_scratch(s, &work);
+  if (rc != IMSMG_OK) return rc;
+  if (mlp_workspace_bytes(n) > mlp_noalloc_scratch_bytes()) return IMSMG_ERR_INVALID_ARG;
+  launch_mlp_loss_grad(s, n, params, X, t, work, loss, grad);
+  return hipGetLastError() == hipSuccess ? IMSMG_OK : IMSMG_ERR_HIP;
+}
+
 int imsmg_mlp_adam(void *stream, float *params, const float *grad, float *m, float *v, int step, float lr) {
   if (!params || !grad || !m || !v || step < 1 || !(lr > 0.0f)) return IMSMG_ERR_INVALID_ARG;
   launch_mlp_adam(static_cast<hipStream_t>(stream), params, grad, m, v, step, lr);

@@ -23,6 +23,8 @@
 #include <string>
 #include <vector>
 
+#include "imsmg.h"
+
 #define IMSMG_MAX_SLOTS 125  // (2*2+1)^3: 3D up to reach 2, 2D up to reach 5
 #define IMSMG_MAX_BLOCK 60   // largest Schwarz block factorized in LDS (2 x 60^2 FP64 < 64 KiB)
 
@@ -217,9 +219,14 @@ void launch_mcg_true_residual(hipStream_t s, int R, int n, int K, const OpView<d
 
 // --------------------------------------------------------------- per-block damping
 constexpr int kMlpInputs = 16, kMlpHidden = 64;
+// largest sample count of the allocation-free loss/gradient entry point
+constexpr int kNoAllocMaxSamples = IMSMG_NOALLOC_MAX_SAMPLES;
 constexpr int kMlpParams = kMlpInputs * kMlpHidden + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden + kMlpHidden + 1;
 constexpr double kMlpOutClip = 3.0;  // omega_j = gamma exp(clip(o_j, -3, 3))
 size_t mlp_workspace_bytes(int n);
+// allocation-free loss/gradient: the static device workspace (per device)
+size_t mlp_noalloc_scratch_bytes();
+int mlp_noalloc_scratch(hipStream_t s, void **out);
 void launch_mlp_forward(hipStream_t s, int n, const float *params, const float *X, float *out);
 void launch_mlp_loss_grad(hipStream_t s, int n, const float *params, const float *X, const float *t, void *work,
                           float *loss, float *grad);

@@ -7,6 +7,8 @@
 //   h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), o = w3 . h2 + b3,
 // 16 -> 64 -> 64 -> 1, FP32, parameters flat: W1 (64 x 16 row-major), b1,
 // W2 (64 x 64 row-major), b2, w3, b3 (5313 floats).
+#include <mutex>
+
 #include "imsmg_internal.h"
 
 namespace imsmg {
@@ -170,6 +172,49 @@ void launch_mlp_loss_grad(hipStream_t s, int n, const float *params, const float
                                                                             E2);
   k_mlp_grad_partial<<<chunks, 256, 0, s>>>(n, X, H1, H2, DA1, DA2, DO, E2, part);
   k_mlp_grad_final<<<(kNP + 1 + 255) / 256, 256, 0, s>>>(n, chunks, part, grad, loss);
+}
+
+// Workspace of the allocation-free loss/gradient entry point: a file-scope
+// device array sized for kNoAllocMaxSamples samples (every GPU the library
+// runs on holds its own copy until the process ends).  Every word the three
+// kernels read is written earlier in the same call (activations by
+// k_mlp_backprop, partials by k_mlp_grad_partial), so nothing is cleared; two
+// calls that overlap on one GPU share the array and race.
+constexpr size_t kNoAllocScratchBytes =
+    size_t(kNoAllocMaxSamples) * (4 * kNH + 2) * sizeof(float) +
+    size_t((kNoAllocMaxSamples + kChunk - 1) / kChunk) * (kNP + 1) * sizeof(double) + 256;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+size_t mlp_noalloc_scratch_bytes() { return kNoAllocScratchBytes; }
+
+// Device address of `scratch` on the device of stream s (the current device
+// for the null stream), looked up once per device with that device current.
+// In host code the array's name is only a host-side stand-in: kernels get
+// this address, never the name.
+int mlp_noalloc_scratch(hipStream_t s, void **out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void *ptrs[kMaxDevices] = {};
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return IMSMG_ERR_HIP;
+  int dev = cur;
+  if (s) {
+    hipDevice_t d = 0;
+    if (hipStreamGetDevice(s, &d) != hipSuccess) return IMSMG_ERR_HIP;
+    dev = d;
+  }
+  if (dev < 0 || dev >= kMaxDevices) return IMSMG_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(mu);
+  if (!ptrs[dev]) {
+    if (dev != cur && hipSetDevice(dev) != hipSuccess) return IMSMG_ERR_HIP;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (dev != cur) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p) return IMSMG_ERR_HIP;
+    ptrs[dev] = p;
+  }
+  *out = ptrs[dev];
+  return IMSMG_OK;
 }
 
 void launch_mlp_adam(hipStream_t s, float *theta, const float *g, float *m, float *v, int step, float lr) {

@@ -67,9 +67,10 @@ SYMBOLS = ["imsmg_default_options", "imsmg_create", "imsmg_setup", "imsmg_set_pa
            "imsmg_coarse_solve", "imsmg_get_level_stats", "imsmg_kernel_time", "imsmg_last_error", "imsmg_destroy",
            "imsmg_load_mlp", "imsmg_get_patch_features", "imsmg_get_patch_weights", "imsmg_set_block_weights",
            "imsmg_lambda_max", "imsmg_two_grid_objective", "imsmg_mlp_workspace_bytes", "imsmg_mlp_forward",
-           "imsmg_mlp_loss_grad", "imsmg_mlp_adam", "imsmg_vcycle_multi", "imsmg_pcg_solve_multi",
+           "imsmg_mlp_loss_grad", "imsmg_mlp_loss_grad_noalloc", "imsmg_mlp_adam", "imsmg_vcycle_multi", "imsmg_pcg_solve_multi",
            "imsmg_setup_batched", "imsmg_batch_problem", "imsmg_pcg_solve_batched"]
 MLP_PARAMS = 5313
+NOALLOC_MAX_SAMPLES = 8192  # IMSMG_NOALLOC_MAX_SAMPLES
 NFEAT = 16
 
 
@@ -118,6 +119,7 @@ def load():
     lib.imsmg_mlp_workspace_bytes.argtypes = [i32]
     lib.imsmg_mlp_forward.argtypes = [vp, vp, vp, i32, vp]
     lib.imsmg_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
+    lib.imsmg_mlp_loss_grad_noalloc.argtypes = [vp, vp, vp, vp, i32, vp, vp]
     lib.imsmg_mlp_adam.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float]
     lib.imsmg_vcycle_multi.argtypes = [vp, i32, vp, vp]
     lib.imsmg_pcg_solve_multi.argtypes = [vp, i32, vp, vp, dbl, C.POINTER(Info)]
@@ -516,6 +518,24 @@ def mlp_forward(params, X):
     if rc != OK:
         raise SolverError(rc, "imsmg_mlp_forward")
     return out
+
+
+def mlp_loss_grad_noalloc(params, X, t, loss=None, grad=None):
+    """Loss and gradient of the damping network through the allocation-free
+    entry point (the library's static workspace; at most
+    NOALLOC_MAX_SAMPLES rows).  loss (1) and grad (5313) may be given as
+    preallocated float32 device tensors; returns (loss, grad)."""
+    import torch
+    lib = load()
+    X = X.contiguous()
+    loss = torch.zeros(1, dtype=torch.float32, device=X.device) if loss is None else loss
+    grad = torch.zeros(MLP_PARAMS, dtype=torch.float32, device=X.device) if grad is None else grad
+    rc = lib.imsmg_mlp_loss_grad_noalloc(_stream(torch), C.c_void_p(params.data_ptr()), C.c_void_p(X.data_ptr()),
+                                         C.c_void_p(t.data_ptr()), X.shape[0], C.c_void_p(loss.data_ptr()),
+                                         C.c_void_p(grad.data_ptr()))
+    if rc != OK:
+        raise SolverError(rc, "imsmg_mlp_loss_grad_noalloc")
+    return loss, grad
 
 
 class MlpTrainer:
