@@ -13,7 +13,10 @@ Readings:
   approximation, r_in - A x (the algorithm's second update read literally
   would subtract the pre-smoothed part twice);
 * nu smoothing steps before and after (the paper uses one; the 1024^2
-  cubic benchmark asks for two): each step is x += S (r_in - A x);
+  cubic benchmark asks for two): each step is x += S (r_in - A x), with the
+  smoother's pre-smoothing operator before and its adjoint after the coarse
+  correction (additive Schwarz: the same symmetric operator; multiplicative
+  Schwarz: the forward colour sweep before, the reversed one after);
 * the coarsest "direct solve" is a dense Cholesky solve;
 * the V-cycle is used as the preconditioner of CG (the paragraph after the
   algorithm), with x_0 = 0 and the stopping test ||r_k|| <= tol min(||r_0||,
@@ -36,12 +39,19 @@ import scipy.linalg as sla
 
 
 class VCycle:
-    def __init__(self, A_list, R_list, smoothers, nu_pre=1, nu_post=1):
+    """cycle = 1: the V-cycle of Algorithm alg:MGV; cycle = 2: the W-cycle
+    (the paragraph after the algorithm names W- and FMG-cycles as other
+    multigrid cycles): on every level above level 1 the coarse correction is
+    computed by two consecutive coarse cycles, the second on the residual the
+    first leaves (level 1's coarse problem is solved directly, once)."""
+
+    def __init__(self, A_list, R_list, smoothers, nu_pre=1, nu_post=1, cycle=1):
         self.A = A_list
         self.R = R_list
         self.S = smoothers          # index 0 (coarsest) unused
         self.nu_pre = nu_pre
         self.nu_post = nu_post
+        self.cycle = cycle
         A1 = A_list[0].toarray()
         self.coarse_chol = sla.cho_factor(A1, lower=True)
 
@@ -52,15 +62,18 @@ class VCycle:
             return sla.cho_solve(self.coarse_chol, r)
         A = self.A[level]
         S = self.S[level]
-        x = S.apply(r)
+        x = S.pre(r)
         for _ in range(self.nu_pre - 1):
-            x = x + S.apply(r - A @ x)
+            x = x + S.pre(r - A @ x)
         rh = r - A @ x
         rc = self.R[level - 1] @ rh
         xc = self.apply(rc, level - 1)
+        if level - 1 > 0:
+            for _ in range(self.cycle - 1):
+                xc = xc + self.apply(rc - self.A[level - 1] @ xc, level - 1)
         x = x + self.R[level - 1].T @ xc
         for _ in range(self.nu_post):
-            x = x + S.apply(r - A @ x)
+            x = x + S.post(r - A @ x)
         return x
 
     def dense(self, level: int = None) -> np.ndarray:

@@ -1,4 +1,4 @@
-"""Additive Schwarz smoother (oracle; test infrastructure only).
+"""Schwarz smoothers (oracle; test infrastructure only).
 
 Smoothers subsection, "Additive Schwarz":
 * M^{-1} = sum_j P_j (P_j^T A P_j)^{-1} P_j^T over N index blocks;
@@ -134,6 +134,14 @@ class Smoother:
             return np.full(len(self.blocks), self.gamma)
         return np.asarray(self.omega, dtype=np.float64)
 
+    def pre(self, r: np.ndarray) -> np.ndarray:
+        """Pre-smoothing operator; additive Schwarz is symmetric, so the
+        post-smoothing operator (its adjoint) is the same."""
+        return self.apply(r)
+
+    def post(self, r: np.ndarray) -> np.ndarray:
+        return self.apply(r)
+
     def apply(self, r: np.ndarray) -> np.ndarray:
         """y = sum_j w_j P_j A_j^{-1} P_j^T r (w_j = gamma unless weights given)."""
         y = np.zeros_like(r)
@@ -149,6 +157,129 @@ class Smoother:
             if len(k):
                 S[np.ix_(k, k)] += wj * inv
         return S
+
+
+def block_elements(lev, blocks):
+    """Active elements touched by each block: the union of E(k) over its
+    members (two blocks interact through A only if these sets meet)."""
+    E = func_elements(lev)
+    return [frozenset().union(*[E[int(k)] for k in blk]) if len(blk) else frozenset() for blk in blocks]
+
+
+def lattice_colour(lev, L, kind="schwarz"):
+    """Colour of a block associated with the lattice function L, from its
+    position (multiplicative Schwarz subsection: same-colour blocks must not
+    share an element; (p+1)^d colours for B-splines, 2^d for Lagrange vertex
+    blocks; the Gauss-Seidel footnote: (p+1)^d for single functions).
+    Reading: B-splines and single-function blocks take sum_a (m_a mod (p+1))
+    (p+1)^a; Lagrange vertex blocks (m_a = p v_a) take sum_a (v_a mod 2) 2^a."""
+    m = lev.lat_to_multi(int(L))
+    if kind == "schwarz" and lev.basis == "lagrange":
+        q, pos = 2, [mi // lev.p for mi in m]
+    else:
+        q, pos = lev.p + 1, list(m)
+    c = 0
+    for a in reversed(range(lev.dim)):
+        c = c * q + pos[a] % q
+    return c
+
+
+def colour_blocks(lev, blocks, given):
+    """Colours of the final blocks: given[j] (an int) where known, else the
+    smallest colour >= the number of lattice colours that no block already
+    coloured (in block order) uses on a shared element.  Raises if two
+    same-colour given blocks share an element."""
+    els = block_elements(lev, blocks)
+    base = (lev.p + 1) ** lev.dim   # above every lattice colour (2^d <= (p+1)^d)
+    used = {}
+    colours = []
+    for j, es in enumerate(els):
+        if given[j] is not None:
+            c = int(given[j])
+            for e in es:
+                if c in used.get(e, ()):
+                    raise ValueError(f"blocks of colour {c} share element {e}")
+        else:
+            taken = set()
+            for e in es:
+                taken |= used.get(e, set())
+            c = base
+            while c in taken:
+                c += 1
+        for e in es:
+            used.setdefault(e, set()).add(c)
+        colours.append(c)
+    return colours
+
+
+class MultiplicativeSmoother(Smoother):
+    """Multiplicative Schwarz (eq:multiplicativeSchwarz1) with the graph
+    colouring of the same subsection: the blocks are visited colour by colour
+    and the residual is updated after every block,
+        dy = P_j A_j^{-1} P_j^T r~,  y~ += dy,  r~ -= A dy,
+    which equals the colour-wise form because blocks of one colour share no
+    element (their updates do not change each other's residual).  No damping
+    (unconditionally stable, as Gauss-Seidel).  The forward sweep visits the
+    colours in ascending order (pre-smoothing); its adjoint visits them in
+    descending order (post-smoothing), which keeps the V-cycle symmetric.
+    kind = "schwarz": the encapsulating-support blocks; kind = "diagonal": one
+    block per function (Gauss-Seidel, Remark rem:coarseGS)."""
+
+    def __init__(self, A, lev, kind="schwarz"):
+        if kind == "diagonal":
+            blocks = [np.array([i], dtype=np.int64) for i in range(A.shape[0])]
+            assoc = list(range(A.shape[0]))
+        else:
+            blocks, assoc = select_blocks(lev)
+        super().__init__(A, lev, blocks=blocks)
+        self.assoc = assoc
+        self.A = A
+        given = [lattice_colour(lev, lev.active[a], kind) for a in assoc]
+        given += [None] * (len(self.blocks) - len(given))   # singletons added for uncovered DOFs
+        self.colours = colour_blocks(lev, self.blocks, given)
+        self.order = sorted(range(len(self.blocks)), key=lambda j: (self.colours[j], j))
+        # per block: the rows its update reaches (A[:, k] non-zero) and A[rows, k]
+        Ac = A.tocsc()
+        self._reach = []
+        for k in self.blocks:
+            sub = Ac[:, k]
+            rows = np.unique(sub.indices)
+            self._reach.append((rows, sub[rows].toarray()))
+
+    def _sweep(self, r, order):
+        y = np.zeros_like(r)
+        rt = r.copy()
+        for j in order:
+            k, inv = self.blocks[j], self.inv[j]
+            if not len(k):
+                continue
+            dy = inv @ rt[k]
+            y[k] += dy
+            rows, Ark = self._reach[j]
+            rt[rows] -= Ark @ dy
+        return y
+
+    def forward(self, r):
+        return self._sweep(r, self.order)
+
+    def backward(self, r):
+        return self._sweep(r, self.order[::-1])
+
+    pre = forward
+    post = backward
+
+    def apply(self, r):
+        return self.forward(r)
+
+
+class DiagonalSmoother(Smoother):
+    """Damped Jacobi as additive Schwarz with one block per function (Remark
+    rem:coarseGS: diagonal smoothing suffices on the coarser levels); the
+    damping follows the additive rule gamma = 1 / max_K N_K."""
+
+    def __init__(self, A, lev):
+        blocks = [np.array([i], dtype=np.int64) for i in range(A.shape[0])]
+        super().__init__(A, lev, blocks=blocks)
 
 
 def max_NK(lev, blocks) -> int:

@@ -83,6 +83,10 @@ class Workload:
         boundary with parameter beta = penalty_factor / h, no strong BCs).
     rhs: "one" (f = 1), "manufactured" (u* = prod sin(2 pi x_i), f = -lap u*,
          Neumann data grad u* . n on the immersed boundary), "zero".
+    smoother: "as" (additive Schwarz) or "ms" (multiplicative Schwarz with
+         colouring) on the finest level; coarse_smoother: "same" (the finest
+         level's smoother on every level), "jacobi" or "gs" (one block per
+         function on the coarser levels); cycle: 1 (V) or 2 (W).
     """
     name: str
     dim: int
@@ -101,6 +105,9 @@ class Workload:
     box_lo: float = 0.0
     box_hi: float = 1.0
     penalty_factor: float = 2.0
+    smoother: str = "as"
+    coarse_smoother: str = "same"
+    cycle: int = 1
 
     def to_json(self) -> str:
         return json.dumps(asdict(self), sort_keys=True)
