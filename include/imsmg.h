@@ -68,11 +68,21 @@ typedef struct {
 } imsmg_csr;
 
 /* Schwarz index blocks of one level (host arrays): block j is
- * idx[ptr[j] .. ptr[j+1]), sorted compact indices. */
+ * idx[ptr[j] .. ptr[j+1]), sorted compact indices.
+ * colour (optional, may be NULL): colour of every block in [0, 4096) for the
+ * multiplicative smoother (smoothers subsection, "Multiplicative Schwarz":
+ * blocks of one colour must not share an element, so they are applied
+ * together and the residual is updated once per colour).  Setup checks, on
+ * the element incidence, that no two blocks of one colour share an active
+ * element (IMSMG_ERR_INVALID_ARG otherwise).  NULL: blocks are coloured
+ * greedily in block order (smallest colour unused on their elements).
+ * Singleton blocks that the factorization adds for DOFs left in no block take
+ * the smallest colour >= max(colour) + 1 unused on their elements. */
 typedef struct {
   int32_t nblocks;
   const int32_t *ptr;
   const int32_t *idx;
+  const int32_t *colour;
 } imsmg_patches;
 
 /* Element incidence of one level (host arrays, optional): for every active
@@ -141,7 +151,24 @@ typedef struct {
                           0: beta_k = r_{k+1}.z_{k+1} / (r_k.z_k) (default).  The two agree in
                           exact arithmetic for the fixed SPD V-cycle.  The multi-column and
                           batched solves use 0 and reject 1 */
+  int32_t smoother;    /* finest level: IMSMG_ADDITIVE (default; additive Schwarz damped by gamma or
+                          the block weights) or IMSMG_MULTIPLICATIVE (multiplicative Schwarz,
+                          eq:multiplicativeSchwarz1, colour by colour: forward colour order before
+                          the coarse correction, reversed after it; undamped).  With blocks of one
+                          function each (passed by the caller) these are Jacobi and Gauss-Seidel */
+  int32_t coarse_smoother; /* the levels between the finest and the coarsest: -1 (default) as
+                          `smoother`, else IMSMG_ADDITIVE or IMSMG_MULTIPLICATIVE.  Remark
+                          rem:coarseGS: diagonal smoothers suffice there (pass one-function blocks
+                          for those levels).  The multi-column and batched solves, per-block
+                          weights and use_learned need the additive smoother on every level */
+  int32_t cycle;       /* 1: V-cycle (Algorithm alg:MGV, default); 2: W-cycle (two coarse cycles
+                          on every level above level 1, the second on the residual of the first) */
+  int32_t flag_min_rows; /* levels with at least this many rows read the solve's convergence flag
+                          in every kernel (skip the tail of a graph replay after convergence);
+                          smaller levels do not (one dependent load less); default 65536 */
 } imsmg_options;
+
+enum { IMSMG_ADDITIVE = 0, IMSMG_MULTIPLICATIVE = 1 };
 
 typedef struct {
   int32_t status;        /* IMSMG_OK or an error code */
@@ -149,6 +176,11 @@ typedef struct {
   double rel_res;        /* ||r_k|| / ||r_0|| (recursive residual) */
   double true_rel_res;   /* ||b - A x|| / ||b|| recomputed at the end */
   double solve_ms;       /* wall time of the call */
+  int32_t restarts;      /* CG restarts after a true-residual check above rtol */
+  int32_t fallback_flags;/* bit l: level l kept gamma although use_learned asked for the network
+                            (stability check or cost judge rejected its weights) */
+  double setup_ms;       /* wall time of the last imsmg_setup on this context */
+  double factor_ms;      /* wall time of the last imsmg_factor_patches */
 } imsmg_info;
 
 /* Fills opt with the defaults (FP64, V(1,1), max_iter 500, check_every 4, graph on, compress on). */
@@ -313,6 +345,11 @@ int imsmg_mlp_loss_grad_noalloc(void *stream, const float *params, const float *
 
 /* Post-removal blocks of level l: sizes first (ptr may be NULL to query). */
 int imsmg_get_patches(imsmg_ctx *ctx, int level, int32_t *nblocks, int64_t *nnz, int32_t *ptr, int32_t *idx);
+/* Colours of the post-removal blocks of level l (multiplicative Schwarz,
+ * smoothers subsection): ncolours = number of colours, colour[nblocks] (may
+ * be NULL to query); the order of imsmg_get_patches.  Defined on every
+ * smoothed level (the additive smoother ignores them). */
+int imsmg_get_patch_colours(imsmg_ctx *ctx, int level, int32_t *ncolours, int32_t *colour);
 /* Damping factor of level l (1 / max_K N_K or the uniform override). */
 int imsmg_get_gamma(imsmg_ctx *ctx, int level, double *gamma);
 

@@ -88,6 +88,13 @@ int imsmg_gen_get_restriction(const imsmg_gen_problem *p, int level, int32_t *ro
 int imsmg_gen_get_two_scale(const imsmg_gen_problem *p, int level, double *R1);
 /* blocks: ptr[nblocks+1], idx[block_nnz] (sorted compact indices), assoc[nblocks] */
 int imsmg_gen_get_blocks(const imsmg_gen_problem *p, int level, int32_t *ptr, int32_t *idx, int32_t *assoc);
+/* Colours for the multiplicative smoother (smoothers subsection: blocks of one
+ * colour share no element).  kind 0: one per Schwarz block (nblocks; B-splines
+ * (p+1)^d colours from the associated function's lattice position mod p+1,
+ * Lagrange vertex blocks 2^d colours from the vertex position mod 2); kind 1:
+ * one per active function (n_active) for one-function blocks (Gauss-Seidel,
+ * (p+1)^d colours). */
+int imsmg_gen_get_block_colours(const imsmg_gen_problem *p, int level, int kind, int32_t *colour);
 /* active elements in ascending element index: eptr[n_active_elements+1],
  * eidx[elem_nnz] = compact indices of the active functions non-zero on the
  * element (x offset fastest), elem[n_active_elements] = element index */

@@ -142,6 +142,26 @@ struct Level {
   double *b_diag = nullptr, *b_wfold = nullptr;
   // coarsest level
   double *Ainv = nullptr;
+  // colours of the final blocks (multiplicative smoother; every smoothed level)
+  std::vector<int32_t> in_colour;  // given colour of every input block (empty: none given)
+  std::vector<int32_t> f_colour;   // colour of every final block
+  int ncolours = 0;
+  // multiplicative smoother on this level: per colour c the rows its blocks
+  // touch, ms_rows[ms_cptr[c] .. ms_cptr[c+1]) with ms_cf (1 / A_ii for
+  // one-function blocks, 0 for members of larger blocks), and the larger
+  // blocks' inverses as CSR on their members
+  bool ms = false;
+  std::vector<int32_t> ms_cptr;
+  int32_t *ms_rows = nullptr;
+  double *ms_cf = nullptr;
+  struct MsGeneral {
+    int ng = 0;
+    int32_t *grow_lat = nullptr, *sptr = nullptr, *scol = nullptr;
+    double *sval = nullptr;
+  };
+  std::vector<MsGeneral> ms_gen;
+  // W-cycle work vectors (cycle >= 2): saved correction and residual
+  double *w_x = nullptr, *w_r = nullptr;
 };
 
 }  // namespace
@@ -227,6 +247,20 @@ void lat_multi(int64_t L, const int *shape, int dim, int *m) {
 }
 
 // ------------------------------------------------------------------ setup
+// colours of the multiplicative smoother: at most this many per level
+constexpr int kMaxColours = 128;
+
+// Level l (1 .. nlevels-1) uses the multiplicative smoother?
+bool level_ms(const imsmg_options &o, int l, int nlevels) {
+  const int kind = (l == nlevels - 1 || o.coarse_smoother < 0) ? o.smoother : o.coarse_smoother;
+  return l >= 1 && kind == IMSMG_MULTIPLICATIVE;
+}
+bool uses_ms(const imsmg_options &o, int nlevels) {
+  for (int l = 1; l < nlevels; ++l)
+    if (level_ms(o, l, nlevels)) return true;
+  return false;
+}
+
 void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice &lat) {
   hipStream_t s = c->stream;
   if (lat.dim < 2 || lat.dim > 3) bad("lattice dim must be 2 or 3");
@@ -446,6 +480,16 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
   L.x = vs[1];
   L.x2 = vs[2];
   L.rh = vs[3];
+  if (c->opt.cycle >= 2) {
+    double *w[2];
+    for (int k = 0; k < 2; ++k) {
+      double *b = dalloc<double>(c->owned, vlen);
+      HIP_CHECK_RET(hipMemsetAsync(b, 0, vlen * sizeof(double), s));
+      w[k] = b + L.guard;
+    }
+    L.w_x = w[0];
+    L.w_r = w[1];
+  }
   // a V-cycle on this level runs (nu_pre - 1) + nu_post ping-pong steps: start
   // in the buffer that makes the result land in x
   L.xs = ((c->opt.nu_pre - 1 + c->opt.nu_post) % 2) ? L.x2 : L.x;
@@ -649,12 +693,15 @@ hipEvent_t *timed_pair(imsmg_ctx *c) {
 
 bool mixed(imsmg_ctx *c) { return c->opt.precision == IMSMG_MIXED; }
 
-// Levels below this many rows are launch-latency bound: their kernels skip
-// the convergence-flag load, which would add one dependent memory round trip
-// to every launch (the wasted work after convergence is negligible there).
+// Levels below opt.flag_min_rows rows (default 65536) are launch-latency
+// bound: their kernels skip the convergence-flag load, which would add one
+// dependent memory round trip to every launch (the wasted work after
+// convergence is negligible there).
 constexpr int kSmallLevel = 65536;
 
-const int32_t *flag_for(const Level &L, const int32_t *done) { return L.n >= kSmallLevel ? done : nullptr; }
+const int32_t *flag_for(const imsmg_ctx *c, const Level &L, const int32_t *done) {
+  return L.n >= c->opt.flag_min_rows ? done : nullptr;
+}
 
 // y = b - A_l x (b == nullptr: y = A_l x); the V-cycle operator precision
 void residual(imsmg_ctx *c, Level &L, const double *x, const double *b, double *y, const int32_t *done,
@@ -708,17 +755,71 @@ void prolong_add(imsmg_ctx *c, Level &L, Level &Cl, const double *xc, double *xf
     launch_ell_gather(c->stream, L.n, L.tw, L.row_lat, L.tcol, L.tval, xc, xf, 1, nullptr, nullptr, done);
 }
 
+// One multiplicative Schwarz sweep on level L (eq:multiplicativeSchwarz1,
+// coloured): colours in ascending order (forward, pre-smoothing) or
+// descending (its adjoint, post-smoothing); x is updated in place from the
+// residual r - A x of level L's input residual r.
+void ms_sweep(imsmg_ctx *c, Level &L, bool forward, const int32_t *done) {
+  for (int k = 0; k < L.ncolours; ++k) {
+    const int cc = forward ? k : L.ncolours - 1 - k;
+    const int a = L.ms_cptr[cc], m = L.ms_cptr[cc + 1] - a;
+    if (m == 0) continue;
+    if (mixed(c))
+      launch_ms_colour(c->stream, m, L.ms_rows + a, L.ms_cf + a, L.K, L.op32, L.row_lat, L.meta, L.r, L.x, L.rh,
+                       done);
+    else
+      launch_ms_colour(c->stream, m, L.ms_rows + a, L.ms_cf + a, L.K, L.op64, L.row_lat, L.meta, L.r, L.x, L.rh,
+                       done);
+    const Level::MsGeneral &G = L.ms_gen[cc];
+    if (G.ng > 0) launch_smooth_general(c->stream, G.ng, G.grow_lat, G.sptr, G.scol, G.sval, L.rh, L.x, done, 4);
+  }
+}
+
+void vcycle_level(imsmg_ctx *c, int l, const int32_t *done_top, bool timing);
+
+// Coarse correction of level l > 0: Cl.x = B_{l-1} Cl.r by one coarse cycle
+// (V), or by two where level l-1 has its own coarse level (W: the second
+// cycle on the residual the first leaves, its result added to the first).
+void coarse_correction(imsmg_ctx *c, int l, const int32_t *done_top, bool timing) {
+  Level &Cl = c->lv[l - 1];
+  vcycle_level(c, l - 1, done_top, timing);
+  if (c->opt.cycle < 2 || l - 1 == 0) return;
+  const int32_t *dn = flag_for(c, Cl, done_top);
+  for (int k = 1; k < c->opt.cycle; ++k) {
+    launch_rows_op(c->stream, Cl.n, Cl.row_lat, Cl.x, Cl.w_x, 1, dn);  // w_x = x
+    residual(c, Cl, Cl.x, Cl.r, Cl.w_r, dn, false);                     // w_r = r - A x
+    std::swap(Cl.r, Cl.w_r);  // the next cycle's input residual (swapped back below)
+    if (!Cl.ms) launch_diag_scale(c->stream, Cl.n, Cl.row_lat, Cl.c, Cl.r, Cl.xs, dn);
+    vcycle_level(c, l - 1, done_top, timing);
+    std::swap(Cl.r, Cl.w_r);
+    launch_rows_op(c->stream, Cl.n, Cl.row_lat, Cl.w_x, Cl.x, 2, dn);  // x += w_x
+  }
+}
+
 // V-cycle on level l (Algorithm alg:MGV): input residual in lv[l].r; on entry
 // lv[l].xs already holds c * r (trivial part of the first smoothing step,
-// written by the caller's fused kernel); the correction is left in lv[l].x.
+// written by the caller's fused kernel) on additive levels; the correction is
+// left in lv[l].x.
 void vcycle_level(imsmg_ctx *c, int l, const int32_t *done_top, bool timing) {
   Level &L = c->lv[l];
-  const int32_t *done = flag_for(L, done_top);
+  const int32_t *done = flag_for(c, L, done_top);
   if (l == 0) {
     launch_dense_gemv(c->stream, L.n, L.row_lat, L.Ainv, L.r, L.x, done);
     return;
   }
   Level &Cl = c->lv[l - 1];
+  if (L.ms) {
+    // multiplicative smoother: x = 0, nu_pre forward sweeps, coarse
+    // correction, nu_post reversed sweeps (symmetric cycle)
+    launch_rows_op(c->stream, L.n, L.row_lat, nullptr, L.x, 0, done);
+    for (int k = 0; k < c->opt.nu_pre; ++k) ms_sweep(c, L, true, done);
+    residual(c, L, L.x, L.r, L.rh, done, false);
+    restrict_to(c, L, Cl, L.rh, Cl.r, (l - 1 > 0 && !Cl.ms) ? Cl.xs : nullptr, flag_for(c, Cl, done_top));
+    coarse_correction(c, l, done_top, timing);
+    prolong_add(c, L, Cl, Cl.x, L.x, done);
+    for (int k = 0; k < c->opt.nu_post; ++k) ms_sweep(c, L, false, done);
+    return;
+  }
   const bool fine = (l == int(c->lv.size()) - 1) && timing;
   // first smoothing step from x = 0: x = S r (general rows)
   launch_smooth_general(c->stream, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, L.r, L.xs, done, L.gen_lanes);
@@ -728,8 +829,8 @@ void vcycle_level(imsmg_ctx *c, int l, const int32_t *done_top, bool timing) {
     std::swap(xa, xb);
   }
   residual(c, L, xa, L.r, L.rh, done, false);
-  restrict_to(c, L, Cl, L.rh, Cl.r, l - 1 > 0 ? Cl.xs : nullptr, flag_for(Cl, done_top));
-  vcycle_level(c, l - 1, done_top, timing);
+  restrict_to(c, L, Cl, L.rh, Cl.r, (l - 1 > 0 && !Cl.ms) ? Cl.xs : nullptr, flag_for(c, Cl, done_top));
+  coarse_correction(c, l, done_top, timing);
   int k = 0;
   if (L.pro_ok && c->opt.nu_post > 0) {
     // x += R^T x_c inside the first post-smoothing step's staging (not one of
@@ -759,6 +860,147 @@ void collect_timing(imsmg_ctx *c) {
 
 // ------------------------------------------------------------- factorization
 void apply_weights(imsmg_ctx *c, Level &L, const std::vector<double> &w);
+
+// Colours of the final blocks (fptr/fidx; forig = input block or -1 for an
+// added singleton).  Blocks interact only through elements they share (A_ij
+// vanishes unless phi_i and phi_j share an active element), so a colouring is
+// valid when no two blocks of one colour touch a common element.  Given
+// colours are checked; blocks without one (no colours given, or added
+// singletons) take, in block order, the smallest colour >= base that no
+// already coloured block uses on their elements (base = 0 without given
+// colours, else max given + 1).
+void colour_level(Level &L, const std::vector<int32_t> &fptr, const std::vector<int32_t> &fidx,
+                  const std::vector<int32_t> &forig) {
+  const int nbf = int(fptr.size()) - 1;
+  L.f_colour.assign(nbf, 0);
+  L.ncolours = 0;
+  if (L.e_ptr.empty()) return;  // without the element incidence there is nothing to colour by
+  const int nel = int(L.e_ptr.size()) - 1;
+  // function -> elements
+  std::vector<int32_t> fe_ptr(L.n + 1, 0), fe_idx(L.e_idx.size());
+  for (int32_t f : L.e_idx) fe_ptr[f + 1]++;
+  for (int i = 0; i < L.n; ++i) fe_ptr[i + 1] += fe_ptr[i];
+  {
+    std::vector<int32_t> fill(fe_ptr.begin(), fe_ptr.end() - 1);
+    for (int e = 0; e < nel; ++e)
+      for (int k = L.e_ptr[e]; k < L.e_ptr[e + 1]; ++k) fe_idx[fill[L.e_idx[k]]++] = e;
+  }
+  const bool given = !L.in_colour.empty();
+  int base = 0;
+  if (given)
+    for (int32_t v : L.in_colour) base = std::max(base, v + 1);
+  std::vector<uint64_t> used(size_t(nel) * 2, 0);
+  std::vector<int32_t> stamp(nel, -1), els;
+  for (int j = 0; j < nbf; ++j) {
+    els.clear();
+    for (int k = fptr[j]; k < fptr[j + 1]; ++k) {
+      const int i = fidx[k];
+      for (int q = fe_ptr[i]; q < fe_ptr[i + 1]; ++q) {
+        const int e = fe_idx[q];
+        if (stamp[e] != j) {
+          stamp[e] = j;
+          els.push_back(e);
+        }
+      }
+    }
+    int col;
+    if (given && forig[j] >= 0) {
+      col = L.in_colour[forig[j]];
+      for (int e : els)
+        if ((used[2 * size_t(e) + (col >> 6)] >> (col & 63)) & 1)
+          bad("blocks of colour " + std::to_string(col) + " share an element");
+    } else {
+      uint64_t taken[2] = {0, 0};
+      for (int e : els) {
+        taken[0] |= used[2 * size_t(e)];
+        taken[1] |= used[2 * size_t(e) + 1];
+      }
+      col = base;
+      while (col < kMaxColours && ((taken[col >> 6] >> (col & 63)) & 1)) ++col;
+      if (col >= kMaxColours) bad("more than " + std::to_string(kMaxColours) + " colours needed");
+    }
+    for (int e : els) used[2 * size_t(e) + (col >> 6)] |= uint64_t(1) << (col & 63);
+    L.f_colour[j] = col;
+    L.ncolours = std::max(L.ncolours, col + 1);
+  }
+}
+
+// Device data of the multiplicative smoother (after the block inverses exist,
+// unscaled): per colour the touched rows with their coefficients and the
+// larger blocks' inverses as CSR on their members (row a of block j = row a
+// of A_j^-1, columns at the members' lattice positions).
+void build_ms(imsmg_ctx *c, Level &L, const std::vector<int32_t> &fptr, const std::vector<int32_t> &fidx,
+              const std::vector<int64_t> &finvoff, const std::vector<double> &diag, int64_t ninv) {
+  hipStream_t s = c->stream;
+  const int nbf = int(fptr.size()) - 1;
+  const int C = L.ncolours;
+  if (C == 0 && nbf > 0) bad("the multiplicative smoother needs the element incidence of the level (colours)");
+  std::vector<double> inv(size_t(std::max<int64_t>(ninv, 1)));
+  if (ninv > 0) d2h(s, inv.data(), L.inv, size_t(ninv));
+  HIP_CHECK_RET(hipStreamSynchronize(s));
+  std::vector<std::vector<int32_t>> rows(C);
+  std::vector<std::vector<double>> cf(C);
+  struct Csr {
+    std::vector<int32_t> glat, ptr{0}, col;
+    std::vector<double> val;
+  };
+  std::vector<Csr> gen(C);
+  for (int j = 0; j < nbf; ++j) {
+    const int sz = fptr[j + 1] - fptr[j];
+    if (sz == 0) continue;
+    const int cc = L.f_colour[j];
+    if (sz == 1) {
+      const int i = fidx[fptr[j]];
+      if (!(diag[i] > 0.0)) bad("non-positive diagonal entry", IMSMG_ERR_NOT_SPD);
+      rows[cc].push_back(i);
+      cf[cc].push_back(1.0 / diag[i]);
+      continue;
+    }
+    if (finvoff[j] < 0) bad("internal: block without an inverse", IMSMG_ERR_HIP);
+    Csr &G = gen[cc];
+    for (int a = 0; a < sz; ++a) {
+      const int i = fidx[fptr[j] + a];
+      rows[cc].push_back(i);
+      cf[cc].push_back(0.0);
+      G.glat.push_back(L.h_row_lat[i]);
+      for (int b = 0; b < sz; ++b) {
+        G.col.push_back(L.h_row_lat[fidx[fptr[j] + b]]);
+        G.val.push_back(inv[size_t(finvoff[j]) + size_t(a) + size_t(sz) * b]);
+      }
+      G.ptr.push_back(int32_t(G.col.size()));
+    }
+  }
+  L.ms_cptr.assign(1, 0);
+  std::vector<int32_t> all_rows;
+  std::vector<double> all_cf;
+  for (int cc = 0; cc < C; ++cc) {
+    all_rows.insert(all_rows.end(), rows[cc].begin(), rows[cc].end());
+    all_cf.insert(all_cf.end(), cf[cc].begin(), cf[cc].end());
+    L.ms_cptr.push_back(int32_t(all_rows.size()));
+  }
+  L.ms_rows = dalloc<int32_t>(c->factor_owned, std::max<size_t>(all_rows.size(), 1));
+  L.ms_cf = dalloc<double>(c->factor_owned, std::max<size_t>(all_cf.size(), 1));
+  if (!all_rows.empty()) {
+    h2d(s, L.ms_rows, all_rows.data(), all_rows.size());
+    h2d(s, L.ms_cf, all_cf.data(), all_cf.size());
+  }
+  L.ms_gen.assign(C, Level::MsGeneral{});
+  for (int cc = 0; cc < C; ++cc) {
+    const Csr &G = gen[cc];
+    Level::MsGeneral &D = L.ms_gen[cc];
+    D.ng = int(G.glat.size());
+    if (D.ng == 0) continue;
+    D.grow_lat = dalloc<int32_t>(c->factor_owned, G.glat.size());
+    D.sptr = dalloc<int32_t>(c->factor_owned, G.ptr.size());
+    D.scol = dalloc<int32_t>(c->factor_owned, G.col.size());
+    D.sval = dalloc<double>(c->factor_owned, G.val.size());
+    h2d(s, D.grow_lat, G.glat.data(), G.glat.size());
+    h2d(s, D.sptr, G.ptr.data(), G.ptr.size());
+    h2d(s, D.scol, G.col.data(), G.col.size());
+    h2d(s, D.sval, G.val.data(), G.val.size());
+  }
+  HIP_CHECK_RET(hipStreamSynchronize(s));
+}
 
 void factor_level(imsmg_ctx *c, int l) {
   hipStream_t s = c->stream;
@@ -916,8 +1158,10 @@ void factor_level(imsmg_ctx *c, int l) {
     L.nk = nk;
   }
   L.gamma = gamma;
-  // per final block weight
-  std::vector<double> w(nbf, gamma);
+  // colours of the final blocks (multiplicative smoother)
+  colour_level(L, fptr, fidx, forig);
+  // per final block weight (the multiplicative smoother is undamped)
+  std::vector<double> w(nbf, L.ms ? 1.0 : gamma);
   if (!L.omega.empty())
     for (int j = 0; j < nbf; ++j)
       if (forig[j] >= 0) w[j] = L.omega[forig[j]];
@@ -1052,7 +1296,7 @@ void factor_level(imsmg_ctx *c, int l) {
     L.h_meta[grows[t]] |= kMetaGeneral;
   }
   L.ng = ngr;
-  L.small = L.n < kSmallLevel;
+  L.small = L.n < c->opt.flag_min_rows;
   L.grow_lat = dalloc<int32_t>(c->factor_owned, std::max(ngr, 1));
   L.sptr = dalloc<int32_t>(c->factor_owned, sp.size());
   L.scol = dalloc<int32_t>(c->factor_owned, std::max<size_t>(scol.size(), 1));
@@ -1140,6 +1384,7 @@ void factor_level(imsmg_ctx *c, int l) {
   L.learned_status = 0;
   L.lambda_max = 0.0;
   apply_weights(c, L, w);
+  if (L.ms) build_ms(c, L, fptr, fidx, finvoff, diag, extra_off);
 }
 
 // Folds per-final-block weights w into the smoother: rescales the stored
@@ -1609,7 +1854,7 @@ void m_vcycle_level(imsmg_ctx *c, int l, const int32_t *done_top) {
   auto &m = c->mb;
   const int R = m.R;
   hipStream_t s = c->stream;
-  const int32_t *done = flag_for(L, done_top);
+  const int32_t *done = flag_for(c, L, done_top);
   if (l == 0) {
     launch_m_dense_gemm(s, R, L.n, L.row_lat, L.Ainv, m.r[0], m.x[0], done);
     return;
@@ -1627,7 +1872,7 @@ void m_vcycle_level(imsmg_ctx *c, int l, const int32_t *done_top) {
     launch_m_residual(s, R, L.n, L.K, L.op64, L.row_lat, L.meta, xa, m.r[l], m.rh[l], done);
   const double *ci = l - 1 > 0 ? Cl.c : nullptr;
   double *xinit = l - 1 > 0 ? m.xs[l - 1] : nullptr;
-  const int32_t *cdone = flag_for(Cl, done_top);
+  const int32_t *cdone = flag_for(c, Cl, done_top);
   if (L.tensor)
     launch_m_tensor_transfer(s, R, L.dim, Cl.n, Cl.row_lat, Cl.shape[0], Cl.shape[1], L.rb_start, L.rb_len,
                              L.rb_coef, L.rbW, L.shape[0], L.shape[1], m.rh[l], m.r[l - 1], 0, ci, xinit, cdone);
@@ -1691,6 +1936,10 @@ void imsmg_default_options(imsmg_options *o) {
   o->timing = 0;
   o->gamma = 0.0;
   o->compress = 1;
+  o->smoother = IMSMG_ADDITIVE;
+  o->coarse_smoother = -1;
+  o->cycle = 1;
+  o->flag_min_rows = kSmallLevel;
 }
 
 int imsmg_create(imsmg_ctx **out, int device, void *stream) {
@@ -1742,6 +1991,11 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
     if (c->opt.block_gemm < 0 || c->opt.block_gemm > 2) bad("block_gemm must be 0, 1 or 2");
     if (c->opt.timing < 0 || c->opt.timing > 64) bad("timing must be 0 .. 64");
     if (c->opt.flexible_cg != 0 && c->opt.flexible_cg != 1) bad("flexible_cg must be 0 or 1");
+    if (c->opt.smoother != IMSMG_ADDITIVE && c->opt.smoother != IMSMG_MULTIPLICATIVE) bad("unknown smoother");
+    if (c->opt.coarse_smoother < -1 || c->opt.coarse_smoother > IMSMG_MULTIPLICATIVE) bad("unknown coarse_smoother");
+    if (c->opt.cycle != 1 && c->opt.cycle != 2) bad("cycle must be 1 (V) or 2 (W)");
+    if (c->opt.flag_min_rows < 0) bad("flag_min_rows must be >= 0");
+    if (c->opt.use_learned && uses_ms(c->opt, nlevels)) bad("use_learned needs the additive smoother on every level");
     c->lv.resize(nlevels);
     for (int l = 0; l < nlevels; ++l) {
       if (Lt[l].dim != Lt[nlevels - 1].dim) bad("all levels must share the dimension");
@@ -1757,6 +2011,13 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
       for (int j = 0; j < p.nblocks; ++j)
         if (L.in_ptr[j + 1] < L.in_ptr[j]) bad("patch ptr must be non-decreasing");
       L.in_idx.assign(p.idx, p.idx + L.in_ptr[p.nblocks]);
+      L.in_colour.clear();
+      if (p.colour) {
+        L.in_colour.assign(p.colour, p.colour + p.nblocks);
+        for (int32_t v : L.in_colour)
+          if (v < 0 || v >= kMaxColours) bad("block colours must lie in [0, " + std::to_string(kMaxColours) + ")");
+      }
+      L.ms = level_ms(c->opt, l, nlevels);
       for (int j = 0; j < p.nblocks; ++j)
         for (int k = L.in_ptr[j]; k < L.in_ptr[j + 1]; ++k) {
           if (L.in_idx[k] < 0 || L.in_idx[k] >= L.n) bad("patch index out of range");
@@ -1818,6 +2079,7 @@ int imsmg_set_patch_weights(imsmg_ctx *c, int level, const double *omega) {
     if (!c->ready) bad("setup first", IMSMG_ERR_STATE);
     if (level < 1 || level >= int(c->lv.size()) || !omega) bad("bad level or null weights");
     Level &L = c->lv[level];
+    if (L.ms) bad("per-block weights apply to the additive smoother only");
     const int nb = int(L.in_ptr.size()) - 1;
     for (int j = 0; j < nb; ++j)
       if (!(omega[j] > 0.0) || !std::isfinite(omega[j])) bad("weights must be positive and finite");
@@ -1861,6 +2123,17 @@ int imsmg_get_patches(imsmg_ctx *c, int level, int32_t *nblocks, int64_t *nnz, i
     if (nnz) *nnz = int64_t(L.f_idx.size());
     if (ptr) std::copy(L.f_ptr.begin(), L.f_ptr.end(), ptr);
     if (idx) std::copy(L.f_idx.begin(), L.f_idx.end(), idx);
+    return IMSMG_OK;
+  });
+}
+
+int imsmg_get_patch_colours(imsmg_ctx *c, int level, int32_t *ncolours, int32_t *colour) {
+  return guarded(c, [&]() -> int {
+    if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    if (level < 1 || level >= int(c->lv.size())) bad("bad level");
+    const Level &L = c->lv[level];
+    if (ncolours) *ncolours = L.ncolours;
+    if (colour) std::copy(L.f_colour.begin(), L.f_colour.end(), colour);
     return IMSMG_OK;
   });
 }
@@ -1982,6 +2255,16 @@ int imsmg_apply_smoother(imsmg_ctx *c, int level, const double *r, double *y) {
     if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
     if (level < 1 || level >= int(c->lv.size()) || !r || !y) bad("bad level or vector");
     Level &L = c->lv[level];
+    if (L.ms) {
+      // multiplicative: one forward sweep from x = 0 on the residual r
+      launch_scatter(c->stream, L.n, L.row_lat, r, L.r);
+      launch_rows_op(c->stream, L.n, L.row_lat, nullptr, L.x, 0, c->zero_flag);
+      ms_sweep(c, L, true, c->zero_flag);
+      launch_gather(c->stream, L.n, L.row_lat, L.x, y);
+      HIP_CHECK_RET(hipGetLastError());
+      HIP_CHECK_RET(hipStreamSynchronize(c->stream));
+      return IMSMG_OK;
+    }
     launch_scatter(c->stream, L.n, L.row_lat, r, L.rh);
     launch_diag_scale(c->stream, L.n, L.row_lat, L.c, L.rh, L.x, c->zero_flag);
     launch_smooth_general(c->stream, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, L.rh, L.x, c->zero_flag, L.gen_lanes);
@@ -2076,6 +2359,7 @@ int imsmg_set_block_weights(imsmg_ctx *c, int level, const double *omega) {
     if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
     if (level < 1 || level >= int(c->lv.size()) || !omega) bad("bad level or null weights");
     Level &L = c->lv[level];
+    if (L.ms) bad("per-block weights apply to the additive smoother only");
     const int nbf = int(L.f_ptr.size()) - 1;
     std::vector<double> w(omega, omega + nbf);
     for (double v : w)
@@ -2181,6 +2465,8 @@ int imsmg_mlp_adam(void *stream, float *params, const float *grad, float *m, flo
 int imsmg_vcycle_multi(imsmg_ctx *c, int nrhs, const double *R_dev, double *Z_dev) {
   return guarded(c, [&]() -> int {
     if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    if (uses_ms(c->opt, int(c->lv.size())) || c->opt.cycle != 1)
+      bad("the multi-column solve runs the additive V-cycle only");
     if (!R_dev || !Z_dev) bad("null vector");
     const int R = rhs_width(nrhs);
     ensure_multi(c, R);
@@ -2204,6 +2490,8 @@ int imsmg_pcg_solve_multi(imsmg_ctx *c, int nrhs, const double *B_dev, double *X
     if (!B_dev || !X_dev) bad("null vector");
     if (!(rtol > 0.0)) bad("rtol must be positive");
     if (c->opt.flexible_cg) bad("flexible_cg applies to imsmg_pcg_solve only");
+    if (uses_ms(c->opt, int(c->lv.size())) || c->opt.cycle != 1)
+      bad("the multi-column solve runs the additive V-cycle only");
     const int R = rhs_width(nrhs);
     auto t0 = std::chrono::steady_clock::now();
     ensure_multi(c, R);

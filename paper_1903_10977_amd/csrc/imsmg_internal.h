@@ -141,6 +141,17 @@ void launch_tensor_transfer(hipStream_t s, int dim, int n, const int32_t *row_la
 void launch_dense_gemv(hipStream_t s, int n, const int32_t *row_lat, const double *Ainv, const double *r, double *x,
                        const int32_t *done);
 void launch_scatter(hipStream_t s, int n, const int32_t *row_lat, const double *src, double *dst);
+// multiplicative Schwarz: one colour's rows (residual of the current x; in-place
+// update of one-function blocks with cf != 0, residual into rh for the others)
+void launch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, int K, const OpView<double> &op,
+                      const int32_t *row_lat, const uint32_t *meta, const double *r, double *x, double *rh,
+                      const int32_t *done);
+void launch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, int K, const OpView<float> &op,
+                      const int32_t *row_lat, const uint32_t *meta, const double *r, double *x, double *rh,
+                      const int32_t *done);
+// active rows of a level vector: op 0: y = 0, 1: y = x, 2: y += x
+void launch_rows_op(hipStream_t s, int n, const int32_t *row_lat, const double *x, double *y, int op,
+                    const int32_t *done);
 void launch_gather(hipStream_t s, int n, const int32_t *row_lat, const double *src, double *dst);
 
 // --------------------------------------------------------------- CG kernels

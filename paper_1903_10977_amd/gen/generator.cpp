@@ -1347,6 +1347,36 @@ int imsmg_gen_get_blocks(const imsmg_gen_problem *p, int level, int32_t *ptr, in
   return 0;
 }
 
+// Colours for the multiplicative smoother from the lattice position m of a
+// block's associated function: blocks of one colour share no element.
+// B-splines and one-function blocks: sum_a (m_a mod (p+1)) (p+1)^a (function
+// m is non-zero on elements m-p .. m per axis, so equal residues mod p+1 are
+// at least p+1 apart); Lagrange vertex blocks (m_a = p v_a, elements
+// v_a - 1 .. v_a): sum_a (v_a mod 2) 2^a.
+int imsmg_gen_get_block_colours(const imsmg_gen_problem *p, int level, int kind, int32_t *colour) {
+  if (!p || !colour || level < 0 || level >= int(p->P.lv.size()) || (kind != 0 && kind != 1)) {
+    g_err = "bad block colour arguments";
+    return -1;
+  }
+  const LevelData &L = p->P.lv[level];
+  const imsmg_gen_spec &sp = p->P.spec;
+  const int d = sp.dim, deg = sp.degree;
+  const bool lagrange_blocks = kind == 0 && sp.basis == IMSMG_GEN_LAGRANGE;
+  const int q = lagrange_blocks ? 2 : deg + 1;
+  auto colour_of = [&](int32_t j) {
+    int m[3] = {0, 0, 0};
+    lat_multi(L.c2lat[size_t(j)], L.nf1, d, m);
+    int c = 0;
+    for (int a = d - 1; a >= 0; --a) c = c * q + (lagrange_blocks ? m[a] / deg : m[a]) % q;
+    return int32_t(c);
+  };
+  if (kind == 0)
+    for (size_t b = 0; b < L.bassoc.size(); ++b) colour[b] = colour_of(L.bassoc[b]);
+  else
+    for (size_t j = 0; j < L.c2lat.size(); ++j) colour[j] = colour_of(int32_t(j));
+  return 0;
+}
+
 int imsmg_gen_get_elements(const imsmg_gen_problem *p, int level, int32_t *eptr, int32_t *eidx, int32_t *elem) {
   if (!p || level < 0 || level >= int(p->P.lv.size())) { g_err = "bad level"; return -1; }
   const LevelData &L = p->P.lv[level];

@@ -35,6 +35,7 @@ def _load():
     lib.imsmg_gen_get_operator.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.imsmg_gen_get_restriction.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.imsmg_gen_get_blocks.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.imsmg_gen_get_block_colours.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p]
     lib.imsmg_gen_get_two_scale.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
     lib.imsmg_gen_get_rhs.argtypes = [C.c_void_p, C.c_void_p]
     lib.imsmg_gen_get_elements.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -92,6 +93,7 @@ class GenLevel:
     elem_idx: Optional[np.ndarray] = None
     elem_id: Optional[np.ndarray] = None   # element index of each active element
     two_scale: Optional[np.ndarray] = None  # 1D factor of R (coarser 1D functions x these)
+    block_colour: Optional[np.ndarray] = None  # colour of every block (multiplicative smoother)
 
     @property
     def n(self):
@@ -159,12 +161,22 @@ def generate(w, with_mass: bool = False, nthreads: int = 0, orders=None) -> Gene
                 R = sp.csr_matrix((rval, rcol, rrp), shape=(nc, n))
                 R1 = np.zeros((levels[l - 1].lattice[0], info.lattice[0]), dtype=np.float64)
                 assert lib.imsmg_gen_get_two_scale(h, l, _ptr(R1)) == 0
-            bp = bi = ba = None
-            if info.nblocks > 0:
+            bp = bi = ba = bc = None
+            diagonal = 0 < l < w.levels - 1 and getattr(w, "coarse_smoother", "same") in ("jacobi", "gs")
+            if diagonal:
+                # one block per function on the coarser levels (Remark rem:coarseGS)
+                bp = np.arange(n + 1, dtype=np.int32)
+                bi = np.arange(n, dtype=np.int32)
+                ba = np.arange(n, dtype=np.int32)
+                bc = np.zeros(n, dtype=np.int32)
+                assert lib.imsmg_gen_get_block_colours(h, l, 1, _ptr(bc)) == 0
+            elif info.nblocks > 0:
                 bp = np.zeros(info.nblocks + 1, dtype=np.int32)
                 bi = np.zeros(info.block_nnz, dtype=np.int32)
                 ba = np.zeros(info.nblocks, dtype=np.int32)
                 assert lib.imsmg_gen_get_blocks(h, l, _ptr(bp), _ptr(bi), _ptr(ba)) == 0
+                bc = np.zeros(info.nblocks, dtype=np.int32)
+                assert lib.imsmg_gen_get_block_colours(h, l, 0, _ptr(bc)) == 0
             eta = np.zeros(info.n_elements ** w.dim, dtype=np.float64)
             assert lib.imsmg_gen_get_volume_fractions(h, l, _ptr(eta)) == 0
             ep = np.zeros(info.n_active_elements + 1, dtype=np.int32)
@@ -175,7 +187,7 @@ def generate(w, with_mass: bool = False, nthreads: int = 0, orders=None) -> Gene
                                    dof_to_lattice=d2l, A=A, R=R, block_ptr=bp, block_idx=bi,
                                    block_assoc=ba, n_cut=info.n_cut, eta_min=info.eta_min, eta=eta,
                                    elem_ptr=ep, elem_idx=ei, elem_id=eid,
-                                   two_scale=R1 if l > 0 else None))
+                                   two_scale=R1 if l > 0 else None, block_colour=bc))
         nf = levels[-1].n
         b = np.zeros(nf, dtype=np.float64)
         lib.imsmg_gen_get_rhs(h, _ptr(b))

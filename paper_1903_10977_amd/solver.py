@@ -20,6 +20,7 @@ from . import LIB_DIR
 OK = 0
 ERR = {-1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "NOT_SPD", -5: "NOT_CONVERGED", -6: "NAN", -7: "STATE"}
 FP64, MIXED = 0, 1
+ADDITIVE, MULTIPLICATIVE = 0, 1
 
 _lib = None
 
@@ -30,7 +31,7 @@ class Csr(C.Structure):
 
 
 class Patches(C.Structure):
-    _fields_ = [("nblocks", C.c_int32), ("ptr", C.c_void_p), ("idx", C.c_void_p)]
+    _fields_ = [("nblocks", C.c_int32), ("ptr", C.c_void_p), ("idx", C.c_void_p), ("colour", C.c_void_p)]
 
 
 class Elements(C.Structure):
@@ -47,12 +48,14 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("max_iter", C.c_int32),
                 ("check_every", C.c_int32), ("use_graph", C.c_int32), ("timing", C.c_int32), ("gamma", C.c_double),
                 ("compress", C.c_int32), ("use_learned", C.c_int32), ("autotune", C.c_int32),
-                ("block_gemm", C.c_int32), ("flexible_cg", C.c_int32)]
+                ("block_gemm", C.c_int32), ("flexible_cg", C.c_int32), ("smoother", C.c_int32),
+                ("coarse_smoother", C.c_int32), ("cycle", C.c_int32), ("flag_min_rows", C.c_int32)]
 
 
 class Info(C.Structure):
     _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("rel_res", C.c_double),
-                ("true_rel_res", C.c_double), ("solve_ms", C.c_double)]
+                ("true_rel_res", C.c_double), ("solve_ms", C.c_double), ("restarts", C.c_int32),
+                ("fallback_flags", C.c_int32), ("setup_ms", C.c_double), ("factor_ms", C.c_double)]
 
 
 class LevelStats(C.Structure):
@@ -62,7 +65,7 @@ class LevelStats(C.Structure):
 
 
 SYMBOLS = ["imsmg_default_options", "imsmg_create", "imsmg_setup", "imsmg_set_patch_weights",
-           "imsmg_factor_patches", "imsmg_get_patches", "imsmg_get_gamma", "imsmg_vcycle", "imsmg_pcg_solve",
+           "imsmg_factor_patches", "imsmg_get_patches", "imsmg_get_patch_colours", "imsmg_get_gamma", "imsmg_vcycle", "imsmg_pcg_solve",
            "imsmg_apply_operator", "imsmg_apply_smoother", "imsmg_apply_restriction", "imsmg_apply_prolongation",
            "imsmg_coarse_solve", "imsmg_get_level_stats", "imsmg_kernel_time", "imsmg_last_error", "imsmg_destroy",
            "imsmg_load_mlp", "imsmg_get_patch_features", "imsmg_get_patch_weights", "imsmg_set_block_weights",
@@ -99,6 +102,7 @@ def load():
     lib.imsmg_factor_patches.argtypes = [vp]
     lib.imsmg_get_patches.argtypes = [vp, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int64), vp, vp]
     lib.imsmg_get_gamma.argtypes = [vp, i32, C.POINTER(C.c_double)]
+    lib.imsmg_get_patch_colours.argtypes = [vp, i32, C.POINTER(C.c_int32), vp]
     lib.imsmg_vcycle.argtypes = [vp, vp, vp]
     lib.imsmg_pcg_solve.argtypes = [vp, vp, vp, dbl, C.POINTER(Info)]
     for f in ("imsmg_apply_operator", "imsmg_apply_smoother", "imsmg_apply_restriction", "imsmg_apply_prolongation"):
@@ -151,6 +155,15 @@ class SolverError(RuntimeError):
         self.code = code
 
 
+def smoother_options(w) -> dict:
+    """Options naming a workload's smoothers and cycle (the blocks of coarse
+    diagonal smoothing come from the generator)."""
+    fine = MULTIPLICATIVE if getattr(w, "smoother", "as") == "ms" else ADDITIVE
+    cs = getattr(w, "coarse_smoother", "same")
+    coarse = -1 if cs == "same" else (MULTIPLICATIVE if cs == "gs" else ADDITIVE)
+    return dict(smoother=fine, coarse_smoother=coarse, cycle=getattr(w, "cycle", 1))
+
+
 def default_options(**kw) -> Options:
     lib = load()
     o = Options()
@@ -169,6 +182,15 @@ class SolveInfo:
     rel_res: float
     true_rel_res: float
     solve_ms: float
+    restarts: int = 0
+    fallback_flags: int = 0
+    setup_ms: float = 0.0
+    factor_ms: float = 0.0
+
+    @staticmethod
+    def of(i):
+        return SolveInfo(i.status, i.iterations, i.rel_res, i.true_rel_res, i.solve_ms, i.restarts,
+                         i.fallback_flags, i.setup_ms, i.factor_ms)
 
 
 def problem_structs(problem, dim: int = None, reach: int = None, implicit_transfer=True):
@@ -204,7 +226,11 @@ def problem_structs(problem, dim: int = None, reach: int = None, implicit_transf
             R[l] = Csr(Rm.shape[0], Rm.shape[1], Rm.nnz, _p(rrp).value, _p(rci).value, _p(rva).value)
             bp, bi = _i32(lev.block_ptr), _i32(lev.block_idx)
             keep += [bp, bi]
-            P[l] = Patches(len(bp) - 1, _p(bp).value, _p(bi).value)
+            bc = None
+            if getattr(lev, "block_colour", None) is not None:
+                bc = _i32(lev.block_colour)
+                keep.append(bc)
+            P[l] = Patches(len(bp) - 1, _p(bp).value, _p(bi).value, _p(bc).value if bc is not None else None)
         if lev.elem_ptr is not None:
             ep, ei = _i32(lev.elem_ptr), _i32(lev.elem_idx)
             keep += [ep, ei]
@@ -279,6 +305,15 @@ class Solver:
         self._check(self.lib.imsmg_get_patches(self.h, level, C.byref(nb), C.byref(nnz), _p(ptr), _p(idx)))
         return ptr, idx
 
+    def get_patch_colours(self, level: int):
+        """(number of colours, colour of every post-removal block)."""
+        nb = C.c_int32()
+        self._check(self.lib.imsmg_get_patches(self.h, level, C.byref(nb), None, None, None))
+        nc = C.c_int32()
+        col = np.zeros(nb.value, np.int32)
+        self._check(self.lib.imsmg_get_patch_colours(self.h, level, C.byref(nc), _p(col)))
+        return nc.value, col
+
     # ------------------------------------------------- per-block damping
     def load_mlp(self, params):
         th = np.ascontiguousarray(params, dtype=np.float32)
@@ -351,7 +386,7 @@ class Solver:
         rc = self.lib.imsmg_pcg_solve(self.h, self._dev(b), self._dev(x), rtol, C.byref(info))
         if rc != OK and raise_on_error:
             self._check(rc)
-        return SolveInfo(info.status, info.iterations, info.rel_res, info.true_rel_res, info.solve_ms)
+        return SolveInfo.of(info)
 
     def _devm(self, t):
         torch = self.torch
@@ -377,7 +412,7 @@ class Solver:
         rc = self.lib.imsmg_pcg_solve_multi(self.h, k, self._devm(Bm), self._devm(Xm), rtol, infos)
         if rc != OK and raise_on_error:
             self._check(rc)
-        return [SolveInfo(i.status, i.iterations, i.rel_res, i.true_rel_res, i.solve_ms) for i in infos]
+        return [SolveInfo.of(i) for i in infos]
 
     def apply_operator(self, level, x, y=None):
         y = self.empty(level) if y is None else y
@@ -487,7 +522,7 @@ class BatchContext:
         rc = self.lib.imsmg_pcg_solve_batched(self.h, nrhs, bp, xp, rtol, infos, nthreads)
         if rc != OK and raise_on_error:
             self._check(rc)
-        return [[SolveInfo(i.status, i.iterations, i.rel_res, i.true_rel_res, i.solve_ms)
+        return [[SolveInfo.of(i)
                  for i in infos[p * nrhs:(p + 1) * nrhs]] for p in range(k)]
 
     def close(self):
