@@ -134,6 +134,14 @@ def tensor_eval(lev: Level, e, pts):
     return V, Gr
 
 
+def _stiffness(vw, Gr):
+    """K_ab = sum_q vw_q grad phi_a(x_q) . grad phi_b(x_q), as one matrix
+    product over the (point, direction) pairs."""
+    a, nq, d = Gr.shape
+    G = Gr.reshape(a, nq * d)
+    return (G * np.repeat(vw, d)) @ G.T
+
+
 def manufactured(pts):
     """u* = prod_a sin(2 pi x_a); returns (u*, f = -lap u*, grad u*)."""
     d = pts.shape[1]
@@ -183,8 +191,8 @@ def assemble(w, leaf, n, depth, orders=None, with_rhs=True) -> System:
         bnd_meas[el] = float(bw.sum())
         omega += float(vw.sum())
         V, Gr = tensor_eval(lev, e, vp)
-        K = np.einsum("q,aqc,bqc->ab", vw, Gr, Gr)
-        Ml = np.einsum("q,aq,bq->ab", vw, V, V)
+        K = _stiffness(vw, Gr)
+        Ml = (V * vw) @ V.T
         fb = np.zeros(len(fl))
         if with_rhs:
             if w.rhs == "one":
@@ -246,7 +254,7 @@ def assemble_rows(w, leaf, n, depth, rows_lattice, orders=None):
         fl = lev.elem_funcs[el]
         vp, vw, bp, bw, bn = Q.element_quadrature(leaf, e, depth, lev.lo, lev.h, qc, qs, qb)
         V, Gr = tensor_eval(lev, e, vp)
-        K = np.einsum("q,aqc,bqc->ab", vw, Gr, Gr)
+        K = _stiffness(vw, Gr)
         fb = np.zeros(len(fl))
         if w.rhs == "one":
             fb += V @ vw

@@ -25,27 +25,35 @@ the same readings in its own code):
 """
 from __future__ import annotations
 
+import functools
 import itertools
 
 import numpy as np
 
 
-def gauss01(q: int):
-    """Gauss-Legendre nodes and weights on [0, 1]."""
+@functools.lru_cache(maxsize=None)
+def _gauss01(q: int):
     x, w = np.polynomial.legendre.leggauss(q)
-    return 0.5 * (x + 1.0), 0.5 * w
+    x, w = 0.5 * (x + 1.0), 0.5 * w
+    x.flags.writeable = False
+    w.flags.writeable = False
+    return x, w
+
+
+def gauss01(q: int):
+    """Gauss-Legendre nodes and weights on [0, 1] (read-only arrays)."""
+    return _gauss01(q)
 
 
 def tensor_rule(lo: np.ndarray, hi: np.ndarray, q: int):
     """Tensor Gauss rule on the box [lo, hi] (d = len(lo))."""
     x, w = gauss01(q)
     d = len(lo)
-    pts = []
-    wts = []
-    for idx in itertools.product(range(q), repeat=d):
-        pts.append([lo[a] + (hi[a] - lo[a]) * x[idx[a]] for a in range(d)])
-        wts.append(np.prod([w[i] for i in idx]) * np.prod(hi - lo))
-    return np.array(pts), np.array(wts)
+    # all index tuples at once, the first axis slowest (itertools.product order)
+    idx = np.array(list(itertools.product(range(q), repeat=d)))
+    pts = lo[None, :] + (hi - lo)[None, :] * x[idx]
+    wts = np.prod(w[idx], axis=1) * np.prod(hi - lo)
+    return pts, wts
 
 
 def triangle_rule(P: np.ndarray, q: int):
@@ -69,15 +77,14 @@ def tet_rule(P: np.ndarray, q: int):
     zeta = u v w, Jacobian u^2 v."""
     x, w = gauss01(q)
     J = abs(np.linalg.det(np.stack([P[1] - P[0], P[2] - P[1], P[3] - P[2]], axis=1)))
-    pts, wts = [], []
-    for i in range(q):
-        for j in range(q):
-            for k in range(q):
-                u, v, s = x[i], x[j], x[k]
-                xi, eta, zeta = u, u * v, u * v * s
-                pts.append(P[0] + xi * (P[1] - P[0]) + eta * (P[2] - P[1]) + zeta * (P[3] - P[2]))
-                wts.append(w[i] * w[j] * w[k] * u * u * v * J)
-    return np.array(pts), np.array(wts)
+    # all (i, j, k) at once, i slowest: the same products in the same order
+    u, v, s = (a.reshape(-1) for a in np.meshgrid(x, x, x, indexing="ij"))
+    wi, wj, wk = (a.reshape(-1) for a in np.meshgrid(w, w, w, indexing="ij"))
+    xi, eta, zeta = u, u * v, u * v * s
+    pts = (P[0] + xi[:, None] * (P[1] - P[0]) + eta[:, None] * (P[2] - P[1])
+           + zeta[:, None] * (P[3] - P[2]))
+    wts = wi * wj * wk * u * u * v * J
+    return pts, wts
 
 
 def segment_rule(A: np.ndarray, B: np.ndarray, q: int):
@@ -91,13 +98,11 @@ def surface_triangle_rule(P: np.ndarray, q: int):
     """Collapsed Gauss rule on a triangle embedded in 3D (area measure)."""
     x, w = gauss01(q)
     area2 = np.linalg.norm(np.cross(P[1] - P[0], P[2] - P[1]))
-    pts, wts = [], []
-    for i in range(q):
-        for j in range(q):
-            u, v = x[i], x[j]
-            pts.append(P[0] + u * (P[1] - P[0]) + u * v * (P[2] - P[1]))
-            wts.append(w[i] * w[j] * u * area2)
-    return np.array(pts), np.array(wts)
+    u, v = (a.reshape(-1) for a in np.meshgrid(x, x, indexing="ij"))
+    wi, wj = (a.reshape(-1) for a in np.meshgrid(w, w, indexing="ij"))
+    pts = P[0] + u[:, None] * (P[1] - P[0]) + (u * v)[:, None] * (P[2] - P[1])
+    wts = wi * wj * u * area2
+    return pts, wts
 
 
 def _cross(a, b, fa, fb):
