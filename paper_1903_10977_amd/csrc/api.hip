@@ -435,9 +435,10 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
     L.op64.ntiles = L.op32.ntiles = int(ntiles);
     HIP_CHECK_RET(hipStreamSynchronize(s));
   }
-  std::vector<double> cv(size_t(L.K) * std::max(nv, 1), 0.0);
+  // stored rows' values in 16-byte slot groups (SlotGroup): FP64 pairs, FP32 quadruples
+  std::vector<double> cv(std::max<size_t>(stored_size(L.K, size_t(nv), 2), 2), 0.0);
   for (int g = 0; g < nv; ++g)
-    for (int sl = 0; sl < L.K; ++sl) cv[size_t(sl) * nv + g] = ell[size_t(sl) * L.n + ord[g]];
+    for (int sl = 0; sl < L.K; ++sl) cv[stored_at<double>(size_t(nv), size_t(g), sl)] = ell[size_t(sl) * L.n + ord[g]];
   L.meta = dalloc<uint32_t>(c->owned, L.n);
   h2d(s, L.meta, L.h_meta.data(), L.n);
   double *cv64 = dalloc<double>(c->owned, cv.size());
@@ -463,7 +464,10 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
     HIP_CHECK_RET(hipStreamSynchronize(s));
   }
   if (c->opt.precision == IMSMG_MIXED) {
-    std::vector<float> c32(cv.begin(), cv.end());
+    std::vector<float> c32(std::max<size_t>(stored_size(L.K, size_t(nv), 4), 4), 0.0f);
+    for (int g = 0; g < nv; ++g)
+      for (int sl = 0; sl < L.K; ++sl)
+        c32[stored_at<float>(size_t(nv), size_t(g), sl)] = float(cv[stored_at<double>(size_t(nv), size_t(g), sl)]);
     float *cv32 = dalloc<float>(c->owned, c32.size());
     h2d(s, cv32, c32.data(), c32.size());
     L.op32.val = cv32;

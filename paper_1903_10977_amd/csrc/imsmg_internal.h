@@ -56,6 +56,23 @@ struct OpView {
   int ntx, nty, ntiles;    // lattice tiles along x, along y, in total
 };
 
+// Stored-row values: the K slots of a row in groups of 16 bytes (G = 2 FP64 or
+// 4 FP32 values), group-major over the stored rows: value (g, s) sits at
+// ((s / G) nv + g) G + s % G.  A lane reads one group of its row with one
+// 16-byte load and consecutive lanes read consecutive groups (a wavefront's
+// load is one contiguous kilobyte), so a row costs ceil(K / G) vector loads
+// instead of K.  Padding slots of the last group hold zeros.
+template <typename V>
+struct SlotGroup {
+  static constexpr int G = 16 / int(sizeof(V));
+};
+template <typename V>
+__host__ __device__ __forceinline__ size_t stored_at(size_t nv, size_t g, int s) {
+  constexpr int G = SlotGroup<V>::G;
+  return (size_t(s / G) * nv + g) * G + size_t(s % G);
+}
+inline size_t stored_size(int K, size_t nv, int G) { return size_t((K + G - 1) / G) * nv * size_t(G); }
+
 // bands of 1D two-scale matrices up to this length take the unrolled
 // transfer paths (B-splines of degree <= 3)
 constexpr int kBandMax = 5;

@@ -38,14 +38,15 @@ __device__ __forceinline__ double mrow(unsigned meta, const OpView<V> &op, const
                                        int col, int Kdyn) {
   const unsigned g = meta & kMetaIndex;
   const bool uni = g == kMetaIndex;
-  const V *__restrict__ v = uni ? op.ref : op.val + g;
-  const size_t st = uni ? 1 : size_t(op.nv);
+  const size_t nv = size_t(op.nv);
   double acc = 0.0;
   if (K > 0) {
 #pragma unroll
-    for (int s = 0; s < K; ++s) acc += double(v[s * st]) * x[size_t(L + op.off.off[s]) * R + col];
+    for (int s = 0; s < K; ++s)
+      acc += double(uni ? op.ref[s] : op.val[stored_at<V>(nv, g, s)]) * x[size_t(L + op.off.off[s]) * R + col];
   } else {
-    for (int s = 0; s < Kdyn; ++s) acc += double(v[s * st]) * x[size_t(L + op.off.off[s]) * R + col];
+    for (int s = 0; s < Kdyn; ++s)
+      acc += double(uni ? op.ref[s] : op.val[stored_at<V>(nv, g, s)]) * x[size_t(L + op.off.off[s]) * R + col];
   }
   return acc;
 }
@@ -216,17 +217,13 @@ __global__ __launch_bounds__(kTileRows) void k_m_tile(int R, OpView<V> op, const
   // phase 2: the tile's stored rows on the first lanes, results to the owners
   if (act2) {
     const int t2 = tile_local<K>(own2);
-    const V *__restrict__ v = op.val + g;
-    const size_t nv = size_t(op.nv);
     double a2[NC] = {};
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
+    stored_row_slots<K, V>(op, g, [&](int s, double a) {
       const int dx = s % SS::W, dy = (s / SS::W) % SS::W, dz = s / (SS::W * SS::W);
       const double *t = win + (t2 + (dz * SS::WY + dy) * SS::WX + dx) * NC;
-      const double a = double(v[s * nv]);
 #pragma unroll
       for (int k = 0; k < NC; ++k) a2[k] += a * t[k];
-    }
+    });
 #pragma unroll
     for (int k = 0; k < NC; ++k) xch[own2 * NC + k] = a2[k];
   }

@@ -57,16 +57,45 @@ __device__ __forceinline__ double op_row(unsigned meta, const OpView<V> &op, con
                                          int Kdyn) {
   const unsigned g = meta & kMetaIndex;
   const bool uni = g == kMetaIndex;
-  const V *__restrict__ v = uni ? op.ref : op.val + g;
-  const size_t st = uni ? 1 : size_t(op.nv);
+  const size_t nv = size_t(op.nv);
   double acc = 0.0;
   if (K > 0) {
 #pragma unroll
-    for (int s = 0; s < K; ++s) acc += double(v[s * st]) * x[L + op.off.off[s]];
+    for (int s = 0; s < K; ++s)
+      acc += double(uni ? op.ref[s] : op.val[stored_at<V>(nv, g, s)]) * x[L + op.off.off[s]];
   } else {
-    for (int s = 0; s < Kdyn; ++s) acc += double(v[s * st]) * x[L + op.off.off[s]];
+    for (int s = 0; s < Kdyn; ++s)
+      acc += double(uni ? op.ref[s] : op.val[stored_at<V>(nv, g, s)]) * x[L + op.off.off[s]];
   }
   return acc;
+}
+
+// The K values of stored row g in slot order, one 16-byte load per slot
+// group (SlotGroup): f(s, a_s) for s = 0 .. K-1.
+template <int K, typename V, typename F>
+__device__ __forceinline__ void stored_row_slots(const OpView<V> &op, int g, F &&f) {
+  constexpr int G = SlotGroup<V>::G;
+  constexpr int NG = (K + G - 1) / G;
+  const size_t nv = size_t(op.nv);
+  if constexpr (G == 2) {
+    const double2 *__restrict__ p = reinterpret_cast<const double2 *>(op.val) + g;
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      const double2 v = p[q * nv];
+      f(2 * q, v.x);
+      if (2 * q + 1 < K) f(2 * q + 1, v.y);
+    }
+  } else {
+    const float4 *__restrict__ p = reinterpret_cast<const float4 *>(op.val) + g;
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      const float4 v = p[q * nv];
+      f(4 * q, double(v.x));
+      if (4 * q + 1 < K) f(4 * q + 1, double(v.y));
+      if (4 * q + 2 < K) f(4 * q + 2, double(v.z));
+      if (4 * q + 3 < K) f(4 * q + 3, double(v.w));
+    }
+  }
 }
 
 // Lattice box of tile b (x fastest over the tile grid).
@@ -328,11 +357,8 @@ __device__ __forceinline__ double2 tile_rows(int n, int blk, const OpView<V> &op
     // phase 2: the tile's stored rows, packed onto the first lanes
     if (act2) {
       const double *t2 = lds + tile_local<K>(own2);
-      const V *__restrict__ v = op.val + g;
-      const size_t nv = size_t(op.nv);
       double a2 = 0.0;
-#pragma unroll
-      for (int s = 0; s < K; ++s) a2 += double(v[s * nv]) * tile_at<K>(t2, s);
+      stored_row_slots<K, V>(op, g, [&](int s, double a) { a2 += a * tile_at<K>(t2, s); });
       xch[own2] = a2;
     }
     __syncthreads();
