@@ -1,26 +1,31 @@
-"""Benchmark: multigrid-preconditioned CG on the 1024^2 cubic B-spline immersed
-Poisson problem (unit square minus 200 seeded discs, manufactured solution,
-6-level V(2,2)), on one MI355X.
+"""Benchmark: multigrid-preconditioned CG on the 3D immersed Poisson problem
+(quadratic B-splines, 128^3 gyroid, 1.48M DOFs, 4-level V(1,1)) on one MI355X,
+with the 2D 1024^2 cubic 200-disc problem (6-level V(2,2)), several
+right-hand sides and the 64-problem batch beside it.
 
-A step is one full PCG solve from x0 = 0 to a relative residual of 1e-8 (every
-V-cycle level, smoother, transfer, coarsest solve and CG update runs inside
-it).  Inputs (operator hierarchy, right-hand side) are resident in HBM before
-the timed region starts.  `value` = fine DOFs x PCG iterations / wall time of
-the timed solves of the headline form (each iteration applies one V-cycle and
-the CG updates); the plain FP64 form is timed in the same run and reported in
-`config`.
+Metric (both parts are reported for every form):
+* V-cycle MDOF/s = fine DOFs / median time of one V-cycle (imsmg_vcycle as
+  one captured graph, HIP events around each of --vcycles cycles after warm-up);
+* PCG time to 1e-8 = wall time of one imsmg_pcg_solve from x0 = 0 until the
+  true relative residual ||b - A x|| / ||b|| <= 1e-8 (rechecked on the host).
+A timed step is one FP64 PCG solve of the workload (every level, smoother,
+transfer, coarsest solve and CG update runs inside it); `value` is the FP64
+V-cycle MDOF/s, `ms_per_step` the FP64 PCG time.  The other forms (FP32
+V-cycle operators, multiplicative Schwarz, the damping network) are timed in
+the same run and reported in `config`.  Inputs (operator hierarchy, right-hand
+side) are resident in HBM before the timed region starts.
 
-The dominant kernel is the finest level's fused residual + trivial-row
-smoothing step; its duration is measured with HIP events on the library stream
-during a second pass of the same solves (each timed step launches the kernel
-TIMED_REPS times back to back between its two events, which spreads the events'
-own overhead; the step only reads x_a and r, so the repeats change nothing),
-and its algorithmic bytes come from the level's storage statistics (compressed
-rows read only vectors).
+Roofline of the dominant kernel (the finest level's fused residual +
+one-function-block smoothing step, FP64): its duration is measured with HIP
+events on the library stream during a second pass of the same solves (each
+timed step launches the kernel TIMED_REPS times back to back between its two
+events; the step only reads x_a and r, so the repeats change nothing), its
+algorithmic bytes come from the level's storage statistics.
 
 Prints one JSON line.
 """
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -41,34 +46,57 @@ def log(msg):
 
 
 def smooth_step_bytes(st):
-    """Algorithmic bytes of one launch of the fused residual + trivial-row
-    smoothing step on a level: per row row_lat (4) + meta (4) + c (8) + r (8)
-    + x_a (8, each entry once) + x_b (8); rows of general blocks also store
-    their residual (8); stored rows read K values."""
+    """Algorithmic bytes of one launch of the fused residual + one-function
+    block smoothing step on a level: per row row_lat (4) + meta (4) + c (8) +
+    r (8) + x_a (8, each entry once) + x_b (8); rows of larger blocks also
+    store their residual (8); stored rows read K values."""
     return (st["n"] * 40 + st["general_rows"] * 8
             + st["stored_rows"] * st["stencil"] * st["value_bytes"])
 
 
-def cpu_baseline():
-    """The oracle (plain FP64 NumPy/SciPy) on a bounded sample of the same
-    workload: the same 200-disc geometry and cubic V(2,2) hierarchy at 128^2
-    (4 levels, coarsest 16^2); throughput in the same unit (DOFs x PCG
-    iterations / solve seconds)."""
+def cpu_baseline(budget_s=25.0):
+    """The oracle (plain FP64 NumPy/SciPy) on bounded samples: the gyroid
+    workload at 16^3 (3 levels; the headline's geometry, basis and cycle at a
+    size the oracle finishes), its V-cycle time (median of 5) in the metric's
+    unit and its PCG solve; C1 (the 32^2 disc configuration, whole) and the
+    200-disc cubic V(2,2) workload at 128^2 when the budget allows."""
+    import numpy as np
     import workloads as W
     from oracle import problem as P
-    w = W.c2(n=128, levels=4)
-    t0 = time.time()
-    op = P.build(w)
-    t_setup = time.time() - t0
-    t0 = time.time()
-    x, it, _ = op.solve(tol=1e-8)
-    t_solve = time.time() - t0
-    n = op.A.shape[0]
-    return {"value": round(n * it / t_solve / 1e6, 4), "unit": "MDOF/s", "cores": 1,
+    out = {}
+
+    def sample(name, w):
+        t0 = time.time()
+        op = P.build(w)
+        t_setup = time.time() - t0
+        r = op.b
+        ts = []
+        for _ in range(5):
+            t0 = time.time()
+            op.vcycle.apply(r)
+            ts.append(time.time() - t0)
+        t0 = time.time()
+        _, it, _ = op.solve(tol=1e-8)
+        t_solve = time.time() - t0
+        n = op.A.shape[0]
+        out[name] = {"dofs": n, "levels": w.levels, "vcycle_ms": round(1e3 * float(np.median(ts)), 2),
+                     "vcycle_mdofs": round(n / float(np.median(ts)) / 1e6, 5), "pcg_s": round(t_solve, 3),
+                     "iterations": it, "setup_s": round(t_setup, 2)}
+        log(f"oracle {name}: {out[name]}")
+
+    t_all = time.time()
+    sample("gyroid-16^3", W.c3(n=16, levels=3))
+    sample("C1", W.c1())
+    if time.time() - t_all < budget_s:
+        sample("discs-cubic-128^2", W.c2(n=128, levels=4))
+    head = out["gyroid-16^3"]
+    return {"value": head["vcycle_mdofs"], "unit": "MDOF/s", "cores": 1,
             "cores_available": len(os.sched_getaffinity(0)), "kind": "oracle",
-            "sample": f"oracle PCG solve to 1e-8 on the same 200-disc cubic V(2,2) workload at 128^2 "
-                      f"({n} DOFs, 4 levels, {it} iterations, solve {t_solve:.2f} s, setup {t_setup:.1f} s); "
-                      f"scipy sparse products and the per-block Python loops run on one thread"}
+            "sample": ("oracle V-cycle (median of 5) on the quadratic gyroid workload at 16^3 "
+                       f"({head['dofs']} DOFs, 3 levels); also its PCG solve and the C1 and 128^2 cubic-disc "
+                       "samples in `samples`; scipy sparse products and the per-block Python loops run on one "
+                       "thread"),
+            "samples": out}
 
 
 def main():
@@ -76,23 +104,22 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed",
-                    help="headline form (the other form is timed too)")
-    ap.add_argument("--n", type=int, default=1024)
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="general-row smoother with 4 lanes per row on every level instead of the measured choice")
-    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
-                    help="c2: 1024^2 cubic discs (headline); c3: 128^3 quadratic gyroid")
+    ap.add_argument("--vcycles", type=int, default=50, help="timed V-cycles per form (median)")
+    ap.add_argument("--workload", choices=["c3", "c2"], default="c3",
+                    help="c3: 128^3 quadratic gyroid (headline); c2: 1024^2 cubic discs")
+    ap.add_argument("--n", type=int, default=0, help="elements per axis (0: the workload's own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the mixed+learned form")
+    ap.add_argument("--no-second", action="store_true", help="skip the second workload (c2 beside c3)")
     ap.add_argument("--nrhs", type=int, default=16, help="columns of the multi-right-hand-side form (1: skip)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-problem form")
+    ap.add_argument("--forms", default="", help="comma list to restrict the timed forms")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for FETCH_SIZE/WRITE_SIZE scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "the solver runs on one GPU: --gpus must be 1 (sharding across GPUs is designed, not implemented)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only: --gpus must be 1 "
+                                   "(sharding across GPUs is designed, not implemented)"}))
         sys.exit(2)
 
     import numpy as np
@@ -103,133 +130,96 @@ def main():
     from paper_1903_10977_amd import solver as S
 
     assert torch.cuda.is_available(), "bench needs a GPU"
-    if args.workload == "c3":
-        # 3D gyroid, quadratic B-splines, 128^3, 4 levels, V(1,1); no multi-column or batched forms
-        w = W.c3(n=args.n if args.n != 1024 else 128)
-        levels = w.levels
-        args.nrhs, args.no_batched = 1, True
-    else:
-        levels = int(round(math.log2(args.n // 32))) + 1
-        w = W.c2(n=args.n, levels=levels)
-    t0 = time.time()
-    g = GN.generate(w, with_mass=args.nrhs > 1)
-    log(f"generated {w.name}: fine DOFs {g.fine.n}, nnz {g.fine.A.nnz}, {time.time() - t0:.1f} s")
-    b = torch.tensor(g.b, device="cuda:0")
-    n = g.fine.n
 
-    def make(prec, timing=0, learned=None, block_gemm=0):
+    def workload(kind):
+        if kind == "c3":
+            return W.c3(n=args.n or 128)
+        n = args.n or 1024
+        return W.c2(n=n, levels=int(round(math.log2(n // 32))) + 1)
+
+    def make(g, w, prec, smoother="as", timing=0, learned=None, block_gemm=0):
+        wl = dataclasses.replace(w, smoother=smoother)  # coarse_smoother: carried by w
         o = S.default_options(nu_pre=w.nu, nu_post=w.nu, precision=prec, timing=timing,
-                              use_graph=0 if (args.no_graph or timing) else 1, max_iter=2000,
-                              use_learned=int(learned is not None), autotune=int(not args.no_autotune),
-                              block_gemm=block_gemm)
+                              use_graph=0 if timing else 1, max_iter=2000, use_learned=int(learned is not None),
+                              autotune=1, block_gemm=block_gemm, **S.smoother_options(wl))
         t = time.time()
         sol = S.Solver(0).setup(g, o)
         if learned is not None:
             sol.load_mlp(learned)
         sol.factor()
-        lanes = [sol.level_stats(l)["general_lanes"] for l in range(1, len(g.levels))]
-        log(f"setup+factor precision={prec} {time.time() - t:.2f} s (general-row lanes per level {lanes})")
+        log(f"{w.name} setup+factor precision={prec} smoother={smoother}: {time.time() - t:.2f} s")
         return sol
 
-    def timed(sol):
-        x = torch.zeros_like(b)
-        for _ in range(args.warmup):
-            x.zero_()
-            sol.pcg(b, x, rtol=1e-8)
-        torch.cuda.synchronize()
-        iters = 0
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            x.zero_()
-            info = sol.pcg(b, x, rtol=1e-8)
-            iters += info.iterations
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        return x, iters, dt
-
-    head = S.MIXED if args.precision == "mixed" else S.FP64
-    other = S.FP64 if head == S.MIXED else S.MIXED
-    results = {}
-    for prec in (other, head):
-        sol = make(prec)
-        x, iters, dt = timed(sol)
-        res = float(np.linalg.norm(g.b - g.fine.A @ x.cpu().numpy()) / np.linalg.norm(g.b))
-        results[prec] = dict(iters=iters, dt=dt, ms=1e3 * dt / args.steps, mdofs=n * iters / dt / 1e6,
-                             true_rel_res=res, x=x)
-        log(f"precision={prec}: {args.steps} solves, {iters} iterations, {1e3 * dt / args.steps:.2f} ms/solve, "
-            f"{n * iters / dt / 1e6:.1f} MDOF/s, true rel. residual {res:.2e}")
-        sol.close()
-    # mixed + learned per-block damping (the committed network), same solves
-    learned = None
-    if not args.no_learned:
-        from paper_1903_10977_amd import learn as LN
-        model = LN.MODEL_DEFAULT + ("_gyroid3d" if args.workload == "c3" else "")
-        sol = make(S.MIXED, learned=LN.load_params(model))
-        status = [sol.weights(l)[1] for l in range(1, len(g.levels))]
-        x, iters, dt = timed(sol)
-        res = float(np.linalg.norm(g.b - g.fine.A @ x.cpu().numpy()) / np.linalg.norm(g.b))
-        learned = dict(iters=iters, ms=1e3 * dt / args.steps, mdofs=n * iters / dt / 1e6, true_rel_res=res,
-                       level_status=status)
-        log(f"mixed+learned: {args.steps} solves, {iters} iterations, {learned['ms']:.2f} ms/solve, "
-            f"level status {status} (1 = network weights kept), true rel. residual {res:.2e}")
-        sol.close()
-    # several right-hand sides with the same matrix: the 16-column form
-    multi = None
-    if args.nrhs > 1:
-        rng = np.random.Generator(np.random.PCG64(1000))
-        M = g.M
-        U = rng.standard_normal((args.nrhs, n))
-        Bm = torch.tensor(np.stack([M @ u for u in U]), device="cuda:0")  # load vectors of random L2 data
-        Bm[0] = b
-        # general Schwarz blocks: 0 assembled FP64 CSR product, 1 FP64 patch
-        # GEMMs on the matrix cores, 2 BF16 patch GEMMs with FP32 accumulation
-        forms = {}
-        for mode, label in ((0, "csr_fp64"), (1, "mfma_fp64"), (2, "mfma_bf16")):
-            sol = make(head, block_gemm=mode)
-            Xm = torch.zeros_like(Bm)
-            sol.pcg_multi(Bm, Xm, rtol=1e-8)  # warm-up (graph capture)
+    def run_forms(w, g, forms, steps, warmup):
+        b = torch.tensor(g.b, device="cuda:0")
+        n = g.fine.n
+        res = {}
+        for label, (prec, smoother, learned, coarse) in forms.items():
+            gg = GN.with_coarse_diagonal(g, coarse) if coarse else g
+            wl = dataclasses.replace(w, coarse_smoother=coarse) if coarse else w
+            sol = make(gg, wl, prec, smoother, learned=learned)
+            x = torch.zeros_like(b)
+            for _ in range(warmup):
+                x.zero_()
+                sol.pcg(b, x, rtol=1e-8)
             torch.cuda.synchronize()
+            iters = 0
             t0 = time.perf_counter()
-            tot_it = 0
-            for _ in range(args.steps):
-                Xm.zero_()
-                infos = sol.pcg_multi(Bm, Xm, rtol=1e-8)
-                tot_it += sum(i.iterations for i in infos)
+            for _ in range(steps):
+                x.zero_()
+                info = sol.pcg(b, x, rtol=1e-8)
+                iters += info.iterations
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            worst = max(i.true_rel_res for i in infos)
-            forms[label] = {"ms_per_solve": round(1e3 * dt / args.steps, 3), "mdofs": round(n * tot_it / dt / 1e6, 1),
-                            "iterations_per_column": [i.iterations for i in infos], "worst_true_rel_res": worst,
-                            "patch_gemm_levels": [sol.level_stats(l)["patch_gemm"] for l in range(1, len(g.levels))]}
-            log(f"{args.nrhs} right-hand sides ({label}): {forms[label]['ms_per_solve']:.2f} ms per solve, "
-                f"{forms[label]['mdofs']} MDOF/s (DOF x iterations summed over columns), worst true rel. residual "
-                f"{worst:.2e}")
+            true_res = float(np.linalg.norm(g.b - g.fine.A @ x.cpu().numpy()) / np.linalg.norm(g.b))
+            vmed, vmean = sol.vcycle_time(b, reps=args.vcycles)
+            entry = {"pcg_ms": round(1e3 * dt / steps, 3), "iterations": iters / steps, "setup_ms": round(info.setup_ms, 1),
+                     "factor_ms": round(info.factor_ms, 1),
+                     "true_rel_res": true_res, "vcycle_ms_median": round(vmed, 4), "vcycle_ms_mean": round(vmean, 4),
+                     "vcycle_mdofs": round(n / (vmed * 1e-3) / 1e6, 1),
+                     "mdofs_x_iterations_per_s": round(n * iters / dt / 1e6, 1)}
+            if learned is not None:
+                entry["learned_status_per_level"] = [sol.weights(l)[1] for l in range(1, len(g.levels))]
+            res[label] = entry
+            log(f"{w.name} {label}: {entry}")
+            if true_res > 1.01e-8:
+                raise RuntimeError(f"{label}: true relative residual {true_res:.2e} above 1e-8")
             sol.close()
-        multi = {"nrhs": args.nrhs, **{k: v for k, v in forms["csr_fp64"].items() if k != "patch_gemm_levels"},
-                 "general_blocks": forms,
-                 "rhs": "column 0: the workload's load vector; others: load vectors M u of random normal u"}
-    # batched: 64 independent problems (n in {64..512}^2, p in {1,2,3}), 16
-    # right-hand sides each, one context and stream per problem, 16 host threads
-    batched = None
-    if not args.no_batched:
-        from paper_1903_10977_amd import batch as BT
-        # the configuration's form: general blocks as BF16 patch GEMMs (FP32
-        # accumulation) on the matrix cores; the assembled CSR product beside it
-        batched = BT.run_batch(64, 16, workers=16, steps=2, precision=head, block_gemm=2)
-        batched["csr_fp64"] = BT.run_batch(64, 16, workers=16, steps=2, precision=head, block_gemm=0)
-    hr = results[head]
-    ms_step = hr["ms"]
-    value = hr["mdofs"]
-    # the two forms' solutions agree (L2 on the coefficients is dominated by
-    # near-null cut modes; report the relative residual of each instead)
+        return res
 
-    # dominant kernel: the finest level's fused residual + trivial smoothing
-    # step, timed with HIP events on the library stream during the same solves
-    solt = make(head, timing=TIMED_REPS)
+    want = set(args.forms.split(",")) if args.forms else None
+
+    def pick(forms):
+        return {k: v for k, v in forms.items() if want is None or k in want}
+
+    # ---------------------------------------------------------------- headline
+    w = workload(args.workload)
+    t0 = time.time()
+    g = GN.generate(w, with_mass=(args.workload == "c2" and args.nrhs > 1))
+    log(f"generated {w.name}: fine DOFs {g.fine.n}, nnz {g.fine.A.nnz}, {time.time() - t0:.1f} s")
+    n = g.fine.n
+    # (precision, finest-level smoother, damping network, coarse-level diagonal smoother)
+    forms = {"fp64": (S.FP64, "as", None, None), "mixed": (S.MIXED, "as", None, None),
+             "ms-fp64": (S.FP64, "ms", None, None), "ms-mixed": (S.MIXED, "ms", None, None),
+             "ms+jacobi-fp64": (S.FP64, "ms", None, "jacobi"), "ms+jacobi-mixed": (S.MIXED, "ms", None, "jacobi"),
+             "ms+gs-mixed": (S.MIXED, "ms", None, "gs")}
+    if not args.no_learned:
+        from paper_1903_10977_amd import learn as LN
+        model = LN.MODEL_DEFAULT + ("_gyroid3d" if w.dim == 3 else "")
+        forms["mixed+learned"] = (S.MIXED, "as", LN.load_params(model), None)
+    head = run_forms(w, g, pick(forms) if want else forms, args.steps, args.warmup)
+    if "fp64" not in head:
+        head.update(run_forms(w, g, {"fp64": forms["fp64"]}, args.steps, args.warmup))
+    hf = head["fp64"]
+
+    # dominant kernel: the finest level's fused residual + smoothing step,
+    # FP64, timed with HIP events on the library stream during the same solves
+    solt = make(g, w, S.FP64, timing=TIMED_REPS)
     stats = solt.level_stats(len(g.levels) - 1)
     solt.kernel_time(reset=True)
+    b = torch.tensor(g.b, device="cuda:0")
     xt = torch.zeros_like(b)
-    for _ in range(args.steps):
+    for _ in range(max(1, min(args.steps, 3))):
         xt.zero_()
         solt.pcg(b, xt, rtol=1e-8)
     ms, cnt = solt.kernel_time()
@@ -239,6 +229,11 @@ def main():
     log(f"fine smoothing-step kernel: {cnt} launches, avg {avg_ms * 1e3:.1f} us, {bytes_launch / 1e6:.1f} MB, "
         f"{achieved:.0f} GB/s; stats {stats}")
     solt.close()
+    tag = "128cube_gyroid" if (args.workload == "c3" and w.n == 128) else (
+        "1024_discs" if (args.workload == "c2" and w.n == 1024) else None)
+    traffic = None
+    if tag:
+        traffic = PR.read_traffic(os.path.join(ROOT, "profiles", f"traffic_k_residual_smooth_{tag}_fp64.txt"))
 
     if args.copy_calibration_mib > 0:
         # a plain device copy of known size for the counter scaling: one
@@ -251,44 +246,90 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: 3 elementwise copies of {args.copy_calibration_mib} MiB")
         del src, dst
+    del g
 
-    # measured HBM traffic of the same kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE,
-    # copy-calibrated), valid only while the kernel sources are unchanged
-    traffic = None
-    if args.n == 1024 and args.workload == "c2":
-        form = "mixed" if head == S.MIXED else "fp64"
-        traffic = PR.read_traffic(os.path.join(ROOT, "profiles", f"traffic_k_residual_smooth_1024_discs_{form}.txt"))
+    # ------------------------------------------------ the second workload (2D)
+    second = None
+    if args.workload == "c3" and not args.no_second:
+        w2 = workload("c2")
+        t0 = time.time()
+        g2 = GN.generate(w2, with_mass=args.nrhs > 1)
+        log(f"generated {w2.name}: fine DOFs {g2.fine.n}, {time.time() - t0:.1f} s")
+        forms2 = {"fp64": (S.FP64, "as", None, None), "mixed": (S.MIXED, "as", None, None),
+                  "ms-fp64": (S.FP64, "ms", None, None), "ms+jacobi-fp64": (S.FP64, "ms", None, "jacobi"),
+                  "ms+jacobi-mixed": (S.MIXED, "ms", None, "jacobi")}
+        second = {"workload": (f"2D Poisson, cubic B-splines, {w2.n}^2, unit square minus 200 seeded discs, "
+                               f"manufactured sin(2 pi x) sin(2 pi y), {w2.levels}-level V(2,2)"),
+                  "fine_dofs": g2.fine.n, "forms": run_forms(w2, g2, pick(forms2) if want else forms2,
+                                                            args.steps, args.warmup)}
+        mw, mg = w2, g2
+    elif args.workload == "c2":
+        mw, mg = w, GN.generate(w, with_mass=True) if args.nrhs > 1 else None
+    else:
+        mw = mg = None
+
+    # several right-hand sides with the C2 matrix: the 16-column form
+    multi = None
+    if args.nrhs > 1 and mg is not None:
+        rng = np.random.Generator(np.random.PCG64(1000))
+        nn = mg.fine.n
+        U = rng.standard_normal((args.nrhs, nn))
+        Bm = torch.tensor(np.stack([mg.M @ u for u in U]), device="cuda:0")  # load vectors of random L2 data
+        Bm[0] = torch.tensor(mg.b, device="cuda:0")
+        fm = {}
+        for mode, label in ((0, "csr_fp64"), (2, "mfma_bf16")):
+            sol = make(mg, mw, S.MIXED, block_gemm=mode)
+            Xm = torch.zeros_like(Bm)
+            sol.pcg_multi(Bm, Xm, rtol=1e-8)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tot_it = 0
+            for _ in range(args.steps):
+                Xm.zero_()
+                infos = sol.pcg_multi(Bm, Xm, rtol=1e-8)
+                tot_it += sum(i.iterations for i in infos)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            fm[label] = {"ms_per_solve": round(1e3 * dt / args.steps, 3),
+                         "mdofs_x_iterations_per_s": round(nn * tot_it / dt / 1e6, 1),
+                         "worst_true_rel_res": max(i.true_rel_res for i in infos)}
+            log(f"{args.nrhs} right-hand sides ({label}): {fm[label]}")
+            sol.close()
+        multi = {"nrhs": args.nrhs, "general_blocks": fm,
+                 "rhs": "column 0: the workload's load vector; others: load vectors M u of random normal u"}
+
+    # batched: 64 independent problems (n in {64..512}^2, p in {1,2,3}), 16
+    # right-hand sides each, one context and stream per problem, 16 host threads
+    batched = None
+    if not args.no_batched:
+        from paper_1903_10977_amd import batch as BT
+        batched = BT.run_batch(64, 16, workers=16, steps=2, precision=S.MIXED, block_gemm=0)
+        batched["bf16_patch_gemms"] = BT.run_batch(64, 16, workers=16, steps=2, precision=S.MIXED, block_gemm=2)
 
     cpu = None
-    if not args.no_cpu_baseline and args.workload == "c2":
-        log("timing the oracle on the host (bounded sample)")
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host (bounded samples)")
         cpu = cpu_baseline()
-    names = {S.FP64: "fp64", S.MIXED: "mixed"}
-    forms = {names[p]: {"ms_per_solve": round(r["ms"], 3), "mdofs": round(r["mdofs"], 1),
-                        "iterations_per_solve": r["iters"] / args.steps, "true_rel_res": r["true_rel_res"]}
-             for p, r in results.items()}
-    if learned is not None:
-        forms["mixed+learned"] = {"ms_per_solve": round(learned["ms"], 3), "mdofs": round(learned["mdofs"], 1),
-                                  "iterations_per_solve": learned["iters"] / args.steps,
-                                  "true_rel_res": learned["true_rel_res"],
-                                  "levels_with_network_weights": learned["level_status"]}
+
     out = {
-        "metric": METRIC, "value": round(value, 2), "unit": "MDOF/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if head == S.FP64 else "f32-vcycle-operators/f64",
-        "data": "synthetic",
-        "config": {"workload": (f"2D Poisson, cubic B-splines, {args.n}^2, unit square minus 200 seeded discs "
-                                f"(r ~ U[0.01,0.04]), manufactured sin(2 pi x) sin(2 pi y), {levels}-level V(2,2), "
-                                f"PCG to 1e-8 from x0 = 0") if args.workload == "c2" else
-                               (f"3D Poisson, quadratic B-splines, {w.n}^3 gyroid {{g < 0.3}} (two periods, seeded "
-                                f"phase), f = 1, u = 0 on the box, {levels}-level V(1,1), PCG to 1e-8 from x0 = 0"),
-                   "fine_dofs": n, "headline_form": names[head],
-                   "pcg_time_s": round(ms_step / 1e3, 5), "forms": forms,
-                   "speedup_mixed_vs_fp64": round(results[S.FP64]["ms"] / results[S.MIXED]["ms"], 3),
-                   "multi_rhs": multi, "batched": batched},
+        "metric": METRIC, "value": hf["vcycle_mdofs"], "unit": "MDOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": hf["pcg_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": (f"3D Poisson, quadratic B-splines, {w.n}^3 gyroid {{g < 0.3}} (two periods, seeded "
+                                f"phase), f = 1, u = 0 on the box, {w.levels}-level V(1,1), PCG to 1e-8 from x0 = 0"
+                                if w.dim == 3 else
+                                f"2D Poisson, cubic B-splines, {w.n}^2 minus 200 seeded discs, manufactured "
+                                f"solution, {w.levels}-level V(2,2), PCG to 1e-8 from x0 = 0"),
+                   "fine_dofs": n, "headline_form": "fp64 (additive Schwarz V-cycle, FP64 everywhere)",
+                   "value_is": "fine DOFs / median time of one V-cycle (50 timed cycles, HIP events)",
+                   "ms_per_step_is": "one FP64 PCG solve from x0 = 0 to a true relative residual <= 1e-8",
+                   "pcg_time_s": round(hf["pcg_ms"] / 1e3, 5), "forms": head,
+                   "speedup_mixed_vs_fp64_pcg": (round(hf["pcg_ms"] / head["mixed"]["pcg_ms"], 3)
+                                                 if "mixed" in head else None),
+                   "second_workload": second, "multi_rhs": multi, "batched": batched},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_residual_smooth (finest level)", "bytes_per_launch": int(bytes_launch),
+                     "kernel": "k_residual_smooth (finest level, FP64)", "bytes_per_launch": int(bytes_launch),
                      "avg_launch_us": round(avg_ms * 1e3, 2), "launches_per_event_pair": TIMED_REPS},
         "cpu_baseline": cpu,
     }

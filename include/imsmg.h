@@ -132,7 +132,9 @@ typedef struct {
                           stencil instead of their own values (default 1) */
   int32_t use_learned; /* 1: imsmg_factor_patches damps every block of every level without given
                           weights by the loaded damping network (imsmg_load_mlp), subject to the
-                          stability check; default 0 */
+                          stability check and to the iteration judge (the weights are kept only
+                          if PCG on a fixed probe needs fewer iterations than with gamma);
+                          2: the same without the judge; default 0 */
   int32_t autotune;    /* 1: imsmg_factor_patches times the general-row smoother with 2, 4 and 8
                           lanes per row on each level (HIP events, a few launches each) and keeps
                           the fastest; 0: 4 lanes.  The lane count fixes the summation order of
@@ -210,7 +212,11 @@ int imsmg_set_patch_weights(imsmg_ctx *ctx, int level, const double *omega);
  * eq:stabilityMulti keeps I - S A a contraction).  On a first failure all
  * weights of the level are scaled by 1.8 / lambda_max and checked again; on a
  * second the level falls back to gamma_l (imsmg_get_patch_weights reports
- * which). */
+ * which).  With use_learned = 1 the uniform smoother then judges the cost:
+ * PCG on the probe b = A v (v_i = 1 + sin(0.7 i + 0.3) / 2 + cos(1.9 i) / 4,
+ * x0 = 0, rtol 1e-8) runs once with gamma on every level and once with the
+ * kept network weights; unless the network needs fewer iterations, every
+ * level returns to gamma (learned_status -2). */
 int imsmg_factor_patches(imsmg_ctx *ctx);
 
 /* ---- several right-hand sides with the same matrix (nrhs = 1 .. 16) ----
@@ -288,7 +294,8 @@ int imsmg_get_patch_features(imsmg_ctx *ctx, int level, int32_t *nblocks, float 
 
 /* Current weight of every final block of level l (host, may be NULL),
  * learned_status 1 = network weights accepted, -1 = rejected by the stability
- * check (gamma used), 0 = gamma or given weights; lambda_max = the stability
+ * check (gamma used), -2 = rejected by the iteration judge (gamma used),
+ * 0 = gamma or given weights; lambda_max = the stability
  * check's estimate (0 if it did not run).  Pointers other than nblocks may be NULL. */
 int imsmg_get_patch_weights(imsmg_ctx *ctx, int level, int32_t *nblocks, double *omega, int32_t *learned_status,
                             double *lambda_max);
@@ -360,6 +367,14 @@ int imsmg_get_gamma(imsmg_ctx *ctx, int level, double *gamma);
  * only read.  Errors: IMSMG_ERR_STATE before imsmg_factor_patches,
  * IMSMG_ERR_INVALID_ARG for a null pointer, IMSMG_ERR_HIP. */
 int imsmg_vcycle(imsmg_ctx *ctx, const double *r_dev, double *z_dev);
+
+/* Times one V-cycle as imsmg_vcycle runs it (residual staged once, then reps
+ * cycles, each between two HIP events on the context's stream; with
+ * opt.use_graph the cycle is one captured graph): median and mean in ms over
+ * the reps (1 .. 100000).  The V-cycle throughput of the solve is
+ * n_L / median.  Errors: IMSMG_ERR_STATE before imsmg_factor_patches,
+ * IMSMG_ERR_INVALID_ARG for bad arguments or opt.timing != 0. */
+int imsmg_vcycle_time(imsmg_ctx *ctx, const double *r_dev, int reps, double *median_ms, double *mean_ms);
 
 /* CG preconditioned by the V-cycle (the paragraph after Algorithm alg:MGV).
  * b_dev: right-hand side, x_dev: x0 on entry and the solution on return, both

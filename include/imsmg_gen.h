@@ -95,6 +95,13 @@ int imsmg_gen_get_blocks(const imsmg_gen_problem *p, int level, int32_t *ptr, in
  * one per active function (n_active) for one-function blocks (Gauss-Seidel,
  * (p+1)^d colours). */
 int imsmg_gen_get_block_colours(const imsmg_gen_problem *p, int level, int kind, int32_t *colour);
+/* The same colour rule on given lattice positions (no problem object):
+ * colour[j] = sum_a ((m_a / stride) mod q) q^a for the function at
+ * dof_to_lattice[j] (x fastest over nf1 functions per axis); q = p + 1,
+ * stride 1 for B-splines and one-function blocks, q = 2, stride p for
+ * Lagrange vertex blocks. */
+int imsmg_gen_lattice_colours(int n, const int32_t *dof_to_lattice, int nf1, int dim, int q, int stride,
+                              int32_t *colour);
 /* active elements in ascending element index: eptr[n_active_elements+1],
  * eidx[elem_nnz] = compact indices of the active functions non-zero on the
  * element (x offset fastest), elem[n_active_elements] = element index */

@@ -187,6 +187,7 @@ struct imsmg_ctx {
   double *c_in = nullptr, *c_out = nullptr;                          // compact staging
   hipGraphExec_t graph = nullptr;
   int graph_iters = 0;
+  hipGraphExec_t vgraph = nullptr;  // one V-cycle from the staged c_in to c_out (imsmg_vcycle)
   // multi-right-hand-side buffers (R interleaved columns), allocated on first use
   struct Multi {
     int R = 0;
@@ -200,6 +201,8 @@ struct imsmg_ctx {
   size_t ev_used = 0;
   double t_kernel_ms = 0.0;
   int64_t t_kernel_n = 0;
+  double setup_ms = 0.0, factor_ms = 0.0;  // wall time of the last setup / factorization
+  int judge_it[2] = {0, 0};                 // probe iterations with gamma / with the network (use_learned 1)
 };
 
 namespace {
@@ -1638,6 +1641,59 @@ void learned_weights(imsmg_ctx *c, int l) {
 
 bool L_has_no_user_weights(const Level &L) { return L.omega.empty(); }
 
+int pcg_solve_core(imsmg_ctx *c, const double *b_dev, double *x_dev, double rtol, imsmg_info *info);
+void destroy_graph(imsmg_ctx *c);
+
+// The uniform smoother as judge of the network's weights: PCG iterations on a
+// fixed probe b = A v (x0 = 0, rtol 1e-8), once with gamma on the levels whose
+// network weights were kept, once with those weights; the network's weights
+// stay only if they need fewer iterations.
+void judge_learned(imsmg_ctx *c) {
+  std::vector<int> lv_on;
+  for (int l = 1; l < int(c->lv.size()); ++l)
+    if (c->lv[l].learned_status == 1) lv_on.push_back(l);
+  if (lv_on.empty()) return;
+  Level &F = c->lv.back();
+  const int n = F.n;
+  std::vector<void *> tmp;
+  struct TmpFree {
+    std::vector<void *> &v;
+    ~TmpFree() { free_list(v); }
+  } tf{tmp};
+  std::vector<double> v(n);
+  for (int i = 0; i < n; ++i) v[i] = 1.0 + 0.5 * std::sin(0.7 * i + 0.3) + 0.25 * std::cos(1.9 * i);
+  double *dv = dalloc<double>(tmp, n), *db = dalloc<double>(tmp, n), *dx = dalloc<double>(tmp, n);
+  h2d(c->stream, dv, v.data(), n);
+  launch_scatter(c->stream, n, F.row_lat, dv, F.x);
+  apply_A64(c, F, F.x, F.rh);
+  launch_gather(c->stream, n, F.row_lat, F.rh, db);
+  HIP_CHECK_RET(hipStreamSynchronize(c->stream));
+  auto iterations = [&]() {
+    HIP_CHECK_RET(hipMemsetAsync(dx, 0, size_t(n) * sizeof(double), c->stream));
+    imsmg_info info{};
+    const int rc = pcg_solve_core(c, db, dx, 1e-8, &info);
+    return rc == IMSMG_OK ? info.iterations : (1 << 30);
+  };
+  std::vector<std::vector<double>> learned(c->lv.size());
+  c->factored = true;  // the probe solves run on the factorized hierarchy
+  const int it_net = iterations();
+  for (int l : lv_on) {
+    Level &L = c->lv[l];
+    learned[l] = L.f_w;
+    apply_weights(c, L, std::vector<double>(L.f_w.size(), L.gamma));
+  }
+  destroy_graph(c);
+  const int it_gamma = iterations();
+  destroy_graph(c);
+  c->judge_it[0] = it_gamma;
+  c->judge_it[1] = it_net;
+  if (it_net < it_gamma)
+    for (int l : lv_on) apply_weights(c, c->lv[l], learned[l]);
+  else
+    for (int l : lv_on) c->lv[l].learned_status = -2;
+  c->factored = false;
+}
+
 // Two-grid objective of level 1 of a two-level hierarchy (see imsmg.h).
 void two_grid(imsmg_ctx *c, int m, const double *Z, int k, double *J, double *grad) {
   if (c->lv.size() != 2) bad("the two-grid objective needs a two-level hierarchy");
@@ -1778,6 +1834,10 @@ void destroy_graph(imsmg_ctx *c) {
   if (c->graph) {
     (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;
+  }
+  if (c->vgraph) {
+    (void)hipGraphExecDestroy(c->vgraph);
+    c->vgraph = nullptr;
   }
   if (c->mb.graph) {
     (void)hipGraphExecDestroy(c->mb.graph);
@@ -1924,6 +1984,92 @@ void cg_iteration(imsmg_ctx *c, bool timing) {
                    c->part, c->st, c->opt.max_iter);
 }
 
+// info fields shared by every solve: restarts, fallback flags, setup/factor times
+void fill_info_common(const imsmg_ctx *c, imsmg_info *info, int restarts) {
+  info->restarts = restarts;
+  int flags = 0;
+  for (size_t l = 1; l < c->lv.size() && l < 31; ++l)
+    if (c->lv[l].learned_status < 0) flags |= 1 << l;
+  info->fallback_flags = flags;
+  info->setup_ms = c->setup_ms;
+  info->factor_ms = c->factor_ms;
+}
+
+// CG preconditioned by the V-cycle (imsmg_pcg_solve without the error guard)
+int pcg_solve_core(imsmg_ctx *c, const double *b_dev, double *x_dev, double rtol, imsmg_info *info) {
+  {
+    if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    if (!b_dev || !x_dev) bad("null vector");
+    if (!(rtol > 0.0)) bad("rtol must be positive");
+    auto t0 = std::chrono::steady_clock::now();
+    Level &F = c->lv.back();
+    hipStream_t s = c->stream;
+    const bool timing = c->opt.timing != 0;
+    launch_scatter(s, F.n, F.row_lat, b_dev, c->bs);
+    launch_scatter(s, F.n, F.row_lat, x_dev, c->xs);
+    CGState h{};
+    int restarts = 0;
+    while (true) {
+      launch_cg_init(s, F.n, F.K, F.op64, F.row_lat, F.meta, c->xs, c->bs, F.r, c->part, c->st, rtol, restarts > 0);
+      launch_diag_scale(s, F.n, F.row_lat, F.c, F.r, F.xs, &c->st->done);
+      HIP_CHECK_RET(hipGetLastError());
+      const int m = c->opt.check_every;
+      const bool graph = c->opt.use_graph && !timing;
+      if (graph && !c->graph) {
+        hipGraph_t g = nullptr;
+        HIP_CHECK_RET(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < m; ++k) cg_iteration(c, false);
+        HIP_CHECK_RET(hipStreamEndCapture(s, &g));
+        hipError_t e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIP_CHECK_RET(e);
+        c->graph_iters = m;
+      }
+      while (true) {
+        if (graph) {
+          HIP_CHECK_RET(hipGraphLaunch(c->graph, s));
+        } else {
+          for (int k = 0; k < m; ++k) cg_iteration(c, timing);
+        }
+        HIP_CHECK_RET(hipGetLastError());
+        HIP_CHECK_RET(hipMemcpyAsync(&h, c->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+        HIP_CHECK_RET(hipStreamSynchronize(s));
+        if (timing) collect_timing(c);
+        if (h.done) break;
+      }
+      // true residual ||b - A x|| / ||b||
+      launch_cg_true_residual(s, F.n, F.K, F.op64, F.row_lat, F.meta, c->xs, c->bs, c->part, c->st);
+      HIP_CHECK_RET(hipMemcpyAsync(&h, c->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+      HIP_CHECK_RET(hipStreamSynchronize(s));
+      const double true_rel = h.bb > 0.0 ? std::sqrt(h.aux / h.bb) : 0.0;
+      if (h.status == 0 && true_rel > rtol && restarts < 3 && h.iters < c->opt.max_iter) {
+        ++restarts;  // recursive residual drifted: restart from the current x
+        continue;
+      }
+      launch_gather(s, F.n, F.row_lat, c->xs, x_dev);
+      HIP_CHECK_RET(hipStreamSynchronize(s));
+      // the solve's criterion is the true relative residual: a solve that ends
+      // above rtol (restarts used up, or max_iter reached) has not converged
+      if (h.status == 0 && true_rel > rtol) h.status = IMSMG_ERR_NOT_CONVERGED;
+      if (info) {
+        fill_info_common(c, info, restarts);
+        info->status = h.status;
+        info->iterations = h.iters;
+        info->rel_res = h.r0sq > 0.0 ? std::sqrt(h.rr / h.r0sq) : 0.0;
+        info->true_rel_res = true_rel;
+        info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      }
+      if (h.status != 0) {
+        c->err = h.status == IMSMG_ERR_NOT_CONVERGED ? "CG did not reach rtol (true relative residual)"
+                 : h.status == IMSMG_ERR_NOT_SPD     ? "CG breakdown: p.Ap <= 0"
+                                                     : "NaN or Inf in the CG iteration";
+        return int(h.status);
+      }
+      return IMSMG_OK;
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -1980,6 +2126,7 @@ int imsmg_create(imsmg_ctx **out, int device, void *stream) {
 int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *R, const imsmg_patches *P,
                 const imsmg_lattice *Lt, const imsmg_elements *E, const imsmg_options *opt) {
   return guarded(c, [&]() -> int {
+    const auto t_setup0 = std::chrono::steady_clock::now();
     if (nlevels < 1 || nlevels > 16 || !A || !Lt) bad("bad level count or null arrays");
     if (nlevels > 1 && (!R || !P)) bad("R and P are required with more than one level");
     destroy_graph(c);
@@ -1999,6 +2146,7 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
     if (c->opt.coarse_smoother < -1 || c->opt.coarse_smoother > IMSMG_MULTIPLICATIVE) bad("unknown coarse_smoother");
     if (c->opt.cycle != 1 && c->opt.cycle != 2) bad("cycle must be 1 (V) or 2 (W)");
     if (c->opt.flag_min_rows < 0) bad("flag_min_rows must be >= 0");
+    if (c->opt.use_learned < 0 || c->opt.use_learned > 2) bad("use_learned must be 0, 1 or 2");
     if (c->opt.use_learned && uses_ms(c->opt, nlevels)) bad("use_learned needs the additive smoother on every level");
     c->lv.resize(nlevels);
     for (int l = 0; l < nlevels; ++l) {
@@ -2074,6 +2222,7 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
     c->part = dalloc<double>(c->owned, 2 * size_t(std::max(reduction_blocks(F.n), F.op64.ntiles)) + 64);
     HIP_CHECK_RET(hipStreamSynchronize(c->stream));
     c->ready = true;
+    c->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_setup0).count();
     return IMSMG_OK;
   });
 }
@@ -2104,16 +2253,20 @@ int imsmg_factor_patches(imsmg_ctx *c) {
   }
   return guarded(c, [&]() -> int {
     if (!c->ready) bad("setup first", IMSMG_ERR_STATE);
+    const auto t_factor0 = std::chrono::steady_clock::now();
     destroy_graph(c);
     free_list(c->factor_owned);
     c->factored = false;
     for (int l = 1; l < int(c->lv.size()); ++l) factor_level(c, l);
     factor_coarsest(c);
-    if (c->opt.use_learned)
+    if (c->opt.use_learned) {
       for (int l = 1; l < int(c->lv.size()); ++l)
         if (L_has_no_user_weights(c->lv[l])) learned_weights(c, l);
+      if (c->opt.use_learned == 1) judge_learned(c);
+    }
     for (int l = 1; l < int(c->lv.size()); ++l) tune_general(c, c->lv[l]);
     c->factored = true;
+    c->factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_factor0).count();
     return IMSMG_OK;
   });
 }
@@ -2151,15 +2304,45 @@ int imsmg_get_gamma(imsmg_ctx *c, int level, double *gamma) {
   });
 }
 
+// The launches of one V-cycle from the staged compact residual c_in to the
+// compact correction c_out (captured once per factorization when graphs are
+// on; the caller's vectors are copied in and out around it).
+void vcycle_body(imsmg_ctx *c, bool timing) {
+  Level &F = c->lv.back();
+  launch_scatter(c->stream, F.n, F.row_lat, c->c_in, F.r);
+  launch_diag_scale(c->stream, F.n, F.row_lat, F.c, F.r, F.xs, c->zero_flag);
+  vcycle_level(c, int(c->lv.size()) - 1, c->zero_flag, timing);
+  launch_gather(c->stream, F.n, F.row_lat, F.x, c->c_out);
+}
+
+// Runs one V-cycle on c_in (graph replay when graphs are on and no kernel is
+// timed); returns without synchronizing.
+void vcycle_launch(imsmg_ctx *c) {
+  const bool timing = c->opt.timing != 0;
+  if (c->opt.use_graph && !timing) {
+    if (!c->vgraph) {
+      hipGraph_t g = nullptr;
+      HIP_CHECK_RET(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      vcycle_body(c, false);
+      HIP_CHECK_RET(hipStreamEndCapture(c->stream, &g));
+      hipError_t e = hipGraphInstantiate(&c->vgraph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIP_CHECK_RET(e);
+    }
+    HIP_CHECK_RET(hipGraphLaunch(c->vgraph, c->stream));
+  } else {
+    vcycle_body(c, timing);
+  }
+}
+
 int imsmg_vcycle(imsmg_ctx *c, const double *r_dev, double *z_dev) {
   return guarded(c, [&]() -> int {
     if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
     if (!r_dev || !z_dev) bad("null vector");
     Level &F = c->lv.back();
-    launch_scatter(c->stream, F.n, F.row_lat, r_dev, F.r);
-    launch_diag_scale(c->stream, F.n, F.row_lat, F.c, F.r, F.xs, c->zero_flag);
-    vcycle_level(c, int(c->lv.size()) - 1, c->zero_flag, c->opt.timing != 0);
-    launch_gather(c->stream, F.n, F.row_lat, F.x, z_dev);
+    HIP_CHECK_RET(hipMemcpyAsync(c->c_in, r_dev, size_t(F.n) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    vcycle_launch(c);
+    HIP_CHECK_RET(hipMemcpyAsync(z_dev, c->c_out, size_t(F.n) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     HIP_CHECK_RET(hipGetLastError());
     HIP_CHECK_RET(hipStreamSynchronize(c->stream));
     if (c->opt.timing) collect_timing(c);
@@ -2167,77 +2350,45 @@ int imsmg_vcycle(imsmg_ctx *c, const double *r_dev, double *z_dev) {
   });
 }
 
-int imsmg_pcg_solve(imsmg_ctx *c, const double *b_dev, double *x_dev, double rtol, imsmg_info *info) {
+int imsmg_vcycle_time(imsmg_ctx *c, const double *r_dev, int reps, double *median_ms, double *mean_ms) {
   return guarded(c, [&]() -> int {
     if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
-    if (!b_dev || !x_dev) bad("null vector");
-    if (!(rtol > 0.0)) bad("rtol must be positive");
-    auto t0 = std::chrono::steady_clock::now();
+    if (!r_dev || reps < 1 || reps > 100000) bad("bad V-cycle timing arguments");
+    if (c->opt.timing) bad("imsmg_vcycle_time needs opt.timing = 0");
     Level &F = c->lv.back();
-    hipStream_t s = c->stream;
-    const bool timing = c->opt.timing != 0;
-    launch_scatter(s, F.n, F.row_lat, b_dev, c->bs);
-    launch_scatter(s, F.n, F.row_lat, x_dev, c->xs);
-    CGState h{};
-    int restarts = 0;
-    while (true) {
-      launch_cg_init(s, F.n, F.K, F.op64, F.row_lat, F.meta, c->xs, c->bs, F.r, c->part, c->st, rtol, restarts > 0);
-      launch_diag_scale(s, F.n, F.row_lat, F.c, F.r, F.xs, &c->st->done);
-      HIP_CHECK_RET(hipGetLastError());
-      const int m = c->opt.check_every;
-      const bool graph = c->opt.use_graph && !timing;
-      if (graph && !c->graph) {
-        hipGraph_t g = nullptr;
-        HIP_CHECK_RET(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < m; ++k) cg_iteration(c, false);
-        HIP_CHECK_RET(hipStreamEndCapture(s, &g));
-        hipError_t e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        HIP_CHECK_RET(e);
-        c->graph_iters = m;
+    HIP_CHECK_RET(hipMemcpyAsync(c->c_in, r_dev, size_t(F.n) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    vcycle_launch(c);  // warm (and capture)
+    std::vector<hipEvent_t> ev(2 * size_t(reps));
+    for (auto &e : ev) HIP_CHECK_RET(hipEventCreate(&e));
+    struct EvFree {
+      std::vector<hipEvent_t> &v;
+      ~EvFree() {
+        for (auto e : v) (void)hipEventDestroy(e);
       }
-      while (true) {
-        if (graph) {
-          HIP_CHECK_RET(hipGraphLaunch(c->graph, s));
-        } else {
-          for (int k = 0; k < m; ++k) cg_iteration(c, timing);
-        }
-        HIP_CHECK_RET(hipGetLastError());
-        HIP_CHECK_RET(hipMemcpyAsync(&h, c->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
-        HIP_CHECK_RET(hipStreamSynchronize(s));
-        if (timing) collect_timing(c);
-        if (h.done) break;
-      }
-      // true residual ||b - A x|| / ||b||
-      launch_cg_true_residual(s, F.n, F.K, F.op64, F.row_lat, F.meta, c->xs, c->bs, c->part, c->st);
-      HIP_CHECK_RET(hipMemcpyAsync(&h, c->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
-      HIP_CHECK_RET(hipStreamSynchronize(s));
-      const double true_rel = h.bb > 0.0 ? std::sqrt(h.aux / h.bb) : 0.0;
-      if (h.status == 0 && true_rel > rtol && restarts < 3 && h.iters < c->opt.max_iter) {
-        ++restarts;  // recursive residual drifted: restart from the current x
-        continue;
-      }
-      launch_gather(s, F.n, F.row_lat, c->xs, x_dev);
-      HIP_CHECK_RET(hipStreamSynchronize(s));
-      // the solve's criterion is the true relative residual: a solve that ends
-      // above rtol (restarts used up, or max_iter reached) has not converged
-      if (h.status == 0 && true_rel > rtol) h.status = IMSMG_ERR_NOT_CONVERGED;
-      if (info) {
-        info->status = h.status;
-        info->iterations = h.iters;
-        info->rel_res = h.r0sq > 0.0 ? std::sqrt(h.rr / h.r0sq) : 0.0;
-        info->true_rel_res = true_rel;
-        info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-      }
-      if (h.status != 0) {
-        c->err = h.status == IMSMG_ERR_NOT_CONVERGED ? "CG did not reach rtol (true relative residual)"
-                 : h.status == IMSMG_ERR_NOT_SPD     ? "CG breakdown: p.Ap <= 0"
-                                                     : "NaN or Inf in the CG iteration";
-        return int(h.status);
-      }
-      return IMSMG_OK;
+    } ef{ev};
+    for (int k = 0; k < reps; ++k) {
+      HIP_CHECK_RET(hipEventRecord(ev[2 * k], c->stream));
+      vcycle_launch(c);
+      HIP_CHECK_RET(hipEventRecord(ev[2 * k + 1], c->stream));
     }
+    HIP_CHECK_RET(hipStreamSynchronize(c->stream));
+    std::vector<double> t(reps);
+    double sum = 0.0;
+    for (int k = 0; k < reps; ++k) {
+      float ms = 0.f;
+      HIP_CHECK_RET(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+      t[k] = ms;
+      sum += ms;
+    }
+    std::sort(t.begin(), t.end());
+    if (median_ms) *median_ms = reps % 2 ? t[reps / 2] : 0.5 * (t[reps / 2 - 1] + t[reps / 2]);
+    if (mean_ms) *mean_ms = sum / reps;
+    return IMSMG_OK;
   });
+}
+
+int imsmg_pcg_solve(imsmg_ctx *c, const double *b_dev, double *x_dev, double rtol, imsmg_info *info) {
+  return guarded(c, [&]() -> int { return pcg_solve_core(c, b_dev, x_dev, rtol, info); });
 }
 
 int imsmg_apply_operator(imsmg_ctx *c, int level, const double *x, double *y) {
@@ -2559,6 +2710,7 @@ int imsmg_pcg_solve_multi(imsmg_ctx *c, int nrhs, const double *B_dev, double *X
     if (h.status == 0 && missed) h.status = IMSMG_ERR_NOT_CONVERGED;
     if (infos)
       for (int k = 0; k < nrhs; ++k) {
+        fill_info_common(c, &infos[k], restarts);
         infos[k].status = h.status == IMSMG_ERR_NOT_CONVERGED ? (true_rel[k] > rtol ? h.status : 0) : h.status;
         infos[k].iterations = h.iters[k];
         infos[k].rel_res = h.r0sq[k] > 0.0 ? std::sqrt(h.rr[k] / h.r0sq[k]) : 0.0;

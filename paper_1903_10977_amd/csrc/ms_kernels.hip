@@ -22,7 +22,11 @@ namespace {
 constexpr int kMsBlock = 256;
 }
 
-template <int K, typename V>
+// LANES lanes share a row (slots lane, lane + LANES, ...), then add their
+// partial sums in a fixed shuffle order: a colour holds a small fraction of
+// the level's rows, so one lane per row would leave most of the chip idle and
+// each lane with a long chain of gathers.
+template <int K, typename V, int LANES>
 __global__ __launch_bounds__(kMsBlock) void k_ms_colour(int m, const int32_t *__restrict__ rows,
                                                         const double *__restrict__ cf, OpView<V> op,
                                                         const int32_t *__restrict__ row_lat,
@@ -31,16 +35,35 @@ __global__ __launch_bounds__(kMsBlock) void k_ms_colour(int m, const int32_t *__
                                                         double *__restrict__ rh, const int32_t *__restrict__ done,
                                                         int Kdyn) {
   if (done && *done) return;
-  const int t = blockIdx.x * kMsBlock + threadIdx.x;
-  if (t >= m) return;
-  const int i = rows[t];
-  const int L = row_lat[i];
-  const double res = r[L] - op_row<K, V>(meta[i], op, x, L, Kdyn);
-  const double c = cf[t];
-  if (c != 0.0)
-    x[L] += c * res;
-  else
-    rh[L] = res;
+  const int tid = blockIdx.x * kMsBlock + threadIdx.x;
+  const int t = tid / LANES, lane = tid % LANES;
+  const bool ok = t < m;
+  double part = 0.0;
+  int L = 0;
+  if (ok) {
+    const int i = rows[t];
+    L = row_lat[i];
+    const unsigned g = meta[i] & kMetaIndex;
+    const bool uni = g == kMetaIndex;
+    const size_t nv = size_t(op.nv);
+    const int KK = K > 0 ? K : Kdyn;
+#pragma unroll
+    for (int s = lane; s < (K > 0 ? K : IMSMG_MAX_SLOTS); s += LANES) {
+      if (K == 0 && s >= KK) break;
+      const double a = double(uni ? op.ref[s] : op.val[stored_at<V>(nv, g, s)]);
+      part += a * x[L + op.off.off[s]];
+    }
+  }
+#pragma unroll
+  for (int o = LANES / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, LANES);
+  if (ok && lane == 0) {
+    const double res = r[L] - part;
+    const double c = cf[t];
+    if (c != 0.0)
+      x[L] += c * res;
+    else
+      rh[L] = res;
+  }
 }
 
 template <typename V>
@@ -48,14 +71,15 @@ static void dispatch_ms_colour(hipStream_t s, int m, const int32_t *rows, const 
                                const OpView<V> &op, const int32_t *row_lat, const uint32_t *meta, const double *r,
                                double *x, double *rh, const int32_t *done) {
   if (m <= 0) return;
-  dim3 g((m + kMsBlock - 1) / kMsBlock), t(kMsBlock);
+  constexpr int LN = 8;
+  dim3 g((size_t(m) * LN + kMsBlock - 1) / kMsBlock), t(kMsBlock);
   switch (K) {
-    case 9: k_ms_colour<9, V><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
-    case 25: k_ms_colour<25, V><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
-    case 49: k_ms_colour<49, V><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
-    case 27: k_ms_colour<27, V><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
-    case 125: k_ms_colour<125, V><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
-    default: k_ms_colour<0, V><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
+    case 9: k_ms_colour<9, V, LN><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
+    case 25: k_ms_colour<25, V, LN><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
+    case 49: k_ms_colour<49, V, LN><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
+    case 27: k_ms_colour<27, V, LN><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
+    case 125: k_ms_colour<125, V, LN><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
+    default: k_ms_colour<0, V, LN><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
   }
 }
 

@@ -1377,6 +1377,22 @@ int imsmg_gen_get_block_colours(const imsmg_gen_problem *p, int level, int kind,
   return 0;
 }
 
+int imsmg_gen_lattice_colours(int n, const int32_t *dof_to_lattice, int nf1, int dim, int q, int stride,
+                              int32_t *colour) {
+  if (n < 0 || (n > 0 && (!dof_to_lattice || !colour)) || nf1 < 1 || dim < 1 || dim > 3 || q < 1 || stride < 1) {
+    g_err = "bad lattice colour arguments";
+    return -1;
+  }
+  for (int j = 0; j < n; ++j) {
+    int m[3] = {0, 0, 0};
+    lat_multi(dof_to_lattice[j], nf1, dim, m);
+    int c = 0;
+    for (int a = dim - 1; a >= 0; --a) c = c * q + (m[a] / stride) % q;
+    colour[j] = c;
+  }
+  return 0;
+}
+
 int imsmg_gen_get_elements(const imsmg_gen_problem *p, int level, int32_t *eptr, int32_t *eidx, int32_t *elem) {
   if (!p || level < 0 || level >= int(p->P.lv.size())) { g_err = "bad level"; return -1; }
   const LevelData &L = p->P.lv[level];

@@ -36,6 +36,7 @@ def _load():
     lib.imsmg_gen_get_restriction.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.imsmg_gen_get_blocks.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.imsmg_gen_get_block_colours.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+    lib.imsmg_gen_lattice_colours.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p]
     lib.imsmg_gen_get_two_scale.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
     lib.imsmg_gen_get_rhs.argtypes = [C.c_void_p, C.c_void_p]
     lib.imsmg_gen_get_elements.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -201,3 +202,24 @@ def generate(w, with_mass: bool = False, nthreads: int = 0, orders=None) -> Gene
     finally:
         lib.imsmg_gen_free(h)
     return GeneratedProblem(workload=w, levels=levels, b=b, M=M, seconds=secs)
+
+
+def with_coarse_diagonal(problem, kind: str = "jacobi"):
+    """A copy of a generated problem whose levels between the finest and the
+    coarsest carry one block per function (Remark rem:coarseGS: diagonal
+    smoothing on the coarser levels), coloured by the lattice rule for
+    one-function blocks; the other arrays are shared."""
+    import dataclasses
+    lib = _load()
+    w = dataclasses.replace(problem.workload, coarse_smoother=kind)
+    levels = list(problem.levels)
+    for l in range(1, len(levels) - 1):
+        lev = levels[l]
+        n = lev.n
+        col = np.zeros(n, dtype=np.int32)
+        d2l = np.ascontiguousarray(lev.dof_to_lattice, dtype=np.int32)
+        assert lib.imsmg_gen_lattice_colours(n, _ptr(d2l), lev.lattice[0], w.dim, w.degree + 1, 1, _ptr(col)) == 0
+        levels[l] = dataclasses.replace(lev, block_ptr=np.arange(n + 1, dtype=np.int32),
+                                        block_idx=np.arange(n, dtype=np.int32),
+                                        block_assoc=np.arange(n, dtype=np.int32), block_colour=col)
+    return dataclasses.replace(problem, workload=w, levels=levels)

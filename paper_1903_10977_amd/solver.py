@@ -65,7 +65,7 @@ class LevelStats(C.Structure):
 
 
 SYMBOLS = ["imsmg_default_options", "imsmg_create", "imsmg_setup", "imsmg_set_patch_weights",
-           "imsmg_factor_patches", "imsmg_get_patches", "imsmg_get_patch_colours", "imsmg_get_gamma", "imsmg_vcycle", "imsmg_pcg_solve",
+           "imsmg_factor_patches", "imsmg_get_patches", "imsmg_get_patch_colours", "imsmg_get_gamma", "imsmg_vcycle", "imsmg_vcycle_time", "imsmg_pcg_solve",
            "imsmg_apply_operator", "imsmg_apply_smoother", "imsmg_apply_restriction", "imsmg_apply_prolongation",
            "imsmg_coarse_solve", "imsmg_get_level_stats", "imsmg_kernel_time", "imsmg_last_error", "imsmg_destroy",
            "imsmg_load_mlp", "imsmg_get_patch_features", "imsmg_get_patch_weights", "imsmg_set_block_weights",
@@ -104,6 +104,7 @@ def load():
     lib.imsmg_get_gamma.argtypes = [vp, i32, C.POINTER(C.c_double)]
     lib.imsmg_get_patch_colours.argtypes = [vp, i32, C.POINTER(C.c_int32), vp]
     lib.imsmg_vcycle.argtypes = [vp, vp, vp]
+    lib.imsmg_vcycle_time.argtypes = [vp, vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.imsmg_pcg_solve.argtypes = [vp, vp, vp, dbl, C.POINTER(Info)]
     for f in ("imsmg_apply_operator", "imsmg_apply_smoother", "imsmg_apply_restriction", "imsmg_apply_prolongation"):
         getattr(lib, f).argtypes = [vp, i32, vp, vp]
@@ -379,6 +380,13 @@ class Solver:
         self._sync()
         self._check(self.lib.imsmg_vcycle(self.h, self._dev(r), self._dev(z)))
         return z
+
+    def vcycle_time(self, r, reps: int = 50):
+        """(median, mean) ms of one V-cycle over reps timed cycles."""
+        med, mean = C.c_double(), C.c_double()
+        self._sync()
+        self._check(self.lib.imsmg_vcycle_time(self.h, self._dev(r), reps, C.byref(med), C.byref(mean)))
+        return med.value, mean.value
 
     def pcg(self, b, x, rtol: float = 1e-8, raise_on_error: bool = True) -> SolveInfo:
         info = Info()

@@ -158,7 +158,7 @@ def test_learned_weights_factorization_and_solve(b3):
     w, g, op, eta = _two_level()
     theta = np.zeros(5313, np.float32)
     theta[-1] = b3
-    sol = _solver(S, g, use_learned=1)
+    sol = _solver(S, g, use_learned=2)  # network and stability check, no iteration judge
     sol.load_mlp(theta).factor()
     om, status, lam = sol.weights(1)
     sm = op.smoothers[1]
@@ -212,3 +212,28 @@ def test_trained_gyroid_network_gain_over_uniform_damping():
         sol.close()
     print(f"[gain] gamma {its['gamma']} iterations, learned {its['learned']}", flush=True)
     assert its["learned"] < its["gamma"]
+
+
+def test_iteration_judge_rejects_slower_network_weights():
+    """The uniform smoother judges the network's weights by cost: a constant
+    network with omega = gamma e^-2.5 is stable (lambda_max(S A) small) but
+    smooths far too little, so PCG on the probe needs more iterations than
+    with gamma; factorization must then keep gamma (learned_status -2,
+    reported in the solve's fallback flags) and the solve equals the
+    oracle's with gamma."""
+    S = _gpu()
+    w, g, op, eta = _two_level()
+    theta = np.zeros(5313, np.float32)
+    theta[-1] = -2.5
+    sol = _solver(S, g, use_learned=1)
+    sol.load_mlp(theta).factor()
+    om, status, lam = sol.weights(1)
+    sm = op.smoothers[1]
+    assert status == -2 and np.allclose(om, sm.gamma, rtol=1e-12), status
+    x_ref, it_ref, _ = op.solve(tol=1e-8)
+    b = torch.tensor(g.b, device="cuda:0")
+    x = torch.zeros_like(b)
+    info = sol.pcg(b, x, rtol=1e-8)
+    assert info.true_rel_res <= 1e-8 and abs(info.iterations - it_ref) <= 1
+    assert info.fallback_flags == 2
+    sol.close()
