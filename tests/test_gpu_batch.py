@@ -67,3 +67,45 @@ def test_concurrent_batch_matches_sequential_and_converges():
     print(f"[case batch] BF16 patch GEMM iterations {[max(x.iterations for x in inf) for inf in infos2]} "
           f"(CSR {[max(x.iterations for x in inf) for inf in infos_c]})", flush=True)
     bs2.close()
+
+
+@pytest.mark.parametrize("index", [16, 48, 17])
+def test_batch_problem_matches_the_oracle(index):
+    """One batch problem per degree p = 1, 2, 3 (64^2 elements, depth 4,
+    3 levels) in a 3-problem batch, columns 0 and 5 of its 16 load vectors
+    M u, against the oracle's PCG on the same right-hand sides (the oracle's
+    M is its own mass matrix; both sides draw u from the same seed):
+    residual <= 1e-8 with the oracle's A, iterations within one of the
+    oracle's, L2(Omega) within 1e-6 of its solution."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import multigrid as MG
+    from oracle import problem as P
+    from paper_1903_10977_amd import batch as BT
+    from paper_1903_10977_amd import generator as GN
+    from paper_1903_10977_amd import solver as S
+    S.load()
+    idx = [index, 1, 2]
+    probs = [GN.generate(W.batched_c4(i), with_mass=True) for i in idx]
+    w = W.batched_c4(index)
+    print(f"[case batch-oracle {index}] n={w.n} p={w.degree}", flush=True)
+    op = P.build(w)
+    bs = BT.BatchSolver(probs, nrhs=16, precision=S.FP64, workers=3)
+    rng = np.random.Generator(np.random.PCG64(1000 + index))
+    U = rng.standard_normal((16, probs[0].fine.n))
+    B = bs.rhs()
+    B[0] = torch.tensor(np.stack([op.system.M @ u for u in U]), device="cuda:0")
+    X, infos, _ = bs.solve(B)
+    M = op.system.M
+    for k in (0, 5):
+        b = B[0][k].cpu().numpy()
+        xo, ito, _ = MG.pcg(op.A, b, op.vcycle.apply, tol=1e-8)
+        xg = X[0][k].cpu().numpy()
+        res = np.linalg.norm(b - op.A @ xg) / np.linalg.norm(b)
+        e = xg - xo
+        rel = np.sqrt(e @ (M @ e)) / np.sqrt(xo @ (M @ xo))
+        print(f"[case batch-oracle {index}] column {k}: iterations gpu {infos[0][k].iterations} oracle {ito}, "
+              f"residual {res:.2e}, L2 {rel:.2e}", flush=True)
+        assert res <= 1.01e-8 and rel <= 1e-6
+        assert abs(infos[0][k].iterations - ito) <= 1
+    bs.close()

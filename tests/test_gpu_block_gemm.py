@@ -56,13 +56,30 @@ def _solver(S, g, **opt):
     return S.Solver(0).setup(g, o).factor()
 
 
+ORACLE = ("cubic-discs", "linear-discs")
+
+
+def _mrel(e, ref, M):
+    return float(np.sqrt(max(e @ (M @ e), 0.0)) / np.sqrt(ref @ (M @ ref)))
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_patch_gemm_vcycle(name):
+    """One multi-column V-cycle on 16 load vectors M u (finite-element
+    consistent: they do not excite the near-null cut modes) with the general
+    blocks as CSR (0), FP64 patch GEMMs (1) and BF16 patch GEMMs (2), per
+    column in L2(Omega) and in the energy norm: FP64 GEMMs against the
+    oracle's V-cycle within 1e-7 (the single-column bar; small cases) and
+    against CSR within 1e-12; BF16 within 1e-2 of both (operands rounded to
+    8 significant bits on the blocks with cond(A_j) <= 16, FP32
+    accumulation: at most ~2 x 2^-8 relative on those blocks' share of the
+    correction), and further from CSR than FP64 where such blocks exist."""
     S = _gpu()
     w, g = _problem(name)
     n = g.fine.n
     rng = np.random.Generator(np.random.PCG64(71))
-    Rm = torch.tensor(rng.standard_normal((16, n)), device="cuda:0")
+    M = g.M
+    Rm = torch.tensor(np.stack([M @ u for u in rng.standard_normal((16, n))]), device="cuda:0")
     Z, nlp = {}, 0
     for mode in (0, 1, 2):
         sol = _solver(S, g, block_gemm=mode)
@@ -74,14 +91,31 @@ def test_patch_gemm_vcycle(name):
         nlp = sum(x["bf16_blocks"] for x in st)
         Z[mode] = sol.vcycle_multi(Rm).cpu().numpy()
         sol.close()
-    scale = np.abs(Z[0]).max()
-    d1 = np.abs(Z[1] - Z[0]).max()
-    d2 = np.abs(Z[2] - Z[0]).max()
-    print(f"[case {name}] FP64 patch GEMM {d1 / scale:.2e}, BF16 {d2 / scale:.2e}", flush=True)
-    assert d1 <= 1e-12 * scale
-    assert d2 <= 2e-2 * scale
+    A = g.fine.A
+    R = Rm.cpu().numpy()
+    ref_cycle = None
+    if name in ORACLE:
+        from oracle import problem as P
+        op = P.build(w)
+        ref_cycle = op.vcycle.apply
+    w1 = w2 = a2 = wo1 = wo2 = 0.0
+    for k in range(16):
+        z0 = Z[0][k]
+        w1 = max(w1, _mrel(Z[1][k] - z0, z0, M))
+        w2 = max(w2, _mrel(Z[2][k] - z0, z0, M))
+        e = Z[2][k] - z0
+        a2 = max(a2, float(np.sqrt(max(e @ (A @ e), 0.0)) / np.sqrt(z0 @ (A @ z0))))
+        if ref_cycle is not None and k < 4:
+            zr = ref_cycle(R[k])
+            wo1 = max(wo1, _mrel(Z[1][k] - zr, zr, M))
+            wo2 = max(wo2, _mrel(Z[2][k] - zr, zr, M))
+    print(f"[case {name}] L2 vs CSR: FP64 GEMM {w1:.2e}, BF16 {w2:.2e} (energy {a2:.2e}); "
+          f"vs oracle: FP64 GEMM {wo1:.2e}, BF16 {wo2:.2e}", flush=True)
+    assert w1 <= 1e-12 and w2 <= 1e-2 and a2 <= 1e-2
+    if ref_cycle is not None:
+        assert wo1 <= 1e-7 and wo2 <= 1e-2
     if nlp > 0:
-        assert d2 > d1  # the BF16 blocks ran
+        assert w2 > w1  # the BF16 blocks ran
 
 
 @pytest.mark.parametrize("name", ["cubic-discs", "discs-256"])
