@@ -154,6 +154,11 @@ struct Level {
   std::vector<int32_t> ms_cptr;
   int32_t *ms_rows = nullptr;
   double *ms_cf = nullptr;
+  // colour-ordered copy of the stored rows' values (a row as often as colours
+  // touch it): ms_vidx per list entry (-1: reference stencil)
+  int32_t *ms_vidx = nullptr;
+  double *ms_val64 = nullptr;
+  float *ms_val32 = nullptr;
   struct MsGeneral {
     int ng = 0;
     int32_t *grow_lat = nullptr, *sptr = nullptr, *scol = nullptr;
@@ -772,11 +777,11 @@ void ms_sweep(imsmg_ctx *c, Level &L, bool forward, const int32_t *done) {
     const int a = L.ms_cptr[cc], m = L.ms_cptr[cc + 1] - a;
     if (m == 0) continue;
     if (mixed(c))
-      launch_ms_colour(c->stream, m, L.ms_rows + a, L.ms_cf + a, L.K, L.op32, L.row_lat, L.meta, L.r, L.x, L.rh,
-                       done);
+      launch_ms_colour(c->stream, m, L.ms_rows + a, L.ms_cf + a, L.ms_vidx + a, L.ms_val32, L.K, L.op32, L.row_lat,
+                       L.r, L.x, L.rh, done);
     else
-      launch_ms_colour(c->stream, m, L.ms_rows + a, L.ms_cf + a, L.K, L.op64, L.row_lat, L.meta, L.r, L.x, L.rh,
-                       done);
+      launch_ms_colour(c->stream, m, L.ms_rows + a, L.ms_cf + a, L.ms_vidx + a, L.ms_val64, L.K, L.op64, L.row_lat,
+                       L.r, L.x, L.rh, done);
     const Level::MsGeneral &G = L.ms_gen[cc];
     if (G.ng > 0) launch_smooth_general(c->stream, G.ng, G.grow_lat, G.sptr, G.scol, G.sval, L.rh, L.x, done, 4);
   }
@@ -990,6 +995,31 @@ void build_ms(imsmg_ctx *c, Level &L, const std::vector<int32_t> &fptr, const st
   if (!all_rows.empty()) {
     h2d(s, L.ms_rows, all_rows.data(), all_rows.size());
     h2d(s, L.ms_cf, all_cf.data(), all_cf.size());
+  }
+  // colour-ordered copy of the stored rows' values: one entry per list entry
+  // whose row keeps its own values
+  std::vector<int32_t> vidx(all_rows.size(), -1), vg;
+  for (size_t t = 0; t < all_rows.size(); ++t) {
+    const uint32_t g = L.h_meta[all_rows[t]] & kMetaIndex;
+    if (g != kMetaIndex) {
+      vidx[t] = int32_t(vg.size());
+      vg.push_back(int32_t(g));
+    }
+  }
+  L.ms_vidx = dalloc<int32_t>(c->factor_owned, std::max<size_t>(vidx.size(), 1));
+  if (!vidx.empty()) h2d(s, L.ms_vidx, vidx.data(), vidx.size());
+  {
+    const int ne = int(vg.size());
+    int32_t *d_g = dalloc<int32_t>(c->factor_owned, std::max(ne, 1));
+    if (ne) h2d(s, d_g, vg.data(), vg.size());
+    const int KP64 = (L.K + 1) / 2 * 2, KP32 = (L.K + 3) / 4 * 4;
+    L.ms_val64 = dalloc<double>(c->factor_owned, std::max<size_t>(size_t(ne) * KP64, 2));
+    launch_ms_pack(s, ne, L.K, KP64, d_g, L.op64.val, L.op64.nv, L.ms_val64);
+    if (mixed(c)) {
+      L.ms_val32 = dalloc<float>(c->factor_owned, std::max<size_t>(size_t(ne) * KP32, 4));
+      launch_ms_pack(s, ne, L.K, KP32, d_g, L.op32.val, L.op32.nv, L.ms_val32);
+    }
+    HIP_CHECK_RET(hipGetLastError());
   }
   L.ms_gen.assign(C, Level::MsGeneral{});
   for (int cc = 0; cc < C; ++cc) {

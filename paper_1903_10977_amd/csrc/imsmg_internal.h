@@ -159,13 +159,17 @@ void launch_dense_gemv(hipStream_t s, int n, const int32_t *row_lat, const doubl
                        const int32_t *done);
 void launch_scatter(hipStream_t s, int n, const int32_t *row_lat, const double *src, double *dst);
 // multiplicative Schwarz: one colour's rows (residual of the current x; in-place
-// update of one-function blocks with cf != 0, residual into rh for the others)
-void launch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, int K, const OpView<double> &op,
-                      const int32_t *row_lat, const uint32_t *meta, const double *r, double *x, double *rh,
-                      const int32_t *done);
-void launch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, int K, const OpView<float> &op,
-                      const int32_t *row_lat, const uint32_t *meta, const double *r, double *x, double *rh,
-                      const int32_t *done);
+// update of one-function blocks with cf != 0, residual into rh for the others);
+// stored rows read the colour-ordered value copy (vidx: its entry, -1 = the
+// reference stencil), built by launch_ms_pack from the level's operator values
+void launch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
+                      const double *vals, int K, const OpView<double> &op, const int32_t *row_lat, const double *r,
+                      double *x, double *rh, const int32_t *done);
+void launch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
+                      const float *vals, int K, const OpView<float> &op, const int32_t *row_lat, const double *r,
+                      double *x, double *rh, const int32_t *done);
+void launch_ms_pack(hipStream_t s, int ne, int K, int KP, const int32_t *g, const double *val, int nv, double *out);
+void launch_ms_pack(hipStream_t s, int ne, int K, int KP, const int32_t *g, const float *val, int nv, float *out);
 // active rows of a level vector: op 0: y = 0, 1: y = x, 2: y += x
 void launch_rows_op(hipStream_t s, int n, const int32_t *row_lat, const double *x, double *y, int op,
                     const int32_t *done);

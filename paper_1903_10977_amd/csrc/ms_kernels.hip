@@ -14,6 +14,8 @@
 // the rows written in place belong to one-function blocks of this colour, and
 // no other row of the colour shares an element with them (the colouring's
 // invariant), so no thread reads a value another thread of the launch writes.
+#include <stdexcept>
+
 #include "op_row.h"
 
 namespace imsmg {
@@ -22,36 +24,57 @@ namespace {
 constexpr int kMsBlock = 256;
 }
 
-// LANES lanes share a row (slots lane, lane + LANES, ...), then add their
-// partial sums in a fixed shuffle order: a colour holds a small fraction of
-// the level's rows, so one lane per row would leave most of the chip idle and
-// each lane with a long chain of gathers.
+// LANES lanes share a row, then add their partial sums in a fixed shuffle
+// order: a colour holds a small fraction of the level's rows, so one lane per
+// row would leave most of the chip idle and each lane with a long chain of
+// gathers.  Stored rows read their values from the colour-ordered copy vals
+// (entry e: KP values, slots in order, zero padded) in 16-byte slot groups
+// q = lane, lane + LANES, ...: the LANES lanes of a row read one contiguous
+// 128-byte line per step.  Rows on the level's reference stencil (vidx < 0)
+// read its coefficients.
 template <int K, typename V, int LANES>
 __global__ __launch_bounds__(kMsBlock) void k_ms_colour(int m, const int32_t *__restrict__ rows,
-                                                        const double *__restrict__ cf, OpView<V> op,
+                                                        const double *__restrict__ cf,
+                                                        const int32_t *__restrict__ vidx,
+                                                        const V *__restrict__ vals, OpView<V> op,
                                                         const int32_t *__restrict__ row_lat,
-                                                        const uint32_t *__restrict__ meta,
                                                         const double *__restrict__ r, double *x,
-                                                        double *__restrict__ rh, const int32_t *__restrict__ done,
-                                                        int Kdyn) {
+                                                        double *__restrict__ rh, const int32_t *__restrict__ done) {
   if (done && *done) return;
+  constexpr int G = SlotGroup<V>::G;
+  constexpr int NG = (K + G - 1) / G;
+  constexpr int W = StencilShape<K>::W, P = StencilShape<K>::P, DIM = StencilShape<K>::DIM;
   const int tid = blockIdx.x * kMsBlock + threadIdx.x;
   const int t = tid / LANES, lane = tid % LANES;
   const bool ok = t < m;
   double part = 0.0;
   int L = 0;
+  // lattice offset of slot s (x fastest, reach P per axis)
+  auto off = [&](int s) {
+    const int dx = s % W - P, dy = (s / W) % W - P, dz = DIM == 3 ? s / (W * W) - P : 0;
+    return dx + op.sx * (dy + op.sy * dz);
+  };
   if (ok) {
     const int i = rows[t];
     L = row_lat[i];
-    const unsigned g = meta[i] & kMetaIndex;
-    const bool uni = g == kMetaIndex;
-    const size_t nv = size_t(op.nv);
-    const int KK = K > 0 ? K : Kdyn;
-#pragma unroll
-    for (int s = lane; s < (K > 0 ? K : IMSMG_MAX_SLOTS); s += LANES) {
-      if (K == 0 && s >= KK) break;
-      const double a = double(uni ? op.ref[s] : op.val[stored_at<V>(nv, g, s)]);
-      part += a * x[L + op.off.off[s]];
+    const int e = vidx[t];
+    if (e < 0) {
+      for (int s = lane; s < K; s += LANES) part += op.refd[s] * x[L + off(s)];
+    } else {
+      const V *__restrict__ rowv = vals + size_t(e) * (NG * G);
+      for (int q = lane; q < NG; q += LANES) {
+        if constexpr (G == 2) {
+          const double2 v = reinterpret_cast<const double2 *>(rowv)[q];
+          part += v.x * x[L + off(2 * q)];
+          if (2 * q + 1 < K) part += v.y * x[L + off(2 * q + 1)];
+        } else {
+          const float4 v = reinterpret_cast<const float4 *>(rowv)[q];
+          part += double(v.x) * x[L + off(4 * q)];
+          if (4 * q + 1 < K) part += double(v.y) * x[L + off(4 * q + 1)];
+          if (4 * q + 2 < K) part += double(v.z) * x[L + off(4 * q + 2)];
+          if (4 * q + 3 < K) part += double(v.w) * x[L + off(4 * q + 3)];
+        }
+      }
     }
   }
 #pragma unroll
@@ -67,31 +90,51 @@ __global__ __launch_bounds__(kMsBlock) void k_ms_colour(int m, const int32_t *__
 }
 
 template <typename V>
-static void dispatch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, int K,
-                               const OpView<V> &op, const int32_t *row_lat, const uint32_t *meta, const double *r,
+static void dispatch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
+                               const V *vals, int K, const OpView<V> &op, const int32_t *row_lat, const double *r,
                                double *x, double *rh, const int32_t *done) {
   if (m <= 0) return;
   constexpr int LN = 8;
   dim3 g((size_t(m) * LN + kMsBlock - 1) / kMsBlock), t(kMsBlock);
   switch (K) {
-    case 9: k_ms_colour<9, V, LN><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
-    case 25: k_ms_colour<25, V, LN><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
-    case 49: k_ms_colour<49, V, LN><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
-    case 27: k_ms_colour<27, V, LN><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
-    case 125: k_ms_colour<125, V, LN><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
-    default: k_ms_colour<0, V, LN><<<g, t, 0, s>>>(m, rows, cf, op, row_lat, meta, r, x, rh, done, K); break;
+    case 9: k_ms_colour<9, V, LN><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, op, row_lat, r, x, rh, done); break;
+    case 25: k_ms_colour<25, V, LN><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, op, row_lat, r, x, rh, done); break;
+    case 49: k_ms_colour<49, V, LN><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, op, row_lat, r, x, rh, done); break;
+    case 27: k_ms_colour<27, V, LN><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, op, row_lat, r, x, rh, done); break;
+    case 125: k_ms_colour<125, V, LN><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, op, row_lat, r, x, rh, done); break;
+    default: throw std::invalid_argument("multiplicative smoother: stencils of 9, 25, 49, 27 or 125 slots");
   }
 }
 
-void launch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, int K, const OpView<double> &op,
-                      const int32_t *row_lat, const uint32_t *meta, const double *r, double *x, double *rh,
-                      const int32_t *done) {
-  dispatch_ms_colour<double>(s, m, rows, cf, K, op, row_lat, meta, r, x, rh, done);
+// The colour-ordered copy of the stored rows' values: entry e takes stored
+// row g[e] of the level's operator (slot groups of SlotGroup<V>) as KP
+// consecutive values, zero padded.
+template <typename V>
+__global__ void k_ms_pack(int ne, int K, int KP, const int32_t *__restrict__ g, const V *__restrict__ val, int nv,
+                          V *__restrict__ out) {
+  const int64_t id = int64_t(blockIdx.x) * kMsBlock + threadIdx.x;
+  if (id >= int64_t(ne) * KP) return;
+  const int e = int(id / KP), s = int(id % KP);
+  out[id] = s < K ? val[stored_at<V>(size_t(nv), size_t(g[e]), s)] : V(0);
 }
-void launch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, int K, const OpView<float> &op,
-                      const int32_t *row_lat, const uint32_t *meta, const double *r, double *x, double *rh,
-                      const int32_t *done) {
-  dispatch_ms_colour<float>(s, m, rows, cf, K, op, row_lat, meta, r, x, rh, done);
+
+void launch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
+                      const double *vals, int K, const OpView<double> &op, const int32_t *row_lat, const double *r,
+                      double *x, double *rh, const int32_t *done) {
+  dispatch_ms_colour<double>(s, m, rows, cf, vidx, vals, K, op, row_lat, r, x, rh, done);
+}
+void launch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
+                      const float *vals, int K, const OpView<float> &op, const int32_t *row_lat, const double *r,
+                      double *x, double *rh, const int32_t *done) {
+  dispatch_ms_colour<float>(s, m, rows, cf, vidx, vals, K, op, row_lat, r, x, rh, done);
+}
+void launch_ms_pack(hipStream_t s, int ne, int K, int KP, const int32_t *g, const double *val, int nv, double *out) {
+  if (ne > 0)
+    k_ms_pack<double><<<(int64_t(ne) * KP + kMsBlock - 1) / kMsBlock, kMsBlock, 0, s>>>(ne, K, KP, g, val, nv, out);
+}
+void launch_ms_pack(hipStream_t s, int ne, int K, int KP, const int32_t *g, const float *val, int nv, float *out) {
+  if (ne > 0)
+    k_ms_pack<float><<<(int64_t(ne) * KP + kMsBlock - 1) / kMsBlock, kMsBlock, 0, s>>>(ne, K, KP, g, val, nv, out);
 }
 
 // Row-wise vector operations on a level's padded lattice vectors (active
