@@ -51,15 +51,36 @@ def psi_star(points: np.ndarray) -> np.ndarray:
     return 0.5 + 0.1 * np.sin(5.0 * th) - r
 
 
-def psi_apple(points: np.ndarray) -> np.ndarray:
-    """Apple with a bite (numerical examples section, box (-2,2)^3):
-    psi = min(psi_1, psi_2) with psi_1 = 1 - (z/1.7)^2 - (r/(1+z/17) - 0.7)^2 and
-    psi_2 = (x-2)^2 + y^2 + z^2 - 1."""
+def apple_parts(points: np.ndarray):
+    """The two level sets of the apple with a bite (numerical examples
+    section, box (-2,2)^3): psi_1 = 1 - (z/1.7)^2 - (r/(1+z/17) - 0.7)^2 (the
+    apple, r^2 = x^2 + y^2) and psi_2 = (x-2)^2 + y^2 + z^2 - 1 (the bite)."""
     x, y, z = points[..., 0], points[..., 1], points[..., 2]
     r = np.sqrt(x * x + y * y)
     p1 = 1.0 - (z / 1.7) ** 2 - (r / (1.0 + z / 17.0) - 0.7) ** 2
     p2 = (x - 2.0) ** 2 + y ** 2 + z ** 2 - 1.0
+    return p1, p2
+
+
+def psi_apple(points: np.ndarray) -> np.ndarray:
+    """Apple with a bite: the intersection min(psi_1, psi_2)."""
+    p1, p2 = apple_parts(points)
     return np.minimum(p1, p2)
+
+
+def dirichlet_mask(w, points: np.ndarray) -> np.ndarray:
+    """Which points of the approximate boundary carry the (penalty) Dirichlet
+    condition.  "all": the whole immersed boundary.  "bite" (the apple
+    example: homogeneous Dirichlet data on the surface of the bite only);
+    reading: a boundary point belongs to the bite when the bite's level set
+    is the smaller of the two there (it is the constraint that cuts)."""
+    part = getattr(w, "dirichlet_part", "all")
+    if part == "all":
+        return np.ones(points.shape[0], dtype=bool)
+    if part == "bite":
+        p1, p2 = apple_parts(points)
+        return p2 <= p1
+    raise ValueError(part)
 
 
 def psi_helix(points: np.ndarray) -> np.ndarray:

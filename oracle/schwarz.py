@@ -126,8 +126,11 @@ class Smoother:
             self.lam.append(lam)
             self.removed.append(rem)
             self.added.append(int(i))
-        self.gamma = 1.0 / max_NK(lev, self.blocks)
+        self.gamma = self._gamma(lev, self.blocks)
         self.omega = omega  # optional per-block weights; None -> uniform gamma
+
+    def _gamma(self, lev, blocks):
+        return 1.0 / max_NK(lev, blocks)
 
     def weights(self):
         if self.omega is None:

@@ -83,6 +83,11 @@ class Workload:
         boundary with parameter beta = penalty_factor / h, no strong BCs).
     rhs: "one" (f = 1), "manufactured" (u* = prod sin(2 pi x_i), f = -lap u*,
          Neumann data grad u* . n on the immersed boundary), "zero".
+    physics: "poisson" (scalar) or "elasticity" (displacement with dim
+         components, Lame parameters lame_lambda / lame_mu, constant body
+         load `force`; bc "penalty" applies the penalty Dirichlet condition
+         on the part of the immersed boundary named by dirichlet_part: "all"
+         or "bite" (the apple's bite), the rest is traction free).
     smoother: "as" (additive Schwarz) or "ms" (multiplicative Schwarz with
          colouring) on the finest level; coarse_smoother: "same" (the finest
          level's smoother on every level), "jacobi" or "gs" (one block per
@@ -108,6 +113,11 @@ class Workload:
     smoother: str = "as"
     coarse_smoother: str = "same"
     cycle: int = 1
+    physics: str = "poisson"
+    lame_lambda: float = 1.0e3
+    lame_mu: float = 1.0e3
+    force: Optional[list] = None
+    dirichlet_part: str = "all"
 
     def to_json(self) -> str:
         return json.dumps(asdict(self), sort_keys=True)
@@ -194,3 +204,15 @@ def batched_c4(index: int) -> Workload:
     return Workload(name=f"C4-{index}", dim=2, degree=p, n=n, depth=depth, levels=levels,
                     geometry="discs", discs=disc_set(100 + index, nd, 0.01, 0.04).tolist(),
                     rhs="zero", nu=1)
+
+
+def apple(n: int = 80, levels: int = 4, nu: int = 1) -> Workload:
+    """3D linear elasticity on the apple with a bite (numerical examples
+    section): box (-2,2)^3, quadratic B-splines, n^3 elements (80^3 in the
+    paper), integration depth 0, lambda = mu = 1e3, gravity load (0, 0, -1),
+    homogeneous Dirichlet data on the bite by the penalty method with
+    beta = 2/h, traction free elsewhere."""
+    return Workload(name="apple" if n == 80 else f"apple-{n}", dim=3, degree=2, n=n, depth=0,
+                    levels=levels, geometry="apple", basis="bspline", bc="penalty", rhs="force",
+                    nu=nu, box_lo=-2.0, box_hi=2.0, penalty_factor=2.0, physics="elasticity",
+                    lame_lambda=1.0e3, lame_mu=1.0e3, force=[0.0, 0.0, -1.0], dirichlet_part="bite")
