@@ -4,7 +4,8 @@
  * Builds, for a synthetic workload, everything the solver library's setup
  * call consumes:
  *   - the fine system A x = b with A_ij = a_h(phi_i, phi_j), b_i = b_h(phi_i)
- *     (eq:systemMulti, scalar analogue of eq:weakMulti / eq:operatorsMulti),
+ *     (eq:systemMulti): the scalar analogue of eq:weakMulti / eq:operatorsMulti,
+ *     or linear elasticity itself (penalty Dirichlet, constant body load),
  *     integrated with the cut-cell procedure of Figure 1 (bisection to a
  *     maximum depth, triangulation, Gauss rules on the clipped subcells and on
  *     the approximate boundary);
@@ -36,7 +37,14 @@ extern "C" {
 enum { IMSMG_GEN_BSPLINE = 0, IMSMG_GEN_LAGRANGE = 1 };
 enum { IMSMG_GEN_BOX_DIRICHLET = 0, IMSMG_GEN_PENALTY = 1, IMSMG_GEN_NEUMANN = 2 };
 enum { IMSMG_GEN_RHS_ONE = 0, IMSMG_GEN_RHS_MANUFACTURED = 1, IMSMG_GEN_RHS_ZERO = 2 };
-enum { IMSMG_GEN_GEOM_NONE = 0, IMSMG_GEN_GEOM_DISCS = 1, IMSMG_GEN_GEOM_GYROID = 2, IMSMG_GEN_GEOM_STAR = 3 };
+enum { IMSMG_GEN_GEOM_NONE = 0, IMSMG_GEN_GEOM_DISCS = 1, IMSMG_GEN_GEOM_GYROID = 2, IMSMG_GEN_GEOM_STAR = 3,
+       IMSMG_GEN_GEOM_APPLE = 4 };
+/* physics: scalar Poisson, or linear elasticity (eq:weakMulti / eq:operatorsMulti) with dim
+ * displacement components */
+enum { IMSMG_GEN_POISSON = 0, IMSMG_GEN_ELASTICITY = 1 };
+/* part of the immersed boundary that carries the penalty Dirichlet condition: all of it, or the
+ * apple's bite (boundary points where the bite's level set is the smaller of the two) */
+enum { IMSMG_GEN_DIRICHLET_ALL = 0, IMSMG_GEN_DIRICHLET_BITE = 1 };
 
 typedef struct {
   int32_t dim;          /* 2 or 3 */
@@ -57,6 +65,10 @@ typedef struct {
   int32_t q_cell, q_simplex, q_bnd; /* Gauss points per axis; 0 = defaults */
   int32_t nthreads;     /* 0 = OpenMP default */
   int32_t with_mass;    /* also assemble the fine mass matrix */
+  int32_t physics;      /* IMSMG_GEN_POISSON / IMSMG_GEN_ELASTICITY */
+  int32_t dirichlet_part; /* IMSMG_GEN_DIRICHLET_* (bc = PENALTY) */
+  double lame_lambda, lame_mu; /* elasticity: Lame parameters */
+  double force[3];      /* elasticity: constant body load */
 } imsmg_gen_spec;
 
 typedef struct imsmg_gen_problem imsmg_gen_problem;
@@ -73,6 +85,7 @@ typedef struct {
   int32_t n_active_elements;
   int64_t elem_nnz;      /* entries of the element -> active function incidence */
   double eta_min;        /* smallest volume fraction of an active element */
+  int32_t ncomp;         /* components per function: 1 (Poisson) or dim (elasticity) */
 } imsmg_gen_level_info;
 
 int imsmg_gen_build(const imsmg_gen_spec *spec, imsmg_gen_problem **out);
@@ -80,6 +93,11 @@ int imsmg_gen_level_info_get(const imsmg_gen_problem *p, int level, imsmg_gen_le
 /* dof_to_lattice[n_active]; rowptr[n_active+1], col[nnz], val[nnz] (any may be NULL) */
 int imsmg_gen_get_operator(const imsmg_gen_problem *p, int level, int32_t *dof_to_lattice,
                            int32_t *rowptr, int32_t *col, double *val);
+/* Elasticity: the values of the operator's component block (ci, cj) (rows: component ci of the
+ * active functions, columns: component cj) on the scalar pattern of imsmg_gen_get_operator;
+ * the vector operator is [A_(ci,cj)] with DOF c n_active + i (component-major).  Poisson:
+ * only (0, 0), equal to the operator's values. */
+int imsmg_gen_get_operator_block(const imsmg_gen_problem *p, int level, int ci, int cj, double *val);
 /* R_l: n_active(level-1) x n_active(level), rowptr[n_{l-1}+1], col/val[r_nnz] */
 int imsmg_gen_get_restriction(const imsmg_gen_problem *p, int level, int32_t *rowptr, int32_t *col,
                               double *val);
@@ -106,7 +124,7 @@ int imsmg_gen_lattice_colours(int n, const int32_t *dof_to_lattice, int nf1, int
  * eidx[elem_nnz] = compact indices of the active functions non-zero on the
  * element (x offset fastest), elem[n_active_elements] = element index */
 int imsmg_gen_get_elements(const imsmg_gen_problem *p, int level, int32_t *eptr, int32_t *eidx, int32_t *elem);
-/* fine right-hand side b[n_active(fine)] */
+/* fine right-hand side b[ncomp n_active(fine)] (component-major for elasticity) */
 int imsmg_gen_get_rhs(const imsmg_gen_problem *p, double *b);
 /* fine mass matrix values on the fine pattern (requires with_mass) */
 int imsmg_gen_get_mass(const imsmg_gen_problem *p, double *val);

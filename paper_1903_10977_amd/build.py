@@ -34,7 +34,7 @@ def build_generator() -> str:
     os.makedirs(LIB_DIR, exist_ok=True)
     out = os.path.join(LIB_DIR, "libimsmg_gen.so")
     src = os.path.join(PACKAGE_DIR, "gen", "generator.cpp")
-    _run(["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+    _run(["g++", "-O3", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
           "-I", INCLUDE_DIR, "-o", out + ".tmp", src])
     os.replace(out + ".tmp", out)
     return out

@@ -241,6 +241,13 @@ struct Geometry {
   int kind, dim;
   std::vector<double> discs;
   double phase[3], level;
+  // the apple with a bite (box (-2,2)^3): apple body psi_1 and bite psi_2
+  static void apple_parts(const double *x, double &p1, double &p2) {
+    const double r = std::sqrt(x[0] * x[0] + x[1] * x[1]);
+    const double zz = x[2] / 1.7, rr = r / (1.0 + x[2] / 17.0) - 0.7;
+    p1 = 1.0 - zz * zz - rr * rr;
+    p2 = (x[0] - 2.0) * (x[0] - 2.0) + x[1] * x[1] + x[2] * x[2] - 1.0;
+  }
   double eval(const double *x) const {
     switch (kind) {
       case IMSMG_GEN_GEOM_NONE:
@@ -265,6 +272,11 @@ struct Geometry {
         double th = std::atan2(x[1], x[0]);
         double r = std::sqrt(x[0] * x[0] + x[1] * x[1]);
         return 0.5 + 0.1 * std::sin(5.0 * th) - r;
+      }
+      case IMSMG_GEN_GEOM_APPLE: {
+        double p1, p2;
+        apple_parts(x, p1, p2);
+        return std::min(p1, p2);
       }
     }
     return 0.0;
@@ -293,6 +305,7 @@ struct LevelData {
   std::vector<int32_t> lat2c;         // lattice -> compact (-1 inactive)
   std::vector<int32_t> c2lat;         // compact -> lattice
   CSR A;
+  std::vector<CSR> Ab;                // elasticity: component blocks (ci, cj) at ci * d + cj, values on A's pattern
   CSR R;                              // maps this level -> level-1
   std::vector<int32_t> bptr, bidx, bassoc;
   int n_cut = 0;
@@ -313,6 +326,7 @@ struct Ctx {
   int nleaf;
   std::vector<double> leaf;   // snapped psi on the leaf lattice, x fastest
   Rule1D gc, gs, gb;
+  bool want_bnd = false;      // 3D: emit the approximate boundary's triangles
   Ctx(const imsmg_gen_spec &sp) : s(sp), d(sp.dim), p(sp.degree) {}
   size_t leaf_index(const int *L) const {
     size_t idx = 0;
@@ -480,6 +494,31 @@ void wedge_tets(const double *A, const double *B, const double *Cc, const double
   }
 }
 
+// Gauss points of a triangle of the approximate boundary (3D): collapsed
+// rule x = T0 + u (T1 - T0) + u v (T2 - T1), area measure, outward normal nn.
+void surface_points(const double *T0, const double *T1, const double *T2, const double *nn, const Rule1D &g,
+                    QPoints &Q) {
+  double e1[3], e2[3];
+  for (int a = 0; a < 3; ++a) {
+    e1[a] = T1[a] - T0[a];
+    e2[a] = T2[a] - T1[a];
+  }
+  const double cx = e1[1] * e2[2] - e1[2] * e2[1];
+  const double cy = e1[2] * e2[0] - e1[0] * e2[2];
+  const double cz = e1[0] * e2[1] - e1[1] * e2[0];
+  const double J = std::sqrt(cx * cx + cy * cy + cz * cz);
+  const int q = int(g.x.size());
+  for (int i = 0; i < q; ++i)
+    for (int j = 0; j < q; ++j) {
+      const double u = g.x[i], uv = g.x[i] * g.x[j];
+      for (int a = 0; a < 3; ++a) {
+        Q.bx.push_back(T0[a] + u * e1[a] + uv * e2[a]);
+        Q.bn.push_back(nn[a]);
+      }
+      Q.bw.push_back(g.w[i] * g.w[j] * u * J);
+    }
+}
+
 void clip_tet(const double P[4][3], const double f[4], const Ctx &C, QPoints &Q) {
   int pos[4], neg[4], npos = 0, nneg = 0;
   for (int a = 0; a < 4; ++a) {
@@ -489,6 +528,30 @@ void clip_tet(const double P[4][3], const double f[4], const Ctx &C, QPoints &Q)
   auto I = [&](int a, int b, double *out) { lerp_zero(P[a], P[b], f[a], f[b], 3, out); };
   if (npos == 0) return;
   if (npos == 4) { tet_points(P, C.gs, Q); return; }
+  // outward normal of the zero set: -grad f / |grad f|, grad f from the
+  // edges P_k - P_0 (Cramer's rule)
+  double nn[3] = {0.0, 0.0, 0.0};
+  if (C.want_bnd) {
+    double M[3][3], r[3];
+    for (int k = 0; k < 3; ++k) {
+      for (int a = 0; a < 3; ++a) M[k][a] = P[k + 1][a] - P[0][a];
+      r[k] = f[k + 1] - f[0];
+    }
+    auto det3 = [](const double A[3][3]) {
+      return A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+             A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    };
+    const double D = det3(M);
+    double g[3];
+    for (int a = 0; a < 3; ++a) {
+      double Ma[3][3];
+      for (int k = 0; k < 3; ++k)
+        for (int b = 0; b < 3; ++b) Ma[k][b] = (b == a) ? r[k] : M[k][b];
+      g[a] = det3(Ma) / D;
+    }
+    const double gn = std::sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    for (int a = 0; a < 3; ++a) nn[a] = -g[a] / gn;
+  }
   if (npos == 1) {
     int a = pos[0];
     double T[4][3];
@@ -497,6 +560,7 @@ void clip_tet(const double P[4][3], const double f[4], const Ctx &C, QPoints &Q)
     I(a, neg[1], T[2]);
     I(a, neg[2], T[3]);
     tet_points(T, C.gs, Q);
+    if (C.want_bnd) surface_points(T[1], T[2], T[3], nn, C.gb, Q);
     return;
   }
   if (npos == 3) {
@@ -506,6 +570,7 @@ void clip_tet(const double P[4][3], const double f[4], const Ctx &C, QPoints &Q)
     I(b, dd, Bd);
     I(c, dd, Cd);
     wedge_tets(P[a], P[b], P[c], Ad, Bd, Cd, C, Q);
+    if (C.want_bnd) surface_points(Ad, Bd, Cd, nn, C.gb, Q);
     return;
   }
   int a = pos[0], b = pos[1], c = neg[0], dd = neg[1];
@@ -515,6 +580,11 @@ void clip_tet(const double P[4][3], const double f[4], const Ctx &C, QPoints &Q)
   I(b, c, Ibc);
   I(b, dd, Ibd);
   wedge_tets(P[a], Iac, Iad, P[b], Ibc, Ibd, C, Q);
+  // the quadrilateral zero set, split along Iac - Ibd
+  if (C.want_bnd) {
+    surface_points(Iac, Iad, Ibd, nn, C.gb, Q);
+    surface_points(Iac, Ibd, Ibc, nn, C.gb, Q);
+  }
 }
 
 // Quadrature of one element on a level of size h whose cells are bisected `depth` times.
@@ -697,8 +767,9 @@ void build_pattern(LevelData &L, const Basis1D &B, int d, const Stencil &st) {
 }
 
 struct Elem1D {
-  // per element index: (p+1)x(p+1) stiffness and mass, (p+1) loads of 1 and sin(2 pi x)
-  std::vector<double> S, M, F1, Fs;
+  // per element index: (p+1)x(p+1) stiffness, mass and first-derivative
+  // matrices (D_ab = int phi_a' phi_b), (p+1) loads of 1 and sin(2 pi x)
+  std::vector<double> S, M, D, F1, Fs;
 };
 
 Elem1D element_1d(const Basis1D &B, const Rule1D &g) {
@@ -706,6 +777,7 @@ Elem1D element_1d(const Basis1D &B, const Rule1D &g) {
   Elem1D E;
   E.S.assign(size_t(B.n) * m * m, 0.0);
   E.M.assign(size_t(B.n) * m * m, 0.0);
+  E.D.assign(size_t(B.n) * m * m, 0.0);
   E.F1.assign(size_t(B.n) * m, 0.0);
   E.Fs.assign(size_t(B.n) * m, 0.0);
   for (int e = 0; e < B.n; ++e) {
@@ -722,6 +794,7 @@ Elem1D element_1d(const Basis1D &B, const Rule1D &g) {
         for (int b = 0; b < m; ++b) {
           E.S[(size_t(e) * m + a) * m + b] += w * dv[a] * dv[b];
           E.M[(size_t(e) * m + a) * m + b] += w * v[a] * v[b];
+          E.D[(size_t(e) * m + a) * m + b] += w * dv[a] * v[b];
         }
       }
     }
@@ -910,6 +983,238 @@ void assemble_fine(Ctx &C, Problem &P, LevelData &L, const Basis1D &B) {
   L.n_cut = ncut;
 }
 
+// Fine-level assembly of linear elasticity (eq:operatorsMulti) into the
+// component blocks L.Ab (values on the scalar structural pattern):
+//   K[(a,c),(b,e)] = lambda d_c phi_a d_e phi_b
+//                    + mu (delta_ce grad phi_a . grad phi_b + d_e phi_a d_c phi_b)
+// plus, on boundary points of the Dirichlet part, lambda beta phi_a phi_b n_c n_e
+// + 2 mu beta delta_ce phi_a phi_b (homogeneous data: no load from it), and
+// the load f_c int phi_a.  Inside elements take tensor products of the 1D
+// matrices S (d/dx on both), D (d/dx on the first function) and M.  Only the
+// blocks c <= e are computed (c = e: a <= b) and mirrored, so the operator is
+// exactly symmetric.
+void assemble_fine_elasticity(Ctx &C, Problem &P, LevelData &L, const Basis1D &B) {
+  const int d = C.d, p = C.p, m = p + 1;
+  int nloc = 1;
+  for (int a = 0; a < d; ++a) nloc *= m;
+  const int n = L.n;
+  const double h = B.h;
+  const double lam = C.s.lame_lambda, mu = C.s.lame_mu;
+  const bool penalty = C.s.bc == IMSMG_GEN_PENALTY;
+  const double beta = penalty ? C.s.penalty_factor / h : 0.0;
+  const bool bite = C.s.dirichlet_part == IMSMG_GEN_DIRICHLET_BITE;
+  const Elem1D E = element_1d(B, C.gc);
+  const int nrows = int(L.c2lat.size());
+  const size_t nb = size_t(d) * d;
+  L.Ab.assign(nb, CSR());
+  for (size_t k = 0; k < nb; ++k) L.Ab[k].val.assign(L.A.col.size(), 0.0);
+  P.b.assign(size_t(d) * nrows, 0.0);
+  if (C.s.with_mass) P.mass.assign(L.A.val.size(), 0.0);
+  L.eta.assign(L.active_el.size(), 0.0);
+  const int stride = B.basis == IMSMG_GEN_BSPLINE ? m : 2;
+  int ncolors = 1;
+  for (int a = 0; a < d; ++a) ncolors *= stride;
+  int ncut = 0;
+  const size_t nl2 = size_t(nloc) * nloc;
+  for (int color = 0; color < ncolors; ++color) {
+    int cc[3] = {0, 0, 0}, r = color;
+    for (int a = 0; a < d; ++a) { cc[a] = r % stride; r /= stride; }
+    int cnt[3] = {1, 1, 1};
+    for (int a = 0; a < d; ++a) cnt[a] = (n - cc[a] + stride - 1) / stride;
+    const int64_t total = int64_t(cnt[0]) * cnt[1] * cnt[2];
+#pragma omp parallel reduction(+ : ncut)
+    {
+      // T[c][e] = int d_c phi_a d_e phi_b (all a, b); K blocks; mass; loads
+      std::vector<double> T(nb * nl2), K(nb * nl2), Ml(nl2), fb(size_t(d) * nloc), F1(nloc);
+      std::vector<double> vals, ders, phi(nloc), grad(size_t(nloc) * d), gradT(size_t(nloc) * d);
+      QPoints Q;
+#pragma omp for schedule(dynamic, 64)
+      for (int64_t t = 0; t < total; ++t) {
+        int e[3] = {0, 0, 0};
+        int64_t rr = t;
+        for (int a = 0; a < d; ++a) { e[a] = cc[a] + stride * int(rr % cnt[a]); rr /= cnt[a]; }
+        const size_t el = size_t(multi_lat(e, n, d));
+        if (!L.active_el[el]) continue;
+        const int sd = 1 << L.depth;
+        int L0[3] = {e[0] * sd, e[1] * sd, d == 3 ? e[2] * sd : 0};
+        bool all_pos = true;
+        for (int k = 0; k <= (d == 3 ? sd : 0) && all_pos; ++k)
+          for (int j = 0; j <= sd && all_pos; ++j)
+            for (int i = 0; i <= sd; ++i) {
+              int LL[3] = {L0[0] + i, L0[1] + j, L0[2] + k};
+              if (!(C.leaf[C.leaf_index(LL)] > 0.0)) { all_pos = false; break; }
+            }
+        std::fill(T.begin(), T.end(), 0.0);
+        std::fill(Ml.begin(), Ml.end(), 0.0);
+        std::fill(F1.begin(), F1.end(), 0.0);
+        std::fill(K.begin(), K.end(), 0.0);
+        if (all_pos) {
+          L.eta[el] = 1.0;
+          for (int A = 0; A < nloc; ++A) {
+            int oa[3] = {0, 0, 0}, ra = A;
+            for (int a = 0; a < d; ++a) { oa[a] = ra % m; ra /= m; }
+            double f1 = 1.0;
+            for (int a = 0; a < d; ++a) f1 *= E.F1[size_t(e[a]) * m + oa[a]];
+            F1[A] = f1;
+            for (int Bi = 0; Bi < nloc; ++Bi) {
+              int ob[3] = {0, 0, 0}, rb = Bi;
+              for (int a = 0; a < d; ++a) { ob[a] = rb % m; rb /= m; }
+              double mv = 1.0;
+              for (int a = 0; a < d; ++a) mv *= E.M[(size_t(e[a]) * m + oa[a]) * m + ob[a]];
+              Ml[size_t(A) * nloc + Bi] = mv;
+              for (int c = 0; c < d; ++c)
+                for (int ee = 0; ee < d; ++ee) {
+                  double tv = 1.0;
+                  for (int a = 0; a < d; ++a) {
+                    const size_t eab = (size_t(e[a]) * m + oa[a]) * m + ob[a];
+                    const size_t eba = (size_t(e[a]) * m + ob[a]) * m + oa[a];
+                    if (a == c && a == ee) tv *= E.S[eab];
+                    else if (a == c) tv *= E.D[eab];   // d/dx on phi_a
+                    else if (a == ee) tv *= E.D[eba];  // d/dx on phi_b
+                    else tv *= E.M[eab];
+                  }
+                  T[(size_t(c) * d + ee) * nl2 + size_t(A) * nloc + Bi] = tv;
+                }
+            }
+          }
+        } else {
+          ++ncut;
+          Q.clear();
+          element_quadrature(C, e, L.depth, h, Q);
+          const size_t nq = Q.w.size();
+          double vol = 0.0;
+          vals.resize(size_t(d) * m);
+          ders.resize(size_t(d) * m);
+          for (size_t q = 0; q < nq; ++q) {
+            const double *x = &Q.x[q * d];
+            const double w = Q.w[q];
+            vol += w;
+            for (int a = 0; a < d; ++a) B.eval(e[a], x[a], &vals[size_t(a) * m], &ders[size_t(a) * m]);
+            for (int A = 0; A < nloc; ++A) {
+              int oa[3] = {0, 0, 0}, ra = A;
+              for (int a = 0; a < d; ++a) { oa[a] = ra % m; ra /= m; }
+              double v = 1.0;
+              for (int a = 0; a < d; ++a) v *= vals[size_t(a) * m + oa[a]];
+              phi[A] = v;
+              for (int c = 0; c < d; ++c) {
+                double g = 1.0;
+                for (int a = 0; a < d; ++a) g *= (a == c) ? ders[size_t(a) * m + oa[a]] : vals[size_t(a) * m + oa[a]];
+                grad[size_t(A) * d + c] = g;
+              }
+            }
+            // gradients component-major (contiguous over the local functions)
+            for (int A = 0; A < nloc; ++A)
+              for (int c = 0; c < d; ++c) gradT[size_t(c) * nloc + A] = grad[size_t(A) * d + c];
+            for (int A = 0; A < nloc; ++A) {
+              F1[A] += w * phi[A];
+              if (C.s.with_mass) {
+                const double wa = w * phi[A];
+                double *row = &Ml[size_t(A) * nloc];
+                for (int Bi = 0; Bi < nloc; ++Bi) row[Bi] += wa * phi[Bi];
+              }
+            }
+            // T[c][e] for c <= e only (T[e][c]_ab = T[c][e]_ba)
+            for (int c = 0; c < d; ++c)
+              for (int ee = c; ee < d; ++ee) {
+                const double *ge = &gradT[size_t(ee) * nloc];
+                double *Tc = &T[(size_t(c) * d + ee) * nl2];
+                for (int A = 0; A < nloc; ++A) {
+                  const double wa = w * gradT[size_t(c) * nloc + A];
+                  double *row = Tc + size_t(A) * nloc;
+                  for (int Bi = 0; Bi < nloc; ++Bi) row[Bi] += wa * ge[Bi];
+                }
+              }
+          }
+          for (int c = 0; c < d; ++c)
+            for (int ee = 0; ee < c; ++ee)
+              for (int A = 0; A < nloc; ++A)
+                for (int Bi = 0; Bi < nloc; ++Bi)
+                  T[(size_t(c) * d + ee) * nl2 + size_t(A) * nloc + Bi] =
+                      T[(size_t(ee) * d + c) * nl2 + size_t(Bi) * nloc + A];
+          L.eta[el] = vol / std::pow(h, d);
+          // penalty on the Dirichlet part of the approximate boundary
+          const size_t nbq = Q.bw.size();
+          if (penalty) {
+            for (size_t q = 0; q < nbq; ++q) {
+              const double *x = &Q.bx[q * d];
+              const double *nn = &Q.bn[q * d];
+              if (bite) {
+                double p1, p2;
+                Geometry::apple_parts(x, p1, p2);
+                if (!(p2 <= p1)) continue;
+              }
+              const double w = Q.bw[q];
+              for (int a = 0; a < d; ++a) B.eval(e[a], x[a], &vals[size_t(a) * m], &ders[size_t(a) * m]);
+              for (int A = 0; A < nloc; ++A) {
+                int oa[3] = {0, 0, 0}, ra = A;
+                for (int a = 0; a < d; ++a) { oa[a] = ra % m; ra /= m; }
+                double v = 1.0;
+                for (int a = 0; a < d; ++a) v *= vals[size_t(a) * m + oa[a]];
+                phi[A] = v;
+              }
+              for (int A = 0; A < nloc; ++A)
+                for (int Bi = 0; Bi < nloc; ++Bi) {
+                  const double pp = w * phi[A] * phi[Bi];
+                  for (int c = 0; c < d; ++c)
+                    for (int ee = 0; ee < d; ++ee) {
+                      double kv = lam * beta * pp * nn[c] * nn[ee];
+                      if (c == ee) kv += 2.0 * mu * beta * pp;
+                      K[(size_t(c) * d + ee) * nl2 + size_t(A) * nloc + Bi] += kv;
+                    }
+                }
+            }
+          }
+        }
+        // K += lambda T[c][e] + mu T[e][c]^T-entry + mu delta_ce sum_g T[g][g]
+        for (int c = 0; c < d; ++c)
+          for (int ee = 0; ee < d; ++ee)
+            for (int A = 0; A < nloc; ++A)
+              for (int Bi = 0; Bi < nloc; ++Bi) {
+                const size_t ab = size_t(A) * nloc + Bi;
+                double kv = lam * T[(size_t(c) * d + ee) * nl2 + ab] + mu * T[(size_t(ee) * d + c) * nl2 + ab];
+                if (c == ee) {
+                  double lap = 0.0;
+                  for (int g = 0; g < d; ++g) lap += T[(size_t(g) * d + g) * nl2 + ab];
+                  kv += mu * lap;
+                }
+                K[(size_t(c) * d + ee) * nl2 + ab] += kv;
+              }
+        for (int c = 0; c < d; ++c)
+          for (int A = 0; A < nloc; ++A) fb[size_t(c) * nloc + A] = C.s.force[c] * F1[A];
+        // scatter the blocks c <= e (c = e: a <= b) and their mirror images
+        int32_t loc[64 * 8];
+        for (int A = 0; A < nloc; ++A) {
+          int oa[3] = {0, 0, 0}, ra = A, mf[3] = {0, 0, 0};
+          for (int a = 0; a < d; ++a) { oa[a] = ra % m; ra /= m; mf[a] = B.first(e[a]) + oa[a]; }
+          loc[A] = L.lat2c[size_t(multi_lat(mf, L.nf1, d))];
+        }
+        for (int A = 0; A < nloc; ++A) {
+          if (loc[A] < 0) continue;
+          for (int c = 0; c < d; ++c) P.b[size_t(c) * nrows + loc[A]] += fb[size_t(c) * nloc + A];
+          for (int Bi = 0; Bi < nloc; ++Bi) {
+            if (loc[Bi] < 0) continue;
+            const int64_t pos = L.A.find(loc[A], loc[Bi]);
+            if (pos < 0) throw GenError(-1, "assembly entry outside the structural pattern");
+            const int lo_ = std::min(A, Bi), hi_ = std::max(A, Bi);
+            if (C.s.with_mass) P.mass[pos] += Ml[size_t(lo_) * nloc + hi_];
+            for (int c = 0; c < d; ++c)
+              for (int ee = 0; ee < d; ++ee) {
+                // entry (A c, Bi ee) = canonical (c <= ee) block value
+                double kv;
+                if (c < ee) kv = K[(size_t(c) * d + ee) * nl2 + size_t(A) * nloc + Bi];
+                else if (c > ee) kv = K[(size_t(ee) * d + c) * nl2 + size_t(Bi) * nloc + A];
+                else kv = K[(size_t(c) * d + c) * nl2 + size_t(lo_) * nloc + hi_];
+                L.Ab[size_t(c) * d + ee].val[pos] += kv;
+              }
+          }
+        }
+      }
+    }
+  }
+  L.n_cut = ncut;
+  L.A.val = L.Ab[0].val;
+}
+
 // Masked tensor two-scale restriction: rows = coarse active, cols = fine active.
 void build_restriction(const LevelData &Lc, LevelData &Lf, int d, int basis, int p, double lo, double hi) {
   const int nc = Lc.n;
@@ -954,9 +1259,9 @@ void build_restriction(const LevelData &Lc, LevelData &Lf, int d, int basis, int
     }
 }
 
-// Galerkin A_c = R A R^T on the coarse structural pattern (T = A R^T first).
-void galerkin(LevelData &Lc, const LevelData &Lf) {
-  const CSR &R = Lf.R, &A = Lf.A;
+// Galerkin A_c = R A R^T on the coarse structural pattern (T = A R^T first);
+// Ac holds the pattern and receives the values.
+void galerkin_csr(const CSR &R, const CSR &A, CSR &Ac) {
   const int nf = A.nrows, ncr = R.nrows;
   // R^T (fine row -> coarse entries)
   std::vector<int32_t> tptr(nf + 1, 0), tcol(R.col.size());
@@ -1000,7 +1305,6 @@ void galerkin(LevelData &Lc, const LevelData &Lf) {
       for (int32_t j : touched) { T[k].push_back({j, acc[j]}); acc[j] = 0.0; }
     }
   }
-  CSR &Ac = Lc.A;
   bool outside = false;
 #pragma omp parallel
   {
@@ -1035,6 +1339,24 @@ void galerkin(LevelData &Lc, const LevelData &Lf) {
     }
   }
   if (outside) throw GenError(-1, "Galerkin product has an entry outside the structural pattern");
+}
+
+// Galerkin coarse operator of level Lc from level Lf (per component block for
+// elasticity: R = I (x) R_scalar keeps the blocks apart).
+void galerkin(LevelData &Lc, const LevelData &Lf) {
+  if (Lf.Ab.empty()) {
+    galerkin_csr(Lf.R, Lf.A, Lc.A);
+    return;
+  }
+  Lc.Ab.assign(Lf.Ab.size(), CSR());
+  for (size_t k = 0; k < Lf.Ab.size(); ++k) {
+    CSR Af = Lf.A;
+    Af.val = Lf.Ab[k].val;
+    CSR Ac = Lc.A;
+    galerkin_csr(Lf.R, Af, Ac);
+    Lc.Ab[k].val = std::move(Ac.val);
+  }
+  Lc.A.val = Lc.Ab[0].val;
 }
 
 // Blocks by encapsulating supports (vertex functions only for Lagrange).
@@ -1103,6 +1425,7 @@ void build(Problem &P) {
   C.gc = gauss_legendre01(qc);
   C.gs = gauss_legendre01(qs);
   C.gb = gauss_legendre01(qb);
+  C.want_bnd = d == 3 && s.physics == IMSMG_GEN_ELASTICITY && s.bc == IMSMG_GEN_PENALTY;
   // leaf lattice
   C.nleaf = s.n << s.depth;
   const int N1 = C.nleaf + 1;
@@ -1177,7 +1500,10 @@ void build(Problem &P) {
     activate_functions(P.lv[l], bases[l], d, strong);
     build_pattern(P.lv[l], bases[l], d, st);
   }
-  assemble_fine(C, P, F, bases[nlev - 1]);
+  if (s.physics == IMSMG_GEN_ELASTICITY)
+    assemble_fine_elasticity(C, P, F, bases[nlev - 1]);
+  else
+    assemble_fine(C, P, F, bases[nlev - 1]);
   // volume fractions of coarse elements: mean of the children
   for (int l = nlev - 2; l >= 0; --l) {
     LevelData &Lc = P.lv[l];
@@ -1225,7 +1551,9 @@ int imsmg_gen_build(const imsmg_gen_spec *spec, imsmg_gen_problem **out) {
   const imsmg_gen_spec &s = *spec;
   if (s.dim < 2 || s.dim > 3 || s.degree < 1 || s.degree > 4 || s.n < 1 || s.levels < 1 || s.depth < 0 ||
       s.depth > 12 || (s.basis != IMSMG_GEN_BSPLINE && s.basis != IMSMG_GEN_LAGRANGE) || s.bc < 0 || s.bc > 2 ||
-      s.rhs < 0 || s.rhs > 2 || s.geometry < 0 || s.geometry > 3 || !(s.box_hi > s.box_lo)) {
+      s.rhs < 0 || s.rhs > 2 || s.geometry < 0 || s.geometry > 4 || !(s.box_hi > s.box_lo) ||
+      (s.physics != IMSMG_GEN_POISSON && s.physics != IMSMG_GEN_ELASTICITY) ||
+      (s.dirichlet_part != IMSMG_GEN_DIRICHLET_ALL && s.dirichlet_part != IMSMG_GEN_DIRICHLET_BITE)) {
     g_err = "invalid workload specification";
     return -1;
   }
@@ -1234,8 +1562,18 @@ int imsmg_gen_build(const imsmg_gen_spec *spec, imsmg_gen_problem **out) {
     g_err = "geometry does not match the dimension";
     return -1;
   }
+  if (s.geometry == IMSMG_GEN_GEOM_APPLE && s.dim != 3) { g_err = "the apple is a 3D geometry"; return -1; }
   if (s.n % (1 << (s.levels - 1))) { g_err = "n must be divisible by 2^(levels-1)"; return -1; }
-  if (s.dim == 3 && (s.bc == IMSMG_GEN_PENALTY || s.rhs == IMSMG_GEN_RHS_MANUFACTURED)) {
+  if (s.physics == IMSMG_GEN_ELASTICITY) {
+    if (s.dim != 3 || s.bc != IMSMG_GEN_PENALTY || s.basis != IMSMG_GEN_BSPLINE) {
+      g_err = "elasticity: 3D B-splines with penalty Dirichlet conditions";
+      return -1;
+    }
+    if (s.dirichlet_part == IMSMG_GEN_DIRICHLET_BITE && s.geometry != IMSMG_GEN_GEOM_APPLE) {
+      g_err = "the bite is a part of the apple's boundary";
+      return -1;
+    }
+  } else if (s.dim == 3 && (s.bc == IMSMG_GEN_PENALTY || s.rhs == IMSMG_GEN_RHS_MANUFACTURED)) {
     g_err = "boundary integrals are implemented for 2D workloads only";
     return -1;
   }
@@ -1307,6 +1645,17 @@ int imsmg_gen_level_info_get(const imsmg_gen_problem *p, int level, imsmg_gen_le
   for (size_t t = 0; t < L.eta.size(); ++t)
     if (L.active_el[t]) em = std::min(em, L.eta[t]);
   info->eta_min = em;
+  info->ncomp = L.Ab.empty() ? 1 : d;
+  return 0;
+}
+
+int imsmg_gen_get_operator_block(const imsmg_gen_problem *p, int level, int ci, int cj, double *val) {
+  if (!p || !val || level < 0 || level >= int(p->P.lv.size())) { g_err = "bad level"; return -1; }
+  const LevelData &L = p->P.lv[level];
+  const int nc = L.Ab.empty() ? 1 : p->P.spec.dim;
+  if (ci < 0 || cj < 0 || ci >= nc || cj >= nc) { g_err = "bad component block"; return -1; }
+  const std::vector<double> &v = L.Ab.empty() ? L.A.val : L.Ab[size_t(ci) * nc + cj].val;
+  std::copy(v.begin(), v.end(), val);
   return 0;
 }
 
