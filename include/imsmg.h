@@ -168,6 +168,18 @@ typedef struct {
   int32_t flag_min_rows; /* levels with at least this many rows read the solve's convergence flag
                           in every kernel (skip the tail of a graph replay after convergence);
                           smaller levels do not (one dependent load less); default 65536 */
+  int32_t ncomp;       /* components per lattice function: 1 (scalar problems, default) or 3 (3D
+                          linear elasticity, eq:weakMulti with a displacement vector).  With ncomp
+                          > 1 every level's unknowns are component-major, DOF c N + i = component
+                          c of the level's lattice function i (N = operator size / ncomp; the
+                          lattice's dof_to_lattice lists the N functions); the CSR holds every
+                          component pair; R_l is block diagonal with one equal block per
+                          component; every Schwarz block holds DOFs of one component (the
+                          smoothers subsection's separate blocks per component); elements list
+                          the DOFs of every component.  Supported: additive Schwarz, V- or
+                          W-cycles, FP64 or FP32 level operators, single right-hand side;
+                          rejected (IMSMG_ERR_INVALID_ARG): the multiplicative smoother, learned
+                          weights, block_gemm, the multi-column and batched calls, 2D lattices */
 } imsmg_options;
 
 enum { IMSMG_ADDITIVE = 0, IMSMG_MULTIPLICATIVE = 1 };

@@ -38,7 +38,7 @@ enum { IMSMG_GEN_BSPLINE = 0, IMSMG_GEN_LAGRANGE = 1 };
 enum { IMSMG_GEN_BOX_DIRICHLET = 0, IMSMG_GEN_PENALTY = 1, IMSMG_GEN_NEUMANN = 2 };
 enum { IMSMG_GEN_RHS_ONE = 0, IMSMG_GEN_RHS_MANUFACTURED = 1, IMSMG_GEN_RHS_ZERO = 2 };
 enum { IMSMG_GEN_GEOM_NONE = 0, IMSMG_GEN_GEOM_DISCS = 1, IMSMG_GEN_GEOM_GYROID = 2, IMSMG_GEN_GEOM_STAR = 3,
-       IMSMG_GEN_GEOM_APPLE = 4 };
+       IMSMG_GEN_GEOM_APPLE = 4, IMSMG_GEN_GEOM_SLAB = 5 };
 /* physics: scalar Poisson, or linear elasticity (eq:weakMulti / eq:operatorsMulti) with dim
  * displacement components */
 enum { IMSMG_GEN_POISSON = 0, IMSMG_GEN_ELASTICITY = 1 };
@@ -69,6 +69,7 @@ typedef struct {
   int32_t dirichlet_part; /* IMSMG_GEN_DIRICHLET_* (bc = PENALTY) */
   double lame_lambda, lame_mu; /* elasticity: Lame parameters */
   double force[3];      /* elasticity: constant body load */
+  double plane_x;       /* slab: Omega = {x < plane_x} */
 } imsmg_gen_spec;
 
 typedef struct imsmg_gen_problem imsmg_gen_problem;

@@ -104,6 +104,11 @@ def psi_helix(points: np.ndarray) -> np.ndarray:
     return out
 
 
+def psi_slab(points: np.ndarray, plane_x: float) -> np.ndarray:
+    """Half of the box cut by the plane x = plane_x: psi = plane_x - x."""
+    return plane_x - points[..., 0]
+
+
 def level_set(w):
     """Return psi(points) for a workload description."""
     if w.geometry == "discs":
@@ -116,6 +121,8 @@ def level_set(w):
         return psi_apple
     if w.geometry == "helix":
         return psi_helix
+    if w.geometry == "slab":
+        return lambda P: psi_slab(P, w.plane_x)
     if w.geometry == "none":
         return lambda P: np.ones(P.shape[:-1])
     raise ValueError(w.geometry)

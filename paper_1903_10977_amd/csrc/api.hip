@@ -59,6 +59,17 @@ void d2h(hipStream_t s, T *dst, const T *src, size_t count) {
 
 struct Level {
   int n = 0;
+  // vector levels (linear elasticity): ncomp components per lattice function,
+  // rows c ns + i (component-major), vectors as ncomp padded scalar arrays
+  // cstride apart; h_lat / srow_lat: the lattice point of every row / of
+  // every scalar row; vops: the component blocks for the vector kernels
+  int ncomp = 1, ns = 0;
+  int64_t cstride = 0;
+  std::vector<int32_t> h_lat;
+  int32_t *srow_lat = nullptr;
+  VecOps<double> vops64{};
+  VecOps<float> vops32{};
+  double *dense0 = nullptr;  // coarsest vector level: the dense operator (setup)
   int K = 0, dim = 2, reach = 0, center = 0;
   int shape[3] = {1, 1, 1};
   Offsets off{};
@@ -269,94 +280,43 @@ bool uses_ms(const imsmg_options &o, int nlevels) {
   return false;
 }
 
-void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice &lat) {
+// Compressed lattice-ELL form of one operator on the level's lattice (rows:
+// lat[i], values ell[s * n + i] in slot order): the uniform interior stencil
+// is the most frequent row among the candidate rows (rows hashed after
+// rounding to 12 significant digits), rows within 1e-14 of it read it from
+// the reference, the others keep their values in 16-byte slot groups,
+// numbered tile by tile (32 x 8 points in 2D, 16 x 4 x 4 in 3D; lattice order
+// inside a tile), so that the stored rows of a tile are one consecutive range.
+// Candidates: the rows whose K values are all non-zero (full == nullptr), or
+// the rows marked in *full.
+struct Compressed {
+  OpView<double> op64{};
+  OpView<float> op32{};
+  std::vector<uint32_t> h_meta;
+  uint32_t *meta = nullptr;
+  int n_uniform = 0;
+};
+
+void compress_operator(imsmg_ctx *c, const Level &L, int n, const std::vector<int32_t> &lat,
+                       const std::vector<double> &ell, const std::vector<uint8_t> *full, Compressed &out) {
   hipStream_t s = c->stream;
-  if (lat.dim < 2 || lat.dim > 3) bad("lattice dim must be 2 or 3");
-  if (lat.reach < 1 || (lat.dim == 3 && lat.reach > 2) || lat.reach > 5) bad("lattice reach must be 1..5 (2D) or 1..2 (3D)");
-  if (A.nrows <= 0 || A.nrows != A.ncols) bad("A must be square and non-empty");
-  if (!A.rowptr || !A.col || !A.val || !lat.dof_to_lattice) bad("null CSR or lattice array");
-  L.dim = lat.dim;
-  L.reach = lat.reach;
-  int64_t latsz = 1;
-  for (int a = 0; a < 3; ++a) {
-    L.shape[a] = a < lat.dim ? lat.shape[a] : 1;
-    if (L.shape[a] < 1) bad("lattice shape must be positive");
-    latsz *= L.shape[a];
-  }
-  if (latsz > (int64_t(1) << 30)) bad("lattice too large");
-  L.lattice = latsz;
-  L.n = A.nrows;
-  const int W = 2 * L.reach + 1;
-  L.K = L.dim == 2 ? W * W : W * W * W;
-  if (L.K > IMSMG_MAX_SLOTS) bad("stencil too large");
-  // slot offsets (x fastest)
-  int64_t maxoff = 0;
-  for (int sl = 0; sl < L.K; ++sl) {
-    int o[3] = {0, 0, 0}, r = sl;
-    for (int a = 0; a < L.dim; ++a) {
-      o[a] = r % W - L.reach;
-      r /= W;
-    }
-    int64_t lin = o[0] + int64_t(L.shape[0]) * (o[1] + int64_t(L.shape[1]) * o[2]);
-    L.off.off[sl] = int32_t(lin);
-    maxoff = std::max<int64_t>(maxoff, lin < 0 ? -lin : lin);
-    if (lin == 0) L.center = sl;
-  }
-  L.guard = maxoff + 64;
-  L.h_row_lat.assign(lat.dof_to_lattice, lat.dof_to_lattice + L.n);
-  for (int i = 0; i < L.n; ++i) {
-    if (L.h_row_lat[i] < 0 || L.h_row_lat[i] >= latsz) bad("dof_to_lattice out of range");
-    if (i && L.h_row_lat[i] <= L.h_row_lat[i - 1]) bad("dof_to_lattice must be strictly increasing");
-  }
-  // CSR -> slot-major lattice-ELL
-  if (A.rowptr[0] != 0 || A.rowptr[L.n] != A.nnz) bad("CSR rowptr inconsistent with nnz");
-  std::vector<double> ell(size_t(L.K) * L.n, 0.0);
-  for (int i = 0; i < L.n; ++i) {
-    int mi[3] = {0, 0, 0};
-    lat_multi(L.h_row_lat[i], L.shape, L.dim, mi);
-    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
-      const int j = A.col[k];
-      if (j < 0 || j >= L.n) bad("CSR column out of range");
-      int mj[3] = {0, 0, 0};
-      lat_multi(L.h_row_lat[j], L.shape, L.dim, mj);
-      int sl = 0;
-      for (int a = L.dim - 1; a >= 0; --a) {
-        const int d = mj[a] - mi[a];
-        if (d < -L.reach || d > L.reach) bad("CSR entry outside the lattice stencil");
-        sl = sl * W + (d + L.reach);
-      }
-      ell[size_t(sl) * L.n + i] = A.val[k];
-    }
-  }
-  // an SPD operator has a positive, finite diagonal: reject the others before
-  // anything is launched on them
-  for (int i = 0; i < L.n; ++i) {
-    const double d = ell[size_t(L.center) * L.n + i];
-    if (!(d > 0.0) || !std::isfinite(d)) bad("operator has a non-positive diagonal entry (not SPD)", IMSMG_ERR_NOT_SPD);
-  }
-  L.row_lat = dalloc<int32_t>(c->owned, L.n);
-  h2d(s, L.row_lat, L.h_row_lat.data(), L.n);
-  L.val = dalloc<double>(c->owned, ell.size());
-  h2d(s, L.val, ell.data(), ell.size());
-  // uniform interior stencil: the most frequent row among rows with all K
-  // slots non-zero (rows hashed after rounding to 12 significant digits)
   std::vector<double> ref(L.K, 0.0);
   bool have_ref = false;
   if (c->opt.compress) {
     std::vector<std::pair<uint64_t, int>> keys;
-    keys.reserve(L.n);
-    for (int i = 0; i < L.n; ++i) {
-      bool full = true;
+    keys.reserve(n);
+    for (int i = 0; i < n; ++i) {
+      bool cand = full ? (*full)[i] != 0 : true;
       uint64_t h = 1469598103934665603ull;
-      for (int sl = 0; sl < L.K && full; ++sl) {
-        const double v = ell[size_t(sl) * L.n + i];
-        if (v == 0.0) full = false;
+      for (int sl = 0; sl < L.K && cand; ++sl) {
+        const double v = ell[size_t(sl) * n + i];
+        if (!full && v == 0.0) cand = false;
         const double q = std::nearbyint(v * 1e12);
         uint64_t u;
         std::memcpy(&u, &q, 8);
         h = (h ^ u) * 1099511628211ull;
       }
-      if (full) keys.push_back({h, i});
+      if (cand) keys.push_back({h, i});
     }
     std::sort(keys.begin(), keys.end());
     int best = -1, bestc = 0;
@@ -370,30 +330,29 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
       a = b;
     }
     if (best >= 0 && bestc >= 16) {
-      for (int sl = 0; sl < L.K; ++sl) ref[sl] = ell[size_t(sl) * L.n + best];
+      for (int sl = 0; sl < L.K; ++sl) ref[sl] = ell[size_t(sl) * n + best];
       have_ref = true;
     }
   }
   double refmax = 0.0;
   for (double v : ref) refmax = std::max(refmax, std::fabs(v));
-  L.h_meta.assign(L.n, 0);
+  out.h_meta.assign(n, 0);
+  out.n_uniform = 0;
   std::vector<int32_t> comp;
-  for (int i = 0; i < L.n; ++i) {
+  for (int i = 0; i < n; ++i) {
     bool uni = have_ref;
-    for (int sl = 0; sl < L.K && uni; ++sl)
-      uni = std::fabs(ell[size_t(sl) * L.n + i] - ref[sl]) <= 1e-14 * refmax;
+    for (int sl = 0; sl < L.K && uni; ++sl) uni = std::fabs(ell[size_t(sl) * n + i] - ref[sl]) <= 1e-14 * refmax;
     if (uni) {
-      L.h_meta[i] = kMetaIndex;
-      ++L.n_uniform;
+      out.h_meta[i] = kMetaIndex;
+      ++out.n_uniform;
     } else {
-      L.h_meta[i] = uint32_t(comp.size());
+      out.h_meta[i] = uint32_t(comp.size());
       comp.push_back(i);
     }
   }
   const int nv = int(comp.size());
-  // lattice tiles of the stencil kernels (32 x 8 points in 2D, 16 x 4 x 4 in
-  // 3D): stored rows renumbered tile by tile (lattice order inside a tile), so
-  // that the stored rows of a tile are one consecutive range of value columns
+  OpView<double> &o64 = out.op64;
+  OpView<float> &o32 = out.op32;
   const bool tiled = (L.dim == 2 && L.reach <= 3) || (L.dim == 3 && L.reach <= 2);
   std::vector<int32_t> ord(comp);  // value column g -> row
   {
@@ -414,48 +373,48 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
     std::vector<int32_t> tg0(size_t(ntiles) + 1, 0), sloc;
     if (tiled) {
       std::vector<int32_t> cnt(size_t(ntiles) + 1, 0);
-      for (int32_t i : comp) ++cnt[size_t(tile_of(L.h_row_lat[i])) + 1];
+      for (int32_t i : comp) ++cnt[size_t(tile_of(lat[i])) + 1];
       for (int64_t b = 0; b < ntiles; ++b) cnt[size_t(b) + 1] += cnt[size_t(b)];
       tg0.assign(cnt.begin(), cnt.end());
       // rows in lattice order: a stable placement keeps lattice order per tile
-      for (int32_t i : comp) ord[size_t(cnt[size_t(tile_of(L.h_row_lat[i]))]++)] = i;
+      for (int32_t i : comp) ord[size_t(cnt[size_t(tile_of(lat[i]))]++)] = i;
       sloc.resize(ord.size());
-      for (size_t g = 0; g < ord.size(); ++g) sloc[g] = local_of(L.h_row_lat[ord[g]]);
+      for (size_t g = 0; g < ord.size(); ++g) sloc[g] = local_of(lat[ord[g]]);
     }
-    for (int g = 0; g < nv; ++g) L.h_meta[ord[g]] = uint32_t(g);
+    for (int g = 0; g < nv; ++g) out.h_meta[ord[g]] = uint32_t(g);
     int32_t *d_sloc = dalloc<int32_t>(c->owned, std::max<size_t>(sloc.size(), 1));
     if (!sloc.empty()) h2d(s, d_sloc, sloc.data(), sloc.size());
     int32_t *d_tg0 = dalloc<int32_t>(c->owned, tg0.size());
     h2d(s, d_tg0, tg0.data(), tg0.size());
     std::vector<int32_t> l2r(tiled ? size_t(L.lattice) : 1, -1);
     if (tiled)
-      for (int i = 0; i < L.n; ++i) l2r[size_t(L.h_row_lat[i])] = i;
+      for (int i = 0; i < n; ++i) l2r[size_t(lat[i])] = i;
     int32_t *d_l2r = dalloc<int32_t>(c->owned, l2r.size());
     h2d(s, d_l2r, l2r.data(), l2r.size());
-    for (auto *o : {&L.op64.sloc, &L.op32.sloc}) *o = d_sloc;
-    for (auto *o : {&L.op64.tile_g0, &L.op32.tile_g0}) *o = d_tg0;
-    for (auto *o : {&L.op64.lat2row, &L.op32.lat2row}) *o = d_l2r;
-    L.op64.sx = L.op32.sx = sx;
-    L.op64.sy = L.op32.sy = sy;
-    L.op64.sz = L.op32.sz = sz;
-    L.op64.ntx = L.op32.ntx = ntx;
-    L.op64.nty = L.op32.nty = nty;
-    L.op64.ntiles = L.op32.ntiles = int(ntiles);
+    o64.sloc = o32.sloc = d_sloc;
+    o64.tile_g0 = o32.tile_g0 = d_tg0;
+    o64.lat2row = o32.lat2row = d_l2r;
+    o64.sx = o32.sx = sx;
+    o64.sy = o32.sy = sy;
+    o64.sz = o32.sz = sz;
+    o64.ntx = o32.ntx = ntx;
+    o64.nty = o32.nty = nty;
+    o64.ntiles = o32.ntiles = int(ntiles);
     HIP_CHECK_RET(hipStreamSynchronize(s));
   }
   // stored rows' values in 16-byte slot groups (SlotGroup): FP64 pairs, FP32 quadruples
   std::vector<double> cv(std::max<size_t>(stored_size(L.K, size_t(nv), 2), 2), 0.0);
   for (int g = 0; g < nv; ++g)
-    for (int sl = 0; sl < L.K; ++sl) cv[stored_at<double>(size_t(nv), size_t(g), sl)] = ell[size_t(sl) * L.n + ord[g]];
-  L.meta = dalloc<uint32_t>(c->owned, L.n);
-  h2d(s, L.meta, L.h_meta.data(), L.n);
+    for (int sl = 0; sl < L.K; ++sl) cv[stored_at<double>(size_t(nv), size_t(g), sl)] = ell[size_t(sl) * n + ord[g]];
+  out.meta = dalloc<uint32_t>(c->owned, n);
+  h2d(s, out.meta, out.h_meta.data(), n);
   double *cv64 = dalloc<double>(c->owned, cv.size());
   h2d(s, cv64, cv.data(), cv.size());
-  L.op64.off = L.off;
-  L.op64.val = cv64;
-  L.op64.nv = nv;
-  L.op32.off = L.off;
-  L.op32.nv = nv;
+  o64.off = L.off;
+  o64.val = cv64;
+  o64.nv = nv;
+  o32.off = L.off;
+  o32.nv = nv;
   {
     std::vector<float> ref32(ref.begin(), ref.end());
     std::vector<double> ref32d(ref32.begin(), ref32.end());
@@ -465,10 +424,10 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
     h2d(s, r64, ref.data(), L.K);
     h2d(s, r32, ref32.data(), L.K);
     h2d(s, r32d, ref32d.data(), L.K);
-    L.op64.ref = r64;
-    L.op64.refd = r64;
-    L.op32.ref = r32;
-    L.op32.refd = r32d;
+    o64.ref = r64;
+    o64.refd = r64;
+    o32.ref = r32;
+    o32.refd = r32d;
     HIP_CHECK_RET(hipStreamSynchronize(s));
   }
   if (c->opt.precision == IMSMG_MIXED) {
@@ -478,10 +437,174 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
         c32[stored_at<float>(size_t(nv), size_t(g), sl)] = float(cv[stored_at<double>(size_t(nv), size_t(g), sl)]);
     float *cv32 = dalloc<float>(c->owned, c32.size());
     h2d(s, cv32, c32.data(), c32.size());
-    L.op32.val = cv32;
+    o32.val = cv32;
     HIP_CHECK_RET(hipStreamSynchronize(s));
   }
-  const size_t vlen = size_t(L.lattice + 2 * L.guard);
+}
+
+// Slot of the lattice offset from row point li to column point lj, or bad().
+int stencil_slot(const Level &L, int64_t li, int64_t lj) {
+  const int W = 2 * L.reach + 1;
+  int mi[3] = {0, 0, 0}, mj[3] = {0, 0, 0};
+  lat_multi(li, L.shape, L.dim, mi);
+  lat_multi(lj, L.shape, L.dim, mj);
+  int sl = 0;
+  for (int a = L.dim - 1; a >= 0; --a) {
+    const int d = mj[a] - mi[a];
+    if (d < -L.reach || d > L.reach) bad("CSR entry outside the lattice stencil");
+    sl = sl * W + (d + L.reach);
+  }
+  return sl;
+}
+
+void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice &lat) {
+  hipStream_t s = c->stream;
+  if (lat.dim < 2 || lat.dim > 3) bad("lattice dim must be 2 or 3");
+  if (lat.reach < 1 || (lat.dim == 3 && lat.reach > 2) || lat.reach > 5) bad("lattice reach must be 1..5 (2D) or 1..2 (3D)");
+  if (A.nrows <= 0 || A.nrows != A.ncols) bad("A must be square and non-empty");
+  if (!A.rowptr || !A.col || !A.val || !lat.dof_to_lattice) bad("null CSR or lattice array");
+  const int nc = c->opt.ncomp;
+  if (A.nrows % nc) bad("the operator's size must be ncomp times the number of lattice functions");
+  L.dim = lat.dim;
+  L.reach = lat.reach;
+  int64_t latsz = 1;
+  for (int a = 0; a < 3; ++a) {
+    L.shape[a] = a < lat.dim ? lat.shape[a] : 1;
+    if (L.shape[a] < 1) bad("lattice shape must be positive");
+    latsz *= L.shape[a];
+  }
+  if (latsz > (int64_t(1) << 30)) bad("lattice too large");
+  L.lattice = latsz;
+  L.n = A.nrows;
+  L.ncomp = nc;
+  L.ns = A.nrows / nc;
+  const int W = 2 * L.reach + 1;
+  L.K = L.dim == 2 ? W * W : W * W * W;
+  if (L.K > IMSMG_MAX_SLOTS) bad("stencil too large");
+  // slot offsets (x fastest)
+  int64_t maxoff = 0;
+  for (int sl = 0; sl < L.K; ++sl) {
+    int o[3] = {0, 0, 0}, r = sl;
+    for (int a = 0; a < L.dim; ++a) {
+      o[a] = r % W - L.reach;
+      r /= W;
+    }
+    int64_t lin = o[0] + int64_t(L.shape[0]) * (o[1] + int64_t(L.shape[1]) * o[2]);
+    L.off.off[sl] = int32_t(lin);
+    maxoff = std::max<int64_t>(maxoff, lin < 0 ? -lin : lin);
+    if (lin == 0) L.center = sl;
+  }
+  L.guard = maxoff + 64;
+  L.cstride = L.lattice + 2 * L.guard;
+  if (nc * L.cstride > (int64_t(1) << 31) - 1) bad("lattice too large");
+  const int ns = L.ns;
+  for (int i = 0; i < ns; ++i) {
+    if (lat.dof_to_lattice[i] < 0 || lat.dof_to_lattice[i] >= latsz) bad("dof_to_lattice out of range");
+    if (i && lat.dof_to_lattice[i] <= lat.dof_to_lattice[i - 1]) bad("dof_to_lattice must be strictly increasing");
+  }
+  // rows: lattice point and memory position (component c at c * cstride)
+  L.h_lat.resize(L.n);
+  L.h_row_lat.resize(L.n);
+  for (int cc = 0; cc < nc; ++cc)
+    for (int i = 0; i < ns; ++i) {
+      L.h_lat[size_t(cc) * ns + i] = lat.dof_to_lattice[i];
+      L.h_row_lat[size_t(cc) * ns + i] = int32_t(cc * L.cstride + lat.dof_to_lattice[i]);
+    }
+  if (A.rowptr[0] != 0 || A.rowptr[L.n] != A.nnz) bad("CSR rowptr inconsistent with nnz");
+  // CSR -> slot-major lattice-ELL per component block (b = ci * nc + cj)
+  const int nb = nc * nc;
+  std::vector<std::vector<double>> ell(nb, std::vector<double>(size_t(L.K) * ns, 0.0));
+  std::vector<std::vector<uint8_t>> full(nc > 1 ? nb : 0, std::vector<uint8_t>(ns, 0));
+  for (int r = 0; r < L.n; ++r) {
+    const int ci = r / ns, i = r % ns;
+    int cnt[kMaxComp] = {0, 0, 0};
+    for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k) {
+      const int j = A.col[k];
+      if (j < 0 || j >= L.n) bad("CSR column out of range");
+      const int cj = j / ns;
+      const int sl = stencil_slot(L, L.h_lat[r], L.h_lat[j]);
+      ell[size_t(ci) * nc + cj][size_t(sl) * ns + i] = A.val[k];
+      ++cnt[cj];
+    }
+    if (nc > 1)
+      for (int cj = 0; cj < nc; ++cj) full[size_t(ci) * nc + cj][i] = cnt[cj] == L.K;
+  }
+  // an SPD operator has a positive, finite diagonal: reject the others before
+  // anything is launched on them
+  for (int cc = 0; cc < nc; ++cc)
+    for (int i = 0; i < ns; ++i) {
+      const double d = ell[size_t(cc) * nc + cc][size_t(L.center) * ns + i];
+      if (!(d > 0.0) || !std::isfinite(d))
+        bad("operator has a non-positive diagonal entry (not SPD)", IMSMG_ERR_NOT_SPD);
+    }
+  L.row_lat = dalloc<int32_t>(c->owned, L.n);
+  h2d(s, L.row_lat, L.h_row_lat.data(), L.n);
+  if (nc == 1) {
+    L.val = dalloc<double>(c->owned, ell[0].size());
+    h2d(s, L.val, ell[0].data(), ell[0].size());
+    L.srow_lat = L.row_lat;
+    Compressed cp;
+    compress_operator(c, L, L.n, L.h_row_lat, ell[0], nullptr, cp);
+    L.op64 = cp.op64;
+    L.op32 = cp.op32;
+    L.h_meta = std::move(cp.h_meta);
+    L.meta = cp.meta;
+    L.n_uniform = cp.n_uniform;
+  } else {
+    // the diagonal blocks as one lattice-ELL over all rows (row c ns + i:
+    // block (c, c)'s row i): the per-component Schwarz blocks gather from it
+    std::vector<double> dv(size_t(L.K) * L.n, 0.0);
+    for (int cc = 0; cc < nc; ++cc)
+      for (int sl = 0; sl < L.K; ++sl)
+        std::copy(ell[size_t(cc) * nc + cc].begin() + size_t(sl) * ns,
+                  ell[size_t(cc) * nc + cc].begin() + size_t(sl + 1) * ns, dv.begin() + size_t(sl) * L.n + size_t(cc) * ns);
+    L.val = dalloc<double>(c->owned, dv.size());
+    h2d(s, L.val, dv.data(), dv.size());
+    L.srow_lat = dalloc<int32_t>(c->owned, ns);
+    h2d(s, L.srow_lat, lat.dof_to_lattice, ns);
+    std::vector<int32_t> slat(lat.dof_to_lattice, lat.dof_to_lattice + ns);
+    L.vops64 = VecOps<double>{};
+    L.vops32 = VecOps<float>{};
+    L.n_uniform = 0;
+    for (int b = 0; b < nb; ++b) {
+      Compressed cp;
+      compress_operator(c, L, ns, slat, ell[b], &full[b], cp);
+      if (b == 0) {
+        L.op64 = cp.op64;
+        L.op32 = cp.op32;
+      }
+      if (b % (nc + 1) == 0) L.n_uniform += cp.n_uniform;
+      L.vops64.refd[b] = cp.op64.refd;
+      L.vops64.val[b] = cp.op64.val;
+      L.vops32.refd[b] = cp.op32.refd;
+      L.vops32.val[b] = cp.op32.val;
+      for (auto *v : {&L.vops64.nv[b], &L.vops32.nv[b]}) *v = cp.op64.nv;
+      L.vops64.sloc[b] = L.vops32.sloc[b] = cp.op64.sloc;
+      L.vops64.tile_g0[b] = L.vops32.tile_g0[b] = cp.op64.tile_g0;
+      L.vops64.meta[b] = L.vops32.meta[b] = cp.meta;
+    }
+    if (L.op64.ntiles == 0) bad("vector operators need a tiled 3D stencil (reach 1 or 2)");
+    auto fill_geom = [&](auto &v) {
+      v.lat2row = L.op64.lat2row;
+      v.sx = L.op64.sx;
+      v.sy = L.op64.sy;
+      v.sz = L.op64.sz;
+      v.ntx = L.op64.ntx;
+      v.nty = L.op64.nty;
+      v.ntiles = L.op64.ntiles;
+      v.ncomp = nc;
+      v.ns = ns;
+      v.cstride = L.cstride;
+    };
+    fill_geom(L.vops64);
+    fill_geom(L.vops32);
+    // per row only the general-block flag (set at factorization)
+    L.h_meta.assign(L.n, 0u);
+    L.meta = dalloc<uint32_t>(c->owned, L.n);
+    h2d(s, L.meta, L.h_meta.data(), L.n);
+    HIP_CHECK_RET(hipStreamSynchronize(s));
+  }
+  const size_t vlen = size_t(nc * L.cstride);
   double *vs[4];
   for (int k = 0; k < 4; ++k) {
     double *b = dalloc<double>(c->owned, vlen);
@@ -543,12 +666,13 @@ void setup_tensor_transfer(imsmg_ctx *c, Level &F, const Level &Cl, const imsmg_
   std::vector<double> M(R1, R1 + size_t(mc) * mf), Mt(size_t(mf) * mc);
   for (int i = 0; i < mc; ++i)
     for (int j = 0; j < mf; ++j) Mt[size_t(j) * mc + i] = M[size_t(i) * mf + j];
-  // check the CSR R entry by entry against the masked tensor product
+  // check the CSR R entry by entry against the masked tensor product (on the
+  // scalar functions: R of a vector level is checked block by block before)
   std::vector<int32_t> f2c(size_t(F.lattice), -1);
-  for (int k = 0; k < F.n; ++k) f2c[F.h_row_lat[k]] = k;
-  for (int i = 0; i < Cl.n; ++i) {
+  for (int k = 0; k < F.ns; ++k) f2c[F.h_lat[k]] = k;
+  for (int i = 0; i < Cl.ns; ++i) {
     int mi[3] = {0, 0, 0};
-    lat_multi(Cl.h_row_lat[i], Cl.shape, Cl.dim, mi);
+    lat_multi(Cl.h_lat[i], Cl.shape, Cl.dim, mi);
     int64_t cnt = 0;
     int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     for (int a = 0; a < 3; ++a) {
@@ -573,7 +697,7 @@ void setup_tensor_transfer(imsmg_ctx *c, Level &F, const Level &Cl, const imsmg_
     if (cnt != R.rowptr[i + 1] - R.rowptr[i]) bad("R is not the masked tensor product of the given two-scale matrix");
     for (int64_t k = R.rowptr[i]; k < R.rowptr[i + 1]; ++k) {
       int mk[3] = {0, 0, 0};
-      lat_multi(F.h_row_lat[R.col[k]], F.shape, F.dim, mk);
+      lat_multi(F.h_lat[R.col[k]], F.shape, F.dim, mk);
       double v = 1.0;
       for (int a = 0; a < F.dim; ++a) v *= M[size_t(mi[a]) * mf + mk[a]];
       if (!(std::fabs(v - R.val[k]) <= 1e-13 * std::fabs(v)))
@@ -603,7 +727,7 @@ void setup_tensor_transfer(imsmg_ctx *c, Level &F, const Level &Cl, const imsmg_
   // (window = tile extent + the stencil reach on both sides)
   F.pro_ok = false;
   const bool tiled = F.op64.ntiles > 0;
-  if (tiled && F.dim == 2 && F.pbW <= kBandMax) {
+  if (tiled && F.dim == 2 && F.ncomp == 1 && F.pbW <= kBandMax) {
     const int T[3] = {F.dim == 2 ? kTile2X : kTile3X, F.dim == 2 ? kTile2Y : kTile3Y, F.dim == 2 ? 1 : kTile3Z};
     const int nt[3] = {F.op64.ntx, F.op64.nty, F.dim == 3 ? (F.shape[2] + T[2] - 1) / T[2] : 1};
     // per-axis bound of the coarse window (the kernels' compile-time extent)
@@ -673,7 +797,34 @@ void setup_transfer(imsmg_ctx *c, Level &F, const Level &Cl, const imsmg_csr &R,
     }
   }
   if (two_scale) {
-    setup_tensor_transfer(c, F, Cl, R, two_scale);
+    if (F.ncomp == 1) {
+      setup_tensor_transfer(c, F, Cl, R, two_scale);
+      return;
+    }
+    // vector level: R = I (x) R_s; the scalar block R_s, and every other
+    // diagonal block equal to it, no coupling between components
+    const int nsf = F.ns, nsc = Cl.ns;
+    std::vector<int32_t> rp(size_t(nsc) + 1, 0), rc;
+    std::vector<double> rv;
+    for (int i = 0; i < nsc; ++i) {
+      for (int64_t k = R.rowptr[i]; k < R.rowptr[i + 1]; ++k) {
+        if (R.col[k] >= nsf) bad("vector R must be block diagonal (one block per component)");
+        rc.push_back(R.col[k]);
+        rv.push_back(R.val[k]);
+      }
+      rp[size_t(i) + 1] = int32_t(rc.size());
+    }
+    for (int cc = 1; cc < F.ncomp; ++cc)
+      for (int i = 0; i < nsc; ++i) {
+        const int r = cc * nsc + i;
+        if (R.rowptr[r + 1] - R.rowptr[r] != rp[size_t(i) + 1] - rp[size_t(i)])
+          bad("vector R must repeat one scalar block per component");
+        for (int64_t k = R.rowptr[r], q = rp[size_t(i)]; k < R.rowptr[r + 1]; ++k, ++q)
+          if (R.col[k] != rc[size_t(q)] + cc * nsf || R.val[k] != rv[size_t(q)])
+            bad("vector R must repeat one scalar block per component");
+      }
+    const imsmg_csr Rs{nsc, nsf, int64_t(rc.size()), rp.data(), rc.data(), rv.data()};
+    setup_tensor_transfer(c, F, Cl, Rs, two_scale);
     return;
   }
   F.rw = rw;
@@ -720,10 +871,16 @@ void residual(imsmg_ctx *c, Level &L, const double *x, const double *b, double *
               bool timed) {
   hipEvent_t *ev = timed ? timed_pair(c) : nullptr;
   if (ev) HIP_CHECK_RET(hipEventRecord(ev[0], c->stream));
-  if (mixed(c))
+  if (L.ncomp > 1) {
+    if (mixed(c))
+      launch_vresidual(c->stream, L.K, L.vops32, L.meta, x, b, y, done);
+    else
+      launch_vresidual(c->stream, L.K, L.vops64, L.meta, x, b, y, done);
+  } else if (mixed(c)) {
     launch_residual(c->stream, L.n, L.K, L.op32, L.row_lat, L.meta, x, b, y, done);
-  else
+  } else {
     launch_residual(c->stream, L.n, L.K, L.op64, L.row_lat, L.meta, x, b, y, done);
+  }
   if (ev) HIP_CHECK_RET(hipEventRecord(ev[1], c->stream));
 }
 
@@ -736,10 +893,17 @@ void smooth_step(imsmg_ctx *c, Level &L, const double *xa, double *xb, const int
   // timed: opt.timing identical launches (xa and r are only read)
   const int reps = ev ? c->opt.timing : 1;
   for (int k = 0; k < reps; ++k) {
-    if (mixed(c))
+    if (L.ncomp > 1) {
+      if (pv) bad("internal: fused prolongation on a vector level", IMSMG_ERR_HIP);
+      if (mixed(c))
+        launch_vresidual_smooth(c->stream, L.K, L.vops32, L.meta, L.c, xa, L.r, L.rh, xb, done);
+      else
+        launch_vresidual_smooth(c->stream, L.K, L.vops64, L.meta, L.c, xa, L.r, L.rh, xb, done);
+    } else if (mixed(c)) {
       launch_residual_smooth(c->stream, L.n, L.K, L.op32, L.row_lat, L.meta, L.c, xa, L.r, L.rh, xb, done, pv);
-    else
+    } else {
       launch_residual_smooth(c->stream, L.n, L.K, L.op64, L.row_lat, L.meta, L.c, xa, L.r, L.rh, xb, done, pv);
+    }
   }
   if (ev) HIP_CHECK_RET(hipEventRecord(ev[1], c->stream));
   launch_smooth_general(c->stream, L.ng, L.grow_lat, L.sptr, L.scol, L.sval, L.rh, xb, done, L.gen_lanes);
@@ -751,18 +915,24 @@ void smooth_step(imsmg_ctx *c, Level &L, const double *xa, double *xb, const int
 void restrict_to(imsmg_ctx *c, Level &L, Level &Cl, const double *rf, double *rc, double *xinit,
                  const int32_t *done) {
   const double *ci = xinit ? Cl.c : nullptr;
-  if (L.tensor)
-    launch_tensor_transfer(c->stream, L.dim, Cl.n, Cl.row_lat, Cl.shape[0], Cl.shape[1], L.rb_start, L.rb_len,
-                           L.rb_coef, L.rbW, L.shape[0], L.shape[1], rf, rc, 0, ci, xinit, done);
-  else
+  if (L.tensor) {
+    // vector levels: the scalar transfer once per component
+    for (int cc = 0; cc < L.ncomp; ++cc)
+      launch_tensor_transfer(c->stream, L.dim, Cl.ns, Cl.srow_lat, Cl.shape[0], Cl.shape[1], L.rb_start, L.rb_len,
+                             L.rb_coef, L.rbW, L.shape[0], L.shape[1], rf + cc * L.cstride, rc + cc * Cl.cstride, 0,
+                             ci ? ci + size_t(cc) * Cl.ns : nullptr, xinit ? xinit + cc * Cl.cstride : nullptr, done);
+  } else {
     launch_ell_gather(c->stream, Cl.n, L.rw, Cl.row_lat, L.rcol, L.rval, rf, rc, 0, ci, xinit, done);
+  }
 }
 
 // xf += R_l^T xc
 void prolong_add(imsmg_ctx *c, Level &L, Level &Cl, const double *xc, double *xf, const int32_t *done) {
   if (L.tensor)
-    launch_tensor_transfer(c->stream, L.dim, L.n, L.row_lat, L.shape[0], L.shape[1], L.pb_start, L.pb_len, L.pb_coef,
-                           L.pbW, Cl.shape[0], Cl.shape[1], xc, xf, 1, nullptr, nullptr, done);
+    for (int cc = 0; cc < L.ncomp; ++cc)
+      launch_tensor_transfer(c->stream, L.dim, L.ns, L.srow_lat, L.shape[0], L.shape[1], L.pb_start, L.pb_len,
+                             L.pb_coef, L.pbW, Cl.shape[0], Cl.shape[1], xc + cc * Cl.cstride, xf + cc * L.cstride, 1,
+                             nullptr, nullptr, done);
   else
     launch_ell_gather(c->stream, L.n, L.tw, L.row_lat, L.tcol, L.tval, xc, xf, 1, nullptr, nullptr, done);
 }
@@ -1069,7 +1239,7 @@ void factor_level(imsmg_ctx *c, int l) {
     h_invoff[t + 1] = h_invoff[t] + int64_t(sz) * sz;
     for (int k = L.in_ptr[j]; k < L.in_ptr[j + 1]; ++k) {
       h_brow.push_back(L.in_idx[k]);
-      h_blat.push_back(L.h_row_lat[L.in_idx[k]]);
+      h_blat.push_back(L.h_lat[L.in_idx[k]]);  // lattice point (the gather's slot geometry)
     }
   }
   std::vector<void *> tmp;
@@ -1594,7 +1764,10 @@ void apply_S(imsmg_ctx *c, Level &L, const double *x, double *y) {
 
 // y = A x on level L in FP64 (y, x padded)
 void apply_A64(imsmg_ctx *c, Level &L, const double *x, double *y) {
-  launch_residual(c->stream, L.n, L.K, L.op64, L.row_lat, L.meta, x, nullptr, y, c->zero_flag);
+  if (L.ncomp > 1)
+    launch_vresidual(c->stream, L.K, L.vops64, L.meta, x, nullptr, y, c->zero_flag);
+  else
+    launch_residual(c->stream, L.n, L.K, L.op64, L.row_lat, L.meta, x, nullptr, y, c->zero_flag);
 }
 
 // Power iteration for lambda_max(S A) with the Rayleigh quotient in the A
@@ -1832,18 +2005,23 @@ void factor_coarsest(imsmg_ctx *c) {
   Level &L = c->lv[0];
   const int n = L.n;
   if (n > 8192) bad("coarsest level larger than 8192 unknowns; use more levels");
-  std::vector<int32_t> lat2c(size_t(L.lattice + 2 * L.guard), -1);
-  for (int i = 0; i < n; ++i) lat2c[size_t(L.h_row_lat[i] + L.guard)] = i;
   std::vector<void *> tmp;
   struct TmpFree {
     std::vector<void *> &v;
     ~TmpFree() { free_list(v); }
   } tf{tmp};
-  int32_t *d_l2c = dalloc<int32_t>(tmp, lat2c.size());
-  h2d(s, d_l2c, lat2c.data(), lat2c.size());
   L.Ainv = dalloc<double>(c->factor_owned, size_t(n) * n);
-  HIP_CHECK_RET(hipMemsetAsync(L.Ainv, 0, size_t(n) * n * sizeof(double), s));
-  launch_dense_from_ell(s, n, L.K, L.off, L.row_lat, d_l2c + L.guard, L.val, L.Ainv);
+  if (L.ncomp > 1) {
+    // vector level: the dense operator kept at setup (every component pair)
+    HIP_CHECK_RET(hipMemcpyAsync(L.Ainv, L.dense0, size_t(n) * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    std::vector<int32_t> lat2c(size_t(L.lattice + 2 * L.guard), -1);
+    for (int i = 0; i < n; ++i) lat2c[size_t(L.h_row_lat[i] + L.guard)] = i;
+    int32_t *d_l2c = dalloc<int32_t>(tmp, lat2c.size());
+    h2d(s, d_l2c, lat2c.data(), lat2c.size());
+    HIP_CHECK_RET(hipMemsetAsync(L.Ainv, 0, size_t(n) * n * sizeof(double), s));
+    launch_dense_from_ell(s, n, L.K, L.off, L.row_lat, d_l2c + L.guard, L.val, L.Ainv);
+  }
   double *colk = dalloc<double>(tmp, n), *rowk = dalloc<double>(tmp, n);
   int32_t *d_bad = dalloc<int32_t>(tmp, 1);
   HIP_CHECK_RET(hipMemsetAsync(d_bad, 0, sizeof(int32_t), s));
@@ -1889,6 +2067,7 @@ void free_multi(imsmg_ctx *c) {
 }
 
 void ensure_multi(imsmg_ctx *c, int R) {
+  if (c->lv.back().ncomp > 1) bad("vector problems: the multi-column form is not supported");
   if (c->mb.R == R) return;
   free_multi(c);
   hipStream_t s = c->stream;
@@ -2008,7 +2187,10 @@ void cg_iteration(imsmg_ctx *c, bool timing) {
   vcycle_level(c, int(c->lv.size()) - 1, done, timing);
   launch_cg_dot_rz(c->stream, F.n, F.row_lat, F.r, F.x, c->part, c->st, c->opt.flexible_cg);
   launch_cg_direction(c->stream, F.n, F.row_lat, F.x, c->p, c->st);
-  launch_cg_spmv_pq(c->stream, F.n, F.K, F.op64, F.row_lat, F.meta, c->p, c->q, c->part, c->st);
+  if (F.ncomp > 1)
+    launch_vcg_spmv_pq(c->stream, F.K, F.vops64, F.meta, c->p, c->q, c->part, c->st);
+  else
+    launch_cg_spmv_pq(c->stream, F.n, F.K, F.op64, F.row_lat, F.meta, c->p, c->q, c->part, c->st);
   // z_k = F.x until the next V-cycle (F.xs may be the same buffer)
   launch_cg_update(c->stream, F.n, F.row_lat, c->p, c->q, c->xs, F.r, F.c, F.xs, c->opt.flexible_cg ? F.x : nullptr,
                    c->part, c->st, c->opt.max_iter);
@@ -2040,7 +2222,11 @@ int pcg_solve_core(imsmg_ctx *c, const double *b_dev, double *x_dev, double rtol
     CGState h{};
     int restarts = 0;
     while (true) {
-      launch_cg_init(s, F.n, F.K, F.op64, F.row_lat, F.meta, c->xs, c->bs, F.r, c->part, c->st, rtol, restarts > 0);
+      if (F.ncomp > 1)
+        launch_vcg_init(s, F.K, F.vops64, F.meta, c->xs, c->bs, F.r, c->part, c->st, rtol, restarts > 0);
+      else
+        launch_cg_init(s, F.n, F.K, F.op64, F.row_lat, F.meta, c->xs, c->bs, F.r, c->part, c->st, rtol,
+                       restarts > 0);
       launch_diag_scale(s, F.n, F.row_lat, F.c, F.r, F.xs, &c->st->done);
       HIP_CHECK_RET(hipGetLastError());
       const int m = c->opt.check_every;
@@ -2068,7 +2254,10 @@ int pcg_solve_core(imsmg_ctx *c, const double *b_dev, double *x_dev, double rtol
         if (h.done) break;
       }
       // true residual ||b - A x|| / ||b||
-      launch_cg_true_residual(s, F.n, F.K, F.op64, F.row_lat, F.meta, c->xs, c->bs, c->part, c->st);
+      if (F.ncomp > 1)
+        launch_vcg_true_residual(s, F.K, F.vops64, F.meta, c->xs, c->bs, c->part, c->st);
+      else
+        launch_cg_true_residual(s, F.n, F.K, F.op64, F.row_lat, F.meta, c->xs, c->bs, c->part, c->st);
       HIP_CHECK_RET(hipMemcpyAsync(&h, c->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
       HIP_CHECK_RET(hipStreamSynchronize(s));
       const double true_rel = h.bb > 0.0 ? std::sqrt(h.aux / h.bb) : 0.0;
@@ -2120,6 +2309,7 @@ void imsmg_default_options(imsmg_options *o) {
   o->coarse_smoother = -1;
   o->cycle = 1;
   o->flag_min_rows = kSmallLevel;
+  o->ncomp = 1;
 }
 
 int imsmg_create(imsmg_ctx **out, int device, void *stream) {
@@ -2178,10 +2368,29 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
     if (c->opt.flag_min_rows < 0) bad("flag_min_rows must be >= 0");
     if (c->opt.use_learned < 0 || c->opt.use_learned > 2) bad("use_learned must be 0, 1 or 2");
     if (c->opt.use_learned && uses_ms(c->opt, nlevels)) bad("use_learned needs the additive smoother on every level");
+    if (c->opt.ncomp != 1 && c->opt.ncomp != kMaxComp) bad("ncomp must be 1 or 3");
+    if (c->opt.ncomp > 1) {
+      if (Lt[nlevels - 1].dim != 3) bad("vector problems (ncomp 3) need a 3D lattice");
+      if (uses_ms(c->opt, nlevels)) bad("vector problems: the multiplicative smoother is not supported");
+      if (c->opt.use_learned) bad("vector problems: learned weights are not supported");
+      if (c->opt.block_gemm) bad("vector problems: block_gemm is not supported");
+    }
     c->lv.resize(nlevels);
     for (int l = 0; l < nlevels; ++l) {
       if (Lt[l].dim != Lt[nlevels - 1].dim) bad("all levels must share the dimension");
       setup_level(c, c->lv[l], A[l], Lt[l]);
+    }
+    if (c->opt.ncomp > 1) {
+      // the coarsest vector operator as a dense matrix (every component pair)
+      Level &C0 = c->lv[0];
+      const int n0 = C0.n;
+      if (n0 > 8192) bad("coarsest level larger than 8192 unknowns; use more levels");
+      std::vector<double> D(size_t(n0) * n0, 0.0);
+      for (int i = 0; i < n0; ++i)
+        for (int64_t k = A[0].rowptr[i]; k < A[0].rowptr[i + 1]; ++k) D[size_t(i) * n0 + A[0].col[k]] = A[0].val[k];
+      C0.dense0 = dalloc<double>(c->owned, D.size());
+      h2d(c->stream, C0.dense0, D.data(), D.size());
+      HIP_CHECK_RET(hipStreamSynchronize(c->stream));
     }
     for (int l = 1; l < nlevels; ++l) setup_transfer(c, c->lv[l], c->lv[l - 1], R[l], Lt[l].two_scale);
     for (int l = 1; l < nlevels; ++l) {
@@ -2204,6 +2413,8 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
         for (int k = L.in_ptr[j]; k < L.in_ptr[j + 1]; ++k) {
           if (L.in_idx[k] < 0 || L.in_idx[k] >= L.n) bad("patch index out of range");
           if (k > L.in_ptr[j] && L.in_idx[k] <= L.in_idx[k - 1]) bad("patch indices must be sorted and unique");
+          if (L.in_idx[k] / L.ns != L.in_idx[L.in_ptr[j]] / L.ns)
+            bad("vector problems: every Schwarz block must hold DOFs of one component");
         }
       if (E) {
         const imsmg_elements &e = E[l];
@@ -2233,7 +2444,7 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
       }
     }
     Level &F = c->lv.back();
-    const size_t vlen = size_t(F.lattice + 2 * F.guard);
+    const size_t vlen = size_t(F.ncomp * F.cstride);
     double *vv[4];
     for (int k = 0; k < 4; ++k) {
       vv[k] = dalloc<double>(c->owned, vlen);
@@ -2249,7 +2460,7 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
     HIP_CHECK_RET(hipMemsetAsync(c->zero_flag, 0, sizeof(int32_t), c->stream));
     c->st = dalloc<CGState>(c->owned, 1);
     HIP_CHECK_RET(hipMemsetAsync(c->st, 0, sizeof(CGState), c->stream));
-    c->part = dalloc<double>(c->owned, 2 * size_t(std::max(reduction_blocks(F.n), F.op64.ntiles)) + 64);
+    c->part = dalloc<double>(c->owned, 2 * size_t(std::max(reduction_blocks(F.n), F.op64.ntiles * F.ncomp)) + 64);
     HIP_CHECK_RET(hipStreamSynchronize(c->stream));
     c->ready = true;
     c->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_setup0).count();
@@ -2764,6 +2975,7 @@ int imsmg_setup_batched(imsmg_ctx *c, int nprob, const int *nlevels, const imsmg
                         const imsmg_elements *const *E, const imsmg_options *opt) {
   if (!c) return IMSMG_ERR_INVALID_ARG;
   if (nprob < 1 || !nlevels || !A || !R || !P || !L) return fail(c, IMSMG_ERR_INVALID_ARG, "bad batched arguments");
+  if (opt && opt->ncomp > 1) return fail(c, IMSMG_ERR_INVALID_ARG, "vector problems: the batched form is not supported");
   if (c->ready) return fail(c, IMSMG_ERR_STATE, "a set-up single-problem context cannot become a batch");
   for (imsmg_ctx *b : c->batch) imsmg_destroy(b);
   c->batch.clear();

@@ -9,8 +9,11 @@
 // the partial stores; no device-scope fence (an L2 write-back on a multi-XCD
 // part) is issued per workgroup.  Once the `done` flag is set, every kernel
 // returns at once.
+#include <stdexcept>
+
 #include "imsmg_internal.h"
 #include "op_row.h"
+#include "vec_row.h"
 
 namespace imsmg {
 
@@ -302,6 +305,91 @@ __global__ __launch_bounds__(kFinThreads) void k_cg_aux_fin(int m, const double 
   const double tot = sum_partials(part, m, lds);
   if (threadIdx.x == 0) st->aux = tot;
 }
+
+// Vector finest level: one workgroup per (lattice tile, component), partial
+// sums at blockIdx.y * gridDim.x + tile (the finalize adds them in index order).
+template <int K>
+__global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_vcg_init(VecOps<double> ops,
+                                                          const uint32_t *__restrict__ flags,
+                                                          const double *__restrict__ x,
+                                                          const double *__restrict__ b, double *__restrict__ r,
+                                                          double *__restrict__ part) {
+  __shared__ double lds[kRedThreads];
+  __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
+  const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
+  const int c = blockIdx.y;
+  const int64_t o = c * ops.cstride;
+  const double2 sm = vtile_rows<K, double>(blk, c, ops, flags, x, tile, InitEpi{b + o, r + o}, nullptr);
+  const double rr = block_sum<kRedThreads>(sm.x, lds);
+  const double bb = block_sum<kRedThreads>(sm.y, lds);
+  const int f = c * gridDim.x + blk, m = gridDim.x * gridDim.y;
+  if (threadIdx.x == 0) {
+    part[f] = rr;
+    part[m + f] = bb;
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_vcg_spmv_pq(VecOps<double> ops,
+                                                             const uint32_t *__restrict__ flags,
+                                                             const double *__restrict__ p, double *__restrict__ q,
+                                                             double *__restrict__ part, const CGState *st) {
+  __shared__ double lds[kRedThreads];
+  __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
+  const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
+  const int c = blockIdx.y;
+  const int64_t o = c * ops.cstride;
+  double acc = vtile_rows<K, double>(blk, c, ops, flags, p, tile, SpmvEpi{q + o}, &st->done).x;
+  if (st->done) return;
+  acc = block_sum<kRedThreads>(acc, lds);
+  if (threadIdx.x == 0) part[c * gridDim.x + blk] = acc;
+}
+
+template <int K>
+__global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_vcg_true_residual(VecOps<double> ops,
+                                                                   const uint32_t *__restrict__ flags,
+                                                                   const double *__restrict__ x,
+                                                                   const double *__restrict__ b,
+                                                                   double *__restrict__ part) {
+  __shared__ double lds[kRedThreads];
+  __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
+  const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
+  const int c = blockIdx.y;
+  const int64_t o = c * ops.cstride;
+  double acc = vtile_rows<K, double>(blk, c, ops, flags, x, tile, TrueResEpi{b + o}, nullptr).x;
+  acc = block_sum<kRedThreads>(acc, lds);
+  if (threadIdx.x == 0) part[c * gridDim.x + blk] = acc;
+}
+
+#define IMSMG_DISPATCH_V(K, KERNEL, ...)                                                 \
+  do {                                                                                   \
+    const dim3 g2(ops.ntiles, ops.ncomp);                                                \
+    if (K == 125)                                                                        \
+      KERNEL<125><<<g2, kRedThreads, 0, s>>>(__VA_ARGS__);                               \
+    else if (K == 27)                                                                    \
+      KERNEL<27><<<g2, kRedThreads, 0, s>>>(__VA_ARGS__);                                \
+    else                                                                                 \
+      throw std::invalid_argument("vector operators: 3D tiled stencils (K = 27 or 125)"); \
+  } while (0)
+
+void launch_vcg_init(hipStream_t s, int K, const VecOps<double> &ops, const uint32_t *flags, const double *x,
+                     const double *b, double *r, double *part, CGState *st, double rtol, int restart) {
+  IMSMG_DISPATCH_V(K, k_vcg_init, ops, flags, x, b, r, part);
+  k_cg_init_fin<<<1, kFinThreads, 0, s>>>(ops.ntiles * ops.ncomp, part, st, rtol, restart);
+}
+
+void launch_vcg_spmv_pq(hipStream_t s, int K, const VecOps<double> &ops, const uint32_t *flags, const double *p,
+                        double *q, double *part, CGState *st) {
+  IMSMG_DISPATCH_V(K, k_vcg_spmv_pq, ops, flags, p, q, part, st);
+  k_cg_pq_fin<<<1, kFinThreads, 0, s>>>(ops.ntiles * ops.ncomp, part, st);
+}
+
+void launch_vcg_true_residual(hipStream_t s, int K, const VecOps<double> &ops, const uint32_t *flags,
+                              const double *x, const double *b, double *part, CGState *st) {
+  IMSMG_DISPATCH_V(K, k_vcg_true_residual, ops, flags, x, b, part);
+  k_cg_aux_fin<<<1, kFinThreads, 0, s>>>(ops.ntiles * ops.ncomp, part, st);
+}
+#undef IMSMG_DISPATCH_V
 
 #define IMSMG_DISPATCH_K(K, KERNEL, ...)                                        \
   switch (K) {                                                                  \

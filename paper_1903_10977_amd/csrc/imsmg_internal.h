@@ -56,6 +56,28 @@ struct OpView {
   int ntx, nty, ntiles;    // lattice tiles along x, along y, in total
 };
 
+// Vector operators (linear elasticity, ncomp displacement components): the
+// ncomp x ncomp component blocks A_(c,e) of a level, each a compressed
+// lattice-ELL operator on the scalar lattice, for the tiled vector kernels
+// (vec_row.h).  Vectors hold the components as consecutive padded scalar
+// arrays: component e of lattice point L at x[e * cstride + L].
+constexpr int kMaxComp = 3;
+
+template <typename V>
+struct VecOps {
+  // block b = c * ncomp + e
+  const double *refd[kMaxComp * kMaxComp];
+  const V *val[kMaxComp * kMaxComp];
+  const int32_t *sloc[kMaxComp * kMaxComp];
+  const int32_t *tile_g0[kMaxComp * kMaxComp];
+  const uint32_t *meta[kMaxComp * kMaxComp];  // per scalar row: stored index or kMetaIndex
+  int nv[kMaxComp * kMaxComp];
+  const int32_t *lat2row;  // lattice point -> scalar row (-1: inactive)
+  int sx, sy, sz, ntx, nty, ntiles;
+  int ncomp, ns;           // components, scalar rows
+  int64_t cstride;         // component stride of the level's vectors
+};
+
 // Stored-row values: the K slots of a row in groups of 16 bytes (G = 2 FP64 or
 // 4 FP32 values), group-major over the stored rows: value (g, s) sits at
 // ((s / G) nv + g) G + s % G.  A lane reads one group of its row with one
@@ -139,6 +161,17 @@ void launch_residual_smooth(hipStream_t s, int n, int K, const OpView<float> &op
                             const uint32_t *meta, const double *c, const double *xa, const double *r, double *rh,
                             double *xb, const int32_t *done, const ProlongView *pv = nullptr);
 // general Schwarz rows: x[grow_lat[t]] += sum_k S[t,k] r[scol[k]]  (S_G in CSR, lattice columns)
+// vector levels: y = b - A x (b == nullptr: y = A x) and the smoothing step
+// (rh = r - A xa on general rows, xb = xa + c (r - A xa)), per component;
+// flags: per vector row, the general-block bit; c: per vector row
+void launch_vresidual(hipStream_t s, int K, const VecOps<double> &ops, const uint32_t *flags, const double *x,
+                      const double *b, double *y, const int32_t *done);
+void launch_vresidual(hipStream_t s, int K, const VecOps<float> &ops, const uint32_t *flags, const double *x,
+                      const double *b, double *y, const int32_t *done);
+void launch_vresidual_smooth(hipStream_t s, int K, const VecOps<double> &ops, const uint32_t *flags, const double *c,
+                             const double *xa, const double *r, double *rh, double *xb, const int32_t *done);
+void launch_vresidual_smooth(hipStream_t s, int K, const VecOps<float> &ops, const uint32_t *flags, const double *c,
+                             const double *xa, const double *r, double *rh, double *xb, const int32_t *done);
 void launch_smooth_general(hipStream_t s, int ng, const int32_t *grow_lat, const int32_t *sptr,
                            const int32_t *scol, const double *sval, const double *r, double *x, const int32_t *done,
                            int lanes = 4);  // lanes per row: 2, 4 or 8
@@ -181,6 +214,14 @@ void launch_cg_init(hipStream_t s, int n, int K, const OpView<double> &op, const
                     const uint32_t *meta, const double *x, const double *b, double *r, double *part, CGState *st,
                     double rtol, int restart);
 // r . z and beta (flexible: Polak-Ribiere form with the r_{k+1} . z_k of the last update)
+// CG on a vector finest level: init (r = b - A x, ||r||^2, ||b||^2), q = A p
+// with p.q, and ||b - A x||^2, partials over all (tile, component) workgroups
+void launch_vcg_init(hipStream_t s, int K, const VecOps<double> &ops, const uint32_t *flags, const double *x,
+                     const double *b, double *r, double *part, CGState *st, double rtol, int restart);
+void launch_vcg_spmv_pq(hipStream_t s, int K, const VecOps<double> &ops, const uint32_t *flags, const double *p,
+                        double *q, double *part, CGState *st);
+void launch_vcg_true_residual(hipStream_t s, int K, const VecOps<double> &ops, const uint32_t *flags,
+                              const double *x, const double *b, double *part, CGState *st);
 void launch_cg_dot_rz(hipStream_t s, int n, const int32_t *row_lat, const double *r, const double *z, double *part,
                       CGState *st, int flexible);
 void launch_cg_direction(hipStream_t s, int n, const int32_t *row_lat, const double *z, double *p, CGState *st);

@@ -25,6 +25,7 @@
 
 #include "imsmg_internal.h"
 #include "op_row.h"
+#include "vec_row.h"
 
 namespace imsmg {
 
@@ -166,6 +167,75 @@ void launch_residual_smooth(hipStream_t s, int n, int K, const OpView<float> &op
                             const uint32_t *meta, const double *c, const double *xa, const double *r, double *rh,
                             double *xb, const int32_t *done, const ProlongView *pv) {
   dispatch_residual_smooth<float>(s, n, K, op, row_lat, meta, c, xa, r, rh, xb, done, pv);
+}
+
+// Vector levels (vec_row.h): one workgroup per (lattice tile, output
+// component); the epilogues are the scalar ones on component c's vectors.
+template <int K, typename V>
+__global__ __launch_bounds__(kRowBlock, kTileBlocksPerCU) void k_vresidual(VecOps<V> ops,
+                                                         const uint32_t *__restrict__ flags,
+                                                         const double *__restrict__ x, const double *__restrict__ b,
+                                                         double *__restrict__ y, const int32_t *__restrict__ done) {
+  __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
+  const int c = blockIdx.y;
+  const int64_t o = c * ops.cstride;
+  vtile_rows<K, V>(xcd_block(blockIdx.x, gridDim.x), c, ops, flags, x, tile, ResidualEpi{b ? b + o : nullptr, y + o},
+                   done);
+}
+
+template <int K, typename V>
+__global__ __launch_bounds__(kRowBlock, kTileBlocksPerCU) void k_vresidual_smooth(
+    VecOps<V> ops, const uint32_t *__restrict__ flags, const double *__restrict__ cd, const double *__restrict__ xa,
+    const double *__restrict__ r, double *__restrict__ rh, double *__restrict__ xb, const int32_t *__restrict__ done) {
+  __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
+  const int c = blockIdx.y;
+  const int64_t o = c * ops.cstride;
+  vtile_rows<K, V>(xcd_block(blockIdx.x, gridDim.x), c, ops, flags, xa, tile,
+                   SmoothEpi{r + o, cd + size_t(c) * ops.ns, rh + o, xb + o}, done);
+}
+
+template <typename V>
+static void dispatch_vresidual(hipStream_t s, int K, const VecOps<V> &ops, const uint32_t *flags, const double *x,
+                               const double *b, double *y, const int32_t *done) {
+  if (ops.ns <= 0) return;
+  dim3 g(ops.ntiles, ops.ncomp), t(kRowBlock);
+  if (K == 125)
+    k_vresidual<125, V><<<g, t, 0, s>>>(ops, flags, x, b, y, done);
+  else if (K == 27)
+    k_vresidual<27, V><<<g, t, 0, s>>>(ops, flags, x, b, y, done);
+  else
+    throw std::invalid_argument("vector operators: 3D tiled stencils (K = 27 or 125)");
+}
+
+template <typename V>
+static void dispatch_vresidual_smooth(hipStream_t s, int K, const VecOps<V> &ops, const uint32_t *flags,
+                                      const double *c, const double *xa, const double *r, double *rh, double *xb,
+                                      const int32_t *done) {
+  if (ops.ns <= 0) return;
+  dim3 g(ops.ntiles, ops.ncomp), t(kRowBlock);
+  if (K == 125)
+    k_vresidual_smooth<125, V><<<g, t, 0, s>>>(ops, flags, c, xa, r, rh, xb, done);
+  else if (K == 27)
+    k_vresidual_smooth<27, V><<<g, t, 0, s>>>(ops, flags, c, xa, r, rh, xb, done);
+  else
+    throw std::invalid_argument("vector operators: 3D tiled stencils (K = 27 or 125)");
+}
+
+void launch_vresidual(hipStream_t s, int K, const VecOps<double> &ops, const uint32_t *flags, const double *x,
+                      const double *b, double *y, const int32_t *done) {
+  dispatch_vresidual<double>(s, K, ops, flags, x, b, y, done);
+}
+void launch_vresidual(hipStream_t s, int K, const VecOps<float> &ops, const uint32_t *flags, const double *x,
+                      const double *b, double *y, const int32_t *done) {
+  dispatch_vresidual<float>(s, K, ops, flags, x, b, y, done);
+}
+void launch_vresidual_smooth(hipStream_t s, int K, const VecOps<double> &ops, const uint32_t *flags, const double *c,
+                             const double *xa, const double *r, double *rh, double *xb, const int32_t *done) {
+  dispatch_vresidual_smooth<double>(s, K, ops, flags, c, xa, r, rh, xb, done);
+}
+void launch_vresidual_smooth(hipStream_t s, int K, const VecOps<float> &ops, const uint32_t *flags, const double *c,
+                             const double *xa, const double *r, double *rh, double *xb, const int32_t *done) {
+  dispatch_vresidual_smooth<float>(s, K, ops, flags, c, xa, r, rh, xb, done);
 }
 
 // General Schwarz rows: x[L_t] += sum_k S_G[t,k] r[col_k].  S_G is the sum of

@@ -240,7 +240,7 @@ std::vector<double> two_scale(int basis, int nc, int p, double lo, double hi) {
 struct Geometry {
   int kind, dim;
   std::vector<double> discs;
-  double phase[3], level;
+  double phase[3], level, plane_x = 0.0;
   // the apple with a bite (box (-2,2)^3): apple body psi_1 and bite psi_2
   static void apple_parts(const double *x, double &p1, double &p2) {
     const double r = std::sqrt(x[0] * x[0] + x[1] * x[1]);
@@ -278,6 +278,8 @@ struct Geometry {
         apple_parts(x, p1, p2);
         return std::min(p1, p2);
       }
+      case IMSMG_GEN_GEOM_SLAB:
+        return plane_x - x[0];
     }
     return 0.0;
   }
@@ -1419,6 +1421,7 @@ void build(Problem &P) {
   C.geo.discs = P.discs;
   for (int a = 0; a < 3; ++a) C.geo.phase[a] = s.phase[a];
   C.geo.level = s.gyroid_level;
+  C.geo.plane_x = s.plane_x;
   const int qc = s.q_cell > 0 ? s.q_cell : p + 1;
   const int qs = s.q_simplex > 0 ? s.q_simplex : (d == 2 ? std::max(2 * p, 1) : 3 * p + 1);
   const int qb = s.q_bnd > 0 ? s.q_bnd : (d == 2 ? 2 * p + 1 : 3 * p + 1);
@@ -1551,7 +1554,7 @@ int imsmg_gen_build(const imsmg_gen_spec *spec, imsmg_gen_problem **out) {
   const imsmg_gen_spec &s = *spec;
   if (s.dim < 2 || s.dim > 3 || s.degree < 1 || s.degree > 4 || s.n < 1 || s.levels < 1 || s.depth < 0 ||
       s.depth > 12 || (s.basis != IMSMG_GEN_BSPLINE && s.basis != IMSMG_GEN_LAGRANGE) || s.bc < 0 || s.bc > 2 ||
-      s.rhs < 0 || s.rhs > 2 || s.geometry < 0 || s.geometry > 4 || !(s.box_hi > s.box_lo) ||
+      s.rhs < 0 || s.rhs > 2 || s.geometry < 0 || s.geometry > 5 || !(s.box_hi > s.box_lo) ||
       (s.physics != IMSMG_GEN_POISSON && s.physics != IMSMG_GEN_ELASTICITY) ||
       (s.dirichlet_part != IMSMG_GEN_DIRICHLET_ALL && s.dirichlet_part != IMSMG_GEN_DIRICHLET_BITE)) {
     g_err = "invalid workload specification";
@@ -1562,7 +1565,10 @@ int imsmg_gen_build(const imsmg_gen_spec *spec, imsmg_gen_problem **out) {
     g_err = "geometry does not match the dimension";
     return -1;
   }
-  if (s.geometry == IMSMG_GEN_GEOM_APPLE && s.dim != 3) { g_err = "the apple is a 3D geometry"; return -1; }
+  if ((s.geometry == IMSMG_GEN_GEOM_APPLE || s.geometry == IMSMG_GEN_GEOM_SLAB) && s.dim != 3) {
+    g_err = "the apple and the slab are 3D geometries";
+    return -1;
+  }
   if (s.n % (1 << (s.levels - 1))) { g_err = "n must be divisible by 2^(levels-1)"; return -1; }
   if (s.physics == IMSMG_GEN_ELASTICITY) {
     if (s.dim != 3 || s.bc != IMSMG_GEN_PENALTY || s.basis != IMSMG_GEN_BSPLINE) {

@@ -59,7 +59,8 @@ class GenSpec(C.Structure):
                 ("box_hi", C.c_double), ("penalty_factor", C.c_double), ("q_cell", C.c_int32),
                 ("q_simplex", C.c_int32), ("q_bnd", C.c_int32), ("nthreads", C.c_int32),
                 ("with_mass", C.c_int32), ("physics", C.c_int32), ("dirichlet_part", C.c_int32),
-                ("lame_lambda", C.c_double), ("lame_mu", C.c_double), ("force", C.c_double * 3)]
+                ("lame_lambda", C.c_double), ("lame_mu", C.c_double), ("force", C.c_double * 3),
+                ("plane_x", C.c_double)]
 
 
 class LevelInfo(C.Structure):
@@ -72,7 +73,7 @@ class LevelInfo(C.Structure):
 _BASIS = {"bspline": 0, "lagrange": 1}
 _BC = {"box_dirichlet": 0, "penalty": 1, "neumann": 2}
 _RHS = {"one": 0, "manufactured": 1, "zero": 2, "force": 2}
-_GEOM = {"none": 0, "discs": 1, "gyroid": 2, "star": 3, "apple": 4}
+_GEOM = {"none": 0, "discs": 1, "gyroid": 2, "star": 3, "apple": 4, "slab": 5}
 _PHYSICS = {"poisson": 0, "elasticity": 1}
 _DPART = {"all": 0, "bite": 1}
 
@@ -153,6 +154,7 @@ def generate(w, with_mass: bool = False, nthreads: int = 0, orders=None) -> Gene
     f = getattr(w, "force", None) or [0.0, 0.0, 0.0]
     for a in range(3):
         spec.force[a] = f[a] if a < len(f) else 0.0
+    spec.plane_x = getattr(w, "plane_x", 0.0)
     h = C.c_void_p()
     rc = lib.imsmg_gen_build(C.byref(spec), C.byref(h))
     if rc != 0:

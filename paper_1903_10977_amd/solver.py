@@ -49,7 +49,8 @@ class Options(C.Structure):
                 ("check_every", C.c_int32), ("use_graph", C.c_int32), ("timing", C.c_int32), ("gamma", C.c_double),
                 ("compress", C.c_int32), ("use_learned", C.c_int32), ("autotune", C.c_int32),
                 ("block_gemm", C.c_int32), ("flexible_cg", C.c_int32), ("smoother", C.c_int32),
-                ("coarse_smoother", C.c_int32), ("cycle", C.c_int32), ("flag_min_rows", C.c_int32)]
+                ("coarse_smoother", C.c_int32), ("cycle", C.c_int32), ("flag_min_rows", C.c_int32),
+                ("ncomp", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -284,6 +285,8 @@ class Solver:
         w = problem.workload
         L, A, R, P, Lt, E, keep = problem_structs(problem, dim, reach, implicit_transfer)
         opt = options if options is not None else default_options(nu_pre=w.nu, nu_post=w.nu)
+        if opt.ncomp == 1:
+            opt.ncomp = getattr(problem.levels[-1], "ncomp", 1)   # vector problems: components per function
         self._check(self.lib.imsmg_setup(self.h, L, A, R, P, Lt, E, C.byref(opt)))
         self.problem = problem
         self.options = opt

@@ -118,6 +118,7 @@ class Workload:
     lame_mu: float = 1.0e3
     force: Optional[list] = None
     dirichlet_part: str = "all"
+    plane_x: float = 0.0
 
     def to_json(self) -> str:
         return json.dumps(asdict(self), sort_keys=True)
@@ -216,3 +217,18 @@ def apple(n: int = 80, levels: int = 4, nu: int = 1) -> Workload:
                     levels=levels, geometry="apple", basis="bspline", bc="penalty", rhs="force",
                     nu=nu, box_lo=-2.0, box_hi=2.0, penalty_factor=2.0, physics="elasticity",
                     lame_lambda=1.0e3, lame_mu=1.0e3, force=[0.0, 0.0, -1.0], dirichlet_part="bite")
+
+
+def slab(n: int = 8, levels: int = 2, fraction: float = 0.37) -> Workload:
+    """3D linear elasticity on the part x < x_c of the unit cube, clamped on
+    the immersed plane x = x_c by the penalty method (beta = 2/h) and loaded
+    by gravity (0, 0, -1), lambda = mu = 1e3, quadratic B-splines.  x_c lies
+    `fraction` of a fine element past a grid plane, so every cut element keeps
+    that volume fraction on every level (no near-singular cut blocks: a
+    parity case whose Schwarz blocks are all well determined)."""
+    h = 1.0 / n
+    xc = (n // 2 + fraction) * h
+    return Workload(name=f"slab-{n}", dim=3, degree=2, n=n, depth=0, levels=levels, geometry="slab",
+                    basis="bspline", bc="penalty", rhs="force", nu=1, penalty_factor=2.0,
+                    physics="elasticity", lame_lambda=1.0e3, lame_mu=1.0e3, force=[0.0, 0.0, -1.0],
+                    dirichlet_part="all", plane_x=xc)
