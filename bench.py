@@ -1,7 +1,8 @@
 """Benchmark: multigrid-preconditioned CG on the 3D immersed Poisson problem
 (quadratic B-splines, 128^3 gyroid, 1.48M DOFs, 4-level V(1,1)) on one MI355X,
-with the 2D 1024^2 cubic 200-disc problem (6-level V(2,2)), several
-right-hand sides and the 64-problem batch beside it.
+with the 2D 1024^2 cubic 200-disc problem (6-level V(2,2)), 3D linear
+elasticity on the 80^3 apple with a bite (667k DOFs), several right-hand sides
+and the 64-problem batch beside it.
 
 Metric (both parts are reported for every form):
 * V-cycle MDOF/s = fine DOFs / median time of one V-cycle (imsmg_vcycle as
@@ -111,6 +112,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the mixed+learned form")
     ap.add_argument("--no-second", action="store_true", help="skip the second workload (c2 beside c3)")
+    ap.add_argument("--no-elasticity", action="store_true", help="skip the 3D elasticity workload (apple 80^3)")
+    ap.add_argument("--elasticity-n", type=int, default=80, help="elements per axis of the elasticity workload")
     ap.add_argument("--nrhs", type=int, default=16, help="columns of the multi-right-hand-side form (1: skip)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-problem form")
     ap.add_argument("--forms", default="", help="comma list to restrict the timed forms")
@@ -268,6 +271,22 @@ def main():
     else:
         mw = mg = None
 
+    # ------------------------------------ linear elasticity (vector problem)
+    elastic = None
+    if not args.no_elasticity and (want is None or "elasticity" in want):
+        we = W.apple(n=args.elasticity_n, levels=4)
+        t0 = time.time()
+        ge = GN.generate(we)
+        log(f"generated {we.name}: fine DOFs {ge.fine.n} (3 components), nnz {ge.fine.A.nnz}, "
+            f"{time.time() - t0:.1f} s")
+        forms_e = {"fp64": (S.FP64, "as", None, None), "mixed": (S.MIXED, "as", None, None)}
+        elastic = {"workload": (f"3D linear elasticity, quadratic B-splines, {we.n}^3 apple with a bite in "
+                                f"(-2,2)^3, lambda = mu = 1e3, gravity, penalty Dirichlet (2/h) on the bite, "
+                                f"{we.levels}-level V(1,1), additive Schwarz with per-component blocks"),
+                   "fine_dofs": ge.fine.n, "generate_s": round(time.time() - t0, 1),
+                   "forms": run_forms(we, ge, forms_e, min(args.steps, 3), min(args.warmup, 1))}
+        del ge
+
     # several right-hand sides with the C2 matrix: the 16-column form
     multi = None
     if args.nrhs > 1 and mg is not None:
@@ -326,7 +345,7 @@ def main():
                    "pcg_time_s": round(hf["pcg_ms"] / 1e3, 5), "forms": head,
                    "speedup_mixed_vs_fp64_pcg": (round(hf["pcg_ms"] / head["mixed"]["pcg_ms"], 3)
                                                  if "mixed" in head else None),
-                   "second_workload": second, "multi_rhs": multi, "batched": batched},
+                   "second_workload": second, "elasticity": elastic, "multi_rhs": multi, "batched": batched},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_residual_smooth (finest level, FP64)", "bytes_per_launch": int(bytes_launch),
