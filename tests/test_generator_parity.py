@@ -71,13 +71,14 @@ def test_generator_rejects_bad_spec():
         GN.generate(w)
 
 
-def test_generator_elasticity_matches_oracle():
-    """Linear elasticity on the apple with a bite (8^3, two levels): vector
-    operators (component-major) on the structural pattern of every component
-    pair, load, vector mass, R = I (x) R_scalar and the per-component blocks
-    against the oracle's independent assembly (1e-12 per row)."""
+@pytest.mark.parametrize("w", [W.apple(n=8, levels=2), W.slab(n=8, levels=2)], ids=lambda w: w.name)
+def test_generator_elasticity_matches_oracle(w):
+    """Linear elasticity on the apple with a bite and on the clamped slab (8^3,
+    two levels): vector operators (component-major) on the structural pattern
+    of every component pair, load, vector mass, R = I (x) R_scalar and the
+    per-component blocks against the oracle's independent assembly (1e-12 per
+    row)."""
     from oracle import elasticity as E
-    w = W.apple(n=8, levels=2)
     g = GN.generate(w, with_mass=True)
     op = E.build(w, smoothers=False)
     assert g.fine.ncomp == 3
