@@ -247,6 +247,27 @@ class VectorSmoother(SW.Smoother):
         return 1.0 / max_NK_vector(lev, blocks, self._vec[1])
 
 
+class VectorMultiplicativeSmoother(SW.MultiplicativeSmoother):
+    """Multiplicative Schwarz (eq:multiplicativeSchwarz1) with per-component
+    blocks.  Blocks of different components that share an element are coupled
+    by A, so they need different colours: the block of component c associated
+    with scalar function a takes c (p+1)^d + the scalar lattice colour of a
+    (d (p+1)^d colours for uncut B-splines, three times the scalar count);
+    added singletons are coloured greedily from d (p+1)^d."""
+
+    def __init__(self, A, lev, d):
+        blocks, vassoc = vector_blocks(lev, d)
+        self._vec = (lev, d)
+        SW.Smoother.__init__(self, A, lev, blocks=blocks)
+        N = len(lev.active)
+        q = (lev.p + 1) ** lev.dim
+        given = [(a // N) * q + SW.lattice_colour(lev, lev.active[a % N]) for a in vassoc]
+        self._order_blocks(A, lev, vassoc, given, lambda b: b % N, d * q)
+
+    def _gamma(self, lev, blocks):
+        return 1.0 / max_NK_vector(lev, blocks, self._vec[1])
+
+
 @dataclass
 class ElasticityProblem:
     w: object
@@ -277,6 +298,9 @@ def build(w, orders=None, smoothers=True) -> ElasticityProblem:
     vc = None
     if smoothers:
         for l in range(1, w.levels):
-            sm[l] = VectorSmoother(hier.A[l], hier.levels[l], sysf.ncomp)
+            if w.smoother == "ms":
+                sm[l] = VectorMultiplicativeSmoother(hier.A[l], hier.levels[l], sysf.ncomp)
+            else:
+                sm[l] = VectorSmoother(hier.A[l], hier.levels[l], sysf.ncomp)
         vc = MG.VCycle(hier.A, hier.R, sm, nu_pre=w.nu, nu_post=w.nu, cycle=w.cycle)
     return ElasticityProblem(w=w, leaf=leaf, system=sysf, hier=hier, smoothers=sm, vcycle=vc)

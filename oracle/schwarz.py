@@ -187,13 +187,14 @@ def lattice_colour(lev, L, kind="schwarz"):
     return c
 
 
-def colour_blocks(lev, blocks, given):
+def colour_blocks(lev, blocks, given, base=None):
     """Colours of the final blocks: given[j] (an int) where known, else the
-    smallest colour >= the number of lattice colours that no block already
-    coloured (in block order) uses on a shared element.  Raises if two
-    same-colour given blocks share an element."""
+    smallest colour >= base (default: the number of lattice colours) that no
+    block already coloured (in block order) uses on a shared element.  Raises
+    if two same-colour given blocks share an element."""
     els = block_elements(lev, blocks)
-    base = (lev.p + 1) ** lev.dim   # above every lattice colour (2^d <= (p+1)^d)
+    if base is None:
+        base = (lev.p + 1) ** lev.dim   # above every lattice colour (2^d <= (p+1)^d)
     used = {}
     colours = []
     for j, es in enumerate(els):
@@ -235,11 +236,17 @@ class MultiplicativeSmoother(Smoother):
         else:
             blocks, assoc = select_blocks(lev)
         super().__init__(A, lev, blocks=blocks)
+        given = [lattice_colour(lev, lev.active[a], kind) for a in assoc]
+        self._order_blocks(A, lev, assoc, given, lambda b: b, None)
+
+    def _order_blocks(self, A, lev, assoc, given, to_scalar, base):
+        """Colours (given ones for the input blocks, greedy from base for the
+        singletons the factorization added; the element sets come from the
+        blocks mapped by to_scalar), the sweep order and each block's reach."""
         self.assoc = assoc
         self.A = A
-        given = [lattice_colour(lev, lev.active[a], kind) for a in assoc]
-        given += [None] * (len(self.blocks) - len(given))   # singletons added for uncovered DOFs
-        self.colours = colour_blocks(lev, self.blocks, given)
+        given = list(given) + [None] * (len(self.blocks) - len(given))   # singletons added for uncovered DOFs
+        self.colours = colour_blocks(lev, [to_scalar(np.asarray(b)) for b in self.blocks], given, base)
         self.order = sorted(range(len(self.blocks)), key=lambda j: (self.colours[j], j))
         # per block: the rows its update reaches (A[:, k] non-zero) and A[rows, k]
         Ac = A.tocsc()
