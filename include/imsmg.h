@@ -176,10 +176,10 @@ typedef struct {
                           component pair; R_l is block diagonal with one equal block per
                           component; every Schwarz block holds DOFs of one component (the
                           smoothers subsection's separate blocks per component); elements list
-                          the DOFs of every component.  Supported: additive Schwarz, V- or
-                          W-cycles, FP64 or FP32 level operators, single right-hand side;
-                          rejected (IMSMG_ERR_INVALID_ARG): the multiplicative smoother, learned
-                          weights, block_gemm, the multi-column and batched calls, 2D lattices */
+                          the DOFs of every component.  Supported: additive and multiplicative
+                          Schwarz, V- or W-cycles, FP64 or FP32 level operators, single
+                          right-hand side; rejected (IMSMG_ERR_INVALID_ARG): learned weights,
+                          block_gemm, the multi-column and batched calls, 2D lattices */
 } imsmg_options;
 
 enum { IMSMG_ADDITIVE = 0, IMSMG_MULTIPLICATIVE = 1 };

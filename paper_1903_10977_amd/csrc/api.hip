@@ -69,6 +69,7 @@ struct Level {
   int32_t *srow_lat = nullptr;
   VecOps<double> vops64{};
   VecOps<float> vops32{};
+  std::vector<std::vector<uint32_t>> h_bmeta;  // per component block: stored index or kMetaIndex per scalar row
   double *dense0 = nullptr;  // coarsest vector level: the dense operator (setup)
   int K = 0, dim = 2, reach = 0, center = 0;
   int shape[3] = {1, 1, 1};
@@ -566,6 +567,7 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
     L.vops64 = VecOps<double>{};
     L.vops32 = VecOps<float>{};
     L.n_uniform = 0;
+    L.h_bmeta.assign(nb, {});
     for (int b = 0; b < nb; ++b) {
       Compressed cp;
       compress_operator(c, L, ns, slat, ell[b], &full[b], cp);
@@ -582,6 +584,7 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
       L.vops64.sloc[b] = L.vops32.sloc[b] = cp.op64.sloc;
       L.vops64.tile_g0[b] = L.vops32.tile_g0[b] = cp.op64.tile_g0;
       L.vops64.meta[b] = L.vops32.meta[b] = cp.meta;
+      L.h_bmeta[b] = std::move(cp.h_meta);
     }
     if (L.op64.ntiles == 0) bad("vector operators need a tiled 3D stencil (reach 1 or 2)");
     auto fill_geom = [&](auto &v) {
@@ -946,7 +949,14 @@ void ms_sweep(imsmg_ctx *c, Level &L, bool forward, const int32_t *done) {
     const int cc = forward ? k : L.ncolours - 1 - k;
     const int a = L.ms_cptr[cc], m = L.ms_cptr[cc + 1] - a;
     if (m == 0) continue;
-    if (mixed(c))
+    if (L.ncomp > 1) {
+      if (mixed(c))
+        launch_vms_colour(c->stream, m, L.ms_rows + a, L.ms_cf + a, L.ms_vidx + size_t(a) * L.ncomp, L.ms_val32,
+                          L.K, L.vops32, L.row_lat, L.r, L.x, L.rh, done);
+      else
+        launch_vms_colour(c->stream, m, L.ms_rows + a, L.ms_cf + a, L.ms_vidx + size_t(a) * L.ncomp, L.ms_val64,
+                          L.K, L.vops64, L.row_lat, L.r, L.x, L.rh, done);
+    } else if (mixed(c))
       launch_ms_colour(c->stream, m, L.ms_rows + a, L.ms_cf + a, L.ms_vidx + a, L.ms_val32, L.K, L.op32, L.row_lat,
                        L.r, L.x, L.rh, done);
     else
@@ -1167,27 +1177,48 @@ void build_ms(imsmg_ctx *c, Level &L, const std::vector<int32_t> &fptr, const st
     h2d(s, L.ms_cf, all_cf.data(), all_cf.size());
   }
   // colour-ordered copy of the stored rows' values: one entry per list entry
-  // whose row keeps its own values
-  std::vector<int32_t> vidx(all_rows.size(), -1), vg;
+  // (vector levels: per list entry and component block) whose row keeps its
+  // own values; entries grouped by block, each group packed from its block
+  const int nc = L.ncomp, nb = nc * nc;
+  std::vector<int32_t> vidx(all_rows.size() * nc, -1);
+  std::vector<std::vector<int32_t>> vg(nb), vpos(nb);
   for (size_t t = 0; t < all_rows.size(); ++t) {
-    const uint32_t g = L.h_meta[all_rows[t]] & kMetaIndex;
-    if (g != kMetaIndex) {
-      vidx[t] = int32_t(vg.size());
-      vg.push_back(int32_t(g));
+    const int i = all_rows[t];
+    const int ci = i / L.ns, is = i % L.ns;
+    for (int e = 0; e < nc; ++e) {
+      const int b = ci * nc + e;
+      const uint32_t g = (nc == 1 ? L.h_meta[i] : L.h_bmeta[b][is]) & kMetaIndex;
+      if (g != kMetaIndex) {
+        vpos[b].push_back(int32_t(t * nc + e));
+        vg[b].push_back(int32_t(g));
+      }
     }
+  }
+  int ne = 0;
+  for (int b = 0; b < nb; ++b) {
+    for (size_t k = 0; k < vpos[b].size(); ++k) vidx[vpos[b][k]] = ne + int32_t(k);
+    ne += int(vg[b].size());
   }
   L.ms_vidx = dalloc<int32_t>(c->factor_owned, std::max<size_t>(vidx.size(), 1));
   if (!vidx.empty()) h2d(s, L.ms_vidx, vidx.data(), vidx.size());
   {
-    const int ne = int(vg.size());
-    int32_t *d_g = dalloc<int32_t>(c->factor_owned, std::max(ne, 1));
-    if (ne) h2d(s, d_g, vg.data(), vg.size());
     const int KP64 = (L.K + 1) / 2 * 2, KP32 = (L.K + 3) / 4 * 4;
     L.ms_val64 = dalloc<double>(c->factor_owned, std::max<size_t>(size_t(ne) * KP64, 2));
-    launch_ms_pack(s, ne, L.K, KP64, d_g, L.op64.val, L.op64.nv, L.ms_val64);
-    if (mixed(c)) {
-      L.ms_val32 = dalloc<float>(c->factor_owned, std::max<size_t>(size_t(ne) * KP32, 4));
-      launch_ms_pack(s, ne, L.K, KP32, d_g, L.op32.val, L.op32.nv, L.ms_val32);
+    if (mixed(c)) L.ms_val32 = dalloc<float>(c->factor_owned, std::max<size_t>(size_t(ne) * KP32, 4));
+    int e0 = 0;
+    for (int b = 0; b < nb; ++b) {
+      const int nbe = int(vg[b].size());
+      if (nbe == 0) continue;
+      int32_t *d_g = dalloc<int32_t>(c->factor_owned, nbe);
+      h2d(s, d_g, vg[b].data(), vg[b].size());
+      const double *v64 = nc == 1 ? L.op64.val : L.vops64.val[b];
+      const int nv = nc == 1 ? L.op64.nv : L.vops64.nv[b];
+      launch_ms_pack(s, nbe, L.K, KP64, d_g, v64, nv, L.ms_val64 + size_t(e0) * KP64);
+      if (mixed(c)) {
+        const float *v32 = nc == 1 ? L.op32.val : L.vops32.val[b];
+        launch_ms_pack(s, nbe, L.K, KP32, d_g, v32, nv, L.ms_val32 + size_t(e0) * KP32);
+      }
+      e0 += nbe;
     }
     HIP_CHECK_RET(hipGetLastError());
   }
@@ -2371,7 +2402,6 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
     if (c->opt.ncomp != 1 && c->opt.ncomp != kMaxComp) bad("ncomp must be 1 or 3");
     if (c->opt.ncomp > 1) {
       if (Lt[nlevels - 1].dim != 3) bad("vector problems (ncomp 3) need a 3D lattice");
-      if (uses_ms(c->opt, nlevels)) bad("vector problems: the multiplicative smoother is not supported");
       if (c->opt.use_learned) bad("vector problems: learned weights are not supported");
       if (c->opt.block_gemm) bad("vector problems: block_gemm is not supported");
     }

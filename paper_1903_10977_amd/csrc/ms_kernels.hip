@@ -89,6 +89,98 @@ __global__ __launch_bounds__(kMsBlock) void k_ms_colour(int m, const int32_t *__
   }
 }
 
+// Vector levels: row i of component c = i / ns sums its ncomp block rows
+// A_(c,e) x_e, block by block (e = 0, 1, ..), each from the block's
+// reference stencil (vidx[t ncomp + e] < 0) or from its entry of the
+// colour-ordered copy; then the same update as the scalar kernel.
+template <int K, typename V, int LANES>
+__global__ __launch_bounds__(kMsBlock) void k_vms_colour(int m, const int32_t *__restrict__ rows,
+                                                         const double *__restrict__ cf,
+                                                         const int32_t *__restrict__ vidx,
+                                                         const V *__restrict__ vals, VecOps<V> ops,
+                                                         const int32_t *__restrict__ row_lat,
+                                                         const double *__restrict__ r, double *x,
+                                                         double *__restrict__ rh, const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  constexpr int G = SlotGroup<V>::G;
+  constexpr int NG = (K + G - 1) / G;
+  constexpr int W = StencilShape<K>::W, P = StencilShape<K>::P;
+  const int tid = blockIdx.x * kMsBlock + threadIdx.x;
+  const int t = tid / LANES, lane = tid % LANES;
+  const bool ok = t < m;
+  double part = 0.0;
+  int L = 0;
+  auto off = [&](int s) {
+    const int dx = s % W - P, dy = (s / W) % W - P, dz = s / (W * W) - P;
+    return dx + ops.sx * (dy + ops.sy * dz);
+  };
+  if (ok) {
+    const int i = rows[t];
+    const int c = i / ops.ns;
+    L = row_lat[i];
+    const int64_t Ls = L - c * ops.cstride;
+    for (int e = 0; e < ops.ncomp; ++e) {
+      const double *xe = x + (e * ops.cstride + Ls);
+      const int ve = vidx[size_t(t) * ops.ncomp + e];
+      if (ve < 0) {
+        const double *__restrict__ ref = ops.refd[c * ops.ncomp + e];
+        for (int s = lane; s < K; s += LANES) part += ref[s] * xe[off(s)];
+      } else {
+        const V *__restrict__ rowv = vals + size_t(ve) * (NG * G);
+        for (int q = lane; q < NG; q += LANES) {
+          if constexpr (G == 2) {
+            const double2 v = reinterpret_cast<const double2 *>(rowv)[q];
+            part += v.x * xe[off(2 * q)];
+            if (2 * q + 1 < K) part += v.y * xe[off(2 * q + 1)];
+          } else {
+            const float4 v = reinterpret_cast<const float4 *>(rowv)[q];
+            part += double(v.x) * xe[off(4 * q)];
+            if (4 * q + 1 < K) part += double(v.y) * xe[off(4 * q + 1)];
+            if (4 * q + 2 < K) part += double(v.z) * xe[off(4 * q + 2)];
+            if (4 * q + 3 < K) part += double(v.w) * xe[off(4 * q + 3)];
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int o = LANES / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, LANES);
+  if (ok && lane == 0) {
+    const double res = r[L] - part;
+    const double cc = cf[t];
+    if (cc != 0.0)
+      x[L] += cc * res;
+    else
+      rh[L] = res;
+  }
+}
+
+template <typename V>
+static void dispatch_vms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
+                                const V *vals, int K, const VecOps<V> &ops, const int32_t *row_lat,
+                                const double *r, double *x, double *rh, const int32_t *done) {
+  if (m <= 0) return;
+  constexpr int LN = 8;
+  dim3 g((size_t(m) * LN + kMsBlock - 1) / kMsBlock), t(kMsBlock);
+  if (K == 125)
+    k_vms_colour<125, V, LN><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, ops, row_lat, r, x, rh, done);
+  else if (K == 27)
+    k_vms_colour<27, V, LN><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, ops, row_lat, r, x, rh, done);
+  else
+    throw std::invalid_argument("vector multiplicative smoother: 3D stencils of 27 or 125 slots");
+}
+
+void launch_vms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
+                       const double *vals, int K, const VecOps<double> &ops, const int32_t *row_lat, const double *r,
+                       double *x, double *rh, const int32_t *done) {
+  dispatch_vms_colour<double>(s, m, rows, cf, vidx, vals, K, ops, row_lat, r, x, rh, done);
+}
+void launch_vms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
+                       const float *vals, int K, const VecOps<float> &ops, const int32_t *row_lat, const double *r,
+                       double *x, double *rh, const int32_t *done) {
+  dispatch_vms_colour<float>(s, m, rows, cf, vidx, vals, K, ops, row_lat, r, x, rh, done);
+}
+
 template <typename V>
 static void dispatch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
                                const V *vals, int K, const OpView<V> &op, const int32_t *row_lat, const double *r,

@@ -218,7 +218,8 @@ def generate(w, with_mass: bool = False, nthreads: int = 0, orders=None) -> Gene
             eid = np.zeros(info.n_active_elements, dtype=np.int32)
             assert lib.imsmg_gen_get_elements(h, l, _ptr(ep), _ptr(ei), _ptr(eid)) == 0
             if nc > 1:
-                bp, bi, ba, bc, ep, ei = _vector_level_arrays(n, nc, bp, bi, ba, bc, ep, ei)
+                bp, bi, ba, bc, ep, ei = _vector_level_arrays(n, nc, bp, bi, ba, bc, ep, ei,
+                                                              (w.degree + 1) ** w.dim)
             levels.append(GenLevel(n_elements=info.n_elements, lattice=tuple(info.lattice[:w.dim]),
                                    dof_to_lattice=d2l, A=A, R=R, block_ptr=bp, block_idx=bi,
                                    block_assoc=ba, n_cut=info.n_cut, eta_min=info.eta_min, eta=eta,
@@ -247,19 +248,19 @@ def generate(w, with_mass: bool = False, nthreads: int = 0, orders=None) -> Gene
     return GeneratedProblem(workload=w, levels=levels, b=b, M=M, seconds=secs)
 
 
-def _vector_level_arrays(n, nc, bp, bi, ba, bc, ep, ei):
+def _vector_level_arrays(n, nc, bp, bi, ba, bc, ep, ei, ncol):
     """Per-component copies of a level's scalar arrays (vector DOF c n + i):
     blocks repeated per component (smoothers subsection: separate blocks for
-    the functions of each component), colours offset by the scalar colour
-    count per component (blocks of different components that share an element
-    are coupled by A), element incidence listing every component."""
+    the functions of each component), colours offset by ncol = (p+1)^d, the
+    scalar lattice colour count, per component (blocks of different
+    components that share an element are coupled by A), element incidence
+    listing every component."""
     if bp is not None:
         nb, nnzb = len(bp) - 1, int(bp[-1])
         bp = np.concatenate([bp[:-1] + c * nnzb for c in range(nc)] + [np.array([nc * nnzb])]).astype(np.int32)
         bi = np.concatenate([bi + c * n for c in range(nc)]).astype(np.int32)
         ba = np.concatenate([ba + c * n for c in range(nc)]).astype(np.int32)
         if bc is not None:
-            ncol = int(bc.max()) + 1 if len(bc) else 0
             bc = np.concatenate([bc + c * ncol for c in range(nc)]).astype(np.int32)
     cnt = np.diff(ep)
     ei2 = np.concatenate([np.concatenate([ei[ep[k]:ep[k + 1]] + c * n for c in range(nc)])
