@@ -114,6 +114,7 @@ def main():
     ap.add_argument("--no-second", action="store_true", help="skip the second workload (c2 beside c3)")
     ap.add_argument("--no-elasticity", action="store_true", help="skip the 3D elasticity workload (apple 80^3)")
     ap.add_argument("--elasticity-n", type=int, default=80, help="elements per axis of the elasticity workload")
+    ap.add_argument("--elasticity-forms", default="", help="comma list to restrict the elasticity forms")
     ap.add_argument("--nrhs", type=int, default=16, help="columns of the multi-right-hand-side form (1: skip)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-problem form")
     ap.add_argument("--forms", default="", help="comma list to restrict the timed forms")
@@ -279,10 +280,16 @@ def main():
         ge = GN.generate(we)
         log(f"generated {we.name}: fine DOFs {ge.fine.n} (3 components), nnz {ge.fine.A.nnz}, "
             f"{time.time() - t0:.1f} s")
-        forms_e = {"fp64": (S.FP64, "as", None, None), "mixed": (S.MIXED, "as", None, None)}
+        # FP32 operators with the multiplicative smoother do not reach 1e-8 here: the colour
+        # residuals feed cut blocks whose inverses amplify FP32 rounding by up to 1e16
+        forms_e = {"fp64": (S.FP64, "as", None, None), "mixed": (S.MIXED, "as", None, None),
+                   "ms-fp64": (S.FP64, "ms", None, None), "ms+jacobi-fp64": (S.FP64, "ms", None, "jacobi")}
+        if args.elasticity_forms:
+            forms_e = {k: v for k, v in forms_e.items() if k in args.elasticity_forms.split(",")}
         elastic = {"workload": (f"3D linear elasticity, quadratic B-splines, {we.n}^3 apple with a bite in "
                                 f"(-2,2)^3, lambda = mu = 1e3, gravity, penalty Dirichlet (2/h) on the bite, "
-                                f"{we.levels}-level V(1,1), additive Schwarz with per-component blocks"),
+                                f"{we.levels}-level V(1,1), additive or multiplicative Schwarz with "
+                                f"per-component blocks"),
                    "fine_dofs": ge.fine.n, "generate_s": round(time.time() - t0, 1),
                    "forms": run_forms(we, ge, forms_e, min(args.steps, 3), min(args.warmup, 1))}
         del ge

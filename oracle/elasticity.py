@@ -298,9 +298,17 @@ def build(w, orders=None, smoothers=True) -> ElasticityProblem:
     vc = None
     if smoothers:
         for l in range(1, w.levels):
-            if w.smoother == "ms":
-                sm[l] = VectorMultiplicativeSmoother(hier.A[l], hier.levels[l], sysf.ncomp)
+            A, lev = hier.A[l], hier.levels[l]
+            kind = w.smoother if (l == w.levels - 1 or w.coarse_smoother == "same") else w.coarse_smoother
+            if kind == "ms":
+                sm[l] = VectorMultiplicativeSmoother(A, lev, sysf.ncomp)
+            elif kind == "jacobi":
+                # diagonal smoothing on the coarser levels (Remark rem:coarseGS),
+                # damped by the additive rule with one block per DOF
+                sm[l] = VectorSmoother(A, lev, sysf.ncomp, blocks=[np.array([i]) for i in range(A.shape[0])])
+            elif kind == "as":
+                sm[l] = VectorSmoother(A, lev, sysf.ncomp)
             else:
-                sm[l] = VectorSmoother(hier.A[l], hier.levels[l], sysf.ncomp)
+                raise ValueError(f"vector problems: smoother {kind}")
         vc = MG.VCycle(hier.A, hier.R, sm, nu_pre=w.nu, nu_post=w.nu, cycle=w.cycle)
     return ElasticityProblem(w=w, leaf=leaf, system=sysf, hier=hier, smoothers=sm, vcycle=vc)

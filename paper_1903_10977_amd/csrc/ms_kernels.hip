@@ -160,7 +160,9 @@ static void dispatch_vms_colour(hipStream_t s, int m, const int32_t *rows, const
                                 const V *vals, int K, const VecOps<V> &ops, const int32_t *row_lat,
                                 const double *r, double *x, double *rh, const int32_t *done) {
   if (m <= 0) return;
-  constexpr int LN = 8;
+  // a vector row is ncomp block rows: 32 lanes per row keep each lane's chain
+  // of dependent gathers as short as the scalar kernel's (8 lanes, one block)
+  constexpr int LN = 32;
   dim3 g((size_t(m) * LN + kMsBlock - 1) / kMsBlock), t(kMsBlock);
   if (K == 125)
     k_vms_colour<125, V, LN><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, ops, row_lat, r, x, rh, done);

@@ -281,9 +281,13 @@ def with_coarse_diagonal(problem, kind: str = "jacobi"):
     for l in range(1, len(levels) - 1):
         lev = levels[l]
         n = lev.n
-        col = np.zeros(n, dtype=np.int32)
+        ns = len(lev.dof_to_lattice)
+        scol = np.zeros(ns, dtype=np.int32)
         d2l = np.ascontiguousarray(lev.dof_to_lattice, dtype=np.int32)
-        assert lib.imsmg_gen_lattice_colours(n, _ptr(d2l), lev.lattice[0], w.dim, w.degree + 1, 1, _ptr(col)) == 0
+        assert lib.imsmg_gen_lattice_colours(ns, _ptr(d2l), lev.lattice[0], w.dim, w.degree + 1, 1, _ptr(scol)) == 0
+        # vector levels: component c's functions after the scalar colours of components < c
+        q = (w.degree + 1) ** w.dim
+        col = np.concatenate([scol + c * q for c in range(lev.ncomp)]).astype(np.int32)
         levels[l] = dataclasses.replace(lev, block_ptr=np.arange(n + 1, dtype=np.int32),
                                         block_idx=np.arange(n, dtype=np.int32),
                                         block_assoc=np.arange(n, dtype=np.int32), block_colour=col)
