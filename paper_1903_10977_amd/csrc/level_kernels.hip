@@ -375,7 +375,9 @@ struct Band {
   int W;
 };
 
-template <int DIM>
+// DIM = 3, WB > 0: every band has at most WB entries (WB = the band width,
+// 2 .. 4 in practice), the row's loads unrolled slice by slice
+template <int DIM, int WB = 0>
 __global__ __launch_bounds__(kRowBlock) void k_tensor_transfer(int n, const int32_t *__restrict__ row_lat,
                                                                int ox, int oy, Band band, int ix_, int iy_,
                                                                const double *__restrict__ xin,
@@ -425,6 +427,40 @@ __global__ __launch_bounds__(kRowBlock) void k_tensor_transfer(int n, const int3
       for (int a = 0; a < nx; ++a) t += cx[a] * row[a];
       acc += cy[b] * t;
     }
+  } else if (DIM == 3 && WB > 0) {
+    // fixed trip counts with guards: per z slice, every input load of the
+    // slice issues before the first wait (the loop form chains up to
+    // (p+2)^3 dependent loads per row)
+    constexpr int B = WB > 0 ? WB : 1;
+    const int sz = band.start[mz], nz = band.len[mz];
+    const double *cz = band.coef + size_t(mz) * band.W;
+    double cxv[B], cyv[B], czv[B];
+#pragma unroll
+    for (int a = 0; a < B; ++a) {
+      cxv[a] = a < nx ? cx[a] : 0.0;
+      cyv[a] = a < ny ? cy[a] : 0.0;
+      czv[a] = a < nz ? cz[a] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      double in[B][B];
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+#pragma unroll
+        for (int a = 0; a < B; ++a) {
+          in[b][a] = 0.0;
+          if (a < nx && b < ny && c < nz) in[b][a] = xin[(size_t(sz + c) * iy_ + (sy + b)) * ix_ + sx + a];
+        }
+      double tz = 0.0;
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        double t = 0.0;
+#pragma unroll
+        for (int a = 0; a < B; ++a) t += cxv[a] * in[b][a];
+        tz += cyv[b] * t;
+      }
+      acc += czv[c] * tz;
+    }
   } else {
     const int sz = band.start[mz], nz = band.len[mz];
     const double *cz = band.coef + size_t(mz) * band.W;
@@ -453,6 +489,15 @@ void launch_tensor_transfer(hipStream_t s, int dim, int n, const int32_t *row_la
   if (dim == 2)
     k_tensor_transfer<2><<<grid_for(n), kRowBlock, 0, s>>>(n, row_lat, ox, oy, b, ix, iy, xin, y, accumulate, cinit,
                                                            xinit, done);
+  else if (W == 2)
+    k_tensor_transfer<3, 2><<<grid_for(n), kRowBlock, 0, s>>>(n, row_lat, ox, oy, b, ix, iy, xin, y, accumulate,
+                                                              cinit, xinit, done);
+  else if (W == 3)
+    k_tensor_transfer<3, 3><<<grid_for(n), kRowBlock, 0, s>>>(n, row_lat, ox, oy, b, ix, iy, xin, y, accumulate,
+                                                              cinit, xinit, done);
+  else if (W == 4)
+    k_tensor_transfer<3, 4><<<grid_for(n), kRowBlock, 0, s>>>(n, row_lat, ox, oy, b, ix, iy, xin, y, accumulate,
+                                                              cinit, xinit, done);
   else
     k_tensor_transfer<3><<<grid_for(n), kRowBlock, 0, s>>>(n, row_lat, ox, oy, b, ix, iy, xin, y, accumulate, cinit,
                                                            xinit, done);
