@@ -56,6 +56,20 @@ struct OpView {
   int ntx, nty, ntiles;    // lattice tiles along x, along y, in total
 };
 
+// Streamed operator values (read once per launch, far more than the caches
+// hold): 16-byte loads with the non-temporal hint, so that they do not evict
+// the x windows that neighbouring tiles share in L2.
+typedef double nt_double2 __attribute__((ext_vector_type(2)));
+typedef float nt_float4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ double2 stream_load(const double2 *p) {
+  const nt_double2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_double2 *>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float4 stream_load(const float4 *p) {
+  const nt_float4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_float4 *>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // Vector operators (linear elasticity, ncomp displacement components): the
 // ncomp x ncomp component blocks A_(c,e) of a level, each a compressed
 // lattice-ELL operator on the scalar lattice, for the tiled vector kernels

@@ -258,6 +258,8 @@ __global__ __launch_bounds__(kRowBlock) void k_smooth_general(int ng, const int3
   if (t >= ng) return;  // all lanes of a row leave together
   const int k0 = sptr[t], k1 = sptr[t + 1];
   const int L = grow_lat[t];
+  // the row's own x, fetched with the row bounds (only this row writes it)
+  const double x0 = sub == 0 ? x[L] : 0.0;
   double acc = 0.0;
   // chunks of 4 entries per lane with guarded, fixed trip counts: the index,
   // value and r loads of a chunk issue together
@@ -278,7 +280,7 @@ __global__ __launch_bounds__(kRowBlock) void k_smooth_general(int ng, const int3
   }
 #pragma unroll
   for (int o = 1; o < LANES; o <<= 1) acc += __shfl_xor(acc, o, LANES);
-  if (sub == 0) x[L] += acc;
+  if (sub == 0) x[L] = x0 + acc;
 }
 
 void launch_smooth_general(hipStream_t s, int ng, const int32_t *grow_lat, const int32_t *sptr,

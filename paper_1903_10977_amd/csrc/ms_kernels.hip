@@ -64,11 +64,11 @@ __global__ __launch_bounds__(kMsBlock) void k_ms_colour(int m, const int32_t *__
       const V *__restrict__ rowv = vals + size_t(e) * (NG * G);
       for (int q = lane; q < NG; q += LANES) {
         if constexpr (G == 2) {
-          const double2 v = reinterpret_cast<const double2 *>(rowv)[q];
+          const double2 v = stream_load(reinterpret_cast<const double2 *>(rowv) + q);
           part += v.x * x[L + off(2 * q)];
           if (2 * q + 1 < K) part += v.y * x[L + off(2 * q + 1)];
         } else {
-          const float4 v = reinterpret_cast<const float4 *>(rowv)[q];
+          const float4 v = stream_load(reinterpret_cast<const float4 *>(rowv) + q);
           part += double(v.x) * x[L + off(4 * q)];
           if (4 * q + 1 < K) part += double(v.y) * x[L + off(4 * q + 1)];
           if (4 * q + 2 < K) part += double(v.z) * x[L + off(4 * q + 2)];
@@ -129,11 +129,11 @@ __global__ __launch_bounds__(kMsBlock) void k_vms_colour(int m, const int32_t *_
         const V *__restrict__ rowv = vals + size_t(ve) * (NG * G);
         for (int q = lane; q < NG; q += LANES) {
           if constexpr (G == 2) {
-            const double2 v = reinterpret_cast<const double2 *>(rowv)[q];
+            const double2 v = stream_load(reinterpret_cast<const double2 *>(rowv) + q);
             part += v.x * xe[off(2 * q)];
             if (2 * q + 1 < K) part += v.y * xe[off(2 * q + 1)];
           } else {
-            const float4 v = reinterpret_cast<const float4 *>(rowv)[q];
+            const float4 v = stream_load(reinterpret_cast<const float4 *>(rowv) + q);
             part += double(v.x) * xe[off(4 * q)];
             if (4 * q + 1 < K) part += double(v.y) * xe[off(4 * q + 1)];
             if (4 * q + 2 < K) part += double(v.z) * xe[off(4 * q + 2)];

@@ -24,7 +24,7 @@ __device__ __forceinline__ void vstored_slots(const V *__restrict__ val, size_t 
     const double2 *__restrict__ p = reinterpret_cast<const double2 *>(val) + g;
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
-      const double2 v = p[q * nv];
+      const double2 v = stream_load(p + q * nv);
       f(2 * q, v.x);
       if (2 * q + 1 < K) f(2 * q + 1, v.y);
     }
@@ -32,7 +32,7 @@ __device__ __forceinline__ void vstored_slots(const V *__restrict__ val, size_t 
     const float4 *__restrict__ p = reinterpret_cast<const float4 *>(val) + g;
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
-      const float4 v = p[q * nv];
+      const float4 v = stream_load(p + q * nv);
       f(4 * q, double(v.x));
       if (4 * q + 1 < K) f(4 * q + 1, double(v.y));
       if (4 * q + 2 < K) f(4 * q + 2, double(v.z));
