@@ -505,8 +505,10 @@ void launch_tensor_transfer(hipStream_t s, int dim, int n, const int32_t *row_la
                                                            xinit, done);
 }
 
-// Dense coarsest solve: r gathered into LDS, one wavefront per output row.
-constexpr int kGemvThreads = 256;
+// Dense coarsest solve: r gathered into LDS, one wavefront per output row;
+// 16 rows per workgroup share one gathered copy of r (with 4 rows per
+// workgroup the gathers of r moved a quarter as many bytes as A^-1 itself).
+constexpr int kGemvThreads = 1024;
 __global__ __launch_bounds__(kGemvThreads) void k_dense_gemv(int n, const int32_t *__restrict__ row_lat,
                                                              const double *__restrict__ Ainv,
                                                              const double *__restrict__ r, double *__restrict__ x,
@@ -515,16 +517,16 @@ __global__ __launch_bounds__(kGemvThreads) void k_dense_gemv(int n, const int32_
   extern __shared__ double rs[];
   // gather r in batches of 8 per thread: indices first, then values, so that
   // the loads of a batch are in flight together
-  for (int j0 = threadIdx.x; j0 < n; j0 += 8 * kGemvThreads) {
+  for (int j0 = threadIdx.x; j0 < n; j0 += 4 * kGemvThreads) {
     // unconditional loads at clamped positions: no wait between them
-    int idx[8];
+    int idx[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) idx[q] = row_lat[min(j0 + q * kGemvThreads, n - 1)];
-    double val[8];
+    for (int q = 0; q < 4; ++q) idx[q] = row_lat[min(j0 + q * kGemvThreads, n - 1)];
+    double val[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) val[q] = r[idx[q]];
+    for (int q = 0; q < 4; ++q) val[q] = r[idx[q]];
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
+    for (int q = 0; q < 4; ++q)
       if (j0 + q * kGemvThreads < n) rs[j0 + q * kGemvThreads] = val[q];
   }
   __syncthreads();
