@@ -24,13 +24,13 @@ namespace {
 constexpr int kMsBlock = 256;
 }
 
-// LANES lanes share a row, then add their partial sums in a fixed shuffle
-// order: a colour holds a small fraction of the level's rows, so one lane per
-// row would leave most of the chip idle and each lane with a long chain of
-// gathers.  Stored rows read their values from the colour-ordered copy vals
+// LANES lanes share a row (16 for scalar rows), then add their partial sums
+// in a fixed shuffle order: a colour holds a small fraction of the level's
+// rows, so one lane per row would leave most of the chip idle and each lane
+// with a long chain of gathers.  Stored rows read their values from the colour-ordered copy vals
 // (entry e: KP values, slots in order, zero padded) in 16-byte slot groups
-// q = lane, lane + LANES, ...: the LANES lanes of a row read one contiguous
-// 128-byte line per step.  Rows on the level's reference stencil (vidx < 0)
+// q = lane, lane + LANES, ...: the LANES lanes of a row read LANES x 16
+// contiguous bytes per step.  Rows on the level's reference stencil (vidx < 0)
 // read its coefficients.
 template <int K, typename V, int LANES>
 __global__ __launch_bounds__(kMsBlock) void k_ms_colour(int m, const int32_t *__restrict__ rows,
@@ -161,7 +161,7 @@ static void dispatch_vms_colour(hipStream_t s, int m, const int32_t *rows, const
                                 const double *r, double *x, double *rh, const int32_t *done) {
   if (m <= 0) return;
   // a vector row is ncomp block rows: 32 lanes per row keep each lane's chain
-  // of dependent gathers as short as the scalar kernel's (8 lanes, one block)
+  // of dependent gathers short (one block per 16 lanes would need 48)
   constexpr int LN = 32;
   dim3 g((size_t(m) * LN + kMsBlock - 1) / kMsBlock), t(kMsBlock);
   if (K == 125)
@@ -188,7 +188,7 @@ static void dispatch_ms_colour(hipStream_t s, int m, const int32_t *rows, const 
                                const V *vals, int K, const OpView<V> &op, const int32_t *row_lat, const double *r,
                                double *x, double *rh, const int32_t *done) {
   if (m <= 0) return;
-  constexpr int LN = 8;
+  constexpr int LN = 16;
   dim3 g((size_t(m) * LN + kMsBlock - 1) / kMsBlock), t(kMsBlock);
   switch (K) {
     case 9: k_ms_colour<9, V, LN><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, op, row_lat, r, x, rh, done); break;
