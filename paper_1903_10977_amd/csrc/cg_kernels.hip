@@ -315,7 +315,7 @@ __global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_vcg_init(VecO
                                                           const double *__restrict__ b, double *__restrict__ r,
                                                           double *__restrict__ part) {
   __shared__ double lds[kRedThreads];
-  __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
+  __shared__ double tile[VecShape<K>::LDS_DOUBLES];
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
   const int c = blockIdx.y;
   const int64_t o = c * ops.cstride;
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_vcg_spmv_pq(V
                                                              const double *__restrict__ p, double *__restrict__ q,
                                                              double *__restrict__ part, const CGState *st) {
   __shared__ double lds[kRedThreads];
-  __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
+  __shared__ double tile[VecShape<K>::LDS_DOUBLES];
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
   const int c = blockIdx.y;
   const int64_t o = c * ops.cstride;
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_vcg_true_resi
                                                                    const double *__restrict__ b,
                                                                    double *__restrict__ part) {
   __shared__ double lds[kRedThreads];
-  __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
+  __shared__ double tile[VecShape<K>::LDS_DOUBLES];
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
   const int c = blockIdx.y;
   const int64_t o = c * ops.cstride;

@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kRowBlock, kTileBlocksPerCU) void k_vresidual(VecOp
                                                          const uint32_t *__restrict__ flags,
                                                          const double *__restrict__ x, const double *__restrict__ b,
                                                          double *__restrict__ y, const int32_t *__restrict__ done) {
-  __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
+  __shared__ double tile[VecShape<K>::LDS_DOUBLES];
   const int c = blockIdx.y;
   const int64_t o = c * ops.cstride;
   vtile_rows<K, V>(xcd_block(blockIdx.x, gridDim.x), c, ops, flags, x, tile, ResidualEpi{b ? b + o : nullptr, y + o},
@@ -187,7 +187,7 @@ template <int K, typename V>
 __global__ __launch_bounds__(kRowBlock, kTileBlocksPerCU) void k_vresidual_smooth(
     VecOps<V> ops, const uint32_t *__restrict__ flags, const double *__restrict__ cd, const double *__restrict__ xa,
     const double *__restrict__ r, double *__restrict__ rh, double *__restrict__ xb, const int32_t *__restrict__ done) {
-  __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
+  __shared__ double tile[VecShape<K>::LDS_DOUBLES];
   const int c = blockIdx.y;
   const int64_t o = c * ops.cstride;
   vtile_rows<K, V>(xcd_block(blockIdx.x, gridDim.x), c, ops, flags, xa, tile,

@@ -63,8 +63,18 @@ __device__ __forceinline__ void vtile_load(const TileBox &tb, int sx, int sy, in
 
 // Applies output component c's block row to every row of tile blk and hands
 // each row once to epi.post(i, L, flags[c ns + i], (A x)_(c,L), x_(c,L), pre);
-// epi's vectors are those of component c (the caller offsets them).  Every
-// thread of the workgroup must call it; tiled K only.
+// epi's vectors are those of component c (the caller offsets them).  The
+// windows of all components are loaded together at the start (one round of
+// global loads), then staged in LDS one after the other (one window and one
+// set of exchange slots in LDS, as the scalar tiles, so the occupancy stays
+// that of the scalar kernels); a row adds its block results in the order
+// e = 0, 1, ...  Every thread of the workgroup must call it; tiled K only;
+// lds holds VecShape<K>::LDS_DOUBLES doubles.
+template <int K>
+struct VecShape {
+  static constexpr int LDS_DOUBLES = StencilShape<K>::WINDOW + kTileRows;
+};
+
 template <int K, typename V, typename Epi>
 __device__ __forceinline__ double2 vtile_rows(int blk, int c, const VecOps<V> &ops, const uint32_t *__restrict__ flags,
                                               const double *__restrict__ x, double *lds, const Epi &epi,
@@ -73,6 +83,7 @@ __device__ __forceinline__ double2 vtile_rows(int blk, int c, const VecOps<V> &o
   using Pre = typename Epi::Pre;
   using SS = StencilShape<K>;
   double2 acc = make_double2(0.0, 0.0);
+  const int nc = ops.ncomp;
   const TileBox tb = tile_box<K>(blk, ops.ntx, ops.nty);
   const int tx = threadIdx.x % SS::TX;
   const int ty = (threadIdx.x / SS::TX) % SS::TY;
@@ -82,6 +93,10 @@ __device__ __forceinline__ double2 vtile_rows(int blk, int c, const VecOps<V> &o
   const int L = inbox ? gx + ops.sx * (gy + ops.sy * gz) : 0;
   const int i0 = ops.lat2row[L];
   const int i = inbox ? i0 : -1;
+  TileRegs<K> w[kMaxComp];
+#pragma unroll
+  for (int e = 0; e < kMaxComp; ++e)
+    if (e < nc) vtile_load<K>(tb, ops.sx, ops.sy, ops.sz, x + e * ops.cstride, w[e]);
   Pre p1{};
   unsigned mf = 0u;
   if (i >= 0) {
@@ -92,16 +107,16 @@ __device__ __forceinline__ double2 vtile_rows(int blk, int c, const VecOps<V> &o
   double *xch = lds + SS::WINDOW;
   const double *t = lds + tile_local<K>(threadIdx.x);
   double ax = 0.0, xc = 0.0;
-  for (int e = 0; e < ops.ncomp; ++e) {
-    const int b = c * ops.ncomp + e;
-    TileRegs<K> w;
-    vtile_load<K>(tb, ops.sx, ops.sy, ops.sz, x + e * ops.cstride, w);
+#pragma unroll
+  for (int e = 0; e < kMaxComp; ++e) {
+    if (e >= nc) break;
+    const int b = c * nc + e;
     const int g = ops.tile_g0[b][blk] + threadIdx.x;
     const bool act2 = g < ops.tile_g0[b][blk + 1];
     const int own2 = act2 ? ops.sloc[b][g] : 0;
     const unsigned m = i >= 0 ? ops.meta[b][i] : 0u;
     if (e > 0) __syncthreads();  // the previous component's window and exchange are consumed
-    tile_store<K>(w, lds);
+    tile_store<K>(w[e], lds);
     __syncthreads();
     double a1 = 0.0;
     if (i >= 0 && (m & kMetaIndex) == kMetaIndex) {
@@ -112,7 +127,7 @@ __device__ __forceinline__ double2 vtile_rows(int blk, int c, const VecOps<V> &o
     if (act2) {
       const double *t2 = lds + tile_local<K>(own2);
       double a2 = 0.0;
-      vstored_slots<K, V>(ops.val[b], size_t(ops.nv[b]), g, [&](int s, double a) { a2 += a * tile_at<K>(t2, s); });
+      vstored_slots<K, V>(ops.val[b], size_t(ops.nv[b]), g, [&](int s, double v) { a2 += v * tile_at<K>(t2, s); });
       xch[own2] = a2;
     }
     __syncthreads();
