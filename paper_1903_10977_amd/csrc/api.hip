@@ -171,6 +171,7 @@ struct Level {
   int32_t *ms_vidx = nullptr;
   double *ms_val64 = nullptr;
   float *ms_val32 = nullptr;
+  int ms_stream64 = 0, ms_stream32 = 0;  // copies larger than the last-level cache: non-temporal loads
   struct MsGeneral {
     int ng = 0;
     int32_t *grow_lat = nullptr, *sptr = nullptr, *scol = nullptr;
@@ -416,6 +417,7 @@ void compress_operator(imsmg_ctx *c, const Level &L, int n, const std::vector<in
   o64.nv = nv;
   o32.off = L.off;
   o32.nv = nv;
+  o64.stream = o32.stream = size_t(nv) * L.K > kStreamValues;
   {
     std::vector<float> ref32(ref.begin(), ref.end());
     std::vector<double> ref32d(ref32.begin(), ref32.end());
@@ -952,16 +954,16 @@ void ms_sweep(imsmg_ctx *c, Level &L, bool forward, const int32_t *done) {
     if (L.ncomp > 1) {
       if (mixed(c))
         launch_vms_colour(c->stream, m, L.ms_rows + a, L.ms_cf + a, L.ms_vidx + size_t(a) * L.ncomp, L.ms_val32,
-                          L.K, L.vops32, L.row_lat, L.r, L.x, L.rh, done);
+                          L.K, L.vops32, L.row_lat, L.r, L.x, L.rh, done, L.ms_stream32);
       else
         launch_vms_colour(c->stream, m, L.ms_rows + a, L.ms_cf + a, L.ms_vidx + size_t(a) * L.ncomp, L.ms_val64,
-                          L.K, L.vops64, L.row_lat, L.r, L.x, L.rh, done);
+                          L.K, L.vops64, L.row_lat, L.r, L.x, L.rh, done, L.ms_stream64);
     } else if (mixed(c))
       launch_ms_colour(c->stream, m, L.ms_rows + a, L.ms_cf + a, L.ms_vidx + a, L.ms_val32, L.K, L.op32, L.row_lat,
-                       L.r, L.x, L.rh, done);
+                       L.r, L.x, L.rh, done, L.ms_stream32);
     else
       launch_ms_colour(c->stream, m, L.ms_rows + a, L.ms_cf + a, L.ms_vidx + a, L.ms_val64, L.K, L.op64, L.row_lat,
-                       L.r, L.x, L.rh, done);
+                       L.r, L.x, L.rh, done, L.ms_stream64);
     const Level::MsGeneral &G = L.ms_gen[cc];
     if (G.ng > 0) launch_smooth_general(c->stream, G.ng, G.grow_lat, G.sptr, G.scol, G.sval, L.rh, L.x, done, 4);
   }
@@ -1203,6 +1205,7 @@ void build_ms(imsmg_ctx *c, Level &L, const std::vector<int32_t> &fptr, const st
   if (!vidx.empty()) h2d(s, L.ms_vidx, vidx.data(), vidx.size());
   {
     const int KP64 = (L.K + 1) / 2 * 2, KP32 = (L.K + 3) / 4 * 4;
+    L.ms_stream64 = L.ms_stream32 = size_t(ne) * KP64 > kStreamValues;
     L.ms_val64 = dalloc<double>(c->factor_owned, std::max<size_t>(size_t(ne) * KP64, 2));
     if (mixed(c)) L.ms_val32 = dalloc<float>(c->factor_owned, std::max<size_t>(size_t(ne) * KP32, 4));
     int e0 = 0;

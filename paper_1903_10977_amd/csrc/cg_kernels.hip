@@ -100,7 +100,7 @@ struct TrueResEpi {
 };
 
 // r = b - A x; partials of ||r||^2 (part[0..g)) and ||b||^2 (part[g..2g))
-template <int K>
+template <int K, bool NT>
 __global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_cg_init(int n, int Kdyn, OpView<double> op,
                                                          const int32_t *__restrict__ row_lat,
                                                          const uint32_t *__restrict__ meta,
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_cg_init(int n
   __shared__ double lds[kRedThreads];
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
-  const double2 s = tile_rows<K, double>(n, blk, op, row_lat, meta, x, tile, Kdyn, InitEpi{b, r});
+  const double2 s = tile_rows<K, double, InitEpi, false, NT>(n, blk, op, row_lat, meta, x, tile, Kdyn, InitEpi{b, r});
   double rr = s.x, bb = s.y;
   rr = block_sum<kRedThreads>(rr, lds);
   bb = block_sum<kRedThreads>(bb, lds);
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_direction(int n, const int32
   p[L] = first ? z[L] : z[L] + beta * p[L];
 }
 
-template <int K>
+template <int K, bool NT>
 __global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_cg_spmv_pq(int n, int Kdyn, OpView<double> op,
                                                             const int32_t *__restrict__ row_lat,
                                                             const uint32_t *__restrict__ meta,
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_cg_spmv_pq(in
   __shared__ double lds[kRedThreads];
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
-  double acc = tile_rows<K, double>(n, blk, op, row_lat, meta, p, tile, Kdyn, SpmvEpi{q}, &st->done).x;
+  double acc = tile_rows<K, double, SpmvEpi, false, NT>(n, blk, op, row_lat, meta, p, tile, Kdyn, SpmvEpi{q}, &st->done).x;
   if (st->done) return;  // uniform: the flag does not change during the kernel
   acc = block_sum<kRedThreads>(acc, lds);
   if (threadIdx.x == 0) part[blk] = acc;
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(kFinThreads) void k_cg_update_fin(int m, const doub
 }
 
 // partials of ||b - A x||^2
-template <int K>
+template <int K, bool NT>
 __global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_cg_true_residual(int n, int Kdyn, OpView<double> op,
                                                                   const int32_t *__restrict__ row_lat,
                                                                   const uint32_t *__restrict__ meta,
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_cg_true_resid
   __shared__ double lds[kRedThreads];
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
   const int blk = xcd_block_cg(blockIdx.x, gridDim.x);
-  double acc = tile_rows<K, double>(n, blk, op, row_lat, meta, x, tile, Kdyn, TrueResEpi{b}).x;
+  double acc = tile_rows<K, double, TrueResEpi, false, NT>(n, blk, op, row_lat, meta, x, tile, Kdyn, TrueResEpi{b}).x;
   acc = block_sum<kRedThreads>(acc, lds);
   if (threadIdx.x == 0) part[blk] = acc;
 }
@@ -391,14 +391,19 @@ void launch_vcg_true_residual(hipStream_t s, int K, const VecOps<double> &ops, c
 }
 #undef IMSMG_DISPATCH_V
 
-#define IMSMG_DISPATCH_K(K, KERNEL, ...)                                        \
-  switch (K) {                                                                  \
-    case 9: KERNEL<9><<<g, kRedThreads, 0, s>>>(__VA_ARGS__); break;            \
-    case 25: KERNEL<25><<<g, kRedThreads, 0, s>>>(__VA_ARGS__); break;          \
-    case 49: KERNEL<49><<<g, kRedThreads, 0, s>>>(__VA_ARGS__); break;          \
-    case 27: KERNEL<27><<<g, kRedThreads, 0, s>>>(__VA_ARGS__); break;          \
-    case 125: KERNEL<125><<<g, kRedThreads, 0, s>>>(__VA_ARGS__); break;        \
-    default: KERNEL<0><<<g, kRedThreads, 0, s>>>(__VA_ARGS__); break;           \
+#define IMSMG_DISPATCH_KN(KK, KERNEL, ...)                                               \
+  if (op.stream)                                                                         \
+    KERNEL<KK, true><<<g, kRedThreads, 0, s>>>(__VA_ARGS__);                             \
+  else                                                                                   \
+    KERNEL<KK, false><<<g, kRedThreads, 0, s>>>(__VA_ARGS__);
+#define IMSMG_DISPATCH_K(K, KERNEL, ...)                                                 \
+  switch (K) {                                                                           \
+    case 9: IMSMG_DISPATCH_KN(9, KERNEL, __VA_ARGS__) break;                             \
+    case 25: IMSMG_DISPATCH_KN(25, KERNEL, __VA_ARGS__) break;                           \
+    case 49: IMSMG_DISPATCH_KN(49, KERNEL, __VA_ARGS__) break;                           \
+    case 27: IMSMG_DISPATCH_KN(27, KERNEL, __VA_ARGS__) break;                           \
+    case 125: IMSMG_DISPATCH_KN(125, KERNEL, __VA_ARGS__) break;                         \
+    default: KERNEL<0, false><<<g, kRedThreads, 0, s>>>(__VA_ARGS__); break;            \
   }
 
 void launch_cg_init(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,

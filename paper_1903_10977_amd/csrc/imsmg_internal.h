@@ -54,20 +54,40 @@ struct OpView {
   const int32_t *lat2row;  // lattice point -> row (-1: inactive)
   int sx, sy, sz;          // lattice shape (sz = 1 in 2D)
   int ntx, nty, ntiles;    // lattice tiles along x, along y, in total
+  int stream;              // 1: stored values read with the non-temporal hint (see stream_load)
 };
 
-// Streamed operator values (read once per launch, far more than the caches
-// hold): 16-byte loads with the non-temporal hint, so that they do not evict
-// the x windows that neighbouring tiles share in L2.
+// Streamed operator values: where a level holds more than kStreamValues
+// stored values (they are read once per launch and, with the level's other
+// data, exceed the last-level cache), 16-byte loads with the non-temporal
+// hint keep them from evicting the x windows that neighbouring tiles share.
+// Smaller levels stay cache-resident between launches and use ordinary loads.
+// Measured (FP64 V-cycle): the 128^3 gyroid 0.590 ms with ordinary loads,
+// 0.564 ms streaming its two finest levels; the 1024^2 discs (7.8M values on
+// the finest level) 0.319 ms with ordinary loads, 0.363 ms streaming; the
+// count, not the bytes, decides (FP32 values: the same levels stream best).
+constexpr size_t kStreamValues = size_t(8) << 20;
 typedef double nt_double2 __attribute__((ext_vector_type(2)));
 typedef float nt_float4 __attribute__((ext_vector_type(4)));
+// NT is a compile-time choice: a run-time test per load splits the unrolled
+// load sequences and serializes them (measured 4.7x slower).
+template <bool NT>
 __device__ __forceinline__ double2 stream_load(const double2 *p) {
-  const nt_double2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_double2 *>(p));
-  return make_double2(v.x, v.y);
+  if constexpr (!NT) {
+    return *p;
+  } else {
+    const nt_double2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_double2 *>(p));
+    return make_double2(v.x, v.y);
+  }
 }
+template <bool NT>
 __device__ __forceinline__ float4 stream_load(const float4 *p) {
-  const nt_float4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_float4 *>(p));
-  return make_float4(v.x, v.y, v.z, v.w);
+  if constexpr (!NT) {
+    return *p;
+  } else {
+    const nt_float4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_float4 *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+  }
 }
 
 // Vector operators (linear elasticity, ncomp displacement components): the
@@ -211,17 +231,17 @@ void launch_scatter(hipStream_t s, int n, const int32_t *row_lat, const double *
 // reference stencil), built by launch_ms_pack from the level's operator values
 void launch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
                       const double *vals, int K, const OpView<double> &op, const int32_t *row_lat, const double *r,
-                      double *x, double *rh, const int32_t *done);
+                      double *x, double *rh, const int32_t *done, int stream);
 void launch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
                       const float *vals, int K, const OpView<float> &op, const int32_t *row_lat, const double *r,
-                      double *x, double *rh, const int32_t *done);
+                      double *x, double *rh, const int32_t *done, int stream);
 // vector levels: vidx holds ncomp entries per list entry (block (c, e) of the row)
 void launch_vms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
                        const double *vals, int K, const VecOps<double> &ops, const int32_t *row_lat, const double *r,
-                       double *x, double *rh, const int32_t *done);
+                       double *x, double *rh, const int32_t *done, int stream);
 void launch_vms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
                        const float *vals, int K, const VecOps<float> &ops, const int32_t *row_lat, const double *r,
-                       double *x, double *rh, const int32_t *done);
+                       double *x, double *rh, const int32_t *done, int stream);
 void launch_ms_pack(hipStream_t s, int ne, int K, int KP, const int32_t *g, const double *val, int nv, double *out);
 void launch_ms_pack(hipStream_t s, int ne, int K, int KP, const int32_t *g, const float *val, int nv, float *out);
 // active rows of a level vector: op 0: y = 0, 1: y = x, 2: y += x

@@ -79,19 +79,20 @@ struct SmoothEpi {
 };
 
 // y = b - A x   (b == nullptr: y = A x)
-template <int K, typename V>
+template <int K, typename V, bool NT>
 __global__ __launch_bounds__(kRowBlock, kTileBlocksPerCU) void k_residual(int n, int Kdyn, OpView<V> op, const int32_t *__restrict__ row_lat,
                                                         const uint32_t *__restrict__ meta,
                                                         const double *__restrict__ x, const double *__restrict__ b,
                                                         double *__restrict__ y, const int32_t *__restrict__ done) {
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES];
-  tile_rows<K, V>(n, xcd_block(blockIdx.x, gridDim.x), op, row_lat, meta, x, tile, Kdyn, ResidualEpi{b, y}, done);
+  tile_rows<K, V, ResidualEpi, false, NT>(n, xcd_block(blockIdx.x, gridDim.x), op, row_lat, meta, x, tile, Kdyn,
+                                          ResidualEpi{b, y}, done);
 }
 
 // smoothing step, trivial rows:  rh = r - A xa  (stored for general rows only),
 // xb = xa + c * rh   (c = 0 on general rows, which the general kernel completes);
 // PRO: xa + R^T xc in place of xa (the prolongation of the coarse correction)
-template <int K, typename V, bool PRO>
+template <int K, typename V, bool PRO, bool NT>
 __global__ __launch_bounds__(kRowBlock, kTileBlocksPerCU) void k_residual_smooth(int n, int Kdyn, OpView<V> op,
                                                                const int32_t *__restrict__ row_lat,
                                                                const uint32_t *__restrict__ meta,
@@ -101,8 +102,8 @@ __global__ __launch_bounds__(kRowBlock, kTileBlocksPerCU) void k_residual_smooth
                                                                double *__restrict__ xb,
                                                                const int32_t *__restrict__ done, ProlongView pv) {
   __shared__ double tile[StencilShape<K>::LDS_DOUBLES + (PRO ? ProShape<K>::LDS_EXTRA : 0)];
-  tile_rows<K, V, SmoothEpi, PRO>(n, xcd_block(blockIdx.x, gridDim.x), op, row_lat, meta, xa, tile, Kdyn,
-                                  SmoothEpi{r, c, rh, xb}, done, &pv);
+  tile_rows<K, V, SmoothEpi, PRO, NT>(n, xcd_block(blockIdx.x, gridDim.x), op, row_lat, meta, xa, tile, Kdyn,
+                                      SmoothEpi{r, c, rh, xb}, done, &pv);
 }
 
 template <typename V>
@@ -110,14 +111,20 @@ static void dispatch_residual(hipStream_t s, int n, int K, const OpView<V> &op, 
                               const uint32_t *meta, const double *x, const double *b, double *y, const int32_t *done) {
   if (n <= 0) return;
   dim3 g(stencil_grid(K, n, op)), t(kRowBlock);
+#define IMSMG_R(KK)                                                                  \
+  if (op.stream)                                                                     \
+    k_residual<KK, V, true><<<g, t, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done);  \
+  else                                                                               \
+    k_residual<KK, V, false><<<g, t, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done);
   switch (K) {
-    case 9: k_residual<9, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done); break;
-    case 25: k_residual<25, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done); break;
-    case 49: k_residual<49, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done); break;
-    case 27: k_residual<27, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done); break;
-    case 125: k_residual<125, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done); break;
-    default: k_residual<0, V><<<g, t, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done); break;
+    case 9: IMSMG_R(9) break;
+    case 25: IMSMG_R(25) break;
+    case 49: IMSMG_R(49) break;
+    case 27: IMSMG_R(27) break;
+    case 125: IMSMG_R(125) break;
+    default: k_residual<0, V, false><<<g, t, 0, s>>>(n, K, op, row_lat, meta, x, b, y, done); break;
   }
+#undef IMSMG_R
 }
 
 template <typename V>
@@ -127,14 +134,19 @@ static void dispatch_residual_smooth(hipStream_t s, int n, int K, const OpView<V
   if (n <= 0) return;
   dim3 g(stencil_grid(K, n, op)), t(kRowBlock);
   const ProlongView p = pv ? *pv : ProlongView{};
-#define IMSMG_RS(KK)                                                                                   \
-  if (pv)                                                                                              \
-    k_residual_smooth<KK, V, true><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done, p); \
-  else                                                                                                 \
-    k_residual_smooth<KK, V, false><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done, p);
-#define IMSMG_RS3(KK)                                                                                   \
-  if (pv) throw std::invalid_argument("fused prolongation: 2D lattices only");                          \
-  k_residual_smooth<KK, V, false><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done, p);
+#define IMSMG_RS(KK)                                                                                         \
+  if (pv)                                                                                                    \
+    k_residual_smooth<KK, V, true, false><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done, p); \
+  else if (op.stream)                                                                                        \
+    k_residual_smooth<KK, V, false, true><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done, p); \
+  else                                                                                                       \
+    k_residual_smooth<KK, V, false, false><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done, p);
+#define IMSMG_RS3(KK)                                                                                        \
+  if (pv) throw std::invalid_argument("fused prolongation: 2D lattices only");                               \
+  if (op.stream)                                                                                             \
+    k_residual_smooth<KK, V, false, true><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done, p); \
+  else                                                                                                       \
+    k_residual_smooth<KK, V, false, false><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done, p);
   switch (K) {
     case 9: IMSMG_RS(9) break;
     case 25: IMSMG_RS(25) break;
@@ -143,7 +155,7 @@ static void dispatch_residual_smooth(hipStream_t s, int n, int K, const OpView<V
     case 125: IMSMG_RS3(125) break;
     default:
       if (pv) throw std::invalid_argument("fused prolongation needs a tiled stencil");
-      k_residual_smooth<0, V, false><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done, p);
+      k_residual_smooth<0, V, false, false><<<g, t, 0, s>>>(n, K, op, row_lat, meta, c, xa, r, rh, xb, done, p);
       break;
   }
 #undef IMSMG_RS
@@ -505,9 +517,11 @@ void launch_tensor_transfer(hipStream_t s, int dim, int n, const int32_t *row_la
                                                            xinit, done);
 }
 
-// Dense coarsest solve: r gathered into LDS, one wavefront per output row;
-// 16 rows per workgroup share one gathered copy of r (with 4 rows per
-// workgroup the gathers of r moved a quarter as many bytes as A^-1 itself).
+// Dense coarsest solve: r gathered into LDS, one wavefront per output row.
+// Large coarsest levels: 16 rows per workgroup share one gathered copy of r
+// (with 4 rows per workgroup the gathers of r moved a quarter as many bytes
+// as A^-1 itself); small ones keep 4 rows per workgroup, so that enough
+// workgroups run.
 constexpr int kGemvThreads = 1024;
 __global__ __launch_bounds__(kGemvThreads) void k_dense_gemv(int n, const int32_t *__restrict__ row_lat,
                                                              const double *__restrict__ Ainv,
@@ -517,22 +531,23 @@ __global__ __launch_bounds__(kGemvThreads) void k_dense_gemv(int n, const int32_
   extern __shared__ double rs[];
   // gather r in batches of 8 per thread: indices first, then values, so that
   // the loads of a batch are in flight together
-  for (int j0 = threadIdx.x; j0 < n; j0 += 4 * kGemvThreads) {
+  const int nt = blockDim.x;
+  for (int j0 = threadIdx.x; j0 < n; j0 += 4 * nt) {
     // unconditional loads at clamped positions: no wait between them
     int idx[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) idx[q] = row_lat[min(j0 + q * kGemvThreads, n - 1)];
+    for (int q = 0; q < 4; ++q) idx[q] = row_lat[min(j0 + q * nt, n - 1)];
     double val[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) val[q] = r[idx[q]];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      if (j0 + q * kGemvThreads < n) rs[j0 + q * kGemvThreads] = val[q];
+      if (j0 + q * nt < n) rs[j0 + q * nt] = val[q];
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int rows_per_block = kGemvThreads / 64;
+  const int rows_per_block = nt / 64;
   const int i = blockIdx.x * rows_per_block + wave;
   if (i >= n) return;
   const double *row = Ainv + size_t(i) * n;
@@ -546,8 +561,9 @@ __global__ __launch_bounds__(kGemvThreads) void k_dense_gemv(int n, const int32_
 void launch_dense_gemv(hipStream_t s, int n, const int32_t *row_lat, const double *Ainv, const double *r, double *x,
                        const int32_t *done) {
   if (n <= 0) return;
-  const int rpb = kGemvThreads / 64;
-  k_dense_gemv<<<(n + rpb - 1) / rpb, kGemvThreads, size_t(n) * sizeof(double), s>>>(n, row_lat, Ainv, r, x, done);
+  const int nt = n >= 2048 ? kGemvThreads : 256;
+  const int rpb = nt / 64;
+  k_dense_gemv<<<(n + rpb - 1) / rpb, nt, size_t(n) * sizeof(double), s>>>(n, row_lat, Ainv, r, x, done);
 }
 
 __global__ void k_scatter(int n, const int32_t *__restrict__ row_lat, const double *__restrict__ src,

@@ -32,7 +32,7 @@ constexpr int kMsBlock = 256;
 // q = lane, lane + LANES, ...: the LANES lanes of a row read LANES x 16
 // contiguous bytes per step.  Rows on the level's reference stencil (vidx < 0)
 // read its coefficients.
-template <int K, typename V, int LANES>
+template <int K, typename V, int LANES, bool NT>
 __global__ __launch_bounds__(kMsBlock) void k_ms_colour(int m, const int32_t *__restrict__ rows,
                                                         const double *__restrict__ cf,
                                                         const int32_t *__restrict__ vidx,
@@ -64,11 +64,11 @@ __global__ __launch_bounds__(kMsBlock) void k_ms_colour(int m, const int32_t *__
       const V *__restrict__ rowv = vals + size_t(e) * (NG * G);
       for (int q = lane; q < NG; q += LANES) {
         if constexpr (G == 2) {
-          const double2 v = stream_load(reinterpret_cast<const double2 *>(rowv) + q);
+          const double2 v = stream_load<NT>(reinterpret_cast<const double2 *>(rowv) + q);
           part += v.x * x[L + off(2 * q)];
           if (2 * q + 1 < K) part += v.y * x[L + off(2 * q + 1)];
         } else {
-          const float4 v = stream_load(reinterpret_cast<const float4 *>(rowv) + q);
+          const float4 v = stream_load<NT>(reinterpret_cast<const float4 *>(rowv) + q);
           part += double(v.x) * x[L + off(4 * q)];
           if (4 * q + 1 < K) part += double(v.y) * x[L + off(4 * q + 1)];
           if (4 * q + 2 < K) part += double(v.z) * x[L + off(4 * q + 2)];
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kMsBlock) void k_ms_colour(int m, const int32_t *__
 // A_(c,e) x_e, block by block (e = 0, 1, ..), each from the block's
 // reference stencil (vidx[t ncomp + e] < 0) or from its entry of the
 // colour-ordered copy; then the same update as the scalar kernel.
-template <int K, typename V, int LANES>
+template <int K, typename V, int LANES, bool NT>
 __global__ __launch_bounds__(kMsBlock) void k_vms_colour(int m, const int32_t *__restrict__ rows,
                                                          const double *__restrict__ cf,
                                                          const int32_t *__restrict__ vidx,
@@ -129,11 +129,11 @@ __global__ __launch_bounds__(kMsBlock) void k_vms_colour(int m, const int32_t *_
         const V *__restrict__ rowv = vals + size_t(ve) * (NG * G);
         for (int q = lane; q < NG; q += LANES) {
           if constexpr (G == 2) {
-            const double2 v = stream_load(reinterpret_cast<const double2 *>(rowv) + q);
+            const double2 v = stream_load<NT>(reinterpret_cast<const double2 *>(rowv) + q);
             part += v.x * xe[off(2 * q)];
             if (2 * q + 1 < K) part += v.y * xe[off(2 * q + 1)];
           } else {
-            const float4 v = stream_load(reinterpret_cast<const float4 *>(rowv) + q);
+            const float4 v = stream_load<NT>(reinterpret_cast<const float4 *>(rowv) + q);
             part += double(v.x) * xe[off(4 * q)];
             if (4 * q + 1 < K) part += double(v.y) * xe[off(4 * q + 1)];
             if (4 * q + 2 < K) part += double(v.z) * xe[off(4 * q + 2)];
@@ -158,46 +158,58 @@ __global__ __launch_bounds__(kMsBlock) void k_vms_colour(int m, const int32_t *_
 template <typename V>
 static void dispatch_vms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
                                 const V *vals, int K, const VecOps<V> &ops, const int32_t *row_lat,
-                                const double *r, double *x, double *rh, const int32_t *done) {
+                                const double *r, double *x, double *rh, const int32_t *done, int stream) {
   if (m <= 0) return;
   // a vector row is ncomp block rows: 32 lanes per row keep each lane's chain
   // of dependent gathers short (one block per 16 lanes would need 48)
   constexpr int LN = 32;
   dim3 g((size_t(m) * LN + kMsBlock - 1) / kMsBlock), t(kMsBlock);
-  if (K == 125)
-    k_vms_colour<125, V, LN><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, ops, row_lat, r, x, rh, done);
-  else if (K == 27)
-    k_vms_colour<27, V, LN><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, ops, row_lat, r, x, rh, done);
-  else
+#define IMSMG_VMS(KK)                                                                                   \
+  if (stream)                                                                                           \
+    k_vms_colour<KK, V, LN, true><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, ops, row_lat, r, x, rh, done);  \
+  else                                                                                                  \
+    k_vms_colour<KK, V, LN, false><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, ops, row_lat, r, x, rh, done);
+  if (K == 125) {
+    IMSMG_VMS(125)
+  } else if (K == 27) {
+    IMSMG_VMS(27)
+  } else
     throw std::invalid_argument("vector multiplicative smoother: 3D stencils of 27 or 125 slots");
+#undef IMSMG_VMS
 }
 
 void launch_vms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
                        const double *vals, int K, const VecOps<double> &ops, const int32_t *row_lat, const double *r,
-                       double *x, double *rh, const int32_t *done) {
-  dispatch_vms_colour<double>(s, m, rows, cf, vidx, vals, K, ops, row_lat, r, x, rh, done);
+                       double *x, double *rh, const int32_t *done, int stream) {
+  dispatch_vms_colour<double>(s, m, rows, cf, vidx, vals, K, ops, row_lat, r, x, rh, done, stream);
 }
 void launch_vms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
                        const float *vals, int K, const VecOps<float> &ops, const int32_t *row_lat, const double *r,
-                       double *x, double *rh, const int32_t *done) {
-  dispatch_vms_colour<float>(s, m, rows, cf, vidx, vals, K, ops, row_lat, r, x, rh, done);
+                       double *x, double *rh, const int32_t *done, int stream) {
+  dispatch_vms_colour<float>(s, m, rows, cf, vidx, vals, K, ops, row_lat, r, x, rh, done, stream);
 }
 
 template <typename V>
 static void dispatch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
                                const V *vals, int K, const OpView<V> &op, const int32_t *row_lat, const double *r,
-                               double *x, double *rh, const int32_t *done) {
+                               double *x, double *rh, const int32_t *done, int stream) {
   if (m <= 0) return;
   constexpr int LN = 16;
   dim3 g((size_t(m) * LN + kMsBlock - 1) / kMsBlock), t(kMsBlock);
+#define IMSMG_MS(KK)                                                                                  \
+  if (stream)                                                                                         \
+    k_ms_colour<KK, V, LN, true><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, op, row_lat, r, x, rh, done);  \
+  else                                                                                                \
+    k_ms_colour<KK, V, LN, false><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, op, row_lat, r, x, rh, done);
   switch (K) {
-    case 9: k_ms_colour<9, V, LN><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, op, row_lat, r, x, rh, done); break;
-    case 25: k_ms_colour<25, V, LN><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, op, row_lat, r, x, rh, done); break;
-    case 49: k_ms_colour<49, V, LN><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, op, row_lat, r, x, rh, done); break;
-    case 27: k_ms_colour<27, V, LN><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, op, row_lat, r, x, rh, done); break;
-    case 125: k_ms_colour<125, V, LN><<<g, t, 0, s>>>(m, rows, cf, vidx, vals, op, row_lat, r, x, rh, done); break;
+    case 9: IMSMG_MS(9) break;
+    case 25: IMSMG_MS(25) break;
+    case 49: IMSMG_MS(49) break;
+    case 27: IMSMG_MS(27) break;
+    case 125: IMSMG_MS(125) break;
     default: throw std::invalid_argument("multiplicative smoother: stencils of 9, 25, 49, 27 or 125 slots");
   }
+#undef IMSMG_MS
 }
 
 // The colour-ordered copy of the stored rows' values: entry e takes stored
@@ -214,13 +226,13 @@ __global__ void k_ms_pack(int ne, int K, int KP, const int32_t *__restrict__ g, 
 
 void launch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
                       const double *vals, int K, const OpView<double> &op, const int32_t *row_lat, const double *r,
-                      double *x, double *rh, const int32_t *done) {
-  dispatch_ms_colour<double>(s, m, rows, cf, vidx, vals, K, op, row_lat, r, x, rh, done);
+                      double *x, double *rh, const int32_t *done, int stream) {
+  dispatch_ms_colour<double>(s, m, rows, cf, vidx, vals, K, op, row_lat, r, x, rh, done, stream);
 }
 void launch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
                       const float *vals, int K, const OpView<float> &op, const int32_t *row_lat, const double *r,
-                      double *x, double *rh, const int32_t *done) {
-  dispatch_ms_colour<float>(s, m, rows, cf, vidx, vals, K, op, row_lat, r, x, rh, done);
+                      double *x, double *rh, const int32_t *done, int stream) {
+  dispatch_ms_colour<float>(s, m, rows, cf, vidx, vals, K, op, row_lat, r, x, rh, done, stream);
 }
 void launch_ms_pack(hipStream_t s, int ne, int K, int KP, const int32_t *g, const double *val, int nv, double *out) {
   if (ne > 0)

@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kTileRows) void k_m_tile(int R, OpView<V> op, const
   if (act2) {
     const int t2 = tile_local<K>(own2);
     double a2[NC] = {};
-    stored_row_slots<K, V>(op, g, [&](int s, double a) {
+    stored_row_slots_nt<K, V, false>(op.val, size_t(op.nv), g, [&](int s, double a) {
       const int dx = s % SS::W, dy = (s / SS::W) % SS::W, dz = s / (SS::W * SS::W);
       const double *t = win + (t2 + (dz * SS::WY + dy) * SS::WX + dx) * NC;
 #pragma unroll

@@ -71,25 +71,24 @@ __device__ __forceinline__ double op_row(unsigned meta, const OpView<V> &op, con
 }
 
 // The K values of stored row g in slot order, one 16-byte load per slot
-// group (SlotGroup): f(s, a_s) for s = 0 .. K-1.
-template <int K, typename V, typename F>
-__device__ __forceinline__ void stored_row_slots(const OpView<V> &op, int g, F &&f) {
+// group (SlotGroup): f(s, a_s) for s = 0 .. K-1; NT: non-temporal loads.
+template <int K, typename V, bool NT, typename F>
+__device__ __forceinline__ void stored_row_slots_nt(const V *__restrict__ val, size_t nv, int g, F &&f) {
   constexpr int G = SlotGroup<V>::G;
   constexpr int NG = (K + G - 1) / G;
-  const size_t nv = size_t(op.nv);
   if constexpr (G == 2) {
-    const double2 *__restrict__ p = reinterpret_cast<const double2 *>(op.val) + g;
+    const double2 *__restrict__ p = reinterpret_cast<const double2 *>(val) + g;
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
-      const double2 v = stream_load(p + q * nv);
+      const double2 v = stream_load<NT>(p + q * nv);
       f(2 * q, v.x);
       if (2 * q + 1 < K) f(2 * q + 1, v.y);
     }
   } else {
-    const float4 *__restrict__ p = reinterpret_cast<const float4 *>(op.val) + g;
+    const float4 *__restrict__ p = reinterpret_cast<const float4 *>(val) + g;
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
-      const float4 v = stream_load(p + q * nv);
+      const float4 v = stream_load<NT>(p + q * nv);
       f(4 * q, double(v.x));
       if (4 * q + 1 < K) f(4 * q + 1, double(v.y));
       if (4 * q + 2 < K) f(4 * q + 2, double(v.z));
@@ -207,7 +206,8 @@ inline int stencil_grid(int K, int n, const OpView<V> &op) {
 }
 
 // Applies the operator to every row of workgroup blk and hands each row
-// exactly once to the epilogue: epi.post(i, L, meta, (A x)_L, x_L, pre) with
+// exactly once to the epilogue (NT: the stored values with non-temporal
+// loads, for levels whose values far exceed the caches; OpView::stream): epi.post(i, L, meta, (A x)_L, x_L, pre) with
 // pre = epi.pre(i, L) fetched before the tile is staged (so that its loads
 // overlap the staging); post returns a pair of partial sums that tile_rows
 // adds up per thread.  Tiled K: blk is a lattice tile; otherwise rows
@@ -224,7 +224,7 @@ inline int stencil_grid(int K, int n, const OpView<V> &op) {
 // coarse window origins join load (1), the coarse window load (2); the
 // corrections are added to the window registers before they go to LDS, in
 // the order of the transfer kernel (bitwise the same x + R^T xc).
-template <int K, typename V, typename Epi, bool PRO = false>
+template <int K, typename V, typename Epi, bool PRO = false, bool NT = false>
 __device__ __forceinline__ double2 tile_rows(int n, int blk, const OpView<V> &op,
                                              const int32_t *__restrict__ row_lat, const uint32_t *__restrict__ meta,
                                              const double *__restrict__ x, double *lds, int Kdyn, const Epi &epi,
@@ -358,7 +358,7 @@ __device__ __forceinline__ double2 tile_rows(int n, int blk, const OpView<V> &op
     if (act2) {
       const double *t2 = lds + tile_local<K>(own2);
       double a2 = 0.0;
-      stored_row_slots<K, V>(op, g, [&](int s, double a) { a2 += a * tile_at<K>(t2, s); });
+      stored_row_slots_nt<K, V, NT>(op.val, size_t(op.nv), g, [&](int s, double a) { a2 += a * tile_at<K>(t2, s); });
       xch[own2] = a2;
     }
     __syncthreads();

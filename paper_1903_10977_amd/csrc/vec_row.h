@@ -15,32 +15,6 @@
 
 namespace imsmg {
 
-// The K values of stored row g of one block (slot groups, as stored_row_slots).
-template <int K, typename V, typename F>
-__device__ __forceinline__ void vstored_slots(const V *__restrict__ val, size_t nv, int g, F &&f) {
-  constexpr int G = SlotGroup<V>::G;
-  constexpr int NG = (K + G - 1) / G;
-  if constexpr (G == 2) {
-    const double2 *__restrict__ p = reinterpret_cast<const double2 *>(val) + g;
-#pragma unroll
-    for (int q = 0; q < NG; ++q) {
-      const double2 v = stream_load(p + q * nv);
-      f(2 * q, v.x);
-      if (2 * q + 1 < K) f(2 * q + 1, v.y);
-    }
-  } else {
-    const float4 *__restrict__ p = reinterpret_cast<const float4 *>(val) + g;
-#pragma unroll
-    for (int q = 0; q < NG; ++q) {
-      const float4 v = stream_load(p + q * nv);
-      f(4 * q, double(v.x));
-      if (4 * q + 1 < K) f(4 * q + 1, double(v.y));
-      if (4 * q + 2 < K) f(4 * q + 2, double(v.z));
-      if (4 * q + 3 < K) f(4 * q + 3, double(v.w));
-    }
-  }
-}
-
 // The x window of tile box tb for one component (zeros outside the lattice).
 template <int K>
 __device__ __forceinline__ void vtile_load(const TileBox &tb, int sx, int sy, int sz, const double *__restrict__ x,
@@ -127,7 +101,10 @@ __device__ __forceinline__ double2 vtile_rows(int blk, int c, const VecOps<V> &o
     if (act2) {
       const double *t2 = lds + tile_local<K>(own2);
       double a2 = 0.0;
-      vstored_slots<K, V>(ops.val[b], size_t(ops.nv[b]), g, [&](int s, double v) { a2 += v * tile_at<K>(t2, s); });
+      // vector levels stream their values (nine blocks per point: the
+      // elasticity operators far exceed the caches on every level that counts)
+      stored_row_slots_nt<K, V, true>(ops.val[b], size_t(ops.nv[b]), g,
+                                      [&](int s, double v) { a2 += v * tile_at<K>(t2, s); });
       xch[own2] = a2;
     }
     __syncthreads();
