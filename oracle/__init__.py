@@ -25,6 +25,12 @@ oracle favours the plain definition of each object over speed:
                   remark, the additive Schwarz operator and its damping.
 * multigrid.py  - the V-cycle (Algorithm alg:MGV) and CG preconditioned by it.
 * mlp.py        - the per-block damping network (forward/backward/Adam).
+* elasticity.py - linear elasticity with penalty Dirichlet conditions and
+                  per-component Schwarz blocks (eq:weakMulti,
+                  eq:operatorsMulti).
+* thb.py        - truncated hierarchical B-splines (Figure fig:THB), the
+                  hierarchical coarsening of Algorithm alg:coarsen and the THB
+                  multigrid hierarchy.
 * learned.py    - per-block damping: block features, the two-grid objective
                   built on eq:eigenMulti with its adjoint gradient, and the
                   lambda_max(S A) < 2(1 - 0.05) stability check.

@@ -92,6 +92,10 @@ class Workload:
          colouring) on the finest level; coarse_smoother: "same" (the finest
          level's smoother on every level), "jacobi" or "gs" (one block per
          function on the coarser levels); cycle: 1 (V) or 2 (W).
+    local_levels: 0 for uniform grids; M > 0 for hierarchically refined
+         meshes (truncated hierarchical B-splines): n is then the number of
+         level-0 cells per axis and the cells cut by the immersed boundary are
+         refined, recursively, M times (finest cells n 2^M per axis).
     """
     name: str
     dim: int
@@ -119,6 +123,7 @@ class Workload:
     force: Optional[list] = None
     dirichlet_part: str = "all"
     plane_x: float = 0.0
+    local_levels: int = 0
 
     def to_json(self) -> str:
         return json.dumps(asdict(self), sort_keys=True)
@@ -232,3 +237,13 @@ def slab(n: int = 8, levels: int = 2, fraction: float = 0.37) -> Workload:
                     basis="bspline", bc="penalty", rhs="force", nu=1, penalty_factor=2.0,
                     physics="elasticity", lame_lambda=1.0e3, lame_mu=1.0e3, force=[0.0, 0.0, -1.0],
                     dirichlet_part="all", plane_x=xc)
+
+
+def thb_discs(seed: int = 7, n: int = 64, local_levels: int = 2, levels: int = 3, n_discs: int = 12,
+              rmin: float = 0.04, rmax: float = 0.12, depth: int = 1) -> Workload:
+    """2D Poisson with quadratic truncated hierarchical B-splines: unit square
+    minus non-overlapping discs, n^2 level-0 cells, the cells cut by the disc
+    boundaries refined local_levels times, f = 1, u = 0 on the box."""
+    return Workload(name=f"thb-s{seed}-n{n}-m{local_levels}", dim=2, degree=2, n=n, depth=depth,
+                    levels=levels, geometry="discs", discs=disc_set(seed, n_discs, rmin, rmax).tolist(),
+                    rhs="one", nu=1, local_levels=local_levels)
