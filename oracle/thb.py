@@ -21,9 +21,9 @@ refined (its four children become coarse elements of level m+1).
 
 Readings (the paper fixes none of these):
 * 2D, degree p, open uniform knot vectors on [lo, hi]^2 at every level;
-* the input mesh: for m = 0..M-1 the level-m cells of Omega^m cut by the
-  immersed boundary (leaf vertices of both signs inside the cell) are
-  refined, so the boundary is resolved at level M;
+* the input mesh: for m = 0..M-1 the level-m cells of Omega^m that hold a
+  cut cell of the finest grid (volume fraction strictly between 0 and 1, to
+  1e-12) are refined, so the boundary is resolved at level M;
 * a coarse element "intersects" a fine element when they overlap with
   positive area (a fine element of level > m inside it);
 * every function is stored by its coefficients C_ik in the B-splines B_k of
@@ -58,6 +58,8 @@ from . import geometry as G
 from . import hierarchy as H
 from . import multigrid as MG
 from . import schwarz as SW
+
+CUT_TOL = 1e-12
 
 
 @dataclass
@@ -96,16 +98,30 @@ def children(mask: np.ndarray) -> np.ndarray:
     return np.kron(mask, np.ones((2, 2), dtype=bool)).astype(bool)
 
 
-def refine_at_boundary(n0: int, M: int, leaf: np.ndarray, depth: int) -> HMesh:
-    """The input mesh: level-m cells cut by the immersed boundary are refined
-    (leaf lattice of the finest grid, n0 2^M cells bisected `depth` times)."""
+def refine_at_boundary(n0: int, M: int, vol_frac: np.ndarray) -> HMesh:
+    """The input mesh: level-m cells holding a cut grid cell are refined.
+    vol_frac[ix, iy]: volume fractions of the cells of the n0 2^M grid."""
+    n_grid = n0 * 2 ** M
+    cut = (vol_frac > CUT_TOL) & (vol_frac < 1.0 - CUT_TOL)
     dom = [np.ones((n0, n0), dtype=bool)]
     for m in range(M):
         nm = n0 * 2 ** m
-        npos, total = G.element_states(leaf, nm, depth + M - m)
-        cut = (npos > 0) & (npos < total)
-        dom.append(children(dom[m] & cut))
+        s = n_grid // nm
+        ref = np.zeros((nm, nm), dtype=bool)
+        for ey in range(nm):
+            for ex in range(nm):
+                if dom[m][ex, ey] and cut[ex * s:(ex + 1) * s, ey * s:(ey + 1) * s].any():
+                    ref[ex, ey] = True
+        dom.append(children(ref))
     return HMesh(n0, M, dom)
+
+
+def grid_volume_fractions(system, n_grid: int) -> np.ndarray:
+    """[ix, iy] volume fractions of a uniform system (0 off the active cells)."""
+    out = np.zeros((n_grid, n_grid))
+    for el, v in system.vol_frac.items():
+        out[el % n_grid, el // n_grid] = v
+    return out
 
 
 def coarsen(fine: HMesh) -> HMesh:
@@ -284,7 +300,7 @@ class THBHierarchy:
         b_grid = np.zeros(nf1 * nf1)
         b_grid[self.grid.level.active] = self.grid.b
         self.meshes = [None] * L
-        self.meshes[L - 1] = refine_at_boundary(w.n, M, self.leaf, w.depth)
+        self.meshes[L - 1] = refine_at_boundary(w.n, M, grid_volume_fractions(self.grid, self.n_grid))
         for k in range(L - 2, -1, -1):
             self.meshes[k] = coarsen(self.meshes[k + 1])
         self.levels = [build_level(m, p, self.n_grid, self.grid.level, w.box_lo, w.box_hi) for m in self.meshes]
