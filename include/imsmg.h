@@ -100,7 +100,20 @@ typedef struct {
   const double *eta;     /* nelements volume fractions, or NULL */
 } imsmg_elements;
 
-/* Function lattice of one level. */
+/* Function lattice of one level.
+ *
+ * dof_to_lattice == NULL makes the level a general sparse level: no function
+ * lattice and no common stencil (locally refined discretizations: truncated
+ * hierarchical B-splines of Figure fig:THB on meshes coarsened by Algorithm
+ * alg:coarsen).  Its operator is kept as CSR with any pattern (columns
+ * sorted and unique, positive diagonal), R and R^T as sparse rows, and the
+ * smoother's blocks and element incidence as given; dim, shape, reach and
+ * two_scale are ignored (two_scale must be NULL).  Either every level of a
+ * setup is general or none is.  General levels support the additive
+ * smoother (with diagonal coarse smoothing and V/W cycles), FP64 and mixed
+ * precision, single right-hand sides; the multiplicative smoother, learned
+ * weights, block_gemm and the multi-column and batched calls return
+ * IMSMG_ERR_INVALID_ARG. */
 typedef struct {
   int32_t dim;                  /* 2 or 3 */
   int32_t shape[3];             /* functions per axis (unused axes: 1) */

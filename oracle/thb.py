@@ -308,6 +308,8 @@ class THBHierarchy:
         A = (F.C @ A_grid @ F.C.T).tocsr()
         self.A_direct = [(lv.C @ A_grid @ lv.C.T).tocsr() for lv in self.levels]
         self.b = F.C @ b_grid
+        M_grid = embed(self.grid.level, self.grid.M, nf1)
+        self.M = (F.C @ M_grid @ F.C.T).tocsr()       # L2(Omega) Gram matrix of the THB functions
         self.A = [None] * L
         self.R = [None] * (L - 1)
         self.A[L - 1] = A

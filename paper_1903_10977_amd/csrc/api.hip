@@ -71,6 +71,15 @@ struct Level {
   VecOps<float> vops32{};
   std::vector<std::vector<uint32_t>> h_bmeta;  // per component block: stored index or kMetaIndex per scalar row
   double *dense0 = nullptr;  // coarsest vector level: the dense operator (setup)
+  // general sparse level (no function lattice: locally refined bases): the
+  // operator as CSR (host copy for the coarsest dense matrix), rows at the
+  // identity positions of the padded vectors, csr_lanes lanes per row
+  bool csr = false;
+  int csr_lanes = 8;
+  CsrView<double> a64{};
+  CsrView<float> a32{};
+  std::vector<int32_t> h_aptr, h_acol;
+  std::vector<double> h_aval;
   int K = 0, dim = 2, reach = 0, center = 0;
   int shape[3] = {1, 1, 1};
   Offsets off{};
@@ -460,8 +469,80 @@ int stencil_slot(const Level &L, int64_t li, int64_t lj) {
   return sl;
 }
 
+void alloc_level_vectors(imsmg_ctx *c, Level &L);
+
+// General sparse level: the operator stays CSR (any pattern); vectors are
+// indexed by row inside the guard band.
+void setup_csr_level(imsmg_ctx *c, Level &L, const imsmg_csr &A) {
+  hipStream_t s = c->stream;
+  if (c->opt.ncomp != 1) bad("general sparse levels (no lattice) take scalar problems (ncomp 1)");
+  if (A.nrows <= 0 || A.nrows != A.ncols) bad("A must be square and non-empty");
+  if (!A.rowptr || !A.col || !A.val) bad("null CSR array");
+  const int n = A.nrows;
+  if (A.rowptr[0] != 0 || A.rowptr[n] != A.nnz) bad("CSR rowptr inconsistent with nnz");
+  if (A.nnz > (int64_t(1) << 31) - 1) bad("operator too large for 32-bit CSR offsets");
+  L.csr = true;
+  L.n = L.ns = n;
+  L.ncomp = 1;
+  L.dim = 0;
+  L.reach = 0;
+  L.K = 1;       // L.val holds the diagonal as a one-slot ELL (diagonal readers)
+  L.center = 0;
+  L.shape[0] = n;
+  L.shape[1] = L.shape[2] = 1;
+  L.lattice = n;
+  L.guard = 64;
+  L.cstride = L.lattice + 2 * L.guard;
+  L.h_lat.resize(n);
+  L.h_row_lat.resize(n);
+  std::iota(L.h_lat.begin(), L.h_lat.end(), 0);
+  std::iota(L.h_row_lat.begin(), L.h_row_lat.end(), 0);
+  L.h_aptr.assign(A.rowptr, A.rowptr + n + 1);
+  L.h_acol.assign(A.col, A.col + A.nnz);
+  L.h_aval.assign(A.val, A.val + A.nnz);
+  std::vector<double> diag(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    if (A.rowptr[i + 1] < A.rowptr[i]) bad("CSR rowptr must be non-decreasing");
+    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+      if (A.col[k] < 0 || A.col[k] >= n) bad("CSR column out of range");
+      if (k > A.rowptr[i] && A.col[k] <= A.col[k - 1]) bad("CSR columns must be sorted and unique");
+      if (A.col[k] == i) diag[i] = A.val[k];
+    }
+    if (!(diag[i] > 0.0) || !std::isfinite(diag[i]))
+      bad("operator has a non-positive diagonal entry (not SPD)", IMSMG_ERR_NOT_SPD);
+  }
+  int32_t *ptr = dalloc<int32_t>(c->owned, n + 1);
+  int32_t *col = dalloc<int32_t>(c->owned, A.nnz);
+  double *v64 = dalloc<double>(c->owned, A.nnz);
+  float *v32 = dalloc<float>(c->owned, A.nnz);
+  std::vector<float> f32(A.val, A.val + A.nnz);
+  h2d(s, ptr, L.h_aptr.data(), n + 1);
+  h2d(s, col, L.h_acol.data(), A.nnz);
+  h2d(s, v64, A.val, A.nnz);
+  h2d(s, v32, f32.data(), A.nnz);
+  L.a64 = CsrView<double>{ptr, col, v64};
+  L.a32 = CsrView<float>{ptr, col, v32};
+  const double avg = double(A.nnz) / n;
+  L.csr_lanes = avg <= 12.0 ? 4 : (avg <= 40.0 ? 8 : 16);
+  L.val = dalloc<double>(c->owned, n);
+  h2d(s, L.val, diag.data(), n);
+  L.row_lat = dalloc<int32_t>(c->owned, n);
+  h2d(s, L.row_lat, L.h_row_lat.data(), n);
+  L.srow_lat = L.row_lat;
+  L.h_meta.assign(n, 0u);
+  L.meta = dalloc<uint32_t>(c->owned, n);
+  h2d(s, L.meta, L.h_meta.data(), n);
+  L.n_uniform = 0;
+  HIP_CHECK_RET(hipStreamSynchronize(s));
+  alloc_level_vectors(c, L);
+}
+
 void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice &lat) {
   hipStream_t s = c->stream;
+  if (!lat.dof_to_lattice) {
+    setup_csr_level(c, L, A);
+    return;
+  }
   if (lat.dim < 2 || lat.dim > 3) bad("lattice dim must be 2 or 3");
   if (lat.reach < 1 || (lat.dim == 3 && lat.reach > 2) || lat.reach > 5) bad("lattice reach must be 1..5 (2D) or 1..2 (3D)");
   if (A.nrows <= 0 || A.nrows != A.ncols) bad("A must be square and non-empty");
@@ -609,7 +690,13 @@ void setup_level(imsmg_ctx *c, Level &L, const imsmg_csr &A, const imsmg_lattice
     h2d(s, L.meta, L.h_meta.data(), L.n);
     HIP_CHECK_RET(hipStreamSynchronize(s));
   }
-  const size_t vlen = size_t(nc * L.cstride);
+  alloc_level_vectors(c, L);
+}
+
+// the level's padded work vectors (x, x2 ping-pong, r, rh; W-cycle copies)
+void alloc_level_vectors(imsmg_ctx *c, Level &L) {
+  hipStream_t s = c->stream;
+  const size_t vlen = size_t(L.ncomp * L.cstride);
   double *vs[4];
   for (int k = 0; k < 4; ++k) {
     double *b = dalloc<double>(c->owned, vlen);
@@ -876,7 +963,12 @@ void residual(imsmg_ctx *c, Level &L, const double *x, const double *b, double *
               bool timed) {
   hipEvent_t *ev = timed ? timed_pair(c) : nullptr;
   if (ev) HIP_CHECK_RET(hipEventRecord(ev[0], c->stream));
-  if (L.ncomp > 1) {
+  if (L.csr) {
+    if (mixed(c))
+      launch_csr_residual(c->stream, L.n, L.csr_lanes, L.a32, L.meta, x, b, y, done);
+    else
+      launch_csr_residual(c->stream, L.n, L.csr_lanes, L.a64, L.meta, x, b, y, done);
+  } else if (L.ncomp > 1) {
     if (mixed(c))
       launch_vresidual(c->stream, L.K, L.vops32, L.meta, x, b, y, done);
     else
@@ -898,7 +990,13 @@ void smooth_step(imsmg_ctx *c, Level &L, const double *xa, double *xb, const int
   // timed: opt.timing identical launches (xa and r are only read)
   const int reps = ev ? c->opt.timing : 1;
   for (int k = 0; k < reps; ++k) {
-    if (L.ncomp > 1) {
+    if (L.csr) {
+      if (pv) bad("internal: fused prolongation on a general sparse level", IMSMG_ERR_HIP);
+      if (mixed(c))
+        launch_csr_residual_smooth(c->stream, L.n, L.csr_lanes, L.a32, L.meta, L.c, xa, L.r, L.rh, xb, done);
+      else
+        launch_csr_residual_smooth(c->stream, L.n, L.csr_lanes, L.a64, L.meta, L.c, xa, L.r, L.rh, xb, done);
+    } else if (L.ncomp > 1) {
       if (pv) bad("internal: fused prolongation on a vector level", IMSMG_ERR_HIP);
       if (mixed(c))
         launch_vresidual_smooth(c->stream, L.K, L.vops32, L.meta, L.c, xa, L.r, L.rh, xb, done);
@@ -1293,9 +1391,12 @@ void factor_level(imsmg_ctx *c, int l) {
   h2d(s, d_blat, h_blat.data(), h_blat.size());
   h2d(s, d_brow, h_brow.data(), h_brow.size());
   h2d(s, d_invoff, h_invoff.data(), nf + 1);
-  if (launch_block_factor_geom(s, nf, maxn, d_bstart, d_bsize, d_blat, d_brow, n, L.dim, L.shape[0], L.shape[1],
-                               L.reach, L.val, d_inv, d_invoff, d_keep, d_lam, d_info, 1e-16) != 0)
-    bad("block factorization launch rejected");
+  const int frc = L.csr ? launch_block_factor_csr(s, nf, maxn, d_bstart, d_bsize, d_brow, L.a64, d_inv, d_invoff,
+                                                  d_keep, d_lam, d_info, 1e-16)
+                       : launch_block_factor_geom(s, nf, maxn, d_bstart, d_bsize, d_blat, d_brow, n, L.dim,
+                                                  L.shape[0], L.shape[1], L.reach, L.val, d_inv, d_invoff, d_keep,
+                                                  d_lam, d_info, 1e-16);
+  if (frc != 0) bad("block factorization launch rejected");
   HIP_CHECK_RET(hipGetLastError());
   std::vector<uint8_t> keep(h_blat.size());
   std::vector<int32_t> info(nf);
@@ -1798,7 +1899,9 @@ void apply_S(imsmg_ctx *c, Level &L, const double *x, double *y) {
 
 // y = A x on level L in FP64 (y, x padded)
 void apply_A64(imsmg_ctx *c, Level &L, const double *x, double *y) {
-  if (L.ncomp > 1)
+  if (L.csr)
+    launch_csr_residual(c->stream, L.n, L.csr_lanes, L.a64, L.meta, x, nullptr, y, c->zero_flag);
+  else if (L.ncomp > 1)
     launch_vresidual(c->stream, L.K, L.vops64, L.meta, x, nullptr, y, c->zero_flag);
   else
     launch_residual(c->stream, L.n, L.K, L.op64, L.row_lat, L.meta, x, nullptr, y, c->zero_flag);
@@ -2048,6 +2151,12 @@ void factor_coarsest(imsmg_ctx *c) {
   if (L.ncomp > 1) {
     // vector level: the dense operator kept at setup (every component pair)
     HIP_CHECK_RET(hipMemcpyAsync(L.Ainv, L.dense0, size_t(n) * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else if (L.csr) {
+    std::vector<double> D(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int k = L.h_aptr[i]; k < L.h_aptr[i + 1]; ++k) D[size_t(i) * n + L.h_acol[k]] = L.h_aval[k];
+    h2d(s, L.Ainv, D.data(), D.size());
+    HIP_CHECK_RET(hipStreamSynchronize(s));
   } else {
     std::vector<int32_t> lat2c(size_t(L.lattice + 2 * L.guard), -1);
     for (int i = 0; i < n; ++i) lat2c[size_t(L.h_row_lat[i] + L.guard)] = i;
@@ -2102,6 +2211,7 @@ void free_multi(imsmg_ctx *c) {
 
 void ensure_multi(imsmg_ctx *c, int R) {
   if (c->lv.back().ncomp > 1) bad("vector problems: the multi-column form is not supported");
+  if (c->lv.back().csr) bad("general sparse levels: the multi-column form is not supported");
   if (c->mb.R == R) return;
   free_multi(c);
   hipStream_t s = c->stream;
@@ -2221,7 +2331,9 @@ void cg_iteration(imsmg_ctx *c, bool timing) {
   vcycle_level(c, int(c->lv.size()) - 1, done, timing);
   launch_cg_dot_rz(c->stream, F.n, F.row_lat, F.r, F.x, c->part, c->st, c->opt.flexible_cg);
   launch_cg_direction(c->stream, F.n, F.row_lat, F.x, c->p, c->st);
-  if (F.ncomp > 1)
+  if (F.csr)
+    launch_csr_cg_spmv_pq(c->stream, F.n, F.csr_lanes, F.a64, c->p, c->q, c->part, c->st);
+  else if (F.ncomp > 1)
     launch_vcg_spmv_pq(c->stream, F.K, F.vops64, F.meta, c->p, c->q, c->part, c->st);
   else
     launch_cg_spmv_pq(c->stream, F.n, F.K, F.op64, F.row_lat, F.meta, c->p, c->q, c->part, c->st);
@@ -2256,7 +2368,9 @@ int pcg_solve_core(imsmg_ctx *c, const double *b_dev, double *x_dev, double rtol
     CGState h{};
     int restarts = 0;
     while (true) {
-      if (F.ncomp > 1)
+      if (F.csr)
+        launch_csr_cg_init(s, F.n, F.csr_lanes, F.a64, c->xs, c->bs, F.r, c->part, c->st, rtol, restarts > 0);
+      else if (F.ncomp > 1)
         launch_vcg_init(s, F.K, F.vops64, F.meta, c->xs, c->bs, F.r, c->part, c->st, rtol, restarts > 0);
       else
         launch_cg_init(s, F.n, F.K, F.op64, F.row_lat, F.meta, c->xs, c->bs, F.r, c->part, c->st, rtol,
@@ -2288,7 +2402,9 @@ int pcg_solve_core(imsmg_ctx *c, const double *b_dev, double *x_dev, double rtol
         if (h.done) break;
       }
       // true residual ||b - A x|| / ||b||
-      if (F.ncomp > 1)
+      if (F.csr)
+        launch_csr_cg_true_residual(s, F.n, F.csr_lanes, F.a64, c->xs, c->bs, c->part, c->st);
+      else if (F.ncomp > 1)
         launch_vcg_true_residual(s, F.K, F.vops64, F.meta, c->xs, c->bs, c->part, c->st);
       else
         launch_cg_true_residual(s, F.n, F.K, F.op64, F.row_lat, F.meta, c->xs, c->bs, c->part, c->st);
@@ -2408,9 +2524,21 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
       if (c->opt.use_learned) bad("vector problems: learned weights are not supported");
       if (c->opt.block_gemm) bad("vector problems: block_gemm is not supported");
     }
+    int ncsr = 0;
+    for (int l = 0; l < nlevels; ++l) ncsr += Lt[l].dof_to_lattice == nullptr;
+    if (ncsr) {
+      // general sparse levels (no function lattice)
+      if (ncsr != nlevels) bad("either every level has a function lattice or none has");
+      if (c->opt.smoother == IMSMG_MULTIPLICATIVE || c->opt.coarse_smoother == IMSMG_MULTIPLICATIVE)
+        bad("general sparse levels: the multiplicative smoother is not supported");
+      if (c->opt.use_learned) bad("general sparse levels: learned weights are not supported");
+      if (c->opt.block_gemm) bad("general sparse levels: block_gemm is not supported");
+      for (int l = 1; l < nlevels; ++l)
+        if (Lt[l].two_scale) bad("general sparse levels take R as CSR only (no two_scale)");
+    }
     c->lv.resize(nlevels);
     for (int l = 0; l < nlevels; ++l) {
-      if (Lt[l].dim != Lt[nlevels - 1].dim) bad("all levels must share the dimension");
+      if (!ncsr && Lt[l].dim != Lt[nlevels - 1].dim) bad("all levels must share the dimension");
       setup_level(c, c->lv[l], A[l], Lt[l]);
     }
     if (c->opt.ncomp > 1) {
@@ -2493,7 +2621,8 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
     HIP_CHECK_RET(hipMemsetAsync(c->zero_flag, 0, sizeof(int32_t), c->stream));
     c->st = dalloc<CGState>(c->owned, 1);
     HIP_CHECK_RET(hipMemsetAsync(c->st, 0, sizeof(CGState), c->stream));
-    c->part = dalloc<double>(c->owned, 2 * size_t(std::max(reduction_blocks(F.n), F.op64.ntiles * F.ncomp)) + 64);
+    c->part = dalloc<double>(c->owned, 2 * size_t(std::max({reduction_blocks(F.n), F.op64.ntiles * F.ncomp,
+                                                               F.csr ? csr_part_blocks(F.n, F.csr_lanes) : 0})) + 64);
     HIP_CHECK_RET(hipStreamSynchronize(c->stream));
     c->ready = true;
     c->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_setup0).count();
@@ -2753,7 +2882,7 @@ int imsmg_get_level_stats(imsmg_ctx *c, int level, imsmg_level_stats *st) {
     if (level < 0 || level >= int(c->lv.size()) || !st) bad("bad level");
     const Level &L = c->lv[level];
     st->n = L.n;
-    st->stencil = L.K;
+    st->stencil = L.csr ? 0 : L.K;  // 0: general sparse level (CSR rows)
     st->stored_rows = L.n - L.n_uniform;
     st->general_rows = L.ng;
     st->sg_nnz = 0;

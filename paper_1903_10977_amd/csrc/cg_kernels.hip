@@ -11,6 +11,7 @@
 // returns at once.
 #include <stdexcept>
 
+#include "csr_row.h"
 #include "imsmg_internal.h"
 #include "op_row.h"
 #include "vec_row.h"
@@ -361,6 +362,74 @@ __global__ __launch_bounds__(kRedThreads, kTileBlocksPerCU) void k_vcg_true_resi
   if (threadIdx.x == 0) part[c * gridDim.x + blk] = acc;
 }
 
+// General sparse finest level (csr_row.h): LN lanes per CSR row, partial
+// sums per workgroup in workgroup order.
+template <int LN>
+__global__ __launch_bounds__(kRedThreads) void k_csr_cg_init(int n, CsrView<double> A, const double *__restrict__ x,
+                                                             const double *__restrict__ b, double *__restrict__ r,
+                                                             double *__restrict__ part) {
+  __shared__ double lds[kRedThreads];
+  const double2 s = csr_rows<LN, double, InitEpi>(n, A, nullptr, x, InitEpi{b, r});
+  const double rr = block_sum<kRedThreads>(s.x, lds);
+  const double bb = block_sum<kRedThreads>(s.y, lds);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = rr;
+    part[gridDim.x + blockIdx.x] = bb;
+  }
+}
+
+template <int LN>
+__global__ __launch_bounds__(kRedThreads) void k_csr_cg_spmv_pq(int n, CsrView<double> A,
+                                                                const double *__restrict__ p, double *__restrict__ q,
+                                                                double *__restrict__ part, const CGState *st) {
+  __shared__ double lds[kRedThreads];
+  if (st->done) return;  // uniform: the flag does not change during the kernel
+  const double acc = block_sum<kRedThreads>(csr_rows<LN, double, SpmvEpi>(n, A, nullptr, p, SpmvEpi{q}).x, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+template <int LN>
+__global__ __launch_bounds__(kRedThreads) void k_csr_cg_true_residual(int n, CsrView<double> A,
+                                                                      const double *__restrict__ x,
+                                                                      const double *__restrict__ b,
+                                                                      double *__restrict__ part) {
+  __shared__ double lds[kRedThreads];
+  const double acc = block_sum<kRedThreads>(csr_rows<LN, double, TrueResEpi>(n, A, nullptr, x, TrueResEpi{b}).x, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+int csr_part_blocks(int n, int ln) { return csr_grid(n, ln); }
+
+#define IMSMG_CSR_CG(KERNEL, ...)                                                      \
+  switch (ln) {                                                                        \
+    case 4: KERNEL<4><<<g, kRedThreads, 0, s>>>(__VA_ARGS__); break;                   \
+    case 8: KERNEL<8><<<g, kRedThreads, 0, s>>>(__VA_ARGS__); break;                   \
+    case 16: KERNEL<16><<<g, kRedThreads, 0, s>>>(__VA_ARGS__); break;                 \
+    default: throw std::invalid_argument("CSR rows: 4, 8 or 16 lanes per row");       \
+  }
+
+void launch_csr_cg_init(hipStream_t s, int n, int ln, const CsrView<double> &A, const double *x, const double *b,
+                        double *r, double *part, CGState *st, double rtol, int restart) {
+  const int g = csr_grid(n, ln);
+  IMSMG_CSR_CG(k_csr_cg_init, n, A, x, b, r, part)
+  k_cg_init_fin<<<1, kFinThreads, 0, s>>>(g, part, st, rtol, restart);
+}
+
+void launch_csr_cg_spmv_pq(hipStream_t s, int n, int ln, const CsrView<double> &A, const double *p, double *q,
+                           double *part, CGState *st) {
+  const int g = csr_grid(n, ln);
+  IMSMG_CSR_CG(k_csr_cg_spmv_pq, n, A, p, q, part, st)
+  k_cg_pq_fin<<<1, kFinThreads, 0, s>>>(g, part, st);
+}
+
+void launch_csr_cg_true_residual(hipStream_t s, int n, int ln, const CsrView<double> &A, const double *x,
+                                 const double *b, double *part, CGState *st) {
+  const int g = csr_grid(n, ln);
+  IMSMG_CSR_CG(k_csr_cg_true_residual, n, A, x, b, part)
+  k_cg_aux_fin<<<1, kFinThreads, 0, s>>>(g, part, st);
+}
+#undef IMSMG_CSR_CG
+
 #define IMSMG_DISPATCH_V(K, KERNEL, ...)                                                 \
   do {                                                                                   \
     const dim3 g2(ops.ntiles, ops.ncomp);                                                \
@@ -409,6 +478,7 @@ void launch_vcg_true_residual(hipStream_t s, int K, const VecOps<double> &ops, c
 void launch_cg_init(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                     const uint32_t *meta, const double *x, const double *b, double *r, double *part, CGState *st,
                     double rtol, int restart) {
+  require_lattice_op(op);
   const int g = stencil_grid(K, n, op);
   IMSMG_DISPATCH_K(K, k_cg_init, n, K, op, row_lat, meta, x, b, r, part);
   k_cg_init_fin<<<1, kFinThreads, 0, s>>>(g, part, st, rtol, restart);
@@ -427,6 +497,7 @@ void launch_cg_direction(hipStream_t s, int n, const int32_t *row_lat, const dou
 
 void launch_cg_spmv_pq(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                        const uint32_t *meta, const double *p, double *q, double *part, CGState *st) {
+  require_lattice_op(op);
   const int g = stencil_grid(K, n, op);
   IMSMG_DISPATCH_K(K, k_cg_spmv_pq, n, K, op, row_lat, meta, p, q, part, st);
   k_cg_pq_fin<<<1, kFinThreads, 0, s>>>(g, part, st);
@@ -445,6 +516,7 @@ void launch_cg_update(hipStream_t s, int n, const int32_t *row_lat, const double
 
 void launch_cg_true_residual(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                              const uint32_t *meta, const double *x, const double *b, double *part, CGState *st) {
+  require_lattice_op(op);
   const int g = stencil_grid(K, n, op);
   IMSMG_DISPATCH_K(K, k_cg_true_residual, n, K, op, row_lat, meta, x, b, part);
   k_cg_aux_fin<<<1, kFinThreads, 0, s>>>(g, part, st);

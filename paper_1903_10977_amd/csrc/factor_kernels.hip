@@ -3,7 +3,8 @@
 //
 // Block factorization (smoothers subsection, additive Schwarz and the remark
 // on eigenvalues of the order of machine precision): one workgroup per block
-// gathers A_j = P_j^T A P_j from the lattice-ELL operator into LDS and runs a
+// gathers A_j = P_j^T A P_j from the lattice-ELL operator (or, on general
+// sparse levels, from the CSR operator) into LDS and runs a
 // cyclic two-sided Jacobi eigensolver with the round-robin parallel ordering
 // (n/2 disjoint rotations per step, rows then columns, eigenvectors
 // accumulated alongside).  Jacobi with the relative off-diagonal test keeps
@@ -36,10 +37,36 @@ __device__ __forceinline__ int slot_of(const LatticeGeom &g, int la, int lb) {
   return (dy + g.reach) * g.W + (dx + g.reach);
 }
 
+// A_ab of a block from the lattice-ELL operator (members' rows and lattice
+// points) or from a CSR operator (members' rows; binary search in the row)
+struct LatticeGather {
+  LatticeGeom geom;
+  const double *__restrict__ val;
+  int n;
+  __device__ double operator()(int ra, int la, int, int lb) const {
+    const int s = slot_of(geom, la, lb);
+    return s >= 0 ? val[size_t(s) * n + ra] : 0.0;
+  }
+};
+
+struct CsrGather {
+  CsrView<double> A;
+  __device__ double operator()(int ra, int, int rb, int) const {
+    int lo = A.ptr[ra], hi = A.ptr[ra + 1];
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (A.col[mid] < rb) lo = mid + 1;
+      else hi = mid;
+    }
+    return (lo < A.ptr[ra + 1] && A.col[lo] == rb) ? A.val[lo] : 0.0;
+  }
+};
+
+template <typename Gather>
 __global__ __launch_bounds__(kFacThreads) void k_block_factor(
     int nblocks, const int32_t *__restrict__ bstart, const int32_t *__restrict__ bsize,
-    const int32_t *__restrict__ blat, const int32_t *__restrict__ brow, int n, LatticeGeom geom,
-    const double *__restrict__ val, double *__restrict__ inv_out, const int64_t *__restrict__ inv_off,
+    const int32_t *__restrict__ blat, const int32_t *__restrict__ brow, Gather gather,
+    double *__restrict__ inv_out, const int64_t *__restrict__ inv_off,
     uint8_t *__restrict__ keep_out, double *__restrict__ lam_out, int32_t *__restrict__ info_out, double ratio,
     int maxn) {
   const int j = blockIdx.x;
@@ -71,11 +98,9 @@ __global__ __launch_bounds__(kFacThreads) void k_block_factor(
     // gather A_j for the kept indices
     for (int e = tid; e < m * m; e += kFacThreads) {
       const int a = e % m, b = e / m;
-      const int ra = brow[st + keep_idx[a]];
-      const int la = blat[st + keep_idx[a]];
-      const int lb = blat[st + keep_idx[b]];
-      const int s = slot_of(geom, la, lb);
-      A[a * maxn + b] = s >= 0 ? val[size_t(s) * n + ra] : 0.0;
+      const int ra = brow[st + keep_idx[a]], rb = brow[st + keep_idx[b]];
+      const int la = blat[st + keep_idx[a]], lb = blat[st + keep_idx[b]];
+      A[a * maxn + b] = gather(ra, la, rb, lb);
       V[a * maxn + b] = (a == b) ? 1.0 : 0.0;
     }
     __syncthreads();
@@ -204,9 +229,20 @@ int launch_block_factor_geom(hipStream_t s, int nblocks, int maxn, const int32_t
                              double *lam_out, int32_t *info_out, double ratio) {
   if (nblocks <= 0) return 0;
   if (maxn > IMSMG_MAX_BLOCK) return -1;
-  LatticeGeom g{dim, nx, ny, reach, 2 * reach + 1};
+  const LatticeGather g{LatticeGeom{dim, nx, ny, reach, 2 * reach + 1}, val, n};
   const size_t shmem = (size_t(2) * maxn * maxn + 2 * (maxn / 2 + 1)) * sizeof(double);
-  k_block_factor<<<nblocks, kFacThreads, shmem, s>>>(nblocks, bstart, bsize, blat, brow, n, g, val, inv_out,
+  k_block_factor<<<nblocks, kFacThreads, shmem, s>>>(nblocks, bstart, bsize, blat, brow, g, inv_out, inv_off,
+                                                     keep_out, lam_out, info_out, ratio, maxn);
+  return 0;
+}
+
+int launch_block_factor_csr(hipStream_t s, int nblocks, int maxn, const int32_t *bstart, const int32_t *bsize,
+                            const int32_t *brow, const CsrView<double> &A, double *inv_out, const int64_t *inv_off,
+                            uint8_t *keep_out, double *lam_out, int32_t *info_out, double ratio) {
+  if (nblocks <= 0) return 0;
+  if (maxn > IMSMG_MAX_BLOCK) return -1;
+  const size_t shmem = (size_t(2) * maxn * maxn + 2 * (maxn / 2 + 1)) * sizeof(double);
+  k_block_factor<<<nblocks, kFacThreads, shmem, s>>>(nblocks, bstart, bsize, brow, brow, CsrGather{A}, inv_out,
                                                      inv_off, keep_out, lam_out, info_out, ratio, maxn);
   return 0;
 }

@@ -15,6 +15,7 @@
 //     x_i += c_i r_i inside the residual kernel; general rows apply rows of
 //     omega_j A_j^{-1} (stored contiguously, FP64) to the block residuals.
 #pragma once
+#include <stdexcept>
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -40,6 +41,15 @@ constexpr uint32_t kMetaGeneral = 0x40000000u;  // row belongs to a general Schw
 
 struct Offsets {
   int32_t off[IMSMG_MAX_SLOTS];
+};
+
+// Operator of a general sparse level (no function lattice): CSR with sorted
+// columns; vectors of such a level are indexed by row.
+template <typename V>
+struct CsrView {
+  const int32_t *ptr;
+  const int32_t *col;
+  const V *val;
 };
 
 template <typename V>
@@ -181,6 +191,14 @@ struct MState {
   int32_t pad;
 };
 
+// The lattice kernels read the stored values and the reference stencil of an
+// OpView; a level without them (a general sparse level, or the FP32 view of
+// an FP64 setup) must never reach those kernels.
+template <typename V>
+inline void require_lattice_op(const OpView<V> &op) {
+  if (!op.val || !op.ref) throw std::invalid_argument("lattice kernel launched without a lattice operator");
+}
+
 // --------------------------------------------------------------- level kernels
 void launch_residual(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                      const uint32_t *meta, const double *x, const double *b, double *y, const int32_t *done);
@@ -194,6 +212,19 @@ void launch_residual_smooth(hipStream_t s, int n, int K, const OpView<double> &o
 void launch_residual_smooth(hipStream_t s, int n, int K, const OpView<float> &op, const int32_t *row_lat,
                             const uint32_t *meta, const double *c, const double *xa, const double *r, double *rh,
                             double *xb, const int32_t *done, const ProlongView *pv = nullptr);
+// general sparse levels (CSR operator, ln lanes per row: 4, 8 or 16):
+// y = b - A x (b == nullptr: y = A x) and the smoothing step with the same
+// contract as launch_residual_smooth (no fused prolongation)
+void launch_csr_residual(hipStream_t s, int n, int ln, const CsrView<double> &A, const uint32_t *meta,
+                         const double *x, const double *b, double *y, const int32_t *done);
+void launch_csr_residual(hipStream_t s, int n, int ln, const CsrView<float> &A, const uint32_t *meta,
+                         const double *x, const double *b, double *y, const int32_t *done);
+void launch_csr_residual_smooth(hipStream_t s, int n, int ln, const CsrView<double> &A, const uint32_t *meta,
+                                const double *c, const double *xa, const double *r, double *rh, double *xb,
+                                const int32_t *done);
+void launch_csr_residual_smooth(hipStream_t s, int n, int ln, const CsrView<float> &A, const uint32_t *meta,
+                                const double *c, const double *xa, const double *r, double *rh, double *xb,
+                                const int32_t *done);
 // general Schwarz rows: x[grow_lat[t]] += sum_k S[t,k] r[scol[k]]  (S_G in CSR, lattice columns)
 // vector levels: y = b - A x (b == nullptr: y = A x) and the smoothing step
 // (rh = r - A xa on general rows, xb = xa + c (r - A xa)), per component;
@@ -276,6 +307,15 @@ void launch_cg_update(hipStream_t s, int n, const int32_t *row_lat, const double
 void launch_cg_true_residual(hipStream_t s, int n, int K, const OpView<double> &op, const int32_t *row_lat,
                              const uint32_t *meta, const double *x, const double *b, double *part, CGState *st);
 int reduction_blocks(int n);
+// CG on a general sparse finest level (CSR operator, ln lanes per row);
+// partial sums per workgroup as the lattice forms (csr_part_blocks of them)
+int csr_part_blocks(int n, int ln);
+void launch_csr_cg_init(hipStream_t s, int n, int ln, const CsrView<double> &A, const double *x, const double *b,
+                        double *r, double *part, CGState *st, double rtol, int restart);
+void launch_csr_cg_spmv_pq(hipStream_t s, int n, int ln, const CsrView<double> &A, const double *p, double *q,
+                           double *part, CGState *st);
+void launch_csr_cg_true_residual(hipStream_t s, int n, int ln, const CsrView<double> &A, const double *x,
+                                 const double *b, double *part, CGState *st);
 
 // --------------------------------------------------------------- multi-RHS (R = 4, 8, 16 interleaved columns)
 bool multi_supported(int R);
@@ -358,6 +398,11 @@ int launch_block_factor_geom(hipStream_t s, int nblocks, int maxn, const int32_t
                              const int32_t *blat, const int32_t *brow, int n, int dim, int nx, int ny, int reach,
                              const double *val, double *inv_out, const int64_t *inv_off, uint8_t *keep_out,
                              double *lam_out, int32_t *info_out, double ratio);
+// the same factorization gathering A_j from a CSR operator (general sparse
+// levels: brow are the members' rows, columns sorted)
+int launch_block_factor_csr(hipStream_t s, int nblocks, int maxn, const int32_t *bstart, const int32_t *bsize,
+                            const int32_t *brow, const CsrView<double> &A, double *inv_out, const int64_t *inv_off,
+                            uint8_t *keep_out, double *lam_out, int32_t *info_out, double ratio);
 void launch_gauss_jordan_step(hipStream_t s, int n, int k, double *A, double *colk, double *rowk,
                               int32_t *bad_pivot);
 void launch_dense_from_ell(hipStream_t s, int n, int K, const Offsets &off, const int32_t *row_lat,

@@ -24,6 +24,7 @@
 #include <stdexcept>
 
 #include "imsmg_internal.h"
+#include "csr_row.h"
 #include "op_row.h"
 #include "vec_row.h"
 
@@ -110,6 +111,7 @@ template <typename V>
 static void dispatch_residual(hipStream_t s, int n, int K, const OpView<V> &op, const int32_t *row_lat,
                               const uint32_t *meta, const double *x, const double *b, double *y, const int32_t *done) {
   if (n <= 0) return;
+  require_lattice_op(op);
   dim3 g(stencil_grid(K, n, op)), t(kRowBlock);
 #define IMSMG_R(KK)                                                                  \
   if (op.stream)                                                                     \
@@ -132,6 +134,7 @@ static void dispatch_residual_smooth(hipStream_t s, int n, int K, const OpView<V
                                      const uint32_t *meta, const double *c, const double *xa, const double *r,
                                      double *rh, double *xb, const int32_t *done, const ProlongView *pv) {
   if (n <= 0) return;
+  require_lattice_op(op);
   dim3 g(stencil_grid(K, n, op)), t(kRowBlock);
   const ProlongView p = pv ? *pv : ProlongView{};
 #define IMSMG_RS(KK)                                                                                         \
@@ -179,6 +182,67 @@ void launch_residual_smooth(hipStream_t s, int n, int K, const OpView<float> &op
                             const uint32_t *meta, const double *c, const double *xa, const double *r, double *rh,
                             double *xb, const int32_t *done, const ProlongView *pv) {
   dispatch_residual_smooth<float>(s, n, K, op, row_lat, meta, c, xa, r, rh, xb, done, pv);
+}
+
+// General sparse levels (csr_row.h): LN lanes per CSR row, the lattice
+// kernels' epilogues at row positions.
+template <int LN, typename V>
+__global__ __launch_bounds__(kRowBlock) void k_csr_residual(int n, CsrView<V> A, const uint32_t *__restrict__ meta,
+                                                            const double *__restrict__ x,
+                                                            const double *__restrict__ b, double *__restrict__ y,
+                                                            const int32_t *__restrict__ done) {
+  csr_rows<LN, V, ResidualEpi>(n, A, meta, x, ResidualEpi{b, y}, done);
+}
+
+template <int LN, typename V>
+__global__ __launch_bounds__(kRowBlock) void k_csr_residual_smooth(int n, CsrView<V> A,
+                                                                   const uint32_t *__restrict__ meta,
+                                                                   const double *__restrict__ c,
+                                                                   const double *__restrict__ xa,
+                                                                   const double *__restrict__ r,
+                                                                   double *__restrict__ rh, double *__restrict__ xb,
+                                                                   const int32_t *__restrict__ done) {
+  csr_rows<LN, V, SmoothEpi>(n, A, meta, xa, SmoothEpi{r, c, rh, xb}, done);
+}
+
+#define IMSMG_CSR_LN(LN_, KERNEL, ...)                                         \
+  switch (LN_) {                                                               \
+    case 4: KERNEL<4, V><<<csr_grid(n, 4), kRowBlock, 0, s>>>(__VA_ARGS__); break;   \
+    case 8: KERNEL<8, V><<<csr_grid(n, 8), kRowBlock, 0, s>>>(__VA_ARGS__); break;   \
+    case 16: KERNEL<16, V><<<csr_grid(n, 16), kRowBlock, 0, s>>>(__VA_ARGS__); break; \
+    default: throw std::invalid_argument("CSR rows: 4, 8 or 16 lanes per row");      \
+  }
+
+template <typename V>
+static void csr_residual(hipStream_t s, int n, int ln, const CsrView<V> &A, const uint32_t *meta, const double *x,
+                         const double *b, double *y, const int32_t *done) {
+  if (n > 0) IMSMG_CSR_LN(ln, k_csr_residual, n, A, meta, x, b, y, done)
+}
+template <typename V>
+static void csr_residual_smooth(hipStream_t s, int n, int ln, const CsrView<V> &A, const uint32_t *meta,
+                                const double *c, const double *xa, const double *r, double *rh, double *xb,
+                                const int32_t *done) {
+  if (n > 0) IMSMG_CSR_LN(ln, k_csr_residual_smooth, n, A, meta, c, xa, r, rh, xb, done)
+}
+#undef IMSMG_CSR_LN
+
+void launch_csr_residual(hipStream_t s, int n, int ln, const CsrView<double> &A, const uint32_t *meta,
+                         const double *x, const double *b, double *y, const int32_t *done) {
+  csr_residual<double>(s, n, ln, A, meta, x, b, y, done);
+}
+void launch_csr_residual(hipStream_t s, int n, int ln, const CsrView<float> &A, const uint32_t *meta,
+                         const double *x, const double *b, double *y, const int32_t *done) {
+  csr_residual<float>(s, n, ln, A, meta, x, b, y, done);
+}
+void launch_csr_residual_smooth(hipStream_t s, int n, int ln, const CsrView<double> &A, const uint32_t *meta,
+                                const double *c, const double *xa, const double *r, double *rh, double *xb,
+                                const int32_t *done) {
+  csr_residual_smooth<double>(s, n, ln, A, meta, c, xa, r, rh, xb, done);
+}
+void launch_csr_residual_smooth(hipStream_t s, int n, int ln, const CsrView<float> &A, const uint32_t *meta,
+                                const double *c, const double *xa, const double *r, double *rh, double *xb,
+                                const int32_t *done) {
+  csr_residual_smooth<float>(s, n, ln, A, meta, c, xa, r, rh, xb, done);
 }
 
 // Vector levels (vec_row.h): one workgroup per (lattice tile, output

@@ -213,14 +213,18 @@ def problem_structs(problem, dim: int = None, reach: int = None, implicit_transf
         rp, ci, va = _i32(lev.A.indptr), _i32(lev.A.indices), np.ascontiguousarray(lev.A.data, np.float64)
         keep += [rp, ci, va]
         A[l] = Csr(lev.A.shape[0], lev.A.shape[1], lev.A.nnz, _p(rp).value, _p(ci).value, _p(va).value)
-        d2l = _i32(lev.dof_to_lattice)
-        keep.append(d2l)
-        shp = (C.c_int32 * 3)(*(list(lev.lattice) + [1] * (3 - len(lev.lattice))))
-        ts = None
-        if implicit_transfer and l > 0 and getattr(lev, "two_scale", None) is not None:
-            ts = np.ascontiguousarray(lev.two_scale, dtype=np.float64)
-            keep.append(ts)
-        Lt[l] = Lattice(dim, shp, reach, _p(d2l).value, _p(ts).value if ts is not None else None)
+        if lev.dof_to_lattice is None:
+            # general sparse level (locally refined basis): no function lattice
+            Lt[l] = Lattice(0, (C.c_int32 * 3)(lev.A.shape[0], 1, 1), 0, None, None)
+        else:
+            d2l = _i32(lev.dof_to_lattice)
+            keep.append(d2l)
+            shp = (C.c_int32 * 3)(*(list(lev.lattice) + [1] * (3 - len(lev.lattice))))
+            ts = None
+            if implicit_transfer and l > 0 and getattr(lev, "two_scale", None) is not None:
+                ts = np.ascontiguousarray(lev.two_scale, dtype=np.float64)
+                keep.append(ts)
+            Lt[l] = Lattice(dim, shp, reach, _p(d2l).value, _p(ts).value if ts is not None else None)
         if l > 0:
             Rm = lev.R
             rrp, rci, rva = _i32(Rm.indptr), _i32(Rm.indices), np.ascontiguousarray(Rm.data, np.float64)

@@ -27,8 +27,9 @@ Construction (2D, degree p):
 * restriction: rows of R with C_coarse = R C_fine; a coarse function that is
   an untruncated B-spline whose two-scale children are all untruncated fine
   functions takes the two-scale coefficients, any other one a least-squares
-  solve over the fine functions that share grid coefficients with it,
-  accepted only when it reproduces the coarse row to 1e-12;
+  solve (normal equations, else an orthogonal solve) over the fine functions
+  that share grid coefficients with it, accepted only when it reproduces the
+  coarse row to 1e-12;
 * blocks: E(k) = elements meeting Omega on which phi_k is non-zero; block of
   phi_j = {phi_k : E(k) within E(j)}; coarse operators R A R^T.
 Numbering on every level: by level m, then lattice index of the level (x
@@ -219,7 +220,15 @@ def _restriction_rows(cs: Space, fs: Space, p: int) -> sp.csr_matrix:
             cols = np.union1d(sub.indices, target.indices)
             Ms = sub[:, cols].toarray()
             tv = target[:, cols].toarray().ravel()
-            x, *_ = np.linalg.lstsq(Ms.T, tv, rcond=None)
+            # normal equations of the (consistent) system Ms^T x = tv: the
+            # grid-coefficient rows of neighbouring functions are far from
+            # dependent, and the exactness check below guards the result
+            try:
+                x = np.linalg.solve(Ms @ Ms.T, Ms @ tv)
+            except np.linalg.LinAlgError:
+                x, *_ = np.linalg.lstsq(Ms.T, tv, rcond=None)
+            if np.abs(Ms.T @ x - tv).max() > 1e-12:
+                x, *_ = np.linalg.lstsq(Ms.T, tv, rcond=None)
             if np.abs(Ms.T @ x - tv).max() <= 1e-12:
                 x[np.abs(x) < 1e-13] = 0.0
                 for k, v in zip(cand, x):

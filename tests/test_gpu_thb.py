@@ -1,0 +1,246 @@
+"""Truncated hierarchical B-splines (Figure fig:THB) with the hierarchical
+coarsening of Algorithm alg:coarsen through the C-ABI: the library runs these
+levels as general sparse levels (CSR operator, no function lattice).  Against
+the THB oracle (oracle/thb.py), with the bars of the scalar parity tests:
+
+* every level's operator (FP64 within 1e-13 relative; FP32 level values
+  within 2^-24 |A| |x| per row), restriction and prolongation within 1e-13;
+* block lists after the tiny-eigenvalue removal equal to the oracle's
+  (except where the removal is decided inside the rounding band of the
+  1e-16 threshold), gamma = 1 / max_K N_K equal; where the lists agree, the
+  smoother on load vectors M u within 1e-6 in L2(Omega) and one V-cycle
+  within 1e-7;
+* PCG to a host-checked true relative residual <= 1e-8, within 1e-6 of the
+  oracle's solution in L2(Omega), bitwise repeatable, and where the block
+  lists agree the oracle's iteration count +-1 (FP64; 5% with FP32 level
+  operators); the same with Jacobi smoothing on the coarser levels;
+* the calls general levels do not support are rejected with INVALID_ARG.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CASES = {
+    "thb-16-m2": lambda: W.thb_discs(n=16, local_levels=2, levels=3),
+    "thb-32-m1": lambda: W.thb_discs(n=32, local_levels=1, levels=3, seed=3),
+    "thb-16-m3": lambda: W.thb_discs(n=16, local_levels=3, levels=2, seed=5),
+    "thb-32-m2": lambda: W.thb_discs(n=32, local_levels=2, levels=4, seed=9),
+}
+
+EPS = 2.0 ** -52
+_cache = {}
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_10977_amd import solver as S
+    S.load()
+    return S
+
+
+def _problem(name, coarse="same"):
+    key = (name, coarse)
+    if key not in _cache:
+        import dataclasses
+        from oracle import thb as T
+        from paper_1903_10977_amd import thb as P
+        w = dataclasses.replace(CASES[name](), coarse_smoother=coarse)
+        print(f"[case {name}/{coarse}] thb n={w.n} local_levels={w.local_levels} levels={w.levels}", flush=True)
+        _cache[key] = (w, P.generate(w), T.build(w))
+    return _cache[key]
+
+
+def _solver(S, g, **opt):
+    w = g.workload
+    o = S.default_options(nu_pre=w.nu, nu_post=w.nu, **opt)
+    return S.Solver(0).setup(g, o).factor()
+
+
+def _t(a):
+    return torch.tensor(np.asarray(a, dtype=np.float64), device="cuda:0")
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _mnorm_rel(e, ref, M):
+    return math.sqrt(max(e @ (M @ e), 0.0)) / math.sqrt(ref @ (M @ ref))
+
+
+def _level_mass(op, l):
+    M = op.hier.M
+    for ll in range(len(op.hier.A) - 1, l, -1):
+        R = op.hier.R[ll - 1]
+        M = R @ M @ R.T
+    return M
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32-operators"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_thb_operators_and_transfers(name, precision):
+    S = _gpu()
+    w, g, op = _problem(name)
+    sol = _solver(S, g, precision=precision)
+    rng = np.random.default_rng(21)
+    for l in range(w.levels):
+        A = op.hier.A[l]
+        x = rng.standard_normal(A.shape[0])
+        y = sol.apply_operator(l, _t(x)).cpu().numpy()
+        if precision == 0:
+            assert _rel(y, A @ x) < 1e-13, (name, l)
+        else:
+            bar = 2.0 ** -24 * (abs(A) @ np.abs(x)) * 1.01 + 1e-300
+            assert np.all(np.abs(y - A @ x) <= bar), (name, l, float(np.max(np.abs(y - A @ x) / bar)))
+        if l > 0:
+            R = op.hier.R[l - 1]
+            rf = rng.standard_normal(R.shape[1])
+            rc = sol.apply_restriction(l, _t(rf)).cpu().numpy()
+            assert _rel(rc, R @ rf) < 1e-13
+            xc = rng.standard_normal(R.shape[0])
+            xf0 = rng.standard_normal(R.shape[1])
+            xf = sol.apply_prolongation(l, _t(xc), _t(xf0)).cpu().numpy()
+            assert _rel(xf, xf0 + R.T @ xc) < 1e-13
+    st = sol.level_stats(w.levels - 1)
+    assert st["stencil"] == 0          # general sparse level
+    print(f"[{name}] fine level stats {st}", flush=True)
+    sol.close()
+
+
+def _removal_band_hit(A, raw):
+    """Does the removal replay on one raw block pass through the rounding
+    band |lambda_min / max diag - 1e-16| <= 4 n eps lambda_max / max diag,
+    where two FP64 eigensolvers may decide differently?"""
+    keep = list(raw)
+    while keep:
+        Aj = A[keep][:, keep].toarray()
+        lam, V = np.linalg.eigh(Aj)
+        dmax = Aj.diagonal().max()
+        ratio = lam[0] / dmax
+        if abs(ratio - 1e-16) <= 4 * len(keep) * EPS * lam[-1] / dmax:
+            return True
+        if ratio >= 1e-16:
+            return False
+        del keep[int(np.argmax(np.abs(V[:, 0])))]
+    return False
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_thb_blocks_gamma_smoother_and_vcycle(name):
+    S = _gpu()
+    w, g, op = _problem(name)
+    sol = _solver(S, g)
+    rng = np.random.default_rng(22)
+    all_equal = True
+    for l in range(1, w.levels):
+        sm = op.smoothers[l]
+        ptr, idx = sol.get_patches(l)
+        gblocks = [idx[ptr[j]:ptr[j + 1]] for j in range(len(ptr) - 1)]
+        oblocks = [np.asarray(b) for b in sm.blocks]
+        nraw = len(sm.raw_blocks)
+        assert len(gblocks) >= nraw and len(oblocks) >= nraw
+        # the given blocks (one per function) first, then singletons for DOFs
+        # the removal left in no block
+        differ = [j for j in range(nraw) if not np.array_equal(gblocks[j], oblocks[j])]
+        A = op.hier.A[l]
+        for j in differ:
+            assert _removal_band_hit(A, np.asarray(sm.raw_blocks[j])), (name, l, j)
+        in_band = set()
+        for j in differ:
+            in_band.update(np.asarray(sm.raw_blocks[j]).tolist())
+        g_added = {int(b[0]) for b in gblocks[nraw:]}
+        o_added = {int(b[0]) for b in oblocks[nraw:]}
+        assert all(len(b) == 1 for b in gblocks[nraw:])
+        assert (g_added ^ o_added) <= in_band, (name, l, sorted(g_added ^ o_added))
+        if g_added != o_added:
+            differ.append(-1)
+        print(f"[{name}] level {l}: {len(differ)} of {len(oblocks)} block lists differ (all in the band); "
+              f"gamma {sm.gamma}", flush=True)
+        if not differ:
+            assert sol.gamma(l) == sm.gamma
+        if differ:
+            all_equal = False
+            continue
+        M = _level_mass(op, l)
+        rm = M @ rng.standard_normal(M.shape[0])
+        ym = sol.apply_smoother(l, _t(rm)).cpu().numpy()
+        refm = sm.apply(rm)
+        d = _mnorm_rel(ym - refm, refm, M)
+        print(f"[{name}] level {l}: smoother L2 rel on M u {d:.2e}", flush=True)
+        assert d <= 1e-6, (name, l, d)
+    if not all_equal:
+        sol.close()
+        return
+    M = op.hier.M
+    r = M @ rng.standard_normal(M.shape[0])
+    z = sol.vcycle(_t(r)).cpu().numpy()
+    zr = op.vcycle.apply(r)
+    d = _mnorm_rel(z - zr, zr, M)
+    print(f"[{name}] vcycle L2 rel diff on M u {d:.3e}", flush=True)
+    assert d <= 1e-7, name
+    sol.close()
+
+
+def _same_blocks(sol, op, w):
+    for l in range(1, w.levels):
+        ptr, idx = sol.get_patches(l)
+        ob = op.smoothers[l].blocks
+        if len(ptr) - 1 != len(ob):
+            return False
+        if any(not np.array_equal(idx[ptr[j]:ptr[j + 1]], np.asarray(ob[j])) for j in range(len(ob))):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("coarse", ["same", "jacobi"])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32-operators"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_thb_pcg_matches_oracle(name, precision, coarse):
+    S = _gpu()
+    w, g, op = _problem(name, coarse)
+    xo, ito, _ = op.solve(tol=1e-8)
+    sol = _solver(S, g, precision=precision)
+    x = torch.zeros(len(g.b), dtype=torch.float64, device="cuda:0")
+    info = sol.pcg(_t(g.b), x, rtol=1e-8)
+    xg = x.cpu().numpy()
+    A = op.A
+    res = np.linalg.norm(op.b - A @ xg) / np.linalg.norm(op.b)
+    M = op.hier.M
+    e = xg - xo
+    rel_l2 = math.sqrt(e @ (M @ e)) / math.sqrt(xo @ (M @ xo))
+    print(f"[{name}/{precision}/{coarse}] iterations gpu {info.iterations} oracle {ito}, host residual "
+          f"{res:.2e}, rel L2 {rel_l2:.2e}", flush=True)
+    assert info.status == 0 and res <= 1.01e-8, (info, res)
+    assert rel_l2 <= 1e-6, (name, rel_l2)
+    if _same_blocks(sol, op, w):
+        # with equal block lists: the oracle's count to rounding (FP64); FP32
+        # level operators shift it by a few percent at most
+        bar = 1 if precision == 0 else max(2, math.ceil(0.05 * ito))
+        assert abs(info.iterations - ito) <= bar, (name, info.iterations, ito)
+    x2 = torch.zeros_like(x)
+    sol.pcg(_t(g.b), x2, rtol=1e-8)
+    assert torch.equal(x, x2)
+    sol.close()
+
+
+def test_thb_rejections():
+    S = _gpu()
+    w, g, _ = _problem("thb-16-m2")
+    for kw in (dict(smoother=S.MULTIPLICATIVE), dict(block_gemm=1), dict(use_learned=1)):
+        with pytest.raises(S.SolverError) as ei:
+            S.Solver(0).setup(g, S.default_options(**kw))
+        assert ei.value.code == -1, kw
+    sol = _solver(S, g)
+    R = torch.zeros((4, len(g.b)), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(S.SolverError) as ei:
+        sol.vcycle_multi(R)
+    assert ei.value.code == -1   # INVALID_ARG
+    sol.close()
