@@ -1,8 +1,9 @@
 """Benchmark: multigrid-preconditioned CG on the 3D immersed Poisson problem
 (quadratic B-splines, 128^3 gyroid, 1.48M DOFs, 4-level V(1,1)) on one MI355X,
 with the 2D 1024^2 cubic 200-disc problem (6-level V(2,2)), 3D linear
-elasticity on the 80^3 apple with a bite (667k DOFs), several right-hand sides
-and the 64-problem batch beside it.
+elasticity on the 80^3 apple with a bite (667k DOFs), a locally refined problem
+with truncated hierarchical B-splines (58k DOFs, general sparse levels),
+several right-hand sides and the 64-problem batch beside it.
 
 Metric (both parts are reported for every form):
 * V-cycle MDOF/s = fine DOFs / median time of one V-cycle (imsmg_vcycle as
@@ -53,6 +54,15 @@ def smooth_step_bytes(st):
     store their residual (8); stored rows read K values."""
     return (st["n"] * 40 + st["general_rows"] * 8
             + st["stored_rows"] * st["stencil"] * st["value_bytes"])
+
+
+def csr_smooth_step_bytes(st, nnz):
+    """Algorithmic bytes of one launch of the CSR residual + smoothing step
+    (general sparse level, FP64 values): per row the row pointer (4), meta
+    (4), c (8), r (8), x_a (8, each entry once), x_b (8); rows of larger
+    blocks also store their residual (8); per stored entry its column (4)
+    and value (8)."""
+    return st["n"] * 40 + st["general_rows"] * 8 + nnz * (4 + st["value_bytes"])
 
 
 def cpu_baseline(budget_s=25.0):
@@ -115,6 +125,7 @@ def main():
     ap.add_argument("--no-elasticity", action="store_true", help="skip the 3D elasticity workload (apple 80^3)")
     ap.add_argument("--elasticity-n", type=int, default=80, help="elements per axis of the elasticity workload")
     ap.add_argument("--elasticity-forms", default="", help="comma list to restrict the elasticity forms")
+    ap.add_argument("--no-thb", action="store_true", help="skip the locally refined (THB) workload")
     ap.add_argument("--nrhs", type=int, default=16, help="columns of the multi-right-hand-side form (1: skip)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-problem form")
     ap.add_argument("--forms", default="", help="comma list to restrict the timed forms")
@@ -294,6 +305,50 @@ def main():
                    "forms": run_forms(we, ge, forms_e, min(args.steps, 3), min(args.warmup, 1))}
         del ge
 
+    # -------------------- truncated hierarchical B-splines (general sparse levels)
+    thb = None
+    if not args.no_thb and (want is None or "thb" in want):
+        from paper_1903_10977_amd import thb as TB
+        wt = W.thb_256()
+        t0 = time.time()
+        gt = TB.generate(wt)
+        gen_s = time.time() - t0
+        log(f"generated {wt.name}: fine DOFs {gt.fine.n}, nnz {gt.fine.A.nnz}, levels "
+            f"{[lv.n for lv in gt.levels]}, {gen_s:.1f} s")
+        forms_t = {"fp64": (S.FP64, "as", None, None), "mixed": (S.MIXED, "as", None, None)}
+        res_t = run_forms(wt, gt, forms_t, args.steps, args.warmup)
+        gj = TB.with_coarse_diagonal(gt)
+        res_t.update(run_forms(gj.workload, gj, {"as+jacobi-fp64": (S.FP64, "as", None, None)},
+                               args.steps, args.warmup))
+        # the finest level's CSR residual + smoothing step, FP64, HIP events
+        solk = make(gt, wt, S.FP64, timing=TIMED_REPS)
+        stk = solk.level_stats(len(gt.levels) - 1)
+        solk.kernel_time(reset=True)
+        bt = torch.tensor(gt.b, device="cuda:0")
+        xk = torch.zeros_like(bt)
+        for _ in range(max(1, min(args.steps, 3))):
+            xk.zero_()
+            solk.pcg(bt, xk, rtol=1e-8)
+        msk, cntk = solk.kernel_time()
+        solk.close()
+        avgk = msk / max(cntk, 1)
+        bytes_k = csr_smooth_step_bytes(stk, gt.fine.A.nnz)
+        ach_k = bytes_k / (avgk * 1e-3) / 1e9
+        log(f"THB fine smoothing step (CSR): {cntk} launches, avg {avgk * 1e3:.2f} us, {bytes_k / 1e6:.2f} MB, "
+            f"{ach_k:.0f} GB/s")
+        thb = {"workload": (f"2D Poisson, quadratic truncated hierarchical B-splines, {wt.n}^2 level-0 cells, "
+                            f"cells cut by 40 seeded discs refined {wt.local_levels} times, f = 1, u = 0 on the "
+                            f"box, {wt.levels}-level V(1,1) on meshes coarsened by Algorithm alg:coarsen, "
+                            f"additive Schwarz (support-inclusion blocks), general sparse (CSR) levels"),
+               "fine_dofs": gt.fine.n, "level_dofs": [lv.n for lv in gt.levels], "fine_nnz": int(gt.fine.A.nnz),
+               "generate_s": round(gen_s, 1), "forms": res_t,
+               "fine_smoothing_kernel": {"kernel": "k_csr_residual_smooth (finest level, FP64)",
+                                         "avg_launch_us": round(avgk * 1e3, 2), "bytes_per_launch": int(bytes_k),
+                                         "achieved_gbs": round(ach_k, 1),
+                                         "frac_of_hbm_peak": round(ach_k / HBM_PEAK_GBS, 4),
+                                         "launches": int(cntk)}}
+        del gt, gj
+
     # several right-hand sides with the C2 matrix: the 16-column form
     multi = None
     if args.nrhs > 1 and mg is not None:
@@ -352,7 +407,8 @@ def main():
                    "pcg_time_s": round(hf["pcg_ms"] / 1e3, 5), "forms": head,
                    "speedup_mixed_vs_fp64_pcg": (round(hf["pcg_ms"] / head["mixed"]["pcg_ms"], 3)
                                                  if "mixed" in head else None),
-                   "second_workload": second, "elasticity": elastic, "multi_rhs": multi, "batched": batched},
+                   "second_workload": second, "elasticity": elastic, "thb": thb, "multi_rhs": multi,
+                   "batched": batched},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_residual_smooth (finest level, FP64)", "bytes_per_launch": int(bytes_launch),

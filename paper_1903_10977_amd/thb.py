@@ -44,6 +44,7 @@ from typing import List
 
 import numpy as np
 import scipy.sparse as sp
+from threadpoolctl import threadpool_limits
 
 from . import generator as GEN
 
@@ -96,30 +97,35 @@ def coarsen(fine: Mesh) -> Mesh:
     return Mesh(n0c, fine.M, dom)
 
 
+_T_CACHE = {}
+
+
 def insertion_matrix(n_c: int, p: int) -> np.ndarray:
     """T (n_f x n_c functions, n_f = 2 n_c + p) with fine coefficients = T
     coarse coefficients, by Boehm insertion of the midpoint of every span of
-    the open uniform knot vector on [0, 1]."""
+    the open uniform knot vector on [0, 1] (one knot at a time: the new
+    coefficient i is (1 - a_i) P_{i-1} + a_i P_i inside the p affected
+    positions, a copy elsewhere)."""
+    key = (n_c, p)
+    if key in _T_CACHE:
+        return _T_CACHE[key]
     t = np.concatenate([np.zeros(p), np.arange(n_c + 1) / n_c, np.ones(p)])
     T = np.eye(n_c + p)
     for e in range(n_c):
         x = (e + 0.5) / n_c
         k = int(np.searchsorted(t, x, side="right")) - 1      # t[k] <= x < t[k+1]
-        n = len(t) - p - 1
-        S = np.zeros((n + 1, n))
-        for i in range(n + 1):
-            if i <= k - p:
-                S[i, i] = 1.0
-            elif i >= k + 1:
-                S[i, i - 1] = 1.0
-            else:
-                a = (x - t[i]) / (t[i + p] - t[i])
-                if i - 1 >= 0:
-                    S[i, i - 1] = 1.0 - a
-                S[i, i] = a
-        T = S @ T
+        n = T.shape[0]
+        Tn = np.empty((n + 1, T.shape[1]))
+        lo = max(k - p + 1, 0)
+        Tn[:lo] = T[:lo]
+        Tn[k + 1:] = T[k:]
+        for i in range(lo, k + 1):
+            a = (x - t[i]) / (t[i + p] - t[i])
+            Tn[i] = a * T[i] + ((1.0 - a) * T[i - 1] if i >= 1 else 0.0)
+        T = Tn
         t = np.insert(t, k + 1, x)
     T[np.abs(T) < 1e-15] = 0.0
+    _T_CACHE[key] = T
     return T
 
 
@@ -186,40 +192,74 @@ def build_space(mesh: Mesh, p: int, n_grid: int) -> Space:
     return Space(mesh, np.concatenate(funcs), C, np.concatenate(untr))
 
 
+def _dense_rows(M: sp.csr_matrix, rows, cols) -> np.ndarray:
+    """M[rows][:, cols] as a dense array (cols sorted, holding every column
+    the rows use)."""
+    out = np.zeros((len(rows), len(cols)))
+    for r, i in enumerate(rows):
+        a, b = M.indptr[i], M.indptr[i + 1]
+        out[r, np.searchsorted(cols, M.indices[a:b])] = M.data[a:b]
+    return out
+
+
 def _restriction_rows(cs: Space, fs: Space, p: int) -> sp.csr_matrix:
     """R (all coarse x all fine functions) with cs.C = R fs.C."""
     nc, nfine = cs.C.shape[0], fs.C.shape[0]
-    # fine function lookup by (level, ix, iy)
-    fkey = {(int(m), int(x), int(y)): i for i, (m, x, y) in enumerate(fs.funcs)}
+    rr, rc, rv = [], [], []
+    fast = np.zeros(nc, dtype=bool)
+    # two-scale rows: untruncated coarse B-splines of level m whose children
+    # (level-m fine B-splines) are all untruncated fine functions
+    for m in range(cs.mesh.M + 1):
+        sel = np.nonzero((cs.funcs[:, 0] == m) & cs.untrunc)[0]
+        if len(sel) == 0:
+            continue
+        n_c = cs.mesh.cells(m)
+        T = insertion_matrix(n_c, p)                      # (2 n_c + p) x (n_c + p)
+        nf1 = 2 * n_c + p
+        fid = np.full((nf1, nf1), -1, dtype=np.int64)     # fine level-m function id by (ix, iy)
+        fm = np.nonzero(fs.funcs[:, 0] == m)[0]
+        fid[fs.funcs[fm, 1], fs.funcs[fm, 2]] = fm
+        # children of every 1D coarse index (p + 2 at most), -1 padded
+        ch = np.full((n_c + p, p + 2), -1, dtype=np.int64)
+        co = np.zeros((n_c + p, p + 2))
+        for i in range(n_c + p):
+            nz = np.nonzero(T[:, i])[0]
+            ch[i, :len(nz)] = nz
+            co[i, :len(nz)] = T[nz, i]
+        ix, iy = cs.funcs[sel, 1], cs.funcs[sel, 2]
+        ax, ay = ch[ix][:, :, None], ch[iy][:, None, :]                 # (N, p+2, 1), (N, 1, p+2)
+        cv = (co[ix][:, :, None] * co[iy][:, None, :]).reshape(len(sel), -1)
+        valid = ((ax >= 0) & (ay >= 0)).reshape(len(sel), -1)
+        kid = np.where(valid, fid[np.maximum(ax, 0), np.maximum(ay, 0)].reshape(len(sel), -1), -1)
+        ok_kid = ~valid | ((kid >= 0) & fs.untrunc[np.maximum(kid, 0)])
+        good = ok_kid.all(axis=1)
+        for q in np.nonzero(good)[0]:
+            v = valid[q]
+            rr.append(np.full(int(v.sum()), sel[q]))
+            rc.append(kid[q][v])
+            rv.append(cv[q][v])
+        fast[sel[good]] = True
     share = (cs.C @ fs.C.T).tocsr()          # coarse x fine: share a grid coefficient
     FT = fs.C.T.tocsr()                      # grid -> fine functions
-    rr, rc, rv = [], [], []
-    T1 = {}
-    for j in range(nc):
-        m, ix, iy = (int(v) for v in cs.funcs[j])
-        done = False
-        if cs.untrunc[j]:
-            n_c = cs.mesh.cells(m)
-            if n_c not in T1:
-                T1[n_c] = insertion_matrix(n_c, p)
-            T = T1[n_c]
-            cx, cy = np.nonzero(T[:, ix])[0], np.nonzero(T[:, iy])[0]
-            kids = [(fkey.get((m, a, b)), T[a, ix] * T[b, iy]) for b in cy for a in cx]
-            if all(k is not None and fs.untrunc[k] for k, _ in kids):
-                for k, v in kids:
-                    rr.append(j)
-                    rc.append(k)
-                    rv.append(v)
-                done = True
-        if done:
-            continue
+    with threadpool_limits(1):               # many tiny dense solves: no BLAS threads
+        _solve_rows(cs, fs, np.nonzero(~fast)[0], share, FT, rr, rc, rv)
+    if not rr:
+        return sp.csr_matrix((nc, nfine))
+    return sp.csr_matrix((np.concatenate(rv), (np.concatenate(rr), np.concatenate(rc))), shape=(nc, nfine))
+
+
+def _solve_rows(cs, fs, rows, share, FT, rr, rc, rv):
+    for j in rows:
         cand = share.indices[share.indptr[j]:share.indptr[j + 1]]
-        target = cs.C[j]
+        tcols = cs.C.indices[cs.C.indptr[j]:cs.C.indptr[j + 1]]
+        tvals = cs.C.data[cs.C.indptr[j]:cs.C.indptr[j + 1]]
+        done = False
         for _ in range(3):
-            sub = fs.C[cand]
-            cols = np.union1d(sub.indices, target.indices)
-            Ms = sub[:, cols].toarray()
-            tv = target[:, cols].toarray().ravel()
+            cols = np.unique(np.concatenate([fs.C.indices[fs.C.indptr[k]:fs.C.indptr[k + 1]] for k in cand]
+                                            + [tcols]))
+            Ms = _dense_rows(fs.C, cand, cols)
+            tv = np.zeros(len(cols))
+            tv[np.searchsorted(cols, tcols)] = tvals
             # normal equations of the (consistent) system Ms^T x = tv: the
             # grid-coefficient rows of neighbouring functions are far from
             # dependent, and the exactness check below guards the result
@@ -231,18 +271,16 @@ def _restriction_rows(cs: Space, fs: Space, p: int) -> sp.csr_matrix:
                 x, *_ = np.linalg.lstsq(Ms.T, tv, rcond=None)
             if np.abs(Ms.T @ x - tv).max() <= 1e-12:
                 x[np.abs(x) < 1e-13] = 0.0
-                for k, v in zip(cand, x):
-                    if v != 0.0:
-                        rr.append(j)
-                        rc.append(int(k))
-                        rv.append(float(v))
+                nz = x != 0.0
+                rr.append(np.full(int(nz.sum()), j))
+                rc.append(np.asarray(cand)[nz])
+                rv.append(x[nz])
                 done = True
                 break
             # widen: fine functions sharing a grid coefficient with the candidates
             cand = np.unique(FT[cols].indices)
         if not done:
             raise RuntimeError(f"coarse THB function {j} is not in the fine THB space")
-    return sp.csr_matrix((rv, (rr, rc)), shape=(nc, nfine))
 
 
 @dataclass
@@ -282,22 +320,24 @@ def level_data(space: Space, p: int, n_grid: int, grid_active_funcs, grid_active
     on = np.zeros(len(elems), dtype=bool)
     on[np.unique(owner[grid_active_cells])] = True
     # grid cells touched by each active function: grid function k covers
-    # cells (kx - p .. kx, ky - p .. ky)
-    Ca = C[np.nonzero(act)[0]].tocoo()
-    kx, ky = Ca.col % nf1, Ca.col // nf1
-    rows, cells = [], []
+    # cells (kx - p .. kx, ky - p .. ky); F = pattern(C) x (grid function ->
+    # elements meeting Omega under its support)
+    g2e_r, g2e_c = [], []
     for dx in range(p + 1):
         for dy in range(p + 1):
-            cx, cy = kx - dx, ky - dy
+            cx, cy = gx - dx, gy - dy
             ok = (cx >= 0) & (cx < n_grid) & (cy >= 0) & (cy < n_grid)
-            rows.append(Ca.row[ok])
-            cells.append(owner[cx[ok], cy[ok]])
-    rows, cells = np.concatenate(rows), np.concatenate(cells)
-    keep = on[cells]
-    F = sp.csr_matrix((np.ones(int(keep.sum())), (rows[keep], cells[keep])), shape=(Ca.shape[0], len(elems)))
+            e = owner[cx[ok], cy[ok]]
+            keep = on[e]
+            g2e_r.append(g[ok][keep])
+            g2e_c.append(e[keep])
+    G2E = sp.csr_matrix((np.ones(sum(len(r) for r in g2e_r)), (np.concatenate(g2e_r), np.concatenate(g2e_c))),
+                        shape=(nf1 * nf1, len(elems)))
+    Ca = C[np.nonzero(act)[0]].copy()
+    Ca.data[:] = 1.0
+    F = (Ca @ G2E).tocsr()
     F.data[:] = 1.0
-    F.sum_duplicates()
-    F.data[:] = 1.0
+    F.sort_indices()
     return THBLevelData(space, act, elems, on, F)
 
 
@@ -379,3 +419,17 @@ def generate(w, nthreads: int = 0):
                                  elem_id=None, two_scale=None, block_colour=None)
     b = Cf @ (P @ gp.b)
     return GEN.GeneratedProblem(workload=w, levels=levels, b=b, M=None, seconds=time.perf_counter() - t0)
+
+
+def with_coarse_diagonal(problem):
+    """The same problem with one block per function on the levels between
+    the coarsest and the finest (Remark rem:coarseGS: Jacobi there)."""
+    levels = list(problem.levels)
+    L = len(levels)
+    for l in range(1, L - 1):
+        n = levels[l].A.shape[0]
+        levels[l] = dataclasses.replace(levels[l], block_ptr=np.arange(n + 1, dtype=np.int32),
+                                        block_idx=np.arange(n, dtype=np.int32),
+                                        block_assoc=np.arange(n, dtype=np.int32))
+    w = dataclasses.replace(problem.workload, coarse_smoother="jacobi")
+    return dataclasses.replace(problem, workload=w, levels=levels)

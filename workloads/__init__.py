@@ -247,3 +247,10 @@ def thb_discs(seed: int = 7, n: int = 64, local_levels: int = 2, levels: int = 3
     return Workload(name=f"thb-s{seed}-n{n}-m{local_levels}", dim=2, degree=2, n=n, depth=depth,
                     levels=levels, geometry="discs", discs=disc_set(seed, n_discs, rmin, rmax).tolist(),
                     rhs="one", nu=1, local_levels=local_levels)
+
+
+def thb_256(seed: int = 7) -> Workload:
+    """The larger THB problem: 256^2 level-0 cells, cut cells refined twice
+    (finest cells 1024^2 near the boundaries), 40 seeded discs with radii
+    U[0.02, 0.06], six multigrid levels."""
+    return thb_discs(seed=seed, n=256, local_levels=2, levels=6, n_discs=40, rmin=0.02, rmax=0.06)
