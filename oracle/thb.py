@@ -318,6 +318,24 @@ class THBHierarchy:
             self.A[k] = (self.R[k] @ self.A[k + 1] @ self.R[k].T).tocsr()
 
 
+class THBMultiplicativeSmoother(SW.MultiplicativeSmoother):
+    """Multiplicative Schwarz (eq:multiplicativeSchwarz1) on a THB level.
+    Reading: THB functions have no lattice position, so every block takes,
+    in block order, the smallest colour that no block already coloured uses
+    on a shared element (greedy from 0; same-colour blocks never share an
+    element, as the subsection requires); kind "diagonal": one block per
+    function (Gauss-Seidel, Remark rem:coarseGS)."""
+
+    def __init__(self, A, lev, kind="schwarz"):
+        if kind == "diagonal":
+            blocks = [np.array([i], dtype=np.int64) for i in range(A.shape[0])]
+            assoc = list(range(A.shape[0]))
+        else:
+            blocks, assoc = SW.select_blocks(lev)
+        SW.Smoother.__init__(self, A, lev, blocks=blocks)
+        self._order_blocks(A, lev, assoc, [None] * len(blocks), lambda b: b, 0)
+
+
 @dataclass
 class THBProblem:
     w: object
@@ -339,8 +357,10 @@ class THBProblem:
 
 
 def build(w, orders=None) -> THBProblem:
-    """The THB hierarchy with additive Schwarz smoothing (blocks by support
-    inclusion on every level above the coarsest) and its V-cycle."""
+    """The THB hierarchy with its smoothers (w.smoother on the finest level:
+    "as" additive or "ms" multiplicative Schwarz over support-inclusion
+    blocks; w.coarse_smoother on the others: "same", "jacobi" or "gs") and
+    its V-cycle."""
     hier = THBHierarchy(w, orders)
     L = w.levels
     sm = [None] * L
@@ -352,6 +372,10 @@ def build(w, orders=None) -> THBProblem:
             sm[l] = SW.Smoother(hier.A[l], lev)
         elif kind == "jacobi":
             sm[l] = SW.DiagonalSmoother(hier.A[l], lev)
+        elif kind == "ms":
+            sm[l] = THBMultiplicativeSmoother(hier.A[l], lev)
+        elif kind == "gs":
+            sm[l] = THBMultiplicativeSmoother(hier.A[l], lev, kind="diagonal")
         else:
             raise ValueError(f"THB levels: smoother {kind!r} not set up")
     vc = MG.VCycle(hier.A, hier.R, sm, nu_pre=w.nu, nu_post=w.nu, cycle=w.cycle)

@@ -1049,7 +1049,12 @@ void ms_sweep(imsmg_ctx *c, Level &L, bool forward, const int32_t *done) {
     const int cc = forward ? k : L.ncolours - 1 - k;
     const int a = L.ms_cptr[cc], m = L.ms_cptr[cc + 1] - a;
     if (m == 0) continue;
-    if (L.ncomp > 1) {
+    if (L.csr) {
+      if (mixed(c))
+        launch_csr_ms_colour(c->stream, m, L.csr_lanes, L.ms_rows + a, L.ms_cf + a, L.a32, L.r, L.x, L.rh, done);
+      else
+        launch_csr_ms_colour(c->stream, m, L.csr_lanes, L.ms_rows + a, L.ms_cf + a, L.a64, L.r, L.x, L.rh, done);
+    } else if (L.ncomp > 1) {
       if (mixed(c))
         launch_vms_colour(c->stream, m, L.ms_rows + a, L.ms_cf + a, L.ms_vidx + size_t(a) * L.ncomp, L.ms_val32,
                           L.K, L.vops32, L.row_lat, L.r, L.x, L.rh, done, L.ms_stream32);
@@ -1279,10 +1284,11 @@ void build_ms(imsmg_ctx *c, Level &L, const std::vector<int32_t> &fptr, const st
   // colour-ordered copy of the stored rows' values: one entry per list entry
   // (vector levels: per list entry and component block) whose row keeps its
   // own values; entries grouped by block, each group packed from its block
-  const int nc = L.ncomp, nb = nc * nc;
+  // (general sparse levels read their CSR rows instead)
+  const int nc = L.ncomp, nb = L.csr ? 0 : nc * nc;
   std::vector<int32_t> vidx(all_rows.size() * nc, -1);
   std::vector<std::vector<int32_t>> vg(nb), vpos(nb);
-  for (size_t t = 0; t < all_rows.size(); ++t) {
+  for (size_t t = 0; nb > 0 && t < all_rows.size(); ++t) {
     const int i = all_rows[t];
     const int ci = i / L.ns, is = i % L.ns;
     for (int e = 0; e < nc; ++e) {
@@ -2529,8 +2535,6 @@ int imsmg_setup(imsmg_ctx *c, int nlevels, const imsmg_csr *A, const imsmg_csr *
     if (ncsr) {
       // general sparse levels (no function lattice)
       if (ncsr != nlevels) bad("either every level has a function lattice or none has");
-      if (c->opt.smoother == IMSMG_MULTIPLICATIVE || c->opt.coarse_smoother == IMSMG_MULTIPLICATIVE)
-        bad("general sparse levels: the multiplicative smoother is not supported");
       if (c->opt.use_learned) bad("general sparse levels: learned weights are not supported");
       if (c->opt.block_gemm) bad("general sparse levels: block_gemm is not supported");
       for (int l = 1; l < nlevels; ++l)

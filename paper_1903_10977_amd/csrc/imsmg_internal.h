@@ -273,6 +273,11 @@ void launch_vms_colour(hipStream_t s, int m, const int32_t *rows, const double *
 void launch_vms_colour(hipStream_t s, int m, const int32_t *rows, const double *cf, const int32_t *vidx,
                        const float *vals, int K, const VecOps<float> &ops, const int32_t *row_lat, const double *r,
                        double *x, double *rh, const int32_t *done, int stream);
+// general sparse levels: the colour step on CSR rows (ln lanes per row)
+void launch_csr_ms_colour(hipStream_t s, int m, int ln, const int32_t *rows, const double *cf,
+                          const CsrView<double> &A, const double *r, double *x, double *rh, const int32_t *done);
+void launch_csr_ms_colour(hipStream_t s, int m, int ln, const int32_t *rows, const double *cf,
+                          const CsrView<float> &A, const double *r, double *x, double *rh, const int32_t *done);
 void launch_ms_pack(hipStream_t s, int ne, int K, int KP, const int32_t *g, const double *val, int nv, double *out);
 void launch_ms_pack(hipStream_t s, int ne, int K, int KP, const int32_t *g, const float *val, int nv, float *out);
 // active rows of a level vector: op 0: y = 0, 1: y = x, 2: y += x

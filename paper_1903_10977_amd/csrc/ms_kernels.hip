@@ -16,6 +16,7 @@
 // invariant), so no thread reads a value another thread of the launch writes.
 #include <stdexcept>
 
+#include "csr_row.h"
 #include "op_row.h"
 
 namespace imsmg {
@@ -234,6 +235,58 @@ void launch_ms_colour(hipStream_t s, int m, const int32_t *rows, const double *c
                       double *x, double *rh, const int32_t *done, int stream) {
   dispatch_ms_colour<float>(s, m, rows, cf, vidx, vals, K, op, row_lat, r, x, rh, done, stream);
 }
+// General sparse levels: the same colour step on CSR rows (LN lanes per row,
+// fixed-order lane sums as csr_rows); the race argument above holds because
+// A couples two functions only where they share an element.
+template <int LN, typename V>
+__global__ __launch_bounds__(kMsBlock) void k_csr_ms_colour(int m, const int32_t *__restrict__ rows,
+                                                            const double *__restrict__ cf, CsrView<V> A,
+                                                            const double *__restrict__ r, double *x,
+                                                            double *__restrict__ rh,
+                                                            const int32_t *__restrict__ done) {
+  if (done && *done) return;
+  const int t = blockIdx.x * (kMsBlock / LN) + int(threadIdx.x) / LN;
+  const int lane = int(threadIdx.x) % LN;
+  const bool ok = t < m;
+  double part = 0.0;
+  int i = 0;
+  if (ok) {
+    i = rows[t];
+    for (int k = A.ptr[i] + lane; k < A.ptr[i + 1]; k += LN) part += double(A.val[k]) * x[A.col[k]];
+  }
+#pragma unroll
+  for (int o = LN / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+  if (ok && lane == 0) {
+    const double res = r[i] - part;
+    const double c = cf[t];
+    if (c != 0.0)
+      x[i] += c * res;
+    else
+      rh[i] = res;
+  }
+}
+
+template <typename V>
+static void csr_ms_colour(hipStream_t s, int m, int ln, const int32_t *rows, const double *cf, const CsrView<V> &A,
+                          const double *r, double *x, double *rh, const int32_t *done) {
+  if (m <= 0) return;
+  switch (ln) {
+    case 4: k_csr_ms_colour<4, V><<<csr_grid(m, 4), kMsBlock, 0, s>>>(m, rows, cf, A, r, x, rh, done); break;
+    case 8: k_csr_ms_colour<8, V><<<csr_grid(m, 8), kMsBlock, 0, s>>>(m, rows, cf, A, r, x, rh, done); break;
+    case 16: k_csr_ms_colour<16, V><<<csr_grid(m, 16), kMsBlock, 0, s>>>(m, rows, cf, A, r, x, rh, done); break;
+    default: throw std::invalid_argument("CSR rows: 4, 8 or 16 lanes per row");
+  }
+}
+
+void launch_csr_ms_colour(hipStream_t s, int m, int ln, const int32_t *rows, const double *cf,
+                          const CsrView<double> &A, const double *r, double *x, double *rh, const int32_t *done) {
+  csr_ms_colour<double>(s, m, ln, rows, cf, A, r, x, rh, done);
+}
+void launch_csr_ms_colour(hipStream_t s, int m, int ln, const int32_t *rows, const double *cf,
+                          const CsrView<float> &A, const double *r, double *x, double *rh, const int32_t *done) {
+  csr_ms_colour<float>(s, m, ln, rows, cf, A, r, x, rh, done);
+}
+
 void launch_ms_pack(hipStream_t s, int ne, int K, int KP, const int32_t *g, const double *val, int nv, double *out) {
   if (ne > 0)
     k_ms_pack<double><<<(int64_t(ne) * KP + kMsBlock - 1) / kMsBlock, kMsBlock, 0, s>>>(ne, K, KP, g, val, nv, out);

@@ -406,7 +406,7 @@ def generate(w, nthreads: int = 0):
         if l > 0:
             bp, bi = inclusion_blocks(d.F)
             ba = np.arange(n, dtype=np.int32)
-            if 0 < l < L - 1 and getattr(w, "coarse_smoother", "same") == "jacobi":
+            if 0 < l < L - 1 and getattr(w, "coarse_smoother", "same") in ("jacobi", "gs"):
                 bp = np.arange(n + 1, dtype=np.int32)
                 bi = np.arange(n, dtype=np.int32)
         Ft = d.F.T.tocsr()
@@ -421,9 +421,10 @@ def generate(w, nthreads: int = 0):
     return GEN.GeneratedProblem(workload=w, levels=levels, b=b, M=None, seconds=time.perf_counter() - t0)
 
 
-def with_coarse_diagonal(problem):
+def with_coarse_diagonal(problem, kind: str = "jacobi"):
     """The same problem with one block per function on the levels between
-    the coarsest and the finest (Remark rem:coarseGS: Jacobi there)."""
+    the coarsest and the finest (Remark rem:coarseGS: Jacobi, or
+    Gauss-Seidel with kind "gs")."""
     levels = list(problem.levels)
     L = len(levels)
     for l in range(1, L - 1):
@@ -431,5 +432,5 @@ def with_coarse_diagonal(problem):
         levels[l] = dataclasses.replace(levels[l], block_ptr=np.arange(n + 1, dtype=np.int32),
                                         block_idx=np.arange(n, dtype=np.int32),
                                         block_assoc=np.arange(n, dtype=np.int32))
-    w = dataclasses.replace(problem.workload, coarse_smoother="jacobi")
+    w = dataclasses.replace(problem.workload, coarse_smoother=kind)
     return dataclasses.replace(problem, workload=w, levels=levels)

@@ -14,6 +14,8 @@ the THB oracle (oracle/thb.py), with the bars of the scalar parity tests:
   oracle's solution in L2(Omega), bitwise repeatable, and where the block
   lists agree the oracle's iteration count +-1 (FP64; 5% with FP32 level
   operators); the same with Jacobi smoothing on the coarser levels;
+* multiplicative Schwarz (greedy colours) and Gauss-Seidel coarse smoothing
+  on these levels against the oracle's;
 * the calls general levels do not support are rejected with INVALID_ARG.
 """
 import math
@@ -234,7 +236,7 @@ def test_thb_pcg_matches_oracle(name, precision, coarse):
 def test_thb_rejections():
     S = _gpu()
     w, g, _ = _problem("thb-16-m2")
-    for kw in (dict(smoother=S.MULTIPLICATIVE), dict(block_gemm=1), dict(use_learned=1)):
+    for kw in (dict(block_gemm=1), dict(use_learned=1)):
         with pytest.raises(S.SolverError) as ei:
             S.Solver(0).setup(g, S.default_options(**kw))
         assert ei.value.code == -1, kw
@@ -243,4 +245,66 @@ def test_thb_rejections():
     with pytest.raises(S.SolverError) as ei:
         sol.vcycle_multi(R)
     assert ei.value.code == -1   # INVALID_ARG
+    sol.close()
+
+
+_ms_cache = {}
+
+
+def _ms_problem(name, coarse="same"):
+    key = (name, coarse)
+    if key not in _ms_cache:
+        import dataclasses
+        from oracle import thb as T
+        from paper_1903_10977_amd import thb as P
+        w, g, _ = _problem(name)
+        wm = dataclasses.replace(w, smoother="ms", coarse_smoother=coarse)
+        gm = P.with_coarse_diagonal(g, coarse) if coarse != "same" else dataclasses.replace(g, workload=wm)
+        gm = dataclasses.replace(gm, workload=wm)
+        print(f"[case {name}] multiplicative oracle ({coarse})", flush=True)
+        _ms_cache[key] = (wm, gm, T.build(wm))
+    return _ms_cache[key]
+
+
+@pytest.mark.parametrize("coarse", ["same", "gs"])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32-operators"])
+@pytest.mark.parametrize("name", ["thb-16-m2", "thb-32-m1", "thb-32-m2"])
+def test_thb_multiplicative_schwarz(name, precision, coarse):
+    """Multiplicative Schwarz on general sparse levels (greedy colours from
+    the element incidence): where the block lists agree, colours equal the
+    oracle's, one V-cycle on load vectors within 1e-7 in L2(Omega) and PCG
+    the oracle's iteration count (FP64 +-1, FP32 operators 5%); everywhere
+    PCG reaches a host-checked 1e-8 within 1e-6 of the oracle's solution."""
+    S = _gpu()
+    wm, g, op = _ms_problem(name, coarse)
+    sol = S.Solver(0).setup(g, S.default_options(nu_pre=1, nu_post=1, precision=precision,
+                                                 **S.smoother_options(wm))).factor()
+    same = _same_blocks(sol, op, wm)
+    if same:
+        for l in range(1, wm.levels):
+            nc, col = sol.get_patch_colours(l)
+            assert list(col) == list(op.smoothers[l].colours), (name, l)
+        if precision == 0:
+            M = op.hier.M
+            r = M @ np.random.default_rng(23).standard_normal(M.shape[0])
+            z = sol.vcycle(_t(r)).cpu().numpy()
+            zr = op.vcycle.apply(r)
+            d = _mnorm_rel(z - zr, zr, M)
+            print(f"[{name}/ms/{coarse}] vcycle L2 rel diff {d:.2e}", flush=True)
+            assert d <= 1e-7
+    xo, ito, _ = op.solve(tol=1e-8)
+    x = torch.zeros(len(g.b), dtype=torch.float64, device="cuda:0")
+    info = sol.pcg(_t(g.b), x, rtol=1e-8)
+    xg = x.cpu().numpy()
+    res = np.linalg.norm(op.b - op.A @ xg) / np.linalg.norm(op.b)
+    M = op.hier.M
+    e = xg - xo
+    rel_l2 = math.sqrt(e @ (M @ e)) / math.sqrt(xo @ (M @ xo))
+    print(f"[{name}/ms/{coarse}/{precision}] iterations gpu {info.iterations} oracle {ito}, residual {res:.2e}, "
+          f"rel L2 {rel_l2:.2e}, same blocks {same}", flush=True)
+    assert info.status == 0 and res <= 1.01e-8
+    assert rel_l2 <= 1e-6
+    if same:
+        bar = 1 if precision == 0 else max(2, math.ceil(0.05 * ito))
+        assert abs(info.iterations - ito) <= bar, (name, info.iterations, ito)
     sol.close()

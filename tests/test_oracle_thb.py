@@ -181,3 +181,42 @@ def test_thb_pcg_converges(small):
     # whole support inside Omega on level-M cells form singleton blocks
     sm = small.smoothers[-1]
     assert all(j in set(b.tolist()) for j, b in zip(sm.assoc, sm.raw_blocks))
+
+
+def test_thb_multiplicative_colours_and_symmetry():
+    """Multiplicative Schwarz on THB levels (greedy colours, R-reading in the
+    smoother's docstring): no two blocks of one colour share an element; on
+    an unrefined mesh the greedy colouring of the (singleton) uncut blocks
+    needs exactly (p+1)^d = 9 colours; the V-cycle with the forward sweep
+    before and the reversed sweep after the coarse correction is symmetric
+    (u.Bv = v.Bu); PCG converges in fewer iterations than with the additive
+    smoother."""
+    w = dataclasses.replace(W.thb_discs(n=16, local_levels=2, levels=3), smoother="ms")
+    ob = T.build(w)
+    for l in range(1, w.levels):
+        sm = ob.smoothers[l]
+        lev = ob.hier.levels[l]
+        els = SW.block_elements(lev, sm.blocks)
+        for c in set(sm.colours):
+            seen = set()
+            for j, cj in enumerate(sm.colours):
+                if cj == c:
+                    assert not (els[j] & seen)
+                    seen |= els[j]
+    rng = np.random.default_rng(5)
+    n = ob.A.shape[0]
+    for _ in range(3):
+        u, v = rng.standard_normal(n), rng.standard_normal(n)
+        a, b = u @ ob.vcycle.apply(v), v @ ob.vcycle.apply(u)
+        assert abs(a - b) <= 1e-10 * max(abs(a), 1e-300)
+    x, it, _ = ob.solve()
+    assert np.linalg.norm(ob.b - ob.A @ x) / np.linalg.norm(ob.b) <= 1e-8
+    wa = W.thb_discs(n=16, local_levels=2, levels=3)
+    _, it_as, _ = T.build(wa).solve()
+    assert it < it_as
+    # an unrefined mesh away from the discs: 9 greedy colours for the interior blocks
+    wu = dataclasses.replace(W.thb_discs(n=16, local_levels=0, levels=2), smoother="ms", discs=[[0.5, 0.5, 0.05]])
+    ou = T.build(wu)
+    smu = ou.smoothers[-1]
+    single = [j for j, b in enumerate(smu.blocks) if len(b) == 1]
+    assert len({smu.colours[j] for j in single}) == 9
