@@ -244,6 +244,23 @@ def main():
     log(f"fine smoothing-step kernel: {cnt} launches, avg {avg_ms * 1e3:.1f} us, {bytes_launch / 1e6:.1f} MB, "
         f"{achieved:.0f} GB/s; stats {stats}")
     solt.close()
+    # what a plain streaming kernel gets from HBM on this device: torch's
+    # device-to-device copy of 1 GiB (read + write), timed with events on
+    # torch's stream (where the copy runs)
+    cb = (1 << 30) // 8
+    csrc = torch.ones(cb, dtype=torch.float64, device="cuda:0")
+    cdst = torch.empty_like(csrc)
+    for _ in range(3):
+        cdst.copy_(csrc)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        cdst.copy_(csrc)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * 8 * cb * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del csrc, cdst
+    log(f"device copy of 1 GiB: {copy_gbs:.0f} GB/s (read + write)")
     tag = "128cube_gyroid" if (args.workload == "c3" and w.n == 128) else (
         "1024_discs" if (args.workload == "c2" and w.n == 1024) else None)
     traffic = None
@@ -315,11 +332,16 @@ def main():
         gen_s = time.time() - t0
         log(f"generated {wt.name}: fine DOFs {gt.fine.n}, nnz {gt.fine.A.nnz}, levels "
             f"{[lv.n for lv in gt.levels]}, {gen_s:.1f} s")
-        forms_t = {"fp64": (S.FP64, "as", None, None), "mixed": (S.MIXED, "as", None, None)}
+        forms_t = {"fp64": (S.FP64, "as", None, None), "mixed": (S.MIXED, "as", None, None),
+                   "ms-fp64": (S.FP64, "ms", None, None)}
         res_t = run_forms(wt, gt, forms_t, args.steps, args.warmup)
         gj = TB.with_coarse_diagonal(gt)
         res_t.update(run_forms(gj.workload, gj, {"as+jacobi-fp64": (S.FP64, "as", None, None)},
                                args.steps, args.warmup))
+        gs = TB.with_coarse_diagonal(gt, "gs")
+        res_t.update(run_forms(gs.workload, gs, {"ms+gs-fp64": (S.FP64, "ms", None, None)},
+                               args.steps, args.warmup))
+        del gs
         # the finest level's CSR residual + smoothing step, FP64, HIP events
         solk = make(gt, wt, S.FP64, timing=TIMED_REPS)
         stk = solk.level_stats(len(gt.levels) - 1)
@@ -339,7 +361,8 @@ def main():
         thb = {"workload": (f"2D Poisson, quadratic truncated hierarchical B-splines, {wt.n}^2 level-0 cells, "
                             f"cells cut by 40 seeded discs refined {wt.local_levels} times, f = 1, u = 0 on the "
                             f"box, {wt.levels}-level V(1,1) on meshes coarsened by Algorithm alg:coarsen, "
-                            f"additive Schwarz (support-inclusion blocks), general sparse (CSR) levels"),
+                            f"additive or multiplicative Schwarz (support-inclusion blocks), general sparse "
+                            f"(CSR) levels"),
                "fine_dofs": gt.fine.n, "level_dofs": [lv.n for lv in gt.levels], "fine_nnz": int(gt.fine.A.nnz),
                "generate_s": round(gen_s, 1), "forms": res_t,
                "fine_smoothing_kernel": {"kernel": "k_csr_residual_smooth (finest level, FP64)",
@@ -412,7 +435,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_residual_smooth (finest level, FP64)", "bytes_per_launch": int(bytes_launch),
-                     "avg_launch_us": round(avg_ms * 1e3, 2), "launches_per_event_pair": TIMED_REPS},
+                     "avg_launch_us": round(avg_ms * 1e3, 2), "launches_per_event_pair": TIMED_REPS,
+                     "device_copy_gbs": round(copy_gbs, 1), "frac_of_device_copy": round(achieved / copy_gbs, 4)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

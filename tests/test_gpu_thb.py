@@ -308,3 +308,21 @@ def test_thb_multiplicative_schwarz(name, precision, coarse):
         bar = 1 if precision == 0 else max(2, math.ceil(0.05 * ito))
         assert abs(info.iterations - ito) <= bar, (name, info.iterations, ito)
     sol.close()
+
+
+@pytest.mark.parametrize("name", ["thb-32-m2"])
+def test_thb_convergence_flag_path(name):
+    """The kernels of levels at or above flag_min_rows read the CG's
+    convergence flag (the thb cases are below the default 65,536 rows):
+    with the flag on every level the solve is bit-for-bit the default one."""
+    S = _gpu()
+    w, g, op = _problem(name)
+    xs = []
+    for fmr in (65536, 0):
+        sol = _solver(S, g, flag_min_rows=fmr)
+        x = torch.zeros(len(g.b), dtype=torch.float64, device="cuda:0")
+        info = sol.pcg(_t(g.b), x, rtol=1e-8)
+        assert info.status == 0
+        xs.append((x, info.iterations))
+        sol.close()
+    assert xs[0][1] == xs[1][1] and torch.equal(xs[0][0], xs[1][0])
