@@ -65,6 +65,22 @@ def csr_smooth_step_bytes(st, nnz):
     return st["n"] * 40 + st["general_rows"] * 8 + nnz * (4 + st["value_bytes"])
 
 
+def device_copy_gbs(torch, mib=1024, reps=10):
+    """Read + write bandwidth of torch's device-to-device copy of `mib` MiB."""
+    cb = (mib << 20) // 8
+    src = torch.ones(cb, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2 * 8 * cb * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
 def cpu_baseline(budget_s=25.0):
     """The oracle (plain FP64 NumPy/SciPy) on bounded samples: the gyroid
     workload at 16^3 (3 levels; the headline's geometry, basis and cycle at a
@@ -246,21 +262,12 @@ def main():
     solt.close()
     # what a plain streaming kernel gets from HBM on this device: torch's
     # device-to-device copy of 1 GiB (read + write), timed with events on
-    # torch's stream (where the copy runs)
-    cb = (1 << 30) // 8
-    csrc = torch.ones(cb, dtype=torch.float64, device="cuda:0")
-    cdst = torch.empty_like(csrc)
-    for _ in range(3):
-        cdst.copy_(csrc)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(10):
-        cdst.copy_(csrc)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 2 * 8 * cb * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del csrc, cdst
-    log(f"device copy of 1 GiB: {copy_gbs:.0f} GB/s (read + write)")
+    # torch's stream (where the copy runs); left out of counter runs, whose
+    # calibration copy must be the only large elementwise kernel
+    copy_gbs = None
+    if args.copy_calibration_mib <= 0:
+        copy_gbs = device_copy_gbs(torch)
+        log(f"device copy of 1 GiB: {copy_gbs:.0f} GB/s (read + write)")
     tag = "128cube_gyroid" if (args.workload == "c3" and w.n == 128) else (
         "1024_discs" if (args.workload == "c2" and w.n == 1024) else None)
     traffic = None
@@ -436,7 +443,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_residual_smooth (finest level, FP64)", "bytes_per_launch": int(bytes_launch),
                      "avg_launch_us": round(avg_ms * 1e3, 2), "launches_per_event_pair": TIMED_REPS,
-                     "device_copy_gbs": round(copy_gbs, 1), "frac_of_device_copy": round(achieved / copy_gbs, 4)},
+                     "device_copy_gbs": round(copy_gbs, 1) if copy_gbs else None,
+                     "frac_of_device_copy": round(achieved / copy_gbs, 4) if copy_gbs else None},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
