@@ -376,7 +376,9 @@ def main():
                                          "avg_launch_us": round(avgk * 1e3, 2), "bytes_per_launch": int(bytes_k),
                                          "achieved_gbs": round(ach_k, 1),
                                          "frac_of_hbm_peak": round(ach_k / HBM_PEAK_GBS, 4),
-                                         "launches": int(cntk)}}
+                                         "launches": int(cntk),
+                                         "traffic": PR.read_traffic(os.path.join(
+                                             ROOT, "profiles", "traffic_k_csr_residual_smooth_thb_256_discs_fp64.txt"))}}
         del gt, gj
 
     # several right-hand sides with the C2 matrix: the 16-column form
