@@ -11,7 +11,7 @@ from oracle import thb as T
 from paper_1903_10977_amd import thb as P
 
 CASES = [dict(n=16, local_levels=2, levels=3), dict(n=32, local_levels=1, levels=3, seed=3),
-         dict(n=16, local_levels=3, levels=2, seed=5)]
+         dict(n=16, local_levels=3, levels=2, seed=5), dict(n=16, local_levels=0, levels=3, seed=11)]
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"n{c['n']}-m{c['local_levels']}-l{c['levels']}")
