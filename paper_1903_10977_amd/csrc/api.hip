@@ -3142,6 +3142,10 @@ int imsmg_setup_batched(imsmg_ctx *c, int nprob, const int *nlevels, const imsmg
   if (!c) return IMSMG_ERR_INVALID_ARG;
   if (nprob < 1 || !nlevels || !A || !R || !P || !L) return fail(c, IMSMG_ERR_INVALID_ARG, "bad batched arguments");
   if (opt && opt->ncomp > 1) return fail(c, IMSMG_ERR_INVALID_ARG, "vector problems: the batched form is not supported");
+  for (int p = 0; p < nprob; ++p)
+    for (int l = 0; L[p] && l < nlevels[p]; ++l)
+      if (!L[p][l].dof_to_lattice)
+        return fail(c, IMSMG_ERR_INVALID_ARG, "general sparse levels: the batched form is not supported");
   if (c->ready) return fail(c, IMSMG_ERR_STATE, "a set-up single-problem context cannot become a batch");
   for (imsmg_ctx *b : c->batch) imsmg_destroy(b);
   c->batch.clear();

@@ -240,6 +240,9 @@ def test_thb_rejections():
         with pytest.raises(S.SolverError) as ei:
             S.Solver(0).setup(g, S.default_options(**kw))
         assert ei.value.code == -1, kw
+    with pytest.raises(S.SolverError) as ei:
+        S.BatchContext(0).setup([g, g], S.default_options())
+    assert ei.value.code == -1   # INVALID_ARG
     sol = _solver(S, g)
     R = torch.zeros((4, len(g.b)), dtype=torch.float64, device="cuda:0")
     with pytest.raises(S.SolverError) as ei:
