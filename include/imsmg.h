@@ -109,9 +109,10 @@ typedef struct {
  * sorted and unique, positive diagonal), R and R^T as sparse rows, and the
  * smoother's blocks and element incidence as given; dim, shape, reach and
  * two_scale are ignored (two_scale must be NULL).  Either every level of a
- * setup is general or none is.  General levels support the additive
- * smoother (with diagonal coarse smoothing and V/W cycles), FP64 and mixed
- * precision, single right-hand sides; the multiplicative smoother, learned
+ * setup is general or none is.  General levels support the additive and
+ * the multiplicative smoother (colours: as given with the blocks, else
+ * greedy from the element incidence), diagonal coarse smoothing, V and W
+ * cycles, FP64 and mixed precision, single right-hand sides; learned
  * weights, block_gemm and the multi-column and batched calls return
  * IMSMG_ERR_INVALID_ARG. */
 typedef struct {
