@@ -371,3 +371,39 @@ def test_general_levels_match_lattice_levels_without_refinement():
             print(f"[uniform-272 smoother={smoother} precision={prec}] iterations lattice {its[0]} general {its[1]}, "
                   f"max rel diff {rel:.2e}", flush=True)
             assert its[0] == its[1] and rel <= 1e-10
+
+
+@pytest.mark.parametrize("variant", ["w-cycle", "v22"])
+@pytest.mark.parametrize("name", ["thb-16-m2", "thb-32-m2"])
+def test_thb_cycle_variants(name, variant):
+    """The W-cycle and V(2,2) on general sparse levels against the oracle's
+    (the same bars as the V(1,1) PCG test)."""
+    import dataclasses
+    from oracle import thb as T
+    S = _gpu()
+    w0, g0, _ = _problem(name)
+    w = dataclasses.replace(w0, cycle=2) if variant == "w-cycle" else dataclasses.replace(w0, nu=2)
+    op = T.build(w)
+    g = dataclasses.replace(g0, workload=w)
+    xo, ito, _ = op.solve(tol=1e-8)
+    sol = S.Solver(0).setup(g, S.default_options(nu_pre=w.nu, nu_post=w.nu, cycle=w.cycle)).factor()
+    x = torch.zeros(len(g.b), dtype=torch.float64, device="cuda:0")
+    info = sol.pcg(_t(g.b), x, rtol=1e-8)
+    xg = x.cpu().numpy()
+    res = np.linalg.norm(op.b - op.A @ xg) / np.linalg.norm(op.b)
+    M = op.hier.M
+    e = xg - xo
+    rel_l2 = math.sqrt(e @ (M @ e)) / math.sqrt(xo @ (M @ xo))
+    print(f"[{name}/{variant}] iterations gpu {info.iterations} oracle {ito}, residual {res:.2e}, rel L2 {rel_l2:.2e}",
+          flush=True)
+    assert info.status == 0 and res <= 1.01e-8 and rel_l2 <= 1e-6
+    if _same_blocks(sol, op, w):
+        assert abs(info.iterations - ito) <= 1
+    if variant == "w-cycle":
+        M = op.hier.M
+        r = M @ np.random.default_rng(29).standard_normal(M.shape[0])
+        z = sol.vcycle(_t(r)).cpu().numpy()
+        zr = op.vcycle.apply(r)
+        if _same_blocks(sol, op, w):
+            assert _mnorm_rel(z - zr, zr, M) <= 1e-7
+    sol.close()
