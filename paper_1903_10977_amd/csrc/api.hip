@@ -174,6 +174,7 @@ struct Level {
   bool ms = false;
   std::vector<int32_t> ms_cptr;
   int32_t *ms_rows = nullptr;
+  int32_t *ms_lat = nullptr;  // lattice position of every list entry (scalar lattice levels)
   double *ms_cf = nullptr;
   // colour-ordered copy of the stored rows' values (a row as often as colours
   // touch it): ms_vidx per list entry (-1: reference stencil)
@@ -1062,10 +1063,10 @@ void ms_sweep(imsmg_ctx *c, Level &L, bool forward, const int32_t *done) {
         launch_vms_colour(c->stream, m, L.ms_rows + a, L.ms_cf + a, L.ms_vidx + size_t(a) * L.ncomp, L.ms_val64,
                           L.K, L.vops64, L.row_lat, L.r, L.x, L.rh, done, L.ms_stream64);
     } else if (mixed(c))
-      launch_ms_colour(c->stream, m, L.ms_rows + a, L.ms_cf + a, L.ms_vidx + a, L.ms_val32, L.K, L.op32, L.row_lat,
+      launch_ms_colour(c->stream, m, L.ms_lat + a, L.ms_cf + a, L.ms_vidx + a, L.ms_val32, L.K, L.op32, nullptr,
                        L.r, L.x, L.rh, done, L.ms_stream32);
     else
-      launch_ms_colour(c->stream, m, L.ms_rows + a, L.ms_cf + a, L.ms_vidx + a, L.ms_val64, L.K, L.op64, L.row_lat,
+      launch_ms_colour(c->stream, m, L.ms_lat + a, L.ms_cf + a, L.ms_vidx + a, L.ms_val64, L.K, L.op64, nullptr,
                        L.r, L.x, L.rh, done, L.ms_stream64);
     const Level::MsGeneral &G = L.ms_gen[cc];
     if (G.ng > 0) launch_smooth_general(c->stream, G.ng, G.grow_lat, G.sptr, G.scol, G.sval, L.rh, L.x, done, 4);
@@ -1276,9 +1277,13 @@ void build_ms(imsmg_ctx *c, Level &L, const std::vector<int32_t> &fptr, const st
     L.ms_cptr.push_back(int32_t(all_rows.size()));
   }
   L.ms_rows = dalloc<int32_t>(c->factor_owned, std::max<size_t>(all_rows.size(), 1));
+  L.ms_lat = dalloc<int32_t>(c->factor_owned, std::max<size_t>(all_rows.size(), 1));
   L.ms_cf = dalloc<double>(c->factor_owned, std::max<size_t>(all_cf.size(), 1));
   if (!all_rows.empty()) {
+    std::vector<int32_t> all_lat(all_rows.size());
+    for (size_t t = 0; t < all_rows.size(); ++t) all_lat[t] = L.h_row_lat[all_rows[t]];
     h2d(s, L.ms_rows, all_rows.data(), all_rows.size());
+    h2d(s, L.ms_lat, all_lat.data(), all_lat.size());
     h2d(s, L.ms_cf, all_cf.data(), all_cf.size());
   }
   // colour-ordered copy of the stored rows' values: one entry per list entry

@@ -56,8 +56,9 @@ __global__ __launch_bounds__(kMsBlock) void k_ms_colour(int m, const int32_t *__
     return dx + op.sx * (dy + op.sy * dz);
   };
   if (ok) {
-    const int i = rows[t];
-    L = row_lat[i];
+    // row_lat == nullptr: rows holds the lattice positions themselves (one
+    // dependent load less at the head of every lane's chain)
+    L = row_lat ? row_lat[rows[t]] : rows[t];
     const int e = vidx[t];
     if (e < 0) {
       for (int s = lane; s < K; s += LANES) part += op.refd[s] * x[L + off(s)];
