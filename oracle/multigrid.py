@@ -25,6 +25,9 @@ Readings:
   restarted from the current x (r = b - A x, fresh direction; the threshold
   and the iteration count carry over), at most three times; a solve that
   ends above tol reports that it did not converge;
+* multigrid as a standalone solver (the same paragraph): x <- x + B(b - A x)
+  from x0 until the relative residual meets tol; full multigrid (FMG, named
+  there too) as nested iteration with one cycle per level;
 * the paper names CG without a variant; besides the Hestenes-Stiefel beta the
   Polak-Ribiere ("flexible") form beta = r_{k+1}.(z_{k+1} - z_k) / r_k.z_k is
   offered, which equals it in exact arithmetic for a fixed SPD preconditioner
@@ -137,3 +140,36 @@ def pcg(A, b, precond, tol=1e-8, max_iter=1000, x0=None, flexible=False, info=No
     if info is not None:
         info.update(restarts=restarts, true_rel=true_rel, converged=bool(true_rel <= tol))
     return x, it, hist
+
+
+def mg_solve(A, b, precond, tol=1e-8, max_cycles=500, x0=None):
+    """Multigrid as a standalone solver (the paragraph after Algorithm
+    alg:MGV): x <- x + B (b - A x) until ||b - A x|| <= tol ||b||.
+    Returns (x, cycles, relative residual)."""
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    bn = np.linalg.norm(b)
+    k = 0
+    while True:
+        r = b - A @ x
+        rel = np.linalg.norm(r) / bn if bn > 0 else np.linalg.norm(r)
+        if rel <= tol or k >= max_cycles:
+            return x, k, rel
+        x = x + precond(r)
+        k += 1
+
+
+def fmg(vc: VCycle, b):
+    """Full multigrid (the FMG cycle named after Algorithm alg:MGV; nested
+    iteration): the right-hand side restricted to every level, the coarsest
+    problem solved directly, and on every finer level the coarser solution,
+    prolongated, improved by one cycle of that level."""
+    L = len(vc.A)
+    bs = [None] * L
+    bs[L - 1] = b
+    for l in range(L - 1, 0, -1):
+        bs[l - 1] = vc.R[l - 1] @ bs[l]
+    x = vc.apply(bs[0], level=0)
+    for l in range(1, L):
+        x = vc.R[l - 1].T @ x
+        x = x + vc.apply(bs[l] - vc.A[l] @ x, level=l)
+    return x
