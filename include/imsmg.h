@@ -420,6 +420,24 @@ int imsmg_vcycle_time(imsmg_ctx *ctx, const double *r_dev, int reps, double *med
  * holds the last iterate, info is filled); IMSMG_ERR_NAN; IMSMG_ERR_HIP. */
 int imsmg_pcg_solve(imsmg_ctx *ctx, const double *b_dev, double *x_dev, double rtol, imsmg_info *info);
 
+/* Multigrid as a standalone solver (the paragraph after Algorithm alg:MGV:
+ * the cycle applied iteratively, x <- x + B (b - A x), B the factorized
+ * cycle of the options: V or W, the configured smoothers and precision).
+ * fmg != 0: the iteration starts from a full multigrid pass (nested
+ * iteration, the FMG cycle named in the same paragraph): b restricted to
+ * every level (r_{l-1} = R_l r_l), the coarsest level solved directly, every
+ * finer level started from the prolongated coarser solution and improved by
+ * one cycle of that level; the x passed in is then ignored.  fmg == 0: x
+ * holds the start.  b_dev, x_dev: device, n of the finest level.  Stops when
+ * ||b - A x|| <= rtol ||b|| (2-norm, FP64 operator) or after max_cycles
+ * cycles (max_cycles = 0 with fmg: the FMG pass alone); x holds the last
+ * iterate.  info->iterations = cycles after the start, rel_res =
+ * true_rel_res = the final relative residual.  Errors: STATE before
+ * factorization, INVALID_ARG (null vector, rtol <= 0, max_cycles < 0),
+ * NOT_CONVERGED (rtol not reached), NAN. */
+int imsmg_mg_solve(imsmg_ctx *ctx, const double *b_dev, double *x_dev, double rtol, int max_cycles, int fmg,
+                   imsmg_info *info);
+
 /* Kernel-level entry points (device, compact vectors of the level). */
 int imsmg_apply_operator(imsmg_ctx *ctx, int level, const double *x, double *y);   /* y = A_l x */
 int imsmg_apply_smoother(imsmg_ctx *ctx, int level, const double *r, double *y);   /* y = S_l r */

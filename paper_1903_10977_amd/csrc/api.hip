@@ -190,6 +190,8 @@ struct Level {
   std::vector<MsGeneral> ms_gen;
   // W-cycle work vectors (cycle >= 2): saved correction and residual
   double *w_x = nullptr, *w_r = nullptr;
+  // full multigrid: the level's right-hand side and solution (first use)
+  double *fmg_b = nullptr, *fmg_x = nullptr;
 };
 
 }  // namespace
@@ -2801,6 +2803,103 @@ int imsmg_vcycle_time(imsmg_ctx *c, const double *r_dev, int reps, double *media
 
 int imsmg_pcg_solve(imsmg_ctx *c, const double *b_dev, double *x_dev, double rtol, imsmg_info *info) {
   return guarded(c, [&]() -> int { return pcg_solve_core(c, b_dev, x_dev, rtol, info); });
+}
+
+namespace {
+
+// Full multigrid into c->xs from c->bs: the right-hand side restricted to
+// every level, the coarsest level solved directly, then on every finer level
+// the prolongated coarser solution improved by one cycle of that level.
+void fmg_pass(imsmg_ctx *c) {
+  hipStream_t s = c->stream;
+  const int nl = int(c->lv.size());
+  for (Level &L : c->lv)
+    if (!L.fmg_b) {
+      const size_t vlen = size_t(L.ncomp * L.cstride);
+      double *v[2];
+      for (int k = 0; k < 2; ++k) {
+        double *b = dalloc<double>(c->owned, vlen);
+        HIP_CHECK_RET(hipMemsetAsync(b, 0, vlen * sizeof(double), s));
+        v[k] = b + L.guard;
+      }
+      L.fmg_b = v[0];
+      L.fmg_x = v[1];
+    }
+  Level &F = c->lv.back();
+  launch_rows_op(s, F.n, F.row_lat, c->bs, F.fmg_b, 1, nullptr);
+  for (int l = nl - 1; l > 0; --l) restrict_to(c, c->lv[l], c->lv[l - 1], c->lv[l].fmg_b, c->lv[l - 1].fmg_b, nullptr,
+                                               nullptr);
+  Level &C0 = c->lv[0];
+  launch_dense_gemv(s, C0.n, C0.row_lat, C0.Ainv, C0.fmg_b, C0.fmg_x, nullptr);
+  for (int l = 1; l < nl; ++l) {
+    Level &L = c->lv[l];
+    launch_rows_op(s, L.n, L.row_lat, nullptr, L.fmg_x, 0, nullptr);
+    prolong_add(c, L, c->lv[l - 1], c->lv[l - 1].fmg_x, L.fmg_x, nullptr);
+    residual(c, L, L.fmg_x, L.fmg_b, L.r, nullptr, false);
+    if (!L.ms) launch_diag_scale(s, L.n, L.row_lat, L.c, L.r, L.xs, nullptr);
+    vcycle_level(c, l, c->zero_flag, false);
+    launch_rows_op(s, L.n, L.row_lat, L.x, L.fmg_x, 2, nullptr);
+  }
+  launch_rows_op(s, F.n, F.row_lat, F.fmg_x, c->xs, 1, nullptr);
+  HIP_CHECK_RET(hipGetLastError());
+}
+
+}  // namespace
+
+int imsmg_mg_solve(imsmg_ctx *c, const double *b_dev, double *x_dev, double rtol, int max_cycles, int fmg,
+                   imsmg_info *info) {
+  return guarded(c, [&]() -> int {
+    if (!c->factored) bad("factor first", IMSMG_ERR_STATE);
+    if (!b_dev || !x_dev) bad("null vector");
+    if (!(rtol > 0.0) || max_cycles < 0) bad("rtol must be positive and max_cycles >= 0");
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = c->stream;
+    Level &F = c->lv.back();
+    std::vector<void *> tmp;
+    struct TmpFree {
+      std::vector<void *> &v;
+      ~TmpFree() { free_list(v); }
+    } tf{tmp};
+    double *part = dalloc<double>(tmp, dot_blocks(F.n));
+    launch_scatter(s, F.n, F.row_lat, b_dev, c->bs);
+    if (fmg)
+      fmg_pass(c);
+    else
+      launch_scatter(s, F.n, F.row_lat, x_dev, c->xs);
+    const double bn = std::sqrt(host_dot(c, F, c->bs, c->bs, part));
+    int k = 0;
+    double rn = 0.0;
+    while (true) {
+      apply_A64(c, F, c->xs, F.r);                       // r = b - A x in FP64
+      launch_sub_from(s, F.n, F.row_lat, c->bs, F.r);
+      rn = std::sqrt(host_dot(c, F, F.r, F.r, part));
+      if (!std::isfinite(rn)) break;
+      if (rn <= rtol * bn || k >= max_cycles) break;
+      if (!F.ms) launch_diag_scale(s, F.n, F.row_lat, F.c, F.r, F.xs, c->zero_flag);
+      vcycle_level(c, int(c->lv.size()) - 1, c->zero_flag, false);
+      launch_rows_op(s, F.n, F.row_lat, F.x, c->xs, 2, nullptr);   // x += B (b - A x)
+      ++k;
+    }
+    launch_gather(s, F.n, F.row_lat, c->xs, x_dev);
+    HIP_CHECK_RET(hipGetLastError());
+    HIP_CHECK_RET(hipStreamSynchronize(s));
+    const double rel = bn > 0.0 ? rn / bn : rn;
+    const int status = !std::isfinite(rn) ? IMSMG_ERR_NAN : (rel <= rtol ? IMSMG_OK : IMSMG_ERR_NOT_CONVERGED);
+    if (info) {
+      fill_info_common(c, info, 0);
+      info->status = status;
+      info->iterations = k;
+      info->rel_res = rel;
+      info->true_rel_res = rel;
+      info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (status != IMSMG_OK) {
+      c->err = status == IMSMG_ERR_NAN ? "NaN or Inf in the multigrid iteration"
+                                       : "the multigrid iteration did not reach rtol within max_cycles";
+      return status;
+    }
+    return IMSMG_OK;
+  });
 }
 
 int imsmg_apply_operator(imsmg_ctx *c, int level, const double *x, double *y) {

@@ -66,7 +66,7 @@ class LevelStats(C.Structure):
 
 
 SYMBOLS = ["imsmg_default_options", "imsmg_create", "imsmg_setup", "imsmg_set_patch_weights",
-           "imsmg_factor_patches", "imsmg_get_patches", "imsmg_get_patch_colours", "imsmg_get_gamma", "imsmg_vcycle", "imsmg_vcycle_time", "imsmg_pcg_solve",
+           "imsmg_factor_patches", "imsmg_get_patches", "imsmg_get_patch_colours", "imsmg_get_gamma", "imsmg_vcycle", "imsmg_vcycle_time", "imsmg_pcg_solve", "imsmg_mg_solve",
            "imsmg_apply_operator", "imsmg_apply_smoother", "imsmg_apply_restriction", "imsmg_apply_prolongation",
            "imsmg_coarse_solve", "imsmg_get_level_stats", "imsmg_kernel_time", "imsmg_last_error", "imsmg_destroy",
            "imsmg_load_mlp", "imsmg_get_patch_features", "imsmg_get_patch_weights", "imsmg_set_block_weights",
@@ -107,6 +107,7 @@ def load():
     lib.imsmg_vcycle.argtypes = [vp, vp, vp]
     lib.imsmg_vcycle_time.argtypes = [vp, vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.imsmg_pcg_solve.argtypes = [vp, vp, vp, dbl, C.POINTER(Info)]
+    lib.imsmg_mg_solve.argtypes = [vp, vp, vp, dbl, i32, i32, C.POINTER(Info)]
     for f in ("imsmg_apply_operator", "imsmg_apply_smoother", "imsmg_apply_restriction", "imsmg_apply_prolongation"):
         getattr(lib, f).argtypes = [vp, i32, vp, vp]
     lib.imsmg_coarse_solve.argtypes = [vp, vp, vp]
@@ -399,6 +400,17 @@ class Solver:
         info = Info()
         self._sync()
         rc = self.lib.imsmg_pcg_solve(self.h, self._dev(b), self._dev(x), rtol, C.byref(info))
+        if rc != OK and raise_on_error:
+            self._check(rc)
+        return SolveInfo.of(info)
+
+    def mg_solve(self, b, x, rtol: float = 1e-8, max_cycles: int = 500, fmg: bool = False,
+                 raise_on_error: bool = True) -> SolveInfo:
+        """Multigrid as a standalone solver (imsmg_mg_solve): x <- x + B (b - A x),
+        optionally started by a full multigrid pass (fmg=True, x's start ignored)."""
+        info = Info()
+        self._sync()
+        rc = self.lib.imsmg_mg_solve(self.h, self._dev(b), self._dev(x), rtol, max_cycles, int(fmg), C.byref(info))
         if rc != OK and raise_on_error:
             self._check(rc)
         return SolveInfo.of(info)

@@ -1,0 +1,149 @@
+"""Multigrid as a standalone solver and full multigrid (imsmg_mg_solve)
+against the oracle (oracle/multigrid.py: mg_solve, fmg) on lattice, vector
+(elasticity) and general sparse (THB) hierarchies:
+
+* one FMG pass (max_cycles = 0) and ten cycles from zero: the oracle's
+  iterates within 1e-7 relative in L2(Omega) (FP64; the bar of the V-cycle
+  parity tests: kept blocks whose smallest eigenvalue sits just above the
+  1e-16 removal threshold turn rounding differences of the residual into
+  differences of that size), additive and multiplicative Schwarz;
+* the whole iteration (multiplicative Schwarz, from zero and from the FMG
+  start): the oracle's cycle count +-1 and its solution within 1e-6 in
+  L2(Omega), the final relative residual (rechecked on the host) at most
+  rtol;
+* the cycle limit reports NOT_CONVERGED with the last iterate in x.
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CASES = {
+    "c1": lambda: W.c1(),
+    "c1-ms": lambda: dataclasses.replace(W.c1(), smoother="ms"),
+    "gyroid-16-ms": lambda: dataclasses.replace(W.small_gyroid(3, 16, levels=3), smoother="ms"),
+    "slab-8": lambda: W.slab(n=8, levels=2),
+    "slab-8-ms": lambda: dataclasses.replace(W.slab(n=8, levels=2), smoother="ms"),
+    "thb-16-m2": lambda: W.thb_discs(n=16, local_levels=2, levels=3),
+    "thb-16-m2-ms": lambda: dataclasses.replace(W.thb_discs(n=16, local_levels=2, levels=3), smoother="ms"),
+}
+# the gamma-damped additive cycle contracts slowly as a standalone solver
+# (C1: 139 cycles, the slab over 2000); full solves run on the multiplicative
+# cases (13-49 cycles)
+CONVERGE = ["c1-ms", "gyroid-16-ms", "slab-8-ms", "thb-16-m2-ms"]
+
+_cache = {}
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_10977_amd import solver as S
+    S.load()
+    return S
+
+
+def _problem(name):
+    if name not in _cache:
+        w = CASES[name]()
+        print(f"[case {name}] n={w.n} levels={w.levels}", flush=True)
+        if w.local_levels > 0:
+            from oracle import thb as T
+            from paper_1903_10977_amd import thb as P
+            g, op = P.generate(w), T.build(w)
+        elif w.physics == "elasticity":
+            from oracle import elasticity as E
+            from paper_1903_10977_amd import generator as GN
+            g, op = GN.generate(w), E.build(w)
+        else:
+            from oracle import problem as OP
+            from paper_1903_10977_amd import generator as GN
+            g, op = GN.generate(w), OP.build(w)
+        _cache[name] = (w, g, op)
+    return _cache[name]
+
+
+def _t(a):
+    return torch.tensor(np.asarray(a, dtype=np.float64), device="cuda:0")
+
+
+def _mnorm_rel(M, e, ref):
+    return math.sqrt(max(e @ (M @ e), 0.0)) / math.sqrt(ref @ (M @ ref))
+
+
+def _mass(op):
+    """The oracle's L2(Omega) Gram matrix of the finest level."""
+    return op.hier.M if hasattr(op.hier, "M") else op.system.M
+
+
+def _solver(S, g, w):
+    return S.Solver(0).setup(g, S.default_options(nu_pre=w.nu, nu_post=w.nu, **S.smoother_options(w))).factor()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fmg_and_cycles_match_oracle(name):
+    """One FMG pass, and ten cycles from zero, equal the oracle's iterates."""
+    from oracle import multigrid as MG
+    S = _gpu()
+    w, g, op = _problem(name)
+    sol = _solver(S, g, w)
+    A, b, M = op.A, op.b, _mass(op)
+    xf = torch.zeros(len(g.b), dtype=torch.float64, device="cuda:0")
+    sol.mg_solve(_t(g.b), xf, rtol=1e-8, max_cycles=0, fmg=True, raise_on_error=False)
+    xo_f = MG.fmg(op.vcycle, b)
+    d = _mnorm_rel(M, xf.cpu().numpy() - xo_f, xo_f)
+    print(f"[{name}] FMG pass vs oracle (L2) {d:.2e}", flush=True)
+    assert d <= 1e-7, d
+    x10 = torch.zeros(len(g.b), dtype=torch.float64, device="cuda:0")
+    info = sol.mg_solve(_t(g.b), x10, rtol=1e-14, max_cycles=10, raise_on_error=False)
+    assert info.iterations == 10
+    xo10, _, _ = MG.mg_solve(A, b, op.vcycle.apply, tol=1e-14, max_cycles=10)
+    d = _mnorm_rel(M, x10.cpu().numpy() - xo10, xo10)
+    print(f"[{name}] ten cycles vs oracle (L2) {d:.2e}", flush=True)
+    assert d <= 1e-7, d
+    sol.close()
+
+
+@pytest.mark.parametrize("name", CONVERGE)
+def test_mg_solver_converges_like_oracle(name):
+    from oracle import multigrid as MG
+    S = _gpu()
+    w, g, op = _problem(name)
+    sol = _solver(S, g, w)
+    A, b, M = op.A, op.b, _mass(op)
+    for fmg in (False, True):
+        x0 = MG.fmg(op.vcycle, b) if fmg else None
+        xo, ko, relo = MG.mg_solve(A, b, op.vcycle.apply, tol=1e-8, max_cycles=500, x0=x0)
+        x = torch.zeros(len(g.b), dtype=torch.float64, device="cuda:0")
+        info = sol.mg_solve(_t(g.b), x, rtol=1e-8, max_cycles=500, fmg=fmg)
+        xg = x.cpu().numpy()
+        res = np.linalg.norm(b - A @ xg) / np.linalg.norm(b)
+        d = _mnorm_rel(M, xg - xo, xo)
+        print(f"[{name}] fmg={fmg}: cycles gpu {info.iterations} oracle {ko}, residual {res:.2e}, "
+              f"L2 diff {d:.2e}", flush=True)
+        assert info.status == 0 and res <= 1.01e-8
+        assert abs(info.iterations - ko) <= 1
+        assert d <= 1e-6
+    sol.close()
+
+
+def test_mg_solver_cycle_limit():
+    S = _gpu()
+    w, g, op = _problem("c1")
+    sol = _solver(S, g, w)
+    x = torch.zeros(len(g.b), dtype=torch.float64, device="cuda:0")
+    info = sol.mg_solve(_t(g.b), x, rtol=1e-8, max_cycles=3, raise_on_error=False)
+    assert info.status == -5 and info.iterations == 3   # NOT_CONVERGED
+    xg = x.cpu().numpy()
+    res = np.linalg.norm(op.b - op.A @ xg) / np.linalg.norm(op.b)
+    assert res == pytest.approx(info.true_rel_res, rel=1e-6) and res > 1e-8
+    with pytest.raises(S.SolverError):
+        sol.mg_solve(_t(g.b), x, rtol=-1.0)
+    sol.close()
