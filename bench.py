@@ -243,6 +243,33 @@ def main():
         head.update(run_forms(w, g, {"fp64": forms["fp64"]}, args.steps, args.warmup))
     hf = head["fp64"]
 
+    # multigrid as a standalone solver (x <- x + B (b - A x)), from zero and
+    # from a full-multigrid start, with the multiplicative cycle and Jacobi
+    # on the coarser levels (the additive cycle contracts slowly on its own)
+    mg_forms = {}
+    if want is None or "mg-solver" in want:
+        gj = GN.with_coarse_diagonal(g, "jacobi")
+        wj = dataclasses.replace(w, coarse_smoother="jacobi")
+        solm = make(gj, wj, S.FP64, "ms")
+        bm = torch.tensor(g.b, device="cuda:0")
+        for label, fmg in (("ms+jacobi-fp64", False), ("fmg+ms+jacobi-fp64", True)):
+            xm = torch.zeros_like(bm)
+            for _ in range(args.warmup):
+                xm.zero_()
+                solm.mg_solve(bm, xm, rtol=1e-8, max_cycles=2000, fmg=fmg)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                xm.zero_()
+                im = solm.mg_solve(bm, xm, rtol=1e-8, max_cycles=2000, fmg=fmg)
+            torch.cuda.synchronize()
+            dtm = (time.perf_counter() - t0) / args.steps
+            res_m = float(np.linalg.norm(g.b - g.fine.A @ xm.cpu().numpy()) / np.linalg.norm(g.b))
+            mg_forms[label] = {"ms_per_solve": round(1e3 * dtm, 3), "cycles": im.iterations, "true_rel_res": res_m}
+            log(f"{w.name} multigrid solver {label}: {mg_forms[label]}")
+        solm.close()
+        del gj
+
     # dominant kernel: the finest level's fused residual + smoothing step,
     # FP64, timed with HIP events on the library stream during the same solves
     solt = make(g, w, S.FP64, timing=TIMED_REPS)
@@ -437,6 +464,7 @@ def main():
                    "value_is": "fine DOFs / median time of one V-cycle (50 timed cycles, HIP events)",
                    "ms_per_step_is": "one FP64 PCG solve from x0 = 0 to a true relative residual <= 1e-8",
                    "pcg_time_s": round(hf["pcg_ms"] / 1e3, 5), "forms": head,
+                   "multigrid_solver": mg_forms,
                    "speedup_mixed_vs_fp64_pcg": (round(hf["pcg_ms"] / head["mixed"]["pcg_ms"], 3)
                                                  if "mixed" in head else None),
                    "second_workload": second, "elasticity": elastic, "thb": thb, "multi_rhs": multi,
