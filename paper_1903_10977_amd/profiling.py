@@ -5,8 +5,11 @@ Usage (on the results directory a rocprofv3 run wrote with `-d DIR -o run`):
     python3 -m paper_1903_10977_amd.profiling kernels DIR [--match SUBSTR]
     python3 -m paper_1903_10977_amd.profiling traffic FETCH_DIR WRITE_DIR --kernel SUBSTR --grid G \
         --copy-mib M [--command TEXT]
+    python3 -m paper_1903_10977_amd.profiling counters DIR [DIR ...] --kernel SUBSTR
 
-`kernels` prints per-kernel launch counts and durations; `traffic` turns the
+`kernels` prints per-kernel launch counts and durations; `counters` prints the
+mean of every counter collected in the given runs per dispatch of the matching
+kernels (one row per kernel name and grid); `traffic` turns the
 FETCH_SIZE / WRITE_SIZE counters (KiB per dispatch) of one kernel into bytes
 per launch, each scaled by what the same counter reads for a plain device
 copy of M MiB (an elementwise kernel that reads M MiB and writes M MiB), and
@@ -58,6 +61,22 @@ def pmc_rows(path, counter):
     q = """select kernel_name, grid_size, count(*), avg(value) from counters_collection
            where counter_name = ? group by kernel_name, grid_size"""
     return {(r[0], r[1]): (r[2], r[3]) for r in c.execute(q, (counter,))}
+
+
+def counter_table(paths, kernel):
+    """{(kernel name, grid size): {counter: (dispatches, mean value, mean
+    duration in us)}} over every counter found in the runs under paths, for
+    kernels containing kernel (a counter's value is summed over the hardware
+    instances of one dispatch; durations are those of the counter runs)."""
+    out = {}
+    for path in paths:
+        c = _db(path)
+        q = """select kernel_name, grid_size, counter_name, count(*), avg(value), avg(duration) / 1000.0
+               from counters_collection group by kernel_name, grid_size, counter_name"""
+        for name, grid, counter, n, mean, dur in c.execute(q):
+            if kernel in name:
+                out.setdefault((name, grid), {})[counter] = (n, mean, dur)
+    return out
 
 
 def _pick(rows, kernel, grid):
@@ -141,6 +160,9 @@ def main(argv=None):
     k.add_argument("dir")
     k.add_argument("--match", default=None)
     k.add_argument("--top", type=int, default=60)
+    pc = sub.add_parser("counters")
+    pc.add_argument("dirs", nargs="+")
+    pc.add_argument("--kernel", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("fetch_dir")
     t.add_argument("write_dir")
@@ -154,6 +176,11 @@ def main(argv=None):
         print(f"{'kernel':72s} {'grid':>9s} {'launches':>8s} {'avg_us':>9s} {'total_ms':>9s}")
         for name, grid, cnt, avg, tot in rows[: a.top]:
             print(f"{name[:72]:72s} {grid:9d} {cnt:8d} {avg:9.2f} {tot:9.3f}")
+    elif a.cmd == "counters":
+        for (name, grid), cs in sorted(counter_table(a.dirs, a.kernel).items()):
+            print(f"kernel: {name[:100]}  grid {grid}")
+            for counter, (n, mean, dur) in sorted(cs.items()):
+                print(f"  {counter:36s} dispatches {n:6d}  mean per dispatch {mean:.6g}  (duration {dur:.2f} us)")
     else:
         sys.stdout.write(traffic_summary(a.fetch_dir, a.write_dir, a.kernel, a.grid, a.copy_mib, a.command))
 
