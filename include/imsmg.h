@@ -432,9 +432,12 @@ int imsmg_pcg_solve(imsmg_ctx *ctx, const double *b_dev, double *x_dev, double r
  * ||b - A x|| <= rtol ||b|| (2-norm, FP64 operator) or after max_cycles
  * cycles (max_cycles = 0 with fmg: the FMG pass alone); x holds the last
  * iterate.  info->iterations = cycles after the start, rel_res =
- * true_rel_res = the final relative residual.  Errors: STATE before
- * factorization, INVALID_ARG (null vector, rtol <= 0, max_cycles < 0),
- * NOT_CONVERGED (rtol not reached), NAN. */
+ * true_rel_res = the final relative residual.  The residual norm is read on
+ * the host after every cycle (one stream synchronization per cycle); the
+ * first call with fmg != 0 allocates two vectors per level, which the context
+ * keeps until imsmg_destroy.  Errors: STATE before factorization,
+ * INVALID_ARG (null vector, rtol <= 0, max_cycles < 0), NOT_CONVERGED (rtol
+ * not reached; x holds the last iterate, info is filled), NAN, HIP. */
 int imsmg_mg_solve(imsmg_ctx *ctx, const double *b_dev, double *x_dev, double rtol, int max_cycles, int fmg,
                    imsmg_info *info);
 
