@@ -89,6 +89,7 @@ class VectorSystem:
     M: sp.csr_matrix          # vector mass kron(I_d, M_scalar): the L2(Omega)^d metric
     omega_measure: float
     gamma_d_measure: float    # |Gamma_D| of the approximate boundary
+    vol_frac: dict = None     # element linear index -> |K cap Omega_h| / |K|
 
 
 def assemble_elasticity(w, leaf, n, depth, orders=None, force=None, g_dirichlet=None, traction=None,
@@ -113,11 +114,13 @@ def assemble_elasticity(w, leaf, n, depth, orders=None, force=None, g_dirichlet=
     b = np.zeros(d * N)
     omega = 0.0
     gd_meas = 0.0
+    vol_frac = {}
     for e in zip(*np.nonzero(lev.active_el)):
         el = AS.element_lin(e, n)
         fl = lev.elem_funcs[el]
         vp, vw, bp, bw, bn = Q.element_quadrature(leaf, e, depth, lev.lo, lev.h, qc, qs, qb)
         omega += float(vw.sum())
+        vol_frac[el] = float(vw.sum()) / lev.h ** d
         V, Gr = AS.tensor_eval(lev, e, vp)
         K = element_stiffness(vw, Gr, lam, mu)
         Ml = (V * vw) @ V.T
@@ -164,7 +167,8 @@ def assemble_elasticity(w, leaf, n, depth, orders=None, force=None, g_dirichlet=
                        shape=(N, N)).tocsr()
     Ms = (0.5 * (Ms + Ms.T)).tocsr()
     M = sp.kron(sp.identity(d, format="csr"), Ms, format="csr")
-    return VectorSystem(level=lev, ncomp=d, A=A, b=b, M=M, omega_measure=omega, gamma_d_measure=gd_meas)
+    return VectorSystem(level=lev, ncomp=d, A=A, b=b, M=M, omega_measure=omega, gamma_d_measure=gd_meas,
+                        vol_frac=vol_frac)
 
 
 def vector_pattern(lev, d):

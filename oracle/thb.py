@@ -43,6 +43,16 @@ Readings (the paper fixes none of these):
   restricted to active rows and columns; coarse operators are Galerkin
   products (Remark rem:gridParamCorr);
 * numbering: by level m, then the level's lattice index (x fastest).
+
+Linear elasticity on THB levels (the physics of the paper's THB example:
+eq:weakMulti / eq:operatorsMulti, penalty Dirichlet conditions) takes the
+same functions for every displacement component: DOF c N + i is component c
+of THB function i (component-major), A = (I_d kron C) A_grid (I_d kron C)^T
+with the vector grid operator of the uniform case, R_l = I_d kron R_l,scalar,
+and the Schwarz blocks of the scalar level repeated per component (the
+smoothers subsection's separate blocks per component); N_K counts the blocks
+of every component, and the multiplicative smoother colours the vector
+blocks greedily in block order, as on scalar THB levels.
 """
 from __future__ import annotations
 
@@ -261,11 +271,18 @@ def build_level(mesh: HMesh, p: int, n_grid: int, grid_level, lo=0.0, hi=1.0) ->
     return lev
 
 
-def embed(grid_level, A: sp.csr_matrix, nf1: int) -> sp.csr_matrix:
-    """A over the active grid functions -> over the whole (nf1^2) lattice."""
+def embed(grid_level, A: sp.csr_matrix, nf1: int, d: int = 1) -> sp.csr_matrix:
+    """A over the active grid functions (d components, component-major) ->
+    over the whole (nf1^2) lattice, per component."""
     P = sp.csr_matrix((np.ones(len(grid_level.active)), (grid_level.active, np.arange(len(grid_level.active)))),
                       shape=(nf1 * nf1, len(grid_level.active)))
+    P = sp.kron(sp.identity(d, format="csr"), P, format="csr")
     return (P @ A @ P.T).tocsr()
+
+
+def per_component(X: sp.csr_matrix, d: int) -> sp.csr_matrix:
+    """I_d kron X (one copy of X per displacement component)."""
+    return X.tocsr() if d == 1 else sp.kron(sp.identity(d, format="csr"), X, format="csr")
 
 
 def restriction(coarse: THBLevel, fine: THBLevel) -> sp.csr_matrix:
@@ -294,27 +311,41 @@ class THBHierarchy:
         self.w = w
         self.n_grid = w.n * 2 ** M
         self.leaf = G.leaf_values(w, self.n_grid, w.depth)
-        self.grid = AS.assemble(w, self.leaf, self.n_grid, w.depth, orders=orders)
+        if getattr(w, "physics", "poisson") == "elasticity":
+            from . import elasticity as EL
+            self.grid = EL.assemble_elasticity(w, self.leaf, self.n_grid, w.depth, orders=orders)
+            d = self.grid.ncomp
+        else:
+            self.grid = AS.assemble(w, self.leaf, self.n_grid, w.depth, orders=orders)
+            d = 1
+        self.ncomp = d
         nf1 = self.n_grid + p
-        A_grid = embed(self.grid.level, self.grid.A, nf1)
-        b_grid = np.zeros(nf1 * nf1)
-        b_grid[self.grid.level.active] = self.grid.b
+        A_grid = embed(self.grid.level, self.grid.A, nf1, d)
+        ng_act = len(self.grid.level.active)
+        b_grid = np.zeros(d * nf1 * nf1)
+        for c in range(d):
+            b_grid[c * nf1 * nf1 + self.grid.level.active] = self.grid.b[c * ng_act:(c + 1) * ng_act]
         self.meshes = [None] * L
         self.meshes[L - 1] = refine_at_boundary(w.n, M, grid_volume_fractions(self.grid, self.n_grid))
         for k in range(L - 2, -1, -1):
             self.meshes[k] = coarsen(self.meshes[k + 1])
         self.levels = [build_level(m, p, self.n_grid, self.grid.level, w.box_lo, w.box_hi) for m in self.meshes]
         F = self.levels[L - 1]
-        A = (F.C @ A_grid @ F.C.T).tocsr()
-        self.A_direct = [(lv.C @ A_grid @ lv.C.T).tocsr() for lv in self.levels]
-        self.b = F.C @ b_grid
-        M_grid = embed(self.grid.level, self.grid.M, nf1)
-        self.M = (F.C @ M_grid @ F.C.T).tocsr()       # L2(Omega) Gram matrix of the THB functions
+        Cf = per_component(F.C, d)
+        A = (Cf @ A_grid @ Cf.T).tocsr()
+        self.A_direct = [(per_component(lv.C, d) @ A_grid @ per_component(lv.C, d).T).tocsr() for lv in self.levels]
+        self.b = Cf @ b_grid
+        # L2(Omega)^d Gram matrix of the THB functions (the grid's mass is
+        # already one copy per component for elasticity)
+        M_grid = embed(self.grid.level, self.grid.M, nf1, d)
+        self.M = (Cf @ M_grid @ Cf.T).tocsr()
         self.A = [None] * L
         self.R = [None] * (L - 1)
+        self.R_scalar = [None] * (L - 1)
         self.A[L - 1] = A
         for k in range(L - 2, -1, -1):
-            self.R[k] = restriction(self.levels[k], self.levels[k + 1])
+            self.R_scalar[k] = restriction(self.levels[k], self.levels[k + 1])
+            self.R[k] = per_component(self.R_scalar[k], d)
             self.A[k] = (self.R[k] @ self.A[k + 1] @ self.R[k].T).tocsr()
 
 
@@ -334,6 +365,25 @@ class THBMultiplicativeSmoother(SW.MultiplicativeSmoother):
             blocks, assoc = SW.select_blocks(lev)
         SW.Smoother.__init__(self, A, lev, blocks=blocks)
         self._order_blocks(A, lev, assoc, [None] * len(blocks), lambda b: b, 0)
+
+
+class THBVectorMultiplicativeSmoother(SW.MultiplicativeSmoother):
+    """Multiplicative Schwarz on a THB level of a vector problem: the scalar
+    level's blocks repeated per component, coloured greedily in block order
+    (blocks of different components that share an element are coupled by A,
+    so they never share a colour); gamma is not used by this smoother."""
+
+    def __init__(self, A, lev, d):
+        from . import elasticity as EL
+        blocks, vassoc = EL.vector_blocks(lev, d)
+        N = lev.C.shape[0]
+        self._d = d
+        SW.Smoother.__init__(self, A, lev, blocks=blocks)
+        self._order_blocks(A, lev, vassoc, [None] * len(blocks), lambda b: b % N, 0)
+
+    def _gamma(self, lev, blocks):
+        from . import elasticity as EL
+        return 1.0 / EL.max_NK_vector(lev, blocks, self._d)
 
 
 @dataclass
@@ -363,11 +413,21 @@ def build(w, orders=None) -> THBProblem:
     its V-cycle."""
     hier = THBHierarchy(w, orders)
     L = w.levels
+    d = hier.ncomp
     sm = [None] * L
     for l in range(1, L):
         lev = hier.levels[l]
         fine = l == L - 1
         kind = w.smoother if (fine or w.coarse_smoother == "same") else w.coarse_smoother
+        if d > 1:
+            from . import elasticity as EL
+            if kind == "as":
+                sm[l] = EL.VectorSmoother(hier.A[l], lev, d)
+            elif kind == "ms":
+                sm[l] = THBVectorMultiplicativeSmoother(hier.A[l], lev, d)
+            else:
+                raise ValueError(f"vector THB levels: smoother {kind!r} not set up")
+            continue
         if kind == "as":
             sm[l] = SW.Smoother(hier.A[l], lev)
         elif kind == "jacobi":

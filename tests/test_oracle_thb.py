@@ -220,3 +220,103 @@ def test_thb_multiplicative_colours_and_symmetry():
     smu = ou.smoothers[-1]
     single = [j for j, b in enumerate(smu.blocks) if len(b) == 1]
     assert len({smu.colours[j] for j in single}) == 9
+
+
+# ---------------------------------------------------------------- elasticity
+# Pins of the vector THB levels (2D linear elasticity on the star domain).
+
+def test_elasticity_without_refinement_equals_uniform_vector_assembly():
+    """No local refinement: the THB functions are the level-0 B-splines, so
+    the finest vector operator, load and mass equal the uniform vector
+    assembly of oracle/elasticity.py (a separate code path: lattice
+    elements instead of grid coefficients; the star leaves the box-face
+    functions inactive, so both keep the same functions)."""
+    from oracle import elasticity as EL
+    w = W.thb_star_elasticity(n=16, local_levels=0, levels=2)
+    th = T.THBHierarchy(w)
+    leaf = G.leaf_values(w, w.n, w.depth)
+    vs = EL.assemble_elasticity(w, leaf, w.n, w.depth)
+    assert th.ncomp == 2 and th.A[-1].shape == vs.A.shape
+    assert abs(th.A[-1] - vs.A).max() <= 1e-12 * abs(vs.A).max()
+    assert np.abs(th.b - vs.b).max() <= 1e-13 * np.abs(vs.b).max()
+    assert abs(th.M - vs.M).max() <= 1e-13 * abs(vs.M).max()
+
+
+def _greville(m, k, n0, p, lo, hi):
+    """Greville abscissa of B-spline k of level m (open uniform knots)."""
+    n = n0 * 2 ** m
+    h = (hi - lo) / n
+    t = np.concatenate([np.full(p, lo), lo + h * np.arange(n + 1), np.full(p, hi)])
+    return float(np.mean(t[k + 1:k + p + 1]))
+
+
+@pytest.mark.parametrize("M", [1, 2])
+def test_elasticity_rigid_motions_in_the_kernel(M):
+    """Without the penalty term (beta = 0) the elasticity operator of the
+    refined THB space annihilates the rigid motions: the THB basis keeps the
+    partition of unity and reproduces linear functions with the Greville
+    abscissae of each function's own level as coefficients, so the
+    translations and the rotation (-y, x) are exactly representable and have
+    zero strain.  A wrong component block, a transposed coupling or a
+    truncation error leaves a residual."""
+    w = dataclasses.replace(W.thb_star_elasticity(n=16, local_levels=M, levels=2), penalty_factor=0.0)
+    th = T.THBHierarchy(w)
+    lev = th.levels[-1]
+    funcs = [f for f, a in zip(lev.funcs, lev.act) if a]
+    N = len(funcs)
+    gx = np.array([_greville(m, ix, w.n, w.degree, w.box_lo, w.box_hi) for (m, ix, iy) in funcs])
+    gy = np.array([_greville(m, iy, w.n, w.degree, w.box_lo, w.box_hi) for (m, ix, iy) in funcs])
+    A = th.A[-1]
+    scale = abs(A).max()
+    modes = {"x": np.concatenate([np.ones(N), np.zeros(N)]), "y": np.concatenate([np.zeros(N), np.ones(N)]),
+             "rotation": np.concatenate([-gy, gx])}
+    for name, u in modes.items():
+        assert np.abs(A @ u).max() <= 1e-10 * scale * np.abs(u).max(), name
+    # and a strain-carrying linear field is not in the kernel
+    ux = np.concatenate([gx, np.zeros(N)])
+    assert np.abs(A @ ux).max() > 1e-3 * scale
+
+
+def test_elasticity_multiplicative_colours_and_symmetry():
+    """Vector THB levels with multiplicative Schwarz: blocks of one colour
+    are uncoupled (A has no entry between any two of them, so their updates
+    commute), the V-cycle is symmetric, and PCG converges in fewer
+    iterations than with the additive smoother; gamma of the additive
+    smoother counts the blocks of both components (twice the scalar N_K of
+    the same level)."""
+    from oracle import elasticity as EL
+    w = dataclasses.replace(W.thb_star_elasticity(n=16, local_levels=2, levels=4), smoother="ms")
+    ob = T.build(w)
+    for l in range(1, w.levels):
+        sm = ob.smoothers[l]
+        A = ob.hier.A[l].tocsr()
+        by_colour = {}
+        for j, c in enumerate(sm.colours):
+            by_colour.setdefault(c, []).append(np.asarray(sm.blocks[j]))
+        for blocks in by_colour.values():
+            owner = np.full(A.shape[0], -1)
+            for j, b in enumerate(blocks):
+                owner[b] = j
+            for j, b in enumerate(blocks):
+                cols = A[b].indices
+                other = owner[cols]
+                assert np.all((other == -1) | (other == j)), (l, j)
+    # symmetry to 1e-6: the vector blocks of cut elements reach kappa ~ 1e8,
+    # so rounding leaves up to ~5e-9; a post-sweep in forward order instead of
+    # reversed leaves 4e-3 .. 4e-2 on the same vectors
+    rng = np.random.default_rng(6)
+    n = ob.A.shape[0]
+    for _ in range(3):
+        u, v = rng.standard_normal(n), rng.standard_normal(n)
+        a, b = u @ ob.vcycle.apply(v), v @ ob.vcycle.apply(u)
+        assert abs(a - b) <= 1e-6 * max(abs(a), 1e-300)
+    _, it_ms, _ = ob.solve()
+    wa = dataclasses.replace(w, smoother="as")
+    oa = T.build(wa)
+    _, it_as, _ = oa.solve()
+    assert it_ms < it_as
+    for l in range(1, w.levels):
+        lev = ob.hier.levels[l]
+        scalar = SW.max_NK(lev, SW.select_blocks(lev)[0])
+        vec = EL.max_NK_vector(lev, EL.vector_blocks(lev, 2)[0], 2)
+        assert vec == 2 * scalar

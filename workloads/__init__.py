@@ -254,3 +254,21 @@ def thb_256(seed: int = 7) -> Workload:
     (finest cells 1024^2 near the boundaries), 40 seeded discs with radii
     U[0.02, 0.06], six multigrid levels."""
     return thb_discs(seed=seed, n=256, local_levels=2, levels=6, n_discs=40, rmin=0.02, rmax=0.06)
+
+
+def thb_star_elasticity(n: int = 96, local_levels: int = 2, levels: int = 5, depth: int = 2) -> Workload:
+    """2D linear elasticity with quadratic truncated hierarchical B-splines
+    (the physics of the paper's THB example: lambda = mu = 1e3, penalty
+    Dirichlet conditions, a constant load (0, -1)) on the star domain
+    psi = 0.5 + 0.1 sin(5 theta) - r in (-1,1)^2, n^2 level-0 cells, the cut
+    cells refined local_levels times and clamped by the penalty method with
+    beta = 2/h of the (finest) boundary cells, which with two local levels
+    is the example's 4 x 2/h of the unrefined cells.  The level counts are
+    chosen so that the coarsest operator stays numerically positive definite
+    (hierarchies whose coarsest mesh leaves tiny pieces of the star's arms
+    get a coarsest operator with eigenvalues at rounding level, which no
+    direct solver without regularization factorizes)."""
+    return Workload(name=f"thb-star-el-n{n}-m{local_levels}", dim=2, degree=2, n=n, depth=depth, levels=levels,
+                    geometry="star", basis="bspline", bc="penalty", rhs="force", nu=1, box_lo=-1.0, box_hi=1.0,
+                    penalty_factor=2.0, physics="elasticity", lame_lambda=1.0e3, lame_mu=1.0e3,
+                    force=[0.0, -1.0], dirichlet_part="all", local_levels=local_levels)
