@@ -1571,8 +1571,8 @@ int imsmg_gen_build(const imsmg_gen_spec *spec, imsmg_gen_problem **out) {
   }
   if (s.n % (1 << (s.levels - 1))) { g_err = "n must be divisible by 2^(levels-1)"; return -1; }
   if (s.physics == IMSMG_GEN_ELASTICITY) {
-    if (s.dim != 3 || s.bc != IMSMG_GEN_PENALTY || s.basis != IMSMG_GEN_BSPLINE) {
-      g_err = "elasticity: 3D B-splines with penalty Dirichlet conditions";
+    if (s.bc != IMSMG_GEN_PENALTY || s.basis != IMSMG_GEN_BSPLINE) {
+      g_err = "elasticity: B-splines with penalty Dirichlet conditions";
       return -1;
     }
     if (s.dirichlet_part == IMSMG_GEN_DIRICHLET_BITE && s.geometry != IMSMG_GEN_GEOM_APPLE) {

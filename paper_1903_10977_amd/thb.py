@@ -34,6 +34,15 @@ Construction (2D, degree p):
   phi_j = {phi_k : E(k) within E(j)}; coarse operators R A R^T.
 Numbering on every level: by level m, then lattice index of the level (x
 fastest); elements likewise.
+
+Linear elasticity (eq:weakMulti / eq:operatorsMulti with penalty Dirichlet
+conditions, the physics of the paper's THB example): every displacement
+component takes the same THB functions, DOF c N + i = component c of
+function i; the grid operator is the generator's vector one, the THB
+operator (I_d kron C) A_grid (I_d kron C)^T, R_l = I_d kron R_l,scalar, the
+blocks those of the scalar level repeated per component, and every element
+lists the DOFs of all components (the library runs such a level as a plain
+general sparse level).
 """
 from __future__ import annotations
 
@@ -356,17 +365,27 @@ def inclusion_blocks(F: sp.csr_matrix):
     return np.array(ptr, dtype=np.int32), np.array(idx, dtype=np.int32)
 
 
+def _per_component(X: sp.csr_matrix, d: int) -> sp.csr_matrix:
+    """I_d kron X."""
+    return X.tocsr() if d == 1 else sp.kron(sp.identity(d, format="csr"), X, format="csr")
+
+
 def generate(w, nthreads: int = 0):
     """GeneratedProblem of a THB workload (w.local_levels >= 0, 2D
-    B-splines); levels 0 = coarsest, as the uniform generator."""
-    if w.dim != 2 or w.basis != "bspline" or getattr(w, "physics", "poisson") != "poisson":
-        raise ValueError("THB problems: 2D scalar B-spline workloads")
+    B-splines, Poisson or linear elasticity); levels 0 = coarsest, as the
+    uniform generator."""
+    physics = getattr(w, "physics", "poisson")
+    if w.dim != 2 or w.basis != "bspline" or physics not in ("poisson", "elasticity"):
+        raise ValueError("THB problems: 2D B-spline workloads (Poisson or linear elasticity)")
+    if physics == "elasticity" and getattr(w, "coarse_smoother", "same") != "same":
+        raise ValueError("vector THB problems: additive or multiplicative Schwarz on every level")
     t0 = time.perf_counter()
     M, L, p = w.local_levels, w.levels, w.degree
     n_grid = w.n << M
     wg = dataclasses.replace(w, n=n_grid, levels=1, local_levels=0)
     gp = GEN.generate(wg, nthreads=nthreads)
     grid = gp.levels[0]
+    d = int(getattr(grid, "ncomp", 1))
     nf1 = n_grid + p
     gl = np.asarray(grid.dof_to_lattice, dtype=np.int64)
     eta = np.asarray(grid.eta).reshape(n_grid, n_grid, order="F")
@@ -374,6 +393,7 @@ def generate(w, nthreads: int = 0):
     eid = np.asarray(grid.elem_id, dtype=np.int64)
     gcell[eid % n_grid, eid // n_grid] = True
     P = sp.csr_matrix((np.ones(len(gl)), (gl, np.arange(len(gl)))), shape=(nf1 * nf1, len(gl)))
+    P = _per_component(P, d)
     A_grid = (P @ grid.A @ P.T).tocsr()
     meshes: List[Mesh] = [None] * L
     meshes[L - 1] = boundary_mesh(w.n, M, eta)
@@ -382,7 +402,7 @@ def generate(w, nthreads: int = 0):
     spaces = [build_space(ms, p, n_grid) for ms in meshes]
     data = [level_data(s, p, n_grid, gl, gcell) for s in spaces]
     fine = data[L - 1]
-    Cf = fine.space.C[np.nonzero(fine.act)[0]]
+    Cf = _per_component(fine.space.C[np.nonzero(fine.act)[0]], d)
     A = (Cf @ A_grid @ Cf.T).tocsr()
     A.sort_indices()
     levels = [None] * L
@@ -391,6 +411,7 @@ def generate(w, nthreads: int = 0):
         Rk = _restriction_rows(spaces[k - 1], spaces[k], p)
         Rk = Rk[np.nonzero(data[k - 1].act)[0]][:, np.nonzero(data[k].act)[0]].tocsr()
         Rk.eliminate_zeros()
+        Rk = _per_component(Rk, d)
         Rk.sort_indices()
         Rs[k] = Rk
     As = [None] * L
@@ -400,24 +421,28 @@ def generate(w, nthreads: int = 0):
         Ac.sort_indices()
         As[k - 1] = Ac
     for l in range(L):
-        d = data[l]
-        n = int(d.act.sum())
+        dl = data[l]
+        n = int(dl.act.sum())
         bp = bi = ba = None
         if l > 0:
-            bp, bi = inclusion_blocks(d.F)
-            ba = np.arange(n, dtype=np.int32)
+            bp, bi = inclusion_blocks(dl.F)
             if 0 < l < L - 1 and getattr(w, "coarse_smoother", "same") in ("jacobi", "gs"):
                 bp = np.arange(n + 1, dtype=np.int32)
                 bi = np.arange(n, dtype=np.int32)
-        Ft = d.F.T.tocsr()
-        keep_el = np.nonzero(d.elem_on)[0]
+            # the scalar blocks once per component (component c shifted by c n)
+            bp = np.concatenate([bp[:-1] + c * bp[-1] for c in range(d)] + [[d * bp[-1]]]).astype(np.int32)
+            bi = np.concatenate([bi + c * n for c in range(d)]).astype(np.int32)
+            ba = np.arange(d * n, dtype=np.int32)
+        Ft = dl.F.T.tocsr()
+        keep_el = np.nonzero(dl.elem_on)[0]
         Ft = Ft[keep_el]
+        Ft = sp.hstack([Ft] * d, format="csr")   # every element lists the DOFs of all components
         Ft.sort_indices()
-        levels[l] = GEN.GenLevel(n_elements=len(keep_el), lattice=(n,), dof_to_lattice=None, A=As[l], R=Rs[l],
+        levels[l] = GEN.GenLevel(n_elements=len(keep_el), lattice=(d * n,), dof_to_lattice=None, A=As[l], R=Rs[l],
                                  block_ptr=bp, block_idx=bi, block_assoc=ba, n_cut=0, eta_min=0.0, eta=None,
                                  elem_ptr=Ft.indptr.astype(np.int32), elem_idx=Ft.indices.astype(np.int32),
                                  elem_id=None, two_scale=None, block_colour=None)
-    b = Cf @ (P @ gp.b)
+    b = Cf @ (P @ np.asarray(gp.b))
     return GEN.GeneratedProblem(workload=w, levels=levels, b=b, M=None, seconds=time.perf_counter() - t0)
 
 
