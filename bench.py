@@ -407,6 +407,22 @@ def main():
                                          "traffic": PR.read_traffic(os.path.join(
                                              ROOT, "profiles", "traffic_k_csr_residual_smooth_thb_256_discs_fp64.txt"))}}
         del gt, gj
+        # 2D linear elasticity on THB levels (the physics of the paper's THB example)
+        we = W.thb_star_elasticity()
+        t0 = time.time()
+        ge = TB.generate(we)
+        gen_e = time.time() - t0
+        log(f"generated {we.name}: fine DOFs {ge.fine.n}, levels {[lv.n for lv in ge.levels]}, {gen_e:.1f} s")
+        res_e = run_forms(we, ge, {"fp64": (S.FP64, "as", None, None), "ms-fp64": (S.FP64, "ms", None, None)},
+                          args.steps, args.warmup)
+        thb["elasticity"] = {
+            "workload": (f"2D linear elasticity (lambda = mu = 1e3, load (0, -1)), quadratic THB-splines on the "
+                         f"star domain, {we.n}^2 level-0 cells, cut cells refined {we.local_levels} times, "
+                         f"penalty Dirichlet conditions (beta = 2/h of the boundary cells), {we.levels}-level "
+                         f"V(1,1), per-component Schwarz blocks, general sparse (CSR) levels"),
+            "fine_dofs": ge.fine.n, "level_dofs": [lv.n for lv in ge.levels], "generate_s": round(gen_e, 1),
+            "forms": res_e}
+        del ge
 
     # several right-hand sides with the C2 matrix: the 16-column form
     multi = None
