@@ -71,21 +71,24 @@ def test_generator_rejects_bad_spec():
         GN.generate(w)
 
 
-@pytest.mark.parametrize("w", [W.apple(n=8, levels=2), W.slab(n=8, levels=2)], ids=lambda w: w.name)
+@pytest.mark.parametrize("w", [W.apple(n=8, levels=2), W.slab(n=8, levels=2),
+                               W.thb_star_elasticity(n=16, local_levels=0, levels=2)], ids=lambda w: w.name)
 def test_generator_elasticity_matches_oracle(w):
     """Linear elasticity on the apple with a bite and on the clamped slab (8^3,
-    two levels): vector operators (component-major) on the structural pattern
-    of every component pair, load, vector mass, R = I (x) R_scalar and the
-    per-component blocks against the oracle's independent assembly (1e-12 per
-    row)."""
+    two levels), and in 2D on the clamped star (16^2, uniform B-splines: the
+    grid operator of the THB levels): vector operators (component-major) on
+    the structural pattern of every component pair, load, vector mass,
+    R = I (x) R_scalar and the per-component blocks against the oracle's
+    independent assembly (1e-12 per row)."""
     from oracle import elasticity as E
     g = GN.generate(w, with_mass=True)
     op = E.build(w, smoothers=False)
-    assert g.fine.ncomp == 3
+    d = w.dim
+    assert g.fine.ncomp == d
     for l in range(w.levels):
         ol, gl = op.hier.levels[l], g.levels[l]
         assert np.array_equal(ol.active, gl.dof_to_lattice)
-        Pv = E.vector_pattern(ol, 3)
+        Pv = E.vector_pattern(ol, d)
         B = gl.A
         assert np.array_equal(Pv.indptr, B.indptr) and np.array_equal(Pv.indices, B.indices)
         assert _rowrel(op.hier.A[l], B) < 1e-12
@@ -93,7 +96,7 @@ def test_generator_elasticity_matches_oracle(w):
         if l > 0:
             R, GR = op.hier.R[l - 1], gl.R
             assert abs(R - GR).max() < 1e-14
-            ob, _ = E.vector_blocks(ol, 3)
+            ob, _ = E.vector_blocks(ol, d)
             gb = gl.blocks()
             assert len(ob) == len(gb)
             assert all(np.array_equal(a, b) for a, b in zip(ob, gb))
