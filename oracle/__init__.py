@@ -30,7 +30,8 @@ oracle favours the plain definition of each object over speed:
                   eq:operatorsMulti).
 * thb.py        - truncated hierarchical B-splines (Figure fig:THB), the
                   hierarchical coarsening of Algorithm alg:coarsen and the THB
-                  multigrid hierarchy.
+                  multigrid hierarchy, for Poisson and for 2D linear
+                  elasticity (per-component blocks).
 * learned.py    - per-block damping: block features, the two-grid objective
                   built on eq:eigenMulti with its adjoint gradient, and the
                   lambda_max(S A) < 2(1 - 0.05) stability check.
