@@ -1,6 +1,6 @@
 """Multigrid as a standalone solver and full multigrid (imsmg_mg_solve)
 against the oracle (oracle/multigrid.py: mg_solve, fmg) on lattice, vector
-(elasticity) and general sparse (THB) hierarchies:
+(elasticity) and general sparse (THB, scalar and elasticity) hierarchies:
 
 * one FMG pass (max_cycles = 0) and ten cycles from zero: the oracle's
   iterates within 1e-7 relative in L2(Omega) (FP64; the bar of the V-cycle
@@ -33,11 +33,13 @@ CASES = {
     "slab-8-ms": lambda: dataclasses.replace(W.slab(n=8, levels=2), smoother="ms"),
     "thb-16-m2": lambda: W.thb_discs(n=16, local_levels=2, levels=3),
     "thb-16-m2-ms": lambda: dataclasses.replace(W.thb_discs(n=16, local_levels=2, levels=3), smoother="ms"),
+    "thb-el-24-m2-ms": lambda: dataclasses.replace(W.thb_star_elasticity(n=24, local_levels=2, levels=3),
+                                                   smoother="ms"),
 }
 # the gamma-damped additive cycle contracts slowly as a standalone solver
 # (C1: 139 cycles, the slab over 2000); full solves run on the multiplicative
-# cases (13-49 cycles)
-CONVERGE = ["c1-ms", "gyroid-16-ms", "slab-8-ms", "thb-16-m2-ms"]
+# cases (13-84 cycles)
+CONVERGE = ["c1-ms", "gyroid-16-ms", "slab-8-ms", "thb-16-m2-ms", "thb-el-24-m2-ms"]
 
 _cache = {}
 
